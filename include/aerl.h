@@ -1,0 +1,268 @@
+/*
+ * aerl.h - C ABI of libaerl, a gfx950 (AMD Instinct MI355X) library that
+ * evaluates whole populations of tensorized rule sets on a resident dataset.
+ *
+ * Method: Shahrzad & Miikkulainen, "GPU-Accelerated Rule Evaluation and
+ * Evolution" (AERL).  Section 3 describes the tensorized rule form (Fig. 1a:
+ * each condition is one row of weights plus a bias, evaluated as
+ * w.x + b > 0), the step activation used for inference, the sigmoid
+ * relaxation used to fine-tune coefficients by back-propagation, and the
+ * split between evolution on the CPU and evaluation on the GPU, which this
+ * interface is.
+ *
+ * Conventions
+ * -----------
+ * - Every call returns aerl_status: AERL_OK (0) or a negative code.  The
+ *   message of the last failure on a context is aerl_last_error(ctx).  No
+ *   C++ exception crosses this interface.
+ * - Device memory is always owned by the caller (for example PyTorch
+ *   tensors).  The library never frees caller memory; it keeps non-owning
+ *   references to registered dataset and population buffers until they are
+ *   released.  The library owns only host-side state (registries, pinned
+ *   staging buffers, events, graphs, threads).
+ * - Calls that take a hipStream_t enqueue work on that stream and return
+ *   before it finishes unless stated otherwise.  Outputs are valid once the
+ *   stream has reached that point.
+ * - One context per host thread for the direct calls.  The serving calls
+ *   (aerl_serve_*) are thread-safe.
+ * - Hard results are bit-exact: conditions compare individually rounded
+ *   IEEE fp32 products (no fused multiply-add, subnormals kept), and counts
+ *   are integers.
+ */
+#ifndef AERL_H
+#define AERL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t aerl_status;
+enum {
+  AERL_OK = 0,
+  AERL_EINVAL = -1,    /* invalid argument or input data, nothing enqueued */
+  AERL_ENOMEM = -2,    /* a caller-supplied buffer or host allocation is too small */
+  AERL_EDEVICE = -3,   /* a HIP runtime call failed; message holds the HIP error */
+  AERL_ENOENT = -4,    /* unknown dataset, population or ticket id */
+  AERL_EAGAIN = -5,    /* serving: admission budget is full, try again */
+  AERL_ETIMEDOUT = -6, /* serving: wait timed out, the ticket stays valid */
+  AERL_ESTATE = -7     /* call not valid in the current state */
+};
+
+/* Limits of this build. */
+#define AERL_MAX_CLASSES 64        /* classes per dataset */
+#define AERL_MAX_FEATURES 512      /* features per dataset (one LDS tile row each) */
+#define AERL_MAX_RULE_CONDS 255    /* conditions per rule */
+#define AERL_TILE 256              /* samples per layout tile (class regions are padded to it) */
+
+/* Condition operators and kinds (Section 3, Fig. 1a/b). */
+enum { AERL_OP_LT = 0, AERL_OP_LE = 1, AERL_OP_GT = 2, AERL_OP_GE = 3 };
+enum {
+  AERL_KIND_THRESHOLD = 0, /* coef*x[f] op theta            (one non-zero weight)            */
+  AERL_KIND_FEATURE = 1    /* coef*x[f] op coef2*x[g]      (two non-zero weights, zero bias) */
+};
+
+typedef struct aerl_ctx aerl_ctx;
+
+/* Create a context bound to HIP device `device_ordinal`.  *out receives the
+ * context (NULL on failure).  Errors: AERL_EINVAL (bad ordinal or NULL out),
+ * AERL_EDEVICE. */
+aerl_status aerl_create(aerl_ctx **out, int device_ordinal);
+
+/* Destroy a context: stops serving if running, waits for the library's own
+ * host work, releases host state.  Caller device memory is untouched.
+ * Accepts NULL. */
+void aerl_destroy(aerl_ctx *ctx);
+
+/* Message of the last failed call on ctx.  Library-owned, valid until the
+ * next call on ctx.  Never NULL ("" when nothing failed). */
+const char *aerl_last_error(const aerl_ctx *ctx);
+
+/* ------------------------------------------------------------------ data */
+
+/* Bytes of the caller-allocated device buffer that holds a resident dataset
+ * of n samples x f features with n_classes classes (feature-major samples,
+ * labels, tile table, tau and upload scratch).  Pure host arithmetic.
+ * Errors: AERL_EINVAL (n < 0, f < 1, f > AERL_MAX_FEATURES, n_classes < 1 or
+ * > AERL_MAX_CLASSES). */
+aerl_status aerl_dataset_bytes(int64_t n, int32_t f, int32_t n_classes, size_t *bytes);
+
+/* Register a labeled dataset (Section 1: fitness is classification
+ * accuracy on a labeled dataset; Section 4.1 uses one such table).
+ *   x         device, fp32 [n][f] row-major, every value finite
+ *   y         device, int32 [n], each in [0, n_classes)
+ *   mem       device buffer of aerl_dataset_bytes(n, f, n_classes) bytes,
+ *             256-byte aligned, owned by the caller and kept alive until
+ *             aerl_release_dataset; x and y may be freed after return.
+ * The library stably groups the samples by label, pads each class region
+ * to a multiple of AERL_TILE samples, stores the features feature-major
+ * (fp32 [f][n_pad], rows 1 KiB-aligned), and computes
+ * tau[f] = 0.05 * (population std of feature f), fp64 then rounded to fp32
+ * (1 where the std is 0), which scales the soft relaxation.  Permuting the
+ * samples never changes a fitness count.
+ * Synchronous: returns after the layout is complete on `stream`.
+ * *dataset_id receives the id.  Errors: AERL_EINVAL (sizes, non-finite
+ * feature, label out of range, misaligned or NULL pointers), AERL_ENOMEM
+ * (mem_bytes too small), AERL_EDEVICE. */
+aerl_status aerl_upload_dataset(aerl_ctx *ctx, const float *x, const int32_t *y, int64_t n,
+                                int32_t f, int32_t n_classes, void *mem, size_t mem_bytes,
+                                hipStream_t stream, int32_t *dataset_id);
+
+/* Information about a registered dataset.  Pointers are into its `mem`:
+ *   x_fm   fp32 [f][n_pad] (label-grouped order), y_pad int32 [n_pad]
+ *          (-1 on padding), perm int32 [n_pad] (original sample index or
+ *          -1), tau fp32 [f].
+ * Errors: AERL_ENOENT. */
+typedef struct {
+  int64_t n, n_pad;
+  int32_t n_features, n_classes;
+  int64_t class_count[AERL_MAX_CLASSES];
+  const float *x_fm;
+  const int32_t *y_pad;
+  const int32_t *perm;
+  const float *tau;
+} aerl_dataset_info;
+aerl_status aerl_dataset_query(aerl_ctx *ctx, int32_t dataset_id, aerl_dataset_info *info);
+
+/* Forget a dataset.  The caller may free its `mem` once every stream that
+ * used it has finished.  Errors: AERL_ENOENT. */
+aerl_status aerl_release_dataset(aerl_ctx *ctx, int32_t dataset_id);
+
+/* ------------------------------------------------------------ population */
+
+/* A population as produced by the evolution loop (Section 3: evolution
+ * runs on the CPU and hands candidates to the GPU).  HOST arrays, structure
+ * of arrays.  Rule set s owns rules [set_rule_off[s], set_rule_off[s+1]) in
+ * order, then falls back to set_default[s] (first rule that fires decides).
+ * Rule r owns conditions [rule_cond_off[r], rule_cond_off[r+1]) (an AND)
+ * and predicts rule_class[r].  Condition j is
+ *   kind 0: coef[j]*x[f[j]] op[j] theta[j]
+ *   kind 1: coef[j]*x[f[j]] op[j] coef2[j]*x[g[j]]
+ * with each product rounded to fp32 once.  Empty rule sets and empty rules
+ * (an empty AND always fires) are allowed. */
+typedef struct {
+  int32_t n_sets;
+  const int32_t *set_rule_off;  /* [n_sets+1], set_rule_off[0] == 0, non-decreasing */
+  const int32_t *set_default;   /* [n_sets] */
+  const int32_t *rule_cond_off; /* [n_rules+1], rule_cond_off[0] == 0, non-decreasing */
+  const int32_t *rule_class;    /* [n_rules] */
+  const uint8_t *op;            /* [n_conds] AERL_OP_* */
+  const uint8_t *kind;          /* [n_conds] AERL_KIND_* */
+  const int32_t *f;             /* [n_conds] */
+  const int32_t *g;             /* [n_conds], read for kind 1 only */
+  const float *coef;            /* [n_conds] */
+  const float *coef2;           /* [n_conds], read for kind 1 only */
+  const float *theta;           /* [n_conds], read for kind 0 only; +-inf allowed */
+} aerl_population;
+
+/* Bytes of the device workspace that holds the packed form of `pop`.
+ * Validates the structure (offsets, ops, kinds, classes, feature indices
+ * against n_features, g != f for kind 1, finite coefficients, non-NaN
+ * thresholds, at most AERL_MAX_RULE_CONDS conditions per rule).
+ * Errors: AERL_EINVAL with the first offending index in the message. */
+aerl_status aerl_population_bytes(const aerl_population *pop, int32_t n_features,
+                                  int32_t n_classes, size_t *bytes);
+
+/* Validate and pack `pop` into the caller's device workspace `ws`
+ * (ws_bytes >= aerl_population_bytes, 256-byte aligned, kept alive until
+ * aerl_release_population).  The host arrays may be reused once the call
+ * returns: they are copied into library-owned pinned staging memory and
+ * sent with an asynchronous copy on `stream`.  *pop_id receives the id.
+ * Errors: AERL_EINVAL, AERL_ENOMEM, AERL_EDEVICE. */
+aerl_status aerl_pack_population(aerl_ctx *ctx, const aerl_population *pop, int32_t n_features,
+                                 int32_t n_classes, void *ws, size_t ws_bytes, hipStream_t stream,
+                                 int32_t *pop_id);
+
+/* Host-only variant of the packing step: validates `pop` and writes its
+ * packed image (the bytes aerl_pack_population sends to the device) into
+ * host memory `dst` of at least aerl_population_bytes bytes.  Lets tools and
+ * tests inspect the exact comparison forms the kernels evaluate.  Errors:
+ * AERL_EINVAL, AERL_ENOMEM. */
+aerl_status aerl_pack_population_host(const aerl_population *pop, int32_t n_features,
+                                      int32_t n_classes, void *dst, size_t dst_bytes);
+
+/* Forget a packed population (waits for its staging copy).  Errors:
+ * AERL_ENOENT. */
+aerl_status aerl_release_population(aerl_ctx *ctx, int32_t pop_id);
+
+/* ------------------------------------------------------------------ hard */
+
+/* Fitness of every rule set of pop_id on dataset_id (Section 1: accuracy on
+ * labeled data; Section 3: step activation, AND of conditions, first
+ * firing rule, else the default class).
+ *   correct    device int32 [n_sets]: samples whose prediction equals the label
+ *   confusion  device int32 [n_sets][C][C] ([true][predicted]) or NULL
+ * Outputs are overwritten (no accumulation).  Bit-exact.  Errors:
+ * AERL_ENOENT, AERL_EINVAL (feature count or class count of the population
+ * and dataset differ, NULL correct), AERL_EDEVICE. */
+aerl_status aerl_eval_population(aerl_ctx *ctx, int32_t dataset_id, int32_t pop_id,
+                                 int32_t *correct, int32_t *confusion, hipStream_t stream);
+
+/* aerl_eval_population with an explicit launch configuration (used by the
+ * autotuner and by tests that cover every code path):
+ *   samples_per_lane  1, 2 or 4 (a wave covers 64*samples_per_lane samples)
+ *   sets_per_chunk    rule sets per workgroup, >= 1
+ *   tiles_per_group   AERL_TILE-sample tiles per workgroup, >= 1
+ * Same outputs, bit for bit, for every valid configuration.  Errors: as
+ * aerl_eval_population, plus AERL_EINVAL for a configuration whose LDS
+ * footprint does not fit. */
+aerl_status aerl_eval_population_cfg(aerl_ctx *ctx, int32_t dataset_id, int32_t pop_id,
+                                     int32_t *correct, int32_t *confusion,
+                                     int32_t samples_per_lane, int32_t sets_per_chunk,
+                                     int32_t tiles_per_group, hipStream_t stream);
+
+/* Predicted class of rule set `set` of pop_id for n rows (Section 3,
+ * inference with the step activation).
+ *   rows  device fp32 [n][f] row-major (f = the population's feature count)
+ *   pred  device int32 [n]
+ * Errors: AERL_ENOENT, AERL_EINVAL (set out of range, n < 0), AERL_EDEVICE. */
+aerl_status aerl_predict(aerl_ctx *ctx, int32_t pop_id, int32_t set, const float *rows, int64_t n,
+                         int32_t *pred, hipStream_t stream);
+
+/* ------------------------------------------------------------------ soft */
+
+/* Device scratch needed by aerl_soft_forward / aerl_soft_backward for this
+ * dataset and population (per-block partial sums that are reduced in a
+ * fixed order, which keeps results bit-identical from run to run).
+ * Errors: AERL_ENOENT, AERL_EINVAL. */
+aerl_status aerl_soft_workspace_bytes(aerl_ctx *ctx, int32_t dataset_id, int32_t pop_id,
+                                      size_t *forward_bytes, size_t *backward_bytes);
+
+/* Soft loss of every rule set (Section 3: a sigmoid replaces the step so
+ * that coefficients can be tuned by back-propagation).  Condition j has soft
+ * truth sigmoid(z_j), z_j = s_j*(coef[j]*x[f] - theta[j])/tau[f] (kind 0) or
+ * s_j*(coef[j]*x[f] - coef2[j]*x[g])/tau[f] (kind 1), s_j = +1 for > and >=,
+ * -1 for < and <=.  A rule's soft truth is the product over its
+ * conditions; rule k fires first with probability r_k*prod_{i<k}(1-r_i);
+ * the rest goes to the default class.  loss[s] = mean over samples of
+ * min(-log P(label), 100).  Computed in log space in fp32; the parameter
+ * arrays (device fp32 [n_conds], the population's condition order) are
+ * live values and may differ from the packed ones; the population's
+ * structure (ops, kinds, features, classes) is used.
+ *   loss  device fp32 [n_sets]
+ *   ws    device scratch of at least forward_bytes (aerl_soft_workspace_bytes)
+ * Deterministic (fixed reduction order).  Errors: AERL_ENOENT, AERL_EINVAL,
+ * AERL_EDEVICE. */
+aerl_status aerl_soft_forward(aerl_ctx *ctx, int32_t dataset_id, int32_t pop_id, const float *coef,
+                              const float *coef2, const float *theta, float *loss, void *ws,
+                              size_t ws_bytes, hipStream_t stream);
+
+/* Gradient of sum_s dloss[s]*loss[s] with respect to coef, coef2 and theta
+ * (device fp32 [n_conds] each; coef2 entries of kind-0 conditions and
+ * theta entries of kind-1 conditions are written as 0).  The adjoint
+ * recomputes every sigmoid instead of storing activations.  dloss is
+ * device fp32 [n_sets]; ws holds at least backward_bytes.  Deterministic.
+ * Errors: AERL_ENOENT, AERL_EINVAL, AERL_EDEVICE. */
+aerl_status aerl_soft_backward(aerl_ctx *ctx, int32_t dataset_id, int32_t pop_id,
+                               const float *coef, const float *coef2, const float *theta,
+                               const float *dloss, float *dcoef, float *dcoef2, float *dtheta,
+                               void *ws, size_t ws_bytes, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AERL_H */

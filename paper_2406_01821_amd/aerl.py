@@ -1,0 +1,308 @@
+"""Python binding of libaerl (ctypes).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of ``libaerl.so``.  PyTorch supplies device memory and streams.
+The raw entry points keep the C names (``aerl_create``, ``aerl_upload_dataset``,
+``aerl_eval_population``, ...); ``Context`` wraps them for torch tensors.
+Importing this module raises if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+import torch
+
+from .population import Dataset, Population
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libaerl.so")
+
+AERL_OK, AERL_EINVAL, AERL_ENOMEM, AERL_EDEVICE, AERL_ENOENT = 0, -1, -2, -3, -4
+AERL_EAGAIN, AERL_ETIMEDOUT, AERL_ESTATE = -5, -6, -7
+AERL_MAX_CLASSES = 64
+AERL_TILE = 256
+STATUS_NAMES = {0: "AERL_OK", -1: "AERL_EINVAL", -2: "AERL_ENOMEM", -3: "AERL_EDEVICE",
+                -4: "AERL_ENOENT", -5: "AERL_EAGAIN", -6: "AERL_ETIMEDOUT", -7: "AERL_ESTATE"}
+
+
+class AerlError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class aerl_population(C.Structure):
+    _fields_ = [("n_sets", C.c_int32),
+                ("set_rule_off", C.c_void_p), ("set_default", C.c_void_p),
+                ("rule_cond_off", C.c_void_p), ("rule_class", C.c_void_p),
+                ("op", C.c_void_p), ("kind", C.c_void_p), ("f", C.c_void_p), ("g", C.c_void_p),
+                ("coef", C.c_void_p), ("coef2", C.c_void_p), ("theta", C.c_void_p)]
+
+
+class aerl_dataset_info(C.Structure):
+    _fields_ = [("n", C.c_int64), ("n_pad", C.c_int64), ("n_features", C.c_int32),
+                ("n_classes", C.c_int32), ("class_count", C.c_int64 * AERL_MAX_CLASSES),
+                ("x_fm", C.c_void_p), ("y_pad", C.c_void_p), ("perm", C.c_void_p),
+                ("tau", C.c_void_p)]
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run paper_2406_01821_amd/build_lib.py "
+                      "or __graft_entry__.build()")
+lib = C.CDLL(LIB_PATH)
+
+_P, _I32, _I64, _SZ = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
+_SIGS = {
+    "aerl_create": ([C.POINTER(C.c_void_p), C.c_int], _I32),
+    "aerl_destroy": ([_P], None),
+    "aerl_last_error": ([_P], C.c_char_p),
+    "aerl_dataset_bytes": ([_I64, _I32, _I32, C.POINTER(_SZ)], _I32),
+    "aerl_upload_dataset": ([_P, _P, _P, _I64, _I32, _I32, _P, _SZ, _P, C.POINTER(_I32)], _I32),
+    "aerl_dataset_query": ([_P, _I32, C.POINTER(aerl_dataset_info)], _I32),
+    "aerl_release_dataset": ([_P, _I32], _I32),
+    "aerl_population_bytes": ([C.POINTER(aerl_population), _I32, _I32, C.POINTER(_SZ)], _I32),
+    "aerl_pack_population": ([_P, C.POINTER(aerl_population), _I32, _I32, _P, _SZ, _P,
+                              C.POINTER(_I32)], _I32),
+    "aerl_pack_population_host": ([C.POINTER(aerl_population), _I32, _I32, _P, _SZ], _I32),
+    "aerl_release_population": ([_P, _I32], _I32),
+    "aerl_eval_population_cfg": ([_P, _I32, _I32, _P, _P, _I32, _I32, _I32, _P], _I32),
+    "aerl_eval_population": ([_P, _I32, _I32, _P, _P, _P], _I32),
+    "aerl_predict": ([_P, _I32, _I32, _P, _I64, _P, _P], _I32),
+    "aerl_soft_workspace_bytes": ([_P, _I32, _I32, C.POINTER(_SZ), C.POINTER(_SZ)], _I32),
+    "aerl_soft_forward": ([_P, _I32, _I32, _P, _P, _P, _P, _P, _SZ, _P], _I32),
+    "aerl_soft_backward": ([_P, _I32, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _SZ, _P], _I32),
+}
+for _name, (_args, _res) in _SIGS.items():
+    _fn = getattr(lib, _name)
+    _fn.argtypes, _fn.restype = _args, _res
+    globals()[_name] = _fn
+
+EXPORTED = tuple(_SIGS)
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    if isinstance(t, torch.Tensor):
+        return t.data_ptr()
+    return t.ctypes.data
+
+
+def _stream(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def pack_host(pop: Population, n_features: int, n_classes: int) -> np.ndarray:
+    """Packed image of ``pop`` as the library sends it to the device (host-only
+    call, no GPU needed)."""
+    hp = _HostPop(pop)
+    nbytes = C.c_size_t()
+    st = aerl_population_bytes(C.byref(hp.s), n_features, n_classes, C.byref(nbytes))
+    if st != AERL_OK:
+        raise AerlError(st, "population rejected")
+    out = np.zeros(nbytes.value, np.uint8)
+    st = aerl_pack_population_host(C.byref(hp.s), n_features, n_classes, out.ctypes.data,
+                                   nbytes.value)
+    if st != AERL_OK:
+        raise AerlError(st, "packing failed")
+    return out
+
+
+def population_status(pop: Population, n_features: int, n_classes: int) -> int:
+    """Validation status of ``pop`` (host-only)."""
+    hp = _HostPop(pop)
+    nbytes = C.c_size_t()
+    return aerl_population_bytes(C.byref(hp.s), n_features, n_classes, C.byref(nbytes))
+
+
+class _HostPop:
+    """Keeps contiguous host arrays of a Population alive for one call."""
+
+    def __init__(self, pop: Population):
+        self.arrays = [np.ascontiguousarray(a) for a in (
+            pop.set_rule_off.astype(np.int32), pop.set_default.astype(np.int32),
+            pop.rule_cond_off.astype(np.int32), pop.rule_class.astype(np.int32),
+            pop.op.astype(np.uint8), pop.kind.astype(np.uint8), pop.f.astype(np.int32),
+            pop.g.astype(np.int32), pop.coef.astype(np.float32), pop.coef2.astype(np.float32),
+            pop.theta.astype(np.float32))]
+        self.s = aerl_population(pop.n_sets, *[a.ctypes.data for a in self.arrays])
+
+
+@dataclass
+class DeviceDataset:
+    id: int
+    mem: torch.Tensor
+    n: int
+    n_features: int
+    n_classes: int
+
+
+@dataclass
+class DevicePopulation:
+    id: int
+    ws: torch.Tensor
+    n_sets: int
+    n_conds: int
+    n_features: int
+    n_classes: int
+
+
+class Context:
+    """One libaerl context on one GPU."""
+
+    def __init__(self, device: int = 0):
+        if not torch.cuda.is_available():
+            raise RuntimeError("libaerl needs a GPU (torch.cuda.is_available() is False)")
+        self.device = torch.device("cuda", device)
+        h = C.c_void_p()
+        st = aerl_create(C.byref(h), device)
+        if st != AERL_OK:
+            raise AerlError(st, "aerl_create failed")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            aerl_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def check(self, st: int):
+        if st != AERL_OK:
+            raise AerlError(st, aerl_last_error(self.h).decode())
+
+    # ------------------------------------------------------------- datasets
+    def upload_dataset(self, data: Dataset, stream=None) -> DeviceDataset:
+        x = torch.as_tensor(data.x, dtype=torch.float32).to(self.device).contiguous()
+        y = torch.as_tensor(data.y, dtype=torch.int32).to(self.device).contiguous()
+        n, nf = x.shape
+        nbytes = C.c_size_t()
+        self.check(aerl_dataset_bytes(n, nf, data.n_classes, C.byref(nbytes)))
+        mem = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=self.device)
+        did = C.c_int32()
+        self.check(aerl_upload_dataset(self.h, _ptr(x), _ptr(y), n, nf, data.n_classes, _ptr(mem),
+                                       nbytes.value, _stream(stream), C.byref(did)))
+        return DeviceDataset(did.value, mem, n, nf, data.n_classes)
+
+    def dataset_info(self, ds: DeviceDataset) -> dict:
+        info = aerl_dataset_info()
+        self.check(aerl_dataset_query(self.h, ds.id, C.byref(info)))
+        n_pad, nf = info.n_pad, info.n_features
+
+        def view(ptr, count, dtype):
+            off = ptr - ds.mem.data_ptr()
+            nbytes = count * torch.tensor([], dtype=dtype).element_size()
+            return ds.mem[off:off + nbytes].view(dtype)
+
+        return dict(n=info.n, n_pad=n_pad, class_count=list(info.class_count[:info.n_classes]),
+                    x_fm=view(info.x_fm, nf * n_pad, torch.float32).view(nf, n_pad),
+                    y_pad=view(info.y_pad, n_pad, torch.int32),
+                    perm=view(info.perm, n_pad, torch.int32),
+                    tau=view(info.tau, nf, torch.float32))
+
+    def release_dataset(self, ds: DeviceDataset):
+        self.check(aerl_release_dataset(self.h, ds.id))
+
+    # ---------------------------------------------------------- populations
+    def pack_population(self, pop: Population, n_features: int, n_classes: int,
+                        stream=None) -> DevicePopulation:
+        hp = _HostPop(pop)
+        nbytes = C.c_size_t()
+        st = aerl_population_bytes(C.byref(hp.s), n_features, n_classes, C.byref(nbytes))
+        if st != AERL_OK:
+            # repeat through the context to get the message
+            ws = torch.empty(256, dtype=torch.uint8, device=self.device)
+            pid = C.c_int32()
+            self.check(aerl_pack_population(self.h, C.byref(hp.s), n_features, n_classes,
+                                            _ptr(ws), 256, _stream(stream), C.byref(pid)))
+            raise AerlError(st, "aerl_population_bytes failed")
+        ws = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+        pid = C.c_int32()
+        self.check(aerl_pack_population(self.h, C.byref(hp.s), n_features, n_classes, _ptr(ws),
+                                        nbytes.value, _stream(stream), C.byref(pid)))
+        return DevicePopulation(pid.value, ws, pop.n_sets, pop.n_conds, n_features, n_classes)
+
+    def release_population(self, p: DevicePopulation):
+        self.check(aerl_release_population(self.h, p.id))
+
+    # ------------------------------------------------------------ hard path
+    def eval_population(self, ds: DeviceDataset, pop: DevicePopulation, confusion: bool = True,
+                        out=None, stream=None, cfg=None):
+        """Returns (correct int32 [P], confusion int32 [P][C][C] or None) on the device.
+        ``cfg = (samples_per_lane, sets_per_chunk, tiles_per_group)`` forces a
+        launch configuration."""
+        if out is None:
+            correct = torch.empty(pop.n_sets, dtype=torch.int32, device=self.device)
+            conf = (torch.empty((pop.n_sets, ds.n_classes, ds.n_classes), dtype=torch.int32,
+                                device=self.device) if confusion else None)
+        else:
+            correct, conf = out
+        if cfg is None:
+            self.check(aerl_eval_population(self.h, ds.id, pop.id, _ptr(correct), _ptr(conf),
+                                            _stream(stream)))
+        else:
+            self.check(aerl_eval_population_cfg(self.h, ds.id, pop.id, _ptr(correct), _ptr(conf),
+                                                cfg[0], cfg[1], cfg[2], _stream(stream)))
+        return correct, conf
+
+    def predict(self, pop: DevicePopulation, rows, set_index: int = 0, out=None, stream=None):
+        rows = torch.as_tensor(rows, dtype=torch.float32).to(self.device).contiguous()
+        n = rows.shape[0]
+        pred = out if out is not None else torch.empty(n, dtype=torch.int32, device=self.device)
+        self.check(aerl_predict(self.h, pop.id, set_index, _ptr(rows), n, _ptr(pred),
+                                _stream(stream)))
+        return pred
+
+    # ------------------------------------------------------------ soft path
+    def soft_workspace(self, ds: DeviceDataset, pop: DevicePopulation, backward: bool):
+        fb, bb = C.c_size_t(), C.c_size_t()
+        self.check(aerl_soft_workspace_bytes(self.h, ds.id, pop.id, C.byref(fb), C.byref(bb)))
+        n = bb.value if backward else fb.value
+        return torch.empty(max(n, 256), dtype=torch.uint8, device=self.device)
+
+    def soft_forward(self, ds, pop, coef, coef2, theta, ws=None, stream=None):
+        ws = ws if ws is not None else self.soft_workspace(ds, pop, False)
+        loss = torch.empty(pop.n_sets, dtype=torch.float32, device=self.device)
+        self.check(aerl_soft_forward(self.h, ds.id, pop.id, _ptr(coef), _ptr(coef2), _ptr(theta),
+                                     _ptr(loss), _ptr(ws), ws.numel(), _stream(stream)))
+        return loss
+
+    def soft_backward(self, ds, pop, coef, coef2, theta, dloss, ws=None, stream=None):
+        ws = ws if ws is not None else self.soft_workspace(ds, pop, True)
+        g = [torch.empty(pop.n_conds, dtype=torch.float32, device=self.device) for _ in range(3)]
+        self.check(aerl_soft_backward(self.h, ds.id, pop.id, _ptr(coef), _ptr(coef2), _ptr(theta),
+                                      _ptr(dloss), _ptr(g[0]), _ptr(g[1]), _ptr(g[2]), _ptr(ws),
+                                      ws.numel(), _stream(stream)))
+        return tuple(g)
+
+
+class SoftLoss(torch.autograd.Function):
+    """loss[P] = soft relaxation loss of every rule set; gradients flow to the
+    coefficient and threshold tensors through the library's adjoint kernel,
+    which recomputes the sigmoids (only the parameters are saved)."""
+
+    @staticmethod
+    def forward(ctx, coef, coef2, theta, aerl_ctx: Context, ds: DeviceDataset,
+                pop: DevicePopulation):
+        coef, coef2, theta = coef.contiguous(), coef2.contiguous(), theta.contiguous()
+        loss = aerl_ctx.soft_forward(ds, pop, coef, coef2, theta)
+        ctx.save_for_backward(coef, coef2, theta)
+        ctx.aerl = (aerl_ctx, ds, pop)
+        return loss
+
+    @staticmethod
+    def backward(ctx, dloss):
+        coef, coef2, theta = ctx.saved_tensors
+        aerl_ctx, ds, pop = ctx.aerl
+        g1, g2, g3 = aerl_ctx.soft_backward(ds, pop, coef, coef2, theta,
+                                            dloss.contiguous().float())
+        return g1, g2, g3, None, None, None

@@ -1,0 +1,467 @@
+// C ABI of libaerl: context, datasets, populations and the direct calls.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+
+#include "internal.h"
+
+namespace aerl {
+
+aerl_status fail(aerl_ctx *ctx, aerl_status code, const char *fmt, ...) {
+  if (ctx) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    ctx->err = buf;
+  }
+  return code;
+}
+
+PackedLayout packed_layout(int32_t n_sets, int32_t n_rules, int32_t n_conds);
+aerl_status validate_population(aerl_ctx *ctx, const aerl_population *p, int32_t nf, int32_t nc,
+                                int32_t *n_rules_out, int32_t *n_conds_out);
+void pack_population_image(const aerl_population *p, int32_t nf, int32_t nc, int32_t n_rules,
+                           int32_t n_conds, void *dst, PopRec *rec);
+
+namespace {
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+struct DatasetMem {
+  int64_t n_pad_max, n_tiles_max, n_blocks;
+  size_t x_off, y_off, perm_off, tile_off, tau_off, counts_off, base_off, flags_off, total;
+};
+
+DatasetMem dataset_mem(int64_t n, int32_t nf, int32_t nc) {
+  DatasetMem m{};
+  m.n_pad_max = n > 0 ? ((n + AERL_TILE - 1) / AERL_TILE + nc) * AERL_TILE : 0;
+  m.n_tiles_max = m.n_pad_max / AERL_TILE;
+  m.n_blocks = (n + kUploadBlock - 1) / kUploadBlock;
+  size_t off = 0;
+  m.x_off = off;     off = align256(off + sizeof(float) * (size_t)nf * (size_t)m.n_pad_max);
+  m.y_off = off;     off = align256(off + sizeof(int32_t) * (size_t)m.n_pad_max);
+  m.perm_off = off;  off = align256(off + sizeof(int32_t) * (size_t)m.n_pad_max);
+  m.tile_off = off;  off = align256(off + sizeof(int32_t) * (size_t)(m.n_tiles_max + 1));
+  m.tau_off = off;   off = align256(off + sizeof(float) * (size_t)nf);
+  m.counts_off = off; off = align256(off + sizeof(int32_t) * (size_t)(m.n_blocks * nc + 1));
+  m.base_off = off;  off = align256(off + sizeof(int32_t) * (size_t)(m.n_blocks * nc + 1));
+  m.flags_off = off; off = align256(off + sizeof(int32_t) * 2);
+  m.total = off;
+  return m;
+}
+
+aerl_status check_dataset_args(aerl_ctx *ctx, int64_t n, int32_t nf, int32_t nc) {
+  if (n < 0 || n > (int64_t)1 << 31) return fail(ctx, AERL_EINVAL, "n = %lld outside [0, 2^31]", (long long)n);
+  if (nf < 1 || nf > AERL_MAX_FEATURES)
+    return fail(ctx, AERL_EINVAL, "n_features %d outside [1, %d]", nf, AERL_MAX_FEATURES);
+  if (nc < 1 || nc > AERL_MAX_CLASSES)
+    return fail(ctx, AERL_EINVAL, "n_classes %d outside [1, %d]", nc, AERL_MAX_CLASSES);
+  return AERL_OK;
+}
+
+// RAII pinned host buffer.
+struct Pinned {
+  void *p = nullptr;
+  ~Pinned() { if (p) (void)hipHostFree(p); }
+};
+
+// Launch configuration of the plain hard-eval path.
+void hard_config(const DatasetRec &ds, int32_t n_sets, int n_cu, int *S, int *Q, int *TG) {
+  const int64_t tiles = ds.n_tiles;
+  int s = 4;
+  while (s > 1 && (size_t)ds.nf * 256 * s > 150 * 1024) s >>= 1;
+  *S = s;
+  const int64_t target = 8LL * n_cu;
+  int q = (int)std::min<int64_t>(std::max<int32_t>(n_sets, 1), 256);
+  auto blocks = [&](int qq, int64_t tg) {
+    int64_t g = 0;
+    for (int c = 0; c < ds.nc; ++c) g += (ds.region_tiles[c] + tg - 1) / tg;
+    return ((n_sets + qq - 1) / qq) * g;
+  };
+  while (q > 16 && blocks(q, 1) < target) q >>= 1;
+  const size_t lds_max = 160 * 1024;
+  while (q > 1 && (size_t)ds.nf * 64 * s * 4 + (size_t)q * ds.nc * 4 > lds_max) q >>= 1;
+  int64_t tg = 1;
+  while (tg * 2 <= tiles && blocks(q, tg * 2) >= target) tg *= 2;
+  *Q = q;
+  *TG = (int)tg;
+}
+
+}  // namespace
+}  // namespace aerl
+
+using namespace aerl;
+
+extern "C" {
+
+aerl_status aerl_create(aerl_ctx **out, int device_ordinal) {
+  if (!out) return AERL_EINVAL;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device_ordinal < 0 || device_ordinal >= count)
+    return AERL_EINVAL;
+  aerl_ctx *ctx = new (std::nothrow) aerl_ctx();
+  if (!ctx) return AERL_ENOMEM;
+  ctx->device = device_ordinal;
+  if (hipSetDevice(device_ordinal) != hipSuccess ||
+      hipDeviceGetAttribute(&ctx->n_cu, hipDeviceAttributeMultiprocessorCount, device_ordinal) !=
+          hipSuccess) {
+    delete ctx;
+    return AERL_EDEVICE;
+  }
+  *out = ctx;
+  return AERL_OK;
+}
+
+void aerl_serve_shutdown_internal(aerl_ctx *ctx);
+
+void aerl_destroy(aerl_ctx *ctx) {
+  if (!ctx) return;
+  aerl_serve_shutdown_internal(ctx);
+  for (auto &kv : ctx->pops) {
+    if (kv.second.staged) {
+      (void)hipEventSynchronize(kv.second.staged);
+      (void)hipEventDestroy(kv.second.staged);
+    }
+    if (kv.second.staging) (void)hipHostFree(kv.second.staging);
+  }
+  delete ctx;
+}
+
+const char *aerl_last_error(const aerl_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+aerl_status aerl_dataset_bytes(int64_t n, int32_t f, int32_t n_classes, size_t *bytes) {
+  if (!bytes) return AERL_EINVAL;
+  aerl_status st = check_dataset_args(nullptr, n, f, n_classes);
+  if (st) return st;
+  *bytes = dataset_mem(n, f, n_classes).total;
+  return AERL_OK;
+}
+
+aerl_status aerl_upload_dataset(aerl_ctx *ctx, const float *x, const int32_t *y, int64_t n,
+                                int32_t nf, int32_t nc, void *mem, size_t mem_bytes,
+                                hipStream_t stream, int32_t *dataset_id) {
+  if (!ctx) return AERL_EINVAL;
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  ctx->err.clear();
+  if (!dataset_id) return fail(ctx, AERL_EINVAL, "dataset_id is NULL");
+  aerl_status st = check_dataset_args(ctx, n, nf, nc);
+  if (st) return st;
+  if (n > 0 && (!x || !y)) return fail(ctx, AERL_EINVAL, "x or y is NULL");
+  if (!mem || ((uintptr_t)mem & 255)) return fail(ctx, AERL_EINVAL, "mem is NULL or not 256-byte aligned");
+  const DatasetMem M = dataset_mem(n, nf, nc);
+  if (mem_bytes < M.total)
+    return fail(ctx, AERL_ENOMEM, "mem holds %zu bytes, %zu needed", mem_bytes, M.total);
+  AERL_HIP(ctx, hipSetDevice(ctx->device));
+  char *base = static_cast<char *>(mem);
+  DatasetRec d;
+  d.n = n;
+  d.nf = nf;
+  d.nc = nc;
+  d.x_fm = reinterpret_cast<float *>(base + M.x_off);
+  d.y_pad = reinterpret_cast<int32_t *>(base + M.y_off);
+  d.perm = reinterpret_cast<int32_t *>(base + M.perm_off);
+  d.tile_info = reinterpret_cast<int32_t *>(base + M.tile_off);
+  d.tau = reinterpret_cast<float *>(base + M.tau_off);
+  int32_t *counts_dev = reinterpret_cast<int32_t *>(base + M.counts_off);
+  int32_t *base_dev = reinterpret_cast<int32_t *>(base + M.base_off);
+  int32_t *flags_dev = reinterpret_cast<int32_t *>(base + M.flags_off);
+
+  const size_t nbc = (size_t)M.n_blocks * nc;
+  Pinned hbuf;
+  const size_t hbytes = sizeof(int32_t) * (2 * nbc + 2 + (size_t)M.n_tiles_max + 1);
+  AERL_HIP(ctx, hipHostMalloc(&hbuf.p, hbytes, hipHostMallocDefault));
+  int32_t *h_counts = static_cast<int32_t *>(hbuf.p);
+  int32_t *h_base = h_counts + nbc;
+  int32_t *h_flags = h_base + nbc;
+  int32_t *h_tiles = h_flags + 2;
+
+  AERL_HIP(ctx, launch_fill_i32(flags_dev, 2, 0, stream));
+  AERL_HIP(ctx, launch_validate_count(x, y, n, nf, nc, counts_dev, flags_dev, M.n_blocks, stream));
+  if (nbc) AERL_HIP(ctx, hipMemcpyAsync(h_counts, counts_dev, nbc * 4, hipMemcpyDeviceToHost, stream));
+  AERL_HIP(ctx, hipMemcpyAsync(h_flags, flags_dev, 8, hipMemcpyDeviceToHost, stream));
+  AERL_HIP(ctx, hipStreamSynchronize(stream));
+  if (h_flags[0]) return fail(ctx, AERL_EINVAL, "x holds a non-finite value");
+  if (h_flags[1]) return fail(ctx, AERL_EINVAL, "y holds a label outside [0, %d)", nc);
+
+  // Class regions, each padded to whole tiles, in class order.
+  int64_t tile = 0;
+  for (int c = 0; c < nc; ++c) {
+    int64_t cnt = 0;
+    for (int64_t b = 0; b < M.n_blocks; ++b) cnt += h_counts[b * nc + c];
+    d.class_count[c] = cnt;
+    d.region_tile0[c] = (int32_t)tile;
+    d.region_tiles[c] = (int32_t)((cnt + AERL_TILE - 1) / AERL_TILE);
+    for (int64_t t = 0; t < d.region_tiles[c]; ++t) {
+      const int64_t valid = std::min<int64_t>(AERL_TILE, cnt - t * AERL_TILE);
+      h_tiles[tile + t] = c | (int32_t)(valid << 8);
+    }
+    int64_t run = (int64_t)d.region_tile0[c] * AERL_TILE;
+    for (int64_t b = 0; b < M.n_blocks; ++b) {
+      h_base[b * nc + c] = (int32_t)run;
+      run += h_counts[b * nc + c];
+    }
+    tile += d.region_tiles[c];
+  }
+  d.n_tiles = tile;
+  d.n_pad = tile * AERL_TILE;
+  if (d.n_pad > M.n_pad_max) return fail(ctx, AERL_EINVAL, "internal: layout overflow");
+  // The x_fm rows use stride n_pad.
+  if (d.n_tiles) AERL_HIP(ctx, hipMemcpyAsync(d.tile_info, h_tiles, (size_t)d.n_tiles * 4, hipMemcpyHostToDevice, stream));
+  if (nbc) AERL_HIP(ctx, hipMemcpyAsync(base_dev, h_base, nbc * 4, hipMemcpyHostToDevice, stream));
+  AERL_HIP(ctx, launch_fill_i32(reinterpret_cast<int32_t *>(d.x_fm), (int64_t)nf * d.n_pad, 0, stream));
+  AERL_HIP(ctx, launch_fill_i32(d.y_pad, d.n_pad, -1, stream));
+  AERL_HIP(ctx, launch_fill_i32(d.perm, d.n_pad, -1, stream));
+  AERL_HIP(ctx, launch_scatter_transpose(x, y, n, nf, nc, base_dev, d.x_fm, d.y_pad, d.perm, d.n_pad,
+                                         M.n_blocks, stream));
+  AERL_HIP(ctx, launch_tau(d.x_fm, d.y_pad, d.n_pad, nf, n, d.tau, stream));
+  AERL_HIP(ctx, hipStreamSynchronize(stream));
+  const int32_t id = ctx->next_id++;
+  ctx->datasets[id] = d;
+  *dataset_id = id;
+  return AERL_OK;
+}
+
+aerl_status aerl_dataset_query(aerl_ctx *ctx, int32_t dataset_id, aerl_dataset_info *info) {
+  if (!ctx) return AERL_EINVAL;
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  if (!info) return fail(ctx, AERL_EINVAL, "info is NULL");
+  auto it = ctx->datasets.find(dataset_id);
+  if (it == ctx->datasets.end()) return fail(ctx, AERL_ENOENT, "unknown dataset %d", dataset_id);
+  const DatasetRec &d = it->second;
+  std::memset(info, 0, sizeof *info);
+  info->n = d.n;
+  info->n_pad = d.n_pad;
+  info->n_features = d.nf;
+  info->n_classes = d.nc;
+  for (int c = 0; c < d.nc; ++c) info->class_count[c] = d.class_count[c];
+  info->x_fm = d.x_fm;
+  info->y_pad = d.y_pad;
+  info->perm = d.perm;
+  info->tau = d.tau;
+  return AERL_OK;
+}
+
+aerl_status aerl_release_dataset(aerl_ctx *ctx, int32_t dataset_id) {
+  if (!ctx) return AERL_EINVAL;
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  if (!ctx->datasets.erase(dataset_id)) return fail(ctx, AERL_ENOENT, "unknown dataset %d", dataset_id);
+  return AERL_OK;
+}
+
+aerl_status aerl_population_bytes(const aerl_population *pop, int32_t n_features, int32_t n_classes,
+                                  size_t *bytes) {
+  if (!bytes) return AERL_EINVAL;
+  int32_t nr = 0, nc = 0;
+  aerl_status st = validate_population(nullptr, pop, n_features, n_classes, &nr, &nc);
+  if (st) return st;
+  *bytes = packed_layout(pop->n_sets, nr, nc).total;
+  return AERL_OK;
+}
+
+aerl_status aerl_pack_population(aerl_ctx *ctx, const aerl_population *pop, int32_t nf, int32_t nc,
+                                 void *ws, size_t ws_bytes, hipStream_t stream, int32_t *pop_id) {
+  if (!ctx) return AERL_EINVAL;
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  ctx->err.clear();
+  if (!pop_id) return fail(ctx, AERL_EINVAL, "pop_id is NULL");
+  int32_t n_rules = 0, n_conds = 0;
+  aerl_status st = validate_population(ctx, pop, nf, nc, &n_rules, &n_conds);
+  if (st) return st;
+  const PackedLayout L = packed_layout(pop->n_sets, n_rules, n_conds);
+  if (!ws || ((uintptr_t)ws & 255)) return fail(ctx, AERL_EINVAL, "ws is NULL or not 256-byte aligned");
+  if (ws_bytes < L.total) return fail(ctx, AERL_ENOMEM, "ws holds %zu bytes, %zu needed", ws_bytes, L.total);
+  AERL_HIP(ctx, hipSetDevice(ctx->device));
+  PopRec rec;
+  AERL_HIP(ctx, hipHostMalloc(&rec.staging, L.total, hipHostMallocDefault));
+  pack_population_image(pop, nf, nc, n_rules, n_conds, rec.staging, &rec);
+  hipError_t e = hipMemcpyAsync(ws, rec.staging, L.total, hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&rec.staged, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventRecord(rec.staged, stream);
+  if (e != hipSuccess) {
+    (void)hipStreamSynchronize(stream);
+    if (rec.staged) (void)hipEventDestroy(rec.staged);
+    (void)hipHostFree(rec.staging);
+    return fail(ctx, AERL_EDEVICE, "staging copy failed: %s", hipGetErrorString(e));
+  }
+  char *b = static_cast<char *>(ws);
+  rec.sets = reinterpret_cast<const int4 *>(b + L.sets_off);
+  rec.rules = reinterpret_cast<const int4 *>(b + L.rules_off);
+  rec.hconds = reinterpret_cast<const uint4 *>(b + L.hconds_off);
+  rec.sconds = reinterpret_cast<const uint32_t *>(b + L.sconds_off);
+  const int32_t id = ctx->next_id++;
+  ctx->pops[id] = rec;
+  *pop_id = id;
+  return AERL_OK;
+}
+
+aerl_status aerl_pack_population_host(const aerl_population *pop, int32_t nf, int32_t nc, void *dst,
+                                      size_t dst_bytes) {
+  int32_t n_rules = 0, n_conds = 0;
+  aerl_status st = validate_population(nullptr, pop, nf, nc, &n_rules, &n_conds);
+  if (st) return st;
+  const PackedLayout L = packed_layout(pop->n_sets, n_rules, n_conds);
+  if (!dst || dst_bytes < L.total) return AERL_ENOMEM;
+  PopRec rec;
+  pack_population_image(pop, nf, nc, n_rules, n_conds, dst, &rec);
+  return AERL_OK;
+}
+
+aerl_status aerl_release_population(aerl_ctx *ctx, int32_t pop_id) {
+  if (!ctx) return AERL_EINVAL;
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  auto it = ctx->pops.find(pop_id);
+  if (it == ctx->pops.end()) return fail(ctx, AERL_ENOENT, "unknown population %d", pop_id);
+  if (it->second.staged) {
+    (void)hipEventSynchronize(it->second.staged);
+    (void)hipEventDestroy(it->second.staged);
+  }
+  if (it->second.staging) (void)hipHostFree(it->second.staging);
+  ctx->pops.erase(it);
+  return AERL_OK;
+}
+
+static aerl_status eval_common(aerl_ctx *ctx, int32_t dataset_id, int32_t pop_id, int32_t *correct,
+                               int32_t *confusion, int S, int Q, int TG, hipStream_t stream) {
+  if (!ctx) return AERL_EINVAL;
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  ctx->err.clear();
+  auto di = ctx->datasets.find(dataset_id);
+  if (di == ctx->datasets.end()) return fail(ctx, AERL_ENOENT, "unknown dataset %d", dataset_id);
+  auto pi = ctx->pops.find(pop_id);
+  if (pi == ctx->pops.end()) return fail(ctx, AERL_ENOENT, "unknown population %d", pop_id);
+  const DatasetRec &ds = di->second;
+  const PopRec &pop = pi->second;
+  if (pop.nf != ds.nf || pop.nc != ds.nc)
+    return fail(ctx, AERL_EINVAL, "population has %d features / %d classes, dataset %d / %d", pop.nf,
+                pop.nc, ds.nf, ds.nc);
+  if (!correct && pop.n_sets > 0) return fail(ctx, AERL_EINVAL, "correct is NULL");
+  HardLaunch h{};
+  h.ds = &ds;
+  h.pop = &pop;
+  h.set_begin = 0;
+  h.set_count = pop.n_sets;
+  h.correct = correct;
+  h.confusion = confusion;
+  if (S == 0) {
+    hard_config(ds, pop.n_sets, ctx->n_cu, &h.samples_per_lane, &h.sets_per_chunk, &h.tiles_per_group);
+  } else {
+    if (S != 1 && S != 2 && S != 4) return fail(ctx, AERL_EINVAL, "samples_per_lane %d not in {1,2,4}", S);
+    if (Q < 1 || TG < 1) return fail(ctx, AERL_EINVAL, "sets_per_chunk and tiles_per_group must be >= 1");
+    if ((size_t)ds.nf * 256 * S + (size_t)Q * ds.nc * 4 > 160 * 1024)
+      return fail(ctx, AERL_EINVAL, "configuration needs more than 160 KiB of LDS");
+    h.samples_per_lane = S;
+    h.sets_per_chunk = Q;
+    h.tiles_per_group = TG;
+  }
+  AERL_HIP(ctx, hipSetDevice(ctx->device));
+  AERL_HIP(ctx, launch_fill_i32(correct, pop.n_sets, 0, stream));
+  if (confusion) AERL_HIP(ctx, launch_fill_i32(confusion, (int64_t)pop.n_sets * ds.nc * ds.nc, 0, stream));
+  AERL_HIP(ctx, launch_hard_eval(h, stream));
+  return AERL_OK;
+}
+
+aerl_status aerl_eval_population(aerl_ctx *ctx, int32_t dataset_id, int32_t pop_id, int32_t *correct,
+                                 int32_t *confusion, hipStream_t stream) {
+  return eval_common(ctx, dataset_id, pop_id, correct, confusion, 0, 0, 0, stream);
+}
+
+aerl_status aerl_eval_population_cfg(aerl_ctx *ctx, int32_t dataset_id, int32_t pop_id,
+                                     int32_t *correct, int32_t *confusion, int32_t samples_per_lane,
+                                     int32_t sets_per_chunk, int32_t tiles_per_group,
+                                     hipStream_t stream) {
+  if (samples_per_lane == 0) samples_per_lane = -1;  // 0 is reserved for the default choice
+  return eval_common(ctx, dataset_id, pop_id, correct, confusion, samples_per_lane, sets_per_chunk,
+                     tiles_per_group, stream);
+}
+
+aerl_status aerl_predict(aerl_ctx *ctx, int32_t pop_id, int32_t set, const float *rows, int64_t n,
+                         int32_t *pred, hipStream_t stream) {
+  if (!ctx) return AERL_EINVAL;
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  ctx->err.clear();
+  auto pi = ctx->pops.find(pop_id);
+  if (pi == ctx->pops.end()) return fail(ctx, AERL_ENOENT, "unknown population %d", pop_id);
+  const PopRec &pop = pi->second;
+  if (set < 0 || set >= pop.n_sets) return fail(ctx, AERL_EINVAL, "set %d outside [0, %d)", set, pop.n_sets);
+  if (n < 0) return fail(ctx, AERL_EINVAL, "n < 0");
+  if (n > 0 && (!rows || !pred)) return fail(ctx, AERL_EINVAL, "rows or pred is NULL");
+  AERL_HIP(ctx, hipSetDevice(ctx->device));
+  AERL_HIP(ctx, launch_predict(pop, set, rows, n, pred, stream));
+  return AERL_OK;
+}
+
+aerl_status aerl_soft_workspace_bytes(aerl_ctx *ctx, int32_t dataset_id, int32_t pop_id,
+                                      size_t *forward_bytes, size_t *backward_bytes) {
+  if (!ctx) return AERL_EINVAL;
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  auto di = ctx->datasets.find(dataset_id);
+  if (di == ctx->datasets.end()) return fail(ctx, AERL_ENOENT, "unknown dataset %d", dataset_id);
+  auto pi = ctx->pops.find(pop_id);
+  if (pi == ctx->pops.end()) return fail(ctx, AERL_ENOENT, "unknown population %d", pop_id);
+  if (forward_bytes) *forward_bytes = soft_ws_bytes(di->second, pi->second, false);
+  if (backward_bytes) *backward_bytes = soft_ws_bytes(di->second, pi->second, true);
+  return AERL_OK;
+}
+
+static aerl_status soft_common(aerl_ctx *ctx, int32_t dataset_id, int32_t pop_id, SoftLaunch *l,
+                               bool backward) {
+  auto di = ctx->datasets.find(dataset_id);
+  if (di == ctx->datasets.end()) return fail(ctx, AERL_ENOENT, "unknown dataset %d", dataset_id);
+  auto pi = ctx->pops.find(pop_id);
+  if (pi == ctx->pops.end()) return fail(ctx, AERL_ENOENT, "unknown population %d", pop_id);
+  const DatasetRec &ds = di->second;
+  const PopRec &pop = pi->second;
+  if (pop.nf != ds.nf || pop.nc != ds.nc)
+    return fail(ctx, AERL_EINVAL, "population and dataset shapes differ");
+  if (pop.n_conds > 0 && (!l->coef || !l->coef2 || !l->theta))
+    return fail(ctx, AERL_EINVAL, "a parameter array is NULL");
+  const size_t need = soft_ws_bytes(ds, pop, backward);
+  if (need && (!l->ws || ((uintptr_t)l->ws & 255)))
+    return fail(ctx, AERL_EINVAL, "ws is NULL or not 256-byte aligned");
+  if (l->ws_bytes < need) return fail(ctx, AERL_ENOMEM, "ws holds %zu bytes, %zu needed", l->ws_bytes, need);
+  l->ds = &ds;
+  l->pop = &pop;
+  return AERL_OK;
+}
+
+aerl_status aerl_soft_forward(aerl_ctx *ctx, int32_t dataset_id, int32_t pop_id, const float *coef,
+                              const float *coef2, const float *theta, float *loss, void *ws,
+                              size_t ws_bytes, hipStream_t stream) {
+  if (!ctx) return AERL_EINVAL;
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  ctx->err.clear();
+  SoftLaunch l{};
+  l.coef = coef; l.coef2 = coef2; l.theta = theta; l.loss = loss; l.ws = ws; l.ws_bytes = ws_bytes;
+  aerl_status st = soft_common(ctx, dataset_id, pop_id, &l, false);
+  if (st) return st;
+  if (!loss && l.pop->n_sets > 0) return fail(ctx, AERL_EINVAL, "loss is NULL");
+  AERL_HIP(ctx, hipSetDevice(ctx->device));
+  AERL_HIP(ctx, launch_soft_forward(l, stream));
+  return AERL_OK;
+}
+
+aerl_status aerl_soft_backward(aerl_ctx *ctx, int32_t dataset_id, int32_t pop_id, const float *coef,
+                               const float *coef2, const float *theta, const float *dloss,
+                               float *dcoef, float *dcoef2, float *dtheta, void *ws, size_t ws_bytes,
+                               hipStream_t stream) {
+  if (!ctx) return AERL_EINVAL;
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  ctx->err.clear();
+  SoftLaunch l{};
+  l.coef = coef; l.coef2 = coef2; l.theta = theta; l.dloss = dloss;
+  l.dcoef = dcoef; l.dcoef2 = dcoef2; l.dtheta = dtheta; l.ws = ws; l.ws_bytes = ws_bytes;
+  aerl_status st = soft_common(ctx, dataset_id, pop_id, &l, true);
+  if (st) return st;
+  if (l.pop->n_conds > 0 && (!dcoef || !dcoef2 || !dtheta))
+    return fail(ctx, AERL_EINVAL, "a gradient array is NULL");
+  if (l.pop->n_sets > 0 && !dloss) return fail(ctx, AERL_EINVAL, "dloss is NULL");
+  AERL_HIP(ctx, hipSetDevice(ctx->device));
+  AERL_HIP(ctx, launch_soft_backward(l, stream));
+  return AERL_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,133 @@
+// Internal declarations shared by the libaerl sources (host and device).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "aerl.h"
+
+namespace aerl {
+
+// ------------------------------------------------------------ error helpers
+struct Error {
+  aerl_status code;
+  std::string msg;
+};
+
+// Fill ctx->err and return code.  printf-style message.
+aerl_status fail(aerl_ctx *ctx, aerl_status code, const char *fmt, ...);
+
+#define AERL_HIP(ctx, call)                                                              \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return ::aerl::fail((ctx), AERL_EDEVICE, "%s failed: %s (%s:%d)", #call,           \
+                          hipGetErrorString(e_), __FILE__, __LINE__);                    \
+  } while (0)
+
+// ------------------------------------------------------------ packed records
+// Rule set: {first rule, rule count, default class, nominal condition count}.
+// Rule: {first hard condition, group counts (threshold | ff-gt << 8 | ff-ge << 16),
+//        class, first condition in the caller's order}.
+// Hard condition (16 bytes): {f*1024, a, b, g*1024} (byte offsets of the
+// feature rows in a 256-sample LDS tile).  Threshold conditions are
+// stored as  a*x[f] > b ; feature conditions as  a*x[f] > b*x[g]  (ff-gt group)
+// or  a*x[f] >= b*x[g]  (ff-ge group).  The rewriting is exact (see pack.cpp).
+// Soft condition (caller order): f | g << 12 | kind << 24 | (op >= 2) << 25.
+struct PackedLayout {
+  size_t sets_off, rules_off, hconds_off, sconds_off, total;
+};
+
+struct DatasetRec {
+  int64_t n = 0, n_pad = 0, n_tiles = 0;
+  int32_t nf = 0, nc = 0;
+  float *x_fm = nullptr;       // [nf][n_pad]
+  int32_t *y_pad = nullptr;    // [n_pad]
+  int32_t *perm = nullptr;     // [n_pad]
+  int32_t *tile_info = nullptr;// [n_tiles]: label | valid << 8
+  float *tau = nullptr;        // [nf]
+  int64_t class_count[AERL_MAX_CLASSES] = {};
+  int32_t region_tile0[AERL_MAX_CLASSES] = {};
+  int32_t region_tiles[AERL_MAX_CLASSES] = {};
+};
+
+struct PopRec {
+  int32_t n_sets = 0, n_rules = 0, n_conds = 0, nf = 0, nc = 0;
+  int32_t max_rules = 0, max_rule_conds = 0;
+  int64_t nominal_conds = 0;
+  const int4 *sets = nullptr;
+  const int4 *rules = nullptr;
+  const uint4 *hconds = nullptr;
+  const uint32_t *sconds = nullptr;
+  void *staging = nullptr;     // pinned host copy of the packed image
+  hipEvent_t staged = nullptr; // completion of the staging copy
+};
+
+}  // namespace aerl
+
+struct aerl_ctx {
+  int device = 0;
+  int n_cu = 0;
+  std::string err;
+  std::recursive_mutex mu;
+  int32_t next_id = 1;
+  std::unordered_map<int32_t, aerl::DatasetRec> datasets;
+  std::unordered_map<int32_t, aerl::PopRec> pops;
+  struct Serve *serve = nullptr;
+};
+
+namespace aerl {
+
+// ------------------------------------------------------------ kernel launchers
+// All return hipSuccess or the first HIP error.
+hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
+
+struct HardLaunch {
+  const DatasetRec *ds;
+  const PopRec *pop;
+  int32_t set_begin, set_count;  // rule sets [set_begin, set_begin+set_count)
+  int32_t *correct;              // indexed by set - set_begin
+  int32_t *confusion;            // may be null
+  int samples_per_lane;          // 1, 2 or 4
+  int sets_per_chunk;
+  int tiles_per_group;           // layout tiles per block
+};
+hipError_t launch_hard_eval(const HardLaunch &h, hipStream_t s);
+
+hipError_t launch_predict(const PopRec &pop, int32_t set, const float *rows, int64_t n,
+                          int32_t *pred, hipStream_t s);
+
+// Upload steps (layout.hip)
+hipError_t launch_validate_count(const float *x, const int32_t *y, int64_t n, int32_t nf,
+                                 int32_t nc, int32_t *block_counts, int32_t *flags,
+                                 int64_t n_blocks, hipStream_t s);
+hipError_t launch_scatter_transpose(const float *x, const int32_t *y, int64_t n, int32_t nf,
+                                    int32_t nc, const int32_t *block_base, float *x_fm,
+                                    int32_t *y_pad, int32_t *perm, int64_t n_pad,
+                                    int64_t n_blocks, hipStream_t s);
+hipError_t launch_tau(const float *x_fm, const int32_t *y_pad, int64_t n_pad, int32_t nf,
+                      int64_t n, float *tau, hipStream_t s);
+constexpr int kUploadBlock = 256;  // samples per block in the upload kernels
+
+// Soft path (soft.hip)
+struct SoftLaunch {
+  const DatasetRec *ds;
+  const PopRec *pop;
+  const float *coef, *coef2, *theta;
+  const float *dloss;            // backward only
+  float *loss;                   // forward only
+  float *dcoef, *dcoef2, *dtheta;
+  void *ws;
+  size_t ws_bytes;
+};
+size_t soft_ws_bytes(const DatasetRec &ds, const PopRec &pop, bool backward);
+hipError_t launch_soft_forward(const SoftLaunch &l, hipStream_t s);
+hipError_t launch_soft_backward(const SoftLaunch &l, hipStream_t s);
+
+}  // namespace aerl

@@ -1,0 +1,196 @@
+// Population validation and packing (host side).
+//
+// The caller hands over rule sets in the paper's tensorized form, stored
+// sparsely: each condition is a rule-tensor row with one weight and a bias
+// (threshold) or two weights and zero bias (feature-vs-feature), Section 3
+// and Fig. 1a.  The packed form regroups each rule's conditions (a rule is an
+// AND, so their order never changes a result) and rewrites every condition
+// exactly into one of three comparison forms the kernels evaluate:
+//
+//   threshold   a*x[f] > b        from  c*x op t:
+//       >   a = c,  b = t
+//       <   a = -c, b = -t                    (-fl(c*x) == fl(-c*x))
+//       >=  a = c,  b = next_down(t)          (no float lies strictly between)
+//       <=  a = -c, b = -next_up(t)
+//       >= -inf and <= +inf always hold and become 0*x > -1.
+//   feature     a*x[f] > b*x[g]   (> as is, < with both weights negated)
+//               a*x[f] >= b*x[g]  (>= as is, <= with both weights negated)
+//
+// Products and comparisons are IEEE fp32 and never NaN for finite inputs, so
+// each rewrite gives the caller's result bit for bit.
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+
+#include "internal.h"
+
+namespace aerl {
+
+namespace {
+
+struct HostPacked {
+  std::vector<int4> sets;
+  std::vector<int4> rules;
+  std::vector<uint4> hconds;
+  std::vector<uint32_t> sconds;
+};
+
+uint32_t fbits(float v) {
+  uint32_t u;
+  std::memcpy(&u, &v, 4);
+  return u;
+}
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+}  // namespace
+
+PackedLayout packed_layout(int32_t n_sets, int32_t n_rules, int32_t n_conds) {
+  PackedLayout L{};
+  size_t off = 0;
+  L.sets_off = off;
+  off = align256(off + sizeof(int4) * (size_t)(n_sets > 0 ? n_sets : 1));
+  L.rules_off = off;
+  off = align256(off + sizeof(int4) * (size_t)(n_rules > 0 ? n_rules : 1));
+  L.hconds_off = off;
+  off = align256(off + sizeof(uint4) * (size_t)(n_conds > 0 ? n_conds : 1));
+  L.sconds_off = off;
+  off = align256(off + sizeof(uint32_t) * (size_t)(n_conds > 0 ? n_conds : 1));
+  L.total = off;
+  return L;
+}
+
+// Validates pop; on success fills the counts.  Returns AERL_OK or AERL_EINVAL
+// with the message in ctx (ctx may be null: then only the code is returned).
+aerl_status validate_population(aerl_ctx *ctx, const aerl_population *p, int32_t nf, int32_t nc,
+                                int32_t *n_rules_out, int32_t *n_conds_out) {
+  if (!p) return fail(ctx, AERL_EINVAL, "population is NULL");
+  if (nf < 1 || nf > AERL_MAX_FEATURES)
+    return fail(ctx, AERL_EINVAL, "n_features %d outside [1, %d]", nf, AERL_MAX_FEATURES);
+  if (nc < 1 || nc > AERL_MAX_CLASSES)
+    return fail(ctx, AERL_EINVAL, "n_classes %d outside [1, %d]", nc, AERL_MAX_CLASSES);
+  if (p->n_sets < 0) return fail(ctx, AERL_EINVAL, "n_sets %d < 0", p->n_sets);
+  if (!p->set_rule_off) return fail(ctx, AERL_EINVAL, "set_rule_off is NULL");
+  if (p->set_rule_off[0] != 0) return fail(ctx, AERL_EINVAL, "set_rule_off[0] != 0");
+  if (p->n_sets > 0 && !p->set_default) return fail(ctx, AERL_EINVAL, "set_default is NULL");
+  for (int32_t s = 0; s < p->n_sets; ++s) {
+    if (p->set_rule_off[s + 1] < p->set_rule_off[s])
+      return fail(ctx, AERL_EINVAL, "set_rule_off decreases at set %d", s);
+    if (p->set_default[s] < 0 || p->set_default[s] >= nc)
+      return fail(ctx, AERL_EINVAL, "set_default[%d] = %d outside [0, %d)", s, p->set_default[s], nc);
+  }
+  const int32_t n_rules = p->set_rule_off[p->n_sets];
+  if (n_rules > 0 && (!p->rule_cond_off || !p->rule_class))
+    return fail(ctx, AERL_EINVAL, "rule arrays are NULL");
+  if (n_rules > 0 && p->rule_cond_off[0] != 0) return fail(ctx, AERL_EINVAL, "rule_cond_off[0] != 0");
+  for (int32_t r = 0; r < n_rules; ++r) {
+    const int32_t k = p->rule_cond_off[r + 1] - p->rule_cond_off[r];
+    if (k < 0) return fail(ctx, AERL_EINVAL, "rule_cond_off decreases at rule %d", r);
+    if (k > AERL_MAX_RULE_CONDS)
+      return fail(ctx, AERL_EINVAL, "rule %d has %d conditions (max %d)", r, k, AERL_MAX_RULE_CONDS);
+    if (p->rule_class[r] < 0 || p->rule_class[r] >= nc)
+      return fail(ctx, AERL_EINVAL, "rule_class[%d] = %d outside [0, %d)", r, p->rule_class[r], nc);
+  }
+  const int32_t n_conds = n_rules > 0 ? p->rule_cond_off[n_rules] : 0;
+  if (n_conds > 0 && (!p->op || !p->kind || !p->f || !p->coef))
+    return fail(ctx, AERL_EINVAL, "condition arrays are NULL");
+  for (int32_t j = 0; j < n_conds; ++j) {
+    if (p->op[j] > 3) return fail(ctx, AERL_EINVAL, "op[%d] = %d is not an operator", j, p->op[j]);
+    if (p->kind[j] > 1) return fail(ctx, AERL_EINVAL, "kind[%d] = %d is not a kind", j, p->kind[j]);
+    if (p->f[j] < 0 || p->f[j] >= nf)
+      return fail(ctx, AERL_EINVAL, "f[%d] = %d outside [0, %d)", j, p->f[j], nf);
+    if (!std::isfinite(p->coef[j])) return fail(ctx, AERL_EINVAL, "coef[%d] is not finite", j);
+    if (p->kind[j] == AERL_KIND_FEATURE) {
+      if (!p->g || !p->coef2) return fail(ctx, AERL_EINVAL, "g/coef2 arrays are NULL");
+      if (p->g[j] < 0 || p->g[j] >= nf)
+        return fail(ctx, AERL_EINVAL, "g[%d] = %d outside [0, %d)", j, p->g[j], nf);
+      if (p->g[j] == p->f[j]) return fail(ctx, AERL_EINVAL, "g[%d] == f[%d]", j, j);
+      if (!std::isfinite(p->coef2[j])) return fail(ctx, AERL_EINVAL, "coef2[%d] is not finite", j);
+    } else {
+      if (!p->theta) return fail(ctx, AERL_EINVAL, "theta array is NULL");
+      if (std::isnan(p->theta[j])) return fail(ctx, AERL_EINVAL, "theta[%d] is NaN", j);
+    }
+  }
+  if (n_rules_out) *n_rules_out = n_rules;
+  if (n_conds_out) *n_conds_out = n_conds;
+  return AERL_OK;
+}
+
+// Writes the packed image of a validated population into `dst` (host memory
+// of PackedLayout::total bytes) and fills the summary fields of `rec`.
+void pack_population_image(const aerl_population *p, int32_t nf, int32_t nc, int32_t n_rules,
+                           int32_t n_conds, void *dst, PopRec *rec) {
+  const PackedLayout L = packed_layout(p->n_sets, n_rules, n_conds);
+  std::memset(dst, 0, L.total);
+  char *base = static_cast<char *>(dst);
+  int4 *sets = reinterpret_cast<int4 *>(base + L.sets_off);
+  int4 *rules = reinterpret_cast<int4 *>(base + L.rules_off);
+  uint4 *hc = reinterpret_cast<uint4 *>(base + L.hconds_off);
+  uint32_t *sc = reinterpret_cast<uint32_t *>(base + L.sconds_off);
+  int32_t max_rules = 0, max_rule_conds = 0;
+  int64_t nominal = 0;
+  for (int32_t s = 0; s < p->n_sets; ++s) {
+    const int32_t r0 = p->set_rule_off[s], r1 = p->set_rule_off[s + 1];
+    const int32_t nominal_s = r1 > r0 ? p->rule_cond_off[r1] - p->rule_cond_off[r0] : 0;
+    sets[s] = make_int4(r0, r1 - r0, p->set_default[s], nominal_s);
+    nominal += nominal_s;
+    if (r1 - r0 > max_rules) max_rules = r1 - r0;
+  }
+  for (int32_t r = 0; r < n_rules; ++r) {
+    const int32_t j0 = p->rule_cond_off[r], j1 = p->rule_cond_off[r + 1];
+    if (j1 - j0 > max_rule_conds) max_rule_conds = j1 - j0;
+    int32_t out = j0;  // hard conditions of rule r occupy [j0, j1) in the packed order
+    int32_t counts[3] = {0, 0, 0};
+    // group 0: thresholds, group 1: feature >, group 2: feature >=
+    for (int grp = 0; grp < 3; ++grp) {
+      for (int32_t j = j0; j < j1; ++j) {
+        const int op = p->op[j];
+        const bool ff = p->kind[j] == AERL_KIND_FEATURE;
+        int my_grp;
+        if (!ff) my_grp = 0;
+        else my_grp = (op == AERL_OP_GT || op == AERL_OP_LT) ? 1 : 2;
+        if (my_grp != grp) continue;
+        float a, b;
+        uint32_t off_f = (uint32_t)p->f[j] * 1024u, off_g = 0;
+        if (!ff) {
+          const float c = p->coef[j], t = p->theta[j];
+          switch (op) {
+            case AERL_OP_GT: a = c; b = t; break;
+            case AERL_OP_LT: a = -c; b = -t; break;
+            case AERL_OP_GE:
+              if (t == -INFINITY) { a = 0.0f; b = -1.0f; }
+              else { a = c; b = std::nextafter(t, -INFINITY); }
+              break;
+            default:  // AERL_OP_LE
+              if (t == INFINITY) { a = 0.0f; b = -1.0f; }
+              else { a = -c; b = -std::nextafter(t, INFINITY); }
+              break;
+          }
+        } else {
+          const bool neg = op == AERL_OP_LT || op == AERL_OP_LE;
+          a = neg ? -p->coef[j] : p->coef[j];
+          b = neg ? -p->coef2[j] : p->coef2[j];
+          off_g = (uint32_t)p->g[j] * 1024u;
+        }
+        hc[out++] = make_uint4(off_f, fbits(a), fbits(b), off_g);
+        counts[grp]++;
+      }
+    }
+    rules[r] = make_int4(j0, counts[0] | (counts[1] << 8) | (counts[2] << 16), p->rule_class[r], j0);
+    for (int32_t j = j0; j < j1; ++j) {
+      const uint32_t g = p->kind[j] == AERL_KIND_FEATURE ? (uint32_t)p->g[j] : 0u;
+      sc[j] = (uint32_t)p->f[j] | (g << 12) | ((uint32_t)p->kind[j] << 24) |
+              ((uint32_t)(p->op[j] >= AERL_OP_GT) << 25);
+    }
+  }
+  rec->n_sets = p->n_sets;
+  rec->n_rules = n_rules;
+  rec->n_conds = n_conds;
+  rec->nf = nf;
+  rec->nc = nc;
+  rec->max_rules = max_rules;
+  rec->max_rule_conds = max_rule_conds;
+  rec->nominal_conds = nominal;
+}
+
+}  // namespace aerl

@@ -1,0 +1,197 @@
+"""GPU parity of the hard path: dataset layout, fitness counts, confusion and
+predictions are bit-exact against the CPU oracle (Section 3 / Fig. 1
+semantics; Section 5: CPU and GPU results are equivalent)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2406_01821_amd import synth
+from paper_2406_01821_amd.population import Dataset, from_rule_lists
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2406_01821_amd.aerl import Context
+    c = Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def run_hard(ctx, data, pop, cfg=None, confusion=True):
+    import torch
+    ds = ctx.upload_dataset(data)
+    p = ctx.pack_population(pop, data.n_features, data.n_classes)
+    correct, conf = ctx.eval_population(ds, p, confusion=confusion, cfg=cfg)
+    torch.cuda.synchronize()
+    return correct.cpu().numpy(), (conf.cpu().numpy() if conf is not None else None)
+
+
+def check_against_oracle(ctx, data, pop, cfg=None):
+    c, m = run_hard(ctx, data, pop, cfg)
+    rc, rm = oracle.hard_eval(data.x, data.y, data.n_classes, pop)
+    np.testing.assert_array_equal(c, rc)
+    np.testing.assert_array_equal(m, rm)
+
+
+def test_upload_layout_groups_labels_and_computes_tau(ctx):
+    import torch
+    w = synth.tiny(1, n=1000, nf=7, n_classes=3)
+    ds = ctx.upload_dataset(w.data)
+    info = ctx.dataset_info(ds)
+    torch.cuda.synchronize()
+    y_pad = info["y_pad"].cpu().numpy()
+    perm = info["perm"].cpu().numpy()
+    x_fm = info["x_fm"].cpu().numpy()
+    counts = np.bincount(w.data.y, minlength=3)
+    assert info["class_count"] == list(counts)
+    valid = perm >= 0
+    assert valid.sum() == w.data.n
+    assert np.array_equal(np.sort(perm[valid]), np.arange(w.data.n))
+    assert np.array_equal(y_pad[valid], w.data.y[perm[valid]])
+    assert np.all(y_pad[~valid] == -1)
+    # stable grouping: within each class the original order is kept
+    for c in range(3):
+        idx = perm[y_pad == c]
+        assert np.all(np.diff(idx) > 0)
+    assert np.array_equal(x_fm[:, valid].T, w.data.x[perm[valid]])
+    assert info["n_pad"] % 256 == 0
+    tau = info["tau"].cpu().numpy()
+    ref = oracle.tau(w.data.x)
+    ulps = np.abs(tau.view(np.int32) - ref.view(np.int32))
+    assert ulps.max() <= 1
+
+
+def test_small_workload_bit_exact(ctx):
+    w = synth.small_hard(0)
+    check_against_oracle(ctx, w.data, w.pop)
+
+
+@pytest.mark.parametrize("cfg", [(1, 1, 1), (2, 3, 1), (4, 7, 2), (4, 100, 5), (1, 64, 3), (2, 256, 1)])
+def test_every_launch_configuration_bit_exact(ctx, cfg):
+    w = synth.tiny(12, n=3000, nf=13, n_classes=3, n_sets=150, rules=(0, 9), conds=(0, 5))
+    check_against_oracle(ctx, w.data, w.pop, cfg)
+
+
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 255, 256, 257, 511, 1000, 4097])
+def test_ragged_sample_counts(ctx, n):
+    w = synth.tiny(100 + n, n=n, nf=5, n_classes=2, n_sets=40)
+    check_against_oracle(ctx, w.data, w.pop)
+
+
+@pytest.mark.parametrize("nc", [1, 2, 4, 5, 64])
+def test_class_counts(ctx, nc):
+    w = synth.tiny(7 + nc, n=2000, nf=6, n_classes=nc, n_sets=30)
+    check_against_oracle(ctx, w.data, w.pop)
+
+
+def test_missing_classes_and_single_class(ctx):
+    w = synth.tiny(9, n=700, nf=4, n_classes=4, n_sets=25)
+    y = np.where(w.data.y == 2, 0, w.data.y).astype(np.int32)  # class 2 absent
+    check_against_oracle(ctx, Dataset(w.data.x, y, 4), w.pop)
+    check_against_oracle(ctx, Dataset(w.data.x, np.zeros_like(y), 4), w.pop)
+
+
+def test_edge_values_subnormals_infinities_ties(ctx):
+    rng = np.random.default_rng(5)
+    n = 900
+    x = rng.uniform(-2, 2, size=(n, 4)).astype(np.float32)
+    x[:100, 0] = np.ldexp(rng.uniform(-1, 1, 100), -130).astype(np.float32)  # subnormal
+    x[100:150, 0] = 0.0
+    x[150:200, 0] = -0.0
+    x[200:260, 1] = np.float32(3e38)
+    x[260:300, 1] = np.float32(-3e38)
+    x[300:400, 2] = np.float32(0.75)
+    y = rng.integers(0, 2, n).astype(np.int32)
+    conds = []
+    for op in range(4):
+        for t in (0.75, 0.0, -0.0, np.inf, -np.inf, 1e-40, -1e-40, 1e-45, 3.4e38):
+            for c in (1.0, -1.0, 0.0, 1e-3, 4.0):
+                for f in (0, 1, 2):
+                    conds.append(dict(op=op, kind=0, f=f, coef=np.float32(c), theta=np.float32(t)))
+        for c, c2 in ((1.0, 1.0), (-1.0, 1e-38), (0.0, 0.0), (2.0, -3.0), (1e-20, 1e-20)):
+            conds.append(dict(op=op, kind=1, f=0, g=1, coef=np.float32(c), coef2=np.float32(c2)))
+            conds.append(dict(op=op, kind=1, f=2, g=0, coef=np.float32(c), coef2=np.float32(c2)))
+    pop = from_rule_lists([(0, [(1, [c])]) for c in conds])
+    check_against_oracle(ctx, Dataset(x, y, 2), pop)
+
+
+def test_empty_population_rules_and_sets(ctx):
+    w = synth.tiny(3, n=500, nf=5)
+    pop = from_rule_lists([(1, []), (0, [(1, [])]), (1, [(0, []), (1, [])])] +
+                          [w.pop.to_rule_list(s) for s in range(5)])
+    check_against_oracle(ctx, w.data, pop)
+
+
+def test_permutation_invariance_on_device(ctx):
+    w = synth.tiny(15, n=3000, nf=6, n_sets=60)
+    c0, m0 = run_hard(ctx, w.data, w.pop)
+    perm = np.random.default_rng(1).permutation(w.data.n)
+    c1, m1 = run_hard(ctx, Dataset(w.data.x[perm], w.data.y[perm], 2), w.pop)
+    assert np.array_equal(c0, c1) and np.array_equal(m0, m1)
+
+
+def test_repeated_calls_are_identical_and_outputs_overwritten(ctx):
+    import torch
+    w = synth.tiny(16, n=5000, nf=9, n_sets=120)
+    ds = ctx.upload_dataset(w.data)
+    p = ctx.pack_population(w.pop, 9, 2)
+    out = ctx.eval_population(ds, p)
+    first = [t.clone() for t in out]
+    for _ in range(3):
+        ctx.eval_population(ds, p, out=out)
+    torch.cuda.synchronize()
+    assert torch.equal(first[0], out[0]) and torch.equal(first[1], out[1])
+
+
+def test_scaled_workload_slice_bit_exact(ctx):
+    w = synth.scaled_hard(1, n=1 << 16, nf=64, n_sets=256)
+    check_against_oracle(ctx, w.data, w.pop)
+
+
+def test_scaled_workload_full_size_sampled_sets(ctx):
+    """2^20 x 64, 4096 rule sets, in the benchmark's launch configuration;
+    32 sampled rule sets are recomputed by the oracle one by one."""
+    w = synth.scaled_hard(1)
+    c, m = run_hard(ctx, w.data, w.pop)
+    sample = np.random.default_rng(0).choice(w.pop.n_sets, 32, replace=False)
+    sub = w.pop.subset(sample)
+    rc, rm = oracle.hard_eval(w.data.x, w.data.y, 4, sub)
+    np.testing.assert_array_equal(c[sample], rc)
+    np.testing.assert_array_equal(m[sample], rm)
+    assert np.all(m.sum(axis=(1, 2)) == w.data.n)
+    assert np.array_equal(np.trace(m, axis1=1, axis2=2), c)
+
+
+@pytest.mark.parametrize("n", [1, 63, 64, 255, 256, 257, 4096])
+def test_predict_matches_oracle(ctx, n):
+    import torch
+    w = synth.tiny(40 + n, n=max(n, 10), nf=11, n_sets=6, rules=(1, 12), conds=(1, 5))
+    rows = w.data.x[:n]
+    p = ctx.pack_population(w.pop, 11, 2)
+    for s in range(w.pop.n_sets):
+        got = ctx.predict(p, rows, s)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(got.cpu().numpy(), oracle.predict(rows, w.pop, s))
+
+
+def test_invalid_inputs_raise(ctx):
+    from paper_2406_01821_amd.aerl import AerlError
+    w = synth.tiny(2, n=50, nf=3)
+    bad = Dataset(w.data.x.copy(), w.data.y, 2)
+    bad.x[3, 1] = np.nan
+    with pytest.raises(AerlError):
+        ctx.upload_dataset(bad)
+    with pytest.raises(AerlError):
+        ctx.upload_dataset(Dataset(w.data.x, np.full(50, 2, np.int32), 2))
+    ds = ctx.upload_dataset(w.data)
+    p = ctx.pack_population(w.pop, 3, 2)
+    other = synth.tiny(2, n=50, nf=4)
+    p4 = ctx.pack_population(other.pop, 4, 2)
+    with pytest.raises(AerlError):
+        ctx.eval_population(ds, p4)
+    with pytest.raises(AerlError):
+        ctx.predict(p, w.data.x, set_index=w.pop.n_sets)

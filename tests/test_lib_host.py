@@ -1,0 +1,142 @@
+"""Host-side tests of libaerl (no GPU): the library loads and exports every
+entry point the header declares, argument validation, and the exact rewriting
+of conditions done by the packer (checked against the oracle on CPU)."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2406_01821_amd import synth
+from paper_2406_01821_amd.population import from_rule_lists
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def aerl():
+    from paper_2406_01821_amd import aerl as mod
+    return mod
+
+
+def header_symbols():
+    text = open(os.path.join(ROOT, "include", "aerl.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:aerl_status|void|const char \*)\s*(aerl_\w+)\(", text, re.M)))
+
+
+def test_library_exports_every_declared_symbol(aerl):
+    names = header_symbols()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(aerl.lib, n), n
+        assert n in aerl.EXPORTED, n
+
+
+def test_dataset_bytes_validation(aerl):
+    import ctypes as C
+    out = C.c_size_t()
+    assert aerl.aerl_dataset_bytes(569, 30, 2, C.byref(out)) == 0
+    # features [30][(3 tiles + 2 classes) * 256] + labels, perm, tiles, tau, scratch
+    assert out.value >= 30 * 5 * 256 * 4
+    assert aerl.aerl_dataset_bytes(-1, 30, 2, C.byref(out)) == aerl.AERL_EINVAL
+    assert aerl.aerl_dataset_bytes(10, 0, 2, C.byref(out)) == aerl.AERL_EINVAL
+    assert aerl.aerl_dataset_bytes(10, 513, 2, C.byref(out)) == aerl.AERL_EINVAL
+    assert aerl.aerl_dataset_bytes(10, 4, 65, C.byref(out)) == aerl.AERL_EINVAL
+    assert aerl.aerl_dataset_bytes(0, 4, 2, C.byref(out)) == 0
+
+
+def _cond(**kw):
+    d = dict(op=2, kind=0, f=0, g=0, coef=np.float32(1), coef2=np.float32(0), theta=np.float32(0))
+    d.update(kw)
+    return d
+
+
+@pytest.mark.parametrize("bad", [
+    dict(op=4), dict(kind=2), dict(f=5), dict(f=-1), dict(kind=1, g=0), dict(kind=1, g=7),
+    dict(coef=np.float32(np.nan)), dict(coef=np.float32(np.inf)), dict(theta=np.float32(np.nan)),
+    dict(kind=1, g=1, coef2=np.float32(np.inf))])
+def test_population_validation_rejects(aerl, bad):
+    pop = from_rule_lists([(0, [(1, [_cond(), _cond(**bad)])])])
+    assert aerl.population_status(pop, 5, 2) == aerl.AERL_EINVAL
+
+
+def test_population_validation_rejects_structure(aerl):
+    ok = from_rule_lists([(0, [(1, [_cond()])]), (1, [])])
+    assert aerl.population_status(ok, 5, 2) == 0
+    bad_cls = from_rule_lists([(0, [(2, [_cond()])])])
+    assert aerl.population_status(bad_cls, 5, 2) == aerl.AERL_EINVAL
+    bad_default = from_rule_lists([(3, [])])
+    assert aerl.population_status(bad_default, 5, 2) == aerl.AERL_EINVAL
+    big = from_rule_lists([(0, [(1, [_cond()] * 256)])])
+    assert aerl.population_status(big, 5, 2) == aerl.AERL_EINVAL
+    inf_theta = from_rule_lists([(0, [(1, [_cond(theta=np.float32(np.inf))])])])
+    assert aerl.population_status(inf_theta, 5, 2) == 0
+
+
+def _align(v):
+    return (v + 255) & ~255
+
+
+def decode_packed(img, n_sets, n_rules, n_conds):
+    sets_off = 0
+    rules_off = _align(sets_off + 16 * max(n_sets, 1))
+    hc_off = _align(rules_off + 16 * max(n_rules, 1))
+    sets = img[sets_off:sets_off + 16 * n_sets].view(np.int32).reshape(-1, 4)
+    rules = img[rules_off:rules_off + 16 * n_rules].view(np.int32).reshape(-1, 4)
+    hc = img[hc_off:hc_off + 16 * n_conds].view(np.uint32).reshape(-1, 4)
+    return sets, rules, hc
+
+
+def eval_packed(x, sets, rules, hc, s):
+    """Evaluates the packed comparison forms a*x[f] > b, a*x[f] > b*x[g],
+    a*x[f] >= b*x[g] with float32 numpy arithmetic."""
+    n = x.shape[0]
+    r0, nr, default, _ = sets[s]
+    pred = np.full(n, default, np.int32)
+    und = np.ones(n, bool)
+    for k in range(r0, r0 + nr):
+        c0, counts, cls, _ = rules[k]
+        nt, ng, ne = counts & 255, (counts >> 8) & 255, (counts >> 16) & 255
+        fire = und.copy()
+        for j in range(c0, c0 + nt + ng + ne):
+            f, a, b, g = hc[j]
+            a = np.uint32(a).view(np.float32)
+            b = np.uint32(b).view(np.float32)
+            lhs = np.float32(a) * x[:, f // 1024]
+            if j < c0 + nt:
+                fire &= lhs > b
+            elif j < c0 + nt + ng:
+                fire &= lhs > np.float32(b) * x[:, g // 1024]
+            else:
+                fire &= lhs >= np.float32(b) * x[:, g // 1024]
+        pred[fire] = cls
+        und &= ~fire
+    return pred
+
+
+def test_packed_rewrite_is_exact_against_oracle(aerl):
+    np.seterr(over="ignore")
+    rng = np.random.default_rng(3)
+    x = rng.uniform(-3, 3, size=(400, 4)).astype(np.float32)
+    x[:20, 0] = 0.0
+    x[20:40, 0] = -0.0
+    x[40:60, 1] = np.float32(1.5)
+    x[60:70, 2] = np.float32(3e38)
+    conds = []
+    for op in range(4):
+        for t in (1.5, 0.0, -0.0, np.inf, -np.inf, 1e-45, -1e-45, 3.4e38, -2.25):
+            for c in (1.0, -1.0, 0.0, 0.5, 2.0):
+                conds.append(_cond(op=op, f=int(rng.integers(4)), coef=np.float32(c), theta=np.float32(t)))
+        for c, c2 in ((1.0, 1.0), (-1.0, 0.5), (0.0, 0.0), (2.0, -3.0)):
+            conds.append(_cond(op=op, kind=1, f=1, g=2, coef=np.float32(c), coef2=np.float32(c2)))
+    sets = [(0, [(1, [c])]) for c in conds]
+    w = synth.tiny(4, n=300, nf=4, n_sets=40, rules=(1, 6), conds=(1, 4))
+    sets += [w.pop.to_rule_list(s) for s in range(w.pop.n_sets)]
+    pop = from_rule_lists(sets)
+    img = aerl.pack_host(pop, 4, 2)
+    S, R, H = decode_packed(img, pop.n_sets, pop.n_rules, pop.n_conds)
+    xx = np.concatenate([x, w.data.x[:, :4]])
+    for s in range(pop.n_sets):
+        np.testing.assert_array_equal(eval_packed(xx, S, R, H, s), oracle.predict(xx, pop, s),
+                                      err_msg=str(s))
