@@ -21,6 +21,8 @@
 
 #include <cstdint>
 
+#include "internal.h"
+
 namespace aerl {
 
 // LDS tile row of S*64 samples for one feature: lane holds samples
@@ -70,107 +72,241 @@ __device__ __forceinline__ T ldc(const T *p, int64_t i) {
   return ldc_at(p + i, 0u);
 }
 
-// Evaluates rule set `set` = {first rule, #rules, default, -} for the S*64
-// samples of the tile.  vm[s]: lanes whose slot-s sample is real.
+// Evaluates rule set `set` = {first record, record count, default, -} of the
+// hard stream for the S*64 samples of the tile.  vm[s]: lanes whose slot-s
+// sample is real.
 // COUNT mode (PRED = false): returns, in lane c, the number of the tile's
 //   real samples predicted as class c.
 // PRED mode: pred[s] receives the predicted class of each lane's samples.
+// Portable form (any S, both modes); the 4-slot counting path below is the
+// same loop written for the scalar unit by hand.
 template <int S, bool PRED>
 __device__ __forceinline__ int eval_set(const float *__restrict__ xs, int lane, int4 set,
-                                        const int4 *__restrict__ rules,
-                                        const uint4 *__restrict__ conds, const uint64_t (&vm)[S],
-                                        int (&pred)[S]) {
-  uint64_t und[S];
+                                        const uint4 *__restrict__ stream,
+                                        const uint64_t (&vm)[S], int (&pred)[S]) {
+  uint64_t und[S], fire[S];
 #pragma unroll
-  for (int s = 0; s < S; ++s) und[s] = vm[s];
+  for (int s = 0; s < S; ++s) und[s] = fire[s] = vm[s];
   int acc = 0;
-  const int rb = set.x, nr = set.y;
-  for (int k = 0; k < nr; ++k) {
-    const int4 r = ldc(rules, rb + k);
-    uint64_t fire[S];
+  const uint4 *base = stream + set.x;
+  uint32_t end = (uint32_t)set.y * 16u;
+  uint32_t o = 0;
+  bool decided = false;
+  while (o < end) {
+    const uint4 r = ldc_at(base, o);
+    const float ca = __uint_as_float(r.y), cb = __uint_as_float(r.z);
+    uint64_t m[S];
+    if ((r.w & kRecFF) == 0) {
+      float v[S];
+      load_row<S>(xs, r.x, lane, v);
 #pragma unroll
-    for (int s = 0; s < S; ++s) fire[s] = und[s];
-    const int nt = r.y & 255, ng = (r.y >> 8) & 255, ne = (r.y >> 16) & 255;
-    const uint4 *cp = conds + r.x;
-    // Three single-exit loops (thresholds, feature >, feature >=).  When no
-    // lane can fire the rule any more (any == 0) the offset jumps to the end;
-    // a dead rule leaves all fire masks zero, so the bookkeeping below needs
-    // no extra branch.
-    uint64_t any = ~0ull;
-    {
-      const uint32_t end = (uint32_t)nt * 16u;
-      for (uint32_t o = 0; o < end;) {
-        const uint4 cc = ldc_at(cp, o);
-        float v[S];
-        load_row<S>(xs, cc.x, lane, v);
-        const float ca = __uint_as_float(cc.y), cb = __uint_as_float(cc.z);
-        any = 0;
+      for (int s = 0; s < S; ++s) m[s] = ballot(ca * v[s] > cb);
+    } else {
+      float v1[S], v2[S];
+      load_row<S>(xs, r.x, lane, v1);
+      load_row<S>(xs, (r.w & kRecGMask) * 1024u, lane, v2);
+      const bool ge = (r.w & kRecGE) != 0;
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-          fire[s] &= ballot(ca * v[s] > cb);
-          any |= fire[s];
-        }
-        o = any == 0 ? end : o + 16u;
+      for (int s = 0; s < S; ++s) {
+        const float p = ca * v1[s], q = cb * v2[s];
+        m[s] = ge ? ballot(p >= q) : ballot(p > q);
       }
     }
-    {
-      const uint32_t end = (uint32_t)(nt + ng) * 16u;
-      for (uint32_t o = any == 0 ? end : (uint32_t)nt * 16u; o < end;) {
-        const uint4 cc = ldc_at(cp, o);
-        float v1[S], v2[S];
-        load_row<S>(xs, cc.x, lane, v1);
-        load_row<S>(xs, cc.w, lane, v2);
-        const float ca = __uint_as_float(cc.y), cb = __uint_as_float(cc.z);
-        any = 0;
+    uint64_t any = 0;
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-          fire[s] &= ballot(ca * v1[s] > cb * v2[s]);
-          any |= fire[s];
+    for (int s = 0; s < S; ++s) {
+      fire[s] &= m[s];
+      any |= fire[s];
+    }
+    uint32_t next = o + 16u;
+    if (any == 0) {  // no undecided lane can fire this rule: next rule
+      next = r.w >> kRecNextShift;
+#pragma unroll
+      for (int s = 0; s < S; ++s) fire[s] = und[s];
+    } else if (r.w & kRecLast) {  // the rule fires: commit it
+      const int cls = (int)((r.w >> kRecClsShift) & 63u);
+      int nfire = 0;
+      uint64_t left = 0;
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        if constexpr (PRED) {
+          if ((fire[s] >> lane) & 1ull) pred[s] = cls;
         }
-        o = any == 0 ? end : o + 16u;
+        nfire += __builtin_popcountll(fire[s]);
+        und[s] &= ~fire[s];
+        left |= und[s];
+        fire[s] = und[s];
+      }
+      if constexpr (!PRED) acc += (lane == cls) ? nfire : 0;
+      if (left == 0) {  // every lane decided
+        decided = true;
+        next = end;
       }
     }
-    {
-      const uint32_t end = (uint32_t)(nt + ng + ne) * 16u;
-      for (uint32_t o = any == 0 ? end : (uint32_t)(nt + ng) * 16u; o < end;) {
-        const uint4 cc = ldc_at(cp, o);
-        float v1[S], v2[S];
-        load_row<S>(xs, cc.x, lane, v1);
-        load_row<S>(xs, cc.w, lane, v2);
-        const float ca = __uint_as_float(cc.y), cb = __uint_as_float(cc.z);
-        any = 0;
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-          fire[s] &= ballot(ca * v1[s] >= cb * v2[s]);
-          any |= fire[s];
-        }
-        o = any == 0 ? end : o + 16u;
-      }
-    }
-    if (any == 0) continue;
-    int nfire = 0;
-    uint64_t left = 0;
+    o = next;
+  }
+  if (!decided) {
+    int nleft = 0;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       if constexpr (PRED) {
-        if ((fire[s] >> lane) & 1ull) pred[s] = r.z;
+        if ((und[s] >> lane) & 1ull) pred[s] = set.z;
       }
-      nfire += __builtin_popcountll(fire[s]);
-      und[s] &= ~fire[s];
-      left |= und[s];
+      nleft += __builtin_popcountll(und[s]);
     }
-    if constexpr (!PRED) acc += (lane == r.z) ? nfire : 0;
-    if (left == 0) return acc;
+    if constexpr (!PRED) acc += (lane == set.z) ? nleft : 0;
   }
-  int nleft = 0;
-#pragma unroll
-  for (int s = 0; s < S; ++s) {
-    if constexpr (PRED) {
-      if ((und[s] >> lane) & 1ull) pred[s] = set.z;
-    }
-    nleft += __builtin_popcountll(und[s]);
-  }
-  if constexpr (!PRED) acc += (lane == set.z) ? nleft : 0;
+  return acc;
+}
+
+// 4-slot counting evaluation written for the scalar unit.  Same semantics as
+// eval_set<4, false>.  Every load is waited on inside the asm block.  Fixed
+// registers: s[84:87] hold the current record, v[32:39] the feature values
+// of the lane's four samples (two rows for feature-vs-feature records).
+//   lds_lane: LDS byte address of the tile plus lane*16.
+#define AERL_T_BODY                                     \
+  "s_waitcnt lgkmcnt(0)\n"                              \
+  "v_mul_f32 v32, s85, v32\n"                           \
+  "v_mul_f32 v33, s85, v33\n"                           \
+  "v_mul_f32 v34, s85, v34\n"                           \
+  "v_mul_f32 v35, s85, v35\n"                           \
+  "v_cmp_lt_f32_e64 %[m0], s86, v32\n"                  \
+  "v_cmp_lt_f32_e64 %[m1], s86, v33\n"                  \
+  "v_cmp_lt_f32_e64 %[m2], s86, v34\n"                  \
+  "v_cmp_lt_f32_e64 %[m3], s86, v35\n"
+
+#define AERL_FF_BODY(TAG)                               \
+  "s_bfe_u32 %[t0], s87, 0x90000\n"                     \
+  "s_lshl_b32 %[t0], %[t0], 10\n"                       \
+  "v_add_u32 %[vt2], %[t0], %[lds]\n"                   \
+  "ds_read_b128 v[36:39], %[vt2]\n"                     \
+  "s_waitcnt lgkmcnt(0)\n"                              \
+  "v_mul_f32 v32, s85, v32\n"                           \
+  "v_mul_f32 v33, s85, v33\n"                           \
+  "v_mul_f32 v34, s85, v34\n"                           \
+  "v_mul_f32 v35, s85, v35\n"                           \
+  "v_mul_f32 v36, s86, v36\n"                           \
+  "v_mul_f32 v37, s86, v37\n"                           \
+  "v_mul_f32 v38, s86, v38\n"                           \
+  "v_mul_f32 v39, s86, v39\n"                           \
+  "s_bitcmp1_b32 s87, 10\n"                             \
+  "s_cbranch_scc1 .Lge_" TAG "_%=\n"                    \
+  "v_cmp_gt_f32_e64 %[m0], v32, v36\n"                  \
+  "v_cmp_gt_f32_e64 %[m1], v33, v37\n"                  \
+  "v_cmp_gt_f32_e64 %[m2], v34, v38\n"                  \
+  "v_cmp_gt_f32_e64 %[m3], v35, v39\n"                  \
+  "s_branch .Land_" TAG "_%=\n"                         \
+  ".Lge_" TAG "_%=:\n"                                  \
+  "v_cmp_ge_f32_e64 %[m0], v32, v36\n"                  \
+  "v_cmp_ge_f32_e64 %[m1], v33, v37\n"                  \
+  "v_cmp_ge_f32_e64 %[m2], v34, v38\n"                  \
+  "v_cmp_ge_f32_e64 %[m3], v35, v39\n"                  \
+  "s_branch .Land_" TAG "_%=\n"
+
+#define AERL_POPC4(A, B, C, D)                          \
+  "s_bcnt1_i32_b64 %[t0], " A "\n"                      \
+  "s_bcnt1_i32_b64 %[t1], " B "\n"                      \
+  "s_add_u32 %[t0], %[t0], %[t1]\n"                     \
+  "s_bcnt1_i32_b64 %[t1], " C "\n"                      \
+  "s_add_u32 %[t0], %[t0], %[t1]\n"                     \
+  "s_bcnt1_i32_b64 %[t1], " D "\n"                      \
+  "s_add_u32 %[t0], %[t0], %[t1]\n"
+
+__device__ __forceinline__ int eval_set_s4_count(uint32_t lds_lane, int lane, int4 set,
+                                                 const uint4 *__restrict__ stream,
+                                                 const uint64_t (&vm)[4]) {
+  const uint4 *base = stream + set.x;
+  const uint32_t end = (uint32_t)set.y * 16u;
+  const int dflt = set.z;
+  uint64_t u0 = vm[0], u1 = vm[1], u2 = vm[2], u3 = vm[3];
+  uint64_t f0, f1, f2, f3, m0, m1, m2, m3;
+  uint32_t o, t0, t1, vt, vt2;
+  int acc = 0;
+  asm volatile(
+      "s_mov_b32 %[o], 0\n"
+      "s_cmp_eq_u32 %[end], 0\n"
+      "s_cbranch_scc1 .Ldefault_%=\n"
+      // first record of a rule: fire = und & m
+      ".Lfirst_%=:\n"
+      "s_load_dwordx4 s[84:87], %[base], %[o]\n"
+      "s_waitcnt lgkmcnt(0)\n"
+      "v_add_u32 %[vt], s84, %[lds]\n"
+      "ds_read_b128 v[32:35], %[vt]\n"
+      "s_bitcmp1_b32 s87, 9\n"
+      "s_cbranch_scc1 .Lff_first_%=\n"
+      AERL_T_BODY
+      ".Land_first_%=:\n"
+      "s_and_b64 %[f3], %[u3], %[m3]\n"
+      "s_and_b64 %[f2], %[u2], %[m2]\n"
+      "s_and_b64 %[f1], %[u1], %[m1]\n"
+      "s_and_b64 %[f0], %[u0], %[m0]\n"
+      "s_cbranch_scc0 .Lcheck_%=\n"
+      ".Lalive_%=:\n"
+      "s_bitcmp1_b32 s87, 11\n"
+      "s_cbranch_scc1 .Lcommit_%=\n"
+      "s_add_u32 %[o], %[o], 16\n"
+      // later record of the same rule: fire &= m
+      "s_load_dwordx4 s[84:87], %[base], %[o]\n"
+      "s_waitcnt lgkmcnt(0)\n"
+      "v_add_u32 %[vt], s84, %[lds]\n"
+      "ds_read_b128 v[32:35], %[vt]\n"
+      "s_bitcmp1_b32 s87, 9\n"
+      "s_cbranch_scc1 .Lff_next_%=\n"
+      AERL_T_BODY
+      ".Land_next_%=:\n"
+      "s_and_b64 %[f3], %[f3], %[m3]\n"
+      "s_and_b64 %[f2], %[f2], %[m2]\n"
+      "s_and_b64 %[f1], %[f1], %[m1]\n"
+      "s_and_b64 %[f0], %[f0], %[m0]\n"
+      "s_cbranch_scc1 .Lalive_%=\n"
+      ".Lcheck_%=:\n"
+      "s_or_b64 %[m0], %[f1], %[f2]\n"
+      "s_or_b64 %[m0], %[m0], %[f3]\n"
+      "s_cbranch_scc1 .Lalive_%=\n"
+      // the rule cannot fire for any undecided lane: go to the next rule
+      "s_lshr_b32 %[o], s87, 18\n"
+      "s_cmp_lt_u32 %[o], %[end]\n"
+      "s_cbranch_scc1 .Lfirst_%=\n"
+      "s_branch .Ldefault_%=\n"
+      ".Lff_first_%=:\n"
+      AERL_FF_BODY("first")
+      ".Lff_next_%=:\n"
+      AERL_FF_BODY("next")
+      // the rule fires for the lanes in f: count them for its class
+      ".Lcommit_%=:\n"
+      AERL_POPC4("%[f0]", "%[f1]", "%[f2]", "%[f3]")
+      "s_bfe_u32 %[t1], s87, 0x6000c\n"
+      "v_cmp_eq_u32_e32 vcc, %[t1], %[lane]\n"
+      "v_mov_b32 %[vt], %[t0]\n"
+      "v_cndmask_b32_e32 %[vt], 0, %[vt], vcc\n"
+      "v_add_u32 %[acc], %[acc], %[vt]\n"
+      "s_andn2_b64 %[u0], %[u0], %[f0]\n"
+      "s_andn2_b64 %[u1], %[u1], %[f1]\n"
+      "s_andn2_b64 %[u2], %[u2], %[f2]\n"
+      "s_andn2_b64 %[u3], %[u3], %[f3]\n"
+      "s_or_b64 %[m0], %[u0], %[u1]\n"
+      "s_or_b64 %[m0], %[m0], %[u2]\n"
+      "s_or_b64 %[m0], %[m0], %[u3]\n"
+      "s_cbranch_scc0 .Ldone_%=\n"
+      "s_lshr_b32 %[o], s87, 18\n"
+      "s_cmp_lt_u32 %[o], %[end]\n"
+      "s_cbranch_scc1 .Lfirst_%=\n"
+      // no rule fired for the remaining lanes: default class
+      ".Ldefault_%=:\n"
+      AERL_POPC4("%[u0]", "%[u1]", "%[u2]", "%[u3]")
+      "v_cmp_eq_u32_e32 vcc, %[dflt], %[lane]\n"
+      "v_mov_b32 %[vt], %[t0]\n"
+      "v_cndmask_b32_e32 %[vt], 0, %[vt], vcc\n"
+      "v_add_u32 %[acc], %[acc], %[vt]\n"
+      ".Ldone_%=:\n"
+      : [acc] "+v"(acc), [u0] "+s"(u0), [u1] "+s"(u1), [u2] "+s"(u2), [u3] "+s"(u3),
+        [f0] "=&s"(f0), [f1] "=&s"(f1), [f2] "=&s"(f2), [f3] "=&s"(f3), [m0] "=&s"(m0),
+        [m1] "=&s"(m1), [m2] "=&s"(m2), [m3] "=&s"(m3), [o] "=&s"(o), [t0] "=&s"(t0),
+        [t1] "=&s"(t1), [vt] "=&v"(vt), [vt2] "=&v"(vt2)
+      : [base] "s"(base), [end] "s"(end), [dflt] "s"(dflt), [lds] "v"(lds_lane),
+        [lane] "v"(lane)
+      : "s84", "s85", "s86", "s87", "v32", "v33", "v34", "v35", "v36", "v37", "v38", "v39",
+        "vcc", "scc", "memory");
   return acc;
 }
 

@@ -20,7 +20,7 @@ namespace aerl {
 
 namespace {
 
-constexpr int kHardBlock = 512;
+constexpr int kHardBlock = 1024;
 
 struct HardArgs {
   const float *x_fm;
@@ -92,7 +92,14 @@ __global__ __launch_bounds__(kHardBlock) void k_hard(const HardArgs a) {
       q = __builtin_amdgcn_readfirstlane(q);
       if (q >= Q) break;
       const int4 set = ldc(a.sets, a.set_begin + q0 + q);
-      const int acc = eval_set<S, false>(xs, lane, set, a.rules, a.conds, vm, dummy);
+      int acc;
+      if constexpr (S == 4) {
+        const uint32_t lds_lane =
+            (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) float *)xs + (uint32_t)lane * 16u;
+        acc = eval_set_s4_count(lds_lane, lane, set, a.conds, vm);
+      } else {
+        acc = eval_set<S, false>(xs, lane, set, a.conds, vm, dummy);
+      }
       if (lane < a.nc) cnt[q * a.nc + lane] += acc;
     }
   }
@@ -133,7 +140,7 @@ __global__ __launch_bounds__(64) void k_predict(const float *__restrict__ rows, 
     vm[s] = ballot(lane * S + s < m);
     pred[s] = set.z;
   }
-  eval_set<S, true>(xs, lane, set, rules, conds, vm, pred);
+  eval_set<S, true>(xs, lane, set, conds, vm, pred);
 #pragma unroll
   for (int s = 0; s < S; ++s)
     if (lane * S + s < m) out[base + lane * S + s] = pred[s];

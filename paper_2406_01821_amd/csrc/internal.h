@@ -32,14 +32,26 @@ aerl_status fail(aerl_ctx *ctx, aerl_status code, const char *fmt, ...);
   } while (0)
 
 // ------------------------------------------------------------ packed records
-// Rule set: {first rule, rule count, default class, nominal condition count}.
-// Rule: {first hard condition, group counts (threshold | ff-gt << 8 | ff-ge << 16),
-//        class, first condition in the caller's order}.
-// Hard condition (16 bytes): {f*1024, a, b, g*1024} (byte offsets of the
-// feature rows in a 256-sample LDS tile).  Threshold conditions are
-// stored as  a*x[f] > b ; feature conditions as  a*x[f] > b*x[g]  (ff-gt group)
-// or  a*x[f] >= b*x[g]  (ff-ge group).  The rewriting is exact (see pack.cpp).
+// Rule set: {first hard-stream record, record count, default class, nominal
+//            condition count}.
+// Rule (soft path): {first condition in the caller's order, condition count,
+//                    class, 0}.
+// Hard stream record (16 bytes), one per condition, rules of a set in order:
+//   x: f*1024 (byte offset of the feature row in a 256-sample LDS tile)
+//   y: a (fp32), z: b (fp32)
+//   w: g | kRecFF | kRecGE | kRecLast | class << 12 | next << 18, where next is
+//      the byte offset (from the set's first record) of the next rule's
+//      first record.
+// Threshold records test a*x[f] > b; feature records a*x[f] > b*x[g] or, with
+// kRecGE, a*x[f] >= b*x[g].  Rewriting the caller's form is exact (pack.cpp).
 // Soft condition (caller order): f | g << 12 | kind << 24 | (op >= 2) << 25.
+constexpr uint32_t kRecGMask = 0x1ffu;
+constexpr uint32_t kRecFF = 1u << 9;
+constexpr uint32_t kRecGE = 1u << 10;
+constexpr uint32_t kRecLast = 1u << 11;
+constexpr uint32_t kRecClsShift = 12;
+constexpr uint32_t kRecNextShift = 18;
+constexpr int32_t kMaxSetRecords = 1023;  // next-rule byte offsets fit 14 bits
 struct PackedLayout {
   size_t sets_off, rules_off, hconds_off, sconds_off, total;
 };

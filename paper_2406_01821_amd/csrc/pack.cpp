@@ -18,6 +18,7 @@
 //
 // Products and comparisons are IEEE fp32 and never NaN for finite inputs, so
 // each rewrite gives the caller's result bit for bit.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstring>
@@ -46,6 +47,9 @@ size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 }  // namespace
 
 PackedLayout packed_layout(int32_t n_sets, int32_t n_rules, int32_t n_conds) {
+  // The hard stream holds one record per condition plus one per empty rule;
+  // n_rules + n_conds bounds it.  One spare record keeps a read-ahead of the
+  // record after the last one inside the buffer.
   PackedLayout L{};
   size_t off = 0;
   L.sets_off = off;
@@ -53,7 +57,7 @@ PackedLayout packed_layout(int32_t n_sets, int32_t n_rules, int32_t n_conds) {
   L.rules_off = off;
   off = align256(off + sizeof(int4) * (size_t)(n_rules > 0 ? n_rules : 1));
   L.hconds_off = off;
-  off = align256(off + sizeof(uint4) * (size_t)(n_conds > 0 ? n_conds : 1));
+  off = align256(off + sizeof(uint4) * ((size_t)n_conds + (size_t)n_rules + 1));
   L.sconds_off = off;
   off = align256(off + sizeof(uint32_t) * (size_t)(n_conds > 0 ? n_conds : 1));
   L.total = off;
@@ -111,6 +115,14 @@ aerl_status validate_population(aerl_ctx *ctx, const aerl_population *p, int32_t
       if (std::isnan(p->theta[j])) return fail(ctx, AERL_EINVAL, "theta[%d] is NaN", j);
     }
   }
+  for (int32_t s = 0; s < p->n_sets; ++s) {
+    int32_t recs = 0;
+    for (int32_t r = p->set_rule_off[s]; r < p->set_rule_off[s + 1]; ++r)
+      recs += std::max(p->rule_cond_off[r + 1] - p->rule_cond_off[r], 1);
+    if (recs > kMaxSetRecords)
+      return fail(ctx, AERL_EINVAL, "rule set %d has %d conditions (+1 per empty rule); max %d", s,
+                  recs, kMaxSetRecords);
+  }
   if (n_rules_out) *n_rules_out = n_rules;
   if (n_conds_out) *n_conds_out = n_conds;
   return AERL_OK;
@@ -129,60 +141,74 @@ void pack_population_image(const aerl_population *p, int32_t nf, int32_t nc, int
   uint32_t *sc = reinterpret_cast<uint32_t *>(base + L.sconds_off);
   int32_t max_rules = 0, max_rule_conds = 0;
   int64_t nominal = 0;
+  // Hard stream: for each rule set its rules in order; inside a rule the
+  // threshold conditions first, then feature >, then feature >=.  An empty
+  // rule (always fires) becomes one always-true record 0*x[0] > -1.
+  int32_t out = 0;
   for (int32_t s = 0; s < p->n_sets; ++s) {
     const int32_t r0 = p->set_rule_off[s], r1 = p->set_rule_off[s + 1];
     const int32_t nominal_s = r1 > r0 ? p->rule_cond_off[r1] - p->rule_cond_off[r0] : 0;
-    sets[s] = make_int4(r0, r1 - r0, p->set_default[s], nominal_s);
+    const int32_t first = out;
+    for (int32_t r = r0; r < r1; ++r) {
+      const int32_t j0 = p->rule_cond_off[r], j1 = p->rule_cond_off[r + 1];
+      const int32_t k = j1 - j0;
+      if (k > max_rule_conds) max_rule_conds = k;
+      const uint32_t cls = (uint32_t)p->rule_class[r] << kRecClsShift;
+      const uint32_t next = (uint32_t)(out - first + std::max(k, 1)) * 16u << kRecNextShift;
+      if (k == 0) {
+        hc[out++] = make_uint4(0u, fbits(0.0f), fbits(-1.0f), kRecLast | cls | next);
+        continue;
+      }
+      int32_t pos = 0;
+      for (int grp = 0; grp < 3; ++grp) {
+        for (int32_t j = j0; j < j1; ++j) {
+          const int op = p->op[j];
+          const bool ff = p->kind[j] == AERL_KIND_FEATURE;
+          const int my_grp = !ff ? 0 : ((op == AERL_OP_GT || op == AERL_OP_LT) ? 1 : 2);
+          if (my_grp != grp) continue;
+          float a, b;
+          uint32_t w = cls | next;
+          if (!ff) {
+            const float c = p->coef[j], t = p->theta[j];
+            switch (op) {
+              case AERL_OP_GT: a = c; b = t; break;
+              case AERL_OP_LT: a = -c; b = -t; break;
+              case AERL_OP_GE:
+                if (t == -INFINITY) { a = 0.0f; b = -1.0f; }
+                else { a = c; b = std::nextafter(t, -INFINITY); }
+                break;
+              default:  // AERL_OP_LE
+                if (t == INFINITY) { a = 0.0f; b = -1.0f; }
+                else { a = -c; b = -std::nextafter(t, INFINITY); }
+                break;
+            }
+          } else {
+            const bool neg = op == AERL_OP_LT || op == AERL_OP_LE;
+            a = neg ? -p->coef[j] : p->coef[j];
+            b = neg ? -p->coef2[j] : p->coef2[j];
+            w |= (uint32_t)p->g[j] | kRecFF | (my_grp == 2 ? kRecGE : 0u);
+          }
+          if (pos == k - 1) w |= kRecLast;
+          hc[out++] = make_uint4((uint32_t)p->f[j] * 1024u, fbits(a), fbits(b), w);
+          ++pos;
+        }
+      }
+    }
+    sets[s] = make_int4(first, out - first, p->set_default[s], nominal_s);
     nominal += nominal_s;
     if (r1 - r0 > max_rules) max_rules = r1 - r0;
   }
+  hc[out] = make_uint4(0u, 0u, 0u, 0u);  // read-ahead pad
   for (int32_t r = 0; r < n_rules; ++r) {
     const int32_t j0 = p->rule_cond_off[r], j1 = p->rule_cond_off[r + 1];
-    if (j1 - j0 > max_rule_conds) max_rule_conds = j1 - j0;
-    int32_t out = j0;  // hard conditions of rule r occupy [j0, j1) in the packed order
-    int32_t counts[3] = {0, 0, 0};
-    // group 0: thresholds, group 1: feature >, group 2: feature >=
-    for (int grp = 0; grp < 3; ++grp) {
-      for (int32_t j = j0; j < j1; ++j) {
-        const int op = p->op[j];
-        const bool ff = p->kind[j] == AERL_KIND_FEATURE;
-        int my_grp;
-        if (!ff) my_grp = 0;
-        else my_grp = (op == AERL_OP_GT || op == AERL_OP_LT) ? 1 : 2;
-        if (my_grp != grp) continue;
-        float a, b;
-        uint32_t off_f = (uint32_t)p->f[j] * 1024u, off_g = 0;
-        if (!ff) {
-          const float c = p->coef[j], t = p->theta[j];
-          switch (op) {
-            case AERL_OP_GT: a = c; b = t; break;
-            case AERL_OP_LT: a = -c; b = -t; break;
-            case AERL_OP_GE:
-              if (t == -INFINITY) { a = 0.0f; b = -1.0f; }
-              else { a = c; b = std::nextafter(t, -INFINITY); }
-              break;
-            default:  // AERL_OP_LE
-              if (t == INFINITY) { a = 0.0f; b = -1.0f; }
-              else { a = -c; b = -std::nextafter(t, INFINITY); }
-              break;
-          }
-        } else {
-          const bool neg = op == AERL_OP_LT || op == AERL_OP_LE;
-          a = neg ? -p->coef[j] : p->coef[j];
-          b = neg ? -p->coef2[j] : p->coef2[j];
-          off_g = (uint32_t)p->g[j] * 1024u;
-        }
-        hc[out++] = make_uint4(off_f, fbits(a), fbits(b), off_g);
-        counts[grp]++;
-      }
-    }
-    rules[r] = make_int4(j0, counts[0] | (counts[1] << 8) | (counts[2] << 16), p->rule_class[r], j0);
+    rules[r] = make_int4(j0, j1 - j0, p->rule_class[r], 0);
     for (int32_t j = j0; j < j1; ++j) {
       const uint32_t g = p->kind[j] == AERL_KIND_FEATURE ? (uint32_t)p->g[j] : 0u;
       sc[j] = (uint32_t)p->f[j] | (g << 12) | ((uint32_t)p->kind[j] << 24) |
               ((uint32_t)(p->op[j] >= AERL_OP_GT) << 25);
     }
   }
+  (void)nc;
   rec->n_sets = p->n_sets;
   rec->n_rules = n_rules;
   rec->n_conds = n_conds;

@@ -70,6 +70,10 @@ def test_population_validation_rejects_structure(aerl):
     assert aerl.population_status(bad_default, 5, 2) == aerl.AERL_EINVAL
     big = from_rule_lists([(0, [(1, [_cond()] * 256)])])
     assert aerl.population_status(big, 5, 2) == aerl.AERL_EINVAL
+    many = from_rule_lists([(0, [(1, [_cond()] * 200)] * 5 + [(0, [])] * 24)])
+    assert aerl.population_status(many, 5, 2) == aerl.AERL_EINVAL  # 1024 records
+    ok_many = from_rule_lists([(0, [(1, [_cond()] * 200)] * 5 + [(0, [])] * 23)])
+    assert aerl.population_status(ok_many, 5, 2) == 0
     inf_theta = from_rule_lists([(0, [(1, [_cond(theta=np.float32(np.inf))])])])
     assert aerl.population_status(inf_theta, 5, 2) == 0
 
@@ -79,39 +83,48 @@ def _align(v):
 
 
 def decode_packed(img, n_sets, n_rules, n_conds):
+    """Splits the packed image into set records and the hard record stream."""
     sets_off = 0
     rules_off = _align(sets_off + 16 * max(n_sets, 1))
     hc_off = _align(rules_off + 16 * max(n_rules, 1))
     sets = img[sets_off:sets_off + 16 * n_sets].view(np.int32).reshape(-1, 4)
-    rules = img[rules_off:rules_off + 16 * n_rules].view(np.int32).reshape(-1, 4)
-    hc = img[hc_off:hc_off + 16 * n_conds].view(np.uint32).reshape(-1, 4)
-    return sets, rules, hc
+    n_rec = n_conds + n_rules + 1
+    hc = img[hc_off:hc_off + 16 * n_rec].view(np.uint32).reshape(-1, 4)
+    return sets, hc
 
 
-def eval_packed(x, sets, rules, hc, s):
-    """Evaluates the packed comparison forms a*x[f] > b, a*x[f] > b*x[g],
-    a*x[f] >= b*x[g] with float32 numpy arithmetic."""
+def eval_packed(x, sets, hc, s):
+    """Walks the packed record stream of rule set s with float32 numpy
+    arithmetic: a*x[f] > b, a*x[f] > b*x[g] or a*x[f] >= b*x[g]; a rule whose
+    records all hold for a sample gives that sample its class."""
     n = x.shape[0]
-    r0, nr, default, _ = sets[s]
+    first, count, default, _ = sets[s]
     pred = np.full(n, default, np.int32)
     und = np.ones(n, bool)
-    for k in range(r0, r0 + nr):
-        c0, counts, cls, _ = rules[k]
-        nt, ng, ne = counts & 255, (counts >> 8) & 255, (counts >> 16) & 255
-        fire = und.copy()
-        for j in range(c0, c0 + nt + ng + ne):
-            f, a, b, g = hc[j]
-            a = np.uint32(a).view(np.float32)
-            b = np.uint32(b).view(np.float32)
-            lhs = np.float32(a) * x[:, f // 1024]
-            if j < c0 + nt:
-                fire &= lhs > b
-            elif j < c0 + nt + ng:
-                fire &= lhs > np.float32(b) * x[:, g // 1024]
-            else:
-                fire &= lhs >= np.float32(b) * x[:, g // 1024]
-        pred[fire] = cls
-        und &= ~fire
+    fire = und.copy()
+    o = 0
+    while o < count * 16:
+        f1024, a, b, w = (int(v) for v in hc[first + o // 16])
+        a = np.uint32(a).view(np.float32)
+        b = np.uint32(b).view(np.float32)
+        lhs = np.float32(a) * x[:, f1024 // 1024]
+        if not w & (1 << 9):
+            m = lhs > b
+        else:
+            rhs = np.float32(b) * x[:, w & 0x1ff]
+            m = lhs >= rhs if w & (1 << 10) else lhs > rhs
+        fire &= m
+        nxt = o + 16
+        if w & (1 << 11):
+            assert nxt == w >> 18
+        if not fire.any():
+            nxt = w >> 18
+            fire = und.copy()
+        elif w & (1 << 11):
+            pred[fire] = (w >> 12) & 63
+            und &= ~fire
+            fire = und.copy()
+        o = nxt
     return pred
 
 
@@ -135,8 +148,8 @@ def test_packed_rewrite_is_exact_against_oracle(aerl):
     sets += [w.pop.to_rule_list(s) for s in range(w.pop.n_sets)]
     pop = from_rule_lists(sets)
     img = aerl.pack_host(pop, 4, 2)
-    S, R, H = decode_packed(img, pop.n_sets, pop.n_rules, pop.n_conds)
+    S, H = decode_packed(img, pop.n_sets, pop.n_rules, pop.n_conds)
     xx = np.concatenate([x, w.data.x[:, :4]])
     for s in range(pop.n_sets):
-        np.testing.assert_array_equal(eval_packed(xx, S, R, H, s), oracle.predict(xx, pop, s),
+        np.testing.assert_array_equal(eval_packed(xx, S, H, s), oracle.predict(xx, pop, s),
                                       err_msg=str(s))
