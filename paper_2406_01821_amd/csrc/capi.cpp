@@ -45,7 +45,7 @@ DatasetMem dataset_mem(int64_t n, int32_t nf, int32_t nc) {
   m.y_off = off;     off = align256(off + sizeof(int32_t) * (size_t)m.n_pad_max);
   m.perm_off = off;  off = align256(off + sizeof(int32_t) * (size_t)m.n_pad_max);
   m.tile_off = off;  off = align256(off + sizeof(int32_t) * (size_t)(m.n_tiles_max + 1));
-  m.tau_off = off;   off = align256(off + sizeof(float) * (size_t)nf);
+  m.tau_off = off;   off = align256(off + sizeof(float) * 2 * (size_t)nf);  // tau, 1/tau
   m.counts_off = off; off = align256(off + sizeof(int32_t) * (size_t)(m.n_blocks * nc + 1));
   m.base_off = off;  off = align256(off + sizeof(int32_t) * (size_t)(m.n_blocks * nc + 1));
   m.flags_off = off; off = align256(off + sizeof(int32_t) * 2);
@@ -166,6 +166,7 @@ aerl_status aerl_upload_dataset(aerl_ctx *ctx, const float *x, const int32_t *y,
   d.perm = reinterpret_cast<int32_t *>(base + M.perm_off);
   d.tile_info = reinterpret_cast<int32_t *>(base + M.tile_off);
   d.tau = reinterpret_cast<float *>(base + M.tau_off);
+  d.inv_tau = d.tau + nf;
   int32_t *counts_dev = reinterpret_cast<int32_t *>(base + M.counts_off);
   int32_t *base_dev = reinterpret_cast<int32_t *>(base + M.base_off);
   int32_t *flags_dev = reinterpret_cast<int32_t *>(base + M.flags_off);
@@ -289,6 +290,7 @@ aerl_status aerl_pack_population(aerl_ctx *ctx, const aerl_population *pop, int3
   }
   char *b = static_cast<char *>(ws);
   rec.sets = reinterpret_cast<const int4 *>(b + L.sets_off);
+  rec.ssets = reinterpret_cast<const int4 *>(b + L.ssets_off);
   rec.rules = reinterpret_cast<const int4 *>(b + L.rules_off);
   rec.hconds = reinterpret_cast<const uint4 *>(b + L.hconds_off);
   rec.sconds = reinterpret_cast<const uint32_t *>(b + L.sconds_off);

@@ -46,6 +46,13 @@ __device__ __forceinline__ void load_row(const float *__restrict__ xs, uint32_t 
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
+// Next work item of a wave from an LDS counter.  Every lane of the (fully
+// active) wave adds 1 and the first lane's old value / 64 is the item: no
+// divergent region, so the surrounding loop stays a uniform loop.
+__device__ __forceinline__ int next_item(int32_t *ctr) {
+  return __builtin_amdgcn_readfirstlane(atomicAdd(ctr, 1)) >> 6;
+}
+
 // Wave-uniform read through the constant address space, so that the compiler
 // issues a scalar load into SGPRs (read-only data: packed rule records).
 // T is a 4- or 16-byte POD (int, int4, uint4).

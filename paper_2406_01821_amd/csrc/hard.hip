@@ -87,9 +87,7 @@ __global__ __launch_bounds__(kHardBlock) void k_hard(const HardArgs a) {
     for (int s = 0; s < S; ++s) vm[s] = ballot(lane * S + s < valid);
     int dummy[S];
     for (;;) {
-      int q = 0;
-      if (lane == 0) q = atomicAdd(&next_q, 1);
-      q = __builtin_amdgcn_readfirstlane(q);
+      const int q = next_item(&next_q);
       if (q >= Q) break;
       const int4 set = ldc(a.sets, a.set_begin + q0 + q);
       int acc;

@@ -34,6 +34,7 @@ aerl_status fail(aerl_ctx *ctx, aerl_status code, const char *fmt, ...);
 // ------------------------------------------------------------ packed records
 // Rule set: {first hard-stream record, record count, default class, nominal
 //            condition count}.
+// Soft rule set: {first rule, rule count, first condition, condition count}.
 // Rule (soft path): {first condition in the caller's order, condition count,
 //                    class, 0}.
 // Hard stream record (16 bytes), one per condition, rules of a set in order:
@@ -53,7 +54,7 @@ constexpr uint32_t kRecClsShift = 12;
 constexpr uint32_t kRecNextShift = 18;
 constexpr int32_t kMaxSetRecords = 1023;  // next-rule byte offsets fit 14 bits
 struct PackedLayout {
-  size_t sets_off, rules_off, hconds_off, sconds_off, total;
+  size_t sets_off, ssets_off, rules_off, hconds_off, sconds_off, total;
 };
 
 struct DatasetRec {
@@ -64,6 +65,7 @@ struct DatasetRec {
   int32_t *perm = nullptr;     // [n_pad]
   int32_t *tile_info = nullptr;// [n_tiles]: label | valid << 8
   float *tau = nullptr;        // [nf]
+  float *inv_tau = nullptr;    // [nf], 1/tau (fp64 division rounded to float)
   int64_t class_count[AERL_MAX_CLASSES] = {};
   int32_t region_tile0[AERL_MAX_CLASSES] = {};
   int32_t region_tiles[AERL_MAX_CLASSES] = {};
@@ -73,7 +75,9 @@ struct PopRec {
   int32_t n_sets = 0, n_rules = 0, n_conds = 0, nf = 0, nc = 0;
   int32_t max_rules = 0, max_rule_conds = 0;
   int64_t nominal_conds = 0;
+  int32_t max_set_conds = 0;
   const int4 *sets = nullptr;
+  const int4 *ssets = nullptr;
   const int4 *rules = nullptr;
   const uint4 *hconds = nullptr;
   const uint32_t *sconds = nullptr;

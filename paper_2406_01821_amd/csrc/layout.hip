@@ -129,7 +129,9 @@ __global__ __launch_bounds__(kTauBlock) void k_tau(const float *__restrict__ x_f
   }
   if (t == 0) {
     double sd = n > 0 ? sqrt(red[0] / (double)n) : 0.0;
-    tau[blockIdx.x] = sd > 0.0 ? (float)(0.05 * sd) : 1.0f;
+    const float tf = sd > 0.0 ? (float)(0.05 * sd) : 1.0f;
+    tau[blockIdx.x] = tf;
+    tau[gridDim.x + blockIdx.x] = (float)(1.0 / (double)tf);  // 1/tau follows tau
   }
 }
 

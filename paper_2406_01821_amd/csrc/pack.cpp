@@ -54,6 +54,8 @@ PackedLayout packed_layout(int32_t n_sets, int32_t n_rules, int32_t n_conds) {
   size_t off = 0;
   L.sets_off = off;
   off = align256(off + sizeof(int4) * (size_t)(n_sets > 0 ? n_sets : 1));
+  L.ssets_off = off;
+  off = align256(off + sizeof(int4) * (size_t)(n_sets > 0 ? n_sets : 1));
   L.rules_off = off;
   off = align256(off + sizeof(int4) * (size_t)(n_rules > 0 ? n_rules : 1));
   L.hconds_off = off;
@@ -134,8 +136,10 @@ void pack_population_image(const aerl_population *p, int32_t nf, int32_t nc, int
                            int32_t n_conds, void *dst, PopRec *rec) {
   const PackedLayout L = packed_layout(p->n_sets, n_rules, n_conds);
   std::memset(dst, 0, L.total);
+  rec->max_set_conds = 0;
   char *base = static_cast<char *>(dst);
   int4 *sets = reinterpret_cast<int4 *>(base + L.sets_off);
+  int4 *ssets = reinterpret_cast<int4 *>(base + L.ssets_off);
   int4 *rules = reinterpret_cast<int4 *>(base + L.rules_off);
   uint4 *hc = reinterpret_cast<uint4 *>(base + L.hconds_off);
   uint32_t *sc = reinterpret_cast<uint32_t *>(base + L.sconds_off);
@@ -195,6 +199,8 @@ void pack_population_image(const aerl_population *p, int32_t nf, int32_t nc, int
       }
     }
     sets[s] = make_int4(first, out - first, p->set_default[s], nominal_s);
+    ssets[s] = make_int4(r0, r1 - r0, r1 > r0 ? p->rule_cond_off[r0] : 0, nominal_s);
+    if (nominal_s > rec->max_set_conds) rec->max_set_conds = nominal_s;
     nominal += nominal_s;
     if (r1 - r0 > max_rules) max_rules = r1 - r0;
   }

@@ -1,10 +1,508 @@
-// Soft (sigmoid-relaxed) forward and backward passes.
+// Soft (sigmoid-relaxed) forward pass and its adjoint.
+//
+// Section 3: a differentiable activation (a sigmoid) replaces the step so that
+// rule coefficients and thresholds can be tuned by back-propagation.  The
+// relaxation evaluated here (one sample, label y, rules k = 0..R-1):
+//   z_j  = s_j * (coef_j * x[f_j] - rhs_j) / tau[f_j],  rhs = theta or coef2*x[g]
+//   a_k  = sum_j log sigmoid(z_j)             (log of the rule's soft truth r_k)
+//   b_k  = log(1 - r_k)
+//   l_k  = a_k + sum_{m<k} b_m                (log P(rule k fires first))
+//   log P_y = LSE({l_k : class_k = y} u {sum_m b_m if default = y})
+//   L = min(-log P_y, 100),  loss = mean over samples.
+// Everything is carried in log space in fp32 with accurate log1p / expm1 /
+// log1mexp built from the hardware exp2/log2 (both within ~1 ulp, also near 1).
+//
+// Adjoint (derivation in the oracle): with V_k = P(class y | rules 0..k did not
+// fire) = exp(U_k), U_{R-1} = [default = y] ? 0 : -inf,
+// U_{k-1} = LSE([class_k = y] a_k, b_k + U_k):
+//   dL/da_k = exp(l_k + U_k - log P_y)                      if class_k != y
+//           = -exp(l_k - log P_y) * (1 - V_k)               if class_k == y
+//   dL/dz_j = dL/da_k * sigmoid(-z_j),  formed as one exponent (bounded by 1).
+// The backward kernel re-evaluates every condition: a forward sweep keeps only
+// a_k and the survival prefix per rule and sample (in LDS), then a reverse
+// sweep rebuilds U_k and recomputes each sigmoid to form its gradient.
+//
+// Work decomposition matches the hard path: block (chunk of rule sets, group
+// of label-uniform tiles).  Per-(set, tile) wave sums go into LDS with one
+// writer per entry; per-block partials go to the caller's workspace and a
+// second kernel reduces them over groups in a fixed order, so every result is
+// bit-identical from run to run.
+#include "eval_core.h"
 #include "internal.h"
 
 namespace aerl {
 
-size_t soft_ws_bytes(const DatasetRec &, const PopRec &, bool) { return 0; }
-hipError_t launch_soft_forward(const SoftLaunch &, hipStream_t) { return hipErrorNotSupported; }
-hipError_t launch_soft_backward(const SoftLaunch &, hipStream_t) { return hipErrorNotSupported; }
+namespace {
+
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kLn2 = 0.6931471805599453f;
+constexpr float kNegInf = -__builtin_huge_valf();
+constexpr float kLossCap = 100.0f;
+
+__device__ __forceinline__ float fexp(float x) { return __builtin_amdgcn_exp2f(x * kLog2e); }
+__device__ __forceinline__ float flog(float x) { return __builtin_amdgcn_logf(x) * kLn2; }
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// log(1 + u) for u in [0, 1]: w = 1 + u is rounded; (w - 1) - u is that
+// rounding error exactly, which corrects log(w) to first order.
+__device__ __forceinline__ float log1p_unit(float u) {
+  const float w = 1.0f + u;
+  return flog(w) - ((w - 1.0f) - u);
+}
+
+// log(sigmoid(z)) = -(max(-z, 0) + log1p(exp(-|z|))).
+__device__ __forceinline__ float log_sigmoid(float z) {
+  return -(fmaxf(-z, 0.0f) + log1p_unit(fexp(-fabsf(z))));
+}
+
+// Per-rule accumulator of the soft truth: a = log r = sum_j log sigmoid(z_j),
+// and us = sum_j exp(kShift - |z_j|).  When every condition holds strongly, a
+// is so close to 0 that fp32 cannot carry -a (it underflows near e^-87), yet
+// log(1 - r) ~ log(sum_j exp(-z_j)) still matters down to the e^-100 loss
+// clamp; the shifted sum keeps it (normal floats down to z ~ 150).
+constexpr float kShift = 64.0f;
+constexpr float kExpNegShift = 1.60381089e-28f;  // e^-64
+struct RuleAcc {
+  float a = 0.0f, us = 0.0f;
+  __device__ __forceinline__ void add(float z) {
+    const float az = fabsf(z);
+    const float e_s = fexp(kShift - az);  // e^(64 - |z|)
+    a -= fmaxf(-z, 0.0f) + log1p_unit(e_s * kExpNegShift);
+    us += e_s;
+  }
+};
+
+// -expm1(a) = 1 - exp(a) for a <= 0.  Near 0 uses Kahan's form
+// (u - 1) * a / log(u) with u = exp(a), which cancels the rounding of u.
+__device__ __forceinline__ float one_minus_exp(float a) {
+  const float u = fexp(a);
+  if (a > -kLn2) {
+    const float lu = flog(u);
+    const float em1 = (u == 1.0f) ? a : (u - 1.0f) * (a * frcp(lu));
+    return -em1;
+  }
+  return 1.0f - u;
+}
+
+// log(1 - exp(a)) for a <= 0 (a = 0 gives -inf).
+__device__ __forceinline__ float log1mexp(float a) { return flog(one_minus_exp(a)); }
+
+// log(1 - r) of a rule: from a while fp32 represents -a well, otherwise from
+// the shifted sum (there 1 - r = sum_j exp(-z_j) to within a relative 1e-30).
+__device__ __forceinline__ float rule_log_miss(const RuleAcc &r) {
+  return r.a > -1e-30f ? flog(r.us) - kShift : log1mexp(r.a);
+}
+
+// log(exp(p) + exp(q)), -inf safe.
+__device__ __forceinline__ float lse(float p, float q) {
+  const float m = fmaxf(p, q);
+  if (m == kNegInf) return kNegInf;
+  return m + log1p_unit(fexp(-fabsf(p - q)));
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+  return v;
+}
+
+struct SoftArgs {
+  const float *x_fm;
+  int64_t n_pad;
+  int32_t nf, nc;
+  const int32_t *tile_info;
+  const float *inv_tau;
+  const int4 *sets;   // hard set records (default class in .z)
+  const int4 *ssets;  // {first rule, #rules, first condition, #conditions}
+  const int4 *rules;  // {first condition, #conditions, class, 0}
+  const uint32_t *sconds;
+  const float *coef, *coef2, *theta;
+  int32_t n_sets;
+  int32_t sets_per_chunk, tiles_per_group, n_groups;
+  int32_t max_rules, max_set_conds;
+  double *part_loss;  // [n_groups][n_sets]
+  float *part_grad;   // [n_groups][n_conds][2]
+  int32_t n_conds;
+  int32_t region_tile0[AERL_MAX_CLASSES];
+  int32_t region_tiles[AERL_MAX_CLASSES];
+};
+
+// Class region and tile range of block group g (uniform).
+__device__ __forceinline__ void group_range(const SoftArgs &a, int g, int &label, int &lo, int &hi) {
+  label = 0; lo = 0; hi = 0;
+  for (int c = 0; c < a.nc; ++c) {
+    const int ng = (a.region_tiles[c] + a.tiles_per_group - 1) / a.tiles_per_group;
+    if (g < ng) {
+      label = c;
+      lo = a.region_tile0[c] + g * a.tiles_per_group;
+      hi = min(lo + a.tiles_per_group, a.region_tile0[c] + a.region_tiles[c]);
+      return;
+    }
+    g -= ng;
+  }
+}
+
+// z of condition j for S values of x[f] (and x[g] for feature conditions).
+template <int S>
+__device__ __forceinline__ void cond_z(const SoftArgs &a, const float *xs, int lane, int j,
+                                       float (&z)[S], float (&xf)[S], float (&xg)[S], bool &ff) {
+  const uint32_t sc = ldc(a.sconds, j);
+  const uint32_t f = sc & 0xfffu, g = (sc >> 12) & 0xfffu;
+  ff = ((sc >> 24) & 1u) != 0;
+  const float inv = ldc(a.inv_tau, f);
+  const float sinv = ((sc >> 25) & 1u) ? inv : -inv;
+  const float c = ldc(a.coef, j);
+  load_row<S>(xs, f * 1024u, lane, xf);
+  if (ff) {
+    const float c2 = ldc(a.coef2, j);
+    load_row<S>(xs, g * 1024u, lane, xg);
+#pragma unroll
+    for (int s = 0; s < S; ++s) z[s] = fmaf(c, xf[s], -(c2 * xg[s])) * sinv;
+  } else {
+    const float th = ldc(a.theta, j);
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      z[s] = fmaf(c, xf[s], -th) * sinv;
+      xg[s] = 0.0f;
+    }
+  }
+}
+
+constexpr int kSoftBlock = 512;
+
+// ------------------------------------------------------------------ forward
+template <int S>
+__global__ __launch_bounds__(kSoftBlock) void k_soft_fwd(const SoftArgs a) {
+  constexpr int TS = 64 * S, WPT = AERL_TILE / TS;
+  extern __shared__ __align__(16) float smem[];
+  float *xs = smem;
+  double *acc = reinterpret_cast<double *>(smem + (size_t)a.nf * TS);  // [Q]
+  __shared__ int32_t next_q;
+  const int lane = threadIdx.x & 63;
+  int label, tile_lo, tile_hi;
+  group_range(a, blockIdx.y, label, tile_lo, tile_hi);
+  const int q0 = blockIdx.x * a.sets_per_chunk;
+  const int Q = min(a.sets_per_chunk, a.n_sets - q0);
+  for (int i = threadIdx.x; i < Q; i += blockDim.x) acc[i] = 0.0;
+  const int n4 = a.nf * (TS / 4);
+  const float4 *src = reinterpret_cast<const float4 *>(a.x_fm);
+  float4 *dst = reinterpret_cast<float4 *>(xs);
+  const int64_t row4 = a.n_pad / 4;
+  for (int64_t wt = (int64_t)tile_lo * WPT; wt < (int64_t)tile_hi * WPT; ++wt) {
+    __syncthreads();
+    const int64_t base4 = wt * (TS / 4);
+    for (int i = threadIdx.x; i < n4; i += blockDim.x) {
+      const int f = i / (TS / 4), k = i % (TS / 4);
+      dst[i] = src[(int64_t)f * row4 + base4 + k];
+    }
+    if (threadIdx.x == 0) next_q = 0;
+    __syncthreads();
+    const int info = ldc(a.tile_info, wt / WPT);
+    const int valid = min(max((info >> 8) - (int)(wt % WPT) * TS, 0), TS);
+    bool live[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) live[s] = lane * S + s < valid;
+    for (;;) {
+      const int q = next_item(&next_q);
+      if (q >= Q) break;
+      const int4 ss = ldc(a.ssets, q0 + q);
+      const int dflt = ldc(a.sets, q0 + q).z;
+      float logpy[S], surv[S];
+#pragma unroll
+      for (int s = 0; s < S; ++s) { logpy[s] = kNegInf; surv[s] = 0.0f; }
+      for (int k = 0; k < ss.y; ++k) {
+        const int4 r = ldc(a.rules, ss.x + k);
+        RuleAcc ra[S];
+        for (int j = r.x; j < r.x + r.y; ++j) {
+          float z[S], xf[S], xg[S];
+          bool ff;
+          cond_z<S>(a, xs, lane, j, z, xf, xg, ff);
+#pragma unroll
+          for (int s = 0; s < S; ++s) ra[s].add(z[s]);
+        }
+        const bool hit = r.z == label;
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          if (hit) logpy[s] = lse(logpy[s], ra[s].a + surv[s]);
+          surv[s] += rule_log_miss(ra[s]);
+        }
+      }
+      float part = 0.0f;
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const float lp = dflt == label ? lse(logpy[s], surv[s]) : logpy[s];
+        part += live[s] ? fminf(-lp, kLossCap) : 0.0f;
+      }
+      part = wave_sum(part);
+      if (lane == 0) acc[q] += (double)part;
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < Q; i += blockDim.x)
+    a.part_loss[(int64_t)blockIdx.y * a.n_sets + q0 + i] = acc[i];
+}
+
+__global__ void k_soft_fwd_final(const double *__restrict__ part, int32_t n_groups, int32_t n_sets,
+                                 int64_t n, float *__restrict__ loss) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_sets) return;
+  double s = 0.0;
+  for (int g = 0; g < n_groups; ++g) s += part[(int64_t)g * n_sets + p];
+  loss[p] = n > 0 ? (float)(s / (double)n) : 0.0f;
+}
+
+// ----------------------------------------------------------------- backward
+constexpr int kBwdWaves = 8;
+
+__global__ __launch_bounds__(kBwdWaves * 64) void k_soft_bwd(const SoftArgs a) {
+  constexpr int TS = 64, WPT = AERL_TILE / TS;
+  extern __shared__ __align__(16) float smem[];
+  float *xs = smem;                                     // [nf][64]
+  float *acc = xs + (size_t)a.nf * TS;                  // [Q][max_set_conds][2]
+  float *store = acc + (size_t)a.sets_per_chunk * a.max_set_conds * 2;  // [wave][R][2][64]
+  __shared__ int32_t next_q;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  float *my = store + (size_t)wave * a.max_rules * 128;
+  int label, tile_lo, tile_hi;
+  group_range(a, blockIdx.y, label, tile_lo, tile_hi);
+  const int q0 = blockIdx.x * a.sets_per_chunk;
+  const int Q = min(a.sets_per_chunk, a.n_sets - q0);
+  for (int i = threadIdx.x; i < Q * a.max_set_conds * 2; i += blockDim.x) acc[i] = 0.0f;
+  const int n4 = a.nf * (TS / 4);
+  const float4 *src = reinterpret_cast<const float4 *>(a.x_fm);
+  float4 *dst = reinterpret_cast<float4 *>(xs);
+  const int64_t row4 = a.n_pad / 4;
+  for (int64_t wt = (int64_t)tile_lo * WPT; wt < (int64_t)tile_hi * WPT; ++wt) {
+    __syncthreads();
+    const int64_t base4 = wt * (TS / 4);
+    for (int i = threadIdx.x; i < n4; i += blockDim.x) {
+      const int f = i / (TS / 4), k = i % (TS / 4);
+      dst[i] = src[(int64_t)f * row4 + base4 + k];
+    }
+    if (threadIdx.x == 0) next_q = 0;
+    __syncthreads();
+    const int info = ldc(a.tile_info, wt / WPT);
+    const int valid = min(max((info >> 8) - (int)(wt % WPT) * TS, 0), TS);
+    const bool live = lane < valid;
+    for (;;) {
+      const int q = next_item(&next_q);
+      if (q >= Q) break;
+      const int4 ss = ldc(a.ssets, q0 + q);
+      const int dflt = ldc(a.sets, q0 + q).z;
+      // forward sweep: keep a_k and the survival prefix before rule k
+      float logpy = kNegInf, surv = 0.0f;
+      for (int k = 0; k < ss.y; ++k) {
+        const int4 r = ldc(a.rules, ss.x + k);
+        RuleAcc ra;
+        for (int j = r.x; j < r.x + r.y; ++j) {
+          float z[1], xf[1], xg[1];
+          bool ff;
+          cond_z<1>(a, xs, lane, j, z, xf, xg, ff);
+          ra.add(z[0]);
+        }
+        my[k * 128 + lane] = ra.a;
+        my[k * 128 + 64 + lane] = surv;
+        if (r.z == label) logpy = lse(logpy, ra.a + surv);
+        surv += rule_log_miss(ra);
+      }
+      if (dflt == label) logpy = lse(logpy, surv);
+      // samples whose loss is clamped (or padding) get no gradient
+      const float gate = (live && -logpy <= kLossCap) ? 1.0f : 0.0f;
+      // reverse sweep
+      float U = dflt == label ? 0.0f : kNegInf;
+      for (int k = ss.y - 1; k >= 0; --k) {
+        const int4 r = ldc(a.rules, ss.x + k);
+        const float ak = my[k * 128 + lane];
+        const float lk = ak + my[k * 128 + 64 + lane];
+        const bool hit = r.z == label;
+        float pre, mul;
+        if (hit) {
+          pre = lk - logpy;
+          mul = -one_minus_exp(U) * gate;
+        } else {
+          pre = lk + U - logpy;
+          mul = gate;
+        }
+        RuleAcc ra;
+        for (int j = r.x; j < r.x + r.y; ++j) {
+          float z[1], xf[1], xg[1];
+          bool ff;
+          cond_z<1>(a, xs, lane, j, z, xf, xg, ff);
+          ra.add(z[0]);
+          const float lsn = log_sigmoid(z[0]) - z[0];  // log sigmoid(-z)
+          const float e = pre + lsn;
+          const float dz = (mul != 0.0f && e > kNegInf) ? mul * fexp(e) : 0.0f;
+          const float g0 = wave_sum(ff ? dz * xg[0] : dz);
+          const float g1 = wave_sum(dz * xf[0]);
+          if (lane == 0) {
+            float *ap = acc + ((size_t)q * a.max_set_conds + (j - ss.z)) * 2;
+            ap[0] += g0;
+            ap[1] += g1;
+          }
+        }
+        U = lse(hit ? ak : kNegInf, rule_log_miss(ra) + U);
+      }
+    }
+  }
+  __syncthreads();
+  for (int q = 0; q < Q; ++q) {
+    const int4 ss = ldc(a.ssets, q0 + q);
+    for (int i = threadIdx.x; i < ss.w * 2; i += blockDim.x)
+      a.part_grad[((int64_t)blockIdx.y * a.n_conds + ss.z) * 2 + i] =
+          acc[(size_t)q * a.max_set_conds * 2 + i];
+  }
+}
+
+// One block per rule set: sums the group partials of its conditions in a
+// fixed order and applies dz/dparam = +-x/tau, -+1/tau and dloss/N.
+__global__ void k_soft_bwd_final(const float *__restrict__ part, int32_t n_groups,
+                                 int32_t n_conds, const int4 *__restrict__ ssets,
+                                 const uint32_t *__restrict__ sconds,
+                                 const float *__restrict__ inv_tau,
+                                 const float *__restrict__ dloss, int64_t n,
+                                 float *__restrict__ dcoef, float *__restrict__ dcoef2,
+                                 float *__restrict__ dtheta) {
+  const int p = blockIdx.x;
+  const int4 ss = ssets[p];
+  const double scale = n > 0 ? (double)dloss[p] / (double)n : 0.0;
+  for (int i = threadIdx.x; i < ss.w; i += blockDim.x) {
+    const int j = ss.z + i;
+    double g0 = 0.0, g1 = 0.0;
+    for (int g = 0; g < n_groups; ++g) {
+      const float *pp = part + ((int64_t)g * n_conds + j) * 2;
+      g0 += (double)pp[0];
+      g1 += (double)pp[1];
+    }
+    const uint32_t sc = sconds[j];
+    const bool ff = ((sc >> 24) & 1u) != 0;
+    const double sinv = (((sc >> 25) & 1u) ? 1.0 : -1.0) * (double)inv_tau[sc & 0xfffu];
+    dcoef[j] = (float)(sinv * g1 * scale);
+    dcoef2[j] = ff ? (float)(-sinv * g0 * scale) : 0.0f;
+    dtheta[j] = ff ? 0.0f : (float)(-sinv * g0 * scale);
+  }
+}
+
+struct SoftPlan {
+  int S, Q, TG, n_groups;
+  size_t lds;
+};
+
+int64_t count_groups(const DatasetRec &ds, int tg) {
+  int64_t g = 0;
+  for (int c = 0; c < ds.nc; ++c) g += (ds.region_tiles[c] + tg - 1) / tg;
+  return g;
+}
+
+constexpr int64_t kMaxGroups = 64;
+
+SoftPlan plan_forward(const DatasetRec &ds, const PopRec &pop) {
+  SoftPlan p{};
+  p.S = 4;
+  while (p.S > 1 && (size_t)ds.nf * 256 * p.S > 64 * 1024) p.S >>= 1;
+  p.Q = std::max(1, std::min(pop.n_sets, 64));
+  p.TG = 1;
+  while (count_groups(ds, p.TG) > kMaxGroups) p.TG *= 2;
+  p.n_groups = (int)count_groups(ds, p.TG);
+  p.lds = (size_t)ds.nf * 64 * p.S * 4 + (size_t)p.Q * 8;
+  return p;
+}
+
+SoftPlan plan_backward(const DatasetRec &ds, const PopRec &pop) {
+  SoftPlan p{};
+  p.S = 1;
+  const size_t xs = (size_t)ds.nf * 64 * 4;
+  const size_t per_wave = (size_t)std::max(pop.max_rules, 1) * 128 * 4;
+  const size_t per_set = (size_t)std::max(pop.max_set_conds, 1) * 2 * 4;
+  p.Q = std::max(1, std::min(pop.n_sets, 16));
+  while (p.Q > 1 && xs + p.Q * per_set + kBwdWaves * per_wave > 160 * 1024) p.Q >>= 1;
+  p.TG = 1;
+  while (count_groups(ds, p.TG) > kMaxGroups) p.TG *= 2;
+  p.n_groups = (int)count_groups(ds, p.TG);
+  p.lds = xs + (size_t)p.Q * per_set + kBwdWaves * per_wave;
+  return p;
+}
+
+void fill_args(SoftArgs &a, const SoftLaunch &l, const SoftPlan &p) {
+  const DatasetRec &ds = *l.ds;
+  const PopRec &pop = *l.pop;
+  a = SoftArgs{};
+  a.x_fm = ds.x_fm;
+  a.n_pad = ds.n_pad;
+  a.nf = ds.nf;
+  a.nc = ds.nc;
+  a.tile_info = ds.tile_info;
+  a.inv_tau = ds.inv_tau;
+  a.sets = pop.sets;
+  a.ssets = pop.ssets;
+  a.rules = pop.rules;
+  a.sconds = pop.sconds;
+  a.coef = l.coef;
+  a.coef2 = l.coef2;
+  a.theta = l.theta;
+  a.n_sets = pop.n_sets;
+  a.n_conds = pop.n_conds;
+  a.sets_per_chunk = p.Q;
+  a.tiles_per_group = p.TG;
+  a.n_groups = p.n_groups;
+  a.max_rules = std::max(pop.max_rules, 1);
+  a.max_set_conds = std::max(pop.max_set_conds, 1);
+  for (int c = 0; c < ds.nc; ++c) {
+    a.region_tile0[c] = ds.region_tile0[c];
+    a.region_tiles[c] = ds.region_tiles[c];
+  }
+}
+
+}  // namespace
+
+size_t soft_ws_bytes(const DatasetRec &ds, const PopRec &pop, bool backward) {
+  if (backward) {
+    const SoftPlan p = plan_backward(ds, pop);
+    return (size_t)p.n_groups * (size_t)std::max(pop.n_conds, 1) * 2 * sizeof(float);
+  }
+  const SoftPlan p = plan_forward(ds, pop);
+  return (size_t)p.n_groups * (size_t)std::max(pop.n_sets, 1) * sizeof(double);
+}
+
+hipError_t launch_soft_forward(const SoftLaunch &l, hipStream_t st) {
+  const PopRec &pop = *l.pop;
+  if (pop.n_sets == 0) return hipSuccess;
+  const SoftPlan p = plan_forward(*l.ds, pop);
+  SoftArgs a;
+  fill_args(a, l, p);
+  a.part_loss = static_cast<double *>(l.ws);
+  if (p.n_groups > 0) {
+    const dim3 grid((unsigned)((pop.n_sets + p.Q - 1) / p.Q), (unsigned)p.n_groups);
+    switch (p.S) {
+      case 4: hipLaunchKernelGGL(k_soft_fwd<4>, grid, dim3(kSoftBlock), p.lds, st, a); break;
+      case 2: hipLaunchKernelGGL(k_soft_fwd<2>, grid, dim3(kSoftBlock), p.lds, st, a); break;
+      default: hipLaunchKernelGGL(k_soft_fwd<1>, grid, dim3(kSoftBlock), p.lds, st, a); break;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_soft_fwd_final, dim3((unsigned)((pop.n_sets + 255) / 256)), dim3(256), 0, st,
+                     a.part_loss, p.n_groups, pop.n_sets, l.ds->n, l.loss);
+  return hipGetLastError();
+}
+
+hipError_t launch_soft_backward(const SoftLaunch &l, hipStream_t st) {
+  const PopRec &pop = *l.pop;
+  if (pop.n_sets == 0) return hipSuccess;
+  const SoftPlan p = plan_backward(*l.ds, pop);
+  if (p.lds > 160 * 1024) return hipErrorInvalidValue;
+  SoftArgs a;
+  fill_args(a, l, p);
+  a.part_grad = static_cast<float *>(l.ws);
+  if (p.n_groups > 0) {
+    const dim3 grid((unsigned)((pop.n_sets + p.Q - 1) / p.Q), (unsigned)p.n_groups);
+    hipLaunchKernelGGL(k_soft_bwd, grid, dim3(kBwdWaves * 64), p.lds, st, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_soft_bwd_final, dim3((unsigned)pop.n_sets), dim3(64), 0, st, a.part_grad,
+                     p.n_groups, pop.n_conds, pop.ssets, pop.sconds, l.ds->inv_tau, l.dloss,
+                     l.ds->n, l.dcoef, l.dcoef2, l.dtheta);
+  return hipGetLastError();
+}
 
 }  // namespace aerl

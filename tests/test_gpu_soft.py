@@ -1,0 +1,181 @@
+"""GPU parity of the soft (sigmoid-relaxed) path against the fp64 oracle:
+loss within 1e-5 relative per rule set (plus 1e-6 absolute: a loss that is
+exactly 0 in fp64 comes out as a few fp32 roundings); gradients within 1e-4
+relative, plus 1e-5 of the sum of the absolute per-sample terms (each fp32
+term carries ~1e-6 relative rounding, and a gradient whose terms cancel across
+samples cannot meet a purely relative bound), plus 1e-7 of the largest entry
+of the same gradient array (fp32 resolution at that array's scale; entries such
+as 1e-50 are not representable in fp32 at all); finite differences on a 64 x 8
+subproblem; determinism; the autograd wrapper."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2406_01821_amd import synth
+from paper_2406_01821_amd.population import Dataset, from_rule_lists
+
+pytestmark = pytest.mark.gpu
+
+LOSS_RTOL = 1e-5
+LOSS_ATOL = 1e-6
+GRAD_RTOL = 1e-4
+GRAD_ABS_SCALE = 1e-5
+GRAD_ARRAY_FLOOR = 1e-7
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2406_01821_amd.aerl import Context
+    c = Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def params(pop, dev):
+    import torch
+    return [torch.tensor(a, device=dev) for a in (pop.coef, pop.coef2, pop.theta)]
+
+
+def gpu_soft(ctx, data, pop, dloss=None):
+    import torch
+    ds = ctx.upload_dataset(data)
+    p = ctx.pack_population(pop, data.n_features, data.n_classes)
+    c1, c2, th = params(pop, ctx.device)
+    loss = ctx.soft_forward(ds, p, c1, c2, th)
+    dl = torch.tensor(np.ones(pop.n_sets) if dloss is None else dloss, dtype=torch.float32,
+                      device=ctx.device)
+    g = ctx.soft_backward(ds, p, c1, c2, th, dl)
+    torch.cuda.synchronize()
+    return loss.cpu().numpy().astype(np.float64), [t.cpu().numpy().astype(np.float64) for t in g]
+
+
+def check_loss(got, ref):
+    err = np.abs(got - ref)
+    bad = err > LOSS_RTOL * np.abs(ref) + LOSS_ATOL
+    assert not bad.any(), (np.nonzero(bad)[0], got[bad], ref[bad])
+
+
+def check_grad(got, ref, ref_abs):
+    for k, (g, r, ra) in enumerate(zip(got, ref, ref_abs)):
+        floor = GRAD_ARRAY_FLOOR * np.abs(r).max() if r.size else 0.0
+        bound = GRAD_RTOL * np.abs(r) + GRAD_ABS_SCALE * ra + floor
+        bad = np.abs(g - r) > bound
+        assert not bad.any(), (k, np.nonzero(bad)[0][:10], g[bad][:5], r[bad][:5], ra[bad][:5])
+
+
+def run_case(ctx, data, pop, dloss=None):
+    loss, grads = gpu_soft(ctx, data, pop, dloss)
+    tau = oracle.tau(data.x)
+    ref = oracle.soft_forward(data.x, data.y, tau, data.n_classes, pop)
+    check_loss(loss, ref)
+    dl = np.ones(pop.n_sets) if dloss is None else dloss
+    rg = oracle.soft_backward(data.x, data.y, tau, data.n_classes, pop, dloss=dl)
+    ra = oracle.soft_backward(data.x, data.y, tau, data.n_classes, pop, dloss=dl, absolute=True)
+    check_grad(grads, rg, ra)
+
+
+def test_soft_workload_shape_small(ctx):
+    w = synth.soft_workload(3, n=8192, nf=16, n_sets=32)
+    run_case(ctx, w.data, w.pop, dloss=np.linspace(0.5, 2.0, 32))
+
+
+@pytest.mark.parametrize("seed,nc", [(1, 2), (2, 3), (3, 4)])
+def test_mixed_kinds_ops_and_classes(ctx, seed, nc):
+    w = synth.tiny(seed, n=3000, nf=9, n_classes=nc, n_sets=40, rules=(1, 8), conds=(1, 4),
+                   ff_frac=0.4)
+    run_case(ctx, w.data, w.pop)
+
+
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 257, 1000])
+def test_ragged_sample_counts(ctx, n):
+    w = synth.tiny(200 + n, n=n, nf=6, n_sets=10, rules=(1, 5), conds=(1, 3))
+    run_case(ctx, w.data, w.pop)
+
+
+def test_degenerate_rules_empty_sets_and_clamp(ctx):
+    w = synth.tiny(5, n=700, nf=5, n_sets=6)
+    sure = dict(op=2, kind=0, f=0, coef=np.float32(1.0), theta=np.float32(-1e30))
+    never = dict(op=2, kind=0, f=1, coef=np.float32(1.0), theta=np.float32(np.inf))
+    sets = [(0, []), (1, []), (0, [(1, [])]), (1, [(1, [sure])]), (0, [(1, [never]), (0, [sure])])]
+    sets += [w.pop.to_rule_list(s) for s in range(w.pop.n_sets)]
+    run_case(ctx, w.data, from_rule_lists(sets))
+
+
+def test_finite_differences_64x8(ctx):
+    """Gradient against fp64 central differences of the oracle's loss on a
+    64-sample x 8-feature subproblem (tau from the subproblem itself)."""
+    w = synth.tiny(31, n=64, nf=8, n_sets=6, rules=(1, 5), conds=(1, 3), ff_frac=0.3)
+    x, y, pop = w.data.x, w.data.y, w.pop
+    loss, grads = gpu_soft(ctx, w.data, pop)
+    tau = oracle.tau(x)
+    base = [pop.coef.astype(np.float64), pop.coef2.astype(np.float64), pop.theta.astype(np.float64)]
+    meanabs = np.abs(x.astype(np.float64)).mean(axis=0)
+
+    def total(ps):
+        return float(oracle.soft_forward(x, y, tau, 2, pop, *ps).sum())
+
+    fd = [np.zeros(pop.n_conds) for _ in range(3)]
+    for j in range(pop.n_conds):
+        f = pop.f[j]
+        for k in ([0, 1] if pop.kind[j] else [0, 2]):
+            h = 1e-4 * float(tau[f]) / (meanabs[pop.g[j] if k == 1 else f] if k < 2 else 1.0)
+            plus = [b.copy() for b in base]
+            minus = [b.copy() for b in base]
+            plus[k][j] += h
+            minus[k][j] -= h
+            fd[k][j] = (total(plus) - total(minus)) / (2 * h)
+    ra = oracle.soft_backward(x, y, tau, 2, pop, absolute=True)
+    check_grad(grads, fd, ra)
+
+
+def test_deterministic_repeats(ctx):
+    import torch
+    w = synth.soft_workload(8, n=4096, nf=8, n_sets=16, n_rules=6, n_conds=3)
+    ds = ctx.upload_dataset(w.data)
+    p = ctx.pack_population(w.pop, 8, 2)
+    c1, c2, th = params(w.pop, ctx.device)
+    dl = torch.ones(16, device=ctx.device)
+    l0 = ctx.soft_forward(ds, p, c1, c2, th)
+    g0 = ctx.soft_backward(ds, p, c1, c2, th, dl)
+    for _ in range(3):
+        assert torch.equal(ctx.soft_forward(ds, p, c1, c2, th), l0)
+        g = ctx.soft_backward(ds, p, c1, c2, th, dl)
+        assert all(torch.equal(a, b) for a, b in zip(g, g0))
+
+
+def test_autograd_function(ctx):
+    import torch
+    from paper_2406_01821_amd.aerl import SoftLoss
+    w = synth.soft_workload(9, n=2048, nf=8, n_sets=8, n_rules=5, n_conds=3)
+    ds = ctx.upload_dataset(w.data)
+    p = ctx.pack_population(w.pop, 8, 2)
+    c1, c2, th = [t.requires_grad_() for t in params(w.pop, ctx.device)]
+    loss = SoftLoss.apply(c1, c2, th, ctx, ds, p)
+    wts = torch.linspace(0.1, 1.0, 8, device=ctx.device)
+    (loss * wts).sum().backward()
+    tau = oracle.tau(w.data.x)
+    dl = wts.cpu().numpy().astype(np.float64)
+    rg = oracle.soft_backward(w.data.x, w.data.y, tau, 2, w.pop, dloss=dl)
+    ra = oracle.soft_backward(w.data.x, w.data.y, tau, 2, w.pop, dloss=dl, absolute=True)
+    check_grad([c1.grad.cpu().numpy().astype(np.float64), c2.grad.cpu().numpy().astype(np.float64),
+                th.grad.cpu().numpy().astype(np.float64)], rg, ra)
+
+
+def test_full_size_sampled_sets(ctx):
+    """262,144 x 32, 1024 rule sets x 16 rules x 4 conditions, in the launch
+    configuration the benchmark times; 8 sampled rule sets are recomputed by
+    the oracle."""
+    import torch
+    w = synth.soft_workload(3)
+    loss, grads = gpu_soft(ctx, w.data, w.pop)
+    sample = np.random.default_rng(1).choice(w.pop.n_sets, 8, replace=False)
+    sub = w.pop.subset(sample)
+    tau = oracle.tau(w.data.x)
+    check_loss(loss[sample], oracle.soft_forward(w.data.x, w.data.y, tau, 2, sub))
+    rg = oracle.soft_backward(w.data.x, w.data.y, tau, 2, sub)
+    ra = oracle.soft_backward(w.data.x, w.data.y, tau, 2, sub, absolute=True)
+    idx = np.concatenate([np.arange(w.pop.rule_cond_off[w.pop.set_rule_off[s]],
+                                    w.pop.rule_cond_off[w.pop.set_rule_off[s + 1]]) for s in sample])
+    check_grad([g[idx] for g in grads], rg, ra)

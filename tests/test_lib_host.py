@@ -85,7 +85,8 @@ def _align(v):
 def decode_packed(img, n_sets, n_rules, n_conds):
     """Splits the packed image into set records and the hard record stream."""
     sets_off = 0
-    rules_off = _align(sets_off + 16 * max(n_sets, 1))
+    ssets_off = _align(sets_off + 16 * max(n_sets, 1))
+    rules_off = _align(ssets_off + 16 * max(n_sets, 1))
     hc_off = _align(rules_off + 16 * max(n_rules, 1))
     sets = img[sets_off:sets_off + 16 * n_sets].view(np.int32).reshape(-1, 4)
     n_rec = n_conds + n_rules + 1
