@@ -66,13 +66,89 @@ def time_cpu_oracle_hard(w, budget_s=15.0):
                        f"{dt:.2f} s")
 
 
+# Algorithmic VALU work of the soft path, in lane issue slots (transcendentals
+# count twice: v_exp_f32 / v_log_f32 issue at half rate on gfx950).
+TRANS = 2
+SOFT_FWD_COND = 6 + 2 * TRANS      # z, log sigmoid(z), accumulate
+SOFT_FWD_RULE = 10 + 3 * TRANS     # log(1-r), survival, class log-sum-exp
+SOFT_BWD_COND = 10 + 3 * TRANS     # sigmoid(-z), dL/dz, parameter terms
+SOFT_BWD_RULE = 3 * TRANS          # suffix recurrence
+
+
+def timed(fn, steps, warmup, stream):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    return float(np.mean([a.elapsed_time(b) for a, b in ev])), wall * 1e3
+
+
+def bench_soft(ctx, steps, warmup, cpu):
+    import torch
+    import oracle
+    from paper_2406_01821_amd import synth
+    w = synth.soft_workload(3)
+    ds = ctx.upload_dataset(w.data)
+    pop = ctx.pack_population(w.pop, w.data.n_features, w.data.n_classes)
+    dev = ctx.device
+    c1, c2, th = [torch.tensor(a, device=dev) for a in (w.pop.coef, w.pop.coef2, w.pop.theta)]
+    wsf = ctx.soft_workspace(ds, pop, False)
+    wsb = ctx.soft_workspace(ds, pop, True)
+    dl = torch.ones(w.pop.n_sets, device=dev)
+    stream = torch.cuda.current_stream()
+    fwd_ms, _ = timed(lambda: ctx.soft_forward(ds, pop, c1, c2, th, ws=wsf), steps, warmup, stream)
+    bwd_ms, _ = timed(lambda: ctx.soft_backward(ds, pop, c1, c2, th, dl, ws=wsb), steps, warmup,
+                      stream)
+    n = w.data.n
+    conds = int(w.pop.nominal_conds_per_set().sum()) * n
+    rules = w.pop.n_rules * n
+    fwd_slots = float(SOFT_FWD_COND * conds + SOFT_FWD_RULE * rules)
+    bwd_slots = fwd_slots + float(SOFT_BWD_COND * conds + SOFT_BWD_RULE * rules)
+    out = {
+        "workload": "soft, 262,144 x 32 fp32 samples, 2 classes, 1024 rule sets x 16 rules x 4 "
+                    "threshold conditions, tau = 0.05 std",
+        "forward": {"ms": fwd_ms, "cond_evals_per_s": conds / (fwd_ms * 1e-3),
+                    "roofline": {"bound": "alu", "achieved": fwd_slots / (fwd_ms * 1e-3) / 1e12,
+                                 "peak": VALU_PEAK / 1e12, "unit": "Tlane-op/s",
+                                 "frac": fwd_slots / (fwd_ms * 1e-3) / VALU_PEAK}},
+        "backward": {"ms": bwd_ms, "cond_evals_per_s": conds / (bwd_ms * 1e-3),
+                     "roofline": {"bound": "alu", "achieved": bwd_slots / (bwd_ms * 1e-3) / 1e12,
+                                  "peak": VALU_PEAK / 1e12, "unit": "Tlane-op/s",
+                                  "frac": bwd_slots / (bwd_ms * 1e-3) / VALU_PEAK}},
+    }
+    log(f"soft forward {fwd_ms:.3f} ms, backward {bwd_ms:.3f} ms")
+    if cpu:
+        tau = oracle.tau(w.data.x)
+        sub = w.pop.subset(range(4))
+        t0 = time.perf_counter()
+        oracle.soft_forward(w.data.x, w.data.y, tau, 2, sub)
+        dt = time.perf_counter() - t0
+        sub_conds = int(sub.nominal_conds_per_set().sum()) * n
+        out["cpu_baseline_forward"] = {"value": sub_conds / dt, "unit": "cond-evals/s",
+                                       "cores": oracle.max_threads(), "kind": "oracle",
+                                       "sample": f"first 4 of 1024 rule sets x all {n} samples, "
+                                                 f"fp64, {dt:.2f} s"}
+    ctx.release_population(pop)
+    ctx.release_dataset(ds)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--only-hard", action="store_true")
+    ap.add_argument("--only-hard", action="store_true", help="time the hard path only")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -92,25 +168,11 @@ def main():
     out = ctx.eval_population(ds, pop)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
-    for _ in range(args.warmup):
-        ctx.eval_population(ds, pop, out=out)
-    torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for a, b in ev:
-        a.record(stream)
-        ctx.eval_population(ds, pop, out=out)
-        b.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_start
-    step_ms = [a.elapsed_time(b) for a, b in ev]
-    ms = float(np.mean(step_ms))
-    log(f"hard eval: mean {ms:.3f} ms, min {min(step_ms):.3f}, max {max(step_ms):.3f} "
-        f"(wall {wall / args.steps * 1e3:.3f} ms/step)")
+    ms, wall_ms = timed(lambda: ctx.eval_population(ds, pop, out=out), args.steps, args.warmup,
+                        stream)
+    log(f"hard eval: kernel+fills {ms:.3f} ms/step (wall {wall_ms:.3f} ms/step)")
     nominal = int(w.pop.nominal_conds_per_set().sum()) * w.data.n
-    value = nominal / (wall / args.steps)
+    value = nominal / (wall_ms * 1e-3)
 
     rec = algorithmic_work(w)
     lane_ops = 64.0 * (2.0 * rec["total_t"] + 3.0 * rec["total_ff"])
@@ -122,7 +184,7 @@ def main():
     result = {
         "metric": "rule-condition evals/s (hard fitness, nominal)",
         "value": value, "unit": "cond-evals/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
+        "warmup": args.warmup, "ms_per_step": wall_ms,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "hard fitness, 2^20 x 64 fp32 samples, 4 classes, 4096 rule sets "
@@ -134,6 +196,11 @@ def main():
     }
     if not args.no_cpu:
         result["cpu_baseline"] = time_cpu_oracle_hard(w)
+    ctx.release_population(pop)
+    ctx.release_dataset(ds)
+    del w
+    if not args.only_hard:
+        result["soft"] = bench_soft(ctx, max(3, args.steps // 4), 1, not args.no_cpu)
     print(json.dumps(result), flush=True)
     ctx.close()
 

@@ -223,6 +223,76 @@ aerl_status aerl_eval_population_cfg(aerl_ctx *ctx, int32_t dataset_id, int32_t 
 aerl_status aerl_predict(aerl_ctx *ctx, int32_t pop_id, int32_t set, const float *rows, int64_t n,
                          int32_t *pred, hipStream_t stream);
 
+/* ----------------------------------------------------------- ragged batch */
+
+/* Many independent evaluations (each its own dataset and population, of any
+ * shapes) in ONE persistent launch, the form in which an evolution loop that
+ * runs several populations or datasets keeps the whole GPU busy (Section 3:
+ * candidates are handed to the GPU for evaluation; Section 4.2: the cost
+ * varies with the number of rules and conditions per generation).  Results
+ * are bit-identical to aerl_eval_population of each item. */
+typedef struct {
+  int32_t dataset_id;
+  int32_t pop_id;
+  int32_t *correct;   /* device int32 [n_sets of pop] */
+  int32_t *confusion; /* device int32 [n_sets][C][C] or NULL */
+} aerl_batch_item;
+
+/* Work-split of a batch: rule sets per work item, AERL_TILE-sample tiles per
+ * work item.  0 in both fields asks for the library's choice (the tuned one
+ * when aerl_autotune has seen a batch of this shape, else a heuristic). */
+typedef struct {
+  int32_t sets_per_task;
+  int32_t tiles_per_task;
+} aerl_batch_cfg;
+
+enum {
+  AERL_BATCH_GRAPH = 1 /* capture the launch sequence once in a hipGraph and replay it */
+};
+
+/* Device workspace needed by aerl_batch_plan for these items and cfg (NULL
+ * cfg = library choice).  Errors: AERL_ENOENT, AERL_EINVAL. */
+aerl_status aerl_batch_workspace_bytes(aerl_ctx *ctx, const aerl_batch_item *items,
+                                       int32_t n_items, const aerl_batch_cfg *cfg,
+                                       size_t *bytes);
+
+/* Build the work list of a batch (one work item = a chunk of rule sets of one
+ * item on a group of label-uniform tiles of its dataset, ordered by
+ * estimated cost, largest first) and store it in the caller's device
+ * workspace `ws` (kept alive until aerl_batch_release); the tables are
+ * copied before the call returns (`stream` is synchronized).  With
+ * AERL_BATCH_GRAPH the zeroing of the outputs and the persistent kernel are
+ * captured once (on a private stream) into a hipGraph that every
+ * aerl_batch_run replays on its stream.  ws: 256-byte aligned.
+ * The items' datasets, populations and output buffers must stay registered
+ * and allocated while the plan exists.  *plan_id receives the id.
+ * Errors: AERL_ENOENT, AERL_EINVAL (shape mismatch, NULL outputs),
+ * AERL_ENOMEM (ws too small), AERL_EDEVICE. */
+aerl_status aerl_batch_plan(aerl_ctx *ctx, const aerl_batch_item *items, int32_t n_items,
+                            const aerl_batch_cfg *cfg, void *ws, size_t ws_bytes, uint32_t flags,
+                            hipStream_t stream, int32_t *plan_id);
+
+/* Run a plan on `stream`: zero every item's outputs, then one persistent
+ * kernel whose workgroups pull work items from a device counter until the
+ * list is exhausted.  Asynchronous.  Errors: AERL_ENOENT, AERL_EDEVICE. */
+aerl_status aerl_batch_run(aerl_ctx *ctx, int32_t plan_id, hipStream_t stream);
+
+/* Forget a plan (and its graph).  Errors: AERL_ENOENT. */
+aerl_status aerl_batch_release(aerl_ctx *ctx, int32_t plan_id);
+
+/* Autotuner: times the batch under candidate work-splits on `stream`
+ * (outputs are overwritten), keeps the fastest for batches of this shape
+ * (number of items, and per item the feature count, sample tiles, rule sets
+ * and conditions, each bucketed by powers of two) and returns it in *best
+ * with its time in *best_ms.  Later plans with cfg NULL or zero fields use
+ * it.  With AERL_AUTOTUNE_CACHE set in the environment the table is also
+ * read from and appended to that file.  ws as for aerl_batch_plan with the
+ * largest candidate (aerl_batch_workspace_bytes with cfg {1, 1}).
+ * Errors: as aerl_batch_plan. */
+aerl_status aerl_autotune(aerl_ctx *ctx, const aerl_batch_item *items, int32_t n_items, void *ws,
+                          size_t ws_bytes, hipStream_t stream, aerl_batch_cfg *best,
+                          float *best_ms);
+
 /* ------------------------------------------------------------------ soft */
 
 /* Device scratch needed by aerl_soft_forward / aerl_soft_backward for this

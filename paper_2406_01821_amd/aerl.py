@@ -50,6 +50,18 @@ class aerl_dataset_info(C.Structure):
                 ("tau", C.c_void_p)]
 
 
+class aerl_batch_item(C.Structure):
+    _fields_ = [("dataset_id", C.c_int32), ("pop_id", C.c_int32),
+                ("correct", C.c_void_p), ("confusion", C.c_void_p)]
+
+
+class aerl_batch_cfg(C.Structure):
+    _fields_ = [("sets_per_task", C.c_int32), ("tiles_per_task", C.c_int32)]
+
+
+AERL_BATCH_GRAPH = 1
+
+
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run paper_2406_01821_amd/build_lib.py "
                       "or __graft_entry__.build()")
@@ -72,6 +84,14 @@ _SIGS = {
     "aerl_eval_population_cfg": ([_P, _I32, _I32, _P, _P, _I32, _I32, _I32, _P], _I32),
     "aerl_eval_population": ([_P, _I32, _I32, _P, _P, _P], _I32),
     "aerl_predict": ([_P, _I32, _I32, _P, _I64, _P, _P], _I32),
+    "aerl_batch_workspace_bytes": ([_P, C.POINTER(aerl_batch_item), _I32,
+                                    C.POINTER(aerl_batch_cfg), C.POINTER(_SZ)], _I32),
+    "aerl_batch_plan": ([_P, C.POINTER(aerl_batch_item), _I32, C.POINTER(aerl_batch_cfg), _P,
+                         _SZ, C.c_uint32, _P, C.POINTER(_I32)], _I32),
+    "aerl_batch_run": ([_P, _I32, _P], _I32),
+    "aerl_batch_release": ([_P, _I32], _I32),
+    "aerl_autotune": ([_P, C.POINTER(aerl_batch_item), _I32, _P, _SZ, _P,
+                       C.POINTER(aerl_batch_cfg), C.POINTER(C.c_float)], _I32),
     "aerl_soft_workspace_bytes": ([_P, _I32, _I32, C.POINTER(_SZ), C.POINTER(_SZ)], _I32),
     "aerl_soft_forward": ([_P, _I32, _I32, _P, _P, _P, _P, _P, _SZ, _P], _I32),
     "aerl_soft_backward": ([_P, _I32, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _SZ, _P], _I32),
@@ -262,6 +282,45 @@ class Context:
                                 _stream(stream)))
         return pred
 
+    # ---------------------------------------------------------- ragged batch
+    def _batch_items(self, items):
+        arr = (aerl_batch_item * max(len(items), 1))()
+        for i, (ds, pop, correct, conf) in enumerate(items):
+            arr[i] = aerl_batch_item(ds.id, pop.id, _ptr(correct), _ptr(conf))
+        return arr
+
+    def batch_outputs(self, ds: DeviceDataset, pop: DevicePopulation, confusion: bool = True):
+        correct = torch.empty(pop.n_sets, dtype=torch.int32, device=self.device)
+        conf = (torch.empty((pop.n_sets, ds.n_classes, ds.n_classes), dtype=torch.int32,
+                            device=self.device) if confusion else None)
+        return correct, conf
+
+    def batch_workspace(self, items, cfg=None):
+        """items: list of (DeviceDataset, DevicePopulation, correct, confusion-or-None)."""
+        arr = self._batch_items(items)
+        nb = C.c_size_t()
+        c = C.byref(aerl_batch_cfg(*cfg)) if cfg is not None else None
+        self.check(aerl_batch_workspace_bytes(self.h, arr, len(items), c, C.byref(nb)))
+        return torch.empty(max(nb.value, 256), dtype=torch.uint8, device=self.device)
+
+    def batch_plan(self, items, ws, cfg=None, graph: bool = False, stream=None) -> "BatchPlan":
+        arr = self._batch_items(items)
+        c = C.byref(aerl_batch_cfg(*cfg)) if cfg is not None else None
+        pid = C.c_int32()
+        self.check(aerl_batch_plan(self.h, arr, len(items), c, _ptr(ws), ws.numel(),
+                                   AERL_BATCH_GRAPH if graph else 0, _stream(stream),
+                                   C.byref(pid)))
+        return BatchPlan(self, pid.value, list(items), ws)
+
+    def autotune(self, items, ws, stream=None):
+        """Returns ((sets_per_task, tiles_per_task), ms)."""
+        arr = self._batch_items(items)
+        best = aerl_batch_cfg()
+        ms = C.c_float()
+        self.check(aerl_autotune(self.h, arr, len(items), _ptr(ws), ws.numel(), _stream(stream),
+                                 C.byref(best), C.byref(ms)))
+        return (best.sets_per_task, best.tiles_per_task), ms.value
+
     # ------------------------------------------------------------ soft path
     def soft_workspace(self, ds: DeviceDataset, pop: DevicePopulation, backward: bool):
         fb, bb = C.c_size_t(), C.c_size_t()
@@ -283,6 +342,21 @@ class Context:
                                       _ptr(dloss), _ptr(g[0]), _ptr(g[1]), _ptr(g[2]), _ptr(ws),
                                       ws.numel(), _stream(stream)))
         return tuple(g)
+
+
+class BatchPlan:
+    """A planned ragged batch; holds the item buffers and workspace alive."""
+
+    def __init__(self, ctx: Context, plan_id: int, items, ws):
+        self.ctx, self.id, self.items, self.ws = ctx, plan_id, items, ws
+
+    def run(self, stream=None):
+        self.ctx.check(aerl_batch_run(self.ctx.h, self.id, _stream(stream)))
+
+    def release(self):
+        if self.id is not None:
+            self.ctx.check(aerl_batch_release(self.ctx.h, self.id))
+            self.id = None
 
 
 class SoftLoss(torch.autograd.Function):

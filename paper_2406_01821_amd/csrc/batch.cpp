@@ -1,0 +1,390 @@
+// Ragged batch planning, hipGraph capture and the autotuner (host side).
+//
+// A plan turns a list of (dataset, population) evaluations into one work
+// list: work item = (item, chunk of rule sets, group of label-uniform tiles).
+// Items are cut with the same (rule sets, tiles) per work item; each item
+// picks its own tile width from its feature count.  Work items are sorted by
+// estimated cost (samples x nominal conditions), largest first, so that the
+// persistent grid's dynamic pull ends evenly.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+
+#include "batch.h"
+
+namespace aerl {
+
+struct BatchPlanRec {
+  BatchLaunch launch{};
+  void *ws = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t capture = nullptr;
+  std::vector<int32_t> dataset_ids, pop_ids;
+  int32_t sets_per_task = 0, tiles_per_task = 0;
+};
+
+void destroy_plan(BatchPlanRec *p) {
+  if (!p) return;
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->capture) (void)hipStreamDestroy(p->capture);
+  delete p;
+}
+
+namespace {
+
+constexpr size_t kBatchLdsMax = kDynLdsMax;
+constexpr size_t kTileBudget = 64 * 1024;  // feature tile of one block, so two fit a CU
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+int samples_per_lane(int32_t nf) {
+  int s = 4;
+  while (s > 1 && (size_t)nf * 256 * s > kTileBudget) s >>= 1;
+  return s;
+}
+
+struct ItemView {
+  const DatasetRec *ds;
+  const PopRec *pop;
+  const aerl_batch_item *item;
+};
+
+aerl_status gather(aerl_ctx *ctx, const aerl_batch_item *items, int32_t n, std::vector<ItemView> *out) {
+  if (n < 0 || (n > 0 && !items)) return fail(ctx, AERL_EINVAL, "bad item list");
+  out->clear();
+  for (int32_t i = 0; i < n; ++i) {
+    auto di = ctx->datasets.find(items[i].dataset_id);
+    if (di == ctx->datasets.end()) return fail(ctx, AERL_ENOENT, "item %d: unknown dataset %d", i, items[i].dataset_id);
+    auto pi = ctx->pops.find(items[i].pop_id);
+    if (pi == ctx->pops.end()) return fail(ctx, AERL_ENOENT, "item %d: unknown population %d", i, items[i].pop_id);
+    if (pi->second.nf != di->second.nf || pi->second.nc != di->second.nc)
+      return fail(ctx, AERL_EINVAL, "item %d: population and dataset shapes differ", i);
+    if (pi->second.n_sets > 0 && !items[i].correct)
+      return fail(ctx, AERL_EINVAL, "item %d: correct is NULL", i);
+    if ((size_t)di->second.nf * 64 * 4 + (size_t)di->second.nc * 4 > kBatchLdsMax)
+      return fail(ctx, AERL_EINVAL, "item %d: %d features exceed the LDS tile", i, di->second.nf);
+    out->push_back({&di->second, &pi->second, &items[i]});
+  }
+  return AERL_OK;
+}
+
+// Per-set nominal condition counts, read from the population's host staging
+// copy of its packed image (set records carry them in .w).
+const int4 *host_sets(const PopRec &p) {
+  return static_cast<const int4 *>(p.staging);  // sets are the first region of the image
+}
+
+struct Built {
+  std::vector<BatchItem> items;
+  std::vector<BatchTask> tasks;
+  std::vector<BatchZero> zero;
+  size_t lds = 0;
+};
+
+void build(const std::vector<ItemView> &v, int32_t Q, int32_t TG, Built *b) {
+  b->items.clear();
+  b->tasks.clear();
+  b->zero.clear();
+  b->lds = 0;
+  std::vector<std::pair<double, BatchTask>> costed;
+  for (size_t i = 0; i < v.size(); ++i) {
+    const DatasetRec &ds = *v[i].ds;
+    const PopRec &pop = *v[i].pop;
+    const int S = samples_per_lane(ds.nf);
+    BatchItem it{};
+    it.x_fm = ds.x_fm;
+    it.n_pad = ds.n_pad;
+    it.tile_info = ds.tile_info;
+    it.sets = pop.sets;
+    it.conds = pop.hconds;
+    it.correct = v[i].item->correct;
+    it.confusion = v[i].item->confusion;
+    it.nf = ds.nf;
+    it.nc = ds.nc;
+    it.S = S;
+    b->items.push_back(it);
+    if (pop.n_sets > 0) {
+      b->zero.push_back({it.correct, pop.n_sets});
+      if (it.confusion) b->zero.push_back({it.confusion, (int64_t)pop.n_sets * ds.nc * ds.nc});
+    }
+    const size_t tile_bytes = (size_t)ds.nf * 64 * S * 4;
+    const int32_t q_fit = (int32_t)std::min<size_t>((kBatchLdsMax - tile_bytes) / (ds.nc * 4), 1 << 20);
+    const int32_t q = std::max(1, std::min({Q, pop.n_sets, q_fit}));
+    b->lds = std::max(b->lds, (size_t)ds.nf * 64 * S * 4 + (size_t)q * ds.nc * 4);
+    const int4 *hs = host_sets(pop);
+    for (int32_t q0 = 0; q0 < pop.n_sets; q0 += q) {
+      const int32_t qe = std::min(q, pop.n_sets - q0);
+      double work = 0;
+      for (int32_t k = q0; k < q0 + qe; ++k) work += (double)hs[k].w + 1.0;
+      for (int c = 0; c < ds.nc; ++c) {
+        for (int32_t t0 = 0; t0 < ds.region_tiles[c]; t0 += TG) {
+          BatchTask tk{};
+          tk.item = (int32_t)i;
+          tk.q0 = q0;
+          tk.Q = qe;
+          tk.tile_lo = ds.region_tile0[c] + t0;
+          tk.tile_hi = ds.region_tile0[c] + std::min(t0 + TG, ds.region_tiles[c]);
+          tk.label = c;
+          costed.push_back({work * (double)(tk.tile_hi - tk.tile_lo), tk});
+        }
+      }
+    }
+  }
+  std::stable_sort(costed.begin(), costed.end(),
+                   [](const auto &x, const auto &y) { return x.first > y.first; });
+  for (auto &c : costed) b->tasks.push_back(c.second);
+}
+
+struct WsLayout {
+  size_t items_off, tasks_off, zero_off, counter_off, total;
+};
+
+WsLayout ws_layout(const Built &b) {
+  WsLayout L{};
+  size_t off = 0;
+  L.items_off = off;   off = align256(off + sizeof(BatchItem) * std::max<size_t>(b.items.size(), 1));
+  L.tasks_off = off;   off = align256(off + sizeof(BatchTask) * std::max<size_t>(b.tasks.size(), 1));
+  L.zero_off = off;    off = align256(off + sizeof(BatchZero) * std::max<size_t>(b.zero.size(), 1));
+  L.counter_off = off; off = align256(off + sizeof(int32_t));
+  L.total = off;
+  return L;
+}
+
+int log2_bucket(double v) { return v <= 1 ? 0 : (int)std::ceil(std::log2(v)); }
+
+std::string shape_key(const std::vector<ItemView> &v) {
+  std::ostringstream k;
+  k << "n" << v.size();
+  for (const auto &it : v) {
+    const double conds = it.pop->n_sets > 0 ? (double)it.pop->nominal_conds / it.pop->n_sets : 0;
+    k << "|" << log2_bucket(it.ds->nf) << "," << log2_bucket((double)it.ds->n_tiles) << ","
+      << log2_bucket(it.pop->n_sets) << "," << log2_bucket(conds);
+  }
+  return k.str();
+}
+
+void load_tune_file(aerl_ctx *ctx) {
+  if (ctx->tune_file_loaded) return;
+  ctx->tune_file_loaded = true;
+  const char *path = std::getenv("AERL_AUTOTUNE_CACHE");
+  if (!path) return;
+  std::ifstream in(path);
+  std::string key;
+  int32_t q, tg;
+  double ms;
+  while (in >> key >> q >> tg >> ms) ctx->tuned[key] = {q, tg};
+}
+
+void default_cfg(aerl_ctx *ctx, const std::vector<ItemView> &v, const aerl_batch_cfg *cfg,
+                 int32_t *Q, int32_t *TG) {
+  *Q = cfg ? cfg->sets_per_task : 0;
+  *TG = cfg ? cfg->tiles_per_task : 0;
+  if (*Q > 0 && *TG > 0) return;
+  load_tune_file(ctx);
+  auto it = ctx->tuned.find(shape_key(v));
+  int32_t q = 64, tg = 4;
+  if (it != ctx->tuned.end()) {
+    q = it->second.first;
+    tg = it->second.second;
+  }
+  if (*Q <= 0) *Q = q;
+  if (*TG <= 0) *TG = tg;
+}
+
+aerl_status upload_plan(aerl_ctx *ctx, const Built &b, void *ws, size_t ws_bytes, hipStream_t st,
+                        BatchPlanRec *plan) {
+  const WsLayout L = ws_layout(b);
+  if (!ws || ((uintptr_t)ws & 255)) return fail(ctx, AERL_EINVAL, "ws is NULL or not 256-byte aligned");
+  if (ws_bytes < L.total) return fail(ctx, AERL_ENOMEM, "ws holds %zu bytes, %zu needed", ws_bytes, L.total);
+  if (b.lds > kBatchLdsMax) return fail(ctx, AERL_EINVAL, "work split needs %zu bytes of LDS", b.lds);
+  std::vector<char> img(L.total, 0);
+  std::memcpy(img.data() + L.items_off, b.items.data(), sizeof(BatchItem) * b.items.size());
+  std::memcpy(img.data() + L.tasks_off, b.tasks.data(), sizeof(BatchTask) * b.tasks.size());
+  std::memcpy(img.data() + L.zero_off, b.zero.data(), sizeof(BatchZero) * b.zero.size());
+  void *pinned = nullptr;
+  AERL_HIP(ctx, hipHostMalloc(&pinned, L.total, hipHostMallocDefault));
+  std::memcpy(pinned, img.data(), L.total);
+  hipError_t e = hipMemcpyAsync(ws, pinned, L.total, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipHostFree(pinned);
+  if (e != hipSuccess) return fail(ctx, AERL_EDEVICE, "plan upload failed: %s", hipGetErrorString(e));
+  char *base = static_cast<char *>(ws);
+  BatchLaunch &bl = plan->launch;
+  bl.items = reinterpret_cast<const BatchItem *>(base + L.items_off);
+  bl.tasks = reinterpret_cast<const BatchTask *>(base + L.tasks_off);
+  bl.zero = reinterpret_cast<const BatchZero *>(base + L.zero_off);
+  bl.counter = reinterpret_cast<int32_t *>(base + L.counter_off);
+  bl.n_tasks = (int32_t)b.tasks.size();
+  bl.n_zero = (int32_t)b.zero.size();
+  bl.lds = b.lds;
+  const int per_cu = 2 * (b.lds + kStaticLds) <= kLdsPerCu ? 2 : 1;
+  bl.grid = (int64_t)ctx->n_cu * per_cu;
+  plan->ws = ws;
+  return AERL_OK;
+}
+
+}  // namespace
+}  // namespace aerl
+
+using namespace aerl;
+
+extern "C" {
+
+aerl_status aerl_batch_workspace_bytes(aerl_ctx *ctx, const aerl_batch_item *items, int32_t n_items,
+                                       const aerl_batch_cfg *cfg, size_t *bytes) {
+  if (!ctx || !bytes) return AERL_EINVAL;
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  std::vector<ItemView> v;
+  aerl_status st = gather(ctx, items, n_items, &v);
+  if (st) return st;
+  int32_t Q, TG;
+  default_cfg(ctx, v, cfg, &Q, &TG);
+  Built b;
+  build(v, Q, TG, &b);
+  *bytes = ws_layout(b).total;
+  return AERL_OK;
+}
+
+aerl_status aerl_batch_plan(aerl_ctx *ctx, const aerl_batch_item *items, int32_t n_items,
+                            const aerl_batch_cfg *cfg, void *ws, size_t ws_bytes, uint32_t flags,
+                            hipStream_t stream, int32_t *plan_id) {
+  if (!ctx) return AERL_EINVAL;
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  ctx->err.clear();
+  if (!plan_id) return fail(ctx, AERL_EINVAL, "plan_id is NULL");
+  std::vector<ItemView> v;
+  aerl_status st = gather(ctx, items, n_items, &v);
+  if (st) return st;
+  int32_t Q, TG;
+  default_cfg(ctx, v, cfg, &Q, &TG);
+  if (Q < 1 || TG < 1) return fail(ctx, AERL_EINVAL, "work split must be >= 1");
+  AERL_HIP(ctx, hipSetDevice(ctx->device));
+  Built b;
+  build(v, Q, TG, &b);
+  std::unique_ptr<BatchPlanRec, PlanDeleter> plan(new BatchPlanRec());
+  st = upload_plan(ctx, b, ws, ws_bytes, stream, plan.get());
+  if (st) return st;
+  plan->sets_per_task = Q;
+  plan->tiles_per_task = TG;
+  for (const auto &it : v) {
+    plan->dataset_ids.push_back(it.item->dataset_id);
+    plan->pop_ids.push_back(it.item->pop_id);
+  }
+  if (flags & AERL_BATCH_GRAPH) {
+    // Captured on a private stream (the caller's may be the legacy default
+    // stream, which cannot be captured) and replayed on the caller's stream.
+    AERL_HIP(ctx, hipStreamCreateWithFlags(&plan->capture, hipStreamNonBlocking));
+    AERL_HIP(ctx, hipStreamBeginCapture(plan->capture, hipStreamCaptureModeThreadLocal));
+    hipError_t e = launch_batch(plan->launch, plan->capture);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(plan->capture, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return fail(ctx, AERL_EDEVICE, "graph capture failed: %s",
+                  hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    plan->graph = g;
+    AERL_HIP(ctx, hipGraphInstantiate(&plan->exec, g, nullptr, nullptr, 0));
+  }
+  const int32_t id = ctx->next_id++;
+  ctx->plans[id] = std::move(plan);
+  *plan_id = id;
+  return AERL_OK;
+}
+
+aerl_status aerl_batch_run(aerl_ctx *ctx, int32_t plan_id, hipStream_t stream) {
+  if (!ctx) return AERL_EINVAL;
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  ctx->err.clear();
+  auto it = ctx->plans.find(plan_id);
+  if (it == ctx->plans.end()) return fail(ctx, AERL_ENOENT, "unknown plan %d", plan_id);
+  for (size_t i = 0; i < it->second->dataset_ids.size(); ++i) {
+    if (!ctx->datasets.count(it->second->dataset_ids[i]) || !ctx->pops.count(it->second->pop_ids[i]))
+      return fail(ctx, AERL_ENOENT, "plan %d refers to a released dataset or population", plan_id);
+  }
+  AERL_HIP(ctx, hipSetDevice(ctx->device));
+  if (it->second->exec) {
+    AERL_HIP(ctx, hipGraphLaunch(it->second->exec, stream));
+  } else {
+    AERL_HIP(ctx, launch_batch(it->second->launch, stream));
+  }
+  return AERL_OK;
+}
+
+aerl_status aerl_batch_release(aerl_ctx *ctx, int32_t plan_id) {
+  if (!ctx) return AERL_EINVAL;
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  if (!ctx->plans.erase(plan_id)) return fail(ctx, AERL_ENOENT, "unknown plan %d", plan_id);
+  return AERL_OK;
+}
+
+aerl_status aerl_autotune(aerl_ctx *ctx, const aerl_batch_item *items, int32_t n_items, void *ws,
+                          size_t ws_bytes, hipStream_t stream, aerl_batch_cfg *best,
+                          float *best_ms) {
+  if (!ctx) return AERL_EINVAL;
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  ctx->err.clear();
+  if (!best) return fail(ctx, AERL_EINVAL, "best is NULL");
+  std::vector<ItemView> v;
+  aerl_status st = gather(ctx, items, n_items, &v);
+  if (st) return st;
+  AERL_HIP(ctx, hipSetDevice(ctx->device));
+  static const int32_t kQ[] = {16, 32, 64, 128};
+  static const int32_t kTG[] = {1, 2, 4, 8, 16};
+  hipEvent_t e0, e1;
+  AERL_HIP(ctx, hipEventCreate(&e0));
+  AERL_HIP(ctx, hipEventCreate(&e1));
+  float best_t = 1e30f;
+  int32_t bq = 64, btg = 4;
+  for (int32_t q : kQ) {
+    for (int32_t tg : kTG) {
+      Built b;
+      build(v, q, tg, &b);
+      if (b.lds > kBatchLdsMax) continue;
+      BatchPlanRec tmp;
+      if (upload_plan(ctx, b, ws, ws_bytes, stream, &tmp) != AERL_OK) continue;
+      hipError_t e = launch_batch(tmp.launch, stream);  // warm-up
+      float t = 0.0f;
+      for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
+        if (e == hipSuccess) e = hipEventRecord(e0, stream);
+        if (e == hipSuccess) e = launch_batch(tmp.launch, stream);
+        if (e == hipSuccess) e = hipEventRecord(e1, stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        t += ms;
+      }
+      if (e != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return fail(ctx, AERL_EDEVICE, "autotune launch failed: %s", hipGetErrorString(e));
+      }
+      t *= 0.5f;
+      if (t < best_t) {
+        best_t = t;
+        bq = q;
+        btg = tg;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  const std::string key = shape_key(v);
+  ctx->tuned[key] = {bq, btg};
+  if (const char *path = std::getenv("AERL_AUTOTUNE_CACHE")) {
+    std::ofstream out(path, std::ios::app);
+    out << key << " " << bq << " " << btg << " " << best_t << "\n";
+  }
+  best->sets_per_task = bq;
+  best->tiles_per_task = btg;
+  if (best_ms) *best_ms = best_t;
+  return AERL_OK;
+}
+
+}  // extern "C"

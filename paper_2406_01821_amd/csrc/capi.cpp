@@ -82,8 +82,7 @@ void hard_config(const DatasetRec &ds, int32_t n_sets, int n_cu, int *S, int *Q,
     return ((n_sets + qq - 1) / qq) * g;
   };
   while (q > 16 && blocks(q, 1) < target) q >>= 1;
-  const size_t lds_max = 160 * 1024;
-  while (q > 1 && (size_t)ds.nf * 64 * s * 4 + (size_t)q * ds.nc * 4 > lds_max) q >>= 1;
+  while (q > 1 && (size_t)ds.nf * 64 * s * 4 + (size_t)q * ds.nc * 4 > kDynLdsMax) q >>= 1;
   int64_t tg = 1;
   while (tg * 2 <= tiles && blocks(q, tg * 2) >= target) tg *= 2;
   *Q = q;
@@ -353,8 +352,8 @@ static aerl_status eval_common(aerl_ctx *ctx, int32_t dataset_id, int32_t pop_id
   } else {
     if (S != 1 && S != 2 && S != 4) return fail(ctx, AERL_EINVAL, "samples_per_lane %d not in {1,2,4}", S);
     if (Q < 1 || TG < 1) return fail(ctx, AERL_EINVAL, "sets_per_chunk and tiles_per_group must be >= 1");
-    if ((size_t)ds.nf * 256 * S + (size_t)Q * ds.nc * 4 > 160 * 1024)
-      return fail(ctx, AERL_EINVAL, "configuration needs more than 160 KiB of LDS");
+    if ((size_t)ds.nf * 256 * S + (size_t)Q * ds.nc * 4 > kDynLdsMax)
+      return fail(ctx, AERL_EINVAL, "configuration needs more LDS than a workgroup can have");
     h.samples_per_lane = S;
     h.sets_per_chunk = Q;
     h.tiles_per_group = TG;

@@ -1,0 +1,83 @@
+// One workgroup's share of a hard fitness evaluation: rule sets
+// [q0, q0+Q) of one population on tiles [tile_lo, tile_hi) of one class
+// region (every sample has label `label`).  Shared by the one-launch-per-
+// population kernel and the persistent batch kernel.
+#pragma once
+
+#include "eval_core.h"
+#include "internal.h"
+
+namespace aerl {
+
+struct HardTask {
+  const float *x_fm;
+  int64_t n_pad;
+  int32_t nf, nc;
+  const int32_t *tile_info;
+  const int4 *sets;   // the population's set records
+  const uint4 *conds; // the population's record stream
+  int32_t *correct;   // [n_sets]
+  int32_t *confusion; // [n_sets][nc][nc] or null
+  int32_t q0, Q, tile_lo, tile_hi, label;
+};
+
+// Stages one wave tile (64*S samples x nf features) at a time into LDS and
+// lets the waves pull rule sets from an LDS counter; per-class prediction
+// counts live in LDS (one writer per rule set and tile) and reach the
+// outputs once, through integer atomics.  smem holds nf*64*S floats followed
+// by Q*nc counters.  Ends with a barrier, so the caller may reuse smem.
+template <int S>
+__device__ __forceinline__ void hard_block(const HardTask &t, float *smem, int32_t *next_q) {
+  constexpr int TS = 64 * S;           // samples per wave tile
+  constexpr int WPT = AERL_TILE / TS;  // wave tiles per layout tile
+  float *xs = smem;                                                    // [nf][TS]
+  int32_t *cnt = reinterpret_cast<int32_t *>(smem + (size_t)t.nf * TS);  // [Q][nc]
+  const int lane = threadIdx.x & 63;
+  for (int i = threadIdx.x; i < t.Q * t.nc; i += blockDim.x) cnt[i] = 0;
+  const int n4 = t.nf * (TS / 4);
+  const float4 *src = reinterpret_cast<const float4 *>(t.x_fm);
+  float4 *dst = reinterpret_cast<float4 *>(xs);
+  const int64_t row4 = t.n_pad / 4;
+  const uint32_t lds_lane =
+      (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) float *)xs + (uint32_t)lane * (4u * S);
+  for (int64_t wt = (int64_t)t.tile_lo * WPT; wt < (int64_t)t.tile_hi * WPT; ++wt) {
+    __syncthreads();  // everyone is done with the previous tile
+    const int64_t base4 = wt * (TS / 4);
+    for (int i = threadIdx.x; i < n4; i += blockDim.x) {
+      const int f = i / (TS / 4), k = i % (TS / 4);
+      dst[i] = src[(int64_t)f * row4 + base4 + k];
+    }
+    if (threadIdx.x == 0) *next_q = 0;
+    __syncthreads();
+    const int info = ldc(t.tile_info, wt / WPT);
+    const int valid = min(max((info >> 8) - (int)(wt % WPT) * TS, 0), TS);
+    uint64_t vm[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) vm[s] = ballot(lane * S + s < valid);
+    int dummy[S];
+    for (;;) {
+      const int q = next_item(next_q);
+      if (q >= t.Q) break;
+      const int4 set = ldc(t.sets, t.q0 + q);
+      int acc;
+      if constexpr (S == 4) {
+        acc = eval_set_s4_count(lds_lane, lane, set, t.conds, vm);
+      } else {
+        acc = eval_set<S, false>(xs, lane, set, t.conds, vm, dummy);
+      }
+      if (lane < t.nc) cnt[q * t.nc + lane] += acc;
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < t.Q * t.nc; i += blockDim.x) {
+    const int v = cnt[i];
+    if (v == 0) continue;
+    const int q = i / t.nc, c = i - q * t.nc;
+    const int64_t p = t.q0 + q;
+    if (t.confusion) atomicAdd(&t.confusion[(p * t.nc + t.label) * t.nc + c], v);
+    if (c == t.label) atomicAdd(&t.correct[p], v);
+  }
+  __syncthreads();
+}
+
+}  // namespace aerl

@@ -5,6 +5,8 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <unordered_map>
@@ -85,6 +87,12 @@ struct PopRec {
   hipEvent_t staged = nullptr; // completion of the staging copy
 };
 
+struct BatchPlanRec;
+void destroy_plan(BatchPlanRec *p);
+struct PlanDeleter {
+  void operator()(BatchPlanRec *p) const { destroy_plan(p); }
+};
+
 }  // namespace aerl
 
 struct aerl_ctx {
@@ -95,6 +103,9 @@ struct aerl_ctx {
   int32_t next_id = 1;
   std::unordered_map<int32_t, aerl::DatasetRec> datasets;
   std::unordered_map<int32_t, aerl::PopRec> pops;
+  std::unordered_map<int32_t, std::unique_ptr<aerl::BatchPlanRec, aerl::PlanDeleter>> plans;
+  std::map<std::string, std::pair<int32_t, int32_t>> tuned;  // batch shape -> (sets, tiles) per task
+  bool tune_file_loaded = false;
   struct Serve *serve = nullptr;
 };
 
@@ -130,6 +141,12 @@ hipError_t launch_scatter_transpose(const float *x, const int32_t *y, int64_t n,
 hipError_t launch_tau(const float *x_fm, const int32_t *y_pad, int64_t n_pad, int32_t nf,
                       int64_t n, float *tau, hipStream_t s);
 constexpr int kUploadBlock = 256;  // samples per block in the upload kernels
+
+// LDS of one CU, and the most dynamic LDS a hard-eval block may ask for (the
+// rest is left for the kernels' own __shared__ words).
+constexpr size_t kLdsPerCu = 160 * 1024;
+constexpr size_t kStaticLds = 64;
+constexpr size_t kDynLdsMax = kLdsPerCu - kStaticLds;
 
 // Soft path (soft.hip)
 struct SoftLaunch {

@@ -1,0 +1,79 @@
+// Ragged batches: many (dataset, population) evaluations in one persistent
+// launch.  The host builds a work list (batch.cpp); every workgroup of the
+// persistent grid pulls work items from a device counter until the list is
+// exhausted, and runs the same block body as the one-launch-per-population
+// kernel, so the results are bit-identical to it.  Each work item fixes its
+// own tile width (samples per lane), so items of different feature counts
+// share the launch.
+#include "batch.h"
+#include "hard_block.h"
+
+namespace aerl {
+
+namespace {
+
+constexpr int kBatchBlock = 1024;
+
+__global__ void k_batch_zero(const BatchZero *__restrict__ z, int32_t n_z, int32_t *__restrict__ counter) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *counter = 0;
+  for (int e = blockIdx.x; e < n_z; e += gridDim.x) {
+    int32_t *p = z[e].p;
+    const int64_t n = z[e].n;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+  }
+}
+
+__global__ __launch_bounds__(kBatchBlock) void k_hard_batch(const BatchItem *__restrict__ items,
+                                                            const BatchTask *__restrict__ tasks,
+                                                            int32_t n_tasks,
+                                                            int32_t *__restrict__ counter) {
+  extern __shared__ __align__(16) float smem[];
+  __shared__ int32_t next_q;
+  __shared__ int32_t task_id;
+  for (;;) {
+    if (threadIdx.x == 0) task_id = atomicAdd(counter, 1);
+    __syncthreads();
+    const int ti = __builtin_amdgcn_readfirstlane(task_id);
+    if (ti >= n_tasks) break;  // same value in every thread: the whole block leaves
+    const BatchTask tk = tasks[ti];
+    const BatchItem it = items[tk.item];
+    HardTask t;
+    t.x_fm = it.x_fm;
+    t.n_pad = it.n_pad;
+    t.nf = it.nf;
+    t.nc = it.nc;
+    t.tile_info = it.tile_info;
+    t.sets = it.sets;
+    t.conds = it.conds;
+    t.correct = it.correct;
+    t.confusion = it.confusion;
+    t.q0 = tk.q0;
+    t.Q = tk.Q;
+    t.tile_lo = tk.tile_lo;
+    t.tile_hi = tk.tile_hi;
+    t.label = tk.label;
+    switch (it.S) {
+      case 4: hard_block<4>(t, smem, &next_q); break;
+      case 2: hard_block<2>(t, smem, &next_q); break;
+      default: hard_block<1>(t, smem, &next_q); break;
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_batch(const BatchLaunch &b, hipStream_t st) {
+  if (b.n_zero > 0) {
+    hipLaunchKernelGGL(k_batch_zero, dim3((unsigned)std::min<int64_t>(b.n_zero, 1024)), dim3(256), 0,
+                       st, b.zero, b.n_zero, b.counter);
+  } else {
+    hipLaunchKernelGGL(k_batch_zero, dim3(1), dim3(64), 0, st, b.zero, 0, b.counter);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || b.n_tasks == 0) return e;
+  hipLaunchKernelGGL(k_hard_batch, dim3((unsigned)b.grid), dim3(kBatchBlock), b.lds, st, b.items,
+                     b.tasks, b.n_tasks, b.counter);
+  return hipGetLastError();
+}
+
+}  // namespace aerl

@@ -414,7 +414,7 @@ SoftPlan plan_backward(const DatasetRec &ds, const PopRec &pop) {
   const size_t per_wave = (size_t)std::max(pop.max_rules, 1) * 128 * 4;
   const size_t per_set = (size_t)std::max(pop.max_set_conds, 1) * 2 * 4;
   p.Q = std::max(1, std::min(pop.n_sets, 16));
-  while (p.Q > 1 && xs + p.Q * per_set + kBwdWaves * per_wave > 160 * 1024) p.Q >>= 1;
+  while (p.Q > 1 && xs + p.Q * per_set + kBwdWaves * per_wave > kDynLdsMax) p.Q >>= 1;
   p.TG = 1;
   while (count_groups(ds, p.TG) > kMaxGroups) p.TG *= 2;
   p.n_groups = (int)count_groups(ds, p.TG);
@@ -489,7 +489,7 @@ hipError_t launch_soft_backward(const SoftLaunch &l, hipStream_t st) {
   const PopRec &pop = *l.pop;
   if (pop.n_sets == 0) return hipSuccess;
   const SoftPlan p = plan_backward(*l.ds, pop);
-  if (p.lds > 160 * 1024) return hipErrorInvalidValue;
+  if (p.lds > kDynLdsMax) return hipErrorInvalidValue;
   SoftArgs a;
   fill_args(a, l, p);
   a.part_grad = static_cast<float *>(l.ws);
