@@ -142,6 +142,56 @@ def bench_soft(ctx, steps, warmup, cpu):
     return out
 
 
+def bench_ragged(ctx, steps, warmup):
+    """64 independent runs (C3 shape) evaluated one launch per population, and
+    as one graph-captured persistent launch with the autotuned work split."""
+    import torch
+    from paper_2406_01821_amd import synth
+    t0 = time.time()
+    runs = synth.ragged_runs()
+    log(f"generated 64 ragged runs in {time.time() - t0:.1f}s")
+    devs = [(ctx.upload_dataset(w.data),
+             ctx.pack_population(w.pop, w.data.n_features, w.data.n_classes)) for w in runs]
+    nominal = sum(int(w.pop.nominal_conds_per_set().sum()) * w.data.n for w in runs)
+    outs = [ctx.eval_population(ds, p) for ds, p in devs]
+    stream = torch.cuda.current_stream()
+
+    def plain():
+        for (ds, p), o in zip(devs, outs):
+            ctx.eval_population(ds, p, out=o)
+
+    plain_ms, plain_wall = timed(plain, steps, warmup, stream)
+    items = []
+    for ds, p in devs:
+        c, m = ctx.batch_outputs(ds, p)
+        items.append((ds, p, c, m))
+    ws = ctx.batch_workspace(items, (1, 1))
+    (q, tg), tune_ms = ctx.autotune(items, ws)
+    plan = ctx.batch_plan(items, ws, graph=True)
+    batch_ms, batch_wall = timed(plan.run, steps, warmup, stream)
+    torch.cuda.synchronize()
+    exact = all(torch.equal(c, o[0]) and torch.equal(m, o[1])
+                for (_, _, c, m), o in zip(items, outs))
+    log(f"ragged: plain {plain_wall:.3f} ms, batched {batch_wall:.3f} ms "
+        f"(tuned split {q} sets x {tg} tiles), identical={exact}")
+    plan.release()
+    for ds, p in devs:
+        ctx.release_population(p)
+        ctx.release_dataset(ds)
+    return {
+        "workload": "64 independent runs: 1k-200k samples (log-uniform) x 16-128 fp32 features, "
+                    "2-4 classes, 16-1024 rule sets of 1-64 rules x 1-8 conditions",
+        "nominal_cond_evals": nominal,
+        "plain": {"ms": plain_wall, "gpu_ms": plain_ms,
+                  "cond_evals_per_s": nominal / (plain_wall * 1e-3)},
+        "batched": {"ms": batch_wall, "gpu_ms": batch_ms,
+                    "cond_evals_per_s": nominal / (batch_wall * 1e-3),
+                    "sets_per_task": q, "tiles_per_task": tg, "graph": True},
+        "speedup_vs_plain": plain_wall / batch_wall,
+        "bit_identical_to_plain": exact,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -149,6 +199,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--only-hard", action="store_true", help="time the hard path only")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run only a plain 256 MiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -158,6 +210,17 @@ def main():
     import torch
     from paper_2406_01821_amd import synth
     from paper_2406_01821_amd.aerl import Context
+
+    if args.copy_probe:
+        nbytes = 256 << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": nbytes, "copy_probe_bytes_written": nbytes,
+                          "launches": 3}), flush=True)
+        return
 
     t0 = time.time()
     w = synth.scaled_hard(1)
@@ -201,6 +264,7 @@ def main():
     del w
     if not args.only_hard:
         result["soft"] = bench_soft(ctx, max(3, args.steps // 4), 1, not args.no_cpu)
+        result["ragged"] = bench_ragged(ctx, max(3, args.steps // 4), 1)
     print(json.dumps(result), flush=True)
     ctx.close()
 

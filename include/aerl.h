@@ -129,7 +129,8 @@ typedef struct {
 aerl_status aerl_dataset_query(aerl_ctx *ctx, int32_t dataset_id, aerl_dataset_info *info);
 
 /* Forget a dataset.  The caller may free its `mem` once every stream that
- * used it has finished.  Errors: AERL_ENOENT. */
+ * used it has finished.  Errors: AERL_ENOENT, AERL_ESTATE (served requests
+ * on it are still in flight). */
 aerl_status aerl_release_dataset(aerl_ctx *ctx, int32_t dataset_id);
 
 /* ------------------------------------------------------------ population */
@@ -292,6 +293,84 @@ aerl_status aerl_batch_release(aerl_ctx *ctx, int32_t plan_id);
 aerl_status aerl_autotune(aerl_ctx *ctx, const aerl_batch_item *items, int32_t n_items, void *ws,
                           size_t ws_bytes, hipStream_t stream, aerl_batch_cfg *best,
                           float *best_ms);
+
+/* -------------------------------------------------------------- serving */
+
+/* A request loop over resident datasets: evolution workers (Section 3: the
+ * CPU side evolves candidates and hands them to the GPU for scoring) submit
+ * fitness and prediction requests of any size from any thread; the loop
+ * admits them in arrival order as long as their device footprint fits in
+ * the caller's arena (the HBM budget), packs every request admitted while
+ * earlier launches are still running into the next launch (one persistent
+ * fitness kernel plus one prediction kernel, on one of several streams, so
+ * launches overlap), and hands results back per request.  Results are
+ * bit-identical to aerl_eval_population / aerl_predict of the same request
+ * alone. */
+enum { AERL_REQ_FITNESS = 0, AERL_REQ_PREDICT = 1 };
+
+typedef struct {
+  int32_t max_batch;    /* most requests per launch; 0 = 256 */
+  int32_t max_inflight; /* launches that may be on the device at once, 1..8; 0 = 4 */
+} aerl_serve_cfg;
+
+typedef struct {
+  int32_t kind;                /* AERL_REQ_FITNESS or AERL_REQ_PREDICT */
+  int32_t dataset_id;          /* fitness: a resident dataset (its shape must match) */
+  const aerl_population *pop;  /* host; copied and packed during submit */
+  int32_t n_features, n_classes;
+  int32_t set_index;           /* predict: the rule set of pop to apply */
+  const float *rows;           /* predict: host fp32 [n_rows][n_features], copied during submit */
+  int64_t n_rows;
+  int32_t *correct;            /* fitness: host int32 [n_sets] */
+  int32_t *confusion;          /* fitness: host int32 [n_sets][C][C] or NULL */
+  int32_t *pred;               /* predict: host int32 [n_rows] */
+} aerl_request;
+
+typedef struct {
+  aerl_status status;  /* AERL_OK, or the device error that ended the launch */
+  int32_t batch_size;  /* requests in the launch that carried this one */
+  double queue_us;     /* submit -> launch */
+  double latency_us;   /* submit -> outputs written to the caller's buffers */
+} aerl_result;
+
+struct aerl_serve_stats {
+  int64_t submitted, completed, launches;
+  double p50_us, p99_us, mean_us, max_us; /* latency of completed requests */
+  double requests_per_s;   /* completed / (last completion - first submit) */
+  double cond_evals_per_s; /* nominal condition evaluations over the same span */
+  double mean_batch;       /* requests per launch */
+  size_t arena_peak;       /* most arena bytes in use at once */
+};
+
+/* Start the loop on ctx's device.  arena: caller-allocated device memory
+ * (256-byte aligned) whose size is the admission budget; it must outlive
+ * aerl_serve_stop.  cfg may be NULL.  Errors: AERL_ESTATE (already
+ * running), AERL_EINVAL, AERL_EDEVICE. */
+aerl_status aerl_serve_start(aerl_ctx *ctx, void *arena, size_t arena_bytes,
+                             const aerl_serve_cfg *cfg);
+
+/* Submit one request; returns at once with *ticket.  Inputs are copied, so
+ * the caller may reuse them; output buffers must stay valid until the
+ * ticket completes.  Errors: AERL_ESTATE (not running), AERL_ENOENT (unknown
+ * dataset), AERL_EINVAL (invalid population, shape mismatch, bad set_index,
+ * NULL outputs), AERL_ENOMEM (the request alone exceeds the arena). */
+aerl_status aerl_serve_submit(aerl_ctx *ctx, const aerl_request *req, uint64_t *ticket);
+
+/* Wait for a ticket (timeout_us < 0: no limit) and collect it: its outputs
+ * are in the caller's buffers and *res (may be NULL) tells how it went.  A
+ * collected ticket is forgotten.  Errors: AERL_ENOENT (unknown or already
+ * collected), AERL_ETIMEDOUT (not done yet; the ticket stays). */
+aerl_status aerl_serve_wait(aerl_ctx *ctx, uint64_t ticket, int64_t timeout_us, aerl_result *res);
+
+/* Latency and throughput since start (or the last reset).  reset != 0
+ * clears the counters after reading them.  Errors: AERL_ESTATE. */
+aerl_status aerl_serve_stats(aerl_ctx *ctx, struct aerl_serve_stats *out, int32_t reset);
+
+/* Finish every accepted request (outputs written), then stop the loop and
+ * free its streams and host buffers.  Completed tickets stay collectable by
+ * aerl_serve_wait until the next aerl_serve_start or aerl_destroy, which
+ * must not race with a waiting thread.  Errors: AERL_ESTATE (not running). */
+aerl_status aerl_serve_stop(aerl_ctx *ctx);
 
 /* ------------------------------------------------------------------ soft */
 

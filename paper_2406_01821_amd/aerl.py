@@ -60,6 +60,32 @@ class aerl_batch_cfg(C.Structure):
 
 
 AERL_BATCH_GRAPH = 1
+AERL_REQ_FITNESS, AERL_REQ_PREDICT = 0, 1
+
+
+class aerl_serve_cfg(C.Structure):
+    _fields_ = [("max_batch", C.c_int32), ("max_inflight", C.c_int32)]
+
+
+class aerl_request(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("dataset_id", C.c_int32),
+                ("pop", C.POINTER(aerl_population)), ("n_features", C.c_int32),
+                ("n_classes", C.c_int32), ("set_index", C.c_int32), ("rows", C.c_void_p),
+                ("n_rows", C.c_int64), ("correct", C.c_void_p), ("confusion", C.c_void_p),
+                ("pred", C.c_void_p)]
+
+
+class aerl_result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("batch_size", C.c_int32), ("queue_us", C.c_double),
+                ("latency_us", C.c_double)]
+
+
+class aerl_serve_stats_t(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("launches", C.c_int64),
+                ("p50_us", C.c_double), ("p99_us", C.c_double), ("mean_us", C.c_double),
+                ("max_us", C.c_double), ("requests_per_s", C.c_double),
+                ("cond_evals_per_s", C.c_double), ("mean_batch", C.c_double),
+                ("arena_peak", C.c_size_t)]
 
 
 if not os.path.exists(LIB_PATH):
@@ -92,6 +118,11 @@ _SIGS = {
     "aerl_batch_release": ([_P, _I32], _I32),
     "aerl_autotune": ([_P, C.POINTER(aerl_batch_item), _I32, _P, _SZ, _P,
                        C.POINTER(aerl_batch_cfg), C.POINTER(C.c_float)], _I32),
+    "aerl_serve_start": ([_P, _P, _SZ, C.POINTER(aerl_serve_cfg)], _I32),
+    "aerl_serve_submit": ([_P, C.POINTER(aerl_request), C.POINTER(C.c_uint64)], _I32),
+    "aerl_serve_wait": ([_P, C.c_uint64, _I64, C.POINTER(aerl_result)], _I32),
+    "aerl_serve_stats": ([_P, C.POINTER(aerl_serve_stats_t), _I32], _I32),
+    "aerl_serve_stop": ([_P], _I32),
     "aerl_soft_workspace_bytes": ([_P, _I32, _I32, C.POINTER(_SZ), C.POINTER(_SZ)], _I32),
     "aerl_soft_forward": ([_P, _I32, _I32, _P, _P, _P, _P, _P, _SZ, _P], _I32),
     "aerl_soft_backward": ([_P, _I32, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _SZ, _P], _I32),
@@ -321,6 +352,45 @@ class Context:
                                  C.byref(best), C.byref(ms)))
         return (best.sets_per_task, best.tiles_per_task), ms.value
 
+    # -------------------------------------------------------------- serving
+    def serve_start(self, arena_bytes: int, max_batch: int = 0, max_inflight: int = 0):
+        """Starts the serving loop with a torch-allocated arena of arena_bytes."""
+        arena = torch.empty(arena_bytes, dtype=torch.uint8, device=self.device)
+        cfg = aerl_serve_cfg(max_batch, max_inflight)
+        torch.cuda.synchronize()
+        self.check(aerl_serve_start(self.h, _ptr(arena), arena_bytes, C.byref(cfg)))
+        self.arena = arena  # kept alive while the loop runs
+
+    def serve_submit_fitness(self, ds: DeviceDataset, pop: Population, confusion: bool = True):
+        """Returns a ServeTicket; its outputs are numpy arrays filled on completion."""
+        hp = _HostPop(pop)
+        correct = np.zeros(pop.n_sets, np.int32)
+        conf = np.zeros((pop.n_sets, ds.n_classes, ds.n_classes), np.int32) if confusion else None
+        req = aerl_request(AERL_REQ_FITNESS, ds.id, C.pointer(hp.s), ds.n_features, ds.n_classes,
+                           0, None, 0, _ptr(correct), _ptr(conf), None)
+        t = C.c_uint64()
+        self.check(aerl_serve_submit(self.h, C.byref(req), C.byref(t)))
+        return ServeTicket(self, t.value, dict(correct=correct, confusion=conf))
+
+    def serve_submit_predict(self, pop: Population, rows, n_features: int, n_classes: int,
+                             set_index: int = 0):
+        hp = _HostPop(pop)
+        rows = np.ascontiguousarray(rows, dtype=np.float32)
+        pred = np.zeros(rows.shape[0], np.int32)
+        req = aerl_request(AERL_REQ_PREDICT, -1, C.pointer(hp.s), n_features, n_classes,
+                           set_index, _ptr(rows), rows.shape[0], None, None, _ptr(pred))
+        t = C.c_uint64()
+        self.check(aerl_serve_submit(self.h, C.byref(req), C.byref(t)))
+        return ServeTicket(self, t.value, dict(pred=pred))
+
+    def serve_stats(self, reset: bool = False) -> dict:
+        st = aerl_serve_stats_t()
+        self.check(aerl_serve_stats(self.h, C.byref(st), 1 if reset else 0))
+        return {k: getattr(st, k) for k, _ in aerl_serve_stats_t._fields_}
+
+    def serve_stop(self):
+        self.check(aerl_serve_stop(self.h))
+
     # ------------------------------------------------------------ soft path
     def soft_workspace(self, ds: DeviceDataset, pop: DevicePopulation, backward: bool):
         fb, bb = C.c_size_t(), C.c_size_t()
@@ -342,6 +412,24 @@ class Context:
                                       _ptr(dloss), _ptr(g[0]), _ptr(g[1]), _ptr(g[2]), _ptr(ws),
                                       ws.numel(), _stream(stream)))
         return tuple(g)
+
+
+class ServeTicket:
+    """A submitted serving request; ``wait()`` returns its outputs."""
+
+    def __init__(self, ctx: Context, ticket: int, out: dict):
+        self.ctx, self.ticket, self.out = ctx, ticket, out
+        self.result = None
+
+    def wait(self, timeout_us: int = -1) -> dict:
+        if self.result is None:
+            r = aerl_result()
+            self.ctx.check(aerl_serve_wait(self.ctx.h, self.ticket, timeout_us, C.byref(r)))
+            self.result = dict(status=r.status, batch_size=r.batch_size, queue_us=r.queue_us,
+                               latency_us=r.latency_us)
+            if r.status != AERL_OK:
+                raise AerlError(r.status, f"served request {self.ticket} failed")
+        return self.out
 
 
 class BatchPlan:

@@ -36,18 +36,111 @@ void destroy_plan(BatchPlanRec *p) {
   delete p;
 }
 
-namespace {
-
-constexpr size_t kBatchLdsMax = kDynLdsMax;
-constexpr size_t kTileBudget = 64 * 1024;  // feature tile of one block, so two fit a CU
-
-size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
-
-int samples_per_lane(int32_t nf) {
+int batch_samples_per_lane(int32_t nf) {
   int s = 4;
-  while (s > 1 && (size_t)nf * 256 * s > kTileBudget) s >>= 1;
+  while (s > 1 && (size_t)nf * 256 * s > 64 * 1024) s >>= 1;
   return s;
 }
+
+namespace {
+size_t align256_(size_t v) { return (v + 255) & ~size_t(255); }
+}  // namespace
+
+namespace {
+int32_t sets_per_item(const DatasetRec &ds, int32_t n_sets, int32_t Q) {
+  const size_t tile_bytes = (size_t)ds.nf * 64 * batch_samples_per_lane(ds.nf) * 4;
+  const int32_t q_fit =
+      (int32_t)std::min<size_t>((kBatchLdsMax - tile_bytes) / ((size_t)ds.nc * 4), 1 << 20);
+  return std::max(1, std::min({Q, n_sets, q_fit}));
+}
+}  // namespace
+
+int64_t batch_task_count(const DatasetRec &ds, int32_t n_sets, int32_t Q, int32_t TG) {
+  if (n_sets <= 0) return 0;
+  const int32_t q = sets_per_item(ds, n_sets, Q);
+  int64_t groups = 0;
+  for (int c = 0; c < ds.nc; ++c) groups += (ds.region_tiles[c] + TG - 1) / TG;
+  return (int64_t)((n_sets + q - 1) / q) * groups;
+}
+
+void build_batch_tables(const std::vector<BatchSource> &src, int32_t Q, int32_t TG, BatchTables *b) {
+  b->items.clear();
+  b->tasks.clear();
+  b->zero.clear();
+  b->lds = 0;
+  std::vector<std::pair<double, BatchTask>> costed;
+  for (size_t i = 0; i < src.size(); ++i) {
+    const DatasetRec &ds = *src[i].ds;
+    const int32_t n_sets = src[i].n_sets;
+    const int S = batch_samples_per_lane(ds.nf);
+    BatchItem it{};
+    it.x_fm = ds.x_fm;
+    it.n_pad = ds.n_pad;
+    it.tile_info = ds.tile_info;
+    it.sets = src[i].sets;
+    it.conds = src[i].conds;
+    it.correct = src[i].correct;
+    it.confusion = src[i].confusion;
+    it.nf = ds.nf;
+    it.nc = ds.nc;
+    it.S = S;
+    b->items.push_back(it);
+    if (n_sets <= 0) continue;
+    b->zero.push_back({it.correct, n_sets});
+    if (it.confusion) b->zero.push_back({it.confusion, (int64_t)n_sets * ds.nc * ds.nc});
+    const size_t tile_bytes = (size_t)ds.nf * 64 * S * 4;
+    const int32_t q = sets_per_item(ds, n_sets, Q);
+    b->lds = std::max(b->lds, tile_bytes + (size_t)q * ds.nc * 4);
+    const int4 *hs = src[i].host_sets;
+    for (int32_t q0 = 0; q0 < n_sets; q0 += q) {
+      const int32_t qe = std::min(q, n_sets - q0);
+      double work = 0;
+      for (int32_t k = q0; k < q0 + qe; ++k) work += (double)hs[k].w + 1.0;
+      for (int c = 0; c < ds.nc; ++c) {
+        for (int32_t t0 = 0; t0 < ds.region_tiles[c]; t0 += TG) {
+          BatchTask tk{};
+          tk.item = (int32_t)i;
+          tk.q0 = q0;
+          tk.Q = qe;
+          tk.tile_lo = ds.region_tile0[c] + t0;
+          tk.tile_hi = ds.region_tile0[c] + std::min(t0 + TG, ds.region_tiles[c]);
+          tk.label = c;
+          costed.push_back({work * (double)(tk.tile_hi - tk.tile_lo), tk});
+        }
+      }
+    }
+  }
+  std::stable_sort(costed.begin(), costed.end(),
+                   [](const auto &x, const auto &y) { return x.first > y.first; });
+  for (auto &c : costed) b->tasks.push_back(c.second);
+  size_t off = 0;
+  b->items_off = off;   off = align256_(off + sizeof(BatchItem) * std::max<size_t>(b->items.size(), 1));
+  b->tasks_off = off;   off = align256_(off + sizeof(BatchTask) * std::max<size_t>(b->tasks.size(), 1));
+  b->zero_off = off;    off = align256_(off + sizeof(BatchZero) * std::max<size_t>(b->zero.size(), 1));
+  b->counter_off = off; off = align256_(off + sizeof(int32_t));
+  b->bytes = off;
+}
+
+void emit_batch_tables(const BatchTables &b, void *img, char *dev, int n_cu, BatchLaunch *bl) {
+  char *h = static_cast<char *>(img);
+  std::memset(h, 0, b.bytes);
+  std::memcpy(h + b.items_off, b.items.data(), sizeof(BatchItem) * b.items.size());
+  std::memcpy(h + b.tasks_off, b.tasks.data(), sizeof(BatchTask) * b.tasks.size());
+  std::memcpy(h + b.zero_off, b.zero.data(), sizeof(BatchZero) * b.zero.size());
+  bl->items = reinterpret_cast<const BatchItem *>(dev + b.items_off);
+  bl->tasks = reinterpret_cast<const BatchTask *>(dev + b.tasks_off);
+  bl->zero = reinterpret_cast<const BatchZero *>(dev + b.zero_off);
+  bl->counter = reinterpret_cast<int32_t *>(dev + b.counter_off);
+  bl->n_tasks = (int32_t)b.tasks.size();
+  bl->n_zero = (int32_t)b.zero.size();
+  bl->lds = b.lds;
+  const int per_cu = 2 * (b.lds + kStaticLds) <= kLdsPerCu ? 2 : 1;
+  bl->grid = std::max<int64_t>(1, std::min<int64_t>((int64_t)n_cu * per_cu, (int64_t)b.tasks.size()));
+}
+
+int predict_samples_per_lane(int32_t nf) { return (size_t)nf * 256 * 4 <= kDynLdsMax ? 4 : 1; }
+
+namespace {
 
 struct ItemView {
   const DatasetRec *ds;
@@ -74,86 +167,14 @@ aerl_status gather(aerl_ctx *ctx, const aerl_batch_item *items, int32_t n, std::
   return AERL_OK;
 }
 
-// Per-set nominal condition counts, read from the population's host staging
-// copy of its packed image (set records carry them in .w).
-const int4 *host_sets(const PopRec &p) {
-  return static_cast<const int4 *>(p.staging);  // sets are the first region of the image
-}
-
-struct Built {
-  std::vector<BatchItem> items;
-  std::vector<BatchTask> tasks;
-  std::vector<BatchZero> zero;
-  size_t lds = 0;
-};
-
-void build(const std::vector<ItemView> &v, int32_t Q, int32_t TG, Built *b) {
-  b->items.clear();
-  b->tasks.clear();
-  b->zero.clear();
-  b->lds = 0;
-  std::vector<std::pair<double, BatchTask>> costed;
-  for (size_t i = 0; i < v.size(); ++i) {
-    const DatasetRec &ds = *v[i].ds;
-    const PopRec &pop = *v[i].pop;
-    const int S = samples_per_lane(ds.nf);
-    BatchItem it{};
-    it.x_fm = ds.x_fm;
-    it.n_pad = ds.n_pad;
-    it.tile_info = ds.tile_info;
-    it.sets = pop.sets;
-    it.conds = pop.hconds;
-    it.correct = v[i].item->correct;
-    it.confusion = v[i].item->confusion;
-    it.nf = ds.nf;
-    it.nc = ds.nc;
-    it.S = S;
-    b->items.push_back(it);
-    if (pop.n_sets > 0) {
-      b->zero.push_back({it.correct, pop.n_sets});
-      if (it.confusion) b->zero.push_back({it.confusion, (int64_t)pop.n_sets * ds.nc * ds.nc});
-    }
-    const size_t tile_bytes = (size_t)ds.nf * 64 * S * 4;
-    const int32_t q_fit = (int32_t)std::min<size_t>((kBatchLdsMax - tile_bytes) / (ds.nc * 4), 1 << 20);
-    const int32_t q = std::max(1, std::min({Q, pop.n_sets, q_fit}));
-    b->lds = std::max(b->lds, (size_t)ds.nf * 64 * S * 4 + (size_t)q * ds.nc * 4);
-    const int4 *hs = host_sets(pop);
-    for (int32_t q0 = 0; q0 < pop.n_sets; q0 += q) {
-      const int32_t qe = std::min(q, pop.n_sets - q0);
-      double work = 0;
-      for (int32_t k = q0; k < q0 + qe; ++k) work += (double)hs[k].w + 1.0;
-      for (int c = 0; c < ds.nc; ++c) {
-        for (int32_t t0 = 0; t0 < ds.region_tiles[c]; t0 += TG) {
-          BatchTask tk{};
-          tk.item = (int32_t)i;
-          tk.q0 = q0;
-          tk.Q = qe;
-          tk.tile_lo = ds.region_tile0[c] + t0;
-          tk.tile_hi = ds.region_tile0[c] + std::min(t0 + TG, ds.region_tiles[c]);
-          tk.label = c;
-          costed.push_back({work * (double)(tk.tile_hi - tk.tile_lo), tk});
-        }
-      }
-    }
+std::vector<BatchSource> sources(const std::vector<ItemView> &v) {
+  std::vector<BatchSource> src;
+  for (const auto &it : v) {
+    // The set records lead the population's host staging copy of its image.
+    src.push_back({it.ds, it.pop->n_sets, static_cast<const int4 *>(it.pop->staging),
+                   it.pop->sets, it.pop->hconds, it.item->correct, it.item->confusion});
   }
-  std::stable_sort(costed.begin(), costed.end(),
-                   [](const auto &x, const auto &y) { return x.first > y.first; });
-  for (auto &c : costed) b->tasks.push_back(c.second);
-}
-
-struct WsLayout {
-  size_t items_off, tasks_off, zero_off, counter_off, total;
-};
-
-WsLayout ws_layout(const Built &b) {
-  WsLayout L{};
-  size_t off = 0;
-  L.items_off = off;   off = align256(off + sizeof(BatchItem) * std::max<size_t>(b.items.size(), 1));
-  L.tasks_off = off;   off = align256(off + sizeof(BatchTask) * std::max<size_t>(b.tasks.size(), 1));
-  L.zero_off = off;    off = align256(off + sizeof(BatchZero) * std::max<size_t>(b.zero.size(), 1));
-  L.counter_off = off; off = align256(off + sizeof(int32_t));
-  L.total = off;
-  return L;
+  return src;
 }
 
 int log2_bucket(double v) { return v <= 1 ? 0 : (int)std::ceil(std::log2(v)); }
@@ -197,34 +218,18 @@ void default_cfg(aerl_ctx *ctx, const std::vector<ItemView> &v, const aerl_batch
   if (*TG <= 0) *TG = tg;
 }
 
-aerl_status upload_plan(aerl_ctx *ctx, const Built &b, void *ws, size_t ws_bytes, hipStream_t st,
+aerl_status upload_plan(aerl_ctx *ctx, const BatchTables &b, void *ws, size_t ws_bytes, hipStream_t st,
                         BatchPlanRec *plan) {
-  const WsLayout L = ws_layout(b);
   if (!ws || ((uintptr_t)ws & 255)) return fail(ctx, AERL_EINVAL, "ws is NULL or not 256-byte aligned");
-  if (ws_bytes < L.total) return fail(ctx, AERL_ENOMEM, "ws holds %zu bytes, %zu needed", ws_bytes, L.total);
+  if (ws_bytes < b.bytes) return fail(ctx, AERL_ENOMEM, "ws holds %zu bytes, %zu needed", ws_bytes, b.bytes);
   if (b.lds > kBatchLdsMax) return fail(ctx, AERL_EINVAL, "work split needs %zu bytes of LDS", b.lds);
-  std::vector<char> img(L.total, 0);
-  std::memcpy(img.data() + L.items_off, b.items.data(), sizeof(BatchItem) * b.items.size());
-  std::memcpy(img.data() + L.tasks_off, b.tasks.data(), sizeof(BatchTask) * b.tasks.size());
-  std::memcpy(img.data() + L.zero_off, b.zero.data(), sizeof(BatchZero) * b.zero.size());
   void *pinned = nullptr;
-  AERL_HIP(ctx, hipHostMalloc(&pinned, L.total, hipHostMallocDefault));
-  std::memcpy(pinned, img.data(), L.total);
-  hipError_t e = hipMemcpyAsync(ws, pinned, L.total, hipMemcpyHostToDevice, st);
+  AERL_HIP(ctx, hipHostMalloc(&pinned, b.bytes, hipHostMallocDefault));
+  emit_batch_tables(b, pinned, static_cast<char *>(ws), ctx->n_cu, &plan->launch);
+  hipError_t e = hipMemcpyAsync(ws, pinned, b.bytes, hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   (void)hipHostFree(pinned);
   if (e != hipSuccess) return fail(ctx, AERL_EDEVICE, "plan upload failed: %s", hipGetErrorString(e));
-  char *base = static_cast<char *>(ws);
-  BatchLaunch &bl = plan->launch;
-  bl.items = reinterpret_cast<const BatchItem *>(base + L.items_off);
-  bl.tasks = reinterpret_cast<const BatchTask *>(base + L.tasks_off);
-  bl.zero = reinterpret_cast<const BatchZero *>(base + L.zero_off);
-  bl.counter = reinterpret_cast<int32_t *>(base + L.counter_off);
-  bl.n_tasks = (int32_t)b.tasks.size();
-  bl.n_zero = (int32_t)b.zero.size();
-  bl.lds = b.lds;
-  const int per_cu = 2 * (b.lds + kStaticLds) <= kLdsPerCu ? 2 : 1;
-  bl.grid = (int64_t)ctx->n_cu * per_cu;
   plan->ws = ws;
   return AERL_OK;
 }
@@ -245,9 +250,9 @@ aerl_status aerl_batch_workspace_bytes(aerl_ctx *ctx, const aerl_batch_item *ite
   if (st) return st;
   int32_t Q, TG;
   default_cfg(ctx, v, cfg, &Q, &TG);
-  Built b;
-  build(v, Q, TG, &b);
-  *bytes = ws_layout(b).total;
+  BatchTables b;
+  build_batch_tables(sources(v), Q, TG, &b);
+  *bytes = b.bytes;
   return AERL_OK;
 }
 
@@ -265,8 +270,8 @@ aerl_status aerl_batch_plan(aerl_ctx *ctx, const aerl_batch_item *items, int32_t
   default_cfg(ctx, v, cfg, &Q, &TG);
   if (Q < 1 || TG < 1) return fail(ctx, AERL_EINVAL, "work split must be >= 1");
   AERL_HIP(ctx, hipSetDevice(ctx->device));
-  Built b;
-  build(v, Q, TG, &b);
+  BatchTables b;
+  build_batch_tables(sources(v), Q, TG, &b);
   std::unique_ptr<BatchPlanRec, PlanDeleter> plan(new BatchPlanRec());
   st = upload_plan(ctx, b, ws, ws_bytes, stream, plan.get());
   if (st) return st;
@@ -344,8 +349,8 @@ aerl_status aerl_autotune(aerl_ctx *ctx, const aerl_batch_item *items, int32_t n
   int32_t bq = 64, btg = 4;
   for (int32_t q : kQ) {
     for (int32_t tg : kTG) {
-      Built b;
-      build(v, q, tg, &b);
+      BatchTables b;
+      build_batch_tables(sources(v), q, tg, &b);
       if (b.lds > kBatchLdsMax) continue;
       BatchPlanRec tmp;
       if (upload_plan(ctx, b, ws, ws_bytes, stream, &tmp) != AERL_OK) continue;

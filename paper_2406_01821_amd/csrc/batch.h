@@ -37,4 +37,61 @@ struct BatchLaunch {
 
 hipError_t launch_batch(const BatchLaunch &b, hipStream_t st);
 
+constexpr size_t kBatchLdsMax = kDynLdsMax;
+
+// Samples per lane a batch item uses for a dataset of nf features (its
+// feature tile stays within 64 KiB, so two blocks fit a CU).
+int batch_samples_per_lane(int32_t nf);
+
+// One evaluation of a batch, as the table builder sees it.
+struct BatchSource {
+  const DatasetRec *ds;
+  int32_t n_sets;
+  const int4 *host_sets;  // host copy of the set records (cost estimates)
+  const int4 *sets;       // device set records
+  const uint4 *conds;     // device record stream
+  int32_t *correct;       // device [n_sets]
+  int32_t *confusion;     // device [n_sets][nc][nc] or null
+};
+
+// Work tables of a batch and their layout in one device copy.
+struct BatchTables {
+  std::vector<BatchItem> items;
+  std::vector<BatchTask> tasks;
+  std::vector<BatchZero> zero;
+  size_t lds = 0;
+  size_t items_off = 0, tasks_off = 0, zero_off = 0, counter_off = 0, bytes = 0;
+};
+
+// Cuts every source into work items of Q rule sets x TG tiles (Q lowered per
+// source until its block fits in LDS), sorts them by estimated cost
+// (samples x nominal conditions), largest first, and lays the tables out.
+void build_batch_tables(const std::vector<BatchSource> &src, int32_t Q, int32_t TG,
+                        BatchTables *t);
+
+// Number of work items build_batch_tables makes for one source.
+int64_t batch_task_count(const DatasetRec &ds, int32_t n_sets, int32_t Q, int32_t TG);
+
+// Writes the tables (t.bytes) to host memory `img` for a copy to device
+// address `dev` and fills the launch record (persistent grid sized for n_cu
+// CUs, never more blocks than work items).
+void emit_batch_tables(const BatchTables &t, void *img, char *dev, int n_cu, BatchLaunch *l);
+
+// Prediction work of a batch: one 64-thread block per task of 64*S rows.
+struct PredictTask {
+  const float *rows;  // device [n][nf] row-major
+  const int4 *set;    // device set record of the rule set to apply
+  const uint4 *conds; // device record stream of its population
+  int32_t *out;       // device [n]
+  int64_t n, row0;    // rows of the request, first row of this task
+  int32_t nf, S;
+};
+struct PredictLaunch {
+  const PredictTask *tasks;
+  int32_t n_tasks;
+  size_t lds;
+};
+hipError_t launch_predict_batch(const PredictLaunch &p, hipStream_t st);
+int predict_samples_per_lane(int32_t nf);  // 4, or 1 when a 256-row tile does not fit LDS
+
 }  // namespace aerl

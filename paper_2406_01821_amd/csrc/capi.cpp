@@ -20,12 +20,6 @@ aerl_status fail(aerl_ctx *ctx, aerl_status code, const char *fmt, ...) {
   return code;
 }
 
-PackedLayout packed_layout(int32_t n_sets, int32_t n_rules, int32_t n_conds);
-aerl_status validate_population(aerl_ctx *ctx, const aerl_population *p, int32_t nf, int32_t nc,
-                                int32_t *n_rules_out, int32_t *n_conds_out);
-void pack_population_image(const aerl_population *p, int32_t nf, int32_t nc, int32_t n_rules,
-                           int32_t n_conds, void *dst, PopRec *rec);
-
 namespace {
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
@@ -115,11 +109,9 @@ aerl_status aerl_create(aerl_ctx **out, int device_ordinal) {
   return AERL_OK;
 }
 
-void aerl_serve_shutdown_internal(aerl_ctx *ctx);
-
 void aerl_destroy(aerl_ctx *ctx) {
   if (!ctx) return;
-  aerl_serve_shutdown_internal(ctx);
+  serve_shutdown(ctx);
   for (auto &kv : ctx->pops) {
     if (kv.second.staged) {
       (void)hipEventSynchronize(kv.second.staged);
@@ -248,7 +240,10 @@ aerl_status aerl_dataset_query(aerl_ctx *ctx, int32_t dataset_id, aerl_dataset_i
 aerl_status aerl_release_dataset(aerl_ctx *ctx, int32_t dataset_id) {
   if (!ctx) return AERL_EINVAL;
   std::lock_guard<std::recursive_mutex> lk(ctx->mu);
-  if (!ctx->datasets.erase(dataset_id)) return fail(ctx, AERL_ENOENT, "unknown dataset %d", dataset_id);
+  if (!ctx->datasets.count(dataset_id)) return fail(ctx, AERL_ENOENT, "unknown dataset %d", dataset_id);
+  if (serve_uses_dataset(ctx, dataset_id))
+    return fail(ctx, AERL_ESTATE, "dataset %d has served requests in flight", dataset_id);
+  ctx->datasets.erase(dataset_id);
   return AERL_OK;
 }
 

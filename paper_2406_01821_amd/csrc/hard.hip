@@ -15,6 +15,7 @@
 // the result does not depend on the schedule.
 #include "eval_core.h"
 #include "hard_block.h"
+#include "predict_block.h"
 #include "internal.h"
 
 namespace aerl {
@@ -77,32 +78,10 @@ __global__ __launch_bounds__(kHardBlock) void k_hard(const HardArgs a) {
 template <int S>
 __global__ __launch_bounds__(64) void k_predict(const float *__restrict__ rows, int64_t n,
                                                 int32_t nf, const int4 *__restrict__ sets,
-                                                int32_t set_idx, const int4 *__restrict__ rules,
-                                                const uint4 *__restrict__ conds,
+                                                int32_t set_idx, const uint4 *__restrict__ conds,
                                                 int32_t *__restrict__ out) {
-  constexpr int TS = 64 * S;
-  extern __shared__ __align__(16) float xs[];  // [nf][TS]
-  const int lane = threadIdx.x;
-  const int4 set = ldc(sets, set_idx);
-  const int64_t base = (int64_t)blockIdx.x * TS;
-  const int64_t m = min((int64_t)TS, n - base);
-  const int64_t total = (int64_t)TS * nf;
-  for (int64_t i = lane; i < total; i += 64) {
-    const int64_t r = i / nf, f = i - r * nf;
-    xs[f * TS + r] = r < m ? rows[(base + r) * nf + f] : 0.0f;
-  }
-  __syncthreads();
-  uint64_t vm[S];
-  int pred[S];
-#pragma unroll
-  for (int s = 0; s < S; ++s) {
-    vm[s] = ballot(lane * S + s < m);
-    pred[s] = set.z;
-  }
-  eval_set<S, true>(xs, lane, set, conds, vm, pred);
-#pragma unroll
-  for (int s = 0; s < S; ++s)
-    if (lane * S + s < m) out[base + lane * S + s] = pred[s];
+  extern __shared__ __align__(16) float xs[];  // [nf][64*S]
+  predict_block<S>(rows, n, nf, ldc(sets, set_idx), conds, out, (int64_t)blockIdx.x * 64 * S, xs);
 }
 
 template <int S>
@@ -157,11 +136,11 @@ hipError_t launch_predict(const PopRec &pop, int32_t set, const float *rows, int
   if ((size_t)pop.nf * 256 * 4 <= kDynLdsMax) {
     const int64_t blocks = (n + 255) / 256;
     hipLaunchKernelGGL(k_predict<4>, dim3((unsigned)blocks), dim3(64), (size_t)pop.nf * 256 * 4,
-                       st, rows, n, pop.nf, pop.sets, set, pop.rules, pop.hconds, pred);
+                       st, rows, n, pop.nf, pop.sets, set, pop.hconds, pred);
   } else if ((size_t)pop.nf * 64 * 4 <= kDynLdsMax) {
     const int64_t blocks = (n + 63) / 64;
     hipLaunchKernelGGL(k_predict<1>, dim3((unsigned)blocks), dim3(64), (size_t)pop.nf * 64 * 4,
-                       st, rows, n, pop.nf, pop.sets, set, pop.rules, pop.hconds, pred);
+                       st, rows, n, pop.nf, pop.sets, set, pop.hconds, pred);
   } else {
     return hipErrorInvalidValue;
   }

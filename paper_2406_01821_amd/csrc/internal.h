@@ -16,6 +16,8 @@
 
 namespace aerl {
 
+struct Serve;
+
 // ------------------------------------------------------------ error helpers
 struct Error {
   aerl_status code;
@@ -87,6 +89,20 @@ struct PopRec {
   hipEvent_t staged = nullptr; // completion of the staging copy
 };
 
+PackedLayout packed_layout(int32_t n_sets, int32_t n_rules, int32_t n_conds);
+// Validates a host population; on success fills the rule and condition
+// counts.  AERL_EINVAL with the message in ctx (ctx may be null).
+aerl_status validate_population(aerl_ctx *ctx, const aerl_population *p, int32_t nf, int32_t nc,
+                                int32_t *n_rules_out, int32_t *n_conds_out);
+// Packed image of a validated population (PackedLayout::total bytes of host
+// memory at dst); fills the summary fields of rec.
+void pack_population_image(const aerl_population *p, int32_t nf, int32_t nc, int32_t n_rules,
+                           int32_t n_conds, void *dst, PopRec *rec);
+
+// Serving loop hooks (serve.cpp).
+void serve_shutdown(aerl_ctx *ctx);
+bool serve_uses_dataset(aerl_ctx *ctx, int32_t dataset_id);
+
 struct BatchPlanRec;
 void destroy_plan(BatchPlanRec *p);
 struct PlanDeleter {
@@ -106,7 +122,7 @@ struct aerl_ctx {
   std::unordered_map<int32_t, std::unique_ptr<aerl::BatchPlanRec, aerl::PlanDeleter>> plans;
   std::map<std::string, std::pair<int32_t, int32_t>> tuned;  // batch shape -> (sets, tiles) per task
   bool tune_file_loaded = false;
-  struct Serve *serve = nullptr;
+  aerl::Serve *serve = nullptr;
 };
 
 namespace aerl {

@@ -7,6 +7,7 @@
 // share the launch.
 #include "batch.h"
 #include "hard_block.h"
+#include "predict_block.h"
 
 namespace aerl {
 
@@ -60,7 +61,26 @@ __global__ __launch_bounds__(kBatchBlock) void k_hard_batch(const BatchItem *__r
   }
 }
 
+// Batched prediction: block b runs task b (64*S rows of one request).
+__global__ __launch_bounds__(64) void k_predict_batch(const PredictTask *__restrict__ tasks) {
+  extern __shared__ __align__(16) float xs[];
+  const PredictTask t = tasks[blockIdx.x];
+  const int4 set = ldc(t.set, 0);
+  if (t.S == 4) {
+    predict_block<4>(t.rows, t.n, t.nf, set, t.conds, t.out, t.row0, xs);
+  } else {
+    predict_block<1>(t.rows, t.n, t.nf, set, t.conds, t.out, t.row0, xs);
+  }
+}
+
 }  // namespace
+
+hipError_t launch_predict_batch(const PredictLaunch &p, hipStream_t st) {
+  if (p.n_tasks <= 0) return hipSuccess;
+  if (p.lds > kDynLdsMax) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_predict_batch, dim3((unsigned)p.n_tasks), dim3(64), p.lds, st, p.tasks);
+  return hipGetLastError();
+}
 
 hipError_t launch_batch(const BatchLaunch &b, hipStream_t st) {
   if (b.n_zero > 0) {
