@@ -27,6 +27,23 @@ VALU_PEAK = 256 * 64 * 2.4e9          # lane-ops/s (fp32 VALU, non-packed)
 HBM_PEAK = 8.0e12                     # bytes/s
 
 
+# HBM bytes per launch of the hard-eval kernel on the 2^20 x 64, 4096-set
+# workload, from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE in KiB per
+# dispatch, each scaled by what the counter reads for a plain 256 MiB copy:
+# 2.000 and 1.000).  Valid only for the kernel sources it was measured on.
+HARD_TRAFFIC = {"bytes": 2.386e9, "sources_sha256": "7fdfe9c22cf73739"}
+HARD_SOURCES = ("hard.hip", "hard_block.h", "eval_core.h")
+
+
+def hard_traffic():
+    import hashlib
+    h = hashlib.sha256()
+    for f in HARD_SOURCES:
+        with open(os.path.join(ROOT, "paper_2406_01821_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return HARD_TRAFFIC["bytes"] if h.hexdigest()[:16] == HARD_TRAFFIC["sources_sha256"] else None
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -192,6 +209,112 @@ def bench_ragged(ctx, steps, warmup):
     }
 
 
+def bench_serve(ctx, small, ds_small, big, ds_big, n_requests=2000, rate_hz=2000.0):
+    """Serving loop on the two resident datasets (569 x 30 and 2^20 x 64):
+    Poisson arrivals at rate_hz, half fitness requests (8-2048 rule sets, 10%
+    on the big dataset), half predictions (one rule set x 1-4096 rows).  The
+    same request stream is also run launching each request alone (pack,
+    evaluate, copy back, synchronize), open loop at the same arrival times and
+    back to back for saturation throughput."""
+    import torch
+    from paper_2406_01821_amd import synth
+    t0 = time.time()
+    reqs = synth.serving_mix(small, big, n_requests, rate_hz=rate_hz, seed=4)
+    log(f"generated {n_requests} serving requests in {time.time() - t0:.1f}s")
+    datas, dss = (small, big), (ds_small, ds_big)
+    nominal = 0.0
+    for r in reqs:
+        conds = r.pop.nominal_conds_per_set()
+        nominal += (float(conds.sum()) * datas[r.dataset].n if r.kind == "fitness"
+                    else float(conds[0]) * len(r.rows))
+
+    def submit(r):
+        if r.kind == "fitness":
+            return ctx.serve_submit_fitness(dss[r.dataset], r.pop)
+        return ctx.serve_submit_predict(r.pop, r.rows, big.n_features, big.n_classes, 0)
+
+    def pace(t_start, t_arrival):
+        while True:
+            dt = t_arrival - (time.perf_counter() - t_start)
+            if dt <= 0:
+                return
+            if dt > 2e-4:
+                time.sleep(dt - 1e-4)
+
+    ctx.serve_start(1 << 30)
+    for t in [submit(r) for r in reqs[:64]]:  # warm-up
+        t.wait()
+    ctx.serve_stats(reset=True)
+    t_start = time.perf_counter()
+    tickets = []
+    for r in reqs:
+        pace(t_start, r.t_arrival)
+        tickets.append(submit(r))
+    served_out = [t.wait() for t in tickets]
+    open_stats = ctx.serve_stats(reset=True)
+    t1 = time.perf_counter()
+    for t in [submit(r) for r in reqs]:
+        t.wait()
+    sat_s = time.perf_counter() - t1
+    sat_stats = ctx.serve_stats(reset=True)
+    ctx.serve_stop()
+    log(f"served: p50 {open_stats['p50_us']:.0f} us, p99 {open_stats['p99_us']:.0f} us at "
+        f"{rate_hz:.0f} req/s; saturation {n_requests / sat_s:.0f} req/s "
+        f"(mean batch {sat_stats['mean_batch']:.1f})")
+
+    def alone(r):
+        d = datas[r.dataset]
+        p = ctx.pack_population(r.pop, d.n_features, d.n_classes)
+        if r.kind == "fitness":
+            c, m = ctx.eval_population(dss[r.dataset], p)
+            out = dict(correct=c.cpu().numpy(), confusion=m.cpu().numpy())
+        else:
+            out = dict(pred=ctx.predict(p, r.rows, 0).cpu().numpy())
+        ctx.release_population(p)
+        return out
+
+    for r in reqs[:64]:
+        alone(r)
+    torch.cuda.synchronize()
+    lat = []
+    t_start = time.perf_counter()
+    identical = True
+    for r, so in zip(reqs, served_out):
+        pace(t_start, r.t_arrival)
+        ao = alone(r)
+        lat.append((time.perf_counter() - t_start - r.t_arrival) * 1e6)
+        identical = identical and all(np.array_equal(ao[k], so[k]) for k in ao)
+    alone_open_s = time.perf_counter() - t_start
+    t1 = time.perf_counter()
+    for r in reqs:
+        alone(r)
+    alone_sat_s = time.perf_counter() - t1
+    lat = np.sort(np.array(lat))
+    pct = lambda p: float(lat[max(0, int(np.ceil(p * len(lat))) - 1)])
+    log(f"alone: p50 {pct(0.5):.0f} us, p99 {pct(0.99):.0f} us at {rate_hz:.0f} req/s; "
+        f"saturation {n_requests / alone_sat_s:.0f} req/s; identical={identical}")
+    served_rps = n_requests / sat_s
+    alone_rps = n_requests / alone_sat_s
+    return {
+        "workload": f"{n_requests} requests, Poisson at {rate_hz:.0f}/s: 50% fitness (8-2048 rule "
+                    "sets of 1-32 rules x 1-6 conditions; 90% on 569 x 30, 10% on 2^20 x 64), "
+                    "50% prediction (1 rule set x 1-4096 rows of 64 features)",
+        "nominal_cond_evals": nominal,
+        "served": {"offered_req_per_s": rate_hz, "p50_us": open_stats["p50_us"],
+                   "p99_us": open_stats["p99_us"], "mean_us": open_stats["mean_us"],
+                   "mean_batch": open_stats["mean_batch"],
+                   "saturation_req_per_s": served_rps,
+                   "saturation_cond_evals_per_s": nominal / sat_s,
+                   "saturation_mean_batch": sat_stats["mean_batch"],
+                   "offered_fraction_of_saturation": rate_hz / served_rps},
+        "alone": {"p50_us": pct(0.5), "p99_us": pct(0.99), "open_loop_s": alone_open_s,
+                  "saturation_req_per_s": alone_rps,
+                  "saturation_cond_evals_per_s": nominal / alone_sat_s},
+        "speedup_vs_alone": served_rps / alone_rps,
+        "results_identical_to_alone": identical,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -241,7 +364,7 @@ def main():
     lane_ops = 64.0 * (2.0 * rec["total_t"] + 3.0 * rec["total_ff"])
     achieved = lane_ops / (ms * 1e-3)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
-                "unit": "Tlane-op/s", "frac": achieved / VALU_PEAK, "traffic": None,
+                "unit": "Tlane-op/s", "frac": achieved / VALU_PEAK, "traffic": hard_traffic(),
                 "kernel": "k_hard", "algorithmic_lane_ops": lane_ops,
                 "hbm_bytes_min": float(w.data.n * (w.data.n_features + 1) * 4)}
     result = {
@@ -260,6 +383,11 @@ def main():
     if not args.no_cpu:
         result["cpu_baseline"] = time_cpu_oracle_hard(w)
     ctx.release_population(pop)
+    if not args.only_hard:
+        small = synth.small_hard(0).data
+        ds_small = ctx.upload_dataset(small)
+        result["serving"] = bench_serve(ctx, small, ds_small, w.data, ds)
+        ctx.release_dataset(ds_small)
     ctx.release_dataset(ds)
     del w
     if not args.only_hard:
