@@ -183,14 +183,14 @@ def bench_ragged(ctx, steps, warmup):
         c, m = ctx.batch_outputs(ds, p)
         items.append((ds, p, c, m))
     ws = ctx.batch_workspace(items, (1, 1))
-    (q, tg), tune_ms = ctx.autotune(items, ws)
+    (q, tg, kib), tune_ms = ctx.autotune(items, ws)
     plan = ctx.batch_plan(items, ws, graph=True)
     batch_ms, batch_wall = timed(plan.run, steps, warmup, stream)
     torch.cuda.synchronize()
     exact = all(torch.equal(c, o[0]) and torch.equal(m, o[1])
                 for (_, _, c, m), o in zip(items, outs))
     log(f"ragged: plain {plain_wall:.3f} ms, batched {batch_wall:.3f} ms "
-        f"(tuned split {q} sets x {tg} tiles), identical={exact}")
+        f"(tuned split {q} sets x {tg} tiles, {kib} KiB tiles), identical={exact}")
     plan.release()
     for ds, p in devs:
         ctx.release_population(p)
@@ -203,7 +203,8 @@ def bench_ragged(ctx, steps, warmup):
                   "cond_evals_per_s": nominal / (plain_wall * 1e-3)},
         "batched": {"ms": batch_wall, "gpu_ms": batch_ms,
                     "cond_evals_per_s": nominal / (batch_wall * 1e-3),
-                    "sets_per_task": q, "tiles_per_task": tg, "graph": True},
+                    "sets_per_task": q, "tiles_per_task": tg, "tile_kib": kib,
+                    "graph": True},
         "speedup_vs_plain": plain_wall / batch_wall,
         "bit_identical_to_plain": exact,
     }
@@ -252,8 +253,14 @@ def bench_serve(ctx, small, ds_small, big, ds_big, n_requests=2000, rate_hz=2000
         tickets.append(submit(r))
     served_out = [t.wait() for t in tickets]
     open_stats = ctx.serve_stats(reset=True)
+    # saturation: four submitting threads (packing runs in parallel in the
+    # library), every request offered at once
+    import concurrent.futures as cf
     t1 = time.perf_counter()
-    for t in [submit(r) for r in reqs]:
+    with cf.ThreadPoolExecutor(4) as ex:
+        sat_tickets = list(ex.map(submit, reqs))
+    submit_s = time.perf_counter() - t1
+    for t in sat_tickets:
         t.wait()
     sat_s = time.perf_counter() - t1
     sat_stats = ctx.serve_stats(reset=True)
@@ -306,6 +313,7 @@ def bench_serve(ctx, small, ds_small, big, ds_big, n_requests=2000, rate_hz=2000
                    "saturation_req_per_s": served_rps,
                    "saturation_cond_evals_per_s": nominal / sat_s,
                    "saturation_mean_batch": sat_stats["mean_batch"],
+                   "saturation_submit_s": submit_s, "saturation_total_s": sat_s,
                    "offered_fraction_of_saturation": rate_hz / served_rps},
         "alone": {"p50_us": pct(0.5), "p99_us": pct(0.99), "open_loop_s": alone_open_s,
                   "saturation_req_per_s": alone_rps,

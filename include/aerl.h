@@ -239,12 +239,16 @@ typedef struct {
   int32_t *confusion; /* device int32 [n_sets][C][C] or NULL */
 } aerl_batch_item;
 
-/* Work-split of a batch: rule sets per work item, AERL_TILE-sample tiles per
- * work item.  0 in both fields asks for the library's choice (the tuned one
- * when aerl_autotune has seen a batch of this shape, else a heuristic). */
+/* Work split of a batch: rule sets per work item, AERL_TILE-sample tiles per
+ * work item, and the LDS budget of a block's feature tile in KiB (an item
+ * takes 4, 2 or 1 samples per lane, the most whose 64-lane tile of all its
+ * features fits the budget; above 80 only one block fits a CU).  0 in a
+ * field asks for the library's choice (the tuned one when aerl_autotune has
+ * seen a batch of this shape, else 64 sets, 4 tiles, 64 KiB). */
 typedef struct {
   int32_t sets_per_task;
   int32_t tiles_per_task;
+  int32_t tile_kib;
 } aerl_batch_cfg;
 
 enum {
@@ -288,7 +292,7 @@ aerl_status aerl_batch_release(aerl_ctx *ctx, int32_t plan_id);
  * with its time in *best_ms.  Later plans with cfg NULL or zero fields use
  * it.  With AERL_AUTOTUNE_CACHE set in the environment the table is also
  * read from and appended to that file.  ws as for aerl_batch_plan with the
- * largest candidate (aerl_batch_workspace_bytes with cfg {1, 1}).
+ * largest candidate (aerl_batch_workspace_bytes with cfg {1, 1, 64}).
  * Errors: as aerl_batch_plan. */
 aerl_status aerl_autotune(aerl_ctx *ctx, const aerl_batch_item *items, int32_t n_items, void *ws,
                           size_t ws_bytes, hipStream_t stream, aerl_batch_cfg *best,

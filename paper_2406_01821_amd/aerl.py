@@ -56,7 +56,8 @@ class aerl_batch_item(C.Structure):
 
 
 class aerl_batch_cfg(C.Structure):
-    _fields_ = [("sets_per_task", C.c_int32), ("tiles_per_task", C.c_int32)]
+    _fields_ = [("sets_per_task", C.c_int32), ("tiles_per_task", C.c_int32),
+                ("tile_kib", C.c_int32)]
 
 
 AERL_BATCH_GRAPH = 1
@@ -175,12 +176,11 @@ class _HostPop:
     """Keeps contiguous host arrays of a Population alive for one call."""
 
     def __init__(self, pop: Population):
-        self.arrays = [np.ascontiguousarray(a) for a in (
-            pop.set_rule_off.astype(np.int32), pop.set_default.astype(np.int32),
-            pop.rule_cond_off.astype(np.int32), pop.rule_class.astype(np.int32),
-            pop.op.astype(np.uint8), pop.kind.astype(np.uint8), pop.f.astype(np.int32),
-            pop.g.astype(np.int32), pop.coef.astype(np.float32), pop.coef2.astype(np.float32),
-            pop.theta.astype(np.float32))]
+        i32, u8, f32 = np.int32, np.uint8, np.float32
+        self.arrays = [np.ascontiguousarray(a, dtype=t) for a, t in (
+            (pop.set_rule_off, i32), (pop.set_default, i32), (pop.rule_cond_off, i32),
+            (pop.rule_class, i32), (pop.op, u8), (pop.kind, u8), (pop.f, i32), (pop.g, i32),
+            (pop.coef, f32), (pop.coef2, f32), (pop.theta, f32))]
         self.s = aerl_population(pop.n_sets, *[a.ctypes.data for a in self.arrays])
 
 
@@ -330,7 +330,7 @@ class Context:
         """items: list of (DeviceDataset, DevicePopulation, correct, confusion-or-None)."""
         arr = self._batch_items(items)
         nb = C.c_size_t()
-        c = C.byref(aerl_batch_cfg(*cfg)) if cfg is not None else None
+        c = C.byref(aerl_batch_cfg(*cfg)) if cfg is not None else None  # 2 or 3 fields
         self.check(aerl_batch_workspace_bytes(self.h, arr, len(items), c, C.byref(nb)))
         return torch.empty(max(nb.value, 256), dtype=torch.uint8, device=self.device)
 
@@ -344,13 +344,13 @@ class Context:
         return BatchPlan(self, pid.value, list(items), ws)
 
     def autotune(self, items, ws, stream=None):
-        """Returns ((sets_per_task, tiles_per_task), ms)."""
+        """Returns ((sets_per_task, tiles_per_task, tile_kib), ms)."""
         arr = self._batch_items(items)
         best = aerl_batch_cfg()
         ms = C.c_float()
         self.check(aerl_autotune(self.h, arr, len(items), _ptr(ws), ws.numel(), _stream(stream),
                                  C.byref(best), C.byref(ms)))
-        return (best.sets_per_task, best.tiles_per_task), ms.value
+        return (best.sets_per_task, best.tiles_per_task, best.tile_kib), ms.value
 
     # -------------------------------------------------------------- serving
     def serve_start(self, arena_bytes: int, max_batch: int = 0, max_inflight: int = 0):

@@ -25,7 +25,6 @@ struct BatchPlanRec {
   hipGraphExec_t exec = nullptr;
   hipStream_t capture = nullptr;
   std::vector<int32_t> dataset_ids, pop_ids;
-  int32_t sets_per_task = 0, tiles_per_task = 0;
 };
 
 void destroy_plan(BatchPlanRec *p) {
@@ -36,9 +35,9 @@ void destroy_plan(BatchPlanRec *p) {
   delete p;
 }
 
-int batch_samples_per_lane(int32_t nf) {
+int batch_samples_per_lane(int32_t nf, size_t tile_budget) {
   int s = 4;
-  while (s > 1 && (size_t)nf * 256 * s > 64 * 1024) s >>= 1;
+  while (s > 1 && (size_t)nf * 256 * s > tile_budget) s >>= 1;
   return s;
 }
 
@@ -47,23 +46,26 @@ size_t align256_(size_t v) { return (v + 255) & ~size_t(255); }
 }  // namespace
 
 namespace {
-int32_t sets_per_item(const DatasetRec &ds, int32_t n_sets, int32_t Q) {
-  const size_t tile_bytes = (size_t)ds.nf * 64 * batch_samples_per_lane(ds.nf) * 4;
+int32_t sets_per_item(const DatasetRec &ds, int32_t n_sets, const BatchSplit &sp) {
+  const int32_t Q = sp.Q;
+  const size_t tile_bytes = (size_t)ds.nf * 64 * batch_samples_per_lane(ds.nf, sp.tile_budget) * 4;
   const int32_t q_fit =
       (int32_t)std::min<size_t>((kBatchLdsMax - tile_bytes) / ((size_t)ds.nc * 4), 1 << 20);
   return std::max(1, std::min({Q, n_sets, q_fit}));
 }
 }  // namespace
 
-int64_t batch_task_count(const DatasetRec &ds, int32_t n_sets, int32_t Q, int32_t TG) {
+int64_t batch_task_count(const DatasetRec &ds, int32_t n_sets, const BatchSplit &sp) {
   if (n_sets <= 0) return 0;
-  const int32_t q = sets_per_item(ds, n_sets, Q);
+  const int32_t q = sets_per_item(ds, n_sets, sp);
+  const int32_t TG = sp.TG;
   int64_t groups = 0;
   for (int c = 0; c < ds.nc; ++c) groups += (ds.region_tiles[c] + TG - 1) / TG;
   return (int64_t)((n_sets + q - 1) / q) * groups;
 }
 
-void build_batch_tables(const std::vector<BatchSource> &src, int32_t Q, int32_t TG, BatchTables *b) {
+void build_batch_tables(const std::vector<BatchSource> &src, const BatchSplit &sp, BatchTables *b) {
+  const int32_t TG = sp.TG;
   b->items.clear();
   b->tasks.clear();
   b->zero.clear();
@@ -72,7 +74,7 @@ void build_batch_tables(const std::vector<BatchSource> &src, int32_t Q, int32_t 
   for (size_t i = 0; i < src.size(); ++i) {
     const DatasetRec &ds = *src[i].ds;
     const int32_t n_sets = src[i].n_sets;
-    const int S = batch_samples_per_lane(ds.nf);
+    const int S = batch_samples_per_lane(ds.nf, sp.tile_budget);
     BatchItem it{};
     it.x_fm = ds.x_fm;
     it.n_pad = ds.n_pad;
@@ -89,7 +91,7 @@ void build_batch_tables(const std::vector<BatchSource> &src, int32_t Q, int32_t 
     b->zero.push_back({it.correct, n_sets});
     if (it.confusion) b->zero.push_back({it.confusion, (int64_t)n_sets * ds.nc * ds.nc});
     const size_t tile_bytes = (size_t)ds.nf * 64 * S * 4;
-    const int32_t q = sets_per_item(ds, n_sets, Q);
+    const int32_t q = sets_per_item(ds, n_sets, sp);
     b->lds = std::max(b->lds, tile_bytes + (size_t)q * ds.nc * 4);
     const int4 *hs = src[i].host_sets;
     for (int32_t q0 = 0; q0 < n_sets; q0 += q) {
@@ -197,25 +199,29 @@ void load_tune_file(aerl_ctx *ctx) {
   if (!path) return;
   std::ifstream in(path);
   std::string key;
-  int32_t q, tg;
+  int32_t q, tg, kib;
   double ms;
-  while (in >> key >> q >> tg >> ms) ctx->tuned[key] = {q, tg};
+  while (in >> key >> q >> tg >> kib >> ms) ctx->tuned[key] = {q, tg, kib};
 }
 
-void default_cfg(aerl_ctx *ctx, const std::vector<ItemView> &v, const aerl_batch_cfg *cfg,
-                 int32_t *Q, int32_t *TG) {
-  *Q = cfg ? cfg->sets_per_task : 0;
-  *TG = cfg ? cfg->tiles_per_task : 0;
-  if (*Q > 0 && *TG > 0) return;
+// The caller's split, with zero fields taken from the tuned table for this
+// batch shape or the defaults.
+aerl_status resolve_split(aerl_ctx *ctx, const std::vector<ItemView> &v, const aerl_batch_cfg *cfg,
+                          BatchSplit *sp) {
+  std::array<int32_t, 3> d = {64, 4, 64};
   load_tune_file(ctx);
   auto it = ctx->tuned.find(shape_key(v));
-  int32_t q = 64, tg = 4;
-  if (it != ctx->tuned.end()) {
-    q = it->second.first;
-    tg = it->second.second;
-  }
-  if (*Q <= 0) *Q = q;
-  if (*TG <= 0) *TG = tg;
+  if (it != ctx->tuned.end()) d = it->second;
+  const int32_t q = cfg && cfg->sets_per_task > 0 ? cfg->sets_per_task : d[0];
+  const int32_t tg = cfg && cfg->tiles_per_task > 0 ? cfg->tiles_per_task : d[1];
+  const int32_t kib = cfg && cfg->tile_kib > 0 ? cfg->tile_kib : d[2];
+  if ((cfg && (cfg->sets_per_task < 0 || cfg->tiles_per_task < 0 || cfg->tile_kib < 0)) ||
+      kib > (int32_t)(kBatchLdsMax / 1024))
+    return fail(ctx, AERL_EINVAL, "invalid work split (%d, %d, %d)", q, tg, kib);
+  sp->Q = q;
+  sp->TG = tg;
+  sp->tile_budget = (size_t)kib * 1024;
+  return AERL_OK;
 }
 
 aerl_status upload_plan(aerl_ctx *ctx, const BatchTables &b, void *ws, size_t ws_bytes, hipStream_t st,
@@ -248,10 +254,11 @@ aerl_status aerl_batch_workspace_bytes(aerl_ctx *ctx, const aerl_batch_item *ite
   std::vector<ItemView> v;
   aerl_status st = gather(ctx, items, n_items, &v);
   if (st) return st;
-  int32_t Q, TG;
-  default_cfg(ctx, v, cfg, &Q, &TG);
+  BatchSplit sp;
+  st = resolve_split(ctx, v, cfg, &sp);
+  if (st) return st;
   BatchTables b;
-  build_batch_tables(sources(v), Q, TG, &b);
+  build_batch_tables(sources(v), sp, &b);
   *bytes = b.bytes;
   return AERL_OK;
 }
@@ -266,17 +273,15 @@ aerl_status aerl_batch_plan(aerl_ctx *ctx, const aerl_batch_item *items, int32_t
   std::vector<ItemView> v;
   aerl_status st = gather(ctx, items, n_items, &v);
   if (st) return st;
-  int32_t Q, TG;
-  default_cfg(ctx, v, cfg, &Q, &TG);
-  if (Q < 1 || TG < 1) return fail(ctx, AERL_EINVAL, "work split must be >= 1");
+  BatchSplit sp;
+  st = resolve_split(ctx, v, cfg, &sp);
+  if (st) return st;
   AERL_HIP(ctx, hipSetDevice(ctx->device));
   BatchTables b;
-  build_batch_tables(sources(v), Q, TG, &b);
+  build_batch_tables(sources(v), sp, &b);
   std::unique_ptr<BatchPlanRec, PlanDeleter> plan(new BatchPlanRec());
   st = upload_plan(ctx, b, ws, ws_bytes, stream, plan.get());
   if (st) return st;
-  plan->sets_per_task = Q;
-  plan->tiles_per_task = TG;
   for (const auto &it : v) {
     plan->dataset_ids.push_back(it.item->dataset_id);
     plan->pop_ids.push_back(it.item->pop_id);
@@ -342,52 +347,61 @@ aerl_status aerl_autotune(aerl_ctx *ctx, const aerl_batch_item *items, int32_t n
   AERL_HIP(ctx, hipSetDevice(ctx->device));
   static const int32_t kQ[] = {16, 32, 64, 128};
   static const int32_t kTG[] = {1, 2, 4, 8, 16};
+  static const int32_t kKiB[] = {64, 128};
   hipEvent_t e0, e1;
   AERL_HIP(ctx, hipEventCreate(&e0));
   AERL_HIP(ctx, hipEventCreate(&e1));
   float best_t = 1e30f;
-  int32_t bq = 64, btg = 4;
-  for (int32_t q : kQ) {
-    for (int32_t tg : kTG) {
-      BatchTables b;
-      build_batch_tables(sources(v), q, tg, &b);
-      if (b.lds > kBatchLdsMax) continue;
-      BatchPlanRec tmp;
-      if (upload_plan(ctx, b, ws, ws_bytes, stream, &tmp) != AERL_OK) continue;
-      hipError_t e = launch_batch(tmp.launch, stream);  // warm-up
-      float t = 0.0f;
-      for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
-        if (e == hipSuccess) e = hipEventRecord(e0, stream);
-        if (e == hipSuccess) e = launch_batch(tmp.launch, stream);
-        if (e == hipSuccess) e = hipEventRecord(e1, stream);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        float ms = 0.0f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        t += ms;
-      }
-      if (e != hipSuccess) {
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        return fail(ctx, AERL_EDEVICE, "autotune launch failed: %s", hipGetErrorString(e));
-      }
-      t *= 0.5f;
-      if (t < best_t) {
-        best_t = t;
-        bq = q;
-        btg = tg;
+  BatchSplit best_sp;
+  for (int32_t kib : kKiB) {
+    for (int32_t q : kQ) {
+      for (int32_t tg : kTG) {
+        BatchSplit sp;
+        sp.Q = q;
+        sp.TG = tg;
+        sp.tile_budget = (size_t)kib * 1024;
+        BatchTables b;
+        build_batch_tables(sources(v), sp, &b);
+        if (b.lds > kBatchLdsMax) continue;
+        BatchPlanRec tmp;
+        if (upload_plan(ctx, b, ws, ws_bytes, stream, &tmp) != AERL_OK) continue;
+        hipError_t e = launch_batch(tmp.launch, stream);  // warm-up
+        float t = 0.0f;
+        for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
+          if (e == hipSuccess) e = hipEventRecord(e0, stream);
+          if (e == hipSuccess) e = launch_batch(tmp.launch, stream);
+          if (e == hipSuccess) e = hipEventRecord(e1, stream);
+          if (e == hipSuccess) e = hipEventSynchronize(e1);
+          float ms = 0.0f;
+          if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+          t += ms;
+        }
+        if (e != hipSuccess) {
+          (void)hipEventDestroy(e0);
+          (void)hipEventDestroy(e1);
+          return fail(ctx, AERL_EDEVICE, "autotune launch failed: %s", hipGetErrorString(e));
+        }
+        t *= 0.5f;
+        if (t < best_t) {
+          best_t = t;
+          best_sp = sp;
+        }
       }
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  if (best_t >= 1e30f) return fail(ctx, AERL_ENOMEM, "no candidate split fits ws (%zu bytes)", ws_bytes);
+  const int32_t bkib = (int32_t)(best_sp.tile_budget / 1024);
   const std::string key = shape_key(v);
-  ctx->tuned[key] = {bq, btg};
+  ctx->tuned[key] = {best_sp.Q, best_sp.TG, bkib};
   if (const char *path = std::getenv("AERL_AUTOTUNE_CACHE")) {
     std::ofstream out(path, std::ios::app);
-    out << key << " " << bq << " " << btg << " " << best_t << "\n";
+    out << key << " " << best_sp.Q << " " << best_sp.TG << " " << bkib << " " << best_t << "\n";
   }
-  best->sets_per_task = bq;
-  best->tiles_per_task = btg;
+  best->sets_per_task = best_sp.Q;
+  best->tiles_per_task = best_sp.TG;
+  best->tile_kib = bkib;
   if (best_ms) *best_ms = best_t;
   return AERL_OK;
 }

@@ -39,9 +39,16 @@ hipError_t launch_batch(const BatchLaunch &b, hipStream_t st);
 
 constexpr size_t kBatchLdsMax = kDynLdsMax;
 
-// Samples per lane a batch item uses for a dataset of nf features (its
-// feature tile stays within 64 KiB, so two blocks fit a CU).
-int batch_samples_per_lane(int32_t nf);
+// Work split: rule sets and layout tiles per work item, and the LDS budget
+// of a block's feature tile.
+struct BatchSplit {
+  int32_t Q = 64, TG = 4;
+  size_t tile_budget = 64 * 1024;
+};
+
+// Samples per lane of an item with nf features: the most of {4, 2, 1} whose
+// 64-lane tile of all features fits the budget.
+int batch_samples_per_lane(int32_t nf, size_t tile_budget);
 
 // One evaluation of a batch, as the table builder sees it.
 struct BatchSource {
@@ -66,11 +73,11 @@ struct BatchTables {
 // Cuts every source into work items of Q rule sets x TG tiles (Q lowered per
 // source until its block fits in LDS), sorts them by estimated cost
 // (samples x nominal conditions), largest first, and lays the tables out.
-void build_batch_tables(const std::vector<BatchSource> &src, int32_t Q, int32_t TG,
+void build_batch_tables(const std::vector<BatchSource> &src, const BatchSplit &sp,
                         BatchTables *t);
 
 // Number of work items build_batch_tables makes for one source.
-int64_t batch_task_count(const DatasetRec &ds, int32_t n_sets, int32_t Q, int32_t TG);
+int64_t batch_task_count(const DatasetRec &ds, int32_t n_sets, const BatchSplit &sp);
 
 // Writes the tables (t.bytes) to host memory `img` for a copy to device
 // address `dev` and fills the launch record (persistent grid sized for n_cu

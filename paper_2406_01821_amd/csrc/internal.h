@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <cstdint>
 #include <cstdio>
 #include <map>
@@ -120,7 +121,7 @@ struct aerl_ctx {
   std::unordered_map<int32_t, aerl::DatasetRec> datasets;
   std::unordered_map<int32_t, aerl::PopRec> pops;
   std::unordered_map<int32_t, std::unique_ptr<aerl::BatchPlanRec, aerl::PlanDeleter>> plans;
-  std::map<std::string, std::pair<int32_t, int32_t>> tuned;  // batch shape -> (sets, tiles) per task
+  std::map<std::string, std::array<int32_t, 3>> tuned;  // batch shape -> (sets, tiles, tile KiB)
   bool tune_file_loaded = false;
   aerl::Serve *serve = nullptr;
 };

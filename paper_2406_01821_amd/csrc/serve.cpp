@@ -28,8 +28,7 @@ using Clock = std::chrono::steady_clock;
 
 namespace {
 
-constexpr int32_t kServeQ = 64;     // rule sets per fitness work item
-constexpr int32_t kServeTG = 4;     // layout tiles per fitness work item
+const BatchSplit kServeSplit{};  // 64 rule sets x 4 tiles per work item, 64 KiB tiles
 constexpr size_t kTableSlack = 16 * 256;  // alignment padding of the per-launch tables
 constexpr size_t kInitialPinned = 4u << 20;
 
@@ -91,7 +90,9 @@ struct Req {
   uint64_t ticket = 0;
   int32_t kind = 0;
   int32_t dataset_id = -1;
-  const DatasetRec *ds = nullptr;
+  DatasetRec dsv;                       // copy of the dataset's record
+  const DatasetRec *ds = nullptr;       // &dsv for fitness requests
+  const DatasetRec *ds_reg = nullptr;   // the registry entry it was copied from
   std::vector<char> image;  // packed population (host)
   PackedLayout L{};
   PopRec rec{};
@@ -238,7 +239,7 @@ bool Serve::launch_one(std::unique_lock<std::mutex> &lk, Slot &slot) {
     }
   }
   BatchTables bt;
-  build_batch_tables(src, kServeQ, kServeTG, &bt);
+  build_batch_tables(src, kServeSplit, &bt);
   const size_t tables_off = al(cur);
   const size_t ptasks_off = al(tables_off + bt.bytes);
   const size_t in_end = al(ptasks_off + sizeof(PredictTask) * ptasks.size());
@@ -441,37 +442,48 @@ aerl_status aerl_serve_start(aerl_ctx *ctx, void *arena, size_t arena_bytes,
 
 aerl_status aerl_serve_submit(aerl_ctx *ctx, const aerl_request *req, uint64_t *ticket) {
   if (!ctx) return AERL_EINVAL;
-  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
-  ctx->err.clear();
-  Serve *sv = ctx->serve;
-  if (!sv || !sv->running) return fail(ctx, AERL_ESTATE, "serving loop is not running");
-  if (!req || !ticket || !req->pop) return fail(ctx, AERL_EINVAL, "NULL request, population or ticket");
+  // Checks and the dataset lookup under the context lock; validation and
+  // packing (the expensive part) without it, so submitting threads pack in
+  // parallel; the lookup is repeated when the request is queued.
+  const Clock::time_point t0 = Clock::now();
   auto r = std::make_unique<Req>();
-  r->kind = req->kind;
-  if (req->kind == AERL_REQ_FITNESS) {
-    auto it = ctx->datasets.find(req->dataset_id);
-    if (it == ctx->datasets.end()) return fail(ctx, AERL_ENOENT, "unknown dataset %d", req->dataset_id);
-    r->ds = &it->second;
-    r->dataset_id = req->dataset_id;
-    if (req->n_features != r->ds->nf || req->n_classes != r->ds->nc)
-      return fail(ctx, AERL_EINVAL, "request shape (%d features, %d classes) differs from the dataset's",
-                  req->n_features, req->n_classes);
-    if (req->pop->n_sets > 0 && !req->correct) return fail(ctx, AERL_EINVAL, "correct is NULL");
-  } else if (req->kind == AERL_REQ_PREDICT) {
-    if (req->n_rows < 0) return fail(ctx, AERL_EINVAL, "n_rows < 0");
-    if (req->n_rows > 0 && (!req->rows || !req->pred)) return fail(ctx, AERL_EINVAL, "NULL rows or pred");
-    if (req->set_index < 0 || req->set_index >= req->pop->n_sets)
-      return fail(ctx, AERL_EINVAL, "set_index %d outside the population", req->set_index);
-    if ((size_t)req->n_features * 64 * 4 > kDynLdsMax)
-      return fail(ctx, AERL_EINVAL, "%d features exceed the prediction tile", req->n_features);
-  } else {
-    return fail(ctx, AERL_EINVAL, "unknown request kind %d", req->kind);
+  Serve *sv = nullptr;
+  {
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    ctx->err.clear();
+    sv = ctx->serve;
+    if (!sv || !sv->running) return fail(ctx, AERL_ESTATE, "serving loop is not running");
+    if (!req || !ticket || !req->pop) return fail(ctx, AERL_EINVAL, "NULL request, population or ticket");
+    r->kind = req->kind;
+    if (req->kind == AERL_REQ_FITNESS) {
+      auto it = ctx->datasets.find(req->dataset_id);
+      if (it == ctx->datasets.end()) return fail(ctx, AERL_ENOENT, "unknown dataset %d", req->dataset_id);
+      r->dsv = it->second;
+      r->ds = &r->dsv;
+      r->ds_reg = &it->second;
+      r->dataset_id = req->dataset_id;
+      if (req->n_features != r->ds->nf || req->n_classes != r->ds->nc)
+        return fail(ctx, AERL_EINVAL, "request shape (%d features, %d classes) differs from the dataset's",
+                    req->n_features, req->n_classes);
+      if (req->pop->n_sets > 0 && !req->correct) return fail(ctx, AERL_EINVAL, "correct is NULL");
+    } else if (req->kind == AERL_REQ_PREDICT) {
+      if (req->n_rows < 0) return fail(ctx, AERL_EINVAL, "n_rows < 0");
+      if (req->n_rows > 0 && (!req->rows || !req->pred)) return fail(ctx, AERL_EINVAL, "NULL rows or pred");
+      if (req->set_index < 0 || req->set_index >= req->pop->n_sets)
+        return fail(ctx, AERL_EINVAL, "set_index %d outside the population", req->set_index);
+      if ((size_t)req->n_features * 64 * 4 > kDynLdsMax)
+        return fail(ctx, AERL_EINVAL, "%d features exceed the prediction tile", req->n_features);
+    } else {
+      return fail(ctx, AERL_EINVAL, "unknown request kind %d", req->kind);
+    }
   }
   r->nf = req->n_features;
   r->nc = req->n_classes;
   int32_t n_rules = 0, n_conds = 0;
-  aerl_status st = validate_population(ctx, req->pop, r->nf, r->nc, &n_rules, &n_conds);
-  if (st) return st;
+  if (validate_population(nullptr, req->pop, r->nf, r->nc, &n_rules, &n_conds) != AERL_OK) {
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);  // again, for the message
+    return validate_population(ctx, req->pop, r->nf, r->nc, &n_rules, &n_conds);
+  }
   r->L = packed_layout(req->pop->n_sets, n_rules, n_conds);
   r->image.resize(r->L.total);
   pack_population_image(req->pop, r->nf, r->nc, n_rules, n_conds, r->image.data(), &r->rec);
@@ -481,7 +493,7 @@ aerl_status aerl_serve_submit(aerl_ctx *ctx, const aerl_request *req, uint64_t *
     r->h_conf = req->confusion;
     r->in_bytes = al(r->L.total);
     r->out_bytes = al(r->correct_bytes()) + al(r->conf_bytes());
-    const int64_t tasks = batch_task_count(*r->ds, r->rec.n_sets, kServeQ, kServeTG);
+    const int64_t tasks = batch_task_count(*r->ds, r->rec.n_sets, kServeSplit);
     r->table_bytes = sizeof(BatchItem) + 2 * sizeof(BatchZero) + (size_t)tasks * sizeof(BatchTask);
     r->nominal = (double)r->ds->n * (double)r->rec.nominal_conds;
   } else {
@@ -495,12 +507,19 @@ aerl_status aerl_serve_submit(aerl_ctx *ctx, const aerl_request *req, uint64_t *
     r->table_bytes = (size_t)((r->n_rows + 64 * S - 1) / (64 * S)) * sizeof(PredictTask);
     r->nominal = (double)r->n_rows * (double)hsets[r->set_index].w;
   }
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  if (sv != ctx->serve || !sv->running) return fail(ctx, AERL_ESTATE, "serving loop is not running");
   if (r->dev_bytes() + kTableSlack > sv->arena_bytes)
     return fail(ctx, AERL_ENOMEM, "request needs %zu bytes of the %zu-byte arena",
                 r->dev_bytes() + kTableSlack, sv->arena_bytes);
+  if (r->kind == AERL_REQ_FITNESS) {
+    auto it = ctx->datasets.find(r->dataset_id);
+    if (it == ctx->datasets.end() || &it->second != r->ds_reg)
+      return fail(ctx, AERL_ENOENT, "dataset %d was released", r->dataset_id);
+  }
   std::lock_guard<std::mutex> sl(sv->m);
   if (sv->stopping) return fail(ctx, AERL_ESTATE, "serving loop is stopping");
-  r->t_submit = Clock::now();
+  r->t_submit = t0;
   r->ticket = sv->next_ticket++;
   if (!sv->have_first) {
     sv->have_first = true;

@@ -59,7 +59,8 @@ def check_items(items, refs, confusion=True):
             np.testing.assert_array_equal(m.cpu().numpy(), rm, err_msg=f"item {k} confusion")
 
 
-@pytest.mark.parametrize("cfg", [None, (1, 1), (3, 2), (16, 1), (64, 4), (128, 16), (1000, 1)])
+@pytest.mark.parametrize("cfg", [None, (1, 1), (3, 2), (16, 1), (64, 4), (128, 16), (1000, 1),
+                                 (64, 4, 128), (7, 3, 32), (16, 2, 1)])
 def test_batch_bit_exact_every_split(ctx, runs, cfg):
     import torch
     ws_, devs, refs = runs
@@ -191,8 +192,8 @@ def test_autotune_picks_a_candidate_and_plans_use_it(ctx, runs):
     ws_, devs, refs = runs
     items = make_items(ctx, devs)
     ws = ctx.batch_workspace(items, (1, 1))
-    (q, tg), ms = ctx.autotune(items, ws)
-    assert q in (16, 32, 64, 128) and tg in (1, 2, 4, 8, 16)
+    (q, tg, kib), ms = ctx.autotune(items, ws)
+    assert q in (16, 32, 64, 128) and tg in (1, 2, 4, 8, 16) and kib in (64, 128)
     assert ms > 0
     check_items(items, refs)  # autotune leaves valid outputs behind
     for _, _, c, m in items:
