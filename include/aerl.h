@@ -409,7 +409,10 @@ aerl_status aerl_soft_forward(aerl_ctx *ctx, int32_t dataset_id, int32_t pop_id,
  * theta entries of kind-1 conditions are written as 0).  The adjoint
  * recomputes every sigmoid instead of storing activations.  dloss is
  * device fp32 [n_sets]; ws holds at least backward_bytes.  Deterministic.
- * Errors: AERL_ENOENT, AERL_EINVAL, AERL_EDEVICE. */
+ * Rule sets of up to 32 rules run with the per-rule state in registers;
+ * longer ones keep it in LDS, which bounds them (about 38 rules with few
+ * features).  Errors: AERL_ENOENT, AERL_EINVAL (also: rule sets too long
+ * for the adjoint kernel), AERL_EDEVICE. */
 aerl_status aerl_soft_backward(aerl_ctx *ctx, int32_t dataset_id, int32_t pop_id,
                                const float *coef, const float *coef2, const float *theta,
                                const float *dloss, float *dcoef, float *dcoef2, float *dtheta,

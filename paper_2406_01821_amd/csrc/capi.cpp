@@ -415,6 +415,8 @@ static aerl_status soft_common(aerl_ctx *ctx, int32_t dataset_id, int32_t pop_id
     return fail(ctx, AERL_EINVAL, "population and dataset shapes differ");
   if (pop.n_conds > 0 && (!l->coef || !l->coef2 || !l->theta))
     return fail(ctx, AERL_EINVAL, "a parameter array is NULL");
+  if (backward && !soft_backward_supported(ds, pop))
+    return fail(ctx, AERL_EINVAL, "rule sets of %d rules exceed the adjoint kernel's LDS", pop.max_rules);
   const size_t need = soft_ws_bytes(ds, pop, backward);
   if (need && (!l->ws || ((uintptr_t)l->ws & 255)))
     return fail(ctx, AERL_EINVAL, "ws is NULL or not 256-byte aligned");

@@ -177,6 +177,7 @@ struct SoftLaunch {
   size_t ws_bytes;
 };
 size_t soft_ws_bytes(const DatasetRec &ds, const PopRec &pop, bool backward);
+bool soft_backward_supported(const DatasetRec &ds, const PopRec &pop);
 hipError_t launch_soft_forward(const SoftLaunch &l, hipStream_t s);
 hipError_t launch_soft_backward(const SoftLaunch &l, hipStream_t s);
 

@@ -64,11 +64,14 @@ constexpr float kShift = 64.0f;
 constexpr float kExpNegShift = 1.60381089e-28f;  // e^-64
 struct RuleAcc {
   float a = 0.0f, us = 0.0f;
-  __device__ __forceinline__ void add(float z) {
+  // Adds condition value z; returns its log sigmoid(z).
+  __device__ __forceinline__ float add(float z) {
     const float az = fabsf(z);
     const float e_s = fexp(kShift - az);  // e^(64 - |z|)
-    a -= fmaxf(-z, 0.0f) + log1p_unit(e_s * kExpNegShift);
+    const float nl = fmaxf(-z, 0.0f) + log1p_unit(e_s * kExpNegShift);  // -log sigmoid(z)
+    a -= nl;
     us += e_s;
+    return -nl;
   }
 };
 
@@ -98,6 +101,23 @@ __device__ __forceinline__ float lse(float p, float q) {
   const float m = fmaxf(p, q);
   if (m == kNegInf) return kNegInf;
   return m + log1p_unit(fexp(-fabsf(p - q)));
+}
+
+// Sum of v over the wave, left in lane 63: an inclusive scan inside each
+// 16-lane row (row_shr 1, 2, 4, 8), then the row totals carried forward
+// with row_bcast 15 and 31.  A fixed order, so bit-identical from run to run.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_add(float v) {
+  return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, true));
+}
+__device__ __forceinline__ float wave_total_last(float v) {
+  v = dpp_add<0x111, 0xf>(v);
+  v = dpp_add<0x112, 0xf>(v);
+  v = dpp_add<0x114, 0xf>(v);
+  v = dpp_add<0x118, 0xf>(v);
+  v = dpp_add<0x142, 0xa>(v);
+  v = dpp_add<0x143, 0xc>(v);
+  return v;
 }
 
 __device__ __forceinline__ float wave_sum(float v) {
@@ -328,8 +348,7 @@ __global__ __launch_bounds__(kBwdWaves * 64) void k_soft_bwd(const SoftArgs a) {
           float z[1], xf[1], xg[1];
           bool ff;
           cond_z<1>(a, xs, lane, j, z, xf, xg, ff);
-          ra.add(z[0]);
-          const float lsn = log_sigmoid(z[0]) - z[0];  // log sigmoid(-z)
+          const float lsn = ra.add(z[0]) - z[0];  // log sigmoid(-z)
           const float e = pre + lsn;
           const float dz = (mul != 0.0f && e > kNegInf) ? mul * fexp(e) : 0.0f;
           const float g0 = wave_sum(ff ? dz * xg[0] : dz);
@@ -341,6 +360,161 @@ __global__ __launch_bounds__(kBwdWaves * 64) void k_soft_bwd(const SoftArgs a) {
           }
         }
         U = lse(hit ? ak : kNegInf, rule_log_miss(ra) + U);
+      }
+    }
+  }
+  __syncthreads();
+  for (int q = 0; q < Q; ++q) {
+    const int4 ss = ldc(a.ssets, q0 + q);
+    for (int i = threadIdx.x; i < ss.w * 2; i += blockDim.x)
+      a.part_grad[((int64_t)blockIdx.y * a.n_conds + ss.z) * 2 + i] =
+          acc[(size_t)q * a.max_set_conds * 2 + i];
+  }
+}
+
+// Register-resident adjoint for rule sets of at most RMAX rules: S samples
+// per lane, and the only per-rule state kept between the two sweeps is
+// l_k = a_k + (survival before k), RMAX x S floats in VGPRs (read and
+// written through a uniform branch chain on k).  The reverse sweep
+// recomputes every condition once: the same exp/log gives the rule's a_k
+// and log(1 - r_k) for the U recurrence and log sigmoid(z) for the
+// gradient.  Per condition the S slots are summed in the lane, then over the
+// wave with DPP; lane 63 adds to the block's LDS accumulators (one writer per
+// rule set and tile).
+template <int K, int RMAX, int S>
+__device__ __forceinline__ void l_get(const float (&L)[RMAX][S], int k, float (&out)[S]) {
+  if constexpr (K < RMAX) {
+    if (k == K) {
+#pragma unroll
+      for (int s = 0; s < S; ++s) out[s] = L[K][s];
+    } else {
+      l_get<K + 1, RMAX, S>(L, k, out);
+    }
+  }
+}
+template <int K, int RMAX, int S>
+__device__ __forceinline__ void l_set(float (&L)[RMAX][S], int k, const float (&v)[S]) {
+  if constexpr (K < RMAX) {
+    if (k == K) {
+#pragma unroll
+      for (int s = 0; s < S; ++s) L[K][s] = v[s];
+    } else {
+      l_set<K + 1, RMAX, S>(L, k, v);
+    }
+  }
+}
+
+constexpr int kBwdRegBlock = 256;
+
+template <int S, int RMAX>
+__global__ __launch_bounds__(kBwdRegBlock) void k_soft_bwd_reg(const SoftArgs a) {
+  constexpr int TS = 64 * S, WPT = AERL_TILE / TS;
+  extern __shared__ __align__(16) float smem[];
+  float *xs = smem;                       // [nf][TS]
+  float *acc = xs + (size_t)a.nf * TS;    // [Q][max_set_conds][2]
+  __shared__ int32_t next_q;
+  const int lane = threadIdx.x & 63;
+  int label, tile_lo, tile_hi;
+  group_range(a, blockIdx.y, label, tile_lo, tile_hi);
+  const int q0 = blockIdx.x * a.sets_per_chunk;
+  const int Q = min(a.sets_per_chunk, a.n_sets - q0);
+  for (int i = threadIdx.x; i < Q * a.max_set_conds * 2; i += blockDim.x) acc[i] = 0.0f;
+  const int n4 = a.nf * (TS / 4);
+  const float4 *src = reinterpret_cast<const float4 *>(a.x_fm);
+  float4 *dst = reinterpret_cast<float4 *>(xs);
+  const int64_t row4 = a.n_pad / 4;
+  for (int64_t wt = (int64_t)tile_lo * WPT; wt < (int64_t)tile_hi * WPT; ++wt) {
+    __syncthreads();
+    const int64_t base4 = wt * (TS / 4);
+    for (int i = threadIdx.x; i < n4; i += blockDim.x) {
+      const int f = i / (TS / 4), k = i % (TS / 4);
+      dst[i] = src[(int64_t)f * row4 + base4 + k];
+    }
+    if (threadIdx.x == 0) next_q = 0;
+    __syncthreads();
+    const int info = ldc(a.tile_info, wt / WPT);
+    const int valid = min(max((info >> 8) - (int)(wt % WPT) * TS, 0), TS);
+    bool live[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) live[s] = lane * S + s < valid;
+    for (;;) {
+      const int q = next_item(&next_q);
+      if (q >= Q) break;
+      const int4 ss = ldc(a.ssets, q0 + q);
+      const int dflt = ldc(a.sets, q0 + q).z;
+      float L[RMAX][S];
+      float logpy[S], surv[S];
+#pragma unroll
+      for (int s = 0; s < S; ++s) { logpy[s] = kNegInf; surv[s] = 0.0f; }
+      // forward sweep
+      for (int k = 0; k < ss.y; ++k) {
+        const int4 r = ldc(a.rules, ss.x + k);
+        RuleAcc ra[S];
+        for (int j = r.x; j < r.x + r.y; ++j) {
+          float z[S], xf[S], xg[S];
+          bool ff;
+          cond_z<S>(a, xs, lane, j, z, xf, xg, ff);
+#pragma unroll
+          for (int s = 0; s < S; ++s) (void)ra[s].add(z[s]);
+        }
+        const bool hit = r.z == label;
+        float lk[S];
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          lk[s] = ra[s].a + surv[s];
+          if (hit) logpy[s] = lse(logpy[s], lk[s]);
+          surv[s] += rule_log_miss(ra[s]);
+        }
+        l_set<0, RMAX, S>(L, k, lk);
+      }
+      float gate[S], U[S];
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        if (dflt == label) logpy[s] = lse(logpy[s], surv[s]);
+        // samples whose loss is clamped (or padding) get no gradient
+        gate[s] = (live[s] && -logpy[s] <= kLossCap) ? 1.0f : 0.0f;
+        U[s] = dflt == label ? 0.0f : kNegInf;
+      }
+      // reverse sweep
+      for (int k = ss.y - 1; k >= 0; --k) {
+        const int4 r = ldc(a.rules, ss.x + k);
+        const bool hit = r.z == label;
+        float lk[S], pre[S], mul[S];
+        l_get<0, RMAX, S>(L, k, lk);
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          if (hit) {
+            pre[s] = lk[s] - logpy[s];
+            mul[s] = -one_minus_exp(U[s]) * gate[s];
+          } else {
+            pre[s] = lk[s] + U[s] - logpy[s];
+            mul[s] = gate[s];
+          }
+        }
+        RuleAcc ra[S];
+        for (int j = r.x; j < r.x + r.y; ++j) {
+          float z[S], xf[S], xg[S];
+          bool ff;
+          cond_z<S>(a, xs, lane, j, z, xf, xg, ff);
+          float g0 = 0.0f, g1 = 0.0f;
+#pragma unroll
+          for (int s = 0; s < S; ++s) {
+            const float e = pre[s] + (ra[s].add(z[s]) - z[s]);  // + log sigmoid(-z)
+            const float dz = (mul[s] != 0.0f && e > kNegInf) ? mul[s] * fexp(e) : 0.0f;
+            g0 += ff ? dz * xg[s] : dz;
+            g1 += dz * xf[s];
+          }
+          g0 = wave_total_last(g0);
+          g1 = wave_total_last(g1);
+          if (lane == 63) {
+            float *ap = acc + ((size_t)q * a.max_set_conds + (j - ss.z)) * 2;
+            ap[0] += g0;
+            ap[1] += g1;
+          }
+        }
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+          U[s] = lse(hit ? ra[s].a : kNegInf, rule_log_miss(ra[s]) + U[s]);
       }
     }
   }
@@ -384,6 +558,7 @@ __global__ void k_soft_bwd_final(const float *__restrict__ part, int32_t n_group
 
 struct SoftPlan {
   int S, Q, TG, n_groups;
+  int rmax;  // backward: rule bound of the register-resident kernel, 0 = general kernel
   size_t lds;
 };
 
@@ -407,17 +582,32 @@ SoftPlan plan_forward(const DatasetRec &ds, const PopRec &pop) {
   return p;
 }
 
+// Backward: the register-resident kernel when the longest rule set has at
+// most 32 rules (bound 8 or 16: four samples per lane; 32: two), else the
+// general kernel with per-rule state in LDS (one sample per lane).
 SoftPlan plan_backward(const DatasetRec &ds, const PopRec &pop) {
   SoftPlan p{};
-  p.S = 1;
-  const size_t xs = (size_t)ds.nf * 64 * 4;
-  const size_t per_wave = (size_t)std::max(pop.max_rules, 1) * 128 * 4;
+  const int R = std::max(pop.max_rules, 1);
   const size_t per_set = (size_t)std::max(pop.max_set_conds, 1) * 2 * 4;
-  p.Q = std::max(1, std::min(pop.n_sets, 16));
-  while (p.Q > 1 && xs + p.Q * per_set + kBwdWaves * per_wave > kDynLdsMax) p.Q >>= 1;
   p.TG = 1;
   while (count_groups(ds, p.TG) > kMaxGroups) p.TG *= 2;
   p.n_groups = (int)count_groups(ds, p.TG);
+  p.rmax = R <= 8 ? 8 : R <= 16 ? 16 : R <= 32 ? 32 : 0;
+  if (p.rmax > 0) {
+    p.S = p.rmax <= 16 ? 4 : 2;
+    while (p.S > 1 && (size_t)ds.nf * 256 * p.S > 64 * 1024) p.S >>= 1;
+    const size_t xs = (size_t)ds.nf * 64 * p.S * 4;
+    p.Q = std::max(1, std::min(pop.n_sets, 64));
+    while (p.Q > 1 && xs + p.Q * per_set > 80 * 1024) p.Q >>= 1;
+    p.lds = xs + (size_t)p.Q * per_set;
+    if (p.lds <= kDynLdsMax) return p;
+  }
+  p.rmax = 0;
+  p.S = 1;
+  const size_t xs = (size_t)ds.nf * 64 * 4;
+  const size_t per_wave = (size_t)R * 128 * 4;
+  p.Q = std::max(1, std::min(pop.n_sets, 16));
+  while (p.Q > 1 && xs + p.Q * per_set + kBwdWaves * per_wave > kDynLdsMax) p.Q >>= 1;
   p.lds = xs + (size_t)p.Q * per_set + kBwdWaves * per_wave;
   return p;
 }
@@ -453,6 +643,10 @@ void fill_args(SoftArgs &a, const SoftLaunch &l, const SoftPlan &p) {
 }
 
 }  // namespace
+
+bool soft_backward_supported(const DatasetRec &ds, const PopRec &pop) {
+  return plan_backward(ds, pop).lds <= kDynLdsMax;
+}
 
 size_t soft_ws_bytes(const DatasetRec &ds, const PopRec &pop, bool backward) {
   if (backward) {
@@ -495,7 +689,27 @@ hipError_t launch_soft_backward(const SoftLaunch &l, hipStream_t st) {
   a.part_grad = static_cast<float *>(l.ws);
   if (p.n_groups > 0) {
     const dim3 grid((unsigned)((pop.n_sets + p.Q - 1) / p.Q), (unsigned)p.n_groups);
-    hipLaunchKernelGGL(k_soft_bwd, grid, dim3(kBwdWaves * 64), p.lds, st, a);
+    const dim3 rb(kBwdRegBlock);
+    if (p.rmax == 8 && p.S == 4) {
+      hipLaunchKernelGGL((k_soft_bwd_reg<4, 8>), grid, rb, p.lds, st, a);
+    } else if (p.rmax == 8 && p.S == 2) {
+      hipLaunchKernelGGL((k_soft_bwd_reg<2, 8>), grid, rb, p.lds, st, a);
+    } else if (p.rmax == 16 && p.S == 4) {
+      hipLaunchKernelGGL((k_soft_bwd_reg<4, 16>), grid, rb, p.lds, st, a);
+    } else if (p.rmax == 16 && p.S == 2) {
+      hipLaunchKernelGGL((k_soft_bwd_reg<2, 16>), grid, rb, p.lds, st, a);
+    } else if (p.rmax == 32 && p.S == 2) {
+      hipLaunchKernelGGL((k_soft_bwd_reg<2, 32>), grid, rb, p.lds, st, a);
+    } else if (p.rmax > 0) {
+      // one sample per lane (wide datasets)
+      switch (p.rmax) {
+        case 8: hipLaunchKernelGGL((k_soft_bwd_reg<1, 8>), grid, rb, p.lds, st, a); break;
+        case 16: hipLaunchKernelGGL((k_soft_bwd_reg<1, 16>), grid, rb, p.lds, st, a); break;
+        default: hipLaunchKernelGGL((k_soft_bwd_reg<1, 32>), grid, rb, p.lds, st, a); break;
+      }
+    } else {
+      hipLaunchKernelGGL(k_soft_bwd, grid, dim3(kBwdWaves * 64), p.lds, st, a);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -88,6 +88,29 @@ def test_mixed_kinds_ops_and_classes(ctx, seed, nc):
     run_case(ctx, w.data, w.pop)
 
 
+@pytest.mark.parametrize("rules,nf", [((17, 32), 12), ((33, 36), 8), ((1, 8), 300),
+                                      ((9, 16), 100)])
+def test_every_adjoint_variant(ctx, rules, nf):
+    """Rule bounds 8/16/32 of the register-resident adjoint (4, 2 or 1
+    samples per lane by feature count) and the LDS-resident kernel beyond
+    32 rules."""
+    w = synth.tiny(70 + rules[0], n=1500, nf=nf, n_classes=3, n_sets=12, rules=rules,
+                   conds=(1, 3), ff_frac=0.3)
+    run_case(ctx, w.data, w.pop)
+
+
+def test_too_long_rule_sets_are_refused(ctx):
+    from paper_2406_01821_amd.aerl import AerlError, AERL_EINVAL
+    w = synth.tiny(90, n=300, nf=8, n_sets=2, rules=(64, 64), conds=(1, 2))
+    ds = ctx.upload_dataset(w.data)
+    p = ctx.pack_population(w.pop, 8, 2)
+    c1, c2, th = params(w.pop, ctx.device)
+    import torch
+    with pytest.raises(AerlError) as e:
+        ctx.soft_backward(ds, p, c1, c2, th, torch.ones(2, device=ctx.device))
+    assert e.value.status == AERL_EINVAL
+
+
 @pytest.mark.parametrize("n", [1, 63, 64, 65, 257, 1000])
 def test_ragged_sample_counts(ctx, n):
     w = synth.tiny(200 + n, n=n, nf=6, n_sets=10, rules=(1, 5), conds=(1, 3))
