@@ -34,74 +34,78 @@ namespace aerl {
 
 namespace {
 
+// Log-domain quantities inside the kernels are in bits (base-2 logs): the
+// hardware computes 2^x (v_exp_f32) and log2(x) (v_log_f32) directly, so the
+// inner loops carry no scaling multiplies.  A condition value is evaluated as
+// z2 = z * log2(e); the loss is converted back to nats at the end.
 constexpr float kLog2e = 1.4426950408889634f;
 constexpr float kLn2 = 0.6931471805599453f;
 constexpr float kNegInf = -__builtin_huge_valf();
-constexpr float kLossCap = 100.0f;
+constexpr float kLossCap = 100.0f;  // nats
 
-__device__ __forceinline__ float fexp(float x) { return __builtin_amdgcn_exp2f(x * kLog2e); }
-__device__ __forceinline__ float flog(float x) { return __builtin_amdgcn_logf(x) * kLn2; }
+__device__ __forceinline__ float fexp2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ float flog2(float x) { return __builtin_amdgcn_logf(x); }
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
-// log(1 + u) for u in [0, 1]: w = 1 + u is rounded; (w - 1) - u is that
-// rounding error exactly, which corrects log(w) to first order.
-__device__ __forceinline__ float log1p_unit(float u) {
+// log2(1 + u) for u in [0, 1]: w = 1 + u is rounded; (w - 1) - u is that
+// rounding error exactly, which corrects log2(w) to first order.
+__device__ __forceinline__ float log2_1p_unit(float u) {
   const float w = 1.0f + u;
-  return flog(w) - ((w - 1.0f) - u);
+  return fmaf(-((w - 1.0f) - u), kLog2e, flog2(w));
 }
 
-// log(sigmoid(z)) = -(max(-z, 0) + log1p(exp(-|z|))).
-__device__ __forceinline__ float log_sigmoid(float z) {
-  return -(fmaxf(-z, 0.0f) + log1p_unit(fexp(-fabsf(z))));
-}
-
-// Per-rule accumulator of the soft truth: a = log r = sum_j log sigmoid(z_j),
-// and us = sum_j exp(kShift - |z_j|).  When every condition holds strongly, a
-// is so close to 0 that fp32 cannot carry -a (it underflows near e^-87), yet
-// log(1 - r) ~ log(sum_j exp(-z_j)) still matters down to the e^-100 loss
-// clamp; the shifted sum keeps it (normal floats down to z ~ 150).
-constexpr float kShift = 64.0f;
-constexpr float kExpNegShift = 1.60381089e-28f;  // e^-64
+// Per-rule accumulator of the soft truth: a = log2 r = sum_j log2 sigmoid(z_j),
+// and us = sum_j 2^(kShift2 - |z2_j|).  When every condition holds strongly,
+// a is so close to 0 that fp32 cannot carry -a (it underflows near 2^-126),
+// yet log(1 - r) ~ log(sum_j e^-z_j) still matters down to the loss clamp
+// (e^-100); the shifted sum keeps it (normal floats down to z ~ 150).  The
+// shift is a power of two, so unscaling it is exact.
+constexpr float kShift2 = 92.0f;
+constexpr float kExp2NegShift = 0x1p-92f;
 struct RuleAcc {
   float a = 0.0f, us = 0.0f;
-  // Adds condition value z; returns its log sigmoid(z).
-  __device__ __forceinline__ float add(float z) {
-    const float az = fabsf(z);
-    const float e_s = fexp(kShift - az);  // e^(64 - |z|)
-    const float nl = fmaxf(-z, 0.0f) + log1p_unit(e_s * kExpNegShift);  // -log sigmoid(z)
-    a -= nl;
+  // Adds condition value z2; returns log2(1 + 2^-|z2|), from which
+  // -log2 sigmoid(+-z) = max(-+z2, 0) + that.
+  __device__ __forceinline__ float add(float z2) {
+    const float e_s = fexp2(kShift2 - fabsf(z2));
+    const float lp = log2_1p_unit(e_s * kExp2NegShift);
+    a -= fmaxf(-z2, 0.0f) + lp;
     us += e_s;
-    return -nl;
+    return lp;
   }
 };
 
-// -expm1(a) = 1 - exp(a) for a <= 0.  Near 0 uses Kahan's form
-// (u - 1) * a / log(u) with u = exp(a), which cancels the rounding of u.
-__device__ __forceinline__ float one_minus_exp(float a) {
-  const float u = fexp(a);
-  if (a > -kLn2) {
-    const float lu = flog(u);
-    const float em1 = (u == 1.0f) ? a : (u - 1.0f) * (a * frcp(lu));
+// 1 - 2^a for a <= 0 (bits).  Near 0 uses Kahan's form of expm1,
+// 2^a - 1 = (u - 1) * a / log2(u) with u = 2^a, which cancels the rounding
+// of u.
+__device__ __forceinline__ float one_minus_exp2(float a) {
+  const float u = fexp2(a);
+  if (a > -1.0f) {
+    const float lu = flog2(u);
+    const float em1 = (u == 1.0f) ? a * kLn2 : (u - 1.0f) * (a * frcp(lu));
     return -em1;
   }
   return 1.0f - u;
 }
 
-// log(1 - exp(a)) for a <= 0 (a = 0 gives -inf).
-__device__ __forceinline__ float log1mexp(float a) { return flog(one_minus_exp(a)); }
+// log2(1 - 2^a) for a <= 0 (a = 0 gives -inf).
+__device__ __forceinline__ float log1mexp2(float a) { return flog2(one_minus_exp2(a)); }
 
-// log(1 - r) of a rule: from a while fp32 represents -a well, otherwise from
-// the shifted sum (there 1 - r = sum_j exp(-z_j) to within a relative 1e-30).
+// log2(1 - r) of a rule: from a while fp32 represents -a well, otherwise from
+// the shifted sum (there 1 - r = sum_j e^-z_j to within a relative 1e-30).
 __device__ __forceinline__ float rule_log_miss(const RuleAcc &r) {
-  return r.a > -1e-30f ? flog(r.us) - kShift : log1mexp(r.a);
+  return r.a > -1e-30f ? flog2(r.us) - kShift2 : log1mexp2(r.a);
 }
 
-// log(exp(p) + exp(q)), -inf safe.
+// log2(2^p + 2^q), -inf safe.
 __device__ __forceinline__ float lse(float p, float q) {
   const float m = fmaxf(p, q);
   if (m == kNegInf) return kNegInf;
-  return m + log1p_unit(fexp(-fabsf(p - q)));
+  return m + log2_1p_unit(fexp2(-fabsf(p - q)));
 }
+
+// Loss of one sample in nats from log2 P_y.
+__device__ __forceinline__ float sample_loss(float logpy2) { return fminf(-logpy2 * kLn2, kLossCap); }
 
 // Sum of v over the wave, left in lane 63: an inclusive scan inside each
 // 16-lane row (row_shr 1, 2, 4, 8), then the row totals carried forward
@@ -162,29 +166,53 @@ __device__ __forceinline__ void group_range(const SoftArgs &a, int g, int &label
   }
 }
 
-// z of condition j for S values of x[f] (and x[g] for feature conditions).
+// z2 = z*log2(e) of condition j for S values of x[f], with x[f] and the
+// right-hand factor xg: x[g] for feature conditions, 1 for threshold ones (so
+// dz*xg is their theta term).  Branch-free on the kind (the row of g is read
+// for threshold conditions too; g is 0 there), which keeps every array in
+// registers.
 template <int S>
 __device__ __forceinline__ void cond_z(const SoftArgs &a, const float *xs, int lane, int j,
                                        float (&z)[S], float (&xf)[S], float (&xg)[S], bool &ff) {
   const uint32_t sc = ldc(a.sconds, j);
   const uint32_t f = sc & 0xfffu, g = (sc >> 12) & 0xfffu;
   ff = ((sc >> 24) & 1u) != 0;
-  const float inv = ldc(a.inv_tau, f);
+  const float inv = ldc(a.inv_tau, f) * kLog2e;
   const float sinv = ((sc >> 25) & 1u) ? inv : -inv;
   const float c = ldc(a.coef, j);
+  const float c2 = ldc(a.coef2, j);
+  const float th = ldc(a.theta, j);
   load_row<S>(xs, f * 1024u, lane, xf);
-  if (ff) {
+  load_row<S>(xs, g * 1024u, lane, xg);
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const float rhs = ff ? c2 * xg[s] : th;
+    xg[s] = ff ? xg[s] : 1.0f;
+    z[s] = fmaf(c, xf[s], -rhs) * sinv;
+  }
+}
+
+// z2 only (forward pass): nothing but z leaves the branch on the kind.
+template <int S>
+__device__ __forceinline__ void cond_z_only(const SoftArgs &a, const float *xs, int lane, int j,
+                                            float (&z)[S]) {
+  const uint32_t sc = ldc(a.sconds, j);
+  const uint32_t f = sc & 0xfffu, g = (sc >> 12) & 0xfffu;
+  const float inv = ldc(a.inv_tau, f) * kLog2e;
+  const float sinv = ((sc >> 25) & 1u) ? inv : -inv;
+  const float c = ldc(a.coef, j);
+  float xf[S];
+  load_row<S>(xs, f * 1024u, lane, xf);
+  if ((sc >> 24) & 1u) {
     const float c2 = ldc(a.coef2, j);
+    float xg[S];
     load_row<S>(xs, g * 1024u, lane, xg);
 #pragma unroll
     for (int s = 0; s < S; ++s) z[s] = fmaf(c, xf[s], -(c2 * xg[s])) * sinv;
   } else {
     const float th = ldc(a.theta, j);
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
-      z[s] = fmaf(c, xf[s], -th) * sinv;
-      xg[s] = 0.0f;
-    }
+    for (int s = 0; s < S; ++s) z[s] = fmaf(c, xf[s], -th) * sinv;
   }
 }
 
@@ -234,9 +262,8 @@ __global__ __launch_bounds__(kSoftBlock) void k_soft_fwd(const SoftArgs a) {
         const int4 r = ldc(a.rules, ss.x + k);
         RuleAcc ra[S];
         for (int j = r.x; j < r.x + r.y; ++j) {
-          float z[S], xf[S], xg[S];
-          bool ff;
-          cond_z<S>(a, xs, lane, j, z, xf, xg, ff);
+          float z[S];
+          cond_z_only<S>(a, xs, lane, j, z);
 #pragma unroll
           for (int s = 0; s < S; ++s) ra[s].add(z[s]);
         }
@@ -251,7 +278,7 @@ __global__ __launch_bounds__(kSoftBlock) void k_soft_fwd(const SoftArgs a) {
 #pragma unroll
       for (int s = 0; s < S; ++s) {
         const float lp = dflt == label ? lse(logpy[s], surv[s]) : logpy[s];
-        part += live[s] ? fminf(-lp, kLossCap) : 0.0f;
+        part += live[s] ? sample_loss(lp) : 0.0f;
       }
       part = wave_sum(part);
       if (lane == 0) acc[q] += (double)part;
@@ -315,9 +342,8 @@ __global__ __launch_bounds__(kBwdWaves * 64) void k_soft_bwd(const SoftArgs a) {
         const int4 r = ldc(a.rules, ss.x + k);
         RuleAcc ra;
         for (int j = r.x; j < r.x + r.y; ++j) {
-          float z[1], xf[1], xg[1];
-          bool ff;
-          cond_z<1>(a, xs, lane, j, z, xf, xg, ff);
+          float z[1];
+          cond_z_only<1>(a, xs, lane, j, z);
           ra.add(z[0]);
         }
         my[k * 128 + lane] = ra.a;
@@ -326,8 +352,11 @@ __global__ __launch_bounds__(kBwdWaves * 64) void k_soft_bwd(const SoftArgs a) {
         surv += rule_log_miss(ra);
       }
       if (dflt == label) logpy = lse(logpy, surv);
-      // samples whose loss is clamped (or padding) get no gradient
-      const float gate = (live && -logpy <= kLossCap) ? 1.0f : 0.0f;
+      // samples whose loss is clamped (or padding) get no gradient; their
+      // log P_y is replaced by 0 so that every exponent below stays finite
+      const bool on = live && -logpy * kLn2 <= kLossCap;
+      const float gate = on ? 1.0f : 0.0f;
+      const float lpy = on ? logpy : 0.0f;
       // reverse sweep
       float U = dflt == label ? 0.0f : kNegInf;
       for (int k = ss.y - 1; k >= 0; --k) {
@@ -337,10 +366,10 @@ __global__ __launch_bounds__(kBwdWaves * 64) void k_soft_bwd(const SoftArgs a) {
         const bool hit = r.z == label;
         float pre, mul;
         if (hit) {
-          pre = lk - logpy;
-          mul = -one_minus_exp(U) * gate;
+          pre = lk - lpy;
+          mul = -one_minus_exp2(U) * gate;
         } else {
-          pre = lk + U - logpy;
+          pre = lk + U - lpy;
           mul = gate;
         }
         RuleAcc ra;
@@ -348,10 +377,10 @@ __global__ __launch_bounds__(kBwdWaves * 64) void k_soft_bwd(const SoftArgs a) {
           float z[1], xf[1], xg[1];
           bool ff;
           cond_z<1>(a, xs, lane, j, z, xf, xg, ff);
-          const float lsn = ra.add(z[0]) - z[0];  // log sigmoid(-z)
-          const float e = pre + lsn;
-          const float dz = (mul != 0.0f && e > kNegInf) ? mul * fexp(e) : 0.0f;
-          const float g0 = wave_sum(ff ? dz * xg[0] : dz);
+          const float lp = ra.add(z[0]);
+          // dL/dz = dL/da_k * sigmoid(-z), one exponent in bits
+          const float dz = mul * fexp2(pre - (fmaxf(z[0], 0.0f) + lp));
+          const float g0 = wave_sum(dz * xg[0]);
           const float g1 = wave_sum(dz * xf[0]);
           if (lane == 0) {
             float *ap = acc + ((size_t)q * a.max_set_conds + (j - ss.z)) * 2;
@@ -451,9 +480,8 @@ __global__ __launch_bounds__(kBwdRegBlock) void k_soft_bwd_reg(const SoftArgs a)
         const int4 r = ldc(a.rules, ss.x + k);
         RuleAcc ra[S];
         for (int j = r.x; j < r.x + r.y; ++j) {
-          float z[S], xf[S], xg[S];
-          bool ff;
-          cond_z<S>(a, xs, lane, j, z, xf, xg, ff);
+          float z[S];
+          cond_z_only<S>(a, xs, lane, j, z);
 #pragma unroll
           for (int s = 0; s < S; ++s) (void)ra[s].add(z[s]);
         }
@@ -471,8 +499,11 @@ __global__ __launch_bounds__(kBwdRegBlock) void k_soft_bwd_reg(const SoftArgs a)
 #pragma unroll
       for (int s = 0; s < S; ++s) {
         if (dflt == label) logpy[s] = lse(logpy[s], surv[s]);
-        // samples whose loss is clamped (or padding) get no gradient
-        gate[s] = (live[s] && -logpy[s] <= kLossCap) ? 1.0f : 0.0f;
+        // samples whose loss is clamped (or padding) get no gradient; their
+        // log P_y is replaced by 0 so that every exponent below stays finite
+        const bool on = live[s] && -logpy[s] * kLn2 <= kLossCap;
+        gate[s] = on ? 1.0f : 0.0f;
+        logpy[s] = on ? logpy[s] : 0.0f;
         U[s] = dflt == label ? 0.0f : kNegInf;
       }
       // reverse sweep
@@ -485,7 +516,7 @@ __global__ __launch_bounds__(kBwdRegBlock) void k_soft_bwd_reg(const SoftArgs a)
         for (int s = 0; s < S; ++s) {
           if (hit) {
             pre[s] = lk[s] - logpy[s];
-            mul[s] = -one_minus_exp(U[s]) * gate[s];
+            mul[s] = -one_minus_exp2(U[s]) * gate[s];
           } else {
             pre[s] = lk[s] + U[s] - logpy[s];
             mul[s] = gate[s];
@@ -499,17 +530,19 @@ __global__ __launch_bounds__(kBwdRegBlock) void k_soft_bwd_reg(const SoftArgs a)
           float g0 = 0.0f, g1 = 0.0f;
 #pragma unroll
           for (int s = 0; s < S; ++s) {
-            const float e = pre[s] + (ra[s].add(z[s]) - z[s]);  // + log sigmoid(-z)
-            const float dz = (mul[s] != 0.0f && e > kNegInf) ? mul[s] * fexp(e) : 0.0f;
-            g0 += ff ? dz * xg[s] : dz;
-            g1 += dz * xf[s];
+            const float lp = ra[s].add(z[s]);
+            // dL/dz = dL/da_k * sigmoid(-z), one exponent in bits
+            const float dz = mul[s] * fexp2(pre[s] - (fmaxf(z[s], 0.0f) + lp));
+            g0 = fmaf(dz, xg[s], g0);
+            g1 = fmaf(dz, xf[s], g1);
           }
           g0 = wave_total_last(g0);
           g1 = wave_total_last(g1);
           if (lane == 63) {
+            // one writer per (rule set, tile): the order of these adds is fixed
             float *ap = acc + ((size_t)q * a.max_set_conds + (j - ss.z)) * 2;
-            ap[0] += g0;
-            ap[1] += g1;
+            atomicAdd(ap, g0);
+            atomicAdd(ap + 1, g1);
           }
         }
 #pragma unroll
