@@ -244,7 +244,7 @@ typedef struct {
  * takes 4, 2 or 1 samples per lane, the most whose 64-lane tile of all its
  * features fits the budget; above 80 only one block fits a CU).  0 in a
  * field asks for the library's choice (the tuned one when aerl_autotune has
- * seen a batch of this shape, else 64 sets, 4 tiles, 64 KiB). */
+ * seen a batch of this shape, else 512 sets, 1 tile, 64 KiB). */
 typedef struct {
   int32_t sets_per_task;
   int32_t tiles_per_task;

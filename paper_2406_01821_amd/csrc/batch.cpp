@@ -208,7 +208,7 @@ void load_tune_file(aerl_ctx *ctx) {
 // batch shape or the defaults.
 aerl_status resolve_split(aerl_ctx *ctx, const std::vector<ItemView> &v, const aerl_batch_cfg *cfg,
                           BatchSplit *sp) {
-  std::array<int32_t, 3> d = {64, 4, 64};
+  std::array<int32_t, 3> d = {512, 1, 64};
   load_tune_file(ctx);
   auto it = ctx->tuned.find(shape_key(v));
   if (it != ctx->tuned.end()) d = it->second;
@@ -345,8 +345,8 @@ aerl_status aerl_autotune(aerl_ctx *ctx, const aerl_batch_item *items, int32_t n
   aerl_status st = gather(ctx, items, n_items, &v);
   if (st) return st;
   AERL_HIP(ctx, hipSetDevice(ctx->device));
-  static const int32_t kQ[] = {16, 32, 64, 128};
-  static const int32_t kTG[] = {1, 2, 4, 8, 16};
+  static const int32_t kQ[] = {64, 128, 256, 512, 1024, 2048};
+  static const int32_t kTG[] = {1, 2, 4, 8};
   static const int32_t kKiB[] = {64, 128};
   hipEvent_t e0, e1;
   AERL_HIP(ctx, hipEventCreate(&e0));

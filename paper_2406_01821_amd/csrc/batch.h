@@ -42,7 +42,7 @@ constexpr size_t kBatchLdsMax = kDynLdsMax;
 // Work split: rule sets and layout tiles per work item, and the LDS budget
 // of a block's feature tile.
 struct BatchSplit {
-  int32_t Q = 64, TG = 4;
+  int32_t Q = 512, TG = 1;
   size_t tile_budget = 64 * 1024;
 };
 

@@ -62,25 +62,22 @@ struct Pinned {
   ~Pinned() { if (p) (void)hipHostFree(p); }
 };
 
-// Launch configuration of the plain hard-eval path.
+// Launch configuration of the plain hard-eval path.  Large set chunks (up to
+// 2048 rule sets per block) over single tiles: every staged tile serves many
+// rule sets, so the per-tile barrier and the restaging of the dataset per
+// chunk are amortized; chunks shrink only when the grid would be too small
+// to fill the GPU or their counters do not fit in LDS.
 void hard_config(const DatasetRec &ds, int32_t n_sets, int n_cu, int *S, int *Q, int *TG) {
-  const int64_t tiles = ds.n_tiles;
   int s = 4;
   while (s > 1 && (size_t)ds.nf * 256 * s > 150 * 1024) s >>= 1;
   *S = s;
-  const int64_t target = 8LL * n_cu;
-  int q = (int)std::min<int64_t>(std::max<int32_t>(n_sets, 1), 256);
-  auto blocks = [&](int qq, int64_t tg) {
-    int64_t g = 0;
-    for (int c = 0; c < ds.nc; ++c) g += (ds.region_tiles[c] + tg - 1) / tg;
-    return ((n_sets + qq - 1) / qq) * g;
-  };
-  while (q > 16 && blocks(q, 1) < target) q >>= 1;
-  while (q > 1 && (size_t)ds.nf * 64 * s * 4 + (size_t)q * ds.nc * 4 > kDynLdsMax) q >>= 1;
-  int64_t tg = 1;
-  while (tg * 2 <= tiles && blocks(q, tg * 2) >= target) tg *= 2;
+  const int64_t tiles = std::max<int64_t>(ds.n_tiles, 1);
+  const int64_t target = 4LL * n_cu;
+  int q = (int)std::min<int64_t>(std::max<int32_t>(n_sets, 1), 2048);
+  while (q > 1 && (size_t)ds.nf * 64 * s * 4 + (size_t)q * ds.nc * 4 > kDynLdsMax) q = (q + 1) / 2;
+  while (q > 64 && ((n_sets + q - 1) / q) * tiles < target) q = (q + 1) / 2;
   *Q = q;
-  *TG = (int)tg;
+  *TG = 1;
 }
 
 }  // namespace

@@ -28,7 +28,7 @@ using Clock = std::chrono::steady_clock;
 
 namespace {
 
-const BatchSplit kServeSplit{};  // 64 rule sets x 4 tiles per work item, 64 KiB tiles
+const BatchSplit kServeSplit{512, 2, 64 * 1024};  // rule sets, tiles per work item; tile LDS
 constexpr size_t kTableSlack = 16 * 256;  // alignment padding of the per-launch tables
 constexpr size_t kInitialPinned = 4u << 20;
 

@@ -104,6 +104,67 @@ __device__ __forceinline__ float lse(float p, float q) {
   return m + log2_1p_unit(fexp2(-fabsf(p - q)));
 }
 
+// Interface shared by the two accumulators below:
+//   add(z2)                 adds a condition, returns a per-condition value t
+//   sig_neg(pre, z2, t)     2^pre * sigmoid(-z) for that condition
+//   finish(a2, b2)          a2 = log2 r, b2 = log2(1 - r) of the rule
+__device__ __forceinline__ void acc_finish(const RuleAcc &r, float &a2, float &b2) {
+  a2 = r.a;
+  b2 = rule_log_miss(r);
+}
+__device__ __forceinline__ float acc_sig_neg(const RuleAcc &, float pre, float z2, float lp) {
+  return fexp2(pre - (fmaxf(z2, 0.0f) + lp));
+}
+
+// log2(1 + p) for any p >= 0 (first-order correction of the rounding of
+// w = 1 + p, as in log2_1p_unit).
+__device__ __forceinline__ float log2_1p(float p) {
+  const float w = 1.0f + p;
+  return fmaf(-((w - 1.0f) - p) * frcp(w), kLog2e, flog2(w));
+}
+
+// Product form of a rule's soft truth, for rules of at most kProdMaxConds
+// conditions.  With u_j = e^-|z_j| and M = sum_j max(-z_j, 0),
+//   r = e^-M / prod_j (1 + u_j),  p = prod_j (1 + u_j) - 1 >= 0,
+//   log r = -M - log1p(p),  1 - r = (p + (1 - e^-M)) / (1 + p),
+// and p is built by p <- p + u + p*u, a sum of non-negative terms, so it
+// keeps full relative accuracy (also when r is within e^-100 of 1) with one
+// exponential per condition; the logarithms are taken once per rule.  p is
+// kept scaled by 2^64 (pt), so that u down to 2^-190 stays a normal float;
+// with at most 60 conditions pt < 2^124.
+constexpr int kProdMaxConds = 60;
+struct RuleProd {
+  float m = 0.0f, pt = 0.0f;  // m = M in bits, pt = p * 2^64
+  __device__ __forceinline__ float add(float z2) {
+    const float ut = fexp2(64.0f - fabsf(z2));  // u * 2^64
+    const float u = ut * 0x1p-64f;
+    pt = fmaf(pt, u, pt + ut);
+    m += fmaxf(-z2, 0.0f);
+    return u;
+  }
+};
+// log2(x * 2^-64) for x >= 0, from the exact exponent and the mantissa, so
+// that a result near -64 carries no rounding of 64.
+__device__ __forceinline__ float log2_scaled64(float x) {
+  const float mant = __builtin_amdgcn_frexp_mantf(x);  // [0.5, 1), or 0
+  const int e = __builtin_amdgcn_frexp_expf(x);
+  return flog2(mant) + (float)(e - 64);
+}
+
+// a2 = log2 r = -M - log2(1 + p) is accurate in every regime.  b2 = log2(1 - r)
+// follows from a2 while r is not within 2^-60 of 1; closer than that, from
+// 1 - r = (p + (1 - e^-M)) / (1 + p) with p kept scaled (p may be far below
+// the normal range there).
+__device__ __forceinline__ void acc_finish(const RuleProd &r, float &a2, float &b2) {
+  const float l1p = log2_1p(r.pt * 0x1p-64f);
+  a2 = -r.m - l1p;
+  b2 = a2 > -0x1p-60f ? log2_scaled64(fmaf(one_minus_exp2(-r.m), 0x1p64f, r.pt)) - l1p
+                       : log1mexp2(a2);
+}
+__device__ __forceinline__ float acc_sig_neg(const RuleProd &, float pre, float z2, float u) {
+  return fexp2(pre - fmaxf(z2, 0.0f)) * frcp(1.0f + u);
+}
+
 // Loss of one sample in nats from log2 P_y.
 __device__ __forceinline__ float sample_loss(float logpy2) { return fminf(-logpy2 * kLn2, kLossCap); }
 
@@ -219,7 +280,7 @@ __device__ __forceinline__ void cond_z_only(const SoftArgs &a, const float *xs, 
 constexpr int kSoftBlock = 512;
 
 // ------------------------------------------------------------------ forward
-template <int S>
+template <int S, class Acc>
 __global__ __launch_bounds__(kSoftBlock) void k_soft_fwd(const SoftArgs a) {
   constexpr int TS = 64 * S, WPT = AERL_TILE / TS;
   extern __shared__ __align__(16) float smem[];
@@ -260,18 +321,20 @@ __global__ __launch_bounds__(kSoftBlock) void k_soft_fwd(const SoftArgs a) {
       for (int s = 0; s < S; ++s) { logpy[s] = kNegInf; surv[s] = 0.0f; }
       for (int k = 0; k < ss.y; ++k) {
         const int4 r = ldc(a.rules, ss.x + k);
-        RuleAcc ra[S];
+        Acc ra[S];
         for (int j = r.x; j < r.x + r.y; ++j) {
           float z[S];
           cond_z_only<S>(a, xs, lane, j, z);
 #pragma unroll
-          for (int s = 0; s < S; ++s) ra[s].add(z[s]);
+          for (int s = 0; s < S; ++s) (void)ra[s].add(z[s]);
         }
         const bool hit = r.z == label;
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-          if (hit) logpy[s] = lse(logpy[s], ra[s].a + surv[s]);
-          surv[s] += rule_log_miss(ra[s]);
+          float a2, b2;
+          acc_finish(ra[s], a2, b2);
+          if (hit) logpy[s] = lse(logpy[s], a2 + surv[s]);
+          surv[s] += b2;
         }
       }
       float part = 0.0f;
@@ -435,7 +498,7 @@ __device__ __forceinline__ void l_set(float (&L)[RMAX][S], int k, const float (&
 
 constexpr int kBwdRegBlock = 256;
 
-template <int S, int RMAX>
+template <int S, int RMAX, class Acc>
 __global__ __launch_bounds__(kBwdRegBlock) void k_soft_bwd_reg(const SoftArgs a) {
   constexpr int TS = 64 * S, WPT = AERL_TILE / TS;
   extern __shared__ __align__(16) float smem[];
@@ -478,7 +541,7 @@ __global__ __launch_bounds__(kBwdRegBlock) void k_soft_bwd_reg(const SoftArgs a)
       // forward sweep
       for (int k = 0; k < ss.y; ++k) {
         const int4 r = ldc(a.rules, ss.x + k);
-        RuleAcc ra[S];
+        Acc ra[S];
         for (int j = r.x; j < r.x + r.y; ++j) {
           float z[S];
           cond_z_only<S>(a, xs, lane, j, z);
@@ -489,9 +552,11 @@ __global__ __launch_bounds__(kBwdRegBlock) void k_soft_bwd_reg(const SoftArgs a)
         float lk[S];
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-          lk[s] = ra[s].a + surv[s];
+          float a2, b2;
+          acc_finish(ra[s], a2, b2);
+          lk[s] = a2 + surv[s];
           if (hit) logpy[s] = lse(logpy[s], lk[s]);
-          surv[s] += rule_log_miss(ra[s]);
+          surv[s] += b2;
         }
         l_set<0, RMAX, S>(L, k, lk);
       }
@@ -522,7 +587,7 @@ __global__ __launch_bounds__(kBwdRegBlock) void k_soft_bwd_reg(const SoftArgs a)
             mul[s] = gate[s];
           }
         }
-        RuleAcc ra[S];
+        Acc ra[S];
         for (int j = r.x; j < r.x + r.y; ++j) {
           float z[S], xf[S], xg[S];
           bool ff;
@@ -530,9 +595,9 @@ __global__ __launch_bounds__(kBwdRegBlock) void k_soft_bwd_reg(const SoftArgs a)
           float g0 = 0.0f, g1 = 0.0f;
 #pragma unroll
           for (int s = 0; s < S; ++s) {
-            const float lp = ra[s].add(z[s]);
-            // dL/dz = dL/da_k * sigmoid(-z), one exponent in bits
-            const float dz = mul[s] * fexp2(pre[s] - (fmaxf(z[s], 0.0f) + lp));
+            const float t = ra[s].add(z[s]);
+            // dL/dz = dL/da_k * sigmoid(-z)
+            const float dz = mul[s] * acc_sig_neg(ra[s], pre[s], z[s], t);
             g0 = fmaf(dz, xg[s], g0);
             g1 = fmaf(dz, xf[s], g1);
           }
@@ -546,8 +611,11 @@ __global__ __launch_bounds__(kBwdRegBlock) void k_soft_bwd_reg(const SoftArgs a)
           }
         }
 #pragma unroll
-        for (int s = 0; s < S; ++s)
-          U[s] = lse(hit ? ra[s].a : kNegInf, rule_log_miss(ra[s]) + U[s]);
+        for (int s = 0; s < S; ++s) {
+          float a2, b2;
+          acc_finish(ra[s], a2, b2);
+          U[s] = lse(hit ? a2 : kNegInf, b2 + U[s]);
+        }
       }
     }
   }
@@ -675,6 +743,37 @@ void fill_args(SoftArgs &a, const SoftLaunch &l, const SoftPlan &p) {
   }
 }
 
+template <class Acc>
+void launch_fwd(const SoftPlan &p, dim3 grid, hipStream_t st, const SoftArgs &a) {
+  switch (p.S) {
+    case 4: hipLaunchKernelGGL((k_soft_fwd<4, Acc>), grid, dim3(kSoftBlock), p.lds, st, a); break;
+    case 2: hipLaunchKernelGGL((k_soft_fwd<2, Acc>), grid, dim3(kSoftBlock), p.lds, st, a); break;
+    default: hipLaunchKernelGGL((k_soft_fwd<1, Acc>), grid, dim3(kSoftBlock), p.lds, st, a); break;
+  }
+}
+
+template <class Acc>
+void launch_bwd_reg(const SoftPlan &p, dim3 grid, hipStream_t st, const SoftArgs &a) {
+  const dim3 rb(kBwdRegBlock);
+  if (p.rmax == 8 && p.S == 4) {
+    hipLaunchKernelGGL((k_soft_bwd_reg<4, 8, Acc>), grid, rb, p.lds, st, a);
+  } else if (p.rmax == 8 && p.S == 2) {
+    hipLaunchKernelGGL((k_soft_bwd_reg<2, 8, Acc>), grid, rb, p.lds, st, a);
+  } else if (p.rmax == 16 && p.S == 4) {
+    hipLaunchKernelGGL((k_soft_bwd_reg<4, 16, Acc>), grid, rb, p.lds, st, a);
+  } else if (p.rmax == 16 && p.S == 2) {
+    hipLaunchKernelGGL((k_soft_bwd_reg<2, 16, Acc>), grid, rb, p.lds, st, a);
+  } else if (p.rmax == 32 && p.S == 2) {
+    hipLaunchKernelGGL((k_soft_bwd_reg<2, 32, Acc>), grid, rb, p.lds, st, a);
+  } else if (p.rmax == 8) {  // one sample per lane (wide datasets)
+    hipLaunchKernelGGL((k_soft_bwd_reg<1, 8, Acc>), grid, rb, p.lds, st, a);
+  } else if (p.rmax == 16) {
+    hipLaunchKernelGGL((k_soft_bwd_reg<1, 16, Acc>), grid, rb, p.lds, st, a);
+  } else {
+    hipLaunchKernelGGL((k_soft_bwd_reg<1, 32, Acc>), grid, rb, p.lds, st, a);
+  }
+}
+
 }  // namespace
 
 bool soft_backward_supported(const DatasetRec &ds, const PopRec &pop) {
@@ -699,10 +798,10 @@ hipError_t launch_soft_forward(const SoftLaunch &l, hipStream_t st) {
   a.part_loss = static_cast<double *>(l.ws);
   if (p.n_groups > 0) {
     const dim3 grid((unsigned)((pop.n_sets + p.Q - 1) / p.Q), (unsigned)p.n_groups);
-    switch (p.S) {
-      case 4: hipLaunchKernelGGL(k_soft_fwd<4>, grid, dim3(kSoftBlock), p.lds, st, a); break;
-      case 2: hipLaunchKernelGGL(k_soft_fwd<2>, grid, dim3(kSoftBlock), p.lds, st, a); break;
-      default: hipLaunchKernelGGL(k_soft_fwd<1>, grid, dim3(kSoftBlock), p.lds, st, a); break;
+    if (pop.max_rule_conds <= kProdMaxConds) {
+      launch_fwd<RuleProd>(p, grid, st, a);
+    } else {
+      launch_fwd<RuleAcc>(p, grid, st, a);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -722,24 +821,10 @@ hipError_t launch_soft_backward(const SoftLaunch &l, hipStream_t st) {
   a.part_grad = static_cast<float *>(l.ws);
   if (p.n_groups > 0) {
     const dim3 grid((unsigned)((pop.n_sets + p.Q - 1) / p.Q), (unsigned)p.n_groups);
-    const dim3 rb(kBwdRegBlock);
-    if (p.rmax == 8 && p.S == 4) {
-      hipLaunchKernelGGL((k_soft_bwd_reg<4, 8>), grid, rb, p.lds, st, a);
-    } else if (p.rmax == 8 && p.S == 2) {
-      hipLaunchKernelGGL((k_soft_bwd_reg<2, 8>), grid, rb, p.lds, st, a);
-    } else if (p.rmax == 16 && p.S == 4) {
-      hipLaunchKernelGGL((k_soft_bwd_reg<4, 16>), grid, rb, p.lds, st, a);
-    } else if (p.rmax == 16 && p.S == 2) {
-      hipLaunchKernelGGL((k_soft_bwd_reg<2, 16>), grid, rb, p.lds, st, a);
-    } else if (p.rmax == 32 && p.S == 2) {
-      hipLaunchKernelGGL((k_soft_bwd_reg<2, 32>), grid, rb, p.lds, st, a);
+    if (p.rmax > 0 && pop.max_rule_conds <= kProdMaxConds) {
+      launch_bwd_reg<RuleProd>(p, grid, st, a);
     } else if (p.rmax > 0) {
-      // one sample per lane (wide datasets)
-      switch (p.rmax) {
-        case 8: hipLaunchKernelGGL((k_soft_bwd_reg<1, 8>), grid, rb, p.lds, st, a); break;
-        case 16: hipLaunchKernelGGL((k_soft_bwd_reg<1, 16>), grid, rb, p.lds, st, a); break;
-        default: hipLaunchKernelGGL((k_soft_bwd_reg<1, 32>), grid, rb, p.lds, st, a); break;
-      }
+      launch_bwd_reg<RuleAcc>(p, grid, st, a);
     } else {
       hipLaunchKernelGGL(k_soft_bwd, grid, dim3(kBwdWaves * 64), p.lds, st, a);
     }

@@ -193,7 +193,7 @@ def test_autotune_picks_a_candidate_and_plans_use_it(ctx, runs):
     items = make_items(ctx, devs)
     ws = ctx.batch_workspace(items, (1, 1))
     (q, tg, kib), ms = ctx.autotune(items, ws)
-    assert q in (16, 32, 64, 128) and tg in (1, 2, 4, 8, 16) and kib in (64, 128)
+    assert q in (64, 128, 256, 512, 1024, 2048) and tg in (1, 2, 4, 8) and kib in (64, 128)
     assert ms > 0
     check_items(items, refs)  # autotune leaves valid outputs behind
     for _, _, c, m in items:

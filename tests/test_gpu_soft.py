@@ -88,14 +88,16 @@ def test_mixed_kinds_ops_and_classes(ctx, seed, nc):
     run_case(ctx, w.data, w.pop)
 
 
-@pytest.mark.parametrize("rules,nf", [((17, 32), 12), ((33, 36), 8), ((1, 8), 300),
-                                      ((9, 16), 100)])
-def test_every_adjoint_variant(ctx, rules, nf):
+@pytest.mark.parametrize("rules,conds,nf", [((17, 32), (1, 3), 12), ((33, 36), (1, 3), 8),
+                                            ((1, 8), (1, 3), 300), ((9, 16), (1, 3), 100),
+                                            ((1, 3), (58, 66), 40), ((9, 12), (55, 64), 16)])
+def test_every_adjoint_variant(ctx, rules, conds, nf):
     """Rule bounds 8/16/32 of the register-resident adjoint (4, 2 or 1
-    samples per lane by feature count) and the LDS-resident kernel beyond
-    32 rules."""
-    w = synth.tiny(70 + rules[0], n=1500, nf=nf, n_classes=3, n_sets=12, rules=rules,
-                   conds=(1, 3), ff_frac=0.3)
+    samples per lane by feature count), the LDS-resident kernel beyond 32
+    rules, and rules of more than 60 conditions (log-sum accumulator instead
+    of the product form)."""
+    w = synth.tiny(70 + rules[0] + conds[0], n=1500, nf=nf, n_classes=3, n_sets=12, rules=rules,
+                   conds=conds, ff_frac=0.3)
     run_case(ctx, w.data, w.pop)
 
 
