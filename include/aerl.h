@@ -207,7 +207,7 @@ aerl_status aerl_eval_population(aerl_ctx *ctx, int32_t dataset_id, int32_t pop_
  * autotuner and by tests that cover every code path):
  *   samples_per_lane  1, 2 or 4 (a wave covers 64*samples_per_lane samples)
  *   sets_per_chunk    rule sets per workgroup, >= 1
- *   tiles_per_group   AERL_TILE-sample tiles per workgroup, >= 1
+ *   tiles_per_group   AERL_TILE-sample tiles per workgroup, 1..255
  * Same outputs, bit for bit, for every valid configuration.  Errors: as
  * aerl_eval_population, plus AERL_EINVAL for a configuration whose LDS
  * footprint does not fit. */
@@ -240,11 +240,12 @@ typedef struct {
 } aerl_batch_item;
 
 /* Work split of a batch: rule sets per work item, AERL_TILE-sample tiles per
- * work item, and the LDS budget of a block's feature tile in KiB (an item
- * takes 4, 2 or 1 samples per lane, the most whose 64-lane tile of all its
- * features fits the budget; above 80 only one block fits a CU).  0 in a
- * field asks for the library's choice (the tuned one when aerl_autotune has
- * seen a batch of this shape, else 512 sets, 1 tile, 64 KiB). */
+ * work item (at most 255), and the LDS budget of a block's feature tile in
+ * KiB (an item takes 4, 2 or 1 samples per lane, the most whose 64-lane
+ * tile of all its features fits the budget; above 80 only one block fits a
+ * CU).  0 in a field asks for the library's choice (the tuned one when
+ * aerl_autotune has seen a batch of this shape, else 512 sets, 1 tile,
+ * 64 KiB). */
 typedef struct {
   int32_t sets_per_task;
   int32_t tiles_per_task;

@@ -50,7 +50,7 @@ int32_t sets_per_item(const DatasetRec &ds, int32_t n_sets, const BatchSplit &sp
   const int32_t Q = sp.Q;
   const size_t tile_bytes = (size_t)ds.nf * 64 * batch_samples_per_lane(ds.nf, sp.tile_budget) * 4;
   const int32_t q_fit =
-      (int32_t)std::min<size_t>((kBatchLdsMax - tile_bytes) / ((size_t)ds.nc * 4), 1 << 20);
+      (int32_t)std::min<size_t>((kBatchLdsMax - tile_bytes - 4) / ((size_t)ds.nc * 2), 1 << 20);
   return std::max(1, std::min({Q, n_sets, q_fit}));
 }
 }  // namespace
@@ -92,7 +92,7 @@ void build_batch_tables(const std::vector<BatchSource> &src, const BatchSplit &s
     if (it.confusion) b->zero.push_back({it.confusion, (int64_t)n_sets * ds.nc * ds.nc});
     const size_t tile_bytes = (size_t)ds.nf * 64 * S * 4;
     const int32_t q = sets_per_item(ds, n_sets, sp);
-    b->lds = std::max(b->lds, tile_bytes + (size_t)q * ds.nc * 4);
+    b->lds = std::max(b->lds, hard_block_lds(ds.nf, S, q, ds.nc));
     const int4 *hs = src[i].host_sets;
     for (int32_t q0 = 0; q0 < n_sets; q0 += q) {
       const int32_t qe = std::min(q, n_sets - q0);
@@ -216,7 +216,7 @@ aerl_status resolve_split(aerl_ctx *ctx, const std::vector<ItemView> &v, const a
   const int32_t tg = cfg && cfg->tiles_per_task > 0 ? cfg->tiles_per_task : d[1];
   const int32_t kib = cfg && cfg->tile_kib > 0 ? cfg->tile_kib : d[2];
   if ((cfg && (cfg->sets_per_task < 0 || cfg->tiles_per_task < 0 || cfg->tile_kib < 0)) ||
-      kib > (int32_t)(kBatchLdsMax / 1024))
+      kib > (int32_t)(kBatchLdsMax / 1024) || tg > kMaxTilesPerBlock)
     return fail(ctx, AERL_EINVAL, "invalid work split (%d, %d, %d)", q, tg, kib);
   sp->Q = q;
   sp->TG = tg;

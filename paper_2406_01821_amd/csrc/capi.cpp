@@ -74,9 +74,11 @@ void hard_config(const DatasetRec &ds, int32_t n_sets, int n_cu, int *S, int *Q,
   const int64_t tiles = std::max<int64_t>(ds.n_tiles, 1);
   const int64_t target = 4LL * n_cu;
   int q = (int)std::min<int64_t>(std::max<int32_t>(n_sets, 1), 2048);
-  while (q > 1 && (size_t)ds.nf * 64 * s * 4 + (size_t)q * ds.nc * 4 > kDynLdsMax) q = (q + 1) / 2;
+  while (q > 1 && hard_block_lds(ds.nf, s, q, ds.nc) > kDynLdsMax) q = (q + 1) / 2;
   while (q > 64 && ((n_sets + q - 1) / q) * tiles < target) q = (q + 1) / 2;
-  *Q = q;
+  // equal chunks (a short last chunk leaves its blocks underused)
+  const int chunks = (std::max<int32_t>(n_sets, 1) + q - 1) / q;
+  *Q = (std::max<int32_t>(n_sets, 1) + chunks - 1) / chunks;
   *TG = 1;
 }
 
@@ -344,8 +346,10 @@ static aerl_status eval_common(aerl_ctx *ctx, int32_t dataset_id, int32_t pop_id
   } else {
     if (S != 1 && S != 2 && S != 4) return fail(ctx, AERL_EINVAL, "samples_per_lane %d not in {1,2,4}", S);
     if (Q < 1 || TG < 1) return fail(ctx, AERL_EINVAL, "sets_per_chunk and tiles_per_group must be >= 1");
-    if ((size_t)ds.nf * 256 * S + (size_t)Q * ds.nc * 4 > kDynLdsMax)
+    if (hard_block_lds(ds.nf, S, Q, ds.nc) > kDynLdsMax)
       return fail(ctx, AERL_EINVAL, "configuration needs more LDS than a workgroup can have");
+    if (TG > kMaxTilesPerBlock)
+      return fail(ctx, AERL_EINVAL, "tiles_per_group %d above %d", TG, kMaxTilesPerBlock);
     h.samples_per_lane = S;
     h.sets_per_chunk = Q;
     h.tiles_per_group = TG;

@@ -118,8 +118,8 @@ hipError_t launch_hard_eval(const HardLaunch &h, hipStream_t st) {
   }
   if (n_groups == 0) return hipSuccess;
   const int64_t n_chunks = (h.set_count + h.sets_per_chunk - 1) / h.sets_per_chunk;
-  const size_t lds = (size_t)ds.nf * 64 * h.samples_per_lane * 4 +
-                     (size_t)h.sets_per_chunk * ds.nc * 4;
+  if (h.tiles_per_group > kMaxTilesPerBlock) return hipErrorInvalidValue;
+  const size_t lds = hard_block_lds(ds.nf, h.samples_per_lane, h.sets_per_chunk, ds.nc);
   if (lds > kDynLdsMax || n_groups > 65535 || n_chunks > 0x7fffffff) return hipErrorInvalidValue;
   const dim3 grid((unsigned)n_chunks, (unsigned)n_groups);
   switch (h.samples_per_lane) {

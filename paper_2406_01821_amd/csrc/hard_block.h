@@ -25,13 +25,15 @@ struct HardTask {
 // lets the waves pull rule sets from an LDS counter; per-class prediction
 // counts live in LDS (one writer per rule set and tile) and reach the
 // outputs once, through integer atomics.  smem holds nf*64*S floats followed
-// by Q*nc counters.  Ends with a barrier, so the caller may reuse smem.
+// by Q*nc 16-bit counters (a block covers at most 255 layout tiles, so a
+// counter stays below 2^16).  Ends with a barrier, so the caller may reuse
+// smem.
 template <int S>
 __device__ __forceinline__ void hard_block(const HardTask &t, float *smem, int32_t *next_q) {
   constexpr int TS = 64 * S;           // samples per wave tile
   constexpr int WPT = AERL_TILE / TS;  // wave tiles per layout tile
   float *xs = smem;                                                    // [nf][TS]
-  int32_t *cnt = reinterpret_cast<int32_t *>(smem + (size_t)t.nf * TS);  // [Q][nc]
+  uint16_t *cnt = reinterpret_cast<uint16_t *>(smem + (size_t)t.nf * TS);  // [Q][nc]
   const int lane = threadIdx.x & 63;
   for (int i = threadIdx.x; i < t.Q * t.nc; i += blockDim.x) cnt[i] = 0;
   const int n4 = t.nf * (TS / 4);
@@ -65,7 +67,7 @@ __device__ __forceinline__ void hard_block(const HardTask &t, float *smem, int32
       } else {
         acc = eval_set<S, false>(xs, lane, set, t.conds, vm, dummy);
       }
-      if (lane < t.nc) cnt[q * t.nc + lane] += acc;
+      if (lane < t.nc) cnt[q * t.nc + lane] += (uint16_t)acc;
     }
   }
   __syncthreads();

@@ -165,6 +165,15 @@ constexpr size_t kLdsPerCu = 160 * 1024;
 constexpr size_t kStaticLds = 64;
 constexpr size_t kDynLdsMax = kLdsPerCu - kStaticLds;
 
+// Dynamic LDS of a hard-eval block: the feature tile (nf x 64*S floats) and
+// one 16-bit prediction counter per (rule set, class).  A block adds at most
+// 256 samples per layout tile to a counter, so it covers at most
+// kMaxTilesPerBlock layout tiles.
+constexpr int kMaxTilesPerBlock = 255;
+inline size_t hard_block_lds(int nf, int S, int Q, int nc) {
+  return (size_t)nf * 64 * S * 4 + (((size_t)Q * nc * 2 + 3) & ~size_t(3));
+}
+
 // Soft path (soft.hip)
 struct SoftLaunch {
   const DatasetRec *ds;

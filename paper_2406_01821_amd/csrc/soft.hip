@@ -496,7 +496,9 @@ __device__ __forceinline__ void l_set(float (&L)[RMAX][S], int k, const float (&
   }
 }
 
-constexpr int kBwdRegBlock = 256;
+// 16 waves share a block's tile and accumulators in LDS, so the LDS limit
+// still leaves 32 waves per CU.
+constexpr int kBwdRegBlock = 1024;
 
 template <int S, int RMAX, class Acc>
 __global__ __launch_bounds__(kBwdRegBlock) void k_soft_bwd_reg(const SoftArgs a) {

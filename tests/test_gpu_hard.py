@@ -195,3 +195,21 @@ def test_invalid_inputs_raise(ctx):
         ctx.eval_population(ds, p4)
     with pytest.raises(AerlError):
         ctx.predict(p, w.data.x, set_index=w.pop.n_sets)
+
+
+def test_block_counters_at_their_widest(ctx):
+    """A block may cover up to 255 layout tiles; its per-(set, class)
+    counters then reach 255 x 256 = 65,280 (16-bit counters in LDS)."""
+    import torch
+    from paper_2406_01821_amd.aerl import AerlError
+    n = 255 * 256
+    rng = np.random.default_rng(5)
+    x = synth.lognormal_features(rng, n, 4)
+    data = Dataset(x, np.zeros(n, np.int32), 1)
+    pop = from_rule_lists([(0, []), (0, [(0, [dict(op=2, kind=0, f=0, g=0, coef=np.float32(1),
+                                                     coef2=np.float32(0), theta=np.float32(-1))])])])
+    check_against_oracle(ctx, data, pop, (4, 2, 255))
+    c, _ = run_hard(ctx, data, pop, (4, 2, 255))
+    assert list(c) == [n, n]
+    with pytest.raises(AerlError):
+        run_hard(ctx, data, pop, (4, 2, 256))
