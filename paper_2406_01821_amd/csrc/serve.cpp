@@ -30,7 +30,7 @@ namespace {
 
 const BatchSplit kServeSplit{512, 2, 64 * 1024};  // rule sets, tiles per work item; tile LDS
 constexpr size_t kTableSlack = 16 * 256;  // alignment padding of the per-launch tables
-constexpr size_t kInitialPinned = 4u << 20;
+constexpr size_t kInitialPinned = 16u << 20;
 
 size_t al(size_t v) { return (v + 255) & ~size_t(255); }
 
@@ -171,11 +171,19 @@ struct Serve {
 // arena range, lays it out and enqueues its copies and kernels on the slot.
 bool Serve::launch_one(std::unique_lock<std::mutex> &lk, Slot &slot) {
   const size_t room = alloc.largest();
-  size_t need = kTableSlack;
+  size_t need = kTableSlack, in = kTableSlack, out = 0;
   std::vector<Req *> take;
+  // A launch also stays within the slot's pinned staging buffers (growing
+  // them costs a host allocation), unless its first request alone needs more.
   while (!pending.empty() && (int32_t)take.size() < max_batch &&
          need + pending.front()->dev_bytes() <= room) {
-    need += pending.front()->dev_bytes();
+    const Req *r = pending.front();
+    if (!take.empty() && (in + r->in_bytes + r->table_bytes > slot.in_cap ||
+                          out + r->out_bytes > slot.out_cap))
+      break;
+    need += r->dev_bytes();
+    in += r->in_bytes + r->table_bytes;
+    out += r->out_bytes;
     take.push_back(pending.front());
     pending.pop_front();
   }
