@@ -28,10 +28,11 @@ HBM_PEAK = 8.0e12                     # bytes/s
 
 
 # HBM bytes per launch of the hard-eval kernel on the 2^20 x 64, 4096-set
-# workload, from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE in KiB per
-# dispatch, each scaled by what the counter reads for a plain 256 MiB copy:
-# 2.000 and 1.000).  Valid only for the kernel sources it was measured on.
-HARD_TRAFFIC = {"bytes": 2.386e9, "sources_sha256": "7fdfe9c22cf73739"}
+# workload, from two rocprofv3 --pmc runs (FETCH_SIZE 274,588 KiB and
+# WRITE_SIZE 589,513 KiB per dispatch, scaled by what the counters read for a
+# plain 256 MiB copy: x2.000 and x1.000).  Valid only for the kernel and
+# launch-configuration sources it was measured on.
+HARD_TRAFFIC = {"bytes": 1.166e9, "sources_sha256": "477fb8c5edca6d95"}
 HARD_SOURCES = ("hard.hip", "hard_block.h", "eval_core.h", "capi.cpp")  # kernel + launch config
 
 
