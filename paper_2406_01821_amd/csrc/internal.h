@@ -81,6 +81,7 @@ struct PopRec {
   int32_t max_rules = 0, max_rule_conds = 0;
   int64_t nominal_conds = 0;
   int32_t max_set_conds = 0;
+  int32_t n_ff = 0;            // feature-vs-feature conditions
   const int4 *sets = nullptr;
   const int4 *ssets = nullptr;
   const int4 *rules = nullptr;

@@ -215,6 +215,9 @@ void pack_population_image(const aerl_population *p, int32_t nf, int32_t nc, int
     }
   }
   (void)nc;
+  int32_t n_ff = 0;
+  for (int32_t j = 0; j < n_conds; ++j) n_ff += p->kind[j] == AERL_KIND_FEATURE;
+  rec->n_ff = n_ff;
   rec->n_sets = p->n_sets;
   rec->n_rules = n_rules;
   rec->n_conds = n_conds;

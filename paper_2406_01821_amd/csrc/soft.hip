@@ -253,6 +253,24 @@ __device__ __forceinline__ void cond_z(const SoftArgs &a, const float *xs, int l
   }
 }
 
+// Threshold-only populations: z2 and x[f] (xg is 1).
+template <int S>
+__device__ __forceinline__ void cond_z_t(const SoftArgs &a, const float *xs, int lane, int j,
+                                         float (&z)[S], float (&xf)[S], float (&xg)[S]) {
+  const uint32_t sc = ldc(a.sconds, j);
+  const uint32_t f = sc & 0xfffu;
+  const float inv = ldc(a.inv_tau, f) * kLog2e;
+  const float sinv = ((sc >> 25) & 1u) ? inv : -inv;
+  const float c = ldc(a.coef, j);
+  const float th = ldc(a.theta, j);
+  load_row<S>(xs, f * 1024u, lane, xf);
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    z[s] = fmaf(c, xf[s], -th) * sinv;
+    xg[s] = 1.0f;
+  }
+}
+
 // z2 only (forward pass): nothing but z leaves the branch on the kind.
 template <int S>
 __device__ __forceinline__ void cond_z_only(const SoftArgs &a, const float *xs, int lane, int j,
@@ -500,7 +518,12 @@ __device__ __forceinline__ void l_set(float (&L)[RMAX][S], int k, const float (&
 // still leaves 32 waves per CU.
 constexpr int kBwdRegBlock = 1024;
 
-template <int S, int RMAX, class Acc>
+// TONLY: the population has threshold conditions only (no x[g] rows).
+// Rule sets of at most 64 conditions keep the wave totals of the current
+// walk in two VGPRs (lane i: condition i of the set) and add them to the
+// block accumulators once per walk; longer
+// rule sets add each condition's totals as they come.
+template <int S, int RMAX, class Acc, bool TONLY>
 __global__ __launch_bounds__(kBwdRegBlock) void k_soft_bwd_reg(const SoftArgs a) {
   constexpr int TS = 64 * S, WPT = AERL_TILE / TS;
   extern __shared__ __align__(16) float smem[];
@@ -574,6 +597,8 @@ __global__ __launch_bounds__(kBwdRegBlock) void k_soft_bwd_reg(const SoftArgs a)
         U[s] = dflt == label ? 0.0f : kNegInf;
       }
       // reverse sweep
+      const bool few = ss.w <= 64;
+      int tot0 = 0, tot1 = 0;
       for (int k = ss.y - 1; k >= 0; --k) {
         const int4 r = ldc(a.rules, ss.x + k);
         const bool hit = r.z == label;
@@ -592,8 +617,12 @@ __global__ __launch_bounds__(kBwdRegBlock) void k_soft_bwd_reg(const SoftArgs a)
         Acc ra[S];
         for (int j = r.x; j < r.x + r.y; ++j) {
           float z[S], xf[S], xg[S];
-          bool ff;
-          cond_z<S>(a, xs, lane, j, z, xf, xg, ff);
+          if constexpr (TONLY) {
+            cond_z_t<S>(a, xs, lane, j, z, xf, xg);
+          } else {
+            bool ff;
+            cond_z<S>(a, xs, lane, j, z, xf, xg, ff);
+          }
           float g0 = 0.0f, g1 = 0.0f;
 #pragma unroll
           for (int s = 0; s < S; ++s) {
@@ -605,11 +634,17 @@ __global__ __launch_bounds__(kBwdRegBlock) void k_soft_bwd_reg(const SoftArgs a)
           }
           g0 = wave_total_last(g0);
           g1 = wave_total_last(g1);
-          if (lane == 63) {
+          if (few) {
+            const int v0 = __builtin_amdgcn_readlane(__float_as_int(g0), 63);
+            const int v1 = __builtin_amdgcn_readlane(__float_as_int(g1), 63);
+            const bool mine = lane == j - ss.z;
+            tot0 = mine ? v0 : tot0;
+            tot1 = mine ? v1 : tot1;
+          } else if (lane == 63) {
             // one writer per (rule set, tile): the order of these adds is fixed
             float *ap = acc + ((size_t)q * a.max_set_conds + (j - ss.z)) * 2;
-            atomicAdd(ap, g0);
-            atomicAdd(ap + 1, g1);
+            ap[0] += g0;
+            ap[1] += g1;
           }
         }
 #pragma unroll
@@ -618,6 +653,13 @@ __global__ __launch_bounds__(kBwdRegBlock) void k_soft_bwd_reg(const SoftArgs a)
           acc_finish(ra[s], a2, b2);
           U[s] = lse(hit ? a2 : kNegInf, b2 + U[s]);
         }
+      }
+      if (few && lane < ss.w) {
+        // every condition of the set was visited once: lane i holds the
+        // totals of condition i; one writer per (rule set, tile)
+        float *ap = acc + ((size_t)q * a.max_set_conds + lane) * 2;
+        ap[0] += __int_as_float(tot0);
+        ap[1] += __int_as_float(tot1);
       }
     }
   }
@@ -754,25 +796,25 @@ void launch_fwd(const SoftPlan &p, dim3 grid, hipStream_t st, const SoftArgs &a)
   }
 }
 
-template <class Acc>
+template <class Acc, bool TONLY>
 void launch_bwd_reg(const SoftPlan &p, dim3 grid, hipStream_t st, const SoftArgs &a) {
   const dim3 rb(kBwdRegBlock);
   if (p.rmax == 8 && p.S == 4) {
-    hipLaunchKernelGGL((k_soft_bwd_reg<4, 8, Acc>), grid, rb, p.lds, st, a);
+    hipLaunchKernelGGL((k_soft_bwd_reg<4, 8, Acc, TONLY>), grid, rb, p.lds, st, a);
   } else if (p.rmax == 8 && p.S == 2) {
-    hipLaunchKernelGGL((k_soft_bwd_reg<2, 8, Acc>), grid, rb, p.lds, st, a);
+    hipLaunchKernelGGL((k_soft_bwd_reg<2, 8, Acc, TONLY>), grid, rb, p.lds, st, a);
   } else if (p.rmax == 16 && p.S == 4) {
-    hipLaunchKernelGGL((k_soft_bwd_reg<4, 16, Acc>), grid, rb, p.lds, st, a);
+    hipLaunchKernelGGL((k_soft_bwd_reg<4, 16, Acc, TONLY>), grid, rb, p.lds, st, a);
   } else if (p.rmax == 16 && p.S == 2) {
-    hipLaunchKernelGGL((k_soft_bwd_reg<2, 16, Acc>), grid, rb, p.lds, st, a);
+    hipLaunchKernelGGL((k_soft_bwd_reg<2, 16, Acc, TONLY>), grid, rb, p.lds, st, a);
   } else if (p.rmax == 32 && p.S == 2) {
-    hipLaunchKernelGGL((k_soft_bwd_reg<2, 32, Acc>), grid, rb, p.lds, st, a);
+    hipLaunchKernelGGL((k_soft_bwd_reg<2, 32, Acc, TONLY>), grid, rb, p.lds, st, a);
   } else if (p.rmax == 8) {  // one sample per lane (wide datasets)
-    hipLaunchKernelGGL((k_soft_bwd_reg<1, 8, Acc>), grid, rb, p.lds, st, a);
+    hipLaunchKernelGGL((k_soft_bwd_reg<1, 8, Acc, TONLY>), grid, rb, p.lds, st, a);
   } else if (p.rmax == 16) {
-    hipLaunchKernelGGL((k_soft_bwd_reg<1, 16, Acc>), grid, rb, p.lds, st, a);
+    hipLaunchKernelGGL((k_soft_bwd_reg<1, 16, Acc, TONLY>), grid, rb, p.lds, st, a);
   } else {
-    hipLaunchKernelGGL((k_soft_bwd_reg<1, 32, Acc>), grid, rb, p.lds, st, a);
+    hipLaunchKernelGGL((k_soft_bwd_reg<1, 32, Acc, TONLY>), grid, rb, p.lds, st, a);
   }
 }
 
@@ -823,10 +865,15 @@ hipError_t launch_soft_backward(const SoftLaunch &l, hipStream_t st) {
   a.part_grad = static_cast<float *>(l.ws);
   if (p.n_groups > 0) {
     const dim3 grid((unsigned)((pop.n_sets + p.Q - 1) / p.Q), (unsigned)p.n_groups);
-    if (p.rmax > 0 && pop.max_rule_conds <= kProdMaxConds) {
-      launch_bwd_reg<RuleProd>(p, grid, st, a);
+    const bool prod = pop.max_rule_conds <= kProdMaxConds, tonly = pop.n_ff == 0;
+    if (p.rmax > 0 && prod && tonly) {
+      launch_bwd_reg<RuleProd, true>(p, grid, st, a);
+    } else if (p.rmax > 0 && prod) {
+      launch_bwd_reg<RuleProd, false>(p, grid, st, a);
+    } else if (p.rmax > 0 && tonly) {
+      launch_bwd_reg<RuleAcc, true>(p, grid, st, a);
     } else if (p.rmax > 0) {
-      launch_bwd_reg<RuleAcc>(p, grid, st, a);
+      launch_bwd_reg<RuleAcc, false>(p, grid, st, a);
     } else {
       hipLaunchKernelGGL(k_soft_bwd, grid, dim3(kBwdWaves * 64), p.lds, st, a);
     }
