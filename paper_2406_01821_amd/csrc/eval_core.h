@@ -167,48 +167,74 @@ __device__ __forceinline__ int eval_set(const float *__restrict__ xs, int lane, 
 }
 
 // 4-slot counting evaluation written for the scalar unit.  Same semantics as
-// eval_set<4, false>.  Every load is waited on inside the asm block.  Fixed
-// registers: s[84:87] hold the current record, v[32:39] the feature values
-// of the lane's four samples (two rows for feature-vs-feature records).
+// eval_set<4, false>.  Records are loaded two at a time (s_load_dwordx8
+// into quads A = s[84:87] and B = s[88:91]): the record after the current
+// one arrives with it, so a rule that goes on past an A record, or a rule
+// that starts right after one, continues without another scalar load or
+// wait.  The record after a rule set's last one lies inside the packed
+// stream (it ends with a spare record).  Every load is waited on inside the
+// asm block.  v[32:39] hold the feature values of the lane's four samples
+// (two rows for feature-vs-feature records).
 //   lds_lane: LDS byte address of the tile plus lane*16.
-#define AERL_T_BODY                                     \
-  "s_waitcnt lgkmcnt(0)\n"                              \
-  "v_mul_f32 v32, s85, v32\n"                           \
-  "v_mul_f32 v33, s85, v33\n"                           \
-  "v_mul_f32 v34, s85, v34\n"                           \
-  "v_mul_f32 v35, s85, v35\n"                           \
-  "v_cmp_lt_f32_e64 %[m0], s86, v32\n"                  \
-  "v_cmp_lt_f32_e64 %[m1], s86, v33\n"                  \
-  "v_cmp_lt_f32_e64 %[m2], s86, v34\n"                  \
-  "v_cmp_lt_f32_e64 %[m3], s86, v35\n"
 
-#define AERL_FF_BODY(TAG)                               \
-  "s_bfe_u32 %[t0], s87, 0x90000\n"                     \
+// Threshold record (a in Y, b in Z): f_i = S_i & (b < a*x_i).
+#define AERL_T_BODY(Y, Z, S0, S1, S2, S3)               \
+  "s_waitcnt lgkmcnt(0)\n"                              \
+  "v_mul_f32 v32, " Y ", v32\n"                         \
+  "v_mul_f32 v33, " Y ", v33\n"                         \
+  "v_mul_f32 v34, " Y ", v34\n"                         \
+  "v_mul_f32 v35, " Y ", v35\n"                         \
+  "v_cmp_lt_f32_e64 %[m0], " Z ", v32\n"                \
+  "v_cmp_lt_f32_e64 %[m1], " Z ", v33\n"                \
+  "v_cmp_lt_f32_e64 %[m2], " Z ", v34\n"                \
+  "v_cmp_lt_f32_e64 %[m3], " Z ", v35\n"                \
+  "s_and_b64 %[f3], " S3 ", %[m3]\n"                    \
+  "s_and_b64 %[f2], " S2 ", %[m2]\n"                    \
+  "s_and_b64 %[f1], " S1 ", %[m1]\n"                    \
+  "s_and_b64 %[f0], " S0 ", %[m0]\n"
+
+#define AERL_FF_CMP(OP, S0, S1, S2, S3)                 \
+  "v_cmp_" OP "_f32_e64 %[m0], v32, v36\n"              \
+  "v_cmp_" OP "_f32_e64 %[m1], v33, v37\n"              \
+  "v_cmp_" OP "_f32_e64 %[m2], v34, v38\n"              \
+  "v_cmp_" OP "_f32_e64 %[m3], v35, v39\n"              \
+  "s_and_b64 %[f3], " S3 ", %[m3]\n"                    \
+  "s_and_b64 %[f2], " S2 ", %[m2]\n"                    \
+  "s_and_b64 %[f1], " S1 ", %[m1]\n"                    \
+  "s_and_b64 %[f0], " S0 ", %[m0]\n"
+
+// Feature-vs-feature record (a in Y, b in Z, g and the >= flag in W):
+// f_i = S_i & (a*x_i > b*x'_i) or (>=); then on to POST.
+#define AERL_FF_BODY(W, Y, Z, S0, S1, S2, S3, TAG, POST) \
+  "s_bfe_u32 %[t0], " W ", 0x90000\n"                   \
   "s_lshl_b32 %[t0], %[t0], 10\n"                       \
   "v_add_u32 %[vt2], %[t0], %[lds]\n"                   \
   "ds_read_b128 v[36:39], %[vt2]\n"                     \
   "s_waitcnt lgkmcnt(0)\n"                              \
-  "v_mul_f32 v32, s85, v32\n"                           \
-  "v_mul_f32 v33, s85, v33\n"                           \
-  "v_mul_f32 v34, s85, v34\n"                           \
-  "v_mul_f32 v35, s85, v35\n"                           \
-  "v_mul_f32 v36, s86, v36\n"                           \
-  "v_mul_f32 v37, s86, v37\n"                           \
-  "v_mul_f32 v38, s86, v38\n"                           \
-  "v_mul_f32 v39, s86, v39\n"                           \
-  "s_bitcmp1_b32 s87, 10\n"                             \
+  "v_mul_f32 v32, " Y ", v32\n"                         \
+  "v_mul_f32 v33, " Y ", v33\n"                         \
+  "v_mul_f32 v34, " Y ", v34\n"                         \
+  "v_mul_f32 v35, " Y ", v35\n"                         \
+  "v_mul_f32 v36, " Z ", v36\n"                         \
+  "v_mul_f32 v37, " Z ", v37\n"                         \
+  "v_mul_f32 v38, " Z ", v38\n"                         \
+  "v_mul_f32 v39, " Z ", v39\n"                         \
+  "s_bitcmp1_b32 " W ", 10\n"                           \
   "s_cbranch_scc1 .Lge_" TAG "_%=\n"                    \
-  "v_cmp_gt_f32_e64 %[m0], v32, v36\n"                  \
-  "v_cmp_gt_f32_e64 %[m1], v33, v37\n"                  \
-  "v_cmp_gt_f32_e64 %[m2], v34, v38\n"                  \
-  "v_cmp_gt_f32_e64 %[m3], v35, v39\n"                  \
-  "s_branch .Land_" TAG "_%=\n"                         \
+  AERL_FF_CMP("gt", S0, S1, S2, S3)                     \
+  "s_branch " POST "\n"                                 \
   ".Lge_" TAG "_%=:\n"                                  \
-  "v_cmp_ge_f32_e64 %[m0], v32, v36\n"                  \
-  "v_cmp_ge_f32_e64 %[m1], v33, v37\n"                  \
-  "v_cmp_ge_f32_e64 %[m2], v34, v38\n"                  \
-  "v_cmp_ge_f32_e64 %[m3], v35, v39\n"                  \
-  "s_branch .Land_" TAG "_%=\n"
+  AERL_FF_CMP("ge", S0, S1, S2, S3)                     \
+  "s_branch " POST "\n"
+
+// Record in quad X at offset o: read its feature row, then compare
+// (threshold inline, feature-vs-feature at FFL).
+#define AERL_RECORD(XX, XY, XZ, XW, S0, S1, S2, S3, FFL) \
+  "v_add_u32 %[vt], " XX ", %[lds]\n"                   \
+  "ds_read_b128 v[32:35], %[vt]\n"                      \
+  "s_bitcmp1_b32 " XW ", 9\n"                           \
+  "s_cbranch_scc1 " FFL "\n"                            \
+  AERL_T_BODY(XY, XZ, S0, S1, S2, S3)
 
 #define AERL_POPC4(A, B, C, D)                          \
   "s_bcnt1_i32_b64 %[t0], " A "\n"                      \
@@ -218,6 +244,35 @@ __device__ __forceinline__ int eval_set(const float *__restrict__ xs, int lane, 
   "s_add_u32 %[t0], %[t0], %[t1]\n"                     \
   "s_bcnt1_i32_b64 %[t1], " D "\n"                      \
   "s_add_u32 %[t0], %[t0], %[t1]\n"
+
+// The rule of the (last) record in W fires for the lanes in f: count them
+// for its class and retire them (SCC = some lane still undecided).
+#define AERL_COMMIT_COUNT(W)                            \
+  AERL_POPC4("%[f0]", "%[f1]", "%[f2]", "%[f3]")        \
+  "s_bfe_u32 %[t1], " W ", 0x6000c\n"                   \
+  "v_cmp_eq_u32_e32 vcc, %[t1], %[lane]\n"              \
+  "v_mov_b32 %[vt], %[t0]\n"                            \
+  "v_cndmask_b32_e32 %[vt], 0, %[vt], vcc\n"            \
+  "v_add_u32 %[acc], %[acc], %[vt]\n"                   \
+  "s_andn2_b64 %[u0], %[u0], %[f0]\n"                   \
+  "s_andn2_b64 %[u1], %[u1], %[f1]\n"                   \
+  "s_andn2_b64 %[u2], %[u2], %[f2]\n"                   \
+  "s_andn2_b64 %[u3], %[u3], %[f3]\n"                   \
+  "s_or_b64 %[m0], %[u0], %[u1]\n"                      \
+  "s_or_b64 %[m0], %[m0], %[u2]\n"                      \
+  "s_or_b64 %[m0], %[m0], %[u3]\n"
+
+// SCC = (f0 != 0) after a compare; true when any f_i is non-zero.
+#define AERL_ANY_F(ALIVE)                               \
+  "s_cbranch_scc1 " ALIVE "\n"                          \
+  "s_or_b64 %[m0], %[f1], %[f2]\n"                      \
+  "s_or_b64 %[m0], %[m0], %[f3]\n"                      \
+  "s_cbranch_scc1 " ALIVE "\n"
+
+#define AERL_U "%[u0]", "%[u1]", "%[u2]", "%[u3]"
+#define AERL_F "%[f0]", "%[f1]", "%[f2]", "%[f3]"
+#define AERL_RECORD_X(...) AERL_RECORD(__VA_ARGS__)
+#define AERL_FF_BODY_X(...) AERL_FF_BODY(__VA_ARGS__)
 
 __device__ __forceinline__ int eval_set_s4_count(uint32_t lds_lane, int lane, int4 set,
                                                  const uint4 *__restrict__ stream,
@@ -233,69 +288,73 @@ __device__ __forceinline__ int eval_set_s4_count(uint32_t lds_lane, int lane, in
       "s_mov_b32 %[o], 0\n"
       "s_cmp_eq_u32 %[end], 0\n"
       "s_cbranch_scc1 .Ldefault_%=\n"
-      // first record of a rule: fire = und & m
+      // load the pair (o, o+16) into A, B
       ".Lfirst_%=:\n"
-      "s_load_dwordx4 s[84:87], %[base], %[o]\n"
+      "s_load_dwordx8 s[84:91], %[base], %[o]\n"
       "s_waitcnt lgkmcnt(0)\n"
-      "v_add_u32 %[vt], s84, %[lds]\n"
-      "ds_read_b128 v[32:35], %[vt]\n"
-      "s_bitcmp1_b32 s87, 9\n"
-      "s_cbranch_scc1 .Lff_first_%=\n"
-      AERL_T_BODY
-      ".Land_first_%=:\n"
-      "s_and_b64 %[f3], %[u3], %[m3]\n"
-      "s_and_b64 %[f2], %[u2], %[m2]\n"
-      "s_and_b64 %[f1], %[u1], %[m1]\n"
-      "s_and_b64 %[f0], %[u0], %[m0]\n"
-      "s_cbranch_scc0 .Lcheck_%=\n"
-      ".Lalive_%=:\n"
+      // first record of a rule in A: f = undecided & m
+      ".Lstart_A_%=:\n"
+      AERL_RECORD_X("s84", "s85", "s86", "s87", AERL_U, ".Lffs_A_%=")
+      // after a record in A
+      ".Lpost_A_%=:\n"
+      AERL_ANY_F(".Lalive_A_%=")
+      // the rule cannot fire for any undecided lane: next rule
+      "s_lshr_b32 %[t1], s87, 18\n"
+      "s_add_u32 %[t0], %[o], 16\n"
+      "s_cmp_ge_u32 %[t1], %[end]\n"
+      "s_cbranch_scc1 .Ldefault_%=\n"
+      "s_cmp_eq_u32 %[t1], %[t0]\n"
+      "s_mov_b32 %[o], %[t1]\n"
+      "s_cbranch_scc1 .Lstart_B_%=\n"
+      "s_branch .Lfirst_%=\n"
+      ".Lalive_A_%=:\n"
       "s_bitcmp1_b32 s87, 11\n"
-      "s_cbranch_scc1 .Lcommit_%=\n"
+      "s_cbranch_scc1 .Lcommit_A_%=\n"
       "s_add_u32 %[o], %[o], 16\n"
-      // later record of the same rule: fire &= m
-      "s_load_dwordx4 s[84:87], %[base], %[o]\n"
-      "s_waitcnt lgkmcnt(0)\n"
-      "v_add_u32 %[vt], s84, %[lds]\n"
-      "ds_read_b128 v[32:35], %[vt]\n"
-      "s_bitcmp1_b32 s87, 9\n"
-      "s_cbranch_scc1 .Lff_next_%=\n"
-      AERL_T_BODY
-      ".Land_next_%=:\n"
-      "s_and_b64 %[f3], %[f3], %[m3]\n"
-      "s_and_b64 %[f2], %[f2], %[m2]\n"
-      "s_and_b64 %[f1], %[f1], %[m1]\n"
-      "s_and_b64 %[f0], %[f0], %[m0]\n"
-      "s_cbranch_scc1 .Lalive_%=\n"
-      ".Lcheck_%=:\n"
-      "s_or_b64 %[m0], %[f1], %[f2]\n"
-      "s_or_b64 %[m0], %[m0], %[f3]\n"
-      "s_cbranch_scc1 .Lalive_%=\n"
-      // the rule cannot fire for any undecided lane: go to the next rule
-      "s_lshr_b32 %[o], s87, 18\n"
+      // later record of the same rule in B: f &= m
+      ".Lnext_B_%=:\n"
+      AERL_RECORD_X("s88", "s89", "s90", "s91", AERL_F, ".Lffn_B_%=")
+      // after a record in B
+      ".Lpost_B_%=:\n"
+      AERL_ANY_F(".Lalive_B_%=")
+      "s_lshr_b32 %[o], s91, 18\n"
       "s_cmp_lt_u32 %[o], %[end]\n"
       "s_cbranch_scc1 .Lfirst_%=\n"
       "s_branch .Ldefault_%=\n"
-      ".Lff_first_%=:\n"
-      AERL_FF_BODY("first")
-      ".Lff_next_%=:\n"
-      AERL_FF_BODY("next")
-      // the rule fires for the lanes in f: count them for its class
-      ".Lcommit_%=:\n"
-      AERL_POPC4("%[f0]", "%[f1]", "%[f2]", "%[f3]")
-      "s_bfe_u32 %[t1], s87, 0x6000c\n"
-      "v_cmp_eq_u32_e32 vcc, %[t1], %[lane]\n"
-      "v_mov_b32 %[vt], %[t0]\n"
-      "v_cndmask_b32_e32 %[vt], 0, %[vt], vcc\n"
-      "v_add_u32 %[acc], %[acc], %[vt]\n"
-      "s_andn2_b64 %[u0], %[u0], %[f0]\n"
-      "s_andn2_b64 %[u1], %[u1], %[f1]\n"
-      "s_andn2_b64 %[u2], %[u2], %[f2]\n"
-      "s_andn2_b64 %[u3], %[u3], %[f3]\n"
-      "s_or_b64 %[m0], %[u0], %[u1]\n"
-      "s_or_b64 %[m0], %[m0], %[u2]\n"
-      "s_or_b64 %[m0], %[m0], %[u3]\n"
+      ".Lalive_B_%=:\n"
+      "s_bitcmp1_b32 s91, 11\n"
+      "s_cbranch_scc1 .Lcommit_B_%=\n"
+      "s_add_u32 %[o], %[o], 16\n"
+      "s_load_dwordx8 s[84:91], %[base], %[o]\n"
+      "s_waitcnt lgkmcnt(0)\n"
+      // later record of the same rule in A
+      AERL_RECORD_X("s84", "s85", "s86", "s87", AERL_F, ".Lffn_A_%=")
+      "s_branch .Lpost_A_%=\n"
+      // first record of a rule in B
+      ".Lstart_B_%=:\n"
+      AERL_RECORD_X("s88", "s89", "s90", "s91", AERL_U, ".Lffs_B_%=")
+      "s_branch .Lpost_B_%=\n"
+      ".Lffs_A_%=:\n"
+      AERL_FF_BODY_X("s87", "s85", "s86", AERL_U, "sA", ".Lpost_A_%=")
+      ".Lffn_A_%=:\n"
+      AERL_FF_BODY_X("s87", "s85", "s86", AERL_F, "nA", ".Lpost_A_%=")
+      ".Lffs_B_%=:\n"
+      AERL_FF_BODY_X("s91", "s89", "s90", AERL_U, "sB", ".Lpost_B_%=")
+      ".Lffn_B_%=:\n"
+      AERL_FF_BODY_X("s91", "s89", "s90", AERL_F, "nB", ".Lpost_B_%=")
+      // the rule of the record in A fires; the next rule starts with B
+      ".Lcommit_A_%=:\n"
+      AERL_COMMIT_COUNT("s87")
       "s_cbranch_scc0 .Ldone_%=\n"
-      "s_lshr_b32 %[o], s87, 18\n"
+      "s_add_u32 %[o], %[o], 16\n"
+      "s_cmp_lt_u32 %[o], %[end]\n"
+      "s_cbranch_scc1 .Lstart_B_%=\n"
+      "s_branch .Ldefault_%=\n"
+      // the rule of the record in B fires; the next rule needs a new pair
+      ".Lcommit_B_%=:\n"
+      AERL_COMMIT_COUNT("s91")
+      "s_cbranch_scc0 .Ldone_%=\n"
+      "s_add_u32 %[o], %[o], 16\n"
       "s_cmp_lt_u32 %[o], %[end]\n"
       "s_cbranch_scc1 .Lfirst_%=\n"
       // no rule fired for the remaining lanes: default class
@@ -312,8 +371,8 @@ __device__ __forceinline__ int eval_set_s4_count(uint32_t lds_lane, int lane, in
         [t1] "=&s"(t1), [vt] "=&v"(vt), [vt2] "=&v"(vt2)
       : [base] "s"(base), [end] "s"(end), [dflt] "s"(dflt), [lds] "v"(lds_lane),
         [lane] "v"(lane)
-      : "s84", "s85", "s86", "s87", "v32", "v33", "v34", "v35", "v36", "v37", "v38", "v39",
-        "vcc", "scc", "memory");
+      : "s84", "s85", "s86", "s87", "s88", "s89", "s90", "s91", "v32", "v33", "v34", "v35",
+        "v36", "v37", "v38", "v39", "vcc", "scc", "memory");
   return acc;
 }
 

@@ -154,3 +154,116 @@ def test_packed_rewrite_is_exact_against_oracle(aerl):
     for s in range(pop.n_sets):
         np.testing.assert_array_equal(eval_packed(xx, S, H, s), oracle.predict(xx, pop, s),
                                       err_msg=str(s))
+
+
+def walk_s4_pairs(x, sets, hc, s, n_records, n_classes):
+    """Label-for-label model of the hard kernel's four-slot record walk,
+    which loads records two at a time into register quads A (offset o) and
+    B (o+16): a rule that goes on past an A record, or starts right after
+    one, continues from B without a load.  Checks that every compare uses
+    the record at its offset, that every pair read stays inside the stream,
+    and that the walk ends.  Returns per-class prediction counts for the
+    rows of x."""
+    first, count, default, _ = (int(v) for v in sets[s])
+    end = count * 16
+    u = np.ones(x.shape[0], bool)
+    f = None
+    counts = np.zeros(n_classes, np.int64)
+    quad = {}
+
+    def rec(off):
+        assert 0 <= first + off // 16 < n_records, "read outside the stream"
+        return tuple(int(v) for v in hc[first + off // 16])
+
+    def compare(r, src):
+        f1024, a, b, w = r
+        a = np.uint32(a).view(np.float32)
+        b = np.uint32(b).view(np.float32)
+        lhs = np.float32(a) * x[:, f1024 // 1024]
+        if not w & (1 << 9):
+            m = b < lhs
+        else:
+            rhs = np.float32(b) * x[:, w & 0x1ff]
+            m = lhs >= rhs if w & (1 << 10) else lhs > rhs
+        return src & m
+
+    def commit(w):
+        nonlocal u
+        counts[(w >> 12) & 63] += int(f.sum())
+        u &= ~f
+        return u.any()
+
+    o = 0
+    state = "default" if end == 0 else "first"
+    for _ in range(4 * count + 8):
+        if state == "first":
+            quad["A"], quad["B"] = rec(o), rec(o + 16)
+            state = "start_A"
+        elif state in ("start_A", "next_A", "start_B", "next_B"):
+            X = state[-1]
+            assert quad[X] == rec(o), "compared a stale record"
+            f = compare(quad[X], u if state.startswith("start") else f)
+            state = "post_" + X
+        elif state == "post_A":
+            w = quad["A"][3]
+            if f.any():
+                if w & (1 << 11):
+                    if not commit(w):
+                        return counts
+                    o += 16
+                    state = "start_B" if o < end else "default"
+                else:
+                    o += 16
+                    state = "next_B"
+            else:
+                t1 = w >> 18
+                if t1 >= end:
+                    state = "default"
+                elif t1 == o + 16:
+                    o = t1
+                    state = "start_B"
+                else:
+                    o = t1
+                    state = "first"
+        elif state == "post_B":
+            w = quad["B"][3]
+            if f.any():
+                if w & (1 << 11):
+                    if not commit(w):
+                        return counts
+                    o += 16
+                    state = "first" if o < end else "default"
+                else:
+                    o += 16
+                    quad["A"], quad["B"] = rec(o), rec(o + 16)
+                    state = "next_A"
+            else:
+                o = w >> 18
+                state = "first" if o < end else "default"
+        else:
+            counts[default] += int(u.sum())
+            return counts
+    raise AssertionError("record walk did not end")
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_paired_record_walk_matches_oracle(aerl, seed):
+    """The paired-load record walk, run on the packed stream with numpy fp32
+    arithmetic over label-uniform 256-sample tiles, reproduces the oracle's
+    confusion counts (random populations with empty rules, 1-12 rules of
+    1-9 conditions, both kinds, all operators)."""
+    from paper_2406_01821_amd import synth
+    w = synth.tiny(600 + seed, n=700, nf=9, n_classes=3, n_sets=25, rules=(0, 12),
+                   conds=(0, 9), ff_frac=0.4)
+    x, y, pop = w.data.x, w.data.y, w.pop
+    img = aerl.pack_host(pop, 9, 3)
+    sets, hc = decode_packed(img, pop.n_sets, pop.n_rules, pop.n_conds)
+    n_records = pop.n_conds + pop.n_rules + 1
+    _, ref = oracle.hard_eval(x, y, 3, pop)
+    for s in range(pop.n_sets):
+        got = np.zeros((3, 3), np.int64)
+        for c in range(3):
+            rows = x[y == c]
+            for t in range(0, len(rows), 256):
+                got[c] += walk_s4_pairs(rows[t:t + 256], sets, hc, s, n_records, 3)
+        np.testing.assert_array_equal(got, ref[s], err_msg=f"set {s}")
