@@ -74,7 +74,13 @@ void hard_config(const DatasetRec &ds, int32_t n_sets, int n_cu, int *S, int *Q,
   const int64_t tiles = std::max<int64_t>(ds.n_tiles, 1);
   const int64_t target = 4LL * n_cu;
   int q = (int)std::min<int64_t>(std::max<int32_t>(n_sets, 1), 2048);
-  while (q > 1 && hard_block_lds(ds.nf, s, q, ds.nc) > kDynLdsMax) q = (q + 1) / 2;
+  // Two blocks per CU (eight waves per SIMD) hide the latency of the scalar
+  // record loads and LDS reads far better than one: take the largest chunk
+  // that lets two blocks share a CU's LDS, when one of at least 64 sets does.
+  const size_t half = kLdsPerCu / 2 - kStaticLds;
+  const int q_min2 = std::min(q, 64);
+  const size_t budget = hard_block_lds(ds.nf, s, q_min2, ds.nc) <= half ? half : kDynLdsMax;
+  while (q > 1 && hard_block_lds(ds.nf, s, q, ds.nc) > budget) q = (q + 1) / 2;
   while (q > 64 && ((n_sets + q - 1) / q) * tiles < target) q = (q + 1) / 2;
   // equal chunks (a short last chunk leaves its blocks underused)
   const int chunks = (std::max<int32_t>(n_sets, 1) + q - 1) / q;

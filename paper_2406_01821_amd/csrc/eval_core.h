@@ -168,7 +168,7 @@ __device__ __forceinline__ int eval_set(const float *__restrict__ xs, int lane, 
 
 // 4-slot counting evaluation written for the scalar unit.  Same semantics as
 // eval_set<4, false>.  Records are loaded two at a time (s_load_dwordx8
-// into quads A = s[84:87] and B = s[88:91]): the record after the current
+// into quads A = s[64:67] and B = s[68:71]): the record after the current
 // one arrives with it, so a rule that goes on past an A record, or a rule
 // that starts right after one, continues without another scalar load or
 // wait.  The record after a rule set's last one lies inside the packed
@@ -177,31 +177,33 @@ __device__ __forceinline__ int eval_set(const float *__restrict__ xs, int lane, 
 // (two rows for feature-vs-feature records).
 //   lds_lane: LDS byte address of the tile plus lane*16.
 
-// Threshold record (a in Y, b in Z): f_i = S_i & (b < a*x_i).
+// Threshold record (a in Y, b in Z): f_i = S_i & (b < a*x_i).  The compare
+// masks go through two temporaries (m and vcc), alternating, so that each
+// AND waits only for its own compare; f0 is written last, so SCC = (f0 != 0).
 #define AERL_T_BODY(Y, Z, S0, S1, S2, S3)               \
   "s_waitcnt lgkmcnt(0)\n"                              \
   "v_mul_f32 v32, " Y ", v32\n"                         \
   "v_mul_f32 v33, " Y ", v33\n"                         \
   "v_mul_f32 v34, " Y ", v34\n"                         \
   "v_mul_f32 v35, " Y ", v35\n"                         \
-  "v_cmp_lt_f32_e64 %[m0], " Z ", v32\n"                \
-  "v_cmp_lt_f32_e64 %[m1], " Z ", v33\n"                \
-  "v_cmp_lt_f32_e64 %[m2], " Z ", v34\n"                \
-  "v_cmp_lt_f32_e64 %[m3], " Z ", v35\n"                \
-  "s_and_b64 %[f3], " S3 ", %[m3]\n"                    \
-  "s_and_b64 %[f2], " S2 ", %[m2]\n"                    \
-  "s_and_b64 %[f1], " S1 ", %[m1]\n"                    \
-  "s_and_b64 %[f0], " S0 ", %[m0]\n"
+  "v_cmp_lt_f32_e64 %[m], " Z ", v35\n"                 \
+  "v_cmp_lt_f32_e32 vcc, " Z ", v34\n"                  \
+  "s_and_b64 %[f3], " S3 ", %[m]\n"                     \
+  "v_cmp_lt_f32_e64 %[m], " Z ", v33\n"                 \
+  "s_and_b64 %[f2], " S2 ", vcc\n"                      \
+  "v_cmp_lt_f32_e32 vcc, " Z ", v32\n"                  \
+  "s_and_b64 %[f1], " S1 ", %[m]\n"                     \
+  "s_and_b64 %[f0], " S0 ", vcc\n"
 
 #define AERL_FF_CMP(OP, S0, S1, S2, S3)                 \
-  "v_cmp_" OP "_f32_e64 %[m0], v32, v36\n"              \
-  "v_cmp_" OP "_f32_e64 %[m1], v33, v37\n"              \
-  "v_cmp_" OP "_f32_e64 %[m2], v34, v38\n"              \
-  "v_cmp_" OP "_f32_e64 %[m3], v35, v39\n"              \
-  "s_and_b64 %[f3], " S3 ", %[m3]\n"                    \
-  "s_and_b64 %[f2], " S2 ", %[m2]\n"                    \
-  "s_and_b64 %[f1], " S1 ", %[m1]\n"                    \
-  "s_and_b64 %[f0], " S0 ", %[m0]\n"
+  "v_cmp_" OP "_f32_e64 %[m], v35, v39\n"               \
+  "v_cmp_" OP "_f32_e32 vcc, v34, v38\n"                \
+  "s_and_b64 %[f3], " S3 ", %[m]\n"                     \
+  "v_cmp_" OP "_f32_e64 %[m], v33, v37\n"               \
+  "s_and_b64 %[f2], " S2 ", vcc\n"                      \
+  "v_cmp_" OP "_f32_e32 vcc, v32, v36\n"                \
+  "s_and_b64 %[f1], " S1 ", %[m]\n"                     \
+  "s_and_b64 %[f0], " S0 ", vcc\n"
 
 // Feature-vs-feature record (a in Y, b in Z, g and the >= flag in W):
 // f_i = S_i & (a*x_i > b*x'_i) or (>=); then on to POST.
@@ -258,15 +260,15 @@ __device__ __forceinline__ int eval_set(const float *__restrict__ xs, int lane, 
   "s_andn2_b64 %[u1], %[u1], %[f1]\n"                   \
   "s_andn2_b64 %[u2], %[u2], %[f2]\n"                   \
   "s_andn2_b64 %[u3], %[u3], %[f3]\n"                   \
-  "s_or_b64 %[m0], %[u0], %[u1]\n"                      \
-  "s_or_b64 %[m0], %[m0], %[u2]\n"                      \
-  "s_or_b64 %[m0], %[m0], %[u3]\n"
+  "s_or_b64 %[m], %[u0], %[u1]\n"                       \
+  "s_or_b64 %[m], %[m], %[u2]\n"                        \
+  "s_or_b64 %[m], %[m], %[u3]\n"
 
 // SCC = (f0 != 0) after a compare; true when any f_i is non-zero.
 #define AERL_ANY_F(ALIVE)                               \
   "s_cbranch_scc1 " ALIVE "\n"                          \
-  "s_or_b64 %[m0], %[f1], %[f2]\n"                      \
-  "s_or_b64 %[m0], %[m0], %[f3]\n"                      \
+  "s_or_b64 %[m], %[f1], %[f2]\n"                      \
+  "s_or_b64 %[m], %[m], %[f3]\n"                      \
   "s_cbranch_scc1 " ALIVE "\n"
 
 #define AERL_U "%[u0]", "%[u1]", "%[u2]", "%[u3]"
@@ -281,7 +283,7 @@ __device__ __forceinline__ int eval_set_s4_count(uint32_t lds_lane, int lane, in
   const uint32_t end = (uint32_t)set.y * 16u;
   const int dflt = set.z;
   uint64_t u0 = vm[0], u1 = vm[1], u2 = vm[2], u3 = vm[3];
-  uint64_t f0, f1, f2, f3, m0, m1, m2, m3;
+  uint64_t f0, f1, f2, f3, m;
   uint32_t o, t0, t1, vt, vt2;
   int acc = 0;
   asm volatile(
@@ -290,16 +292,16 @@ __device__ __forceinline__ int eval_set_s4_count(uint32_t lds_lane, int lane, in
       "s_cbranch_scc1 .Ldefault_%=\n"
       // load the pair (o, o+16) into A, B
       ".Lfirst_%=:\n"
-      "s_load_dwordx8 s[84:91], %[base], %[o]\n"
+      "s_load_dwordx8 s[64:71], %[base], %[o]\n"
       "s_waitcnt lgkmcnt(0)\n"
       // first record of a rule in A: f = undecided & m
       ".Lstart_A_%=:\n"
-      AERL_RECORD_X("s84", "s85", "s86", "s87", AERL_U, ".Lffs_A_%=")
+      AERL_RECORD_X("s64", "s65", "s66", "s67", AERL_U, ".Lffs_A_%=")
       // after a record in A
       ".Lpost_A_%=:\n"
       AERL_ANY_F(".Lalive_A_%=")
       // the rule cannot fire for any undecided lane: next rule
-      "s_lshr_b32 %[t1], s87, 18\n"
+      "s_lshr_b32 %[t1], s67, 18\n"
       "s_add_u32 %[t0], %[o], 16\n"
       "s_cmp_ge_u32 %[t1], %[end]\n"
       "s_cbranch_scc1 .Ldefault_%=\n"
@@ -308,43 +310,43 @@ __device__ __forceinline__ int eval_set_s4_count(uint32_t lds_lane, int lane, in
       "s_cbranch_scc1 .Lstart_B_%=\n"
       "s_branch .Lfirst_%=\n"
       ".Lalive_A_%=:\n"
-      "s_bitcmp1_b32 s87, 11\n"
+      "s_bitcmp1_b32 s67, 11\n"
       "s_cbranch_scc1 .Lcommit_A_%=\n"
       "s_add_u32 %[o], %[o], 16\n"
       // later record of the same rule in B: f &= m
       ".Lnext_B_%=:\n"
-      AERL_RECORD_X("s88", "s89", "s90", "s91", AERL_F, ".Lffn_B_%=")
+      AERL_RECORD_X("s68", "s69", "s70", "s71", AERL_F, ".Lffn_B_%=")
       // after a record in B
       ".Lpost_B_%=:\n"
       AERL_ANY_F(".Lalive_B_%=")
-      "s_lshr_b32 %[o], s91, 18\n"
+      "s_lshr_b32 %[o], s71, 18\n"
       "s_cmp_lt_u32 %[o], %[end]\n"
       "s_cbranch_scc1 .Lfirst_%=\n"
       "s_branch .Ldefault_%=\n"
       ".Lalive_B_%=:\n"
-      "s_bitcmp1_b32 s91, 11\n"
+      "s_bitcmp1_b32 s71, 11\n"
       "s_cbranch_scc1 .Lcommit_B_%=\n"
       "s_add_u32 %[o], %[o], 16\n"
-      "s_load_dwordx8 s[84:91], %[base], %[o]\n"
+      "s_load_dwordx8 s[64:71], %[base], %[o]\n"
       "s_waitcnt lgkmcnt(0)\n"
       // later record of the same rule in A
-      AERL_RECORD_X("s84", "s85", "s86", "s87", AERL_F, ".Lffn_A_%=")
+      AERL_RECORD_X("s64", "s65", "s66", "s67", AERL_F, ".Lffn_A_%=")
       "s_branch .Lpost_A_%=\n"
       // first record of a rule in B
       ".Lstart_B_%=:\n"
-      AERL_RECORD_X("s88", "s89", "s90", "s91", AERL_U, ".Lffs_B_%=")
+      AERL_RECORD_X("s68", "s69", "s70", "s71", AERL_U, ".Lffs_B_%=")
       "s_branch .Lpost_B_%=\n"
       ".Lffs_A_%=:\n"
-      AERL_FF_BODY_X("s87", "s85", "s86", AERL_U, "sA", ".Lpost_A_%=")
+      AERL_FF_BODY_X("s67", "s65", "s66", AERL_U, "sA", ".Lpost_A_%=")
       ".Lffn_A_%=:\n"
-      AERL_FF_BODY_X("s87", "s85", "s86", AERL_F, "nA", ".Lpost_A_%=")
+      AERL_FF_BODY_X("s67", "s65", "s66", AERL_F, "nA", ".Lpost_A_%=")
       ".Lffs_B_%=:\n"
-      AERL_FF_BODY_X("s91", "s89", "s90", AERL_U, "sB", ".Lpost_B_%=")
+      AERL_FF_BODY_X("s71", "s69", "s70", AERL_U, "sB", ".Lpost_B_%=")
       ".Lffn_B_%=:\n"
-      AERL_FF_BODY_X("s91", "s89", "s90", AERL_F, "nB", ".Lpost_B_%=")
+      AERL_FF_BODY_X("s71", "s69", "s70", AERL_F, "nB", ".Lpost_B_%=")
       // the rule of the record in A fires; the next rule starts with B
       ".Lcommit_A_%=:\n"
-      AERL_COMMIT_COUNT("s87")
+      AERL_COMMIT_COUNT("s67")
       "s_cbranch_scc0 .Ldone_%=\n"
       "s_add_u32 %[o], %[o], 16\n"
       "s_cmp_lt_u32 %[o], %[end]\n"
@@ -352,7 +354,7 @@ __device__ __forceinline__ int eval_set_s4_count(uint32_t lds_lane, int lane, in
       "s_branch .Ldefault_%=\n"
       // the rule of the record in B fires; the next rule needs a new pair
       ".Lcommit_B_%=:\n"
-      AERL_COMMIT_COUNT("s91")
+      AERL_COMMIT_COUNT("s71")
       "s_cbranch_scc0 .Ldone_%=\n"
       "s_add_u32 %[o], %[o], 16\n"
       "s_cmp_lt_u32 %[o], %[end]\n"
@@ -366,12 +368,11 @@ __device__ __forceinline__ int eval_set_s4_count(uint32_t lds_lane, int lane, in
       "v_add_u32 %[acc], %[acc], %[vt]\n"
       ".Ldone_%=:\n"
       : [acc] "+v"(acc), [u0] "+s"(u0), [u1] "+s"(u1), [u2] "+s"(u2), [u3] "+s"(u3),
-        [f0] "=&s"(f0), [f1] "=&s"(f1), [f2] "=&s"(f2), [f3] "=&s"(f3), [m0] "=&s"(m0),
-        [m1] "=&s"(m1), [m2] "=&s"(m2), [m3] "=&s"(m3), [o] "=&s"(o), [t0] "=&s"(t0),
+        [f0] "=&s"(f0), [f1] "=&s"(f1), [f2] "=&s"(f2), [f3] "=&s"(f3), [m] "=&s"(m), [o] "=&s"(o), [t0] "=&s"(t0),
         [t1] "=&s"(t1), [vt] "=&v"(vt), [vt2] "=&v"(vt2)
       : [base] "s"(base), [end] "s"(end), [dflt] "s"(dflt), [lds] "v"(lds_lane),
         [lane] "v"(lane)
-      : "s84", "s85", "s86", "s87", "s88", "s89", "s90", "s91", "v32", "v33", "v34", "v35",
+      : "s64", "s65", "s66", "s67", "s68", "s69", "s70", "s71", "v32", "v33", "v34", "v35",
         "v36", "v37", "v38", "v39", "vcc", "scc", "memory");
   return acc;
 }

@@ -40,7 +40,7 @@ struct HardArgs {
 };
 
 template <int S>
-__global__ __launch_bounds__(kHardBlock) void k_hard(const HardArgs a) {
+__global__ __launch_bounds__(kHardBlock) AERL_HARD_SGPR_CAP void k_hard(const HardArgs a) {
   extern __shared__ __align__(16) float smem[];
   __shared__ int32_t next_q;
   // Which class region and which tiles this block covers (uniform loop).

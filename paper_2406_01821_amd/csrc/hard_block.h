@@ -9,6 +9,13 @@
 
 namespace aerl {
 
+// Kernels running hard_block with 1024-thread blocks: two such blocks share a
+// CU (eight waves per SIMD) only when a wave holds at most 80 SGPRs; measured
+// on gfx950, 82 already leaves room for one block.  The cap makes the
+// compiler keep within it (spilling a few loop-invariant values to VGPR lanes
+// outside the rule-set loop); the asm walk's fixed quads s[64:71] lie below it.
+#define AERL_HARD_SGPR_CAP __attribute__((amdgpu_num_sgpr(80)))
+
 struct HardTask {
   const float *x_fm;
   int64_t n_pad;

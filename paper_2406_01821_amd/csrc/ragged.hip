@@ -24,10 +24,9 @@ __global__ void k_batch_zero(const BatchZero *__restrict__ z, int32_t n_z, int32
   }
 }
 
-__global__ __launch_bounds__(kBatchBlock) void k_hard_batch(const BatchItem *__restrict__ items,
-                                                            const BatchTask *__restrict__ tasks,
-                                                            int32_t n_tasks,
-                                                            int32_t *__restrict__ counter) {
+__global__ __launch_bounds__(kBatchBlock) AERL_HARD_SGPR_CAP void k_hard_batch(
+    const BatchItem *__restrict__ items, const BatchTask *__restrict__ tasks, int32_t n_tasks,
+    int32_t *__restrict__ counter) {
   extern __shared__ __align__(16) float smem[];
   __shared__ int32_t next_q;
   __shared__ int32_t task_id;

@@ -267,3 +267,25 @@ def test_paired_record_walk_matches_oracle(aerl, seed):
             for t in range(0, len(rows), 256):
                 got[c] += walk_s4_pairs(rows[t:t + 256], sets, hc, s, n_records, 3)
         np.testing.assert_array_equal(got, ref[s], err_msg=f"set {s}")
+
+
+def test_hard_kernels_fit_two_blocks_per_cu(tmp_path):
+    """The 1024-thread hard-eval kernels must keep a wave's SGPR count at or
+    below 80, or two blocks no longer share a CU (half the resident waves);
+    a compile of the sources checks the kernel metadata."""
+    from paper_2406_01821_amd import build_lib
+    counts = {}
+    for src in ("hard.hip", "ragged.hip"):
+        out = tmp_path / (src + ".s")
+        build_lib.asm(src, str(out))
+        name = None
+        for line in out.read_text().splitlines():
+            m = re.match(r"\s+\.name:\s+(\S+)", line)
+            if m:
+                name = m.group(1)
+            m = re.match(r"\s+\.sgpr_count:\s+(\d+)", line)
+            if m and name:
+                counts[name] = int(m.group(1))
+    hard = {k: v for k, v in counts.items() if "k_hardILi4" in k or "k_hard_batch" in k}
+    assert len(hard) == 2, counts
+    assert all(v <= 80 for v in hard.values()), hard
