@@ -518,13 +518,20 @@ __device__ __forceinline__ void l_set(float (&L)[RMAX][S], int k, const float (&
 // still leaves 32 waves per CU.
 constexpr int kBwdRegBlock = 1024;
 
+// Eight waves per SIMD (two blocks per CU) need at most 64 VGPRs and 80
+// SGPRs per wave (the SGPR bound measured on gfx950): k_soft_bwd_reg is held
+// to that; the variants that keep two samples per lane over 16 or 32 rules
+// would spill VGPRs at that size and run as k_soft_bwd_reg_wide, one block
+// per CU.
+#define AERL_BWD_SGPR_CAP __attribute__((amdgpu_num_sgpr(80)))
+
 // TONLY: the population has threshold conditions only (no x[g] rows).
 // Rule sets of at most 64 conditions keep the wave totals of the current
 // walk in two VGPRs (lane i: condition i of the set) and add them to the
 // block accumulators once per walk; longer
 // rule sets add each condition's totals as they come.
 template <int S, int RMAX, class Acc, bool TONLY>
-__global__ __launch_bounds__(kBwdRegBlock) void k_soft_bwd_reg(const SoftArgs a) {
+__device__ __forceinline__ void soft_bwd_reg(const SoftArgs &a) {
   constexpr int TS = 64 * S, WPT = AERL_TILE / TS;
   extern __shared__ __align__(16) float smem[];
   float *xs = smem;                       // [nf][TS]
@@ -672,6 +679,17 @@ __global__ __launch_bounds__(kBwdRegBlock) void k_soft_bwd_reg(const SoftArgs a)
   }
 }
 
+template <int S, int RMAX, class Acc, bool TONLY>
+__global__ __launch_bounds__(kBwdRegBlock, 8) AERL_BWD_SGPR_CAP void k_soft_bwd_reg(
+    const SoftArgs a) {
+  soft_bwd_reg<S, RMAX, Acc, TONLY>(a);
+}
+
+template <int S, int RMAX, class Acc, bool TONLY>
+__global__ __launch_bounds__(kBwdRegBlock) void k_soft_bwd_reg_wide(const SoftArgs a) {
+  soft_bwd_reg<S, RMAX, Acc, TONLY>(a);
+}
+
 // One block per rule set: sums the group partials of its conditions in a
 // fixed order and applies dz/dparam = +-x/tau, -+1/tau and dloss/N.
 __global__ void k_soft_bwd_final(const float *__restrict__ part, int32_t n_groups,
@@ -743,7 +761,7 @@ SoftPlan plan_backward(const DatasetRec &ds, const PopRec &pop) {
     while (p.S > 1 && (size_t)ds.nf * 256 * p.S > 64 * 1024) p.S >>= 1;
     const size_t xs = (size_t)ds.nf * 64 * p.S * 4;
     p.Q = std::max(1, std::min(pop.n_sets, 64));
-    while (p.Q > 1 && xs + p.Q * per_set > 80 * 1024) p.Q >>= 1;
+    while (p.Q > 1 && xs + p.Q * per_set > kLdsPerCu / 2 - kStaticLds) p.Q >>= 1;  // two blocks per CU
     p.lds = xs + (size_t)p.Q * per_set;
     if (p.lds <= kDynLdsMax) return p;
   }
@@ -806,9 +824,9 @@ void launch_bwd_reg(const SoftPlan &p, dim3 grid, hipStream_t st, const SoftArgs
   } else if (p.rmax == 16 && p.S == 4) {
     hipLaunchKernelGGL((k_soft_bwd_reg<4, 16, Acc, TONLY>), grid, rb, p.lds, st, a);
   } else if (p.rmax == 16 && p.S == 2) {
-    hipLaunchKernelGGL((k_soft_bwd_reg<2, 16, Acc, TONLY>), grid, rb, p.lds, st, a);
+    hipLaunchKernelGGL((k_soft_bwd_reg_wide<2, 16, Acc, TONLY>), grid, rb, p.lds, st, a);
   } else if (p.rmax == 32 && p.S == 2) {
-    hipLaunchKernelGGL((k_soft_bwd_reg<2, 32, Acc, TONLY>), grid, rb, p.lds, st, a);
+    hipLaunchKernelGGL((k_soft_bwd_reg_wide<2, 32, Acc, TONLY>), grid, rb, p.lds, st, a);
   } else if (p.rmax == 8) {  // one sample per lane (wide datasets)
     hipLaunchKernelGGL((k_soft_bwd_reg<1, 8, Acc, TONLY>), grid, rb, p.lds, st, a);
   } else if (p.rmax == 16) {
