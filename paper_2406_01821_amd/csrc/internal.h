@@ -42,22 +42,37 @@ aerl_status fail(aerl_ctx *ctx, aerl_status code, const char *fmt, ...);
 // Soft rule set: {first rule, rule count, first condition, condition count}.
 // Rule (soft path): {first condition in the caller's order, condition count,
 //                    class, 0}.
-// Hard stream record (16 bytes), one per condition, rules of a set in order:
+// Hard stream record (16 bytes), one per condition, rules of a set in order,
+// then one closing record per set:
 //   x: f*1024 (byte offset of the feature row in a 256-sample LDS tile)
-//   y: a (fp32), z: b (fp32)
-//   w: g | kRecFF | kRecGE | kRecLast | class << 12 | next << 18, where next is
-//      the byte offset (from the set's first record) of the next rule's
-//      first record.
-// Threshold records test a*x[f] > b; feature records a*x[f] > b*x[g] or, with
-// kRecGE, a*x[f] >= b*x[g].  Rewriting the caller's form is exact (pack.cpp).
+//   y, z: fp32 operands (below)
+//   w: flags | class << 12 | next << 18, where next is the byte offset (from
+//      the set's first record) of the next rule's first record.
+// Kinds (all exact rewrites of the caller's condition, pack.cpp):
+//   threshold, folded:      x[f] >= y            (no flag)
+//                           x[f] <= y            (kRecLE)
+//   threshold, zero coef:   y*x[f] > z           (kRecMul)
+//   always true:            empty rule           (kRecAlways)
+//   feature:                y*x[f] > z*x[g]      (kRecFF, g in the low bits)
+//                           y*x[f] >= z*x[g]     (kRecFF | kRecGE)
+// kRecLast marks a rule's last record.  The closing record is an always-true
+// last record of the set's default class, so every walk ends in a commit.
 // Soft condition (caller order): f | g << 12 | kind << 24 | (op >= 2) << 25.
 constexpr uint32_t kRecGMask = 0x1ffu;
+constexpr uint32_t kRecMul = 1u << 0;     // threshold records only
+constexpr uint32_t kRecAlways = 1u << 1;  // threshold records only
 constexpr uint32_t kRecFF = 1u << 9;
-constexpr uint32_t kRecGE = 1u << 10;
+constexpr uint32_t kRecGE = 1u << 10;  // feature records
+constexpr uint32_t kRecLE = 1u << 10;  // threshold records
 constexpr uint32_t kRecLast = 1u << 11;
+// Records that leave the counting walk's fast path (the folded >= / <=
+// compare of a rule's non-last record).
+constexpr uint32_t kRecSpecial = kRecFF | kRecLast | kRecMul | kRecAlways;
 constexpr uint32_t kRecClsShift = 12;
 constexpr uint32_t kRecNextShift = 18;
-constexpr int32_t kMaxSetRecords = 1023;  // next-rule byte offsets fit 14 bits
+// Records of one rule set, closing record included: next-rule byte offsets
+// fit 14 bits.
+constexpr int32_t kMaxSetRecords = 1023;
 struct PackedLayout {
   size_t sets_off, ssets_off, rules_off, hconds_off, sconds_off, total;
 };

@@ -19,6 +19,7 @@
 // Products and comparisons are IEEE fp32 and never NaN for finite inputs, so
 // each rewrite gives the caller's result bit for bit.
 #include <algorithm>
+#include <cfloat>
 #include <cmath>
 #include <cstdarg>
 #include <cstring>
@@ -44,12 +45,86 @@ uint32_t fbits(float v) {
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
+// Position of a non-NaN float in the order -inf < ... < -0 < +0 < ... < +inf.
+int64_t fkey(float v) {
+  const uint32_t u = fbits(v);
+  return (u >> 31) ? -(int64_t)(u & 0x7fffffffu) - 1 : (int64_t)u;
+}
+
+float fkey_float(int64_t k) {
+  const uint32_t u = k >= 0 ? (uint32_t)k : (0x80000000u | (uint32_t)(-(k + 1)));
+  float v;
+  std::memcpy(&v, &u, 4);
+  return v;
+}
+
+// The product a*x (one fp32 rounding) against b.
+bool passes(float a, float x, float b, bool strict) {
+  const float p = a * x;
+  return strict ? p > b : p >= b;
+}
+
+// Threshold folding.  For a > 0 and b not NaN, x -> fl(a*x) is monotone
+// non-decreasing over the floats (rounding is monotone; -0 and +0 give equal
+// products), so the x that pass form an upper interval of the order above.
+// Returns its least element (NaN when no x passes), which turns the test
+// into the single compare x >= t, exact for every x including +-inf and NaN.
+// Bisection over the order, started from b/a and its neighbours, which
+// settles almost every case in a few products.
+float fold_least(float a, float b, bool strict) {
+  if (!passes(a, INFINITY, b, strict)) return NAN;
+  if (passes(a, -INFINITY, b, strict)) return -INFINITY;
+  int64_t lo = fkey(-INFINITY), hi = fkey(INFINITY);  // lo fails, hi passes
+  const float q = (float)((double)b / (double)a);
+  if (!std::isnan(q)) {
+    const int64_t k = std::min(std::max(fkey(q), lo + 1), hi - 1);
+    if (passes(a, fkey_float(k), b, strict)) {
+      hi = k;
+      if (k - 2 > lo && !passes(a, fkey_float(k - 2), b, strict)) lo = k - 2;
+    } else {
+      lo = k;
+      if (k + 2 < hi && passes(a, fkey_float(k + 2), b, strict)) hi = k + 2;
+    }
+  }
+  while (hi - lo > 1) {
+    const int64_t mid = lo + (hi - lo) / 2;
+    if (passes(a, fkey_float(mid), b, strict)) hi = mid;
+    else lo = mid;
+  }
+  return fkey_float(hi);
+}
+
+// Threshold record for coef*x[f] op theta: (y, z, flags).
+void threshold_record(float c, float t, int op, float *y, float *z, uint32_t *flags) {
+  // c*x > t, c*x >= t as they are; c*x < t as (-c)*x > -t (negation is exact)
+  const bool strict = op == AERL_OP_GT || op == AERL_OP_LT;
+  const bool neg = op == AERL_OP_LT || op == AERL_OP_LE;
+  const float a = neg ? -c : c, b = neg ? -t : t;
+  if (a > 0.0f) {
+    *y = fold_least(a, b, strict);
+    *z = b;
+    *flags = 0;
+  } else if (a < 0.0f) {
+    // a*x = (-a)*(-x) exactly: the passing x form a lower interval
+    *y = -fold_least(-a, b, strict);
+    *z = b;
+    *flags = kRecLE;
+  } else {
+    // zero coefficient: the product is +-0 for finite x and NaN otherwise;
+    // >= b on those values is > the float below b (> -max for b = -inf)
+    *y = a;
+    *z = strict ? b : (b == -INFINITY ? -FLT_MAX : std::nextafter(b, -INFINITY));
+    *flags = kRecMul;
+  }
+}
+
 }  // namespace
 
 PackedLayout packed_layout(int32_t n_sets, int32_t n_rules, int32_t n_conds) {
-  // The hard stream holds one record per condition plus one per empty rule;
-  // n_rules + n_conds bounds it.  One spare record keeps a read-ahead of the
-  // record after the last one inside the buffer.
+  // The hard stream holds one record per condition, one per empty rule and
+  // one closing record per set; n_conds + n_rules + n_sets bounds it.  One
+  // spare record keeps a read-ahead of the record after the last one inside
+  // the buffer.
   PackedLayout L{};
   size_t off = 0;
   L.sets_off = off;
@@ -59,7 +134,7 @@ PackedLayout packed_layout(int32_t n_sets, int32_t n_rules, int32_t n_conds) {
   L.rules_off = off;
   off = align256(off + sizeof(int4) * (size_t)(n_rules > 0 ? n_rules : 1));
   L.hconds_off = off;
-  off = align256(off + sizeof(uint4) * ((size_t)n_conds + (size_t)n_rules + 1));
+  off = align256(off + sizeof(uint4) * ((size_t)n_conds + (size_t)n_rules + (size_t)std::max(n_sets, 0) + 1));
   L.sconds_off = off;
   off = align256(off + sizeof(uint32_t) * (size_t)(n_conds > 0 ? n_conds : 1));
   L.total = off;
@@ -121,9 +196,9 @@ aerl_status validate_population(aerl_ctx *ctx, const aerl_population *p, int32_t
     int32_t recs = 0;
     for (int32_t r = p->set_rule_off[s]; r < p->set_rule_off[s + 1]; ++r)
       recs += std::max(p->rule_cond_off[r + 1] - p->rule_cond_off[r], 1);
-    if (recs > kMaxSetRecords)
+    if (recs + 1 > kMaxSetRecords)
       return fail(ctx, AERL_EINVAL, "rule set %d has %d conditions (+1 per empty rule); max %d", s,
-                  recs, kMaxSetRecords);
+                  recs, kMaxSetRecords - 1);
   }
   if (n_rules_out) *n_rules_out = n_rules;
   if (n_conds_out) *n_conds_out = n_conds;
@@ -145,9 +220,10 @@ void pack_population_image(const aerl_population *p, int32_t nf, int32_t nc, int
   uint32_t *sc = reinterpret_cast<uint32_t *>(base + L.sconds_off);
   int32_t max_rules = 0, max_rule_conds = 0;
   int64_t nominal = 0;
-  // Hard stream: for each rule set its rules in order; inside a rule the
-  // threshold conditions first, then feature >, then feature >=.  An empty
-  // rule (always fires) becomes one always-true record 0*x[0] > -1.
+  // Hard stream: for each rule set its rules in order, then a closing
+  // always-true record of the default class; inside a rule the threshold
+  // conditions first, then feature >, then feature >=.  An empty rule (always
+  // fires) becomes one always-true record.
   int32_t out = 0;
   for (int32_t s = 0; s < p->n_sets; ++s) {
     const int32_t r0 = p->set_rule_off[s], r1 = p->set_rule_off[s + 1];
@@ -160,7 +236,7 @@ void pack_population_image(const aerl_population *p, int32_t nf, int32_t nc, int
       const uint32_t cls = (uint32_t)p->rule_class[r] << kRecClsShift;
       const uint32_t next = (uint32_t)(out - first + std::max(k, 1)) * 16u << kRecNextShift;
       if (k == 0) {
-        hc[out++] = make_uint4(0u, fbits(0.0f), fbits(-1.0f), kRecLast | cls | next);
+        hc[out++] = make_uint4(0u, 0u, 0u, kRecAlways | kRecLast | cls | next);
         continue;
       }
       int32_t pos = 0;
@@ -173,19 +249,9 @@ void pack_population_image(const aerl_population *p, int32_t nf, int32_t nc, int
           float a, b;
           uint32_t w = cls | next;
           if (!ff) {
-            const float c = p->coef[j], t = p->theta[j];
-            switch (op) {
-              case AERL_OP_GT: a = c; b = t; break;
-              case AERL_OP_LT: a = -c; b = -t; break;
-              case AERL_OP_GE:
-                if (t == -INFINITY) { a = 0.0f; b = -1.0f; }
-                else { a = c; b = std::nextafter(t, -INFINITY); }
-                break;
-              default:  // AERL_OP_LE
-                if (t == INFINITY) { a = 0.0f; b = -1.0f; }
-                else { a = -c; b = -std::nextafter(t, INFINITY); }
-                break;
-            }
+            uint32_t flags;
+            threshold_record(p->coef[j], p->theta[j], op, &a, &b, &flags);
+            w |= flags;
           } else {
             const bool neg = op == AERL_OP_LT || op == AERL_OP_LE;
             a = neg ? -p->coef[j] : p->coef[j];
@@ -198,6 +264,9 @@ void pack_population_image(const aerl_population *p, int32_t nf, int32_t nc, int
         }
       }
     }
+    const uint32_t end = (uint32_t)(out - first + 1) * 16u << kRecNextShift;
+    hc[out++] = make_uint4(0u, 0u, 0u,
+                           kRecAlways | kRecLast | (uint32_t)p->set_default[s] << kRecClsShift | end);
     sets[s] = make_int4(first, out - first, p->set_default[s], nominal_s);
     ssets[s] = make_int4(r0, r1 - r0, r1 > r0 ? p->rule_cond_off[r0] : 0, nominal_s);
     if (nominal_s > rec->max_set_conds) rec->max_set_conds = nominal_s;

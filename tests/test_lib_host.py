@@ -70,9 +70,11 @@ def test_population_validation_rejects_structure(aerl):
     assert aerl.population_status(bad_default, 5, 2) == aerl.AERL_EINVAL
     big = from_rule_lists([(0, [(1, [_cond()] * 256)])])
     assert aerl.population_status(big, 5, 2) == aerl.AERL_EINVAL
-    many = from_rule_lists([(0, [(1, [_cond()] * 200)] * 5 + [(0, [])] * 24)])
-    assert aerl.population_status(many, 5, 2) == aerl.AERL_EINVAL  # 1024 records
-    ok_many = from_rule_lists([(0, [(1, [_cond()] * 200)] * 5 + [(0, [])] * 23)])
+    # at most 1022 records per set (conditions, +1 per empty rule) besides
+    # the closing default record
+    many = from_rule_lists([(0, [(1, [_cond()] * 200)] * 5 + [(0, [])] * 23)])
+    assert aerl.population_status(many, 5, 2) == aerl.AERL_EINVAL
+    ok_many = from_rule_lists([(0, [(1, [_cond()] * 200)] * 5 + [(0, [])] * 22)])
     assert aerl.population_status(ok_many, 5, 2) == 0
     inf_theta = from_rule_lists([(0, [(1, [_cond(theta=np.float32(np.inf))])])])
     assert aerl.population_status(inf_theta, 5, 2) == 0
@@ -89,43 +91,61 @@ def decode_packed(img, n_sets, n_rules, n_conds):
     rules_off = _align(ssets_off + 16 * max(n_sets, 1))
     hc_off = _align(rules_off + 16 * max(n_rules, 1))
     sets = img[sets_off:sets_off + 16 * n_sets].view(np.int32).reshape(-1, 4)
-    n_rec = n_conds + n_rules + 1
+    n_rec = n_conds + n_rules + n_sets + 1
     hc = img[hc_off:hc_off + 16 * n_rec].view(np.uint32).reshape(-1, 4)
     return sets, hc
 
 
+FF, GE_LE, LAST, MUL, ALWAYS = 1 << 9, 1 << 10, 1 << 11, 1 << 0, 1 << 1
+
+
+def record_mask(x, r):
+    """Samples of x for which packed record r holds, in float32 numpy
+    arithmetic: x[f] >= y, x[f] <= y, y*x[f] > z, always, y*x[f] > z*x[g] or
+    y*x[f] >= z*x[g]."""
+    f1024, a, b, w = r
+    a = np.uint32(a).view(np.float32)
+    b = np.uint32(b).view(np.float32)
+    xf = x[:, f1024 // 1024]
+    if w & FF:
+        lhs = np.float32(a) * xf
+        rhs = np.float32(b) * x[:, w & 0x1ff]
+        return lhs >= rhs if w & GE_LE else lhs > rhs
+    if w & ALWAYS:
+        return np.ones(x.shape[0], bool)
+    if w & MUL:
+        return np.float32(a) * xf > b
+    return xf <= a if w & GE_LE else xf >= a
+
+
 def eval_packed(x, sets, hc, s):
-    """Walks the packed record stream of rule set s with float32 numpy
-    arithmetic: a*x[f] > b, a*x[f] > b*x[g] or a*x[f] >= b*x[g]; a rule whose
-    records all hold for a sample gives that sample its class."""
+    """Walks the packed record stream of rule set s: a rule whose records all
+    hold for a sample gives that sample its class; the set's closing record
+    (always true, default class) takes the samples no rule fired for."""
     n = x.shape[0]
     first, count, default, _ = sets[s]
-    pred = np.full(n, default, np.int32)
+    pred = np.full(n, -1, np.int32)
     und = np.ones(n, bool)
     fire = und.copy()
     o = 0
+    last = tuple(int(v) for v in hc[first + count - 1])
+    assert last[3] & (ALWAYS | LAST) == ALWAYS | LAST and (last[3] >> 12) & 63 == default
     while o < count * 16:
-        f1024, a, b, w = (int(v) for v in hc[first + o // 16])
-        a = np.uint32(a).view(np.float32)
-        b = np.uint32(b).view(np.float32)
-        lhs = np.float32(a) * x[:, f1024 // 1024]
-        if not w & (1 << 9):
-            m = lhs > b
-        else:
-            rhs = np.float32(b) * x[:, w & 0x1ff]
-            m = lhs >= rhs if w & (1 << 10) else lhs > rhs
-        fire &= m
+        r = tuple(int(v) for v in hc[first + o // 16])
+        w = r[3]
+        fire &= record_mask(x, r)
         nxt = o + 16
-        if w & (1 << 11):
+        if w & LAST:
             assert nxt == w >> 18
         if not fire.any():
             nxt = w >> 18
             fire = und.copy()
-        elif w & (1 << 11):
+        elif w & LAST:
             pred[fire] = (w >> 12) & 63
             und &= ~fire
             fire = und.copy()
         o = nxt
+    assert not und.any()
     return pred
 
 
@@ -137,10 +157,15 @@ def test_packed_rewrite_is_exact_against_oracle(aerl):
     x[20:40, 0] = -0.0
     x[40:60, 1] = np.float32(1.5)
     x[60:70, 2] = np.float32(3e38)
+    x[70:75, 3] = np.inf
+    x[75:80, 3] = -np.inf
+    x[80:85, 3] = np.nan
+    x[85:90, 1] = np.float32(1e-45)
+    x[90:95, 1] = np.float32(-3.4e38)
     conds = []
     for op in range(4):
         for t in (1.5, 0.0, -0.0, np.inf, -np.inf, 1e-45, -1e-45, 3.4e38, -2.25):
-            for c in (1.0, -1.0, 0.0, 0.5, 2.0):
+            for c in (1.0, -1.0, 0.0, -0.0, 0.5, 2.0, 1e-45, -3e38):
                 conds.append(_cond(op=op, f=int(rng.integers(4)), coef=np.float32(c), theta=np.float32(t)))
         for c, c2 in ((1.0, 1.0), (-1.0, 0.5), (0.0, 0.0), (2.0, -3.0)):
             conds.append(_cond(op=op, kind=1, f=1, g=2, coef=np.float32(c), coef2=np.float32(c2)))
@@ -156,16 +181,53 @@ def test_packed_rewrite_is_exact_against_oracle(aerl):
                                       err_msg=str(s))
 
 
+@pytest.mark.parametrize("seed", range(3))
+def test_threshold_folding_is_exact_at_the_boundary(aerl, seed):
+    """Folded thresholds (x >= t or x <= t) against the oracle's fp32
+    product compare on the floats around every boundary: for random
+    coefficients and thresholds over many binades and both signs, the
+    samples are t/c and its 8 nearest floats on each side, plus +-0, +-inf
+    and NaN, for all four operators."""
+    np.seterr(all="ignore")
+    rng = np.random.default_rng(100 + seed)
+    n_cond = 120
+    c = (rng.choice([-1.0, 1.0], n_cond) * 10.0 ** rng.uniform(-30, 30, n_cond)).astype(np.float32)
+    t = (rng.choice([-1.0, 1.0], n_cond) * 10.0 ** rng.uniform(-30, 30, n_cond)).astype(np.float32)
+    c[:4] = np.float32([1e-45, -1e-45, 3e38, -3e38])
+    t[4:8] = np.float32([0.0, -0.0, 3.4e38, -3.4e38])
+    cols = []
+    for j in range(n_cond):
+        q = np.float32(np.float64(t[j]) / np.float64(c[j]))
+        near = [q]
+        up = down = q
+        for _ in range(8):
+            up = np.nextafter(up, np.float32(np.inf))
+            down = np.nextafter(down, np.float32(-np.inf))
+            near += [up, down]
+        cols.append(near)
+    col = np.concatenate([np.array(v, np.float32) for v in cols] +
+                         [np.float32([0.0, -0.0, np.inf, -np.inf, np.nan, 1e-45, -1e-45])])
+    x = col[:, None].astype(np.float32)
+    conds = [_cond(op=op, f=0, coef=c[j], theta=t[j]) for j in range(n_cond) for op in range(4)]
+    pop = from_rule_lists([(0, [(1, [cd])]) for cd in conds])
+    img = aerl.pack_host(pop, 1, 2)
+    S, H = decode_packed(img, pop.n_sets, pop.n_rules, pop.n_conds)
+    for s in range(pop.n_sets):
+        np.testing.assert_array_equal(eval_packed(x, S, H, s), oracle.predict(x, pop, s),
+                                      err_msg=f"set {s}: {conds[s]}")
+
+
 def walk_s4_pairs(x, sets, hc, s, n_records, n_classes):
     """Label-for-label model of the hard kernel's four-slot record walk,
     which loads records two at a time into register quads A (offset o) and
     B (o+16): a rule that goes on past an A record, or starts right after
-    one, continues from B without a load.  Checks that every compare uses
-    the record at its offset, that every pair read stays inside the stream,
-    and that the walk ends.  Returns per-class prediction counts for the
-    rows of x."""
+    one, continues from B without a load.  Non-last folded threshold records
+    take the fast path (no LAST test); special records (feature, zero
+    coefficient, always true, last) branch out.  Checks that every compare
+    uses the record at its offset, that every pair read stays inside the
+    stream, that always-true records only start rules, and that the walk
+    ends.  Returns per-class prediction counts for the rows of x."""
     first, count, default, _ = (int(v) for v in sets[s])
-    end = count * 16
     u = np.ones(x.shape[0], bool)
     f = None
     counts = np.zeros(n_classes, np.int64)
@@ -175,74 +237,59 @@ def walk_s4_pairs(x, sets, hc, s, n_records, n_classes):
         assert 0 <= first + off // 16 < n_records, "read outside the stream"
         return tuple(int(v) for v in hc[first + off // 16])
 
-    def compare(r, src):
-        f1024, a, b, w = r
-        a = np.uint32(a).view(np.float32)
-        b = np.uint32(b).view(np.float32)
-        lhs = np.float32(a) * x[:, f1024 // 1024]
-        if not w & (1 << 9):
-            m = b < lhs
-        else:
-            rhs = np.float32(b) * x[:, w & 0x1ff]
-            m = lhs >= rhs if w & (1 << 10) else lhs > rhs
-        return src & m
-
-    def commit(w):
-        nonlocal u
-        counts[(w >> 12) & 63] += int(f.sum())
-        u &= ~f
-        return u.any()
-
     o = 0
-    state = "default" if end == 0 else "first"
+    if not u.any():
+        return counts
+    state = "load"
     for _ in range(4 * count + 8):
-        if state == "first":
+        if state in ("load", "next_load"):
+            if state == "next_load":
+                o += 32
             quad["A"], quad["B"] = rec(o), rec(o + 16)
-            state = "start_A"
-        elif state in ("start_A", "next_A", "start_B", "next_B"):
-            X = state[-1]
-            assert quad[X] == rec(o), "compared a stale record"
-            f = compare(quad[X], u if state.startswith("start") else f)
-            state = "post_" + X
-        elif state == "post_A":
-            w = quad["A"][3]
+            state = ("A", "start" if state == "load" else "next")
+            continue
+        X, mode = state
+        r = quad[X]
+        assert r == rec(o if X == "A" else o + 16), "compared a stale record"
+        w = r[3]
+        src = u if mode == "start" else f
+        cls = (w >> 12) & 63
+        if not w & 0xa03:  # fast path: a folded threshold, not a rule's last record
+            f = src & record_mask(x, r)
             if f.any():
-                if w & (1 << 11):
-                    if not commit(w):
-                        return counts
-                    o += 16
-                    state = "start_B" if o < end else "default"
-                else:
-                    o += 16
-                    state = "next_B"
-            else:
-                t1 = w >> 18
-                if t1 >= end:
-                    state = "default"
-                elif t1 == o + 16:
-                    o = t1
-                    state = "start_B"
-                else:
-                    o = t1
-                    state = "first"
-        elif state == "post_B":
-            w = quad["B"][3]
-            if f.any():
-                if w & (1 << 11):
-                    if not commit(w):
-                        return counts
-                    o += 16
-                    state = "first" if o < end else "default"
-                else:
-                    o += 16
-                    quad["A"], quad["B"] = rec(o), rec(o + 16)
-                    state = "next_A"
+                state = ("B", "next") if X == "A" else "next_load"
             else:
                 o = w >> 18
-                state = "first" if o < end else "default"
-        else:
-            counts[default] += int(u.sum())
+                state = "load"
+            continue
+        if not w & FF and w & ALWAYS:
+            assert mode == "start", "always-true record inside a rule"
+            counts[cls] += int(u.sum())
             return counts
+        f = src & record_mask(x, r)
+        alive, last = f.any(), bool(w & LAST)
+        if alive and last:
+            counts[cls] += int(f.sum())
+            u &= ~f
+            if not u.any():
+                return counts
+        if X == "A":
+            if alive and not last:
+                state = ("B", "next")
+            elif last:
+                state = ("B", "start")
+            else:
+                o = w >> 18
+                state = "load"
+        else:
+            if alive and not last:
+                state = "next_load"
+            elif alive:
+                o += 32
+                state = "load"
+            else:
+                o = w >> 18
+                state = "load"
     raise AssertionError("record walk did not end")
 
 
@@ -258,7 +305,7 @@ def test_paired_record_walk_matches_oracle(aerl, seed):
     x, y, pop = w.data.x, w.data.y, w.pop
     img = aerl.pack_host(pop, 9, 3)
     sets, hc = decode_packed(img, pop.n_sets, pop.n_rules, pop.n_conds)
-    n_records = pop.n_conds + pop.n_rules + 1
+    n_records = pop.n_conds + pop.n_rules + pop.n_sets + 1
     _, ref = oracle.hard_eval(x, y, 3, pop)
     for s in range(pop.n_sets):
         got = np.zeros((3, 3), np.int64)
