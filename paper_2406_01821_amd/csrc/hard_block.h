@@ -16,6 +16,8 @@ namespace aerl {
 // outside the rule-set loop); the asm walk's fixed quads s[64:71] lie below it.
 #define AERL_HARD_SGPR_CAP __attribute__((amdgpu_num_sgpr(80)))
 
+typedef float f4v __attribute__((ext_vector_type(4)));
+
 struct HardTask {
   const float *x_fm;
   int64_t n_pad;
@@ -54,7 +56,10 @@ __device__ __forceinline__ void hard_block(const HardTask &t, float *smem, int32
     const int64_t base4 = wt * (TS / 4);
     for (int i = threadIdx.x; i < n4; i += blockDim.x) {
       const int f = i / (TS / 4), k = i % (TS / 4);
-      dst[i] = src[(int64_t)f * row4 + base4 + k];
+      // streamed once per block: a non-temporal load keeps it from pushing
+      // the rule records out of the L2
+      reinterpret_cast<f4v *>(dst)[i] =
+          __builtin_nontemporal_load(reinterpret_cast<const f4v *>(src + (int64_t)f * row4 + base4 + k));
     }
     if (threadIdx.x == 0) *next_q = 0;
     __syncthreads();

@@ -69,23 +69,28 @@ bool passes(float a, float x, float b, bool strict) {
 // products), so the x that pass form an upper interval of the order above.
 // Returns its least element (NaN when no x passes), which turns the test
 // into the single compare x >= t, exact for every x including +-inf and NaN.
-// Bisection over the order, started from b/a and its neighbours, which
-// settles almost every case in a few products.
+// The least element is found next to b/a in almost every case (a few
+// products, each answer checked against its neighbour below); otherwise by
+// bisection over the order.
 float fold_least(float a, float b, bool strict) {
+  const float q = (float)((double)b / (double)a);
+  if (std::isfinite(q)) {
+    int64_t k = fkey(q);
+    bool pk = passes(a, q, b, strict);
+    for (int step = 0; step < 4; ++step) {
+      if (pk) {  // k passes: the answer unless k-1 passes too
+        if (!passes(a, fkey_float(k - 1), b, strict)) return fkey_float(k);
+        --k;
+      } else {  // k fails: the answer is k+1 if it passes
+        ++k;
+        pk = passes(a, fkey_float(k), b, strict);
+        if (pk) return fkey_float(k);
+      }
+    }
+  }
   if (!passes(a, INFINITY, b, strict)) return NAN;
   if (passes(a, -INFINITY, b, strict)) return -INFINITY;
   int64_t lo = fkey(-INFINITY), hi = fkey(INFINITY);  // lo fails, hi passes
-  const float q = (float)((double)b / (double)a);
-  if (!std::isnan(q)) {
-    const int64_t k = std::min(std::max(fkey(q), lo + 1), hi - 1);
-    if (passes(a, fkey_float(k), b, strict)) {
-      hi = k;
-      if (k - 2 > lo && !passes(a, fkey_float(k - 2), b, strict)) lo = k - 2;
-    } else {
-      lo = k;
-      if (k + 2 < hi && passes(a, fkey_float(k + 2), b, strict)) hi = k + 2;
-    }
-  }
   while (hi - lo > 1) {
     const int64_t mid = lo + (hi - lo) / 2;
     if (passes(a, fkey_float(mid), b, strict)) hi = mid;
