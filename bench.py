@@ -146,15 +146,20 @@ def bench_soft(ctx, steps, warmup, cpu):
     log(f"soft forward {fwd_ms:.3f} ms, backward {bwd_ms:.3f} ms")
     if cpu:
         tau = oracle.tau(w.data.x)
-        sub = w.pop.subset(range(4))
-        t0 = time.perf_counter()
-        oracle.soft_forward(w.data.x, w.data.y, tau, 2, sub)
-        dt = time.perf_counter() - t0
+        k = 4
+        while True:  # grow the sample to about 10 s of CPU work
+            sub = w.pop.subset(range(k))
+            t0 = time.perf_counter()
+            oracle.soft_forward(w.data.x, w.data.y, tau, 2, sub)
+            dt = time.perf_counter() - t0
+            if dt * 2 > 10.0 or k * 2 > w.pop.n_sets:
+                break
+            k = min(w.pop.n_sets, int(k * max(2.0, 10.0 / max(dt, 1e-3) / 2)))
         sub_conds = int(sub.nominal_conds_per_set().sum()) * n
         out["cpu_baseline_forward"] = {"value": sub_conds / dt, "unit": "cond-evals/s",
                                        "cores": oracle.max_threads(), "kind": "oracle",
-                                       "sample": f"first 4 of 1024 rule sets x all {n} samples, "
-                                                 f"fp64, {dt:.2f} s"}
+                                       "sample": f"first {k} of {w.pop.n_sets} rule sets x all "
+                                                 f"{n} samples, fp64, {dt:.2f} s"}
     ctx.release_population(pop)
     ctx.release_dataset(ds)
     return out
