@@ -198,6 +198,35 @@ def tiny(seed: int, n: int = 100, nf: int = 8, n_classes: int = 2, n_sets: int =
     return Workload(Dataset(x, y, n_classes, f"tiny{n}x{nf}"), pop, f"tiny-{seed}")
 
 
+def special_values_population(seed: int, nf: int, n_classes: int, n_sets: int) -> Population:
+    """Rule sets of 1-9 rules x 0-6 conditions whose coefficients and
+    thresholds come from a list of special values (signed zeros, tiny and
+    huge magnitudes, +-inf thresholds), 30% feature-vs-feature, empty rules
+    anywhere (for edge-case tests)."""
+    from .population import from_rule_lists
+    rng = np.random.default_rng(seed)
+    coefs = np.float32([0.0, -0.0, 1.0, -1.0, 0.5, -2.0, 1e-30, 3e38])
+    thetas = np.float32([0.0, -0.0, 0.25, -1.5, np.inf, -np.inf, 1e-40])
+    sets = []
+    for _ in range(n_sets):
+        rules = []
+        for _ in range(int(rng.integers(1, 10))):
+            conds = []
+            for _ in range(int(rng.integers(0, 7))):
+                op = int(rng.integers(4))
+                f = int(rng.integers(nf))
+                if rng.random() < 0.3:
+                    g = int((f + 1 + rng.integers(nf - 1)) % nf)
+                    conds.append(dict(op=op, kind=1, f=f, g=g, coef=rng.choice(coefs),
+                                      coef2=rng.choice(coefs)))
+                else:
+                    conds.append(dict(op=op, kind=0, f=f, coef=rng.choice(coefs),
+                                      theta=rng.choice(thetas)))
+            rules.append((int(rng.integers(n_classes)), conds))
+        sets.append((int(rng.integers(n_classes)), rules))
+    return from_rule_lists(sets)
+
+
 @dataclass
 class Request:
     kind: str            # "fitness" or "predict"

@@ -119,6 +119,34 @@ def test_edge_values_subnormals_infinities_ties(ctx):
     check_against_oracle(ctx, Dataset(x, y, 2), pop)
 
 
+def test_special_records_inside_long_rules(ctx):
+    """Rules of up to 6 conditions mixing every record kind at every
+    position of the paired walk: folded thresholds in both directions, zero
+    coefficients (product form), +-inf thresholds, feature-vs-feature, and
+    empty rules anywhere in a set; fitness against the oracle, and
+    prediction on rows holding +-inf and NaN."""
+    import torch
+    rng = np.random.default_rng(21)
+    n, nf = 3000, 6
+    x = rng.uniform(-2, 2, size=(n, nf)).astype(np.float32)
+    x[:200, 0] = 0.0
+    x[200:300, 1] = np.float32(-0.0)
+    x[300:400, 2] = np.float32(1e-40)
+    y = rng.integers(0, 3, n).astype(np.int32)
+    pop = synth.special_values_population(22, nf, 3, 80)
+    check_against_oracle(ctx, Dataset(x, y, 3), pop)
+    rows = x[:500].copy()
+    rows[::7, 0] = np.inf
+    rows[::11, 1] = -np.inf
+    rows[::13, 2] = np.nan
+    p = ctx.pack_population(pop, nf, 3)
+    for s in range(0, pop.n_sets, 5):
+        got = ctx.predict(p, rows, s)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(got.cpu().numpy(), oracle.predict(rows, pop, s),
+                                      err_msg=f"set {s}")
+
+
 def test_empty_population_rules_and_sets(ctx):
     w = synth.tiny(3, n=500, nf=5)
     pop = from_rule_lists([(1, []), (0, [(1, [])]), (1, [(0, []), (1, [])])] +

@@ -316,6 +316,35 @@ def test_paired_record_walk_matches_oracle(aerl, seed):
         np.testing.assert_array_equal(got, ref[s], err_msg=f"set {s}")
 
 
+def test_record_walk_with_special_values(aerl):
+    """The walk model on rule sets mixing every record kind at every pair
+    position (signed zeros, zero coefficients, +-inf thresholds, empty
+    rules), against the oracle."""
+    np.seterr(all="ignore")
+    rng = np.random.default_rng(23)
+    x = rng.uniform(-2, 2, size=(512, 6)).astype(np.float32)
+    x[:60, 0] = 0.0
+    x[60:90, 1] = np.float32(-0.0)
+    y = np.repeat(np.arange(2, dtype=np.int32), 256)
+    pop = synth.special_values_population(24, 6, 2, 60)
+    img = aerl.pack_host(pop, 6, 2)
+    sets, hc = decode_packed(img, pop.n_sets, pop.n_rules, pop.n_conds)
+    n_records = pop.n_conds + pop.n_rules + pop.n_sets + 1
+    _, ref = oracle.hard_eval(x, y, 2, pop)
+    for s in range(pop.n_sets):
+        got = np.zeros((2, 2), np.int64)
+        for c in range(2):
+            got[c] = walk_s4_pairs(x[y == c], sets, hc, s, n_records, 2)
+        np.testing.assert_array_equal(got, ref[s], err_msg=f"set {s}")
+    rows = x[:200].copy()
+    rows[::7, 0] = np.inf
+    rows[::11, 1] = -np.inf
+    rows[::13, 2] = np.nan
+    for s in range(pop.n_sets):  # prediction rows may be non-finite
+        np.testing.assert_array_equal(eval_packed(rows, sets, hc, s), oracle.predict(rows, pop, s),
+                                      err_msg=f"set {s}")
+
+
 def test_hard_kernels_fit_two_blocks_per_cu(tmp_path):
     """The 1024-thread hard-eval kernels must keep a wave's SGPR count at or
     below 80, or two blocks no longer share a CU (half the resident waves);
