@@ -68,18 +68,26 @@ struct Pinned {
 // chunk are amortized; chunks shrink only when the grid would be too small
 // to fill the GPU or their counters do not fit in LDS.
 void hard_config(const DatasetRec &ds, int32_t n_sets, int n_cu, int *S, int *Q, int *TG) {
-  int s = 4;
-  while (s > 1 && (size_t)ds.nf * 256 * s > 150 * 1024) s >>= 1;
-  *S = s;
   const int64_t tiles = std::max<int64_t>(ds.n_tiles, 1);
   const int64_t target = 4LL * n_cu;
   int q = (int)std::min<int64_t>(std::max<int32_t>(n_sets, 1), 2048);
   // Two blocks per CU (eight waves per SIMD) hide the latency of the scalar
-  // record loads and LDS reads far better than one: take the largest chunk
-  // that lets two blocks share a CU's LDS, when one of at least 64 sets does.
+  // record loads and LDS reads far better than one: take the most samples per
+  // lane whose tile leaves room for two blocks with a chunk of at least 64
+  // sets (measured: two samples per lane at two blocks beat four at one),
+  // and then the largest chunk that keeps two blocks; with no such S, the
+  // most samples per lane that fit one block.
   const size_t half = kLdsPerCu / 2 - kStaticLds;
   const int q_min2 = std::min(q, 64);
-  const size_t budget = hard_block_lds(ds.nf, s, q_min2, ds.nc) <= half ? half : kDynLdsMax;
+  int s = 4;
+  while (s > 1 && hard_block_lds(ds.nf, s, q_min2, ds.nc) > half) s >>= 1;
+  size_t budget = half;
+  if (hard_block_lds(ds.nf, s, q_min2, ds.nc) > half) {
+    s = 4;
+    while (s > 1 && (size_t)ds.nf * 256 * s > 150 * 1024) s >>= 1;
+    budget = kDynLdsMax;
+  }
+  *S = s;
   while (q > 1 && hard_block_lds(ds.nf, s, q, ds.nc) > budget) q = (q + 1) / 2;
   while (q > 64 && ((n_sets + q - 1) / q) * tiles < target) q = (q + 1) / 2;
   // equal chunks (a short last chunk leaves its blocks underused)

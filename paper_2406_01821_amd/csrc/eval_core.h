@@ -89,8 +89,9 @@ __device__ __forceinline__ T ldc(const T *p, int64_t i) {
 // COUNT mode (PRED = false): returns, in lane c, the number of the tile's
 //   real samples predicted as class c.
 // PRED mode: pred[s] receives the predicted class of each lane's samples.
-// Portable form (any S, both modes); the 4-slot counting path below is the
-// same walk written for the scalar unit by hand.
+// Portable form (any S, both modes), used for prediction; the counting
+// kernels run eval_set_count below, the same walk written for the scalar
+// unit by hand.
 template <int S, bool PRED>
 __device__ __forceinline__ int eval_set(const float *__restrict__ xs, int lane, int4 set,
                                         const uint4 *__restrict__ stream,
@@ -160,28 +161,48 @@ __device__ __forceinline__ int eval_set(const float *__restrict__ xs, int lane, 
   return acc;
 }
 
-// 4-slot counting evaluation written for the scalar unit.  Same semantics as
-// eval_set<4, false>.  Records are loaded two at a time (s_load_dwordx8 at
-// byte offset o into quads A = s[64:67] and B = s[68:71]): a rule that goes
-// on past an A record, or starts right after one, continues from B without
-// another scalar load or wait.  The record after a rule set's last one lies
-// inside the packed stream (the stream ends with a spare record).
+// Counting evaluation written for the scalar unit, for S = 4, 2 or 1
+// samples per lane.  Same semantics as eval_set<S, false>.  Records are
+// loaded two at a time (s_load_dwordx8 at byte offset o into quads
+// A = s[64:67] and B = s[68:71]): a rule that goes on past an A record, or
+// starts right after one, continues from B without another scalar load or
+// wait.  The record after a rule set's last one lies inside the packed
+// stream (the stream ends with a spare record).
 //
 // A non-last record with a folded threshold (x >= t or x <= t) takes the
-// fast path: one flag test for the special kinds, one for the direction,
-// four compares and four mask ANDs.  Special kinds (feature-vs-feature,
-// zero coefficient, always true, a rule's last record) branch out to their
-// own bodies.  Every walk ends in a commit of an always-true record or with
-// no undecided lane left, so no end-of-stream test is needed.  Every load is
-// waited on inside the asm block.  v[32:39] hold the feature values of the
-// lane's four samples (two rows for feature-vs-feature records).
-//   lds_lane: LDS byte address of the tile plus lane*16.
+// fast path: one flag test for the special kinds, one for the direction, S
+// compares and S mask ANDs.  Special kinds (feature-vs-feature, zero
+// coefficient, always true, a rule's last record) branch out to their own
+// bodies.  Every walk ends in a commit of an always-true record or with no
+// undecided lane left, so no end-of-stream test is needed.  Every load is
+// waited on inside the asm block.  v32.. hold the feature values of the
+// lane's S samples, v36.. the second row of a feature-vs-feature record.
+//   lds_lane: LDS byte address of the tile plus lane*4*S; record x fields
+//   are row offsets in a 256-sample tile (f*1024), scaled down for S < 4.
 
-// Four compares of v32..v35 (or of the products in them) against T with
-// opcode OP (T op x_i), ANDed into f_i = S_i & m_i.  The masks go through two
-// temporaries (m and vcc), alternating, so that each AND waits only for its
-// own compare; f0 is written last, so SCC = (f0 != 0).
-#define AERL_CMP4(OP, T, S0, S1, S2, S3)                \
+#define AERL_CAT_(a, b) a##b
+#define AERL_CAT(a, b) AERL_CAT_(a, b)
+#define AERL_SM(S, MODE) AERL_CAT(S, MODE)
+
+// Row address and read (first row into v32.., second into v36..).
+#define AERL_ADDR_4(XX) "v_add_u32 %[vt], " XX ", %[lds]\n"
+#define AERL_ADDR_2(XX) "v_lshrrev_b32_e64 %[vt], 1, " XX "\n v_add_u32 %[vt], %[vt], %[lds]\n"
+#define AERL_ADDR_1(XX) "v_lshrrev_b32_e64 %[vt], 2, " XX "\n v_add_u32 %[vt], %[vt], %[lds]\n"
+#define AERL_RD_4 "ds_read_b128 v[32:35], %[vt]\n"
+#define AERL_RD_2 "ds_read_b64 v[32:33], %[vt]\n"
+#define AERL_RD_1 "ds_read_b32 v32, %[vt]\n"
+#define AERL_RD2_4 "ds_read_b128 v[36:39], %[vt2]\n"
+#define AERL_RD2_2 "ds_read_b64 v[36:37], %[vt2]\n"
+#define AERL_RD2_1 "ds_read_b32 v36, %[vt2]\n"
+#define AERL_GSHIFT_4 "10"
+#define AERL_GSHIFT_2 "9"
+#define AERL_GSHIFT_1 "8"
+
+// S compares of the first row (or of the products in it) against T with
+// opcode OP (T op x_i), ANDed into f_i = src_i & m_i.  The masks go through
+// two temporaries (m and vcc), alternating, so that each AND waits only for
+// its own compare; f0 is written last, so SCC = (f0 != 0).
+#define AERL_CMPT_4(OP, T, S0, S1, S2, S3)              \
   "v_cmp_" OP "_f32_e64 %[m], " T ", v35\n"             \
   "v_cmp_" OP "_f32_e32 vcc, " T ", v34\n"              \
   "s_and_b64 %[f3], " S3 ", %[m]\n"                     \
@@ -190,9 +211,23 @@ __device__ __forceinline__ int eval_set(const float *__restrict__ xs, int lane, 
   "v_cmp_" OP "_f32_e32 vcc, " T ", v32\n"              \
   "s_and_b64 %[f1], " S1 ", %[m]\n"                     \
   "s_and_b64 %[f0], " S0 ", vcc\n"
+#define AERL_CMPT_2(OP, T, S0, S1)                      \
+  "v_cmp_" OP "_f32_e64 %[m], " T ", v33\n"             \
+  "v_cmp_" OP "_f32_e32 vcc, " T ", v32\n"              \
+  "s_and_b64 %[f1], " S1 ", %[m]\n"                     \
+  "s_and_b64 %[f0], " S0 ", vcc\n"
+#define AERL_CMPT_1(OP, T, S0)                          \
+  "v_cmp_" OP "_f32_e32 vcc, " T ", v32\n"              \
+  "s_and_b64 %[f0], " S0 ", vcc\n"
+#define AERL_CMP_4U(OP, T) AERL_CMPT_4(OP, T, "%[u0]", "%[u1]", "%[u2]", "%[u3]")
+#define AERL_CMP_4F(OP, T) AERL_CMPT_4(OP, T, "%[f0]", "%[f1]", "%[f2]", "%[f3]")
+#define AERL_CMP_2U(OP, T) AERL_CMPT_2(OP, T, "%[u0]", "%[u1]")
+#define AERL_CMP_2F(OP, T) AERL_CMPT_2(OP, T, "%[f0]", "%[f1]")
+#define AERL_CMP_1U(OP, T) AERL_CMPT_1(OP, T, "%[u0]")
+#define AERL_CMP_1F(OP, T) AERL_CMPT_1(OP, T, "%[f0]")
 
-// Feature-vs-feature compare of the products in v32..v35 and v36..v39.
-#define AERL_FF_CMP(OP, S0, S1, S2, S3)                 \
+// Feature-vs-feature compare of the products in v32.. and v36...
+#define AERL_FFCMPT_4(OP, S0, S1, S2, S3)               \
   "v_cmp_" OP "_f32_e64 %[m], v35, v39\n"               \
   "v_cmp_" OP "_f32_e32 vcc, v34, v38\n"                \
   "s_and_b64 %[f3], " S3 ", %[m]\n"                     \
@@ -201,83 +236,99 @@ __device__ __forceinline__ int eval_set(const float *__restrict__ xs, int lane, 
   "v_cmp_" OP "_f32_e32 vcc, v32, v36\n"                \
   "s_and_b64 %[f1], " S1 ", %[m]\n"                     \
   "s_and_b64 %[f0], " S0 ", vcc\n"
+#define AERL_FFCMPT_2(OP, S0, S1)                       \
+  "v_cmp_" OP "_f32_e64 %[m], v33, v37\n"               \
+  "v_cmp_" OP "_f32_e32 vcc, v32, v36\n"                \
+  "s_and_b64 %[f1], " S1 ", %[m]\n"                     \
+  "s_and_b64 %[f0], " S0 ", vcc\n"
+#define AERL_FFCMPT_1(OP, S0)                           \
+  "v_cmp_" OP "_f32_e32 vcc, v32, v36\n"                \
+  "s_and_b64 %[f0], " S0 ", vcc\n"
+#define AERL_FFCMP_4U(OP) AERL_FFCMPT_4(OP, "%[u0]", "%[u1]", "%[u2]", "%[u3]")
+#define AERL_FFCMP_4F(OP) AERL_FFCMPT_4(OP, "%[f0]", "%[f1]", "%[f2]", "%[f3]")
+#define AERL_FFCMP_2U(OP) AERL_FFCMPT_2(OP, "%[u0]", "%[u1]")
+#define AERL_FFCMP_2F(OP) AERL_FFCMPT_2(OP, "%[f0]", "%[f1]")
+#define AERL_FFCMP_1U(OP) AERL_FFCMPT_1(OP, "%[u0]")
+#define AERL_FFCMP_1F(OP) AERL_FFCMPT_1(OP, "%[f0]")
 
-// Start of a record whose row is at byte offset XX: read the row; special
-// kinds go to SPEC, the <= direction to LE; falls through (row waited for)
-// with a >= record.  kRecSpecial = 0xa03, kRecLE = bit 10.
-#define AERL_FETCH(XX, XW, SPEC, LE)                    \
-  "v_add_u32 %[vt], " XX ", %[lds]\n"                   \
-  "ds_read_b128 v[32:35], %[vt]\n"                      \
-  "s_and_b32 %[t0], " XW ", 0xa03\n"                    \
-  "s_cbranch_scc1 " SPEC "\n"                           \
-  "s_bitcmp1_b32 " XW ", 10\n"                          \
-  "s_waitcnt lgkmcnt(0)\n"                              \
-  "s_cbranch_scc1 " LE "\n"
-
-// Special threshold kinds of the record (y in Y, z in Z, flags in W), row
-// already requested: zero coefficient (y*x > z), <=, or >= (a last record);
-// then on to POST with SCC = (f0 != 0).
-#define AERL_TSPEC(Y, Z, W, S0, S1, S2, S3, TAG, POST)  \
-  "s_waitcnt lgkmcnt(0)\n"                              \
-  "s_bitcmp1_b32 " W ", 0\n"                            \
-  "s_cbranch_scc1 .Lmul_" TAG "_%=\n"                   \
-  "s_bitcmp1_b32 " W ", 10\n"                           \
-  "s_cbranch_scc1 .Lle_" TAG "_%=\n"                    \
-  AERL_CMP4("le", Y, S0, S1, S2, S3)                    \
-  "s_branch " POST "\n"                                 \
-  ".Lle_" TAG "_%=:\n"                                  \
-  AERL_CMP4("ge", Y, S0, S1, S2, S3)                    \
-  "s_branch " POST "\n"                                 \
-  ".Lmul_" TAG "_%=:\n"                                 \
+// Products of the first row by Y (and of the second by Z).
+#define AERL_MUL1_4(Y)                                  \
   "v_mul_f32 v32, " Y ", v32\n"                         \
   "v_mul_f32 v33, " Y ", v33\n"                         \
   "v_mul_f32 v34, " Y ", v34\n"                         \
-  "v_mul_f32 v35, " Y ", v35\n"                         \
-  AERL_CMP4("lt", Z, S0, S1, S2, S3)                    \
-  "s_branch " POST "\n"
-
-// Feature-vs-feature record (a in Y, b in Z, g and the >= flag in W), first
-// row already requested: f_i = S_i & (a*x_i > b*x'_i) or (>=); then POST.
-#define AERL_FF_BODY(W, Y, Z, S0, S1, S2, S3, TAG, POST) \
-  "s_bfe_u32 %[t0], " W ", 0x90000\n"                   \
-  "s_lshl_b32 %[t0], %[t0], 10\n"                       \
-  "v_add_u32 %[vt2], %[t0], %[lds]\n"                   \
-  "ds_read_b128 v[36:39], %[vt2]\n"                     \
-  "s_waitcnt lgkmcnt(0)\n"                              \
-  "v_mul_f32 v32, " Y ", v32\n"                         \
-  "v_mul_f32 v33, " Y ", v33\n"                         \
-  "v_mul_f32 v34, " Y ", v34\n"                         \
-  "v_mul_f32 v35, " Y ", v35\n"                         \
+  "v_mul_f32 v35, " Y ", v35\n"
+#define AERL_MUL1_2(Y) "v_mul_f32 v32, " Y ", v32\n v_mul_f32 v33, " Y ", v33\n"
+#define AERL_MUL1_1(Y) "v_mul_f32 v32, " Y ", v32\n"
+#define AERL_MUL2_4(Z)                                  \
   "v_mul_f32 v36, " Z ", v36\n"                         \
   "v_mul_f32 v37, " Z ", v37\n"                         \
   "v_mul_f32 v38, " Z ", v38\n"                         \
-  "v_mul_f32 v39, " Z ", v39\n"                         \
-  "s_bitcmp1_b32 " W ", 10\n"                           \
-  "s_cbranch_scc1 .Lge_" TAG "_%=\n"                    \
-  AERL_FF_CMP("gt", S0, S1, S2, S3)                     \
-  "s_branch " POST "\n"                                 \
-  ".Lge_" TAG "_%=:\n"                                  \
-  AERL_FF_CMP("ge", S0, S1, S2, S3)                     \
-  "s_branch " POST "\n"
+  "v_mul_f32 v39, " Z ", v39\n"
+#define AERL_MUL2_2(Z) "v_mul_f32 v36, " Z ", v36\n v_mul_f32 v37, " Z ", v37\n"
+#define AERL_MUL2_1(Z) "v_mul_f32 v36, " Z ", v36\n"
 
-// Special record entry: feature-vs-feature to FFL, always-true (rule starts
-// only) to ALW, else a special threshold kind; then POST.
-#define AERL_SPEC(Y, Z, W, S0, S1, S2, S3, TAG, POST, ALW) \
-  "s_bitcmp1_b32 " W ", 9\n"                            \
-  "s_cbranch_scc1 .Lff_" TAG "_%=\n"                    \
-  ALW                                                   \
-  AERL_TSPEC(Y, Z, W, S0, S1, S2, S3, TAG, POST)        \
-  ".Lff_" TAG "_%=:\n"                                  \
-  AERL_FF_BODY(W, Y, Z, S0, S1, S2, S3, TAG, POST)
+// SCC = (f0 != 0) after a compare: to ALIVE when some f_i is non-zero.
+#define AERL_ANY_F_4(ALIVE)                             \
+  "s_cbranch_scc1 " ALIVE "\n"                          \
+  "s_or_b64 %[m], %[f1], %[f2]\n"                       \
+  "s_or_b64 %[m], %[m], %[f3]\n"                        \
+  "s_cbranch_scc1 " ALIVE "\n"
+#define AERL_ANY_F_2(ALIVE)                             \
+  "s_cbranch_scc1 " ALIVE "\n"                          \
+  "s_cmp_lg_u64 %[f1], 0\n"                             \
+  "s_cbranch_scc1 " ALIVE "\n"
+#define AERL_ANY_F_1(ALIVE) "s_cbranch_scc1 " ALIVE "\n"
 
-#define AERL_POPC4(A, B, C, D)                          \
-  "s_bcnt1_i32_b64 %[t0], " A "\n"                      \
-  "s_bcnt1_i32_b64 %[t1], " B "\n"                      \
+// t0 = number of lanes set in the masks F_i (U_i).
+#define AERL_POPC_4F                                    \
+  "s_bcnt1_i32_b64 %[t0], %[f0]\n"                      \
+  "s_bcnt1_i32_b64 %[t1], %[f1]\n"                      \
   "s_add_u32 %[t0], %[t0], %[t1]\n"                     \
-  "s_bcnt1_i32_b64 %[t1], " C "\n"                      \
+  "s_bcnt1_i32_b64 %[t1], %[f2]\n"                      \
   "s_add_u32 %[t0], %[t0], %[t1]\n"                     \
-  "s_bcnt1_i32_b64 %[t1], " D "\n"                      \
+  "s_bcnt1_i32_b64 %[t1], %[f3]\n"                      \
   "s_add_u32 %[t0], %[t0], %[t1]\n"
+#define AERL_POPC_4U                                    \
+  "s_bcnt1_i32_b64 %[t0], %[u0]\n"                      \
+  "s_bcnt1_i32_b64 %[t1], %[u1]\n"                      \
+  "s_add_u32 %[t0], %[t0], %[t1]\n"                     \
+  "s_bcnt1_i32_b64 %[t1], %[u2]\n"                      \
+  "s_add_u32 %[t0], %[t0], %[t1]\n"                     \
+  "s_bcnt1_i32_b64 %[t1], %[u3]\n"                      \
+  "s_add_u32 %[t0], %[t0], %[t1]\n"
+#define AERL_POPC_2F                                    \
+  "s_bcnt1_i32_b64 %[t0], %[f0]\n"                      \
+  "s_bcnt1_i32_b64 %[t1], %[f1]\n"                      \
+  "s_add_u32 %[t0], %[t0], %[t1]\n"
+#define AERL_POPC_2U                                    \
+  "s_bcnt1_i32_b64 %[t0], %[u0]\n"                      \
+  "s_bcnt1_i32_b64 %[t1], %[u1]\n"                      \
+  "s_add_u32 %[t0], %[t0], %[t1]\n"
+#define AERL_POPC_1F "s_bcnt1_i32_b64 %[t0], %[f0]\n"
+#define AERL_POPC_1U "s_bcnt1_i32_b64 %[t0], %[u0]\n"
+
+// Retire the fired lanes; SCC = some lane still undecided.
+#define AERL_RETIRE_4                                   \
+  "s_andn2_b64 %[u0], %[u0], %[f0]\n"                   \
+  "s_andn2_b64 %[u1], %[u1], %[f1]\n"                   \
+  "s_andn2_b64 %[u2], %[u2], %[f2]\n"                   \
+  "s_andn2_b64 %[u3], %[u3], %[f3]\n"                   \
+  "s_or_b64 %[m], %[u0], %[u1]\n"                       \
+  "s_or_b64 %[m], %[m], %[u2]\n"                        \
+  "s_or_b64 %[m], %[m], %[u3]\n"
+#define AERL_RETIRE_2                                   \
+  "s_andn2_b64 %[u0], %[u0], %[f0]\n"                   \
+  "s_andn2_b64 %[u1], %[u1], %[f1]\n"                   \
+  "s_or_b64 %[m], %[u0], %[u1]\n"
+#define AERL_RETIRE_1 "s_andn2_b64 %[u0], %[u0], %[f0]\n"
+
+// SCC = some lane undecided, at the start of a walk.
+#define AERL_ANY_U_4                                    \
+  "s_or_b64 %[m], %[u0], %[u1]\n"                       \
+  "s_or_b64 %[m], %[m], %[u2]\n"                        \
+  "s_or_b64 %[m], %[m], %[u3]\n"
+#define AERL_ANY_U_2 "s_or_b64 %[m], %[u0], %[u1]\n"
+#define AERL_ANY_U_1 "s_cmp_lg_u64 %[u0], 0\n"
 
 // Adds the t0 samples of the class in W to the class's lane of acc.
 #define AERL_ADD_CLASS(W)                               \
@@ -289,29 +340,182 @@ __device__ __forceinline__ int eval_set(const float *__restrict__ xs, int lane, 
 
 // The rule of the (last) record in W fires for the lanes in f: count them
 // for its class and retire them (SCC = some lane still undecided).
-#define AERL_COMMIT_COUNT(W)                            \
-  AERL_POPC4("%[f0]", "%[f1]", "%[f2]", "%[f3]")        \
-  AERL_ADD_CLASS(W)                                     \
-  "s_andn2_b64 %[u0], %[u0], %[f0]\n"                   \
-  "s_andn2_b64 %[u1], %[u1], %[f1]\n"                   \
-  "s_andn2_b64 %[u2], %[u2], %[f2]\n"                   \
-  "s_andn2_b64 %[u3], %[u3], %[f3]\n"                   \
-  "s_or_b64 %[m], %[u0], %[u1]\n"                       \
-  "s_or_b64 %[m], %[m], %[u2]\n"                        \
-  "s_or_b64 %[m], %[m], %[u3]\n"
+#define AERL_COMMIT(S, W) AERL_CAT(AERL_POPC_, AERL_SM(S, F)) AERL_ADD_CLASS(W) AERL_CAT(AERL_RETIRE_, S)
 
-// SCC = (f0 != 0) after a compare: to ALIVE when some f_i is non-zero.
-#define AERL_ANY_F(ALIVE)                               \
-  "s_cbranch_scc1 " ALIVE "\n"                          \
-  "s_or_b64 %[m], %[f1], %[f2]\n"                       \
-  "s_or_b64 %[m], %[m], %[f3]\n"                        \
-  "s_cbranch_scc1 " ALIVE "\n"
+// Start of a record whose row is at byte offset XX: read the row; special
+// kinds go to SPEC, the <= direction to LE; falls through (row waited for)
+// with a >= record.  kRecSpecial = 0xa03, kRecLE = bit 10.
+#define AERL_FETCH(S, XX, XW, SPEC, LE)                 \
+  AERL_CAT(AERL_ADDR_, S)(XX)                           \
+  AERL_CAT(AERL_RD_, S)                                 \
+  "s_and_b32 %[t0], " XW ", 0xa03\n"                    \
+  "s_cbranch_scc1 " SPEC "\n"                           \
+  "s_bitcmp1_b32 " XW ", 10\n"                          \
+  "s_waitcnt lgkmcnt(0)\n"                              \
+  "s_cbranch_scc1 " LE "\n"
 
-#define AERL_U "%[u0]", "%[u1]", "%[u2]", "%[u3]"
-#define AERL_F "%[f0]", "%[f1]", "%[f2]", "%[f3]"
-#define AERL_X(M, ...) M(__VA_ARGS__)
+// Special threshold kinds of the record (y in Y, z in Z, flags in W), row
+// already requested: zero coefficient (y*x > z), <=, or >= (a last record);
+// then on to POST with SCC = (f0 != 0).
+#define AERL_TSPEC(S, MODE, Y, Z, W, TAG, POST)         \
+  "s_waitcnt lgkmcnt(0)\n"                              \
+  "s_bitcmp1_b32 " W ", 0\n"                            \
+  "s_cbranch_scc1 .Lmul_" TAG "_%=\n"                   \
+  "s_bitcmp1_b32 " W ", 10\n"                           \
+  "s_cbranch_scc1 .Lle_" TAG "_%=\n"                    \
+  AERL_CAT(AERL_CMP_, AERL_SM(S, MODE))("le", Y)        \
+  "s_branch " POST "\n"                                 \
+  ".Lle_" TAG "_%=:\n"                                  \
+  AERL_CAT(AERL_CMP_, AERL_SM(S, MODE))("ge", Y)        \
+  "s_branch " POST "\n"                                 \
+  ".Lmul_" TAG "_%=:\n"                                 \
+  AERL_CAT(AERL_MUL1_, S)(Y)                            \
+  AERL_CAT(AERL_CMP_, AERL_SM(S, MODE))("lt", Z)        \
+  "s_branch " POST "\n"
 
-__device__ __forceinline__ int eval_set_s4_count(uint32_t lds_lane, int lane, int4 set,
+// Feature-vs-feature record (a in Y, b in Z, g and the >= flag in W), first
+// row already requested: f_i = src_i & (a*x_i > b*x'_i) or (>=); then POST.
+#define AERL_FF_BODY(S, MODE, W, Y, Z, TAG, POST)       \
+  "s_bfe_u32 %[t0], " W ", 0x90000\n"                   \
+  "s_lshl_b32 %[t0], %[t0], " AERL_CAT(AERL_GSHIFT_, S) "\n" \
+  "v_add_u32 %[vt2], %[t0], %[lds]\n"                   \
+  AERL_CAT(AERL_RD2_, S)                                \
+  "s_waitcnt lgkmcnt(0)\n"                              \
+  AERL_CAT(AERL_MUL1_, S)(Y)                            \
+  AERL_CAT(AERL_MUL2_, S)(Z)                            \
+  "s_bitcmp1_b32 " W ", 10\n"                           \
+  "s_cbranch_scc1 .Lge_" TAG "_%=\n"                    \
+  AERL_CAT(AERL_FFCMP_, AERL_SM(S, MODE))("gt")         \
+  "s_branch " POST "\n"                                 \
+  ".Lge_" TAG "_%=:\n"                                  \
+  AERL_CAT(AERL_FFCMP_, AERL_SM(S, MODE))("ge")         \
+  "s_branch " POST "\n"
+
+// Special record entry: feature-vs-feature, always-true (rule starts only,
+// ALW), else a special threshold kind; then POST.
+#define AERL_SPEC(S, MODE, Y, Z, W, TAG, POST, ALW)     \
+  "s_bitcmp1_b32 " W ", 9\n"                            \
+  "s_cbranch_scc1 .Lff_" TAG "_%=\n"                    \
+  ALW                                                   \
+  AERL_TSPEC(S, MODE, Y, Z, W, TAG, POST)               \
+  ".Lff_" TAG "_%=:\n"                                  \
+  AERL_FF_BODY(S, MODE, W, Y, Z, TAG, POST)
+
+// The whole walk for S samples per lane.
+#define AERL_WALK(S)                                                       \
+  "s_mov_b32 %[o], 0\n"                                                    \
+  AERL_CAT(AERL_ANY_U_, S)                                                 \
+  "s_cbranch_scc0 .Ldone_%=\n"                                             \
+  /* load the pair (o, o+16) into A, B; a rule starts at A */              \
+  ".Lload_%=:\n"                                                           \
+  "s_load_dwordx8 s[64:71], %[base], %[o]\n"                               \
+  "s_waitcnt lgkmcnt(0)\n"                                                 \
+  AERL_FETCH(S, "s64", "s67", ".Lpsa_%=", ".Llsa_%=")                      \
+  AERL_CAT(AERL_CMP_, AERL_SM(S, U))("le", "s65")                          \
+  /* after a fast record in A: on with B unless no f_i fires */            \
+  ".Lqa_%=:\n"                                                             \
+  "s_cbranch_scc0 .Lka_%=\n"                                               \
+  /* B continues the rule */                                               \
+  ".Lnb_%=:\n"                                                             \
+  AERL_FETCH(S, "s68", "s71", ".Lpnb_%=", ".Llnb_%=")                      \
+  AERL_CAT(AERL_CMP_, AERL_SM(S, F))("le", "s69")                          \
+  ".Lqb_%=:\n"                                                             \
+  "s_cbranch_scc0 .Lkb_%=\n"                                               \
+  /* the next pair continues the rule */                                   \
+  ".Llna_load_%=:\n"                                                       \
+  "s_add_u32 %[o], %[o], 32\n"                                             \
+  "s_load_dwordx8 s[64:71], %[base], %[o]\n"                               \
+  "s_waitcnt lgkmcnt(0)\n"                                                 \
+  AERL_FETCH(S, "s64", "s67", ".Lpna_%=", ".Llna_%=")                      \
+  AERL_CAT(AERL_CMP_, AERL_SM(S, F))("le", "s65")                          \
+  "s_cbranch_scc1 .Lnb_%=\n"                                               \
+  /* f0 == 0 after a fast record in A: alive if another slot fires, else */ \
+  /* the next rule starts past B (A is not a rule's last record) */        \
+  ".Lka_%=:\n"                                                             \
+  AERL_CAT(AERL_ANY_F_, S)(".Lnb_%=")                                      \
+  "s_lshr_b32 %[o], s67, 18\n"                                             \
+  "s_branch .Lload_%=\n"                                                   \
+  ".Lkb_%=:\n"                                                             \
+  AERL_CAT(AERL_ANY_F_, S)(".Llna_load_%=")                                \
+  "s_lshr_b32 %[o], s71, 18\n"                                             \
+  "s_branch .Lload_%=\n"                                                   \
+  /* a rule starts at B (the previous one ended at A) */                   \
+  ".Lsb_%=:\n"                                                             \
+  AERL_FETCH(S, "s68", "s71", ".Lpsb_%=", ".Llsb_%=")                      \
+  AERL_CAT(AERL_CMP_, AERL_SM(S, U))("le", "s69")                          \
+  "s_branch .Lqb_%=\n"                                                     \
+  /* fast records in the <= direction */                                   \
+  ".Llsa_%=:\n"                                                            \
+  AERL_CAT(AERL_CMP_, AERL_SM(S, U))("ge", "s65")                          \
+  "s_branch .Lqa_%=\n"                                                     \
+  ".Llna_%=:\n"                                                            \
+  AERL_CAT(AERL_CMP_, AERL_SM(S, F))("ge", "s65")                          \
+  "s_branch .Lqa_%=\n"                                                     \
+  ".Llsb_%=:\n"                                                            \
+  AERL_CAT(AERL_CMP_, AERL_SM(S, U))("ge", "s69")                          \
+  "s_branch .Lqb_%=\n"                                                     \
+  ".Llnb_%=:\n"                                                            \
+  AERL_CAT(AERL_CMP_, AERL_SM(S, F))("ge", "s69")                          \
+  "s_branch .Lqb_%=\n"                                                     \
+  /* special records */                                                    \
+  ".Lpsa_%=:\n"                                                            \
+  AERL_SPEC(S, U, "s65", "s66", "s67", "sa", ".Lxa_%=",                    \
+            "s_bitcmp1_b32 s67, 1\n s_cbranch_scc1 .Lalwa_%=\n")           \
+  ".Lpna_%=:\n"                                                            \
+  AERL_SPEC(S, F, "s65", "s66", "s67", "na", ".Lxa_%=", "")                \
+  ".Lpsb_%=:\n"                                                            \
+  AERL_SPEC(S, U, "s69", "s70", "s71", "sb", ".Lxb_%=",                    \
+            "s_bitcmp1_b32 s71, 1\n s_cbranch_scc1 .Lalwb_%=\n")           \
+  ".Lpnb_%=:\n"                                                            \
+  AERL_SPEC(S, F, "s69", "s70", "s71", "nb", ".Lxb_%=", "")                \
+  /* after a special record in A */                                        \
+  ".Lxa_%=:\n"                                                             \
+  AERL_CAT(AERL_ANY_F_, S)(".Lya_%=")                                      \
+  "s_bitcmp1_b32 s67, 11\n"                                                \
+  "s_cbranch_scc1 .Lsb_%=\n" /* dead, and the next rule starts at B */     \
+  "s_lshr_b32 %[o], s67, 18\n"                                             \
+  "s_branch .Lload_%=\n"                                                   \
+  ".Lya_%=:\n"                                                             \
+  "s_bitcmp1_b32 s67, 11\n"                                                \
+  "s_cbranch_scc0 .Lnb_%=\n"                                               \
+  AERL_COMMIT(S, "s67")                                                    \
+  "s_cbranch_scc1 .Lsb_%=\n"                                               \
+  "s_branch .Ldone_%=\n"                                                   \
+  /* after a special record in B */                                        \
+  ".Lxb_%=:\n"                                                             \
+  AERL_CAT(AERL_ANY_F_, S)(".Lyb_%=")                                      \
+  "s_lshr_b32 %[o], s71, 18\n"                                             \
+  "s_branch .Lload_%=\n"                                                   \
+  ".Lyb_%=:\n"                                                             \
+  "s_bitcmp1_b32 s71, 11\n"                                                \
+  "s_cbranch_scc0 .Llna_load_%=\n"                                         \
+  AERL_COMMIT(S, "s71")                                                    \
+  "s_cbranch_scc0 .Ldone_%=\n"                                             \
+  "s_add_u32 %[o], %[o], 32\n"                                             \
+  "s_branch .Lload_%=\n"                                                   \
+  /* an always-true rule decides every undecided lane */                   \
+  ".Lalwa_%=:\n"                                                           \
+  "s_waitcnt lgkmcnt(0)\n"                                                 \
+  AERL_CAT(AERL_POPC_, AERL_SM(S, U))                                      \
+  AERL_ADD_CLASS("s67")                                                    \
+  "s_branch .Ldone_%=\n"                                                   \
+  ".Lalwb_%=:\n"                                                           \
+  "s_waitcnt lgkmcnt(0)\n"                                                 \
+  AERL_CAT(AERL_POPC_, AERL_SM(S, U))                                      \
+  AERL_ADD_CLASS("s71")                                                    \
+  ".Ldone_%=:\n"
+
+#define AERL_WALK_CLOBBERS                                                 \
+  "s64", "s65", "s66", "s67", "s68", "s69", "s70", "s71", "v32", "v33", "v34", \
+      "v35", "v36", "v37", "v38", "v39", "vcc", "scc", "memory"
+
+template <int S>
+__device__ __forceinline__ int eval_set_count(uint32_t lds_lane, int lane, int4 set,
+                                              const uint4 *__restrict__ stream,
+                                              const uint64_t (&vm)[S]);
+
+template <>
+__device__ __forceinline__ int eval_set_count<4>(uint32_t lds_lane, int lane, int4 set,
                                                  const uint4 *__restrict__ stream,
                                                  const uint64_t (&vm)[4]) {
   const uint4 *base = stream + set.x;
@@ -319,120 +523,47 @@ __device__ __forceinline__ int eval_set_s4_count(uint32_t lds_lane, int lane, in
   uint64_t f0, f1, f2, f3, m;
   uint32_t o, t0, t1, vt, vt2;
   int acc = 0;
-  asm volatile(
-      "s_mov_b32 %[o], 0\n"
-      "s_or_b64 %[m], %[u0], %[u1]\n"
-      "s_or_b64 %[m], %[m], %[u2]\n"
-      "s_or_b64 %[m], %[m], %[u3]\n"
-      "s_cbranch_scc0 .Ldone_%=\n"
-      // load the pair (o, o+16) into A, B; a rule starts at A
-      ".Lload_%=:\n"
-      "s_load_dwordx8 s[64:71], %[base], %[o]\n"
-      "s_waitcnt lgkmcnt(0)\n"
-      AERL_X(AERL_FETCH, "s64", "s67", ".Lpsa_%=", ".Llsa_%=")
-      AERL_X(AERL_CMP4, "le", "s65", AERL_U)
-      // after a fast record in A: on with B unless no f_i fires
-      ".Lqa_%=:\n"
-      "s_cbranch_scc0 .Lka_%=\n"
-      // B continues the rule
-      ".Lnb_%=:\n"
-      AERL_X(AERL_FETCH, "s68", "s71", ".Lpnb_%=", ".Llnb_%=")
-      AERL_X(AERL_CMP4, "le", "s69", AERL_F)
-      ".Lqb_%=:\n"
-      "s_cbranch_scc0 .Lkb_%=\n"
-      // the next pair continues the rule
-      ".Llna_load_%=:\n"
-      "s_add_u32 %[o], %[o], 32\n"
-      "s_load_dwordx8 s[64:71], %[base], %[o]\n"
-      "s_waitcnt lgkmcnt(0)\n"
-      AERL_X(AERL_FETCH, "s64", "s67", ".Lpna_%=", ".Llna_%=")
-      AERL_X(AERL_CMP4, "le", "s65", AERL_F)
-      "s_cbranch_scc1 .Lnb_%=\n"
-      // f0 == 0 after a fast record in A: alive if another slot fires, else
-      // the next rule starts past B (A is not a rule's last record)
-      ".Lka_%=:\n"
-      "s_or_b64 %[m], %[f1], %[f2]\n"
-      "s_or_b64 %[m], %[m], %[f3]\n"
-      "s_cbranch_scc1 .Lnb_%=\n"
-      "s_lshr_b32 %[o], s67, 18\n"
-      "s_branch .Lload_%=\n"
-      ".Lkb_%=:\n"
-      "s_or_b64 %[m], %[f1], %[f2]\n"
-      "s_or_b64 %[m], %[m], %[f3]\n"
-      "s_cbranch_scc1 .Llna_load_%=\n"
-      "s_lshr_b32 %[o], s71, 18\n"
-      "s_branch .Lload_%=\n"
-      // a rule starts at B (the previous one ended at A)
-      ".Lsb_%=:\n"
-      AERL_X(AERL_FETCH, "s68", "s71", ".Lpsb_%=", ".Llsb_%=")
-      AERL_X(AERL_CMP4, "le", "s69", AERL_U)
-      "s_branch .Lqb_%=\n"
-      // fast records in the <= direction
-      ".Llsa_%=:\n"
-      AERL_X(AERL_CMP4, "ge", "s65", AERL_U)
-      "s_branch .Lqa_%=\n"
-      ".Llna_%=:\n"
-      AERL_X(AERL_CMP4, "ge", "s65", AERL_F)
-      "s_branch .Lqa_%=\n"
-      ".Llsb_%=:\n"
-      AERL_X(AERL_CMP4, "ge", "s69", AERL_U)
-      "s_branch .Lqb_%=\n"
-      ".Llnb_%=:\n"
-      AERL_X(AERL_CMP4, "ge", "s69", AERL_F)
-      "s_branch .Lqb_%=\n"
-      // special records
-      ".Lpsa_%=:\n"
-      AERL_X(AERL_SPEC, "s65", "s66", "s67", AERL_U, "sa", ".Lxa_%=",
-             "s_bitcmp1_b32 s67, 1\n s_cbranch_scc1 .Lalwa_%=\n")
-      ".Lpna_%=:\n"
-      AERL_X(AERL_SPEC, "s65", "s66", "s67", AERL_F, "na", ".Lxa_%=", "")
-      ".Lpsb_%=:\n"
-      AERL_X(AERL_SPEC, "s69", "s70", "s71", AERL_U, "sb", ".Lxb_%=",
-             "s_bitcmp1_b32 s71, 1\n s_cbranch_scc1 .Lalwb_%=\n")
-      ".Lpnb_%=:\n"
-      AERL_X(AERL_SPEC, "s69", "s70", "s71", AERL_F, "nb", ".Lxb_%=", "")
-      // after a special record in A
-      ".Lxa_%=:\n"
-      AERL_ANY_F(".Lya_%=")
-      "s_bitcmp1_b32 s67, 11\n"
-      "s_cbranch_scc1 .Lsb_%=\n"  // dead, and the next rule starts at B
-      "s_lshr_b32 %[o], s67, 18\n"
-      "s_branch .Lload_%=\n"
-      ".Lya_%=:\n"
-      "s_bitcmp1_b32 s67, 11\n"
-      "s_cbranch_scc0 .Lnb_%=\n"
-      AERL_COMMIT_COUNT("s67")
-      "s_cbranch_scc1 .Lsb_%=\n"
-      "s_branch .Ldone_%=\n"
-      // after a special record in B
-      ".Lxb_%=:\n"
-      AERL_ANY_F(".Lyb_%=")
-      "s_lshr_b32 %[o], s71, 18\n"
-      "s_branch .Lload_%=\n"
-      ".Lyb_%=:\n"
-      "s_bitcmp1_b32 s71, 11\n"
-      "s_cbranch_scc0 .Llna_load_%=\n"
-      AERL_COMMIT_COUNT("s71")
-      "s_cbranch_scc0 .Ldone_%=\n"
-      "s_add_u32 %[o], %[o], 32\n"
-      "s_branch .Lload_%=\n"
-      // an always-true rule decides every undecided lane
-      ".Lalwa_%=:\n"
-      "s_waitcnt lgkmcnt(0)\n"
-      AERL_POPC4("%[u0]", "%[u1]", "%[u2]", "%[u3]")
-      AERL_ADD_CLASS("s67")
-      "s_branch .Ldone_%=\n"
-      ".Lalwb_%=:\n"
-      "s_waitcnt lgkmcnt(0)\n"
-      AERL_POPC4("%[u0]", "%[u1]", "%[u2]", "%[u3]")
-      AERL_ADD_CLASS("s71")
-      ".Ldone_%=:\n"
-      : [acc] "+v"(acc), [u0] "+s"(u0), [u1] "+s"(u1), [u2] "+s"(u2), [u3] "+s"(u3),
-        [f0] "=&s"(f0), [f1] "=&s"(f1), [f2] "=&s"(f2), [f3] "=&s"(f3), [m] "=&s"(m),
-        [o] "=&s"(o), [t0] "=&s"(t0), [t1] "=&s"(t1), [vt] "=&v"(vt), [vt2] "=&v"(vt2)
-      : [base] "s"(base), [lds] "v"(lds_lane), [lane] "v"(lane)
-      : "s64", "s65", "s66", "s67", "s68", "s69", "s70", "s71", "v32", "v33", "v34", "v35",
-        "v36", "v37", "v38", "v39", "vcc", "scc", "memory");
+  asm volatile(AERL_WALK(4)
+               : [acc] "+v"(acc), [u0] "+s"(u0), [u1] "+s"(u1), [u2] "+s"(u2), [u3] "+s"(u3),
+                 [f0] "=&s"(f0), [f1] "=&s"(f1), [f2] "=&s"(f2), [f3] "=&s"(f3), [m] "=&s"(m),
+                 [o] "=&s"(o), [t0] "=&s"(t0), [t1] "=&s"(t1), [vt] "=&v"(vt), [vt2] "=&v"(vt2)
+               : [base] "s"(base), [lds] "v"(lds_lane), [lane] "v"(lane)
+               : AERL_WALK_CLOBBERS);
+  return acc;
+}
+
+template <>
+__device__ __forceinline__ int eval_set_count<2>(uint32_t lds_lane, int lane, int4 set,
+                                                 const uint4 *__restrict__ stream,
+                                                 const uint64_t (&vm)[2]) {
+  const uint4 *base = stream + set.x;
+  uint64_t u0 = vm[0], u1 = vm[1];
+  uint64_t f0, f1, m;
+  uint32_t o, t0, t1, vt, vt2;
+  int acc = 0;
+  asm volatile(AERL_WALK(2)
+               : [acc] "+v"(acc), [u0] "+s"(u0), [u1] "+s"(u1), [f0] "=&s"(f0), [f1] "=&s"(f1),
+                 [m] "=&s"(m), [o] "=&s"(o), [t0] "=&s"(t0), [t1] "=&s"(t1), [vt] "=&v"(vt),
+                 [vt2] "=&v"(vt2)
+               : [base] "s"(base), [lds] "v"(lds_lane), [lane] "v"(lane)
+               : AERL_WALK_CLOBBERS);
+  return acc;
+}
+
+template <>
+__device__ __forceinline__ int eval_set_count<1>(uint32_t lds_lane, int lane, int4 set,
+                                                 const uint4 *__restrict__ stream,
+                                                 const uint64_t (&vm)[1]) {
+  const uint4 *base = stream + set.x;
+  uint64_t u0 = vm[0];
+  uint64_t f0, m;
+  uint32_t o, t0, t1, vt, vt2;
+  int acc = 0;
+  asm volatile(AERL_WALK(1)
+               : [acc] "+v"(acc), [u0] "+s"(u0), [f0] "=&s"(f0), [m] "=&s"(m), [o] "=&s"(o),
+                 [t0] "=&s"(t0), [t1] "=&s"(t1), [vt] "=&v"(vt), [vt2] "=&v"(vt2)
+               : [base] "s"(base), [lds] "v"(lds_lane), [lane] "v"(lane)
+               : AERL_WALK_CLOBBERS);
   return acc;
 }
 

@@ -68,17 +68,11 @@ __device__ __forceinline__ void hard_block(const HardTask &t, float *smem, int32
     uint64_t vm[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) vm[s] = ballot(lane * S + s < valid);
-    int dummy[S];
     for (;;) {
       const int q = next_item(next_q);
       if (q >= t.Q) break;
       const int4 set = ldc(t.sets, t.q0 + q);
-      int acc;
-      if constexpr (S == 4) {
-        acc = eval_set_s4_count(lds_lane, lane, set, t.conds, vm);
-      } else {
-        acc = eval_set<S, false>(xs, lane, set, t.conds, vm, dummy);
-      }
+      const int acc = eval_set_count<S>(lds_lane, lane, set, t.conds, vm);
       if (lane < t.nc) cnt[q * t.nc + lane] += (uint16_t)acc;
     }
   }
