@@ -89,9 +89,9 @@ __device__ __forceinline__ T ldc(const T *p, int64_t i) {
 // COUNT mode (PRED = false): returns, in lane c, the number of the tile's
 //   real samples predicted as class c.
 // PRED mode: pred[s] receives the predicted class of each lane's samples.
-// Portable form (any S, both modes), used for prediction; the counting
-// kernels run eval_set_count below, the same walk written for the scalar
-// unit by hand.
+// Portable reference form (any S, both modes); the kernels run
+// eval_set_count / eval_set_pred below, the same walk written for the
+// scalar unit by hand.
 template <int S, bool PRED>
 __device__ __forceinline__ int eval_set(const float *__restrict__ xs, int lane, int4 set,
                                         const uint4 *__restrict__ stream,
@@ -338,9 +338,38 @@ __device__ __forceinline__ int eval_set(const float *__restrict__ xs, int lane, 
   "v_cndmask_b32_e32 %[vt], 0, %[vt], vcc\n"            \
   "v_add_u32 %[acc], %[acc], %[vt]\n"
 
+// Prediction: lanes set in the masks M_i take the class in W (pred_i).
+#define AERL_SET_CLASS_4(W, M0, M1, M2, M3)             \
+  "s_bfe_u32 %[t1], " W ", 0x6000c\n"                   \
+  "v_mov_b32 %[vt], %[t1]\n"                            \
+  "v_cndmask_b32_e64 %[p0], %[p0], %[vt], " M0 "\n"     \
+  "v_cndmask_b32_e64 %[p1], %[p1], %[vt], " M1 "\n"     \
+  "v_cndmask_b32_e64 %[p2], %[p2], %[vt], " M2 "\n"     \
+  "v_cndmask_b32_e64 %[p3], %[p3], %[vt], " M3 "\n"
+#define AERL_SET_CLASS_2(W, M0, M1)                     \
+  "s_bfe_u32 %[t1], " W ", 0x6000c\n"                   \
+  "v_mov_b32 %[vt], %[t1]\n"                            \
+  "v_cndmask_b32_e64 %[p0], %[p0], %[vt], " M0 "\n"     \
+  "v_cndmask_b32_e64 %[p1], %[p1], %[vt], " M1 "\n"
+#define AERL_SET_CLASS_1(W, M0)                         \
+  "s_bfe_u32 %[t1], " W ", 0x6000c\n"                   \
+  "v_mov_b32 %[vt], %[t1]\n"                            \
+  "v_cndmask_b32_e64 %[p0], %[p0], %[vt], " M0 "\n"
+#define AERL_SETC_4F(W) AERL_SET_CLASS_4(W, "%[f0]", "%[f1]", "%[f2]", "%[f3]")
+#define AERL_SETC_4U(W) AERL_SET_CLASS_4(W, "%[u0]", "%[u1]", "%[u2]", "%[u3]")
+#define AERL_SETC_2F(W) AERL_SET_CLASS_2(W, "%[f0]", "%[f1]")
+#define AERL_SETC_2U(W) AERL_SET_CLASS_2(W, "%[u0]", "%[u1]")
+#define AERL_SETC_1F(W) AERL_SET_CLASS_1(W, "%[f0]")
+#define AERL_SETC_1U(W) AERL_SET_CLASS_1(W, "%[u0]")
+
 // The rule of the (last) record in W fires for the lanes in f: count them
-// for its class and retire them (SCC = some lane still undecided).
-#define AERL_COMMIT(S, W) AERL_CAT(AERL_POPC_, AERL_SM(S, F)) AERL_ADD_CLASS(W) AERL_CAT(AERL_RETIRE_, S)
+// for its class (COUNT) or give them its class (PRED), and retire them
+// (SCC = some lane still undecided).
+#define AERL_COMMIT_COUNT(S, W) AERL_CAT(AERL_POPC_, AERL_SM(S, F)) AERL_ADD_CLASS(W) AERL_CAT(AERL_RETIRE_, S)
+#define AERL_COMMIT_PRED(S, W) AERL_CAT(AERL_SETC_, AERL_SM(S, F))(W) AERL_CAT(AERL_RETIRE_, S)
+// An always-true rule in W decides every undecided lane.
+#define AERL_ALWAYS_COUNT(S, W) AERL_CAT(AERL_POPC_, AERL_SM(S, U)) AERL_ADD_CLASS(W)
+#define AERL_ALWAYS_PRED(S, W) AERL_CAT(AERL_SETC_, AERL_SM(S, U))(W)
 
 // Start of a record whose row is at byte offset XX: read the row; special
 // kinds go to SPEC, the <= direction to LE; falls through (row waited for)
@@ -401,8 +430,8 @@ __device__ __forceinline__ int eval_set(const float *__restrict__ xs, int lane, 
   ".Lff_" TAG "_%=:\n"                                  \
   AERL_FF_BODY(S, MODE, W, Y, Z, TAG, POST)
 
-// The whole walk for S samples per lane.
-#define AERL_WALK(S)                                                       \
+// The whole walk for S samples per lane; KIND is COUNT or PRED.
+#define AERL_WALK(S, KIND)                                                 \
   "s_mov_b32 %[o], 0\n"                                                    \
   AERL_CAT(AERL_ANY_U_, S)                                                 \
   "s_cbranch_scc0 .Ldone_%=\n"                                             \
@@ -478,7 +507,7 @@ __device__ __forceinline__ int eval_set(const float *__restrict__ xs, int lane, 
   ".Lya_%=:\n"                                                             \
   "s_bitcmp1_b32 s67, 11\n"                                                \
   "s_cbranch_scc0 .Lnb_%=\n"                                               \
-  AERL_COMMIT(S, "s67")                                                    \
+  AERL_CAT(AERL_COMMIT_, KIND)(S, "s67")                                   \
   "s_cbranch_scc1 .Lsb_%=\n"                                               \
   "s_branch .Ldone_%=\n"                                                   \
   /* after a special record in B */                                        \
@@ -489,20 +518,18 @@ __device__ __forceinline__ int eval_set(const float *__restrict__ xs, int lane, 
   ".Lyb_%=:\n"                                                             \
   "s_bitcmp1_b32 s71, 11\n"                                                \
   "s_cbranch_scc0 .Llna_load_%=\n"                                         \
-  AERL_COMMIT(S, "s71")                                                    \
+  AERL_CAT(AERL_COMMIT_, KIND)(S, "s71")                                   \
   "s_cbranch_scc0 .Ldone_%=\n"                                             \
   "s_add_u32 %[o], %[o], 32\n"                                             \
   "s_branch .Lload_%=\n"                                                   \
   /* an always-true rule decides every undecided lane */                   \
   ".Lalwa_%=:\n"                                                           \
   "s_waitcnt lgkmcnt(0)\n"                                                 \
-  AERL_CAT(AERL_POPC_, AERL_SM(S, U))                                      \
-  AERL_ADD_CLASS("s67")                                                    \
+  AERL_CAT(AERL_ALWAYS_, KIND)(S, "s67")                                   \
   "s_branch .Ldone_%=\n"                                                   \
   ".Lalwb_%=:\n"                                                           \
   "s_waitcnt lgkmcnt(0)\n"                                                 \
-  AERL_CAT(AERL_POPC_, AERL_SM(S, U))                                      \
-  AERL_ADD_CLASS("s71")                                                    \
+  AERL_CAT(AERL_ALWAYS_, KIND)(S, "s71")                                   \
   ".Ldone_%=:\n"
 
 #define AERL_WALK_CLOBBERS                                                 \
@@ -523,7 +550,7 @@ __device__ __forceinline__ int eval_set_count<4>(uint32_t lds_lane, int lane, in
   uint64_t f0, f1, f2, f3, m;
   uint32_t o, t0, t1, vt, vt2;
   int acc = 0;
-  asm volatile(AERL_WALK(4)
+  asm volatile(AERL_WALK(4, COUNT)
                : [acc] "+v"(acc), [u0] "+s"(u0), [u1] "+s"(u1), [u2] "+s"(u2), [u3] "+s"(u3),
                  [f0] "=&s"(f0), [f1] "=&s"(f1), [f2] "=&s"(f2), [f3] "=&s"(f3), [m] "=&s"(m),
                  [o] "=&s"(o), [t0] "=&s"(t0), [t1] "=&s"(t1), [vt] "=&v"(vt), [vt2] "=&v"(vt2)
@@ -541,7 +568,7 @@ __device__ __forceinline__ int eval_set_count<2>(uint32_t lds_lane, int lane, in
   uint64_t f0, f1, m;
   uint32_t o, t0, t1, vt, vt2;
   int acc = 0;
-  asm volatile(AERL_WALK(2)
+  asm volatile(AERL_WALK(2, COUNT)
                : [acc] "+v"(acc), [u0] "+s"(u0), [u1] "+s"(u1), [f0] "=&s"(f0), [f1] "=&s"(f1),
                  [m] "=&s"(m), [o] "=&s"(o), [t0] "=&s"(t0), [t1] "=&s"(t1), [vt] "=&v"(vt),
                  [vt2] "=&v"(vt2)
@@ -559,12 +586,76 @@ __device__ __forceinline__ int eval_set_count<1>(uint32_t lds_lane, int lane, in
   uint64_t f0, m;
   uint32_t o, t0, t1, vt, vt2;
   int acc = 0;
-  asm volatile(AERL_WALK(1)
+  asm volatile(AERL_WALK(1, COUNT)
                : [acc] "+v"(acc), [u0] "+s"(u0), [f0] "=&s"(f0), [m] "=&s"(m), [o] "=&s"(o),
                  [t0] "=&s"(t0), [t1] "=&s"(t1), [vt] "=&v"(vt), [vt2] "=&v"(vt2)
                : [base] "s"(base), [lds] "v"(lds_lane), [lane] "v"(lane)
                : AERL_WALK_CLOBBERS);
   return acc;
+}
+
+// Prediction form of the same walk: pred[s] receives the class of each
+// lane's samples in vm (others keep their value).
+template <int S>
+__device__ __forceinline__ void eval_set_pred(uint32_t lds_lane, int lane, int4 set,
+                                              const uint4 *__restrict__ stream,
+                                              const uint64_t (&vm)[S], int (&pred)[S]);
+
+template <>
+__device__ __forceinline__ void eval_set_pred<4>(uint32_t lds_lane, int lane, int4 set,
+                                                 const uint4 *__restrict__ stream,
+                                                 const uint64_t (&vm)[4], int (&pred)[4]) {
+  const uint4 *base = stream + set.x;
+  uint64_t u0 = vm[0], u1 = vm[1], u2 = vm[2], u3 = vm[3];
+  uint64_t f0, f1, f2, f3, m;
+  uint32_t o, t0, t1, vt, vt2;
+  int p0 = pred[0], p1 = pred[1], p2 = pred[2], p3 = pred[3];
+  asm volatile(AERL_WALK(4, PRED)
+               : [p0] "+v"(p0), [p1] "+v"(p1), [p2] "+v"(p2), [p3] "+v"(p3), [u0] "+s"(u0),
+                 [u1] "+s"(u1), [u2] "+s"(u2), [u3] "+s"(u3), [f0] "=&s"(f0), [f1] "=&s"(f1),
+                 [f2] "=&s"(f2), [f3] "=&s"(f3), [m] "=&s"(m), [o] "=&s"(o), [t0] "=&s"(t0),
+                 [t1] "=&s"(t1), [vt] "=&v"(vt), [vt2] "=&v"(vt2)
+               : [base] "s"(base), [lds] "v"(lds_lane)
+               : AERL_WALK_CLOBBERS);
+  (void)lane;
+  pred[0] = p0; pred[1] = p1; pred[2] = p2; pred[3] = p3;
+}
+
+template <>
+__device__ __forceinline__ void eval_set_pred<2>(uint32_t lds_lane, int lane, int4 set,
+                                                 const uint4 *__restrict__ stream,
+                                                 const uint64_t (&vm)[2], int (&pred)[2]) {
+  const uint4 *base = stream + set.x;
+  uint64_t u0 = vm[0], u1 = vm[1];
+  uint64_t f0, f1, m;
+  uint32_t o, t0, t1, vt, vt2;
+  int p0 = pred[0], p1 = pred[1];
+  asm volatile(AERL_WALK(2, PRED)
+               : [p0] "+v"(p0), [p1] "+v"(p1), [u0] "+s"(u0), [u1] "+s"(u1), [f0] "=&s"(f0),
+                 [f1] "=&s"(f1), [m] "=&s"(m), [o] "=&s"(o), [t0] "=&s"(t0), [t1] "=&s"(t1),
+                 [vt] "=&v"(vt), [vt2] "=&v"(vt2)
+               : [base] "s"(base), [lds] "v"(lds_lane)
+               : AERL_WALK_CLOBBERS);
+  (void)lane;
+  pred[0] = p0; pred[1] = p1;
+}
+
+template <>
+__device__ __forceinline__ void eval_set_pred<1>(uint32_t lds_lane, int lane, int4 set,
+                                                 const uint4 *__restrict__ stream,
+                                                 const uint64_t (&vm)[1], int (&pred)[1]) {
+  const uint4 *base = stream + set.x;
+  uint64_t u0 = vm[0];
+  uint64_t f0, m;
+  uint32_t o, t0, t1, vt, vt2;
+  int p0 = pred[0];
+  asm volatile(AERL_WALK(1, PRED)
+               : [p0] "+v"(p0), [u0] "+s"(u0), [f0] "=&s"(f0), [m] "=&s"(m), [o] "=&s"(o),
+                 [t0] "=&s"(t0), [t1] "=&s"(t1), [vt] "=&v"(vt), [vt2] "=&v"(vt2)
+               : [base] "s"(base), [lds] "v"(lds_lane)
+               : AERL_WALK_CLOBBERS);
+  (void)lane;
+  pred[0] = p0;
 }
 
 }  // namespace aerl

@@ -30,7 +30,9 @@ __device__ __forceinline__ void predict_block(const float *__restrict__ rows, in
     vm[s] = ballot(lane * S + s < m);
     pred[s] = set.z;
   }
-  eval_set<S, true>(xs, lane, set, conds, vm, pred);
+  const uint32_t lds_lane =
+      (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) float *)xs + (uint32_t)lane * (4u * S);
+  eval_set_pred<S>(lds_lane, lane, set, conds, vm, pred);
 #pragma unroll
   for (int s = 0; s < S; ++s)
     if (lane * S + s < m) out[base + lane * S + s] = pred[s];

@@ -147,6 +147,14 @@ def test_special_records_inside_long_rules(ctx):
                                       err_msg=f"set {s}")
 
 
+@pytest.mark.parametrize("nf", [65, 129, 300])
+def test_wide_datasets_default_launch(ctx, nf):
+    """Feature counts that move the default launch to two and one samples
+    per lane (and, at 300, one block per CU)."""
+    w = synth.tiny(70 + nf, n=2500, nf=nf, n_classes=3, n_sets=64, rules=(0, 9), conds=(0, 6))
+    check_against_oracle(ctx, w.data, w.pop)
+
+
 def test_empty_population_rules_and_sets(ctx):
     w = synth.tiny(3, n=500, nf=5)
     pop = from_rule_lists([(1, []), (0, [(1, [])]), (1, [(0, []), (1, [])])] +
