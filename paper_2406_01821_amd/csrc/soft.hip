@@ -202,6 +202,9 @@ struct SoftArgs {
   const int4 *rules;  // {first condition, #conditions, class, 0}
   const uint32_t *sconds;
   const float *coef, *coef2, *theta;
+  // per condition {sconds, coef, theta or coef2, +-log2(e)/tau_f}, gathered
+  // once per launch so that a condition is one scalar load
+  const uint4 *crec;
   int32_t n_sets;
   int32_t sets_per_chunk, tiles_per_group, n_groups;
   int32_t max_rules, max_set_conds;
@@ -235,19 +238,16 @@ __device__ __forceinline__ void group_range(const SoftArgs &a, int g, int &label
 template <int S>
 __device__ __forceinline__ void cond_z(const SoftArgs &a, const float *xs, int lane, int j,
                                        float (&z)[S], float (&xf)[S], float (&xg)[S], bool &ff) {
-  const uint32_t sc = ldc(a.sconds, j);
+  const uint4 r = ldc(a.crec, j);
+  const uint32_t sc = r.x;
   const uint32_t f = sc & 0xfffu, g = (sc >> 12) & 0xfffu;
   ff = ((sc >> 24) & 1u) != 0;
-  const float inv = ldc(a.inv_tau, f) * kLog2e;
-  const float sinv = ((sc >> 25) & 1u) ? inv : -inv;
-  const float c = ldc(a.coef, j);
-  const float c2 = ldc(a.coef2, j);
-  const float th = ldc(a.theta, j);
+  const float c = __uint_as_float(r.y), rv = __uint_as_float(r.z), sinv = __uint_as_float(r.w);
   load_row<S>(xs, f * 1024u, lane, xf);
   load_row<S>(xs, g * 1024u, lane, xg);
 #pragma unroll
   for (int s = 0; s < S; ++s) {
-    const float rhs = ff ? c2 * xg[s] : th;
+    const float rhs = ff ? rv * xg[s] : rv;
     xg[s] = ff ? xg[s] : 1.0f;
     z[s] = fmaf(c, xf[s], -rhs) * sinv;
   }
@@ -257,12 +257,9 @@ __device__ __forceinline__ void cond_z(const SoftArgs &a, const float *xs, int l
 template <int S>
 __device__ __forceinline__ void cond_z_t(const SoftArgs &a, const float *xs, int lane, int j,
                                          float (&z)[S], float (&xf)[S], float (&xg)[S]) {
-  const uint32_t sc = ldc(a.sconds, j);
-  const uint32_t f = sc & 0xfffu;
-  const float inv = ldc(a.inv_tau, f) * kLog2e;
-  const float sinv = ((sc >> 25) & 1u) ? inv : -inv;
-  const float c = ldc(a.coef, j);
-  const float th = ldc(a.theta, j);
+  const uint4 r = ldc(a.crec, j);
+  const uint32_t f = r.x & 0xfffu;
+  const float c = __uint_as_float(r.y), th = __uint_as_float(r.z), sinv = __uint_as_float(r.w);
   load_row<S>(xs, f * 1024u, lane, xf);
 #pragma unroll
   for (int s = 0; s < S; ++s) {
@@ -275,24 +272,37 @@ __device__ __forceinline__ void cond_z_t(const SoftArgs &a, const float *xs, int
 template <int S>
 __device__ __forceinline__ void cond_z_only(const SoftArgs &a, const float *xs, int lane, int j,
                                             float (&z)[S]) {
-  const uint32_t sc = ldc(a.sconds, j);
+  const uint4 r = ldc(a.crec, j);
+  const uint32_t sc = r.x;
   const uint32_t f = sc & 0xfffu, g = (sc >> 12) & 0xfffu;
-  const float inv = ldc(a.inv_tau, f) * kLog2e;
-  const float sinv = ((sc >> 25) & 1u) ? inv : -inv;
-  const float c = ldc(a.coef, j);
+  const float c = __uint_as_float(r.y), rv = __uint_as_float(r.z), sinv = __uint_as_float(r.w);
   float xf[S];
   load_row<S>(xs, f * 1024u, lane, xf);
   if ((sc >> 24) & 1u) {
-    const float c2 = ldc(a.coef2, j);
     float xg[S];
     load_row<S>(xs, g * 1024u, lane, xg);
 #pragma unroll
-    for (int s = 0; s < S; ++s) z[s] = fmaf(c, xf[s], -(c2 * xg[s])) * sinv;
+    for (int s = 0; s < S; ++s) z[s] = fmaf(c, xf[s], -(rv * xg[s])) * sinv;
   } else {
-    const float th = ldc(a.theta, j);
 #pragma unroll
-    for (int s = 0; s < S; ++s) z[s] = fmaf(c, xf[s], -th) * sinv;
+    for (int s = 0; s < S; ++s) z[s] = fmaf(c, xf[s], -rv) * sinv;
   }
+}
+
+// Gathers the per-condition record read by the kernels above: the operand of
+// the right-hand side is theta for a threshold and coef2 for a
+// feature-vs-feature condition; sinv = +-log2(e)/tau_f by direction.
+__global__ void k_soft_prep(const uint32_t *__restrict__ sconds, const float *__restrict__ inv_tau,
+                            const float *__restrict__ coef, const float *__restrict__ coef2,
+                            const float *__restrict__ theta, int32_t n_conds,
+                            uint4 *__restrict__ crec) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n_conds) return;
+  const uint32_t sc = sconds[j];
+  const float inv = inv_tau[sc & 0xfffu] * kLog2e;
+  const float sinv = ((sc >> 25) & 1u) ? inv : -inv;
+  const float rv = ((sc >> 24) & 1u) ? coef2[j] : theta[j];
+  crec[j] = make_uint4(sc, __float_as_uint(coef[j]), __float_as_uint(rv), __float_as_uint(sinv));
 }
 
 constexpr int kSoftBlock = 512;
@@ -842,13 +852,33 @@ bool soft_backward_supported(const DatasetRec &ds, const PopRec &pop) {
   return plan_backward(ds, pop).lds <= kDynLdsMax;
 }
 
-size_t soft_ws_bytes(const DatasetRec &ds, const PopRec &pop, bool backward) {
+namespace {
+
+// Workspace: the partial sums, then (256-byte aligned) the condition records.
+size_t soft_part_bytes(const DatasetRec &ds, const PopRec &pop, bool backward) {
+  size_t b;
   if (backward) {
     const SoftPlan p = plan_backward(ds, pop);
-    return (size_t)p.n_groups * (size_t)std::max(pop.n_conds, 1) * 2 * sizeof(float);
+    b = (size_t)p.n_groups * (size_t)std::max(pop.n_conds, 1) * 2 * sizeof(float);
+  } else {
+    const SoftPlan p = plan_forward(ds, pop);
+    b = (size_t)p.n_groups * (size_t)std::max(pop.n_sets, 1) * sizeof(double);
   }
-  const SoftPlan p = plan_forward(ds, pop);
-  return (size_t)p.n_groups * (size_t)std::max(pop.n_sets, 1) * sizeof(double);
+  return (b + 255) & ~size_t(255);
+}
+
+hipError_t launch_prep(const SoftLaunch &l, const SoftArgs &a, uint4 *crec, hipStream_t st) {
+  const int n = l.pop->n_conds;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_soft_prep, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a.sconds,
+                     a.inv_tau, a.coef, a.coef2, a.theta, n, crec);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+size_t soft_ws_bytes(const DatasetRec &ds, const PopRec &pop, bool backward) {
+  return soft_part_bytes(ds, pop, backward) + (size_t)std::max(pop.n_conds, 1) * sizeof(uint4);
 }
 
 hipError_t launch_soft_forward(const SoftLaunch &l, hipStream_t st) {
@@ -858,6 +888,10 @@ hipError_t launch_soft_forward(const SoftLaunch &l, hipStream_t st) {
   SoftArgs a;
   fill_args(a, l, p);
   a.part_loss = static_cast<double *>(l.ws);
+  uint4 *crec = reinterpret_cast<uint4 *>(static_cast<char *>(l.ws) + soft_part_bytes(*l.ds, pop, false));
+  a.crec = crec;
+  hipError_t e0 = launch_prep(l, a, crec, st);
+  if (e0 != hipSuccess) return e0;
   if (p.n_groups > 0) {
     const dim3 grid((unsigned)((pop.n_sets + p.Q - 1) / p.Q), (unsigned)p.n_groups);
     if (pop.max_rule_conds <= kProdMaxConds) {
@@ -881,6 +915,10 @@ hipError_t launch_soft_backward(const SoftLaunch &l, hipStream_t st) {
   SoftArgs a;
   fill_args(a, l, p);
   a.part_grad = static_cast<float *>(l.ws);
+  uint4 *crec = reinterpret_cast<uint4 *>(static_cast<char *>(l.ws) + soft_part_bytes(*l.ds, pop, true));
+  a.crec = crec;
+  hipError_t e0 = launch_prep(l, a, crec, st);
+  if (e0 != hipSuccess) return e0;
   if (p.n_groups > 0) {
     const dim3 grid((unsigned)((pop.n_sets + p.Q - 1) / p.Q), (unsigned)p.n_groups);
     const bool prod = pop.max_rule_conds <= kProdMaxConds, tonly = pop.n_ff == 0;
