@@ -169,11 +169,12 @@ __device__ __forceinline__ int eval_set(const float *__restrict__ xs, int lane, 
 // wait.  The record after a rule set's last one lies inside the packed
 // stream (the stream ends with a spare record).
 //
-// A non-last record with a folded threshold (x >= t or x <= t) takes the
-// fast path: one flag test for the special kinds, one for the direction, S
-// compares and S mask ANDs.  Special kinds (feature-vs-feature, zero
-// coefficient, always true, a rule's last record) branch out to their own
-// bodies.  Every walk ends in a commit of an always-true record or with no
+// A non-last record with a folded threshold takes the fast path: one flag
+// test, S compares and S mask ANDs.  Inside a rule the >= records come
+// before the <= ones, so the walk runs in the >= direction until a rule's
+// first <= record (flagged) and in the <= direction to the rule's end.
+// Special kinds (feature-vs-feature, zero coefficient, always true, a rule's
+// last record) branch out to their own bodies.  Every walk ends in a commit of an always-true record or with no
 // undecided lane left, so no end-of-stream test is needed.  Every load is
 // waited on inside the asm block.  v32.. hold the feature values of the
 // lane's S samples, v36.. the second row of a feature-vs-feature record.
@@ -371,17 +372,16 @@ __device__ __forceinline__ int eval_set(const float *__restrict__ xs, int lane, 
 #define AERL_ALWAYS_COUNT(S, W) AERL_CAT(AERL_POPC_, AERL_SM(S, U)) AERL_ADD_CLASS(W)
 #define AERL_ALWAYS_PRED(S, W) AERL_CAT(AERL_SETC_, AERL_SM(S, U))(W)
 
-// Start of a record whose row is at byte offset XX: read the row; special
-// kinds go to SPEC, the <= direction to LE; falls through (row waited for)
-// with a >= record.  kRecSpecial = 0xa03, kRecLE = bit 10.
-#define AERL_FETCH(S, XX, XW, SPEC, LE)                 \
+// Start of a record whose row is at byte offset XX: read the row; records
+// with a flag in MASK go to SPEC; falls through (row waited for) with a fast
+// record of the walk's current direction.  In the >= direction MASK is
+// kRecSpecial | kRecDirChg = 0xa07, in the <= direction kRecSpecial = 0xa03.
+#define AERL_FETCH(S, XX, XW, MASK, SPEC)               \
   AERL_CAT(AERL_ADDR_, S)(XX)                           \
   AERL_CAT(AERL_RD_, S)                                 \
-  "s_and_b32 %[t0], " XW ", 0xa03\n"                    \
+  "s_and_b32 %[t0], " XW ", " MASK "\n"                 \
   "s_cbranch_scc1 " SPEC "\n"                           \
-  "s_bitcmp1_b32 " XW ", 10\n"                          \
-  "s_waitcnt lgkmcnt(0)\n"                              \
-  "s_cbranch_scc1 " LE "\n"
+  "s_waitcnt lgkmcnt(0)\n"
 
 // Special threshold kinds of the record (y in Y, z in Z, flags in W), row
 // already requested: zero coefficient (y*x > z), <=, or >= (a last record);
@@ -430,7 +430,9 @@ __device__ __forceinline__ int eval_set(const float *__restrict__ xs, int lane, 
   ".Lff_" TAG "_%=:\n"                                  \
   AERL_FF_BODY(S, MODE, W, Y, Z, TAG, POST)
 
-// The whole walk for S samples per lane; KIND is COUNT or PRED.
+// The whole walk for S samples per lane; KIND is COUNT or PRED.  Labels:
+// s/n = a rule starts / continues at the record, a/b = quad A / B, _le = the
+// <= direction (taken from a rule's first <= record to its end).
 #define AERL_WALK(S, KIND)                                                 \
   "s_mov_b32 %[o], 0\n"                                                    \
   AERL_CAT(AERL_ANY_U_, S)                                                 \
@@ -439,14 +441,14 @@ __device__ __forceinline__ int eval_set(const float *__restrict__ xs, int lane, 
   ".Lload_%=:\n"                                                           \
   "s_load_dwordx8 s[64:71], %[base], %[o]\n"                               \
   "s_waitcnt lgkmcnt(0)\n"                                                 \
-  AERL_FETCH(S, "s64", "s67", ".Lpsa_%=", ".Llsa_%=")                      \
+  AERL_FETCH(S, "s64", "s67", "0xa07", ".Lpsa_%=")                         \
   AERL_CAT(AERL_CMP_, AERL_SM(S, U))("le", "s65")                          \
   /* after a fast record in A: on with B unless no f_i fires */            \
   ".Lqa_%=:\n"                                                             \
   "s_cbranch_scc0 .Lka_%=\n"                                               \
   /* B continues the rule */                                               \
   ".Lnb_%=:\n"                                                             \
-  AERL_FETCH(S, "s68", "s71", ".Lpnb_%=", ".Llnb_%=")                      \
+  AERL_FETCH(S, "s68", "s71", "0xa07", ".Lpnb_%=")                         \
   AERL_CAT(AERL_CMP_, AERL_SM(S, F))("le", "s69")                          \
   ".Lqb_%=:\n"                                                             \
   "s_cbranch_scc0 .Lkb_%=\n"                                               \
@@ -455,7 +457,7 @@ __device__ __forceinline__ int eval_set(const float *__restrict__ xs, int lane, 
   "s_add_u32 %[o], %[o], 32\n"                                             \
   "s_load_dwordx8 s[64:71], %[base], %[o]\n"                               \
   "s_waitcnt lgkmcnt(0)\n"                                                 \
-  AERL_FETCH(S, "s64", "s67", ".Lpna_%=", ".Llna_%=")                      \
+  AERL_FETCH(S, "s64", "s67", "0xa07", ".Lpna_%=")                         \
   AERL_CAT(AERL_CMP_, AERL_SM(S, F))("le", "s65")                          \
   "s_cbranch_scc1 .Lnb_%=\n"                                               \
   /* f0 == 0 after a fast record in A: alive if another slot fires, else */ \
@@ -470,34 +472,70 @@ __device__ __forceinline__ int eval_set(const float *__restrict__ xs, int lane, 
   "s_branch .Lload_%=\n"                                                   \
   /* a rule starts at B (the previous one ended at A) */                   \
   ".Lsb_%=:\n"                                                             \
-  AERL_FETCH(S, "s68", "s71", ".Lpsb_%=", ".Llsb_%=")                      \
+  AERL_FETCH(S, "s68", "s71", "0xa07", ".Lpsb_%=")                         \
   AERL_CAT(AERL_CMP_, AERL_SM(S, U))("le", "s69")                          \
   "s_branch .Lqb_%=\n"                                                     \
-  /* fast records in the <= direction */                                   \
-  ".Llsa_%=:\n"                                                            \
-  AERL_CAT(AERL_CMP_, AERL_SM(S, U))("ge", "s65")                          \
-  "s_branch .Lqa_%=\n"                                                     \
-  ".Llna_%=:\n"                                                            \
-  AERL_CAT(AERL_CMP_, AERL_SM(S, F))("ge", "s65")                          \
-  "s_branch .Lqa_%=\n"                                                     \
-  ".Llsb_%=:\n"                                                            \
-  AERL_CAT(AERL_CMP_, AERL_SM(S, U))("ge", "s69")                          \
-  "s_branch .Lqb_%=\n"                                                     \
-  ".Llnb_%=:\n"                                                            \
+  /* the same walk in the <= direction (rules continue, never start) */    \
+  ".Lqa_le_%=:\n"                                                          \
+  "s_cbranch_scc0 .Lka_le_%=\n"                                            \
+  ".Lnb_le_%=:\n"                                                          \
+  AERL_FETCH(S, "s68", "s71", "0xa03", ".Lpnb_%=")                         \
   AERL_CAT(AERL_CMP_, AERL_SM(S, F))("ge", "s69")                          \
-  "s_branch .Lqb_%=\n"                                                     \
-  /* special records */                                                    \
+  ".Lqb_le_%=:\n"                                                          \
+  "s_cbranch_scc0 .Lkb_le_%=\n"                                            \
+  ".Llna_load_le_%=:\n"                                                    \
+  "s_add_u32 %[o], %[o], 32\n"                                             \
+  "s_load_dwordx8 s[64:71], %[base], %[o]\n"                               \
+  "s_waitcnt lgkmcnt(0)\n"                                                 \
+  AERL_FETCH(S, "s64", "s67", "0xa03", ".Lpna_%=")                         \
+  AERL_CAT(AERL_CMP_, AERL_SM(S, F))("ge", "s65")                          \
+  "s_cbranch_scc1 .Lnb_le_%=\n"                                            \
+  ".Lka_le_%=:\n"                                                          \
+  AERL_CAT(AERL_ANY_F_, S)(".Lnb_le_%=")                                   \
+  "s_lshr_b32 %[o], s67, 18\n"                                             \
+  "s_branch .Lload_%=\n"                                                   \
+  ".Lkb_le_%=:\n"                                                          \
+  AERL_CAT(AERL_ANY_F_, S)(".Llna_load_le_%=")                             \
+  "s_lshr_b32 %[o], s71, 18\n"                                             \
+  "s_branch .Lload_%=\n"                                                   \
+  /* a rule's first <= record (no other flag): compare, then <= walk */    \
+  ".Ldsa_%=:\n"                                                            \
+  "s_waitcnt lgkmcnt(0)\n"                                                 \
+  AERL_CAT(AERL_CMP_, AERL_SM(S, U))("ge", "s65")                          \
+  "s_branch .Lqa_le_%=\n"                                                  \
+  ".Ldna_%=:\n"                                                            \
+  "s_waitcnt lgkmcnt(0)\n"                                                 \
+  AERL_CAT(AERL_CMP_, AERL_SM(S, F))("ge", "s65")                          \
+  "s_branch .Lqa_le_%=\n"                                                  \
+  ".Ldsb_%=:\n"                                                            \
+  "s_waitcnt lgkmcnt(0)\n"                                                 \
+  AERL_CAT(AERL_CMP_, AERL_SM(S, U))("ge", "s69")                          \
+  "s_branch .Lqb_le_%=\n"                                                  \
+  ".Ldnb_%=:\n"                                                            \
+  "s_waitcnt lgkmcnt(0)\n"                                                 \
+  AERL_CAT(AERL_CMP_, AERL_SM(S, F))("ge", "s69")                          \
+  "s_branch .Lqb_le_%=\n"                                                  \
+  /* special records (the direction change alone goes to .Ld*) */          \
   ".Lpsa_%=:\n"                                                            \
+  "s_and_b32 %[t0], s67, 0xa03\n"                                          \
+  "s_cbranch_scc0 .Ldsa_%=\n"                                              \
   AERL_SPEC(S, U, "s65", "s66", "s67", "sa", ".Lxa_%=",                    \
             "s_bitcmp1_b32 s67, 1\n s_cbranch_scc1 .Lalwa_%=\n")           \
   ".Lpna_%=:\n"                                                            \
+  "s_and_b32 %[t0], s67, 0xa03\n"                                          \
+  "s_cbranch_scc0 .Ldna_%=\n"                                              \
   AERL_SPEC(S, F, "s65", "s66", "s67", "na", ".Lxa_%=", "")                \
   ".Lpsb_%=:\n"                                                            \
+  "s_and_b32 %[t0], s71, 0xa03\n"                                          \
+  "s_cbranch_scc0 .Ldsb_%=\n"                                              \
   AERL_SPEC(S, U, "s69", "s70", "s71", "sb", ".Lxb_%=",                    \
             "s_bitcmp1_b32 s71, 1\n s_cbranch_scc1 .Lalwb_%=\n")           \
   ".Lpnb_%=:\n"                                                            \
+  "s_and_b32 %[t0], s71, 0xa03\n"                                          \
+  "s_cbranch_scc0 .Ldnb_%=\n"                                              \
   AERL_SPEC(S, F, "s69", "s70", "s71", "nb", ".Lxb_%=", "")                \
-  /* after a special record in A */                                        \
+  /* after a special record in A (what follows it in its rule is special */ \
+  /* too, or starts a new rule, so the >= labels serve both directions) */ \
   ".Lxa_%=:\n"                                                             \
   AERL_CAT(AERL_ANY_F_, S)(".Lya_%=")                                      \
   "s_bitcmp1_b32 s67, 11\n"                                                \

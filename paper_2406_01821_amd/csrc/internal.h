@@ -48,7 +48,8 @@ aerl_status fail(aerl_ctx *ctx, aerl_status code, const char *fmt, ...);
 //   y, z: fp32 operands (below)
 //   w: flags | class << 12 | next << 18, where next is the byte offset (from
 //      the set's first record) of the next rule's first record.
-// Kinds (all exact rewrites of the caller's condition, pack.cpp):
+// Kinds (all exact rewrites of the caller's condition, pack.cpp), in this
+// order inside a rule:
 //   threshold, folded:      x[f] >= y            (no flag)
 //                           x[f] <= y            (kRecLE)
 //   threshold, zero coef:   y*x[f] > z           (kRecMul)
@@ -61,12 +62,15 @@ aerl_status fail(aerl_ctx *ctx, aerl_status code, const char *fmt, ...);
 constexpr uint32_t kRecGMask = 0x1ffu;
 constexpr uint32_t kRecMul = 1u << 0;     // threshold records only
 constexpr uint32_t kRecAlways = 1u << 1;  // threshold records only
+// Inside a rule the folded thresholds come >= first, then <=; the first <=
+// record carries kRecDirChg, which moves the walk to its <= fast path.
+constexpr uint32_t kRecDirChg = 1u << 2;  // threshold records only
 constexpr uint32_t kRecFF = 1u << 9;
 constexpr uint32_t kRecGE = 1u << 10;  // feature records
 constexpr uint32_t kRecLE = 1u << 10;  // threshold records
 constexpr uint32_t kRecLast = 1u << 11;
-// Records that leave the counting walk's fast path (the folded >= / <=
-// compare of a rule's non-last record).
+// Records that leave the walk's fast path (the folded compare of a rule's
+// non-last record in the walk's current direction).
 constexpr uint32_t kRecSpecial = kRecFF | kRecLast | kRecMul | kRecAlways;
 constexpr uint32_t kRecClsShift = 12;
 constexpr uint32_t kRecNextShift = 18;

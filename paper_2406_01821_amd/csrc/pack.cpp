@@ -226,9 +226,10 @@ void pack_population_image(const aerl_population *p, int32_t nf, int32_t nc, int
   int32_t max_rules = 0, max_rule_conds = 0;
   int64_t nominal = 0;
   // Hard stream: for each rule set its rules in order, then a closing
-  // always-true record of the default class; inside a rule the threshold
-  // conditions first, then feature >, then feature >=.  An empty rule (always
-  // fires) becomes one always-true record.
+  // always-true record of the default class; inside a rule the folded >=
+  // thresholds first, then <=, zero coefficients, feature >, feature >= (an
+  // AND: the order changes no result).  An empty rule (always fires) becomes
+  // one always-true record.
   int32_t out = 0;
   for (int32_t s = 0; s < p->n_sets; ++s) {
     const int32_t r0 = p->set_rule_off[s], r1 = p->set_rule_off[s + 1];
@@ -244,25 +245,44 @@ void pack_population_image(const aerl_population *p, int32_t nf, int32_t nc, int
         hc[out++] = make_uint4(0u, 0u, 0u, kRecAlways | kRecLast | cls | next);
         continue;
       }
+      // groups: folded >=, folded <=, zero coefficient, feature >, feature >=
+      // (the sign of the rewritten coefficient decides a threshold's group)
+      uint8_t grp_of[256];  // a rule has at most AERL_MAX_RULE_CONDS conditions
+      int32_t in_grp[5] = {0, 0, 0, 0, 0};
+      for (int32_t j = j0; j < j1; ++j) {
+        const int op = p->op[j];
+        const bool neg = op == AERL_OP_LT || op == AERL_OP_LE;
+        int g;
+        if (p->kind[j] == AERL_KIND_FEATURE) {
+          g = (op == AERL_OP_GT || op == AERL_OP_LT) ? 3 : 4;
+        } else {
+          const float a0 = neg ? -p->coef[j] : p->coef[j];
+          g = a0 > 0.0f ? 0 : a0 < 0.0f ? 1 : 2;
+        }
+        grp_of[j - j0] = (uint8_t)g;
+        ++in_grp[g];
+      }
       int32_t pos = 0;
-      for (int grp = 0; grp < 3; ++grp) {
+      for (int grp = 0; grp < 5; ++grp) {
+        if (in_grp[grp] == 0) continue;
+        bool first_of_grp = true;
         for (int32_t j = j0; j < j1; ++j) {
+          if (grp_of[j - j0] != grp) continue;
           const int op = p->op[j];
-          const bool ff = p->kind[j] == AERL_KIND_FEATURE;
-          const int my_grp = !ff ? 0 : ((op == AERL_OP_GT || op == AERL_OP_LT) ? 1 : 2);
-          if (my_grp != grp) continue;
           float a, b;
           uint32_t w = cls | next;
-          if (!ff) {
+          if (grp < 3) {
             uint32_t flags;
             threshold_record(p->coef[j], p->theta[j], op, &a, &b, &flags);
+            if (grp == 1 && first_of_grp) flags |= kRecDirChg;
             w |= flags;
           } else {
             const bool neg = op == AERL_OP_LT || op == AERL_OP_LE;
             a = neg ? -p->coef[j] : p->coef[j];
             b = neg ? -p->coef2[j] : p->coef2[j];
-            w |= (uint32_t)p->g[j] | kRecFF | (my_grp == 2 ? kRecGE : 0u);
+            w |= (uint32_t)p->g[j] | kRecFF | (grp == 4 ? kRecGE : 0u);
           }
+          first_of_grp = false;
           if (pos == k - 1) w |= kRecLast;
           hc[out++] = make_uint4((uint32_t)p->f[j] * 1024u, fbits(a), fbits(b), w);
           ++pos;

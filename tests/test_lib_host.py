@@ -217,16 +217,21 @@ def test_threshold_folding_is_exact_at_the_boundary(aerl, seed):
                                       err_msg=f"set {s}: {conds[s]}")
 
 
+DIRCHG = 1 << 2
+
+
 def walk_s4_pairs(x, sets, hc, s, n_records, n_classes):
-    """Label-for-label model of the hard kernel's four-slot record walk,
-    which loads records two at a time into register quads A (offset o) and
-    B (o+16): a rule that goes on past an A record, or starts right after
-    one, continues from B without a load.  Non-last folded threshold records
-    take the fast path (no LAST test); special records (feature, zero
-    coefficient, always true, last) branch out.  Checks that every compare
-    uses the record at its offset, that every pair read stays inside the
-    stream, that always-true records only start rules, and that the walk
-    ends.  Returns per-class prediction counts for the rows of x."""
+    """Label-for-label model of the hard kernel's record walk, which loads
+    records two at a time into register quads A (offset o) and B (o+16): a
+    rule that goes on past an A record, or starts right after one, continues
+    from B without a load.  Non-last folded threshold records take the fast
+    path of the walk's direction: >= from a rule's start, <= from the rule's
+    flagged first <= record on; special records (feature, zero coefficient,
+    always true, last) branch out.  Checks that every compare uses the record
+    at its offset and that a fast record's direction is the walk's, that
+    every pair read stays inside the stream, that always-true records only
+    start rules, and that the walk ends.  Returns per-class prediction counts
+    for the rows of x."""
     first, count, default, _ = (int(v) for v in sets[s])
     u = np.ones(x.shape[0], bool)
     f = None
@@ -240,11 +245,13 @@ def walk_s4_pairs(x, sets, hc, s, n_records, n_classes):
     o = 0
     if not u.any():
         return counts
-    state = "load"
+    state, le = "load", False
     for _ in range(4 * count + 8):
         if state in ("load", "next_load"):
             if state == "next_load":
                 o += 32
+            else:
+                le = False  # a rule starts at A
             quad["A"], quad["B"] = rec(o), rec(o + 16)
             state = ("A", "start" if state == "load" else "next")
             continue
@@ -252,9 +259,16 @@ def walk_s4_pairs(x, sets, hc, s, n_records, n_classes):
         r = quad[X]
         assert r == rec(o if X == "A" else o + 16), "compared a stale record"
         w = r[3]
+        if mode == "start":
+            le = False
         src = u if mode == "start" else f
         cls = (w >> 12) & 63
-        if not w & 0xa03:  # fast path: a folded threshold, not a rule's last record
+        fast = not w & (0xa03 if le else 0xa07)
+        if not fast and not w & 0xa03:  # a rule's first <= record
+            assert w & GE_LE and not le and not w & FF
+            le, fast = True, True
+        if fast:
+            assert not w & FF and bool(w & GE_LE) == le, "compare in the wrong direction"
             f = src & record_mask(x, r)
             if f.any():
                 state = ("B", "next") if X == "A" else "next_load"
@@ -262,6 +276,7 @@ def walk_s4_pairs(x, sets, hc, s, n_records, n_classes):
                 o = w >> 18
                 state = "load"
             continue
+        le = False  # after a special record the >= labels serve
         if not w & FF and w & ALWAYS:
             assert mode == "start", "always-true record inside a rule"
             counts[cls] += int(u.sum())
