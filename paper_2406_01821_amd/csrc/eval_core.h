@@ -177,7 +177,9 @@ __device__ __forceinline__ int eval_set(const float *__restrict__ xs, int lane, 
 // last record) branch out to their own bodies.  Every walk ends in a commit of an always-true record or with no
 // undecided lane left, so no end-of-stream test is needed.  Every load is
 // waited on inside the asm block.  v32.. hold the feature values of the
-// lane's S samples, v36.. the second row of a feature-vs-feature record.
+// lane's S samples, v36.. the second row of a feature-vs-feature record; the
+// fire masks live in the fixed pairs s[56:57], s[58:59], ... so that a commit
+// can count them 32 bits at a time on the VALU.
 //   lds_lane: LDS byte address of the tile plus lane*4*S; record x fields
 //   are row offsets in a 256-sample tile (f*1024), scaled down for S < 4.
 
@@ -206,51 +208,51 @@ __device__ __forceinline__ int eval_set(const float *__restrict__ xs, int lane, 
 #define AERL_CMPT_4(OP, T, S0, S1, S2, S3)              \
   "v_cmp_" OP "_f32_e64 %[m], " T ", v35\n"             \
   "v_cmp_" OP "_f32_e32 vcc, " T ", v34\n"              \
-  "s_and_b64 %[f3], " S3 ", %[m]\n"                     \
+  "s_and_b64 s[62:63], " S3 ", %[m]\n"                     \
   "v_cmp_" OP "_f32_e64 %[m], " T ", v33\n"             \
-  "s_and_b64 %[f2], " S2 ", vcc\n"                      \
+  "s_and_b64 s[60:61], " S2 ", vcc\n"                      \
   "v_cmp_" OP "_f32_e32 vcc, " T ", v32\n"              \
-  "s_and_b64 %[f1], " S1 ", %[m]\n"                     \
-  "s_and_b64 %[f0], " S0 ", vcc\n"
+  "s_and_b64 s[58:59], " S1 ", %[m]\n"                     \
+  "s_and_b64 s[56:57], " S0 ", vcc\n"
 #define AERL_CMPT_2(OP, T, S0, S1)                      \
   "v_cmp_" OP "_f32_e64 %[m], " T ", v33\n"             \
   "v_cmp_" OP "_f32_e32 vcc, " T ", v32\n"              \
-  "s_and_b64 %[f1], " S1 ", %[m]\n"                     \
-  "s_and_b64 %[f0], " S0 ", vcc\n"
+  "s_and_b64 s[58:59], " S1 ", %[m]\n"                     \
+  "s_and_b64 s[56:57], " S0 ", vcc\n"
 #define AERL_CMPT_1(OP, T, S0)                          \
   "v_cmp_" OP "_f32_e32 vcc, " T ", v32\n"              \
-  "s_and_b64 %[f0], " S0 ", vcc\n"
+  "s_and_b64 s[56:57], " S0 ", vcc\n"
 #define AERL_CMP_4U(OP, T) AERL_CMPT_4(OP, T, "%[u0]", "%[u1]", "%[u2]", "%[u3]")
-#define AERL_CMP_4F(OP, T) AERL_CMPT_4(OP, T, "%[f0]", "%[f1]", "%[f2]", "%[f3]")
+#define AERL_CMP_4F(OP, T) AERL_CMPT_4(OP, T, "s[56:57]", "s[58:59]", "s[60:61]", "s[62:63]")
 #define AERL_CMP_2U(OP, T) AERL_CMPT_2(OP, T, "%[u0]", "%[u1]")
-#define AERL_CMP_2F(OP, T) AERL_CMPT_2(OP, T, "%[f0]", "%[f1]")
+#define AERL_CMP_2F(OP, T) AERL_CMPT_2(OP, T, "s[56:57]", "s[58:59]")
 #define AERL_CMP_1U(OP, T) AERL_CMPT_1(OP, T, "%[u0]")
-#define AERL_CMP_1F(OP, T) AERL_CMPT_1(OP, T, "%[f0]")
+#define AERL_CMP_1F(OP, T) AERL_CMPT_1(OP, T, "s[56:57]")
 
 // Feature-vs-feature compare of the products in v32.. and v36...
 #define AERL_FFCMPT_4(OP, S0, S1, S2, S3)               \
   "v_cmp_" OP "_f32_e64 %[m], v35, v39\n"               \
   "v_cmp_" OP "_f32_e32 vcc, v34, v38\n"                \
-  "s_and_b64 %[f3], " S3 ", %[m]\n"                     \
+  "s_and_b64 s[62:63], " S3 ", %[m]\n"                     \
   "v_cmp_" OP "_f32_e64 %[m], v33, v37\n"               \
-  "s_and_b64 %[f2], " S2 ", vcc\n"                      \
+  "s_and_b64 s[60:61], " S2 ", vcc\n"                      \
   "v_cmp_" OP "_f32_e32 vcc, v32, v36\n"                \
-  "s_and_b64 %[f1], " S1 ", %[m]\n"                     \
-  "s_and_b64 %[f0], " S0 ", vcc\n"
+  "s_and_b64 s[58:59], " S1 ", %[m]\n"                     \
+  "s_and_b64 s[56:57], " S0 ", vcc\n"
 #define AERL_FFCMPT_2(OP, S0, S1)                       \
   "v_cmp_" OP "_f32_e64 %[m], v33, v37\n"               \
   "v_cmp_" OP "_f32_e32 vcc, v32, v36\n"                \
-  "s_and_b64 %[f1], " S1 ", %[m]\n"                     \
-  "s_and_b64 %[f0], " S0 ", vcc\n"
+  "s_and_b64 s[58:59], " S1 ", %[m]\n"                     \
+  "s_and_b64 s[56:57], " S0 ", vcc\n"
 #define AERL_FFCMPT_1(OP, S0)                           \
   "v_cmp_" OP "_f32_e32 vcc, v32, v36\n"                \
-  "s_and_b64 %[f0], " S0 ", vcc\n"
+  "s_and_b64 s[56:57], " S0 ", vcc\n"
 #define AERL_FFCMP_4U(OP) AERL_FFCMPT_4(OP, "%[u0]", "%[u1]", "%[u2]", "%[u3]")
-#define AERL_FFCMP_4F(OP) AERL_FFCMPT_4(OP, "%[f0]", "%[f1]", "%[f2]", "%[f3]")
+#define AERL_FFCMP_4F(OP) AERL_FFCMPT_4(OP, "s[56:57]", "s[58:59]", "s[60:61]", "s[62:63]")
 #define AERL_FFCMP_2U(OP) AERL_FFCMPT_2(OP, "%[u0]", "%[u1]")
-#define AERL_FFCMP_2F(OP) AERL_FFCMPT_2(OP, "%[f0]", "%[f1]")
+#define AERL_FFCMP_2F(OP) AERL_FFCMPT_2(OP, "s[56:57]", "s[58:59]")
 #define AERL_FFCMP_1U(OP) AERL_FFCMPT_1(OP, "%[u0]")
-#define AERL_FFCMP_1F(OP) AERL_FFCMPT_1(OP, "%[f0]")
+#define AERL_FFCMP_1F(OP) AERL_FFCMPT_1(OP, "s[56:57]")
 
 // Products of the first row by Y (and of the second by Z).
 #define AERL_MUL1_4(Y)                                  \
@@ -271,24 +273,27 @@ __device__ __forceinline__ int eval_set(const float *__restrict__ xs, int lane, 
 // SCC = (f0 != 0) after a compare: to ALIVE when some f_i is non-zero.
 #define AERL_ANY_F_4(ALIVE)                             \
   "s_cbranch_scc1 " ALIVE "\n"                          \
-  "s_or_b64 %[m], %[f1], %[f2]\n"                       \
-  "s_or_b64 %[m], %[m], %[f3]\n"                        \
+  "s_or_b64 %[m], s[58:59], s[60:61]\n"                       \
+  "s_or_b64 %[m], %[m], s[62:63]\n"                        \
   "s_cbranch_scc1 " ALIVE "\n"
 #define AERL_ANY_F_2(ALIVE)                             \
   "s_cbranch_scc1 " ALIVE "\n"                          \
-  "s_cmp_lg_u64 %[f1], 0\n"                             \
+  "s_cmp_lg_u64 s[58:59], 0\n"                             \
   "s_cbranch_scc1 " ALIVE "\n"
 #define AERL_ANY_F_1(ALIVE) "s_cbranch_scc1 " ALIVE "\n"
 
-// t0 = number of lanes set in the masks F_i (U_i).
+// Lanes set in the fire masks, counted 32 bits at a time on the VALU (the
+// scalar unit is the walk's busiest), into vt; in the undecided masks U_i,
+// on the scalar unit into t0.
 #define AERL_POPC_4F                                    \
-  "s_bcnt1_i32_b64 %[t0], %[f0]\n"                      \
-  "s_bcnt1_i32_b64 %[t1], %[f1]\n"                      \
-  "s_add_u32 %[t0], %[t0], %[t1]\n"                     \
-  "s_bcnt1_i32_b64 %[t1], %[f2]\n"                      \
-  "s_add_u32 %[t0], %[t0], %[t1]\n"                     \
-  "s_bcnt1_i32_b64 %[t1], %[f3]\n"                      \
-  "s_add_u32 %[t0], %[t0], %[t1]\n"
+  "v_bcnt_u32_b32 %[vt], s56, 0\n"                       \
+  "v_bcnt_u32_b32 %[vt], s57, %[vt]\n"                   \
+  "v_bcnt_u32_b32 %[vt], s58, %[vt]\n"                   \
+  "v_bcnt_u32_b32 %[vt], s59, %[vt]\n"                   \
+  "v_bcnt_u32_b32 %[vt], s60, %[vt]\n"                   \
+  "v_bcnt_u32_b32 %[vt], s61, %[vt]\n"                   \
+  "v_bcnt_u32_b32 %[vt], s62, %[vt]\n"                   \
+  "v_bcnt_u32_b32 %[vt], s63, %[vt]\n"
 #define AERL_POPC_4U                                    \
   "s_bcnt1_i32_b64 %[t0], %[u0]\n"                      \
   "s_bcnt1_i32_b64 %[t1], %[u1]\n"                      \
@@ -298,30 +303,31 @@ __device__ __forceinline__ int eval_set(const float *__restrict__ xs, int lane, 
   "s_bcnt1_i32_b64 %[t1], %[u3]\n"                      \
   "s_add_u32 %[t0], %[t0], %[t1]\n"
 #define AERL_POPC_2F                                    \
-  "s_bcnt1_i32_b64 %[t0], %[f0]\n"                      \
-  "s_bcnt1_i32_b64 %[t1], %[f1]\n"                      \
-  "s_add_u32 %[t0], %[t0], %[t1]\n"
+  "v_bcnt_u32_b32 %[vt], s56, 0\n"                       \
+  "v_bcnt_u32_b32 %[vt], s57, %[vt]\n"                   \
+  "v_bcnt_u32_b32 %[vt], s58, %[vt]\n"                   \
+  "v_bcnt_u32_b32 %[vt], s59, %[vt]\n"
 #define AERL_POPC_2U                                    \
   "s_bcnt1_i32_b64 %[t0], %[u0]\n"                      \
   "s_bcnt1_i32_b64 %[t1], %[u1]\n"                      \
   "s_add_u32 %[t0], %[t0], %[t1]\n"
-#define AERL_POPC_1F "s_bcnt1_i32_b64 %[t0], %[f0]\n"
+#define AERL_POPC_1F "v_bcnt_u32_b32 %[vt], s56, 0\n v_bcnt_u32_b32 %[vt], s57, %[vt]\n"
 #define AERL_POPC_1U "s_bcnt1_i32_b64 %[t0], %[u0]\n"
 
 // Retire the fired lanes; SCC = some lane still undecided.
 #define AERL_RETIRE_4                                   \
-  "s_andn2_b64 %[u0], %[u0], %[f0]\n"                   \
-  "s_andn2_b64 %[u1], %[u1], %[f1]\n"                   \
-  "s_andn2_b64 %[u2], %[u2], %[f2]\n"                   \
-  "s_andn2_b64 %[u3], %[u3], %[f3]\n"                   \
+  "s_andn2_b64 %[u0], %[u0], s[56:57]\n"                   \
+  "s_andn2_b64 %[u1], %[u1], s[58:59]\n"                   \
+  "s_andn2_b64 %[u2], %[u2], s[60:61]\n"                   \
+  "s_andn2_b64 %[u3], %[u3], s[62:63]\n"                   \
   "s_or_b64 %[m], %[u0], %[u1]\n"                       \
   "s_or_b64 %[m], %[m], %[u2]\n"                        \
   "s_or_b64 %[m], %[m], %[u3]\n"
 #define AERL_RETIRE_2                                   \
-  "s_andn2_b64 %[u0], %[u0], %[f0]\n"                   \
-  "s_andn2_b64 %[u1], %[u1], %[f1]\n"                   \
+  "s_andn2_b64 %[u0], %[u0], s[56:57]\n"                   \
+  "s_andn2_b64 %[u1], %[u1], s[58:59]\n"                   \
   "s_or_b64 %[m], %[u0], %[u1]\n"
-#define AERL_RETIRE_1 "s_andn2_b64 %[u0], %[u0], %[f0]\n"
+#define AERL_RETIRE_1 "s_andn2_b64 %[u0], %[u0], s[56:57]\n"
 
 // SCC = some lane undecided, at the start of a walk.
 #define AERL_ANY_U_4                                    \
@@ -331,13 +337,15 @@ __device__ __forceinline__ int eval_set(const float *__restrict__ xs, int lane, 
 #define AERL_ANY_U_2 "s_or_b64 %[m], %[u0], %[u1]\n"
 #define AERL_ANY_U_1 "s_cmp_lg_u64 %[u0], 0\n"
 
-// Adds the t0 samples of the class in W to the class's lane of acc.
-#define AERL_ADD_CLASS(W)                               \
+// Adds the vt (t0) samples of the class in W to the class's lane of acc.
+#define AERL_ADD_CLASS_V(W)                             \
   "s_bfe_u32 %[t1], " W ", 0x6000c\n"                   \
   "v_cmp_eq_u32_e32 vcc, %[t1], %[lane]\n"              \
-  "v_mov_b32 %[vt], %[t0]\n"                            \
   "v_cndmask_b32_e32 %[vt], 0, %[vt], vcc\n"            \
   "v_add_u32 %[acc], %[acc], %[vt]\n"
+#define AERL_ADD_CLASS(W)                               \
+  "v_mov_b32 %[vt], %[t0]\n"                            \
+  AERL_ADD_CLASS_V(W)
 
 // Prediction: lanes set in the masks M_i take the class in W (pred_i).
 #define AERL_SET_CLASS_4(W, M0, M1, M2, M3)             \
@@ -356,17 +364,17 @@ __device__ __forceinline__ int eval_set(const float *__restrict__ xs, int lane, 
   "s_bfe_u32 %[t1], " W ", 0x6000c\n"                   \
   "v_mov_b32 %[vt], %[t1]\n"                            \
   "v_cndmask_b32_e64 %[p0], %[p0], %[vt], " M0 "\n"
-#define AERL_SETC_4F(W) AERL_SET_CLASS_4(W, "%[f0]", "%[f1]", "%[f2]", "%[f3]")
+#define AERL_SETC_4F(W) AERL_SET_CLASS_4(W, "s[56:57]", "s[58:59]", "s[60:61]", "s[62:63]")
 #define AERL_SETC_4U(W) AERL_SET_CLASS_4(W, "%[u0]", "%[u1]", "%[u2]", "%[u3]")
-#define AERL_SETC_2F(W) AERL_SET_CLASS_2(W, "%[f0]", "%[f1]")
+#define AERL_SETC_2F(W) AERL_SET_CLASS_2(W, "s[56:57]", "s[58:59]")
 #define AERL_SETC_2U(W) AERL_SET_CLASS_2(W, "%[u0]", "%[u1]")
-#define AERL_SETC_1F(W) AERL_SET_CLASS_1(W, "%[f0]")
+#define AERL_SETC_1F(W) AERL_SET_CLASS_1(W, "s[56:57]")
 #define AERL_SETC_1U(W) AERL_SET_CLASS_1(W, "%[u0]")
 
 // The rule of the (last) record in W fires for the lanes in f: count them
 // for its class (COUNT) or give them its class (PRED), and retire them
 // (SCC = some lane still undecided).
-#define AERL_COMMIT_COUNT(S, W) AERL_CAT(AERL_POPC_, AERL_SM(S, F)) AERL_ADD_CLASS(W) AERL_CAT(AERL_RETIRE_, S)
+#define AERL_COMMIT_COUNT(S, W) AERL_CAT(AERL_POPC_, AERL_SM(S, F)) AERL_ADD_CLASS_V(W) AERL_CAT(AERL_RETIRE_, S)
 #define AERL_COMMIT_PRED(S, W) AERL_CAT(AERL_SETC_, AERL_SM(S, F))(W) AERL_CAT(AERL_RETIRE_, S)
 // An always-true rule in W decides every undecided lane.
 #define AERL_ALWAYS_COUNT(S, W) AERL_CAT(AERL_POPC_, AERL_SM(S, U)) AERL_ADD_CLASS(W)
@@ -571,7 +579,7 @@ __device__ __forceinline__ int eval_set(const float *__restrict__ xs, int lane, 
   ".Ldone_%=:\n"
 
 #define AERL_WALK_CLOBBERS                                                 \
-  "s64", "s65", "s66", "s67", "s68", "s69", "s70", "s71", "v32", "v33", "v34", \
+  "s56", "s57", "s58", "s59", "s60", "s61", "s62", "s63", "s64", "s65", "s66", "s67", "s68", "s69", "s70", "s71", "v32", "v33", "v34", \
       "v35", "v36", "v37", "v38", "v39", "vcc", "scc", "memory"
 
 template <int S>
@@ -585,12 +593,12 @@ __device__ __forceinline__ int eval_set_count<4>(uint32_t lds_lane, int lane, in
                                                  const uint64_t (&vm)[4]) {
   const uint4 *base = stream + set.x;
   uint64_t u0 = vm[0], u1 = vm[1], u2 = vm[2], u3 = vm[3];
-  uint64_t f0, f1, f2, f3, m;
+  uint64_t m;
   uint32_t o, t0, t1, vt, vt2;
   int acc = 0;
   asm volatile(AERL_WALK(4, COUNT)
                : [acc] "+v"(acc), [u0] "+s"(u0), [u1] "+s"(u1), [u2] "+s"(u2), [u3] "+s"(u3),
-                 [f0] "=&s"(f0), [f1] "=&s"(f1), [f2] "=&s"(f2), [f3] "=&s"(f3), [m] "=&s"(m),
+                 [m] "=&s"(m),
                  [o] "=&s"(o), [t0] "=&s"(t0), [t1] "=&s"(t1), [vt] "=&v"(vt), [vt2] "=&v"(vt2)
                : [base] "s"(base), [lds] "v"(lds_lane), [lane] "v"(lane)
                : AERL_WALK_CLOBBERS);
@@ -603,12 +611,11 @@ __device__ __forceinline__ int eval_set_count<2>(uint32_t lds_lane, int lane, in
                                                  const uint64_t (&vm)[2]) {
   const uint4 *base = stream + set.x;
   uint64_t u0 = vm[0], u1 = vm[1];
-  uint64_t f0, f1, m;
+  uint64_t m;
   uint32_t o, t0, t1, vt, vt2;
   int acc = 0;
   asm volatile(AERL_WALK(2, COUNT)
-               : [acc] "+v"(acc), [u0] "+s"(u0), [u1] "+s"(u1), [f0] "=&s"(f0), [f1] "=&s"(f1),
-                 [m] "=&s"(m), [o] "=&s"(o), [t0] "=&s"(t0), [t1] "=&s"(t1), [vt] "=&v"(vt),
+               : [acc] "+v"(acc), [u0] "+s"(u0), [u1] "+s"(u1), [m] "=&s"(m), [o] "=&s"(o), [t0] "=&s"(t0), [t1] "=&s"(t1), [vt] "=&v"(vt),
                  [vt2] "=&v"(vt2)
                : [base] "s"(base), [lds] "v"(lds_lane), [lane] "v"(lane)
                : AERL_WALK_CLOBBERS);
@@ -621,11 +628,11 @@ __device__ __forceinline__ int eval_set_count<1>(uint32_t lds_lane, int lane, in
                                                  const uint64_t (&vm)[1]) {
   const uint4 *base = stream + set.x;
   uint64_t u0 = vm[0];
-  uint64_t f0, m;
+  uint64_t m;
   uint32_t o, t0, t1, vt, vt2;
   int acc = 0;
   asm volatile(AERL_WALK(1, COUNT)
-               : [acc] "+v"(acc), [u0] "+s"(u0), [f0] "=&s"(f0), [m] "=&s"(m), [o] "=&s"(o),
+               : [acc] "+v"(acc), [u0] "+s"(u0), [m] "=&s"(m), [o] "=&s"(o),
                  [t0] "=&s"(t0), [t1] "=&s"(t1), [vt] "=&v"(vt), [vt2] "=&v"(vt2)
                : [base] "s"(base), [lds] "v"(lds_lane), [lane] "v"(lane)
                : AERL_WALK_CLOBBERS);
@@ -645,13 +652,12 @@ __device__ __forceinline__ void eval_set_pred<4>(uint32_t lds_lane, int lane, in
                                                  const uint64_t (&vm)[4], int (&pred)[4]) {
   const uint4 *base = stream + set.x;
   uint64_t u0 = vm[0], u1 = vm[1], u2 = vm[2], u3 = vm[3];
-  uint64_t f0, f1, f2, f3, m;
+  uint64_t m;
   uint32_t o, t0, t1, vt, vt2;
   int p0 = pred[0], p1 = pred[1], p2 = pred[2], p3 = pred[3];
   asm volatile(AERL_WALK(4, PRED)
                : [p0] "+v"(p0), [p1] "+v"(p1), [p2] "+v"(p2), [p3] "+v"(p3), [u0] "+s"(u0),
-                 [u1] "+s"(u1), [u2] "+s"(u2), [u3] "+s"(u3), [f0] "=&s"(f0), [f1] "=&s"(f1),
-                 [f2] "=&s"(f2), [f3] "=&s"(f3), [m] "=&s"(m), [o] "=&s"(o), [t0] "=&s"(t0),
+                 [u1] "+s"(u1), [u2] "+s"(u2), [u3] "+s"(u3), [m] "=&s"(m), [o] "=&s"(o), [t0] "=&s"(t0),
                  [t1] "=&s"(t1), [vt] "=&v"(vt), [vt2] "=&v"(vt2)
                : [base] "s"(base), [lds] "v"(lds_lane)
                : AERL_WALK_CLOBBERS);
@@ -665,12 +671,11 @@ __device__ __forceinline__ void eval_set_pred<2>(uint32_t lds_lane, int lane, in
                                                  const uint64_t (&vm)[2], int (&pred)[2]) {
   const uint4 *base = stream + set.x;
   uint64_t u0 = vm[0], u1 = vm[1];
-  uint64_t f0, f1, m;
+  uint64_t m;
   uint32_t o, t0, t1, vt, vt2;
   int p0 = pred[0], p1 = pred[1];
   asm volatile(AERL_WALK(2, PRED)
-               : [p0] "+v"(p0), [p1] "+v"(p1), [u0] "+s"(u0), [u1] "+s"(u1), [f0] "=&s"(f0),
-                 [f1] "=&s"(f1), [m] "=&s"(m), [o] "=&s"(o), [t0] "=&s"(t0), [t1] "=&s"(t1),
+               : [p0] "+v"(p0), [p1] "+v"(p1), [u0] "+s"(u0), [u1] "+s"(u1), [m] "=&s"(m), [o] "=&s"(o), [t0] "=&s"(t0), [t1] "=&s"(t1),
                  [vt] "=&v"(vt), [vt2] "=&v"(vt2)
                : [base] "s"(base), [lds] "v"(lds_lane)
                : AERL_WALK_CLOBBERS);
@@ -684,11 +689,11 @@ __device__ __forceinline__ void eval_set_pred<1>(uint32_t lds_lane, int lane, in
                                                  const uint64_t (&vm)[1], int (&pred)[1]) {
   const uint4 *base = stream + set.x;
   uint64_t u0 = vm[0];
-  uint64_t f0, m;
+  uint64_t m;
   uint32_t o, t0, t1, vt, vt2;
   int p0 = pred[0];
   asm volatile(AERL_WALK(1, PRED)
-               : [p0] "+v"(p0), [u0] "+s"(u0), [f0] "=&s"(f0), [m] "=&s"(m), [o] "=&s"(o),
+               : [p0] "+v"(p0), [u0] "+s"(u0), [m] "=&s"(m), [o] "=&s"(o),
                  [t0] "=&s"(t0), [t1] "=&s"(t1), [vt] "=&v"(vt), [vt2] "=&v"(vt2)
                : [base] "s"(base), [lds] "v"(lds_lane)
                : AERL_WALK_CLOBBERS);
