@@ -174,9 +174,11 @@ __device__ __forceinline__ int eval_set(const float *__restrict__ xs, int lane, 
 // before the <= ones, so the walk runs in the >= direction until a rule's
 // first <= record (flagged) and in the <= direction to the rule's end.
 // Special kinds (feature-vs-feature, zero coefficient, always true, a rule's
-// last record) branch out to their own bodies.  Every walk ends in a commit of an always-true record or with no
-// undecided lane left, so no end-of-stream test is needed.  Every load is
-// waited on inside the asm block.  v32.. hold the feature values of the
+// last record) branch out to their own bodies.  Every walk ends in a commit
+// of an always-true record or with no undecided lane left, so no
+// end-of-stream test is needed (a walk that starts with no undecided lane
+// ends at the closing record, counting none).  Every load is waited on
+// inside the asm block.  v32.. hold the feature values of the
 // lane's S samples, v36.. the second row of a feature-vs-feature record; the
 // fire masks live in the fixed pairs s[56:57], s[58:59], ... so that a commit
 // can count them 32 bits at a time on the VALU.
@@ -329,14 +331,6 @@ __device__ __forceinline__ int eval_set(const float *__restrict__ xs, int lane, 
   "s_or_b64 %[m], %[u0], %[u1]\n"
 #define AERL_RETIRE_1 "s_andn2_b64 %[u0], %[u0], s[56:57]\n"
 
-// SCC = some lane undecided, at the start of a walk.
-#define AERL_ANY_U_4                                    \
-  "s_or_b64 %[m], %[u0], %[u1]\n"                       \
-  "s_or_b64 %[m], %[m], %[u2]\n"                        \
-  "s_or_b64 %[m], %[m], %[u3]\n"
-#define AERL_ANY_U_2 "s_or_b64 %[m], %[u0], %[u1]\n"
-#define AERL_ANY_U_1 "s_cmp_lg_u64 %[u0], 0\n"
-
 // Adds the vt (t0) samples of the class in W to the class's lane of acc.
 #define AERL_ADD_CLASS_V(W)                             \
   "s_bfe_u32 %[t1], " W ", 0x6000c\n"                   \
@@ -443,8 +437,6 @@ __device__ __forceinline__ int eval_set(const float *__restrict__ xs, int lane, 
 // <= direction (taken from a rule's first <= record to its end).
 #define AERL_WALK(S, KIND)                                                 \
   "s_mov_b32 %[o], 0\n"                                                    \
-  AERL_CAT(AERL_ANY_U_, S)                                                 \
-  "s_cbranch_scc0 .Ldone_%=\n"                                             \
   /* load the pair (o, o+16) into A, B; a rule starts at A */              \
   ".Lload_%=:\n"                                                           \
   "s_load_dwordx8 s[64:71], %[base], %[o]\n"                               \

@@ -68,12 +68,18 @@ __device__ __forceinline__ void hard_block(const HardTask &t, float *smem, int32
     uint64_t vm[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) vm[s] = ballot(lane * S + s < valid);
+    if (valid == 0) continue;  // an empty wave tile (S < 4 at a region's end)
     for (;;) {
-      const int q = next_item(next_q);
-      if (q >= t.Q) break;
-      const int4 set = ldc(t.sets, t.q0 + q);
-      const int acc = eval_set_count<S>(lds_lane, lane, set, t.conds, vm);
-      if (lane < t.nc) cnt[q * t.nc + lane] += (uint16_t)acc;
+      int q0 = 0;
+      if (lane == 0) q0 = atomicAdd(next_q, 2);  // two rule sets per grab
+      q0 = __builtin_amdgcn_readfirstlane(q0);
+      if (q0 >= t.Q) break;
+      const int q1 = min(q0 + 2, t.Q);
+      for (int q = q0; q < q1; ++q) {
+        const int4 set = ldc(t.sets, t.q0 + q);
+        const int acc = eval_set_count<S>(lds_lane, lane, set, t.conds, vm);
+        if (lane < t.nc) cnt[q * t.nc + lane] += (uint16_t)acc;
+      }
     }
   }
   __syncthreads();
