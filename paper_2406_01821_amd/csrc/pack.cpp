@@ -246,47 +246,45 @@ void pack_population_image(const aerl_population *p, int32_t nf, int32_t nc, int
         continue;
       }
       // groups: folded >=, folded <=, zero coefficient, feature >, feature >=
-      // (the sign of the rewritten coefficient decides a threshold's group)
-      uint8_t grp_of[256];  // a rule has at most AERL_MAX_RULE_CONDS conditions
-      int32_t in_grp[5] = {0, 0, 0, 0, 0};
+      // (the sign of the rewritten coefficient decides a threshold's group);
+      // a stable counting sort puts the rule's conditions in group order
+      uint8_t grp_of[256], order[256];  // at most AERL_MAX_RULE_CONDS conditions
+      int32_t start[6] = {0, 0, 0, 0, 0, 0};
       for (int32_t j = j0; j < j1; ++j) {
         const int op = p->op[j];
-        const bool neg = op == AERL_OP_LT || op == AERL_OP_LE;
         int g;
         if (p->kind[j] == AERL_KIND_FEATURE) {
           g = (op == AERL_OP_GT || op == AERL_OP_LT) ? 3 : 4;
         } else {
-          const float a0 = neg ? -p->coef[j] : p->coef[j];
+          const float a0 = (op == AERL_OP_LT || op == AERL_OP_LE) ? -p->coef[j] : p->coef[j];
           g = a0 > 0.0f ? 0 : a0 < 0.0f ? 1 : 2;
         }
         grp_of[j - j0] = (uint8_t)g;
-        ++in_grp[g];
+        ++start[g + 1];
       }
-      int32_t pos = 0;
-      for (int grp = 0; grp < 5; ++grp) {
-        if (in_grp[grp] == 0) continue;
-        bool first_of_grp = true;
-        for (int32_t j = j0; j < j1; ++j) {
-          if (grp_of[j - j0] != grp) continue;
-          const int op = p->op[j];
-          float a, b;
-          uint32_t w = cls | next;
-          if (grp < 3) {
-            uint32_t flags;
-            threshold_record(p->coef[j], p->theta[j], op, &a, &b, &flags);
-            if (grp == 1 && first_of_grp) flags |= kRecDirChg;
-            w |= flags;
-          } else {
-            const bool neg = op == AERL_OP_LT || op == AERL_OP_LE;
-            a = neg ? -p->coef[j] : p->coef[j];
-            b = neg ? -p->coef2[j] : p->coef2[j];
-            w |= (uint32_t)p->g[j] | kRecFF | (grp == 4 ? kRecGE : 0u);
-          }
-          first_of_grp = false;
-          if (pos == k - 1) w |= kRecLast;
-          hc[out++] = make_uint4((uint32_t)p->f[j] * 1024u, fbits(a), fbits(b), w);
-          ++pos;
+      for (int g = 0; g < 5; ++g) start[g + 1] += start[g];
+      for (int32_t i = 0; i < k; ++i) order[start[grp_of[i]]++] = (uint8_t)i;
+      int prev_grp = -1;
+      for (int32_t pos = 0; pos < k; ++pos) {
+        const int32_t j = j0 + order[pos];
+        const int grp = grp_of[order[pos]];
+        const int op = p->op[j];
+        float a, b;
+        uint32_t w = cls | next;
+        if (grp < 3) {
+          uint32_t flags;
+          threshold_record(p->coef[j], p->theta[j], op, &a, &b, &flags);
+          if (grp == 1 && prev_grp != 1) flags |= kRecDirChg;
+          w |= flags;
+        } else {
+          const bool neg = op == AERL_OP_LT || op == AERL_OP_LE;
+          a = neg ? -p->coef[j] : p->coef[j];
+          b = neg ? -p->coef2[j] : p->coef2[j];
+          w |= (uint32_t)p->g[j] | kRecFF | (grp == 4 ? kRecGE : 0u);
         }
+        prev_grp = grp;
+        if (pos == k - 1) w |= kRecLast;
+        hc[out++] = make_uint4((uint32_t)p->f[j] * 1024u, fbits(a), fbits(b), w);
       }
     }
     const uint32_t end = (uint32_t)(out - first + 1) * 16u << kRecNextShift;
