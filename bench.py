@@ -357,8 +357,8 @@ def main():
                     help="run only a plain 256 MiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(rule sets or samples would be split across GPUs)", file=sys.stderr)
         sys.exit(2)
 
     import torch

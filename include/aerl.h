@@ -53,7 +53,7 @@ enum {
   AERL_ESTATE = -7     /* call not valid in the current state */
 };
 
-/* Limits of this build. */
+/* Limits of the library. */
 #define AERL_MAX_CLASSES 64        /* classes per dataset */
 #define AERL_MAX_FEATURES 512      /* features per dataset (one LDS tile row each) */
 #define AERL_MAX_RULE_CONDS 255    /* conditions per rule */
