@@ -31,9 +31,9 @@ struct HardTask {
 };
 
 // Stages one wave tile (64*S samples x nf features) at a time into LDS and
-// lets the waves pull rule sets from an LDS counter; per-class prediction
-// counts live in LDS (one writer per rule set and tile) and reach the
-// outputs once, through integer atomics.  smem holds nf*64*S floats followed
+// lets the waves pull rule sets, two at a time, from an LDS counter;
+// per-class prediction counts live in LDS (one writer per rule set and tile)
+// and reach the outputs once, through integer atomics.  smem holds nf*64*S floats followed
 // by Q*nc 16-bit counters (a block covers at most 255 layout tiles, so a
 // counter stays below 2^16).  Ends with a barrier, so the caller may reuse
 // smem.
