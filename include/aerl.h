@@ -163,7 +163,8 @@ typedef struct {
 /* Bytes of the device workspace that holds the packed form of `pop`.
  * Validates the structure (offsets, ops, kinds, classes, feature indices
  * against n_features, g != f for kind 1, finite coefficients, non-NaN
- * thresholds, at most AERL_MAX_RULE_CONDS conditions per rule).
+ * thresholds, at most AERL_MAX_RULE_CONDS conditions per rule and at most
+ * 1022 conditions per rule set, an empty rule counting as one).
  * Errors: AERL_EINVAL with the first offending index in the message. */
 aerl_status aerl_population_bytes(const aerl_population *pop, int32_t n_features,
                                   int32_t n_classes, size_t *bytes);
@@ -381,7 +382,8 @@ aerl_status aerl_serve_stop(aerl_ctx *ctx);
 
 /* Device scratch needed by aerl_soft_forward / aerl_soft_backward for this
  * dataset and population (per-block partial sums that are reduced in a
- * fixed order, which keeps results bit-identical from run to run).
+ * fixed order, which keeps results bit-identical from run to run, and one
+ * 16-byte record per condition gathered at each call).
  * Errors: AERL_ENOENT, AERL_EINVAL. */
 aerl_status aerl_soft_workspace_bytes(aerl_ctx *ctx, int32_t dataset_id, int32_t pop_id,
                                       size_t *forward_bytes, size_t *backward_bytes);
