@@ -81,6 +81,7 @@ void build_batch_tables(const std::vector<BatchSource> &src, const BatchSplit &s
     it.tile_info = ds.tile_info;
     it.sets = src[i].sets;
     it.conds = src[i].conds;
+    it.heads = src[i].heads;
     it.correct = src[i].correct;
     it.confusion = src[i].confusion;
     it.nf = ds.nf;
@@ -162,7 +163,7 @@ aerl_status gather(aerl_ctx *ctx, const aerl_batch_item *items, int32_t n, std::
       return fail(ctx, AERL_EINVAL, "item %d: population and dataset shapes differ", i);
     if (pi->second.n_sets > 0 && !items[i].correct)
       return fail(ctx, AERL_EINVAL, "item %d: correct is NULL", i);
-    if ((size_t)di->second.nf * 64 * 4 + (size_t)di->second.nc * 4 > kBatchLdsMax)
+    if (hard_block_lds(di->second.nf, 1, 1, di->second.nc) > kBatchLdsMax)
       return fail(ctx, AERL_EINVAL, "item %d: %d features exceed the LDS tile", i, di->second.nf);
     out->push_back({&di->second, &pi->second, &items[i]});
   }
@@ -174,7 +175,8 @@ std::vector<BatchSource> sources(const std::vector<ItemView> &v) {
   for (const auto &it : v) {
     // The set records lead the population's host staging copy of its image.
     src.push_back({it.ds, it.pop->n_sets, static_cast<const int4 *>(it.pop->staging),
-                   it.pop->sets, it.pop->hconds, it.item->correct, it.item->confusion});
+                   it.pop->sets, it.pop->hconds, it.pop->heads, it.item->correct,
+                   it.item->confusion});
   }
   return src;
 }

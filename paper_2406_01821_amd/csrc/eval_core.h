@@ -82,6 +82,15 @@ __device__ __forceinline__ T ldc(const T *p, int64_t i) {
   return ldc_at(p + i, 0u);
 }
 
+// Two consecutive 16-byte records in one 32-byte scalar load.
+__device__ __forceinline__ void ldc_pair(const int4 *p, int4 (&out)[2]) {
+  typedef int32_t v8i __attribute__((ext_vector_type(8)));
+  typedef const __attribute__((address_space(4))) v8i *cptr;
+  const v8i v = *(cptr)(p);
+  out[0] = make_int4(v[0], v[1], v[2], v[3]);
+  out[1] = make_int4(v[4], v[5], v[6], v[7]);
+}
+
 // Evaluates rule set `set` = {first record, record count, default, -} of the
 // hard stream for the S*64 samples of the tile.  vm[s]: lanes whose slot-s
 // sample is real.  The set's closing record (always true, default class)
@@ -101,7 +110,7 @@ __device__ __forceinline__ int eval_set(const float *__restrict__ xs, int lane, 
   for (int s = 0; s < S; ++s) und[s] = fire[s] = vm[s];
   int acc = 0;
   const uint4 *base = stream + set.x;
-  const uint32_t end = (uint32_t)set.y * 16u;
+  const uint32_t end = (uint32_t)(set.y & 0xffff) * 16u;
   uint32_t o = 0;
   while (o < end) {
     const uint4 r = ldc_at(base, o);
@@ -286,7 +295,7 @@ __device__ __forceinline__ int eval_set(const float *__restrict__ xs, int lane, 
 
 // Lanes set in the fire masks, counted 32 bits at a time on the VALU (the
 // scalar unit is the walk's busiest), into vt; in the undecided masks U_i,
-// on the scalar unit into t0.
+// on the scalar unit into t0 (o as the temporary: the walk ends there).
 #define AERL_POPC_4F                                    \
   "v_bcnt_u32_b32 %[vt], s56, 0\n"                       \
   "v_bcnt_u32_b32 %[vt], s57, %[vt]\n"                   \
@@ -298,12 +307,12 @@ __device__ __forceinline__ int eval_set(const float *__restrict__ xs, int lane, 
   "v_bcnt_u32_b32 %[vt], s63, %[vt]\n"
 #define AERL_POPC_4U                                    \
   "s_bcnt1_i32_b64 %[t0], %[u0]\n"                      \
-  "s_bcnt1_i32_b64 %[t1], %[u1]\n"                      \
-  "s_add_u32 %[t0], %[t0], %[t1]\n"                     \
-  "s_bcnt1_i32_b64 %[t1], %[u2]\n"                      \
-  "s_add_u32 %[t0], %[t0], %[t1]\n"                     \
-  "s_bcnt1_i32_b64 %[t1], %[u3]\n"                      \
-  "s_add_u32 %[t0], %[t0], %[t1]\n"
+  "s_bcnt1_i32_b64 %[o], %[u1]\n"                       \
+  "s_add_u32 %[t0], %[t0], %[o]\n"                     \
+  "s_bcnt1_i32_b64 %[o], %[u2]\n"                       \
+  "s_add_u32 %[t0], %[t0], %[o]\n"                     \
+  "s_bcnt1_i32_b64 %[o], %[u3]\n"                       \
+  "s_add_u32 %[t0], %[t0], %[o]\n"
 #define AERL_POPC_2F                                    \
   "v_bcnt_u32_b32 %[vt], s56, 0\n"                       \
   "v_bcnt_u32_b32 %[vt], s57, %[vt]\n"                   \
@@ -311,30 +320,32 @@ __device__ __forceinline__ int eval_set(const float *__restrict__ xs, int lane, 
   "v_bcnt_u32_b32 %[vt], s59, %[vt]\n"
 #define AERL_POPC_2U                                    \
   "s_bcnt1_i32_b64 %[t0], %[u0]\n"                      \
-  "s_bcnt1_i32_b64 %[t1], %[u1]\n"                      \
-  "s_add_u32 %[t0], %[t0], %[t1]\n"
+  "s_bcnt1_i32_b64 %[o], %[u1]\n"                       \
+  "s_add_u32 %[t0], %[t0], %[o]\n"
 #define AERL_POPC_1F "v_bcnt_u32_b32 %[vt], s56, 0\n v_bcnt_u32_b32 %[vt], s57, %[vt]\n"
 #define AERL_POPC_1U "s_bcnt1_i32_b64 %[t0], %[u0]\n"
 
-// Retire the fired lanes; SCC = some lane still undecided.
-#define AERL_RETIRE_4                                   \
+// Retire the fired lanes: to ALIVE as soon as the last slot still has an
+// undecided lane, else falls through with SCC = some lane still undecided.
+#define AERL_RETIRE_4(ALIVE)                            \
   "s_andn2_b64 %[u0], %[u0], s[56:57]\n"                   \
   "s_andn2_b64 %[u1], %[u1], s[58:59]\n"                   \
   "s_andn2_b64 %[u2], %[u2], s[60:61]\n"                   \
   "s_andn2_b64 %[u3], %[u3], s[62:63]\n"                   \
+  "s_cbranch_scc1 " ALIVE "\n"                          \
   "s_or_b64 %[m], %[u0], %[u1]\n"                       \
-  "s_or_b64 %[m], %[m], %[u2]\n"                        \
-  "s_or_b64 %[m], %[m], %[u3]\n"
-#define AERL_RETIRE_2                                   \
+  "s_or_b64 %[m], %[m], %[u2]\n"
+#define AERL_RETIRE_2(ALIVE)                            \
   "s_andn2_b64 %[u0], %[u0], s[56:57]\n"                   \
   "s_andn2_b64 %[u1], %[u1], s[58:59]\n"                   \
-  "s_or_b64 %[m], %[u0], %[u1]\n"
-#define AERL_RETIRE_1 "s_andn2_b64 %[u0], %[u0], s[56:57]\n"
+  "s_cbranch_scc1 " ALIVE "\n"                          \
+  "s_cmp_lg_u64 %[u0], 0\n"
+#define AERL_RETIRE_1(ALIVE) "s_andn2_b64 %[u0], %[u0], s[56:57]\n"
 
 // Adds the vt (t0) samples of the class in W to the class's lane of acc.
 #define AERL_ADD_CLASS_V(W)                             \
-  "s_bfe_u32 %[t1], " W ", 0x6000c\n"                   \
-  "v_cmp_eq_u32_e32 vcc, %[t1], %[lane]\n"              \
+  "v_bfe_u32 %[vt2], " W ", 12, 6\n"                    \
+  "v_cmp_eq_u32_e32 vcc, %[vt2], %[lane]\n"             \
   "v_cndmask_b32_e32 %[vt], 0, %[vt], vcc\n"            \
   "v_add_u32 %[acc], %[acc], %[vt]\n"
 #define AERL_ADD_CLASS(W)                               \
@@ -343,20 +354,17 @@ __device__ __forceinline__ int eval_set(const float *__restrict__ xs, int lane, 
 
 // Prediction: lanes set in the masks M_i take the class in W (pred_i).
 #define AERL_SET_CLASS_4(W, M0, M1, M2, M3)             \
-  "s_bfe_u32 %[t1], " W ", 0x6000c\n"                   \
-  "v_mov_b32 %[vt], %[t1]\n"                            \
+  "v_bfe_u32 %[vt], " W ", 12, 6\n"                     \
   "v_cndmask_b32_e64 %[p0], %[p0], %[vt], " M0 "\n"     \
   "v_cndmask_b32_e64 %[p1], %[p1], %[vt], " M1 "\n"     \
   "v_cndmask_b32_e64 %[p2], %[p2], %[vt], " M2 "\n"     \
   "v_cndmask_b32_e64 %[p3], %[p3], %[vt], " M3 "\n"
 #define AERL_SET_CLASS_2(W, M0, M1)                     \
-  "s_bfe_u32 %[t1], " W ", 0x6000c\n"                   \
-  "v_mov_b32 %[vt], %[t1]\n"                            \
+  "v_bfe_u32 %[vt], " W ", 12, 6\n"                     \
   "v_cndmask_b32_e64 %[p0], %[p0], %[vt], " M0 "\n"     \
   "v_cndmask_b32_e64 %[p1], %[p1], %[vt], " M1 "\n"
 #define AERL_SET_CLASS_1(W, M0)                         \
-  "s_bfe_u32 %[t1], " W ", 0x6000c\n"                   \
-  "v_mov_b32 %[vt], %[t1]\n"                            \
+  "v_bfe_u32 %[vt], " W ", 12, 6\n"                     \
   "v_cndmask_b32_e64 %[p0], %[p0], %[vt], " M0 "\n"
 #define AERL_SETC_4F(W) AERL_SET_CLASS_4(W, "s[56:57]", "s[58:59]", "s[60:61]", "s[62:63]")
 #define AERL_SETC_4U(W) AERL_SET_CLASS_4(W, "%[u0]", "%[u1]", "%[u2]", "%[u3]")
@@ -366,10 +374,12 @@ __device__ __forceinline__ int eval_set(const float *__restrict__ xs, int lane, 
 #define AERL_SETC_1U(W) AERL_SET_CLASS_1(W, "%[u0]")
 
 // The rule of the (last) record in W fires for the lanes in f: count them
-// for its class (COUNT) or give them its class (PRED), and retire them
-// (SCC = some lane still undecided).
-#define AERL_COMMIT_COUNT(S, W) AERL_CAT(AERL_POPC_, AERL_SM(S, F)) AERL_ADD_CLASS_V(W) AERL_CAT(AERL_RETIRE_, S)
-#define AERL_COMMIT_PRED(S, W) AERL_CAT(AERL_SETC_, AERL_SM(S, F))(W) AERL_CAT(AERL_RETIRE_, S)
+// for its class (COUNT) or give them its class (PRED), and retire them (to
+// ALIVE, or on with SCC = some lane still undecided).
+#define AERL_COMMIT_COUNT(S, W, ALIVE) \
+  AERL_CAT(AERL_POPC_, AERL_SM(S, F)) AERL_ADD_CLASS_V(W) AERL_CAT(AERL_RETIRE_, S)(ALIVE)
+#define AERL_COMMIT_PRED(S, W, ALIVE) \
+  AERL_CAT(AERL_SETC_, AERL_SM(S, F))(W) AERL_CAT(AERL_RETIRE_, S)(ALIVE)
 // An always-true rule in W decides every undecided lane.
 #define AERL_ALWAYS_COUNT(S, W) AERL_CAT(AERL_POPC_, AERL_SM(S, U)) AERL_ADD_CLASS(W)
 #define AERL_ALWAYS_PRED(S, W) AERL_CAT(AERL_SETC_, AERL_SM(S, U))(W)
@@ -385,31 +395,32 @@ __device__ __forceinline__ int eval_set(const float *__restrict__ xs, int lane, 
   "s_cbranch_scc1 " SPEC "\n"                           \
   "s_waitcnt lgkmcnt(0)\n"
 
-// Special threshold kinds of the record (y in Y, z in Z, flags in W), row
-// already requested: zero coefficient (y*x > z), <=, or >= (a last record);
-// then on to POST with SCC = (f0 != 0).
-#define AERL_TSPEC(S, MODE, Y, Z, W, TAG, POST)         \
+// Zero-coefficient record (y*x > z; y in Y, z in Z), row already
+// requested; then on to POST with SCC = (f0 != 0).
+#define AERL_MULREC(S, MODE, Y, Z, POST)                \
   "s_waitcnt lgkmcnt(0)\n"                              \
-  "s_bitcmp1_b32 " W ", 0\n"                            \
-  "s_cbranch_scc1 .Lmul_" TAG "_%=\n"                   \
+  AERL_CAT(AERL_MUL1_, S)(Y)                            \
+  AERL_CAT(AERL_CMP_, AERL_SM(S, MODE))("lt", Z)        \
+  "s_branch " POST "\n"
+
+// A rule's last record with a folded threshold (x >= y, or x <= y when
+// flagged; y in Y, flags in W), row already requested; then on to POST with
+// SCC = (f0 != 0).
+#define AERL_LASTREC(S, MODE, Y, W, TAG, POST)          \
+  "s_waitcnt lgkmcnt(0)\n"                              \
   "s_bitcmp1_b32 " W ", 10\n"                           \
   "s_cbranch_scc1 .Lle_" TAG "_%=\n"                    \
   AERL_CAT(AERL_CMP_, AERL_SM(S, MODE))("le", Y)        \
   "s_branch " POST "\n"                                 \
   ".Lle_" TAG "_%=:\n"                                  \
   AERL_CAT(AERL_CMP_, AERL_SM(S, MODE))("ge", Y)        \
-  "s_branch " POST "\n"                                 \
-  ".Lmul_" TAG "_%=:\n"                                 \
-  AERL_CAT(AERL_MUL1_, S)(Y)                            \
-  AERL_CAT(AERL_CMP_, AERL_SM(S, MODE))("lt", Z)        \
   "s_branch " POST "\n"
 
 // Feature-vs-feature record (a in Y, b in Z, g and the >= flag in W), first
 // row already requested: f_i = src_i & (a*x_i > b*x'_i) or (>=); then POST.
 #define AERL_FF_BODY(S, MODE, W, Y, Z, TAG, POST)       \
-  "s_bfe_u32 %[t0], " W ", 0x90000\n"                   \
-  "s_lshl_b32 %[t0], %[t0], " AERL_CAT(AERL_GSHIFT_, S) "\n" \
-  "v_add_u32 %[vt2], %[t0], %[lds]\n"                   \
+  "v_bfe_u32 %[vt2], " W ", 0, 9\n"                     \
+  "v_lshl_add_u32 %[vt2], %[vt2], " AERL_CAT(AERL_GSHIFT_, S) ", %[lds]\n" \
   AERL_CAT(AERL_RD2_, S)                                \
   "s_waitcnt lgkmcnt(0)\n"                              \
   AERL_CAT(AERL_MUL1_, S)(Y)                            \
@@ -422,21 +433,59 @@ __device__ __forceinline__ int eval_set(const float *__restrict__ xs, int lane, 
   AERL_CAT(AERL_FFCMP_, AERL_SM(S, MODE))("ge")         \
   "s_branch " POST "\n"
 
-// Special record entry: feature-vs-feature, always-true (rule starts only,
-// ALW), else a special threshold kind; then POST.
+// Special record entry once a plain last record is ruled out:
+// feature-vs-feature, always-true (rule starts only, ALW), else a zero
+// coefficient; then POST.
 #define AERL_SPEC(S, MODE, Y, Z, W, TAG, POST, ALW)     \
   "s_bitcmp1_b32 " W ", 9\n"                            \
   "s_cbranch_scc1 .Lff_" TAG "_%=\n"                    \
   ALW                                                   \
-  AERL_TSPEC(S, MODE, Y, Z, W, TAG, POST)               \
+  AERL_MULREC(S, MODE, Y, Z, POST)                      \
   ".Lff_" TAG "_%=:\n"                                  \
   AERL_FF_BODY(S, MODE, W, Y, Z, TAG, POST)
+
+// How a walk moves between rules.  SEQ visits every rule in order (the
+// next rule starts where a record's next field points, or right after a
+// rule's last record); FLT visits only the rules whose bit is set in the mask
+// mk (rule k starts at byte offset vst of lane k), lowest first, and needs
+// the closing record's bit set so that every walk ends in a commit.
+#define AERL_START_SEQ "s_mov_b32 %[o], 0\n"
+#define AERL_START_FLT                                  \
+  ".Lnext_%=:\n"                                        \
+  "s_ff1_i32_b64 %[t0], %[mk]\n"                        \
+  "v_readlane_b32 %[o], %[vst], %[t0]\n"                \
+  "s_bitset0_b64 %[mk], %[t0]\n"
+// the rule of the (non-last) record in W is dead
+#define AERL_NXD_SEQ(W) "s_lshr_b32 %[o], " W ", 18\n s_branch .Lload_%=\n"
+#define AERL_NXD_FLT(W) "s_branch .Lnext_%=\n"
+// a special record in A (flags in s67) left no lane alive
+#define AERL_XAD_SEQ                                    \
+  "s_bitcmp1_b32 s67, 11\n"                             \
+  "s_cbranch_scc1 .Lsb_%=\n"                            \
+  "s_lshr_b32 %[o], s67, 18\n"                          \
+  "s_branch .Lload_%=\n"
+#define AERL_XAD_FLT "s_branch .Lnext_%=\n"
+// where the walk goes after a rule ending at A
+#define AERL_NXA_SEQ ".Lsb_%="
+#define AERL_NXA_FLT ".Lnext_%="
+// after a commit at B: CBL is taken with lanes still undecided, then NXB
+// follows the retire (SCC = some lane still undecided)
+#define AERL_CBL_SEQ ".Lcb_%="
+#define AERL_CBL_FLT ".Lnext_%="
+#define AERL_NXB_SEQ                                    \
+  "s_cbranch_scc0 .Ldone_%=\n"                          \
+  ".Lcb_%=:\n"                                          \
+  "s_add_u32 %[o], %[o], 32\n"                          \
+  "s_branch .Lload_%=\n"
+#define AERL_NXB_FLT                                    \
+  "s_cbranch_scc1 .Lnext_%=\n"                          \
+  "s_branch .Ldone_%=\n"
 
 // The whole walk for S samples per lane; KIND is COUNT or PRED.  Labels:
 // s/n = a rule starts / continues at the record, a/b = quad A / B, _le = the
 // <= direction (taken from a rule's first <= record to its end).
-#define AERL_WALK(S, KIND)                                                 \
-  "s_mov_b32 %[o], 0\n"                                                    \
+#define AERL_WALK(S, KIND, WAY)                                            \
+  AERL_CAT(AERL_START_, WAY)                                               \
   /* load the pair (o, o+16) into A, B; a rule starts at A */              \
   ".Lload_%=:\n"                                                           \
   "s_load_dwordx8 s[64:71], %[base], %[o]\n"                               \
@@ -464,12 +513,10 @@ __device__ __forceinline__ int eval_set(const float *__restrict__ xs, int lane, 
   /* the next rule starts past B (A is not a rule's last record) */        \
   ".Lka_%=:\n"                                                             \
   AERL_CAT(AERL_ANY_F_, S)(".Lnb_%=")                                      \
-  "s_lshr_b32 %[o], s67, 18\n"                                             \
-  "s_branch .Lload_%=\n"                                                   \
+  AERL_CAT(AERL_NXD_, WAY)("s67")                                          \
   ".Lkb_%=:\n"                                                             \
   AERL_CAT(AERL_ANY_F_, S)(".Llna_load_%=")                                \
-  "s_lshr_b32 %[o], s71, 18\n"                                             \
-  "s_branch .Lload_%=\n"                                                   \
+  AERL_CAT(AERL_NXD_, WAY)("s71")                                          \
   /* a rule starts at B (the previous one ended at A) */                   \
   ".Lsb_%=:\n"                                                             \
   AERL_FETCH(S, "s68", "s71", "0xa07", ".Lpsb_%=")                         \
@@ -492,12 +539,10 @@ __device__ __forceinline__ int eval_set(const float *__restrict__ xs, int lane, 
   "s_cbranch_scc1 .Lnb_le_%=\n"                                            \
   ".Lka_le_%=:\n"                                                          \
   AERL_CAT(AERL_ANY_F_, S)(".Lnb_le_%=")                                   \
-  "s_lshr_b32 %[o], s67, 18\n"                                             \
-  "s_branch .Lload_%=\n"                                                   \
+  AERL_CAT(AERL_NXD_, WAY)("s67")                                          \
   ".Lkb_le_%=:\n"                                                          \
   AERL_CAT(AERL_ANY_F_, S)(".Llna_load_le_%=")                             \
-  "s_lshr_b32 %[o], s71, 18\n"                                             \
-  "s_branch .Lload_%=\n"                                                   \
+  AERL_CAT(AERL_NXD_, WAY)("s71")                                          \
   /* a rule's first <= record (no other flag): compare, then <= walk */    \
   ".Ldsa_%=:\n"                                                            \
   "s_waitcnt lgkmcnt(0)\n"                                                 \
@@ -515,51 +560,71 @@ __device__ __forceinline__ int eval_set(const float *__restrict__ xs, int lane, 
   "s_waitcnt lgkmcnt(0)\n"                                                 \
   AERL_CAT(AERL_CMP_, AERL_SM(S, F))("ge", "s69")                          \
   "s_branch .Lqb_le_%=\n"                                                  \
-  /* special records (the direction change alone goes to .Ld*) */          \
+  /* special records (the direction change alone goes to .Ld*, a plain */  \
+  /* last record, flags 0x203 clear, to .Lt*) */                           \
   ".Lpsa_%=:\n"                                                            \
   "s_and_b32 %[t0], s67, 0xa03\n"                                          \
   "s_cbranch_scc0 .Ldsa_%=\n"                                              \
+  "s_and_b32 %[t0], s67, 0x203\n"                                          \
+  "s_cbranch_scc0 .Ltsa_%=\n"                                              \
   AERL_SPEC(S, U, "s65", "s66", "s67", "sa", ".Lxa_%=",                    \
             "s_bitcmp1_b32 s67, 1\n s_cbranch_scc1 .Lalwa_%=\n")           \
+  ".Ltsa_%=:\n"                                                            \
+  AERL_LASTREC(S, U, "s65", "s67", "tsa", ".Lza_%=")                       \
   ".Lpna_%=:\n"                                                            \
   "s_and_b32 %[t0], s67, 0xa03\n"                                          \
   "s_cbranch_scc0 .Ldna_%=\n"                                              \
+  "s_and_b32 %[t0], s67, 0x203\n"                                          \
+  "s_cbranch_scc0 .Ltna_%=\n"                                              \
   AERL_SPEC(S, F, "s65", "s66", "s67", "na", ".Lxa_%=", "")                \
+  ".Ltna_%=:\n"                                                            \
+  AERL_LASTREC(S, F, "s65", "s67", "tna", ".Lza_%=")                       \
   ".Lpsb_%=:\n"                                                            \
   "s_and_b32 %[t0], s71, 0xa03\n"                                          \
   "s_cbranch_scc0 .Ldsb_%=\n"                                              \
+  "s_and_b32 %[t0], s71, 0x203\n"                                          \
+  "s_cbranch_scc0 .Ltsb_%=\n"                                              \
   AERL_SPEC(S, U, "s69", "s70", "s71", "sb", ".Lxb_%=",                    \
             "s_bitcmp1_b32 s71, 1\n s_cbranch_scc1 .Lalwb_%=\n")           \
+  ".Ltsb_%=:\n"                                                            \
+  AERL_LASTREC(S, U, "s69", "s71", "tsb", ".Lzb_%=")                       \
   ".Lpnb_%=:\n"                                                            \
   "s_and_b32 %[t0], s71, 0xa03\n"                                          \
   "s_cbranch_scc0 .Ldnb_%=\n"                                              \
+  "s_and_b32 %[t0], s71, 0x203\n"                                          \
+  "s_cbranch_scc0 .Ltnb_%=\n"                                              \
   AERL_SPEC(S, F, "s69", "s70", "s71", "nb", ".Lxb_%=", "")                \
+  ".Ltnb_%=:\n"                                                            \
+  AERL_LASTREC(S, F, "s69", "s71", "tnb", ".Lzb_%=")                       \
   /* after a special record in A (what follows it in its rule is special */ \
   /* too, or starts a new rule, so the >= labels serve both directions) */ \
   ".Lxa_%=:\n"                                                             \
   AERL_CAT(AERL_ANY_F_, S)(".Lya_%=")                                      \
-  "s_bitcmp1_b32 s67, 11\n"                                                \
-  "s_cbranch_scc1 .Lsb_%=\n" /* dead, and the next rule starts at B */     \
-  "s_lshr_b32 %[o], s67, 18\n"                                             \
-  "s_branch .Lload_%=\n"                                                   \
+  AERL_CAT(AERL_XAD_, WAY)                                                 \
+  /* after a rule's last record in A */                                    \
+  ".Lza_%=:\n"                                                             \
+  AERL_CAT(AERL_ANY_F_, S)(".Lwa_%=")                                      \
+  "s_branch " AERL_CAT(AERL_NXA_, WAY) "\n"                                \
   ".Lya_%=:\n"                                                             \
   "s_bitcmp1_b32 s67, 11\n"                                                \
   "s_cbranch_scc0 .Lnb_%=\n"                                               \
-  AERL_CAT(AERL_COMMIT_, KIND)(S, "s67")                                   \
-  "s_cbranch_scc1 .Lsb_%=\n"                                               \
+  ".Lwa_%=:\n"                                                             \
+  AERL_CAT(AERL_COMMIT_, KIND)(S, "s67", AERL_CAT(AERL_NXA_, WAY))         \
+  "s_cbranch_scc1 " AERL_CAT(AERL_NXA_, WAY) "\n"                          \
   "s_branch .Ldone_%=\n"                                                   \
-  /* after a special record in B */                                        \
+  /* after a special record in B, or a rule's last record in B */          \
   ".Lxb_%=:\n"                                                             \
   AERL_CAT(AERL_ANY_F_, S)(".Lyb_%=")                                      \
-  "s_lshr_b32 %[o], s71, 18\n"                                             \
-  "s_branch .Lload_%=\n"                                                   \
+  AERL_CAT(AERL_NXD_, WAY)("s71")                                          \
+  ".Lzb_%=:\n"                                                             \
+  AERL_CAT(AERL_ANY_F_, S)(".Lwb_%=")                                      \
+  AERL_CAT(AERL_NXD_, WAY)("s71")                                          \
   ".Lyb_%=:\n"                                                             \
   "s_bitcmp1_b32 s71, 11\n"                                                \
   "s_cbranch_scc0 .Llna_load_%=\n"                                         \
-  AERL_CAT(AERL_COMMIT_, KIND)(S, "s71")                                   \
-  "s_cbranch_scc0 .Ldone_%=\n"                                             \
-  "s_add_u32 %[o], %[o], 32\n"                                             \
-  "s_branch .Lload_%=\n"                                                   \
+  ".Lwb_%=:\n"                                                             \
+  AERL_CAT(AERL_COMMIT_, KIND)(S, "s71", AERL_CAT(AERL_CBL_, WAY))         \
+  AERL_CAT(AERL_NXB_, WAY)                                                 \
   /* an always-true rule decides every undecided lane */                   \
   ".Lalwa_%=:\n"                                                           \
   "s_waitcnt lgkmcnt(0)\n"                                                 \
@@ -574,64 +639,59 @@ __device__ __forceinline__ int eval_set(const float *__restrict__ xs, int lane, 
   "s56", "s57", "s58", "s59", "s60", "s61", "s62", "s63", "s64", "s65", "s66", "s67", "s68", "s69", "s70", "s71", "v32", "v33", "v34", \
       "v35", "v36", "v37", "v38", "v39", "vcc", "scc", "memory"
 
-template <int S>
+// Counting walk over every rule of the set (SEQ) or over the rules whose bit
+// is set in mk (FLT; vst holds the rules' byte offsets, one per lane).
+template <int S, bool FLT>
 __device__ __forceinline__ int eval_set_count(uint32_t lds_lane, int lane, int4 set,
                                               const uint4 *__restrict__ stream,
-                                              const uint64_t (&vm)[S]);
+                                              const uint64_t (&vm)[S], uint64_t mk = 0,
+                                              uint32_t vst = 0);
 
-template <>
-__device__ __forceinline__ int eval_set_count<4>(uint32_t lds_lane, int lane, int4 set,
-                                                 const uint4 *__restrict__ stream,
-                                                 const uint64_t (&vm)[4]) {
-  const uint4 *base = stream + set.x;
-  uint64_t u0 = vm[0], u1 = vm[1], u2 = vm[2], u3 = vm[3];
-  uint64_t m;
-  uint32_t o, t0, t1, vt, vt2;
-  int acc = 0;
-  asm volatile(AERL_WALK(4, COUNT)
-               : [acc] "+v"(acc), [u0] "+s"(u0), [u1] "+s"(u1), [u2] "+s"(u2), [u3] "+s"(u3),
-                 [m] "=&s"(m),
-                 [o] "=&s"(o), [t0] "=&s"(t0), [t1] "=&s"(t1), [vt] "=&v"(vt), [vt2] "=&v"(vt2)
-               : [base] "s"(base), [lds] "v"(lds_lane), [lane] "v"(lane)
-               : AERL_WALK_CLOBBERS);
-  return acc;
-}
+#define AERL_COUNT_OUTS_4 [acc] "+v"(acc), [u0] "+s"(u0), [u1] "+s"(u1), [u2] "+s"(u2), [u3] "+s"(u3)
+#define AERL_COUNT_OUTS_2 [acc] "+v"(acc), [u0] "+s"(u0), [u1] "+s"(u1)
+#define AERL_COUNT_OUTS_1 [acc] "+v"(acc), [u0] "+s"(u0)
+#define AERL_TEMPS [m] "=&s"(m), [o] "=&s"(o), [t0] "=&s"(t0), [vt] "=&v"(vt), [vt2] "=&v"(vt2)
+#define AERL_U_4 uint64_t u0 = vm[0], u1 = vm[1], u2 = vm[2], u3 = vm[3];
+#define AERL_U_2 uint64_t u0 = vm[0], u1 = vm[1];
+#define AERL_U_1 uint64_t u0 = vm[0];
 
-template <>
-__device__ __forceinline__ int eval_set_count<2>(uint32_t lds_lane, int lane, int4 set,
-                                                 const uint4 *__restrict__ stream,
-                                                 const uint64_t (&vm)[2]) {
-  const uint4 *base = stream + set.x;
-  uint64_t u0 = vm[0], u1 = vm[1];
-  uint64_t m;
-  uint32_t o, t0, t1, vt, vt2;
-  int acc = 0;
-  asm volatile(AERL_WALK(2, COUNT)
-               : [acc] "+v"(acc), [u0] "+s"(u0), [u1] "+s"(u1), [m] "=&s"(m), [o] "=&s"(o), [t0] "=&s"(t0), [t1] "=&s"(t1), [vt] "=&v"(vt),
-                 [vt2] "=&v"(vt2)
-               : [base] "s"(base), [lds] "v"(lds_lane), [lane] "v"(lane)
-               : AERL_WALK_CLOBBERS);
-  return acc;
-}
+#define AERL_COUNT_SPECIALIZE(S)                                                              \
+  template <>                                                                                 \
+  __device__ __forceinline__ int eval_set_count<S, false>(                                    \
+      uint32_t lds_lane, int lane, int4 set, const uint4 *__restrict__ stream,                \
+      const uint64_t(&vm)[S], uint64_t, uint32_t) {                                           \
+    const uint4 *base = stream + set.x;                                                       \
+    AERL_U_##S                                                                                \
+    uint64_t m;                                                                               \
+    uint32_t o, t0, vt, vt2;                                                                  \
+    int acc = 0;                                                                              \
+    asm volatile(AERL_WALK(S, COUNT, SEQ)                                                     \
+                 : AERL_COUNT_OUTS_##S, AERL_TEMPS                                            \
+                 : [base] "s"(base), [lds] "v"(lds_lane), [lane] "v"(lane)                    \
+                 : AERL_WALK_CLOBBERS);                                                       \
+    return acc;                                                                               \
+  }                                                                                           \
+  template <>                                                                                 \
+  __device__ __forceinline__ int eval_set_count<S, true>(                                     \
+      uint32_t lds_lane, int lane, int4 set, const uint4 *__restrict__ stream,                \
+      const uint64_t(&vm)[S], uint64_t mk, uint32_t vst) {                                    \
+    const uint4 *base = stream + set.x;                                                       \
+    AERL_U_##S                                                                                \
+    uint64_t m;                                                                               \
+    uint32_t o, t0, vt, vt2;                                                                  \
+    int acc = 0;                                                                              \
+    asm volatile(AERL_WALK(S, COUNT, FLT)                                                     \
+                 : AERL_COUNT_OUTS_##S, AERL_TEMPS, [mk] "+s"(mk)                             \
+                 : [base] "s"(base), [lds] "v"(lds_lane), [lane] "v"(lane), [vst] "v"(vst)    \
+                 : AERL_WALK_CLOBBERS);                                                       \
+    return acc;                                                                               \
+  }
 
-template <>
-__device__ __forceinline__ int eval_set_count<1>(uint32_t lds_lane, int lane, int4 set,
-                                                 const uint4 *__restrict__ stream,
-                                                 const uint64_t (&vm)[1]) {
-  const uint4 *base = stream + set.x;
-  uint64_t u0 = vm[0];
-  uint64_t m;
-  uint32_t o, t0, t1, vt, vt2;
-  int acc = 0;
-  asm volatile(AERL_WALK(1, COUNT)
-               : [acc] "+v"(acc), [u0] "+s"(u0), [m] "=&s"(m), [o] "=&s"(o),
-                 [t0] "=&s"(t0), [t1] "=&s"(t1), [vt] "=&v"(vt), [vt2] "=&v"(vt2)
-               : [base] "s"(base), [lds] "v"(lds_lane), [lane] "v"(lane)
-               : AERL_WALK_CLOBBERS);
-  return acc;
-}
+AERL_COUNT_SPECIALIZE(4)
+AERL_COUNT_SPECIALIZE(2)
+AERL_COUNT_SPECIALIZE(1)
 
-// Prediction form of the same walk: pred[s] receives the class of each
+// Prediction form of the sequential walk: pred[s] receives the class of each
 // lane's samples in vm (others keep their value).
 template <int S>
 __device__ __forceinline__ void eval_set_pred(uint32_t lds_lane, int lane, int4 set,
@@ -643,14 +703,13 @@ __device__ __forceinline__ void eval_set_pred<4>(uint32_t lds_lane, int lane, in
                                                  const uint4 *__restrict__ stream,
                                                  const uint64_t (&vm)[4], int (&pred)[4]) {
   const uint4 *base = stream + set.x;
-  uint64_t u0 = vm[0], u1 = vm[1], u2 = vm[2], u3 = vm[3];
+  AERL_U_4
   uint64_t m;
-  uint32_t o, t0, t1, vt, vt2;
+  uint32_t o, t0, vt, vt2;
   int p0 = pred[0], p1 = pred[1], p2 = pred[2], p3 = pred[3];
-  asm volatile(AERL_WALK(4, PRED)
+  asm volatile(AERL_WALK(4, PRED, SEQ)
                : [p0] "+v"(p0), [p1] "+v"(p1), [p2] "+v"(p2), [p3] "+v"(p3), [u0] "+s"(u0),
-                 [u1] "+s"(u1), [u2] "+s"(u2), [u3] "+s"(u3), [m] "=&s"(m), [o] "=&s"(o), [t0] "=&s"(t0),
-                 [t1] "=&s"(t1), [vt] "=&v"(vt), [vt2] "=&v"(vt2)
+                 [u1] "+s"(u1), [u2] "+s"(u2), [u3] "+s"(u3), AERL_TEMPS
                : [base] "s"(base), [lds] "v"(lds_lane)
                : AERL_WALK_CLOBBERS);
   (void)lane;
@@ -662,13 +721,12 @@ __device__ __forceinline__ void eval_set_pred<2>(uint32_t lds_lane, int lane, in
                                                  const uint4 *__restrict__ stream,
                                                  const uint64_t (&vm)[2], int (&pred)[2]) {
   const uint4 *base = stream + set.x;
-  uint64_t u0 = vm[0], u1 = vm[1];
+  AERL_U_2
   uint64_t m;
-  uint32_t o, t0, t1, vt, vt2;
+  uint32_t o, t0, vt, vt2;
   int p0 = pred[0], p1 = pred[1];
-  asm volatile(AERL_WALK(2, PRED)
-               : [p0] "+v"(p0), [p1] "+v"(p1), [u0] "+s"(u0), [u1] "+s"(u1), [m] "=&s"(m), [o] "=&s"(o), [t0] "=&s"(t0), [t1] "=&s"(t1),
-                 [vt] "=&v"(vt), [vt2] "=&v"(vt2)
+  asm volatile(AERL_WALK(2, PRED, SEQ)
+               : [p0] "+v"(p0), [p1] "+v"(p1), [u0] "+s"(u0), [u1] "+s"(u1), AERL_TEMPS
                : [base] "s"(base), [lds] "v"(lds_lane)
                : AERL_WALK_CLOBBERS);
   (void)lane;
@@ -680,13 +738,12 @@ __device__ __forceinline__ void eval_set_pred<1>(uint32_t lds_lane, int lane, in
                                                  const uint4 *__restrict__ stream,
                                                  const uint64_t (&vm)[1], int (&pred)[1]) {
   const uint4 *base = stream + set.x;
-  uint64_t u0 = vm[0];
+  AERL_U_1
   uint64_t m;
-  uint32_t o, t0, t1, vt, vt2;
+  uint32_t o, t0, vt, vt2;
   int p0 = pred[0];
-  asm volatile(AERL_WALK(1, PRED)
-               : [p0] "+v"(p0), [u0] "+s"(u0), [m] "=&s"(m), [o] "=&s"(o),
-                 [t0] "=&s"(t0), [t1] "=&s"(t1), [vt] "=&v"(vt), [vt2] "=&v"(vt2)
+  asm volatile(AERL_WALK(1, PRED, SEQ)
+               : [p0] "+v"(p0), [u0] "+s"(u0), AERL_TEMPS
                : [base] "s"(base), [lds] "v"(lds_lane)
                : AERL_WALK_CLOBBERS);
   (void)lane;

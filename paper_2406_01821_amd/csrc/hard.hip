@@ -31,6 +31,7 @@ struct HardArgs {
   const int32_t *tile_info;
   const int4 *sets;
   const uint4 *conds;
+  const uint2 *heads;
   int32_t set_begin, set_count;
   int32_t *correct;
   int32_t *confusion;
@@ -52,6 +53,7 @@ __global__ __launch_bounds__(kHardBlock) AERL_HARD_SGPR_CAP void k_hard(const Ha
   t.tile_info = a.tile_info;
   t.sets = a.sets + a.set_begin;
   t.conds = a.conds;
+  t.heads = a.heads;
   t.correct = a.correct;
   t.confusion = a.confusion;
   t.label = 0;
@@ -104,6 +106,7 @@ hipError_t launch_hard_eval(const HardLaunch &h, hipStream_t st) {
   a.tile_info = ds.tile_info;
   a.sets = pop.sets;
   a.conds = pop.hconds;
+  a.heads = pop.heads;
   a.set_begin = h.set_begin;
   a.set_count = h.set_count;
   a.correct = h.correct;

@@ -25,16 +25,22 @@ struct HardTask {
   const int32_t *tile_info;
   const int4 *sets;   // the population's set records
   const uint4 *conds; // the population's record stream
+  const uint2 *heads; // the population's head table (null: walk every rule)
   int32_t *correct;   // [n_sets]
   int32_t *confusion; // [n_sets][nc][nc] or null
   int32_t q0, Q, tile_lo, tile_hi, label;
 };
 
-// Stages one wave tile (64*S samples x nf features) at a time into LDS and
-// lets the waves pull rule sets, two at a time, from an LDS counter;
-// per-class prediction counts live in LDS (one writer per rule set and tile)
-// and reach the outputs once, through integer atomics.  smem holds nf*64*S floats followed
-// by Q*nc 16-bit counters (a block covers at most 255 layout tiles, so a
+// Stages one wave tile (64*S samples x nf features) at a time into LDS,
+// with the largest and smallest value of each feature over the tile's
+// samples, and lets the waves pull rule sets, two at a time, from an LDS
+// counter.  A rule whose first record is a folded threshold that no sample
+// of the tile passes (x >= t with t above the tile's largest x, or x <= t
+// with t below its smallest) cannot fire for any of them: the walk skips it
+// without reading its records (exact).  Per-class prediction counts live in
+// LDS (one writer per rule set and tile) and reach the outputs once, through
+// integer atomics.  smem holds nf*64*S floats, then nf (max, min) pairs, then
+// Q*nc 16-bit counters (a block covers at most 255 layout tiles, so a
 // counter stays below 2^16).  Ends with a barrier, so the caller may reuse
 // smem.
 template <int S>
@@ -42,7 +48,9 @@ __device__ __forceinline__ void hard_block(const HardTask &t, float *smem, int32
   constexpr int TS = 64 * S;           // samples per wave tile
   constexpr int WPT = AERL_TILE / TS;  // wave tiles per layout tile
   float *xs = smem;                                                    // [nf][TS]
-  uint16_t *cnt = reinterpret_cast<uint16_t *>(smem + (size_t)t.nf * TS);  // [Q][nc]
+  float *ext = smem + (size_t)t.nf * TS;                               // [nf][max, min]
+  uint16_t *cnt = reinterpret_cast<uint16_t *>(ext + 2 * t.nf);        // [Q][nc]
+  uint32_t *cnt32 = reinterpret_cast<uint32_t *>(cnt);
   const int lane = threadIdx.x & 63;
   for (int i = threadIdx.x; i < t.Q * t.nc; i += blockDim.x) cnt[i] = 0;
   const int n4 = t.nf * (TS / 4);
@@ -69,16 +77,75 @@ __device__ __forceinline__ void hard_block(const HardTask &t, float *smem, int32
 #pragma unroll
     for (int s = 0; s < S; ++s) vm[s] = ballot(lane * S + s < valid);
     if (valid == 0) continue;  // an empty wave tile (S < 4 at a region's end)
+    // largest and smallest value of each feature over the valid samples:
+    // 16 threads per feature
+    for (int f0 = 0; f0 < t.nf; f0 += 64) {
+      const int f = f0 + (threadIdx.x >> 4), part = threadIdx.x & 15;
+      float hi = -INFINITY, lo = INFINITY;
+      if (f < t.nf) {
+        for (int i = part; i < valid; i += 16) {
+          const float v = xs[f * TS + i];
+          hi = fmaxf(hi, v);
+          lo = fminf(lo, v);
+        }
+      }
+      for (int d = 1; d < 16; d <<= 1) {
+        hi = fmaxf(hi, __shfl_xor(hi, d));
+        lo = fminf(lo, __shfl_xor(lo, d));
+      }
+      if (f < t.nf && part == 0) {
+        ext[2 * f] = hi;
+        ext[2 * f + 1] = lo;
+      }
+    }
+    __syncthreads();
     for (;;) {
       int q0 = 0;
       if (lane == 0) q0 = atomicAdd(next_q, 2);  // two rule sets per grab
       q0 = __builtin_amdgcn_readfirstlane(q0);
       if (q0 >= t.Q) break;
       const int q1 = min(q0 + 2, t.Q);
-      for (int q = q0; q < q1; ++q) {
-        const int4 set = ldc(t.sets, t.q0 + q);
-        const int acc = eval_set_count<S>(lds_lane, lane, set, t.conds, vm);
-        if (lane < t.nc) cnt[q * t.nc + lane] += (uint16_t)acc;
+      // both set records in one scalar load (at the chunk's odd end the
+      // second is the record after it, inside the population image and
+      // never used), and both sets' head entries requested before the
+      // first walk
+      int4 set[2];
+      ldc_pair(t.sets + t.q0 + q0, set);
+      uint2 head[2];
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const int nh = set[k].y >> 16;
+        head[k] = make_uint2(0u, 0u);
+        if (q0 + k < q1 && t.heads && nh >= 1 && nh <= kMaxHeads && lane < nh)
+          head[k] = t.heads[set[k].x + lane];
+      }
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const int q = q0 + k;
+        if (q >= q1) break;
+        const int4 s4 = set[k];
+        const int nh = s4.y >> 16;
+        int acc;
+        if (t.heads && nh >= 1 && nh <= kMaxHeads) {
+          // branch-free: the extreme is read for every lane
+          const uint32_t hx = head[k].x;
+          const uint32_t le = (hx >> 29) & 1u;
+          const float e = ext[2 * ((hx >> kHeadFShift) & 511u) + le];
+          const float th = __uint_as_float(head[k].y);
+          const uint32_t fails = le ? (uint32_t)(e > th) : (uint32_t)(e < th);
+          const uint32_t keep = (hx >> 31) & ~(fails & (hx >> 30));
+          // the closing record (last entry) is always visited
+          const uint64_t mk = ballot(keep & 1u) | (1ull << (nh - 1));
+          acc = eval_set_count<S, true>(lds_lane, lane, s4, t.conds, vm, mk, hx & kHeadOffMask);
+        } else {
+          acc = eval_set_count<S, false>(lds_lane, lane, s4, t.conds, vm);
+        }
+        // two 16-bit counters per word: a no-return atomic add, no carry
+        // between the halves (each counter stays below 2^16)
+        if (lane < t.nc) {
+          const int i = q * t.nc + lane;
+          atomicAdd(cnt32 + (i >> 1), (uint32_t)acc << ((i & 1) * 16));
+        }
       }
     }
   }

@@ -37,8 +37,8 @@ aerl_status fail(aerl_ctx *ctx, aerl_status code, const char *fmt, ...);
   } while (0)
 
 // ------------------------------------------------------------ packed records
-// Rule set: {first hard-stream record, record count, default class, nominal
-//            condition count}.
+// Rule set: {first hard-stream record, record count | head count << 16,
+//            default class, nominal condition count}.
 // Soft rule set: {first rule, rule count, first condition, condition count}.
 // Rule (soft path): {first condition in the caller's order, condition count,
 //                    class, 0}.
@@ -77,8 +77,22 @@ constexpr uint32_t kRecNextShift = 18;
 // Records of one rule set, closing record included: next-rule byte offsets
 // fit 14 bits.
 constexpr int32_t kMaxSetRecords = 1023;
+// Head table (8 bytes per entry, parallel to the hard stream: the entries of
+// a set start at its first record's index): one entry per rule in order, then
+// one for the closing record.  x: the rule's first-record byte offset (from
+// the set's first record) | f << 14 of that record | kHeadLE | kHeadTest |
+// kHeadValid; y: its folded threshold.  kHeadTest marks a first record that
+// is a folded threshold (x[f] >= y, or x[f] <= y with kHeadLE): when no
+// sample of a tile passes it, no sample of the tile can fire the rule.
+constexpr uint32_t kHeadOffMask = 0x3fffu;
+constexpr uint32_t kHeadFShift = 14;
+constexpr uint32_t kHeadLE = 1u << 29;
+constexpr uint32_t kHeadTest = 1u << 30;
+constexpr uint32_t kHeadValid = 1u << 31;
+// Sets with at most this many head entries take the filtered walk.
+constexpr int32_t kMaxHeads = 64;
 struct PackedLayout {
-  size_t sets_off, ssets_off, rules_off, hconds_off, sconds_off, total;
+  size_t sets_off, ssets_off, rules_off, hconds_off, sconds_off, heads_off, total;
 };
 
 struct DatasetRec {
@@ -106,6 +120,7 @@ struct PopRec {
   const int4 *rules = nullptr;
   const uint4 *hconds = nullptr;
   const uint32_t *sconds = nullptr;
+  const uint2 *heads = nullptr;
   void *staging = nullptr;     // pinned host copy of the packed image
   hipEvent_t staged = nullptr; // completion of the staging copy
 };
@@ -191,7 +206,7 @@ constexpr size_t kDynLdsMax = kLdsPerCu - kStaticLds;
 // kMaxTilesPerBlock layout tiles.
 constexpr int kMaxTilesPerBlock = 255;
 inline size_t hard_block_lds(int nf, int S, int Q, int nc) {
-  return (size_t)nf * 64 * S * 4 + (((size_t)Q * nc * 2 + 3) & ~size_t(3));
+  return (size_t)nf * 64 * S * 4 + (size_t)nf * 8 + (((size_t)Q * nc * 2 + 3) & ~size_t(3));
 }
 
 // Soft path (soft.hip)

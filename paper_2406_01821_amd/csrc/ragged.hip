@@ -45,6 +45,7 @@ __global__ __launch_bounds__(kBatchBlock) AERL_HARD_SGPR_CAP void k_hard_batch(
     t.tile_info = it.tile_info;
     t.sets = it.sets;
     t.conds = it.conds;
+    t.heads = it.heads;
     t.correct = it.correct;
     t.confusion = it.confusion;
     t.q0 = tk.q0;

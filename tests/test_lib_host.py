@@ -84,16 +84,25 @@ def _align(v):
     return (v + 255) & ~255
 
 
-def decode_packed(img, n_sets, n_rules, n_conds):
-    """Splits the packed image into set records and the hard record stream."""
+def decode_packed(img, n_sets, n_rules, n_conds, heads=False):
+    """Splits the packed image into set records (record count in column 1),
+    the hard record stream and, with heads=True, the head table and each
+    set's head count."""
     sets_off = 0
     ssets_off = _align(sets_off + 16 * max(n_sets, 1))
     rules_off = _align(ssets_off + 16 * max(n_sets, 1))
     hc_off = _align(rules_off + 16 * max(n_rules, 1))
-    sets = img[sets_off:sets_off + 16 * n_sets].view(np.int32).reshape(-1, 4)
+    raw = img[sets_off:sets_off + 16 * n_sets].view(np.int32).reshape(-1, 4)
+    sets = raw.copy()
+    sets[:, 1] &= 0xffff
     n_rec = n_conds + n_rules + n_sets + 1
     hc = img[hc_off:hc_off + 16 * n_rec].view(np.uint32).reshape(-1, 4)
-    return sets, hc
+    if not heads:
+        return sets, hc
+    sc_off = _align(hc_off + 16 * n_rec)
+    hd_off = _align(sc_off + 4 * max(n_conds, 1))
+    hd = img[hd_off:hd_off + 8 * n_rec].view(np.uint32).reshape(-1, 2)
+    return sets, hc, hd, raw[:, 1] >> 16
 
 
 FF, GE_LE, LAST, MUL, ALWAYS = 1 << 9, 1 << 10, 1 << 11, 1 << 0, 1 << 1
@@ -380,3 +389,94 @@ def test_hard_kernels_fit_two_blocks_per_cu(tmp_path):
     hard = {k: v for k, v in counts.items() if "k_hardILi" in k or "k_hard_batch" in k}
     assert len(hard) == 4, counts  # k_hard<4>, <2>, <1>, k_hard_batch
     assert all(v <= 80 for v in hard.values()), hard
+
+
+HEAD_LE, HEAD_TEST, HEAD_VALID = 1 << 29, 1 << 30, 1 << 31
+
+
+def eval_packed_filtered(x, sets, hc, hd, nh, s):
+    """Model of the filtered walk over the rows of x taken as one tile: the
+    rules whose head entry's test fails for every row (x[f] >= t with t above
+    the rows' largest x[f], or x[f] <= t with t below the smallest) are
+    skipped; the others are walked from their start offset, in order; the
+    closing record is always visited.  Returns the predictions and the
+    number of rules skipped."""
+    first, count, default, _ = (int(v) for v in sets[s])
+    n_heads = int(nh[s])
+    assert 1 <= n_heads <= count
+    hi, lo = x.max(axis=0), x.min(axis=0)
+    pred = np.full(x.shape[0], -1, np.int32)
+    und = np.ones(x.shape[0], bool)
+    skipped = 0
+    for k in range(n_heads):
+        hx, hy = (int(v) for v in hd[first + k])
+        assert hx & HEAD_VALID
+        if hx & HEAD_TEST and k < n_heads - 1:
+            t = np.uint32(hy).view(np.float32)
+            f = (hx >> 14) & 511
+            if (lo[f] > t) if hx & HEAD_LE else (hi[f] < t):
+                skipped += 1
+                continue
+        o = hx & 0x3fff
+        fire = und.copy()
+        while True:
+            r = tuple(int(v) for v in hc[first + o // 16])
+            fire &= record_mask(x, r)
+            if r[3] & LAST:
+                break
+            o += 16
+        if fire.any():
+            pred[fire] = (r[3] >> 12) & 63
+            und &= ~fire
+        if not und.any():
+            break
+    assert not und.any()
+    return pred, skipped
+
+
+def test_head_table_describes_every_rule(aerl):
+    """One head entry per rule and one for the closing record: the rule's
+    first-record offset, and for a rule whose first record is a folded
+    threshold, that record's feature, direction and threshold."""
+    pop = synth.special_values_population(31, 6, 3, 80)
+    img = aerl.pack_host(pop, 6, 3)
+    sets, hc, hd, nh = decode_packed(img, pop.n_sets, pop.n_rules, pop.n_conds, heads=True)
+    for s in range(pop.n_sets):
+        first, count, _, _ = (int(v) for v in sets[s])
+        n_rules = int(pop.set_rule_off[s + 1] - pop.set_rule_off[s])
+        assert nh[s] == n_rules + 1
+        starts = [0]
+        for i in range(count - 1):
+            if hc[first + i][3] & LAST:
+                starts.append(16 * (i + 1))
+        assert len(starts) == n_rules + 1 and starts[-1] == 16 * (count - 1)
+        for k, o in enumerate(starts):
+            hx, hy = (int(v) for v in hd[first + k])
+            assert hx & HEAD_VALID and hx & 0x3fff == o
+            r = [int(v) for v in hc[first + o // 16]]
+            threshold = not r[3] & (FF | MUL | ALWAYS)
+            assert bool(hx & HEAD_TEST) == threshold, (s, k)
+            if threshold:
+                assert (hx >> 14) & 511 == r[0] // 1024 and hy == r[1]
+                assert bool(hx & HEAD_LE) == bool(r[3] & GE_LE)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_head_filter_skips_only_rules_that_cannot_fire(aerl, seed):
+    """The filtered walk on tiles of 1-256 rows gives the oracle's
+    predictions, and the heavy-tailed workload's thresholds let it skip
+    rules."""
+    rng = np.random.default_rng(40 + seed)
+    w = synth.tiny(50 + seed, n=2048, nf=12, n_classes=3, n_sets=60, rules=(1, 16), conds=(1, 5))
+    pops = [w.pop, synth.special_values_population(60 + seed, 12, 3, 40)]
+    skipped = 0
+    for pop in pops:
+        img = aerl.pack_host(pop, 12, 3)
+        sets, hc, hd, nh = decode_packed(img, pop.n_sets, pop.n_rules, pop.n_conds, heads=True)
+        for n in (1, 7, 64, 256):
+            rows = w.data.x[rng.choice(w.data.n, n, replace=False)]
+            for s in range(pop.n_sets):
+                got, k = eval_packed_filtered(rows, sets, hc, hd, nh, s)
+                np.testing.assert_array_equal(got, oracle.predict(rows, pop, s), err_msg=f"set {s}")
+                skipped += k
+    assert skipped > 0
