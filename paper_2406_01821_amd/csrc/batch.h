@@ -11,7 +11,7 @@ struct BatchItem {
   const int32_t *tile_info;
   const int4 *sets;
   const uint4 *conds;
-  const uint2 *heads;
+  const uint4 *heads;
   int32_t *correct;
   int32_t *confusion;
   int32_t nf, nc, S, pad;
@@ -58,7 +58,7 @@ struct BatchSource {
   const int4 *host_sets;  // host copy of the set records (cost estimates)
   const int4 *sets;       // device set records
   const uint4 *conds;     // device record stream
-  const uint2 *heads;     // device head table
+  const uint4 *heads;     // device head table
   int32_t *correct;       // device [n_sets]
   int32_t *confusion;     // device [n_sets][nc][nc] or null
 };

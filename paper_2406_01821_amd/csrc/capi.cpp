@@ -301,7 +301,7 @@ aerl_status aerl_pack_population(aerl_ctx *ctx, const aerl_population *pop, int3
   rec.rules = reinterpret_cast<const int4 *>(b + L.rules_off);
   rec.hconds = reinterpret_cast<const uint4 *>(b + L.hconds_off);
   rec.sconds = reinterpret_cast<const uint32_t *>(b + L.sconds_off);
-  rec.heads = reinterpret_cast<const uint2 *>(b + L.heads_off);
+  rec.heads = reinterpret_cast<const uint4 *>(b + L.heads_off);
   const int32_t id = ctx->next_id++;
   ctx->pops[id] = rec;
   *pop_id = id;

@@ -31,7 +31,7 @@ struct HardArgs {
   const int32_t *tile_info;
   const int4 *sets;
   const uint4 *conds;
-  const uint2 *heads;
+  const uint4 *heads;
   int32_t set_begin, set_count;
   int32_t *correct;
   int32_t *confusion;

@@ -25,30 +25,30 @@ struct HardTask {
   const int32_t *tile_info;
   const int4 *sets;   // the population's set records
   const uint4 *conds; // the population's record stream
-  const uint2 *heads; // the population's head table (null: walk every rule)
+  const uint4 *heads; // the population's head table (null: walk every rule)
   int32_t *correct;   // [n_sets]
   int32_t *confusion; // [n_sets][nc][nc] or null
   int32_t q0, Q, tile_lo, tile_hi, label;
 };
 
 // Stages one wave tile (64*S samples x nf features) at a time into LDS,
-// with the largest and smallest value of each feature over the tile's
-// samples, and lets the waves pull rule sets, two at a time, from an LDS
-// counter.  A rule whose first record is a folded threshold that no sample
-// of the tile passes (x >= t with t above the tile's largest x, or x <= t
-// with t below its smallest) cannot fire for any of them: the walk skips it
-// without reading its records (exact).  Per-class prediction counts live in
-// LDS (one writer per rule set and tile) and reach the outputs once, through
-// integer atomics.  smem holds nf*64*S floats, then nf (max, min) pairs, then
-// Q*nc 16-bit counters (a block covers at most 255 layout tiles, so a
-// counter stays below 2^16).  Ends with a barrier, so the caller may reuse
-// smem.
+// with the largest value and the negated smallest value of each feature
+// over the tile's samples, and lets the waves pull rule sets, two at a time,
+// from an LDS counter.  A rule with one of its first two records a folded
+// threshold that no sample of the tile passes (x >= t with t above the
+// tile's largest x, or x <= t with t below its smallest) cannot fire for any
+// of them: the walk skips it without reading its records (exact).
+// Per-class prediction counts live in LDS (one writer per rule set and
+// tile) and reach the outputs once, through integer atomics.  smem holds
+// nf*64*S floats, then nf (max, -min) pairs, then Q*nc 16-bit counters (a
+// block covers at most 255 layout tiles, so a counter stays below 2^16).
+// Ends with a barrier, so the caller may reuse smem.
 template <int S>
 __device__ __forceinline__ void hard_block(const HardTask &t, float *smem, int32_t *next_q) {
   constexpr int TS = 64 * S;           // samples per wave tile
   constexpr int WPT = AERL_TILE / TS;  // wave tiles per layout tile
   float *xs = smem;                                                    // [nf][TS]
-  float *ext = smem + (size_t)t.nf * TS;                               // [nf][max, min]
+  float *ext = smem + (size_t)t.nf * TS;                               // [nf][max, -min]
   uint16_t *cnt = reinterpret_cast<uint16_t *>(ext + 2 * t.nf);        // [Q][nc]
   uint32_t *cnt32 = reinterpret_cast<uint32_t *>(cnt);
   const int lane = threadIdx.x & 63;
@@ -77,8 +77,8 @@ __device__ __forceinline__ void hard_block(const HardTask &t, float *smem, int32
 #pragma unroll
     for (int s = 0; s < S; ++s) vm[s] = ballot(lane * S + s < valid);
     if (valid == 0) continue;  // an empty wave tile (S < 4 at a region's end)
-    // largest and smallest value of each feature over the valid samples:
-    // 16 threads per feature
+    // largest and negated smallest value of each feature over the valid
+    // samples: 16 threads per feature
     for (int f0 = 0; f0 < t.nf; f0 += 64) {
       const int f = f0 + (threadIdx.x >> 4), part = threadIdx.x & 15;
       float hi = -INFINITY, lo = INFINITY;
@@ -95,7 +95,7 @@ __device__ __forceinline__ void hard_block(const HardTask &t, float *smem, int32
       }
       if (f < t.nf && part == 0) {
         ext[2 * f] = hi;
-        ext[2 * f + 1] = lo;
+        ext[2 * f + 1] = -lo;
       }
     }
     __syncthreads();
@@ -111,11 +111,11 @@ __device__ __forceinline__ void hard_block(const HardTask &t, float *smem, int32
       // first walk
       int4 set[2];
       ldc_pair(t.sets + t.q0 + q0, set);
-      uint2 head[2];
+      uint4 head[2];
 #pragma unroll
       for (int k = 0; k < 2; ++k) {
         const int nh = set[k].y >> 16;
-        head[k] = make_uint2(0u, 0u);
+        head[k] = make_uint4(0u, 0u, 0u, 0u);
         if (q0 + k < q1 && t.heads && nh >= 1 && nh <= kMaxHeads && lane < nh)
           head[k] = t.heads[set[k].x + lane];
       }
@@ -127,16 +127,17 @@ __device__ __forceinline__ void hard_block(const HardTask &t, float *smem, int32
         const int nh = s4.y >> 16;
         int acc;
         if (t.heads && nh >= 1 && nh <= kMaxHeads) {
-          // branch-free: the extreme is read for every lane
-          const uint32_t hx = head[k].x;
-          const uint32_t le = (hx >> 29) & 1u;
-          const float e = ext[2 * ((hx >> kHeadFShift) & 511u) + le];
-          const float th = __uint_as_float(head[k].y);
-          const uint32_t fails = le ? (uint32_t)(e > th) : (uint32_t)(e < th);
-          const uint32_t keep = (hx >> 31) & ~(fails & (hx >> 30));
+          // lane j: rule j; table[e] < t' when no sample of the tile passes
+          const uint4 h = head[k];
+          const char *tb = reinterpret_cast<const char *>(ext);
+          const float e1 = *reinterpret_cast<const float *>(tb + (h.x >> kHeadExtShift));
+          const float e2 = *reinterpret_cast<const float *>(tb + h.z);
+          // (bitwise, so that both table reads are unconditional)
+          const uint32_t keep = (uint32_t)(lane < nh) & (uint32_t)!(e1 < __uint_as_float(h.y)) &
+                                (uint32_t)!(e2 < __uint_as_float(h.w));
           // the closing record (last entry) is always visited
-          const uint64_t mk = ballot(keep & 1u) | (1ull << (nh - 1));
-          acc = eval_set_count<S, true>(lds_lane, lane, s4, t.conds, vm, mk, hx & kHeadOffMask);
+          const uint64_t mk = ballot(keep != 0u) | (1ull << (nh - 1));
+          acc = eval_set_count<S, true>(lds_lane, lane, s4, t.conds, vm, mk, h.x & kHeadOffMask);
         } else {
           acc = eval_set_count<S, false>(lds_lane, lane, s4, t.conds, vm);
         }

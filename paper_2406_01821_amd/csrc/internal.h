@@ -77,18 +77,19 @@ constexpr uint32_t kRecNextShift = 18;
 // Records of one rule set, closing record included: next-rule byte offsets
 // fit 14 bits.
 constexpr int32_t kMaxSetRecords = 1023;
-// Head table (8 bytes per entry, parallel to the hard stream: the entries of
-// a set start at its first record's index): one entry per rule in order, then
-// one for the closing record.  x: the rule's first-record byte offset (from
-// the set's first record) | f << 14 of that record | kHeadLE | kHeadTest |
-// kHeadValid; y: its folded threshold.  kHeadTest marks a first record that
-// is a folded threshold (x[f] >= y, or x[f] <= y with kHeadLE): when no
-// sample of a tile passes it, no sample of the tile can fire the rule.
+// Head table (16 bytes per entry, parallel to the hard stream: the entries
+// of a set start at its first record's index): one entry per rule in order,
+// then one for the closing record.
+//   x: the rule's first-record byte offset (from the set's first record) |
+//      e1 << 14;  y: t1;  z: e2;  w: t2
+// Tests i = 1, 2 stand for the rule's first two records: a folded threshold
+// x[f] >= t gives e = 8f, t' = t, and x[f] <= t gives e = 8f + 4, t' = -t;
+// any other record gives e = 0, t' = -inf.  With a tile's per-feature table
+// {max x[f], -min x[f]} at byte offsets 8f and 8f + 4, table[e] < t' holds
+// exactly when no sample of the tile passes the record, and then no sample
+// of the tile can fire the rule.
 constexpr uint32_t kHeadOffMask = 0x3fffu;
-constexpr uint32_t kHeadFShift = 14;
-constexpr uint32_t kHeadLE = 1u << 29;
-constexpr uint32_t kHeadTest = 1u << 30;
-constexpr uint32_t kHeadValid = 1u << 31;
+constexpr uint32_t kHeadExtShift = 14;
 // Sets with at most this many head entries take the filtered walk.
 constexpr int32_t kMaxHeads = 64;
 struct PackedLayout {
@@ -120,7 +121,7 @@ struct PopRec {
   const int4 *rules = nullptr;
   const uint4 *hconds = nullptr;
   const uint32_t *sconds = nullptr;
-  const uint2 *heads = nullptr;
+  const uint4 *heads = nullptr;
   void *staging = nullptr;     // pinned host copy of the packed image
   hipEvent_t staged = nullptr; // completion of the staging copy
 };

@@ -143,7 +143,7 @@ PackedLayout packed_layout(int32_t n_sets, int32_t n_rules, int32_t n_conds) {
   L.sconds_off = off;
   off = align256(off + sizeof(uint32_t) * (size_t)(n_conds > 0 ? n_conds : 1));
   L.heads_off = off;
-  off = align256(off + sizeof(uint2) * ((size_t)n_conds + (size_t)n_rules + (size_t)std::max(n_sets, 0) + 1));
+  off = align256(off + sizeof(uint4) * ((size_t)n_conds + (size_t)n_rules + (size_t)std::max(n_sets, 0) + 1));
   L.total = off;
   return L;
 }
@@ -225,7 +225,8 @@ void pack_population_image(const aerl_population *p, int32_t nf, int32_t nc, int
   int4 *rules = reinterpret_cast<int4 *>(base + L.rules_off);
   uint4 *hc = reinterpret_cast<uint4 *>(base + L.hconds_off);
   uint32_t *sc = reinterpret_cast<uint32_t *>(base + L.sconds_off);
-  uint2 *heads = reinterpret_cast<uint2 *>(base + L.heads_off);
+  uint4 *heads = reinterpret_cast<uint4 *>(base + L.heads_off);
+  const uint32_t no_test = fbits(-INFINITY);
   int32_t max_rules = 0, max_rule_conds = 0;
   int64_t nominal = 0;
   // Hard stream: for each rule set its rules in order, then a closing
@@ -244,10 +245,10 @@ void pack_population_image(const aerl_population *p, int32_t nf, int32_t nc, int
       if (k > max_rule_conds) max_rule_conds = k;
       const uint32_t cls = (uint32_t)p->rule_class[r] << kRecClsShift;
       const uint32_t next = (uint32_t)(out - first + std::max(k, 1)) * 16u << kRecNextShift;
-      // the rule's head entry: its start, and its first record's test when
-      // that is a folded threshold (filled in below)
-      uint2 &head = heads[first + (r - r0)];
-      head = make_uint2(kHeadValid | (uint32_t)(out - first) * 16u, 0u);
+      // the rule's head entry: its start, and the tile tests of its first
+      // two records when they are folded thresholds (filled in below)
+      uint4 &head = heads[first + (r - r0)];
+      head = make_uint4((uint32_t)(out - first) * 16u, no_test, 0u, no_test);
       if (k == 0) {
         hc[out++] = make_uint4(0u, 0u, 0u, kRecAlways | kRecLast | cls | next);
         continue;
@@ -291,14 +292,22 @@ void pack_population_image(const aerl_population *p, int32_t nf, int32_t nc, int
         }
         prev_grp = grp;
         if (pos == k - 1) w |= kRecLast;
-        if (pos == 0 && grp < 2)
-          head = make_uint2(head.x | (uint32_t)p->f[j] << kHeadFShift | kHeadTest | (grp == 1 ? kHeadLE : 0u),
-                            fbits(a));
+        if (pos < 2 && grp < 2) {
+          const uint32_t e = 8u * (uint32_t)p->f[j] + (grp == 1 ? 4u : 0u);
+          const uint32_t tt = fbits(grp == 1 ? -a : a);
+          if (pos == 0) {
+            head.x |= e << kHeadExtShift;
+            head.y = tt;
+          } else {
+            head.z = e;
+            head.w = tt;
+          }
+        }
         hc[out++] = make_uint4((uint32_t)p->f[j] * 1024u, fbits(a), fbits(b), w);
       }
     }
     const uint32_t end = (uint32_t)(out - first + 1) * 16u << kRecNextShift;
-    heads[first + (r1 - r0)] = make_uint2(kHeadValid | (uint32_t)(out - first) * 16u, 0u);
+    heads[first + (r1 - r0)] = make_uint4((uint32_t)(out - first) * 16u, no_test, 0u, no_test);
     hc[out++] = make_uint4(0u, 0u, 0u,
                            kRecAlways | kRecLast | (uint32_t)p->set_default[s] << kRecClsShift | end);
     sets[s] = make_int4(first, (out - first) | (r1 - r0 + 1) << 16, p->set_default[s], nominal_s);

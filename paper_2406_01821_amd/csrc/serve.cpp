@@ -223,7 +223,7 @@ bool Serve::launch_one(std::unique_lock<std::mutex> &lk, Slot &slot) {
   for (Req *r : take) {
     const int4 *dsets = reinterpret_cast<const int4 *>(dev + r->in_off + r->L.sets_off);
     const uint4 *dconds = reinterpret_cast<const uint4 *>(dev + r->in_off + r->L.hconds_off);
-    const uint2 *dheads = reinterpret_cast<const uint2 *>(dev + r->in_off + r->L.heads_off);
+    const uint4 *dheads = reinterpret_cast<const uint4 *>(dev + r->in_off + r->L.heads_off);
     if (r->kind == AERL_REQ_FITNESS) {
       int32_t *c = reinterpret_cast<int32_t *>(dev + r->out_off);
       int32_t *cf = r->h_conf ? reinterpret_cast<int32_t *>(dev + r->out_off + al(r->correct_bytes()))

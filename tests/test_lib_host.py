@@ -101,7 +101,7 @@ def decode_packed(img, n_sets, n_rules, n_conds, heads=False):
         return sets, hc
     sc_off = _align(hc_off + 16 * n_rec)
     hd_off = _align(sc_off + 4 * max(n_conds, 1))
-    hd = img[hd_off:hd_off + 8 * n_rec].view(np.uint32).reshape(-1, 2)
+    hd = img[hd_off:hd_off + 16 * n_rec].view(np.uint32).reshape(-1, 4)
     return sets, hc, hd, raw[:, 1] >> 16
 
 
@@ -391,33 +391,37 @@ def test_hard_kernels_fit_two_blocks_per_cu(tmp_path):
     assert all(v <= 80 for v in hard.values()), hard
 
 
-HEAD_LE, HEAD_TEST, HEAD_VALID = 1 << 29, 1 << 30, 1 << 31
+NO_TEST = int(np.float32(-np.inf).view(np.uint32))
+
+
+def head_tests(entry):
+    """The (table offset, t') pairs of a head entry."""
+    hx, hy, hz, hw = (int(v) for v in entry)
+    return [(hx >> 14, hy), (hz, hw)]
 
 
 def eval_packed_filtered(x, sets, hc, hd, nh, s):
-    """Model of the filtered walk over the rows of x taken as one tile: the
-    rules whose head entry's test fails for every row (x[f] >= t with t above
-    the rows' largest x[f], or x[f] <= t with t below the smallest) are
-    skipped; the others are walked from their start offset, in order; the
-    closing record is always visited.  Returns the predictions and the
-    number of rules skipped."""
+    """Model of the filtered walk over the rows of x taken as one tile: with
+    the table {max x[f], -min x[f]} at byte offsets 8f and 8f + 4, a rule is
+    skipped when table[e] < t' for one of its head entry's two tests; the
+    others are walked from their start offset, in order; the closing record
+    is always visited.  Returns the predictions and the number of rules
+    skipped."""
     first, count, default, _ = (int(v) for v in sets[s])
     n_heads = int(nh[s])
     assert 1 <= n_heads <= count
-    hi, lo = x.max(axis=0), x.min(axis=0)
+    table = np.empty(2 * x.shape[1], np.float32)
+    table[0::2] = x.max(axis=0)
+    table[1::2] = -x.min(axis=0)
     pred = np.full(x.shape[0], -1, np.int32)
     und = np.ones(x.shape[0], bool)
     skipped = 0
     for k in range(n_heads):
-        hx, hy = (int(v) for v in hd[first + k])
-        assert hx & HEAD_VALID
-        if hx & HEAD_TEST and k < n_heads - 1:
-            t = np.uint32(hy).view(np.float32)
-            f = (hx >> 14) & 511
-            if (lo[f] > t) if hx & HEAD_LE else (hi[f] < t):
-                skipped += 1
-                continue
-        o = hx & 0x3fff
+        if k < n_heads - 1 and any(table[e // 4] < np.uint32(t).view(np.float32)
+                                   for e, t in head_tests(hd[first + k])):
+            skipped += 1
+            continue
+        o = int(hd[first + k][0]) & 0x3fff
         fire = und.copy()
         while True:
             r = tuple(int(v) for v in hc[first + o // 16])
@@ -436,8 +440,9 @@ def eval_packed_filtered(x, sets, hc, hd, nh, s):
 
 def test_head_table_describes_every_rule(aerl):
     """One head entry per rule and one for the closing record: the rule's
-    first-record offset, and for a rule whose first record is a folded
-    threshold, that record's feature, direction and threshold."""
+    first-record offset and, for each of its first two records that is a
+    folded threshold, that record's feature, direction and threshold in the
+    table-compare form (no test otherwise)."""
     pop = synth.special_values_population(31, 6, 3, 80)
     img = aerl.pack_host(pop, 6, 3)
     sets, hc, hd, nh = decode_packed(img, pop.n_sets, pop.n_rules, pop.n_conds, heads=True)
@@ -451,16 +456,18 @@ def test_head_table_describes_every_rule(aerl):
                 starts.append(16 * (i + 1))
         assert len(starts) == n_rules + 1 and starts[-1] == 16 * (count - 1)
         for k, o in enumerate(starts):
-            hx, hy = (int(v) for v in hd[first + k])
-            assert hx & HEAD_VALID and hx & 0x3fff == o
-            r = [int(v) for v in hc[first + o // 16]]
-            threshold = not r[3] & (FF | MUL | ALWAYS)
-            assert bool(hx & HEAD_TEST) == threshold, (s, k)
-            if threshold:
-                assert (hx >> 14) & 511 == r[0] // 1024 and hy == r[1]
-                assert bool(hx & HEAD_LE) == bool(r[3] & GE_LE)
-
-
+            assert int(hd[first + k][0]) & 0x3fff == o
+            for i, (e, t) in enumerate(head_tests(hd[first + k])):
+                r = [int(v) for v in hc[first + o // 16 + i]]
+                same_rule = i == 0 or not int(hc[first + o // 16][3]) & LAST
+                threshold = same_rule and not r[3] & (FF | MUL | ALWAYS)
+                if not threshold:
+                    assert (e, t) == (0, NO_TEST), (s, k, i)
+                    continue
+                le = bool(r[3] & GE_LE)
+                assert e == 8 * (r[0] // 1024) + (4 if le else 0), (s, k, i)
+                y = np.uint32(r[1]).view(np.float32)
+                assert t == int((-y if le else y).view(np.uint32)), (s, k, i)
 @pytest.mark.parametrize("seed", range(3))
 def test_head_filter_skips_only_rules_that_cannot_fire(aerl, seed):
     """The filtered walk on tiles of 1-256 rows gives the oracle's
