@@ -249,3 +249,65 @@ def test_block_counters_at_their_widest(ctx):
     assert list(c) == [n, n]
     with pytest.raises(AerlError):
         run_hard(ctx, data, pop, (4, 2, 256))
+
+
+def _layout_tiles(y, n_classes, tile=256):
+    """Sample indices of each layout tile: samples grouped by label (stable),
+    each class region cut into tiles of 256."""
+    tiles = []
+    for c in range(n_classes):
+        idx = np.flatnonzero(y == c)
+        tiles += [idx[i:i + tile] for i in range(0, len(idx), tile)]
+    return tiles
+
+
+@pytest.mark.parametrize("cfg", [None, (4, 64, 1), (2, 33, 2), (1, 7, 1)])
+def test_tile_test_at_the_tile_extremes(ctx, cfg):
+    """Rules whose first or second condition sits exactly at a tile's largest
+    or smallest value (x >= max passes one sample, x > max none; x <= min
+    one, x < min none; also through coefficient 0.5 and through negated
+    coefficients, and signed zeros), next to rule sets of more than 63 rules
+    (which walk every rule), against the oracle on every set."""
+    rng = np.random.default_rng(71)
+    n, nf = 2500, 6
+    x = synth.lognormal_features(rng, n, nf)
+    x[:40, 2] = 0.0
+    x[40:80, 2] = -0.0
+    x[80:120, 3] = -x[80:120, 3]
+    y = rng.integers(0, 2, n).astype(np.int32)
+    data = Dataset(x, y, 2)
+    ext = []
+    for t in _layout_tiles(y, 2):
+        ext += [(f, x[t, f].max(), x[t, f].min()) for f in range(nf)]
+
+    def cond(op, f, theta, coef=1.0):
+        return dict(op=op, kind=0, f=f, g=0, coef=np.float32(coef), coef2=np.float32(0),
+                    theta=np.float32(theta))
+
+    def boundary_cond():
+        f, hi, lo = ext[rng.integers(len(ext))]
+        k = rng.integers(8)
+        if k == 0: return cond(3, f, hi)               # x >= max
+        if k == 1: return cond(2, f, hi)               # x > max
+        if k == 2: return cond(1, f, lo)               # x <= min
+        if k == 3: return cond(0, f, lo)               # x < min
+        if k == 4: return cond(3, f, np.float32(0.5) * hi, 0.5)
+        if k == 5: return cond(1, f, -hi, -1.0)        # -x <= -max
+        if k == 6: return cond(2, 2, 0.0)              # x > 0 (signed zeros)
+        return cond(0, 2, -0.0)                        # x < -0
+
+    sets = []
+    for s in range(60):
+        n_rules = int(rng.integers(1, 20)) if s % 6 else int(rng.integers(64, 90))
+        rules = []
+        for _ in range(n_rules):
+            conds = [boundary_cond()]
+            if rng.random() < 0.5:
+                conds.append(boundary_cond())
+            for _ in range(int(rng.integers(0, 3))):
+                f = int(rng.integers(nf))
+                conds.append(cond(int(rng.integers(4)), f, np.float32(rng.choice(x[:, f]))))
+            rules.append((int(rng.integers(2)), conds))
+        sets.append((int(rng.integers(2)), rules))
+    pop = from_rule_lists(sets)
+    check_against_oracle(ctx, data, pop, cfg)
