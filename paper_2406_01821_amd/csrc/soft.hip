@@ -289,6 +289,36 @@ __device__ __forceinline__ void cond_z_only(const SoftArgs &a, const float *xs, 
   }
 }
 
+// z2 of conditions j .. j+3 (forward pass): the four records in one 64-byte
+// scalar load and the four x[f] rows requested together, so that their
+// latencies overlap; the same arithmetic as cond_z_only.  TONLY: threshold
+// conditions only.
+template <int S, bool TONLY>
+__device__ __forceinline__ void cond_z4(const SoftArgs &a, const float *xs, int lane, int j,
+                                        float (&z)[4][S]) {
+  typedef uint32_t v16u __attribute__((ext_vector_type(16)));
+  typedef const __attribute__((address_space(4))) v16u *cptr;
+  const v16u r = *(cptr)(a.crec + j);
+  float xf[4][S];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) load_row<S>(xs, (r[4 * k] & 0xfffu) * 1024u, lane, xf[k]);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const uint32_t sc = r[4 * k];
+    const float c = __uint_as_float(r[4 * k + 1]), rv = __uint_as_float(r[4 * k + 2]);
+    const float sinv = __uint_as_float(r[4 * k + 3]);
+    if (!TONLY && ((sc >> 24) & 1u)) {
+      float xg[S];
+      load_row<S>(xs, ((sc >> 12) & 0xfffu) * 1024u, lane, xg);
+#pragma unroll
+      for (int s = 0; s < S; ++s) z[k][s] = fmaf(c, xf[k][s], -(rv * xg[s])) * sinv;
+    } else {
+#pragma unroll
+      for (int s = 0; s < S; ++s) z[k][s] = fmaf(c, xf[k][s], -rv) * sinv;
+    }
+  }
+}
+
 // Gathers the per-condition record read by the kernels above: the operand of
 // the right-hand side is theta for a threshold and coef2 for a
 // feature-vs-feature condition; sinv = +-log2(e)/tau_f by direction.
@@ -308,7 +338,7 @@ __global__ void k_soft_prep(const uint32_t *__restrict__ sconds, const float *__
 constexpr int kSoftBlock = 512;
 
 // ------------------------------------------------------------------ forward
-template <int S, class Acc>
+template <int S, class Acc, bool TONLY>
 __global__ __launch_bounds__(kSoftBlock) void k_soft_fwd(const SoftArgs a) {
   constexpr int TS = 64 * S, WPT = AERL_TILE / TS;
   extern __shared__ __align__(16) float smem[];
@@ -350,7 +380,19 @@ __global__ __launch_bounds__(kSoftBlock) void k_soft_fwd(const SoftArgs a) {
       for (int k = 0; k < ss.y; ++k) {
         const int4 r = ldc(a.rules, ss.x + k);
         Acc ra[S];
-        for (int j = r.x; j < r.x + r.y; ++j) {
+        // conditions four at a time, then one at a time (same order)
+        int j = r.x;
+        const int je = r.x + r.y;
+        for (; j + 4 <= je; j += 4) {
+          float z[4][S];
+          cond_z4<S, TONLY>(a, xs, lane, j, z);
+#pragma unroll
+          for (int c4 = 0; c4 < 4; ++c4) {
+#pragma unroll
+            for (int s = 0; s < S; ++s) (void)ra[s].add(z[c4][s]);
+          }
+        }
+        for (; j < je; ++j) {
           float z[S];
           cond_z_only<S>(a, xs, lane, j, z);
 #pragma unroll
@@ -815,12 +857,12 @@ void fill_args(SoftArgs &a, const SoftLaunch &l, const SoftPlan &p) {
   }
 }
 
-template <class Acc>
+template <class Acc, bool TONLY>
 void launch_fwd(const SoftPlan &p, dim3 grid, hipStream_t st, const SoftArgs &a) {
   switch (p.S) {
-    case 4: hipLaunchKernelGGL((k_soft_fwd<4, Acc>), grid, dim3(kSoftBlock), p.lds, st, a); break;
-    case 2: hipLaunchKernelGGL((k_soft_fwd<2, Acc>), grid, dim3(kSoftBlock), p.lds, st, a); break;
-    default: hipLaunchKernelGGL((k_soft_fwd<1, Acc>), grid, dim3(kSoftBlock), p.lds, st, a); break;
+    case 4: hipLaunchKernelGGL((k_soft_fwd<4, Acc, TONLY>), grid, dim3(kSoftBlock), p.lds, st, a); break;
+    case 2: hipLaunchKernelGGL((k_soft_fwd<2, Acc, TONLY>), grid, dim3(kSoftBlock), p.lds, st, a); break;
+    default: hipLaunchKernelGGL((k_soft_fwd<1, Acc, TONLY>), grid, dim3(kSoftBlock), p.lds, st, a); break;
   }
 }
 
@@ -894,10 +936,15 @@ hipError_t launch_soft_forward(const SoftLaunch &l, hipStream_t st) {
   if (e0 != hipSuccess) return e0;
   if (p.n_groups > 0) {
     const dim3 grid((unsigned)((pop.n_sets + p.Q - 1) / p.Q), (unsigned)p.n_groups);
-    if (pop.max_rule_conds <= kProdMaxConds) {
-      launch_fwd<RuleProd>(p, grid, st, a);
+    const bool prod = pop.max_rule_conds <= kProdMaxConds, tonly = pop.n_ff == 0;
+    if (prod && tonly) {
+      launch_fwd<RuleProd, true>(p, grid, st, a);
+    } else if (prod) {
+      launch_fwd<RuleProd, false>(p, grid, st, a);
+    } else if (tonly) {
+      launch_fwd<RuleAcc, true>(p, grid, st, a);
     } else {
-      launch_fwd<RuleAcc>(p, grid, st, a);
+      launch_fwd<RuleAcc, false>(p, grid, st, a);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
