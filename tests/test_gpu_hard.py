@@ -266,8 +266,9 @@ def test_tile_test_at_the_tile_extremes(ctx, cfg):
     """Rules whose first or second condition sits exactly at a tile's largest
     or smallest value (x >= max passes one sample, x > max none; x <= min
     one, x < min none; also through coefficient 0.5 and through negated
-    coefficients, and signed zeros), next to rule sets of more than 63 rules
-    (which walk every rule), against the oracle on every set."""
+    coefficients, and signed zeros), in rule sets of up to 63 rules (tile
+    test) and of 64 and more (which walk every rule), against the oracle on
+    every set."""
     rng = np.random.default_rng(71)
     n, nf = 2500, 6
     x = synth.lognormal_features(rng, n, nf)
@@ -297,8 +298,14 @@ def test_tile_test_at_the_tile_extremes(ctx, cfg):
         return cond(0, 2, -0.0)                        # x < -0
 
     sets = []
-    for s in range(60):
-        n_rules = int(rng.integers(1, 20)) if s % 6 else int(rng.integers(64, 90))
+    # 62 and 63 rules: the tile test's largest sets (up to 64 head entries
+    # with the closing record); 64 and more: every rule walked
+    sizes = [62, 63, 64, 65]
+    for s in range(64):
+        if s < len(sizes):
+            n_rules = sizes[s]
+        else:
+            n_rules = int(rng.integers(1, 20)) if s % 6 else int(rng.integers(66, 90))
         rules = []
         for _ in range(n_rules):
             conds = [boundary_cond()]
