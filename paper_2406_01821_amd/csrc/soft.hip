@@ -133,13 +133,23 @@ __device__ __forceinline__ float log2_1p(float p) {
 // kept scaled by 2^64 (pt), so that u down to 2^-190 stays a normal float;
 // with at most 60 conditions pt < 2^124.
 constexpr int kProdMaxConds = 60;
+// min(v, 0) in one v_min_f32.  fminf on a value the compiler cannot prove
+// canonical (here a product carried across the wave reductions' branches)
+// gets a canonicalizing copy first; no signaling NaN reaches this point, so
+// the copy changes nothing and is left out.
+__device__ __forceinline__ float min0(float v) {
+  float r;
+  asm("v_min_f32 %0, 0, %1" : "=v"(r) : "v"(v));
+  return r;
+}
+
 struct RuleProd {
   float m = 0.0f, pt = 0.0f;  // m = M in bits, pt = p * 2^64
   __device__ __forceinline__ float add(float z2) {
     const float ut = fexp2(64.0f - fabsf(z2));  // u * 2^64
     const float u = ut * 0x1p-64f;
     pt = fmaf(pt, u, pt + ut);
-    m += fmaxf(-z2, 0.0f);
+    m -= min0(z2);  // m += max(-z2, 0), the same value bit for bit
     return u;
   }
 };
@@ -377,8 +387,11 @@ __global__ __launch_bounds__(kSoftBlock) void k_soft_fwd(const SoftArgs a) {
       float logpy[S], surv[S];
 #pragma unroll
       for (int s = 0; s < S; ++s) { logpy[s] = kNegInf; surv[s] = 0.0f; }
+      // each rule's record is requested one rule ahead (the last one twice)
+      int4 r_next = ldc(a.rules, ss.x);
       for (int k = 0; k < ss.y; ++k) {
-        const int4 r = ldc(a.rules, ss.x + k);
+        const int4 r = r_next;
+        r_next = ldc(a.rules, ss.x + min(k + 1, ss.y - 1));
         Acc ra[S];
         // conditions four at a time, then one at a time (same order)
         int j = r.x;
