@@ -99,7 +99,8 @@ __device__ __forceinline__ float rule_log_miss(const RuleAcc &r) {
 
 // log2(2^p + 2^q), -inf safe.
 __device__ __forceinline__ float lse(float p, float q) {
-  const float m = fmaxf(p, q);
+  float m;  // fmaxf(p, q); p and q are never NaN, so no canonicalizing copies
+  asm("v_max_f32 %0, %1, %2" : "=v"(m) : "v"(p), "v"(q));
   if (m == kNegInf) return kNegInf;
   return m + log2_1p_unit(fexp2(-fabsf(p - q)));
 }
