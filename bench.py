@@ -84,6 +84,37 @@ def time_cpu_oracle_hard(w, budget_s=15.0):
                        f"{dt:.2f} s")
 
 
+def cpu_oracle_detail(w, budget_s=2.0):
+    """The oracle on one host thread (a slice of rule sets grown to about
+    budget_s of CPU work), with the host's CPU model and usable cores."""
+    import oracle
+    n_sets = 1
+    while True:
+        sub = w.pop.subset(range(n_sets))
+        t0 = time.perf_counter()
+        oracle.hard_eval(w.data.x, w.data.y, w.data.n_classes, sub, nthreads=1)
+        dt = time.perf_counter() - t0
+        if dt * 2 > budget_s or n_sets * 2 > w.pop.n_sets:
+            break
+        n_sets = min(w.pop.n_sets, int(n_sets * max(2.0, budget_s / max(dt, 1e-3) / 2)))
+    nominal = int(sub.nominal_conds_per_set().sum()) * w.data.n
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"single_thread": {"value": nominal / dt, "unit": "cond-evals/s",
+                              "sample": f"first {n_sets} of {w.pop.n_sets} rule sets x all "
+                                        f"{w.data.n} samples, {dt:.2f} s"},
+            "oracle_threads": oracle.max_threads(), "cpu_model": model,
+            "usable_cpus": usable}
+
+
 # Algorithmic VALU work of the soft path, in lane issue slots (transcendentals
 # count twice: v_exp_f32 / v_log_f32 issue at half rate on gfx950).
 TRANS = 2
@@ -415,6 +446,7 @@ def main():
     }
     if not args.no_cpu:
         result["cpu_baseline"] = time_cpu_oracle_hard(w)
+        result["cpu_oracle_detail"] = cpu_oracle_detail(w)
     ctx.release_population(pop)
     if not args.only_hard:
         small = synth.small_hard(0).data
