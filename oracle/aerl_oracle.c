@@ -69,11 +69,15 @@ int orc_max_threads(void) {
 #endif
 }
 
-static void set_threads(int nthreads) {
+/* Threads of one call's parallel region: nthreads when positive, else the
+ * OpenMP default.  Passed as a num_threads clause, so a call never changes
+ * the thread count of later calls. */
+static int pick_threads(int nthreads) {
 #ifdef _OPENMP
-  if (nthreads > 0) omp_set_num_threads(nthreads);
+  return nthreads > 0 ? nthreads : omp_get_max_threads();
 #else
   (void)nthreads;
+  return 1;
 #endif
 }
 
@@ -114,10 +118,11 @@ static int32_t predict_one(const orc_population *p, int32_t s, const float *xr) 
  * confusion[s][true][pred] (optional, may be NULL).  x is [n][nf] row-major. */
 int orc_hard_eval(int64_t n, int32_t nf, const float *x, const int32_t *y, int32_t nc,
                   const orc_population *p, int32_t *correct, int32_t *confusion, int nthreads) {
-  set_threads(nthreads);
+  const int nt = pick_threads(nthreads);
+  (void)nt;
   int64_t cc = (int64_t)nc * nc;
   if (confusion) memset(confusion, 0, sizeof(int32_t) * (size_t)(p->n_sets * cc));
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) num_threads(nt)
   for (int32_t s = 0; s < p->n_sets; ++s) {
     int32_t good = 0;
     for (int64_t i = 0; i < n; ++i) {
@@ -148,12 +153,13 @@ int orc_predict(int64_t n, int32_t nf, const float *x, const orc_population *p, 
 int orc_workcount(int64_t n_tiles, const int64_t *tile_ptr, const int64_t *tile_idx, int32_t nf,
                   const float *x, const orc_population *p, int64_t *work_t, int64_t *work_ff,
                   int nthreads) {
-  set_threads(nthreads);
+  const int nt = pick_threads(nthreads);
+  (void)nt;
   int64_t max_tile = 0;
   for (int64_t t = 0; t < n_tiles; ++t)
     if (tile_ptr[t + 1] - tile_ptr[t] > max_tile) max_tile = tile_ptr[t + 1] - tile_ptr[t];
   int bad = 0;
-#pragma omp parallel
+#pragma omp parallel num_threads(nt)
   {
     unsigned char *undecided = (unsigned char *)malloc((size_t)max_tile + 1);
     unsigned char *alive = (unsigned char *)malloc((size_t)max_tile + 1);
@@ -286,8 +292,9 @@ int orc_soft_forward(int64_t n, int32_t nf, const float *x, const int32_t *y, co
                      int32_t nc, const orc_population *p, const double *coef, const double *coef2,
                      const double *theta, double *loss, int nthreads) {
   if (nc > MAX_CLASSES) return -1;
-  set_threads(nthreads);
-#pragma omp parallel for schedule(static)
+  const int nt = pick_threads(nthreads);
+  (void)nt;
+#pragma omp parallel for schedule(static) num_threads(nt)
   for (int32_t s = 0; s < p->n_sets; ++s) {
     double logp[MAX_CLASSES];
     double acc = 0.0;
@@ -357,9 +364,10 @@ int orc_soft_backward(int64_t n, int32_t nf, const float *x, const int32_t *y, c
     int32_t r = p->set_rule_off[s + 1] - p->set_rule_off[s];
     if (r > max_r) max_r = r;
   }
-  set_threads(nthreads);
+  const int nt = pick_threads(nthreads);
+  (void)nt;
   int bad = 0;
-#pragma omp parallel
+#pragma omp parallel num_threads(nt)
   {
     double *a = (double *)malloc(sizeof(double) * (size_t)(max_r + 1));
     double *b = (double *)malloc(sizeof(double) * (size_t)(max_r + 1));
