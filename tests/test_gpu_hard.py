@@ -318,3 +318,22 @@ def test_tile_test_at_the_tile_extremes(ctx, cfg):
         sets.append((int(rng.integers(2)), rules))
     pop = from_rule_lists(sets)
     check_against_oracle(ctx, data, pop, cfg)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_tile_test_random_shapes(ctx, seed):
+    """Random shapes on heavy-tailed data: 8-100 features (four or two
+    samples per lane by default), 2-5 classes, rule sets of 1-70 rules x 1-8
+    conditions (30% feature-vs-feature), so that tile-tested sets and sets
+    walked rule by rule share launches, and thresholds over each column's
+    range that sit above or below many tiles' extremes; bit-exact against
+    the oracle."""
+    rng = np.random.default_rng(900 + seed)
+    nf = int(rng.integers(8, 101))
+    nc = int(rng.integers(2, 6))
+    n = int(rng.integers(700, 3000))
+    x = synth.lognormal_features(rng, n, nf)
+    y = rng.integers(0, nc, n).astype(np.int32)
+    data = Dataset(x, y, nc)
+    pop = synth.random_population(rng, x, 48, (1, 70), (1, 8), nc, 0.3)
+    check_against_oracle(ctx, data, pop)
