@@ -84,6 +84,28 @@ def time_cpu_oracle_hard(w, budget_s=15.0):
                        f"{dt:.2f} s")
 
 
+def time_call_level(ctx, ds, w, reps=3):
+    """One whole call from host rule sets to host results: validation and
+    packing on the host, the copy to the device, the evaluation and the
+    copy of the counts back (median of reps; the dataset stays resident)."""
+    import torch
+    total, pack = [], []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        p = ctx.pack_population(w.pop, w.data.n_features, w.data.n_classes)
+        t1 = time.perf_counter()
+        c, m = ctx.eval_population(ds, p)
+        c.cpu(), m.cpu()
+        t2 = time.perf_counter()
+        ctx.release_population(p)
+        total.append((t2 - t0) * 1e3)
+        pack.append((t1 - t0) * 1e3)
+    med = lambda v: sorted(v)[len(v) // 2]
+    return {"ms": med(total), "host_pack_ms": med(pack),
+            "what": "pack on the host + copy to the device + evaluation + counts back"}
+
+
 def cpu_oracle_detail(w, budget_s=2.0):
     """The oracle on one host thread (a slice of rule sets grown to about
     budget_s of CPU work), with the host's CPU model and usable cores."""
@@ -444,6 +466,7 @@ def main():
         "kernel_ms": ms,
         "roofline": roofline,
     }
+    result["call_level"] = time_call_level(ctx, ds, w)
     if not args.no_cpu:
         result["cpu_baseline"] = time_cpu_oracle_hard(w)
         result["cpu_oracle_detail"] = cpu_oracle_detail(w)
