@@ -23,6 +23,8 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstring>
+#include <thread>
+#include <vector>
 
 #include "internal.h"
 
@@ -212,33 +214,31 @@ aerl_status validate_population(aerl_ctx *ctx, const aerl_population *p, int32_t
   return AERL_OK;
 }
 
-// Writes the packed image of a validated population into `dst` (host memory
-// of PackedLayout::total bytes) and fills the summary fields of `rec`.
-void pack_population_image(const aerl_population *p, int32_t nf, int32_t nc, int32_t n_rules,
-                           int32_t n_conds, void *dst, PopRec *rec) {
-  const PackedLayout L = packed_layout(p->n_sets, n_rules, n_conds);
-  std::memset(dst, 0, L.total);
-  rec->max_set_conds = 0;
-  char *base = static_cast<char *>(dst);
-  int4 *sets = reinterpret_cast<int4 *>(base + L.sets_off);
-  int4 *ssets = reinterpret_cast<int4 *>(base + L.ssets_off);
-  int4 *rules = reinterpret_cast<int4 *>(base + L.rules_off);
-  uint4 *hc = reinterpret_cast<uint4 *>(base + L.hconds_off);
-  uint32_t *sc = reinterpret_cast<uint32_t *>(base + L.sconds_off);
-  uint4 *heads = reinterpret_cast<uint4 *>(base + L.heads_off);
+namespace {
+
+// Summary counts of a range of rule sets.
+struct PackStats {
+  int32_t max_rules = 0, max_rule_conds = 0, max_set_conds = 0;
+  int64_t nominal = 0;
+};
+
+// Hard stream, head table and set records of rule sets [s0, s1), whose
+// first records start at index first[s] (sets do not share records, so
+// ranges of sets are packed independently).  For each rule set its rules in
+// order, then a closing always-true record of the default class; inside a
+// rule the folded >= thresholds first, then <=, zero coefficients,
+// feature >, feature >= (an AND: the order changes no result).  An empty
+// rule (always fires) becomes one always-true record.
+void pack_sets(const aerl_population *p, const int32_t *first_of, int32_t s0, int32_t s1,
+               int4 *sets, int4 *ssets, uint4 *hc, uint4 *heads, PackStats *st) {
   const uint32_t no_test = fbits(-INFINITY);
   int32_t max_rules = 0, max_rule_conds = 0;
   int64_t nominal = 0;
-  // Hard stream: for each rule set its rules in order, then a closing
-  // always-true record of the default class; inside a rule the folded >=
-  // thresholds first, then <=, zero coefficients, feature >, feature >= (an
-  // AND: the order changes no result).  An empty rule (always fires) becomes
-  // one always-true record.
-  int32_t out = 0;
-  for (int32_t s = 0; s < p->n_sets; ++s) {
+  for (int32_t s = s0; s < s1; ++s) {
     const int32_t r0 = p->set_rule_off[s], r1 = p->set_rule_off[s + 1];
     const int32_t nominal_s = r1 > r0 ? p->rule_cond_off[r1] - p->rule_cond_off[r0] : 0;
-    const int32_t first = out;
+    const int32_t first = first_of[s];
+    int32_t out = first;
     for (int32_t r = r0; r < r1; ++r) {
       const int32_t j0 = p->rule_cond_off[r], j1 = p->rule_cond_off[r + 1];
       const int32_t k = j1 - j0;
@@ -308,36 +308,132 @@ void pack_population_image(const aerl_population *p, int32_t nf, int32_t nc, int
     }
     const uint32_t end = (uint32_t)(out - first + 1) * 16u << kRecNextShift;
     heads[first + (r1 - r0)] = make_uint4((uint32_t)(out - first) * 16u, no_test, 0u, no_test);
+    // entries past the head count are never read; zero keeps the image exact
+    for (int32_t e = first + (r1 - r0) + 1; e <= out; ++e) heads[e] = make_uint4(0u, 0u, 0u, 0u);
     hc[out++] = make_uint4(0u, 0u, 0u,
                            kRecAlways | kRecLast | (uint32_t)p->set_default[s] << kRecClsShift | end);
     sets[s] = make_int4(first, (out - first) | (r1 - r0 + 1) << 16, p->set_default[s], nominal_s);
     ssets[s] = make_int4(r0, r1 - r0, r1 > r0 ? p->rule_cond_off[r0] : 0, nominal_s);
-    if (nominal_s > rec->max_set_conds) rec->max_set_conds = nominal_s;
+    if (nominal_s > st->max_set_conds) st->max_set_conds = nominal_s;
     nominal += nominal_s;
     if (r1 - r0 > max_rules) max_rules = r1 - r0;
   }
-  hc[out] = make_uint4(0u, 0u, 0u, 0u);  // read-ahead pad
-  for (int32_t r = 0; r < n_rules; ++r) {
+  st->max_rules = std::max(st->max_rules, max_rules);
+  st->max_rule_conds = std::max(st->max_rule_conds, max_rule_conds);
+  st->nominal += nominal;
+}
+
+// Soft-path rule records and condition words of rules [q0, q1); counts the
+// feature-vs-feature conditions among their conditions.
+void pack_rules(const aerl_population *p, int32_t q0, int32_t q1, int4 *rules, uint32_t *sc,
+                int32_t *n_ff) {
+  int32_t ff = 0;
+  for (int32_t r = q0; r < q1; ++r) {
     const int32_t j0 = p->rule_cond_off[r], j1 = p->rule_cond_off[r + 1];
     rules[r] = make_int4(j0, j1 - j0, p->rule_class[r], 0);
     for (int32_t j = j0; j < j1; ++j) {
       const uint32_t g = p->kind[j] == AERL_KIND_FEATURE ? (uint32_t)p->g[j] : 0u;
       sc[j] = (uint32_t)p->f[j] | (g << 12) | ((uint32_t)p->kind[j] << 24) |
               ((uint32_t)(p->op[j] >= AERL_OP_GT) << 25);
+      ff += p->kind[j] == AERL_KIND_FEATURE;
     }
   }
-  (void)nc;
+  *n_ff = ff;
+}
+
+// Runs fn(i) for i in [0, n) on up to n host threads (i = 0 on the caller).
+template <class F>
+void run_parts(int n, const F &fn) {
+  std::vector<std::thread> th;
+  th.reserve(n > 1 ? n - 1 : 0);
+  for (int i = 1; i < n; ++i) {
+    try {
+      th.emplace_back(fn, i);
+    } catch (...) {  // no thread to be had: this part runs here
+      fn(i);
+    }
+  }
+  fn(0);
+  for (auto &t : th) t.join();
+}
+
+}  // namespace
+
+// Writes the packed image of a validated population into `dst` (host memory
+// of PackedLayout::total bytes) and fills the summary fields of `rec`.
+// Large populations are packed by several host threads, each a range of
+// rule sets (and of rules); the image does not depend on their number.
+void pack_population_image(const aerl_population *p, int32_t nf, int32_t nc, int32_t n_rules,
+                           int32_t n_conds, void *dst, PopRec *rec) {
+  const PackedLayout L = packed_layout(p->n_sets, n_rules, n_conds);
+  char *base = static_cast<char *>(dst);
+  int4 *sets = reinterpret_cast<int4 *>(base + L.sets_off);
+  int4 *ssets = reinterpret_cast<int4 *>(base + L.ssets_off);
+  int4 *rules = reinterpret_cast<int4 *>(base + L.rules_off);
+  uint4 *hc = reinterpret_cast<uint4 *>(base + L.hconds_off);
+  uint32_t *sc = reinterpret_cast<uint32_t *>(base + L.sconds_off);
+  uint4 *heads = reinterpret_cast<uint4 *>(base + L.heads_off);
+  // first record of every rule set: one per condition, one per empty rule,
+  // one closing record
+  std::vector<int32_t> first(p->n_sets + 1);
+  first[0] = 0;
+  for (int32_t s = 0; s < p->n_sets; ++s) {
+    int32_t recs = 1;
+    for (int32_t r = p->set_rule_off[s]; r < p->set_rule_off[s + 1]; ++r)
+      recs += std::max(p->rule_cond_off[r + 1] - p->rule_cond_off[r], 1);
+    first[s + 1] = first[s] + recs;
+  }
+  const int32_t n_rec = first[p->n_sets];
+  // bytes no part writes: the read-ahead pad record, the unused tails of the
+  // regions and the alignment gaps between them
+  const auto zero_tail = [&](size_t used_end, size_t region_end) {
+    if (region_end > used_end) std::memset(base + used_end, 0, region_end - used_end);
+  };
+  zero_tail(L.sets_off + sizeof(int4) * (size_t)p->n_sets, L.ssets_off);
+  zero_tail(L.ssets_off + sizeof(int4) * (size_t)p->n_sets, L.rules_off);
+  zero_tail(L.rules_off + sizeof(int4) * (size_t)n_rules, L.hconds_off);
+  zero_tail(L.hconds_off + sizeof(uint4) * (size_t)n_rec, L.sconds_off);
+  zero_tail(L.sconds_off + sizeof(uint32_t) * (size_t)n_conds, L.heads_off);
+  zero_tail(L.heads_off + sizeof(uint4) * (size_t)n_rec, L.total);
+  // about 16k conditions per thread, at most 8 threads
+  const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+  const int parts = (int)std::max<int64_t>(
+      1, std::min<int64_t>({(int64_t)std::min(hw, 8u), (int64_t)n_conds / 16384 + 1,
+                            (int64_t)std::max(p->n_sets, 1)}));
+  std::vector<PackStats> stats(parts);
+  std::vector<int32_t> ffs(parts, 0);
+  run_parts(parts, [&](int i) {
+    // sets split by records, rules by index
+    const int64_t lo_rec = (int64_t)n_rec * i / parts, hi_rec = (int64_t)n_rec * (i + 1) / parts;
+    const int32_t s0 = (int32_t)(std::lower_bound(first.begin(), first.end() - 1, (int32_t)lo_rec) - first.begin());
+    const int32_t s1 = i + 1 == parts ? p->n_sets
+        : (int32_t)(std::lower_bound(first.begin(), first.end() - 1, (int32_t)hi_rec) - first.begin());
+    pack_sets(p, first.data(), s0, s1, sets, ssets, hc, heads, &stats[i]);
+    const int32_t q0 = (int32_t)((int64_t)n_rules * i / parts);
+    const int32_t q1 = (int32_t)((int64_t)n_rules * (i + 1) / parts);
+    pack_rules(p, q0, q1, rules, sc, &ffs[i]);
+  });
+  PackStats all;
   int32_t n_ff = 0;
-  for (int32_t j = 0; j < n_conds; ++j) n_ff += p->kind[j] == AERL_KIND_FEATURE;
+  for (int i = 0; i < parts; ++i) {
+    all.max_rules = std::max(all.max_rules, stats[i].max_rules);
+    all.max_rule_conds = std::max(all.max_rule_conds, stats[i].max_rule_conds);
+    all.max_set_conds = std::max(all.max_set_conds, stats[i].max_set_conds);
+    all.nominal += stats[i].nominal;
+    n_ff += ffs[i];
+  }
+  (void)nf;
+  (void)nc;
+  rec->max_set_conds = all.max_set_conds;
   rec->n_ff = n_ff;
   rec->n_sets = p->n_sets;
   rec->n_rules = n_rules;
   rec->n_conds = n_conds;
   rec->nf = nf;
   rec->nc = nc;
-  rec->max_rules = max_rules;
-  rec->max_rule_conds = max_rule_conds;
-  rec->nominal_conds = nominal;
+  rec->max_rules = all.max_rules;
+  rec->max_rule_conds = all.max_rule_conds;
+  rec->nominal_conds = all.nominal;
 }
 
 }  // namespace aerl

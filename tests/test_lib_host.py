@@ -487,3 +487,24 @@ def test_head_filter_skips_only_rules_that_cannot_fire(aerl, seed):
                 np.testing.assert_array_equal(got, oracle.predict(rows, pop, s), err_msg=f"set {s}")
                 skipped += k
     assert skipped > 0
+
+
+def test_large_population_packs_like_each_set_alone(aerl):
+    """A population large enough to be packed by several host threads (about
+    16k conditions per thread) gives, for every rule set, the same records,
+    head entries and set fields as that rule set packed on its own."""
+    rng = np.random.default_rng(77)
+    x = synth.lognormal_features(rng, 500, 24)
+    pop = synth.random_population(rng, x, 400, (0, 70), (0, 8), 3, 0.3)
+    assert pop.n_conds > 3 * 16384
+    img = aerl.pack_host(pop, 24, 3)
+    sets, hc, hd, nh = decode_packed(img, pop.n_sets, pop.n_rules, pop.n_conds, heads=True)
+    for s in range(0, pop.n_sets, 7):
+        one = pop.subset([s])
+        img1 = aerl.pack_host(one, 24, 3)
+        s1, hc1, hd1, nh1 = decode_packed(img1, 1, one.n_rules, one.n_conds, heads=True)
+        first, count = int(sets[s][0]), int(sets[s][1])
+        assert int(s1[0][1]) == count and nh1[0] == nh[s]
+        assert list(s1[0][2:]) == list(sets[s][2:])
+        np.testing.assert_array_equal(hc[first:first + count], hc1[:count], err_msg=f"set {s}")
+        np.testing.assert_array_equal(hd[first:first + count], hd1[:count], err_msg=f"set {s}")
