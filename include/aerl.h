@@ -84,11 +84,18 @@ const char *aerl_last_error(const aerl_ctx *ctx);
 
 /* ------------------------------------------------------------------ data */
 
+/* Largest sample count a dataset with n_classes classes may hold: the
+ * label-grouped layout pads every class region to a multiple of AERL_TILE
+ * samples and indexes the padded samples with int32, so
+ * (ceil(n / AERL_TILE) + n_classes) * AERL_TILE must stay below 2^31.
+ * Pure host arithmetic; n_classes outside [1, AERL_MAX_CLASSES] gives 0. */
+int64_t aerl_max_samples(int32_t n_classes);
+
 /* Bytes of the caller-allocated device buffer that holds a resident dataset
  * of n samples x f features with n_classes classes (feature-major samples,
  * labels, tile table, tau and upload scratch).  Pure host arithmetic.
- * Errors: AERL_EINVAL (n < 0, f < 1, f > AERL_MAX_FEATURES, n_classes < 1 or
- * > AERL_MAX_CLASSES). */
+ * Errors: AERL_EINVAL (n < 0, n > aerl_max_samples(n_classes), f < 1,
+ * f > AERL_MAX_FEATURES, n_classes < 1 or > AERL_MAX_CLASSES). */
 aerl_status aerl_dataset_bytes(int64_t n, int32_t f, int32_t n_classes, size_t *bytes);
 
 /* Register a labeled dataset (Section 1: fitness is classification
@@ -204,6 +211,25 @@ aerl_status aerl_release_population(aerl_ctx *ctx, int32_t pop_id);
 aerl_status aerl_eval_population(aerl_ctx *ctx, int32_t dataset_id, int32_t pop_id,
                                  int32_t *correct, int32_t *confusion, hipStream_t stream);
 
+/* Launch configuration aerl_eval_population picks for a dataset with the
+ * given per-class sample counts (class_count[n_classes]) and a population of
+ * n_sets rule sets on a GPU with n_cu compute units.  Pure host arithmetic,
+ * the same planner the call runs.
+ *   samples_per_lane, sets_per_chunk, tiles_per_group  as in
+ *                    aerl_eval_population_cfg
+ *   workgroups       one per (chunk of rule sets, group of tiles), in a
+ *                    one-dimensional grid of 1024-thread workgroups
+ * Datasets past 65,535 x 255 tiles take groups of several tiles so that the
+ * grid's work-item count fits 32 bits.  Errors: AERL_EINVAL (bad counts,
+ * a total above aerl_max_samples, n_sets < 0, n_cu < 1, or a grid that
+ * does not fit even with 255-tile groups). */
+typedef struct {
+  int32_t samples_per_lane, sets_per_chunk, tiles_per_group, pad;
+  int64_t workgroups;
+} aerl_eval_launch;
+aerl_status aerl_eval_plan(const int64_t *class_count, int32_t n_classes, int32_t n_features,
+                           int32_t n_sets, int32_t n_cu, aerl_eval_launch *out);
+
 /* aerl_eval_population with an explicit launch configuration (used by the
  * autotuner and by tests that cover every code path):
  *   samples_per_lane  1, 2 or 4 (a wave covers 64*samples_per_lane samples)
@@ -211,7 +237,7 @@ aerl_status aerl_eval_population(aerl_ctx *ctx, int32_t dataset_id, int32_t pop_
  *   tiles_per_group   AERL_TILE-sample tiles per workgroup, 1..255
  * Same outputs, bit for bit, for every valid configuration.  Errors: as
  * aerl_eval_population, plus AERL_EINVAL for a configuration whose LDS
- * footprint does not fit. */
+ * footprint does not fit or whose grid exceeds the launch limit. */
 aerl_status aerl_eval_population_cfg(aerl_ctx *ctx, int32_t dataset_id, int32_t pop_id,
                                      int32_t *correct, int32_t *confusion,
                                      int32_t samples_per_lane, int32_t sets_per_chunk,

@@ -346,15 +346,11 @@ int orc_soft_forward_naive(int64_t n, int32_t nf, const float *x, const int32_t 
  * with a_k = log r_k = sum_j log sigmoid(z_kj), so dL/dz_kj = dL/da_k *
  * sigmoid(-z_kj).  All in log space: U_k = log V_k, l_k = a_k + sum_{m<k}
  * b_m.  A clamped sample (-log P_y > 100) contributes nothing.
- * dz/dc = s x_f / tau_f, dz/dtheta = -s / tau_f, dz/dc2 = -s x_g / tau_f.
- * With absolute != 0 the outputs are instead the sums of the absolute values
- * of the per-sample terms (the scale against which the rounding of a sum of
- * terms of both signs is judged). */
+ * dz/dc = s x_f / tau_f, dz/dtheta = -s / tau_f, dz/dc2 = -s x_g / tau_f. */
 int orc_soft_backward(int64_t n, int32_t nf, const float *x, const int32_t *y, const float *tau,
                       int32_t nc, const orc_population *p, const double *coef,
                       const double *coef2, const double *theta, const double *dloss,
-                      double *dcoef, double *dcoef2, double *dtheta, int nthreads,
-                      int absolute) {
+                      double *dcoef, double *dcoef2, double *dtheta, int nthreads) {
   int32_t n_conds = p->rule_cond_off[p->set_rule_off[p->n_sets]];
   memset(dcoef, 0, sizeof(double) * (size_t)n_conds);
   memset(dcoef2, 0, sizeof(double) * (size_t)n_conds);
@@ -414,7 +410,6 @@ int orc_soft_backward(int64_t n, int32_t nf, const float *x, const int32_t *y, c
             double st = cond_sign(p->op[j]) / (double)tau[f];
             double tc = scale * dz * st * (double)xr[f];
             double t2 = -scale * dz * st * (p->kind[j] ? (double)xr[p->g[j]] : 1.0);
-            if (absolute) { tc = fabs(tc); t2 = fabs(t2); }
             dcoef[j] += tc;
             if (p->kind[j])
               dcoef2[j] += t2;

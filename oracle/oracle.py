@@ -59,7 +59,7 @@ def _load():
             "orc_soft_logprobs": ([I64, I32, P, P, I32, PP, P, P, P, I32, P], C.c_int),
             "orc_soft_forward": ([I64, I32, P, P, P, I32, PP, P, P, P, P, C.c_int], C.c_int),
             "orc_soft_forward_naive": ([I64, I32, P, P, P, I32, PP, P, P, P, P], C.c_int),
-            "orc_soft_backward": ([I64, I32, P, P, P, I32, PP, P, P, P, P, P, P, P, C.c_int, C.c_int], C.c_int),
+            "orc_soft_backward": ([I64, I32, P, P, P, I32, PP, P, P, P, P, P, P, P, C.c_int], C.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(lib, name)
@@ -207,9 +207,8 @@ def soft_forward_naive(x, y, tau_, n_classes, pop, coef=None, coef2=None, theta=
 
 
 def soft_backward(x, y, tau_, n_classes, pop, dloss=None, coef=None, coef2=None, theta=None,
-                  nthreads=0, absolute=False):
-    """fp64 gradients (dcoef, dcoef2, dtheta) of sum_s dloss[s] * loss[s].
-    absolute=True returns the sums of |per-sample terms| instead."""
+                  nthreads=0):
+    """fp64 gradients (dcoef, dcoef2, dtheta) of sum_s dloss[s] * loss[s]."""
     x, y = _xy(x, y)
     v = _PopView(pop)
     c1, c2, th = _params(pop, coef, coef2, theta)
@@ -220,6 +219,6 @@ def soft_backward(x, y, tau_, n_classes, pop, dloss=None, coef=None, coef2=None,
     g3 = np.zeros(v.n_conds, np.float64)
     rc = _load().orc_soft_backward(x.shape[0], x.shape[1], _ptr(x), _ptr(y), _ptr(t), n_classes,
                                    v.ref(), _ptr(c1), _ptr(c2), _ptr(th), _ptr(dl), _ptr(g1),
-                                   _ptr(g2), _ptr(g3), nthreads, int(absolute))
+                                   _ptr(g2), _ptr(g3), nthreads)
     assert rc == 0
     return g1, g2, g3

@@ -50,6 +50,11 @@ class aerl_dataset_info(C.Structure):
                 ("tau", C.c_void_p)]
 
 
+class aerl_eval_launch(C.Structure):
+    _fields_ = [("samples_per_lane", C.c_int32), ("sets_per_chunk", C.c_int32),
+                ("tiles_per_group", C.c_int32), ("pad", C.c_int32), ("workgroups", C.c_int64)]
+
+
 class aerl_batch_item(C.Structure):
     _fields_ = [("dataset_id", C.c_int32), ("pop_id", C.c_int32),
                 ("correct", C.c_void_p), ("confusion", C.c_void_p)]
@@ -99,6 +104,8 @@ _SIGS = {
     "aerl_create": ([C.POINTER(C.c_void_p), C.c_int], _I32),
     "aerl_destroy": ([_P], None),
     "aerl_last_error": ([_P], C.c_char_p),
+    "aerl_max_samples": ([_I32], _I64),
+    "aerl_eval_plan": ([C.POINTER(_I64), _I32, _I32, _I32, _I32, C.POINTER(aerl_eval_launch)], _I32),
     "aerl_dataset_bytes": ([_I64, _I32, _I32, C.POINTER(_SZ)], _I32),
     "aerl_upload_dataset": ([_P, _P, _P, _I64, _I32, _I32, _P, _SZ, _P, C.POINTER(_I32)], _I32),
     "aerl_dataset_query": ([_P, _I32, C.POINTER(aerl_dataset_info)], _I32),
@@ -147,6 +154,23 @@ def _ptr(t) -> Optional[int]:
 def _stream(stream=None) -> int:
     s = stream if stream is not None else torch.cuda.current_stream()
     return s.cuda_stream
+
+
+def max_samples(n_classes: int) -> int:
+    """Largest sample count a dataset of n_classes classes may hold."""
+    return int(aerl_max_samples(n_classes))
+
+
+def eval_plan(class_count, n_features: int, n_sets: int, n_cu: int = 256) -> dict:
+    """Launch configuration the hard evaluation picks (host arithmetic only)."""
+    cc = np.ascontiguousarray(class_count, dtype=np.int64)
+    out = aerl_eval_launch()
+    st = aerl_eval_plan(cc.ctypes.data_as(C.POINTER(_I64)), len(cc), n_features, n_sets, n_cu,
+                        C.byref(out))
+    if st != AERL_OK:
+        raise AerlError(st, "no launch configuration")
+    return dict(samples_per_lane=out.samples_per_lane, sets_per_chunk=out.sets_per_chunk,
+                tiles_per_group=out.tiles_per_group, workgroups=out.workgroups)
 
 
 def pack_host(pop: Population, n_features: int, n_classes: int) -> np.ndarray:

@@ -8,6 +8,7 @@
 // persistent grid's dynamic pull ends evenly.
 #include <algorithm>
 #include <chrono>
+#include <climits>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -223,6 +224,11 @@ aerl_status resolve_split(aerl_ctx *ctx, const std::vector<ItemView> &v, const a
   sp->Q = q;
   sp->TG = tg;
   sp->tile_budget = (size_t)kib * 1024;
+  // work items are counted and indexed with int32 on the device
+  int64_t tasks = 0;
+  for (const auto &e : v) tasks += batch_task_count(*e.ds, e.pop->n_sets, *sp);
+  if (tasks > INT32_MAX)
+    return fail(ctx, AERL_EINVAL, "%lld work items exceed 2^31 - 1; raise tiles_per_task", (long long)tasks);
   return AERL_OK;
 }
 
@@ -362,6 +368,9 @@ aerl_status aerl_autotune(aerl_ctx *ctx, const aerl_batch_item *items, int32_t n
         sp.Q = q;
         sp.TG = tg;
         sp.tile_budget = (size_t)kib * 1024;
+        int64_t tasks = 0;
+        for (const auto &e : v) tasks += batch_task_count(*e.ds, e.pop->n_sets, sp);
+        if (tasks > INT32_MAX) continue;
         BatchTables b;
         build_batch_tables(sources(v), sp, &b);
         if (b.lds > kBatchLdsMax) continue;

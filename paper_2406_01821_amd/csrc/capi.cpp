@@ -2,6 +2,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
+#include <climits>
 #include <cstring>
 
 #include "internal.h"
@@ -48,12 +49,30 @@ DatasetMem dataset_mem(int64_t n, int32_t nf, int32_t nc) {
 }
 
 aerl_status check_dataset_args(aerl_ctx *ctx, int64_t n, int32_t nf, int32_t nc) {
-  if (n < 0 || n > (int64_t)1 << 31) return fail(ctx, AERL_EINVAL, "n = %lld outside [0, 2^31]", (long long)n);
   if (nf < 1 || nf > AERL_MAX_FEATURES)
     return fail(ctx, AERL_EINVAL, "n_features %d outside [1, %d]", nf, AERL_MAX_FEATURES);
   if (nc < 1 || nc > AERL_MAX_CLASSES)
     return fail(ctx, AERL_EINVAL, "n_classes %d outside [1, %d]", nc, AERL_MAX_CLASSES);
+  // Slots of the label-grouped layout (original indices, scatter bases) are
+  // int32: the padded sample count must stay below 2^31.
+  if (n < 0 || n > aerl_max_samples(nc))
+    return fail(ctx, AERL_EINVAL, "n = %lld outside [0, %lld] for %d classes", (long long)n,
+                (long long)aerl_max_samples(nc), nc);
   return AERL_OK;
+}
+
+// Class regions of the label-grouped layout from the per-class counts
+// (d.nc set): each region padded to whole tiles, in class order.
+void set_regions(DatasetRec &d, const int64_t *counts) {
+  int64_t tile = 0;
+  for (int c = 0; c < d.nc; ++c) {
+    d.class_count[c] = counts[c];
+    d.region_tile0[c] = (int32_t)tile;
+    d.region_tiles[c] = (int32_t)((counts[c] + AERL_TILE - 1) / AERL_TILE);
+    tile += d.region_tiles[c];
+  }
+  d.n_tiles = tile;
+  d.n_pad = tile * AERL_TILE;
 }
 
 // RAII pinned host buffer.
@@ -93,7 +112,12 @@ void hard_config(const DatasetRec &ds, int32_t n_sets, int n_cu, int *S, int *Q,
   // equal chunks (a short last chunk leaves its blocks underused)
   const int chunks = (std::max<int32_t>(n_sets, 1) + q - 1) / q;
   *Q = (std::max<int32_t>(n_sets, 1) + chunks - 1) / chunks;
-  *TG = 1;
+  // Single-tile groups (measured fastest: larger groups leave a partly
+  // filled last round of blocks), unless the grid would exceed the launch
+  // limit; then the fewest tiles per group that fit it.
+  int tg = 1;
+  while (tg < kMaxTilesPerBlock && hard_block_count(ds, *Q, n_sets, tg) > kMaxHardBlocks) ++tg;
+  *TG = tg;
 }
 
 }  // namespace
@@ -136,6 +160,12 @@ void aerl_destroy(aerl_ctx *ctx) {
 }
 
 const char *aerl_last_error(const aerl_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int64_t aerl_max_samples(int32_t n_classes) {
+  if (n_classes < 1 || n_classes > AERL_MAX_CLASSES) return 0;
+  const int64_t tiles = (int64_t)INT32_MAX / AERL_TILE;  // whole padded tiles below 2^31
+  return (tiles - n_classes) * AERL_TILE;
+}
 
 aerl_status aerl_dataset_bytes(int64_t n, int32_t f, int32_t n_classes, size_t *bytes) {
   if (!bytes) return AERL_EINVAL;
@@ -193,27 +223,23 @@ aerl_status aerl_upload_dataset(aerl_ctx *ctx, const float *x, const int32_t *y,
   if (h_flags[1]) return fail(ctx, AERL_EINVAL, "y holds a label outside [0, %d)", nc);
 
   // Class regions, each padded to whole tiles, in class order.
-  int64_t tile = 0;
+  int64_t counts[AERL_MAX_CLASSES] = {};
+  for (int c = 0; c < nc; ++c)
+    for (int64_t b = 0; b < M.n_blocks; ++b) counts[c] += h_counts[b * nc + c];
+  set_regions(d, counts);
+  if (d.n_pad > M.n_pad_max) return fail(ctx, AERL_EINVAL, "internal: layout overflow");
   for (int c = 0; c < nc; ++c) {
-    int64_t cnt = 0;
-    for (int64_t b = 0; b < M.n_blocks; ++b) cnt += h_counts[b * nc + c];
-    d.class_count[c] = cnt;
-    d.region_tile0[c] = (int32_t)tile;
-    d.region_tiles[c] = (int32_t)((cnt + AERL_TILE - 1) / AERL_TILE);
+    const int64_t tile = d.region_tile0[c];
     for (int64_t t = 0; t < d.region_tiles[c]; ++t) {
-      const int64_t valid = std::min<int64_t>(AERL_TILE, cnt - t * AERL_TILE);
+      const int64_t valid = std::min<int64_t>(AERL_TILE, counts[c] - t * AERL_TILE);
       h_tiles[tile + t] = c | (int32_t)(valid << 8);
     }
-    int64_t run = (int64_t)d.region_tile0[c] * AERL_TILE;
+    int64_t run = tile * AERL_TILE;
     for (int64_t b = 0; b < M.n_blocks; ++b) {
       h_base[b * nc + c] = (int32_t)run;
       run += h_counts[b * nc + c];
     }
-    tile += d.region_tiles[c];
   }
-  d.n_tiles = tile;
-  d.n_pad = tile * AERL_TILE;
-  if (d.n_pad > M.n_pad_max) return fail(ctx, AERL_EINVAL, "internal: layout overflow");
   // The x_fm rows use stride n_pad.
   if (d.n_tiles) AERL_HIP(ctx, hipMemcpyAsync(d.tile_info, h_tiles, (size_t)d.n_tiles * 4, hipMemcpyHostToDevice, stream));
   if (nbc) AERL_HIP(ctx, hipMemcpyAsync(base_dev, h_base, nbc * 4, hipMemcpyHostToDevice, stream));
@@ -369,10 +395,42 @@ static aerl_status eval_common(aerl_ctx *ctx, int32_t dataset_id, int32_t pop_id
     h.sets_per_chunk = Q;
     h.tiles_per_group = TG;
   }
+  if (hard_block_count(ds, h.sets_per_chunk, pop.n_sets, h.tiles_per_group) > kMaxHardBlocks)
+    return fail(ctx, AERL_EINVAL, "%lld workgroups exceed the launch limit %lld; raise tiles_per_group",
+                (long long)hard_block_count(ds, h.sets_per_chunk, pop.n_sets, h.tiles_per_group),
+                (long long)kMaxHardBlocks);
   AERL_HIP(ctx, hipSetDevice(ctx->device));
   AERL_HIP(ctx, launch_fill_i32(correct, pop.n_sets, 0, stream));
   if (confusion) AERL_HIP(ctx, launch_fill_i32(confusion, (int64_t)pop.n_sets * ds.nc * ds.nc, 0, stream));
   AERL_HIP(ctx, launch_hard_eval(h, stream));
+  return AERL_OK;
+}
+
+aerl_status aerl_eval_plan(const int64_t *class_count, int32_t n_classes, int32_t n_features,
+                           int32_t n_sets, int32_t n_cu, aerl_eval_launch *out) {
+  if (!class_count || !out || n_sets < 0 || n_cu < 1) return AERL_EINVAL;
+  int64_t n = 0;
+  for (int c = 0; c < std::max(n_classes, 0) && c < AERL_MAX_CLASSES; ++c) {
+    if (class_count[c] < 0) return AERL_EINVAL;
+    n += class_count[c];
+    if (n > INT32_MAX) return AERL_EINVAL;
+  }
+  aerl_status st = check_dataset_args(nullptr, n, n_features, n_classes);
+  if (st) return st;
+  DatasetRec d;
+  d.n = n;
+  d.nf = n_features;
+  d.nc = n_classes;
+  set_regions(d, class_count);
+  int S = 0, Q = 0, TG = 0;
+  hard_config(d, n_sets, n_cu, &S, &Q, &TG);
+  const int64_t blocks = hard_block_count(d, Q, n_sets, TG);
+  if (blocks > kMaxHardBlocks) return AERL_EINVAL;
+  out->samples_per_lane = S;
+  out->sets_per_chunk = Q;
+  out->tiles_per_group = TG;
+  out->pad = 0;
+  out->workgroups = blocks;
   return AERL_OK;
 }
 
@@ -399,7 +457,7 @@ aerl_status aerl_predict(aerl_ctx *ctx, int32_t pop_id, int32_t set, const float
   if (pi == ctx->pops.end()) return fail(ctx, AERL_ENOENT, "unknown population %d", pop_id);
   const PopRec &pop = pi->second;
   if (set < 0 || set >= pop.n_sets) return fail(ctx, AERL_EINVAL, "set %d outside [0, %d)", set, pop.n_sets);
-  if (n < 0) return fail(ctx, AERL_EINVAL, "n < 0");
+  if (n < 0 || n > INT32_MAX) return fail(ctx, AERL_EINVAL, "n = %lld outside [0, 2^31)", (long long)n);
   if (n > 0 && (!rows || !pred)) return fail(ctx, AERL_EINVAL, "rows or pred is NULL");
   AERL_HIP(ctx, hipSetDevice(ctx->device));
   AERL_HIP(ctx, launch_predict(pop, set, rows, n, pred, stream));
@@ -431,6 +489,9 @@ static aerl_status soft_common(aerl_ctx *ctx, int32_t dataset_id, int32_t pop_id
     return fail(ctx, AERL_EINVAL, "population and dataset shapes differ");
   if (pop.n_conds > 0 && (!l->coef || !l->coef2 || !l->theta))
     return fail(ctx, AERL_EINVAL, "a parameter array is NULL");
+  if ((int64_t)pop.n_sets > kMaxHardBlocks)
+    return fail(ctx, AERL_EINVAL, "%d rule sets exceed the soft kernels' launch limit %lld", pop.n_sets,
+                (long long)kMaxHardBlocks);
   if (backward && !soft_backward_supported(ds, pop))
     return fail(ctx, AERL_EINVAL, "rule sets of %d rules exceed the adjoint kernel's LDS", pop.max_rules);
   const size_t need = soft_ws_bytes(ds, pop, backward);

@@ -35,7 +35,7 @@ struct HardArgs {
   int32_t set_begin, set_count;
   int32_t *correct;
   int32_t *confusion;
-  int32_t sets_per_chunk, tiles_per_group;
+  int32_t sets_per_chunk, tiles_per_group, n_chunks;
   int32_t region_tile0[AERL_MAX_CLASSES];
   int32_t region_tiles[AERL_MAX_CLASSES];
 };
@@ -58,8 +58,12 @@ __global__ __launch_bounds__(kHardBlock) AERL_HARD_SGPR_CAP void k_hard(const Ha
   t.confusion = a.confusion;
   t.label = 0;
   t.tile_lo = t.tile_hi = 0;
+  // one-dimensional grid, set chunk fastest: consecutive blocks share a tile
+  // group, and (blocks being spread over the XCDs in turn) an XCD keeps
+  // seeing the same chunk's records when the chunk count divides eight
+  const int chunk = (int)(blockIdx.x % (unsigned)a.n_chunks);
   {
-    int g = blockIdx.y;
+    int g = (int)(blockIdx.x / (unsigned)a.n_chunks);
     for (int c = 0; c < a.nc; ++c) {
       const int ng = (a.region_tiles[c] + a.tiles_per_group - 1) / a.tiles_per_group;
       if (g < ng) {
@@ -71,7 +75,7 @@ __global__ __launch_bounds__(kHardBlock) AERL_HARD_SGPR_CAP void k_hard(const Ha
       g -= ng;
     }
   }
-  t.q0 = blockIdx.x * a.sets_per_chunk;
+  t.q0 = chunk * a.sets_per_chunk;
   t.Q = min(a.sets_per_chunk, a.set_count - t.q0);
   hard_block<S>(t, smem, &next_q);
 }
@@ -113,18 +117,19 @@ hipError_t launch_hard_eval(const HardLaunch &h, hipStream_t st) {
   a.confusion = h.confusion;
   a.sets_per_chunk = h.sets_per_chunk;
   a.tiles_per_group = h.tiles_per_group;
-  int64_t n_groups = 0;
   for (int c = 0; c < ds.nc; ++c) {
     a.region_tile0[c] = ds.region_tile0[c];
     a.region_tiles[c] = ds.region_tiles[c];
-    n_groups += (ds.region_tiles[c] + h.tiles_per_group - 1) / h.tiles_per_group;
   }
+  if (h.tiles_per_group < 1 || h.tiles_per_group > kMaxTilesPerBlock || h.sets_per_chunk < 1)
+    return hipErrorInvalidValue;
+  const int64_t n_groups = hard_group_count(ds, h.tiles_per_group);
   if (n_groups == 0) return hipSuccess;
   const int64_t n_chunks = (h.set_count + h.sets_per_chunk - 1) / h.sets_per_chunk;
-  if (h.tiles_per_group > kMaxTilesPerBlock) return hipErrorInvalidValue;
   const size_t lds = hard_block_lds(ds.nf, h.samples_per_lane, h.sets_per_chunk, ds.nc);
-  if (lds > kDynLdsMax || n_groups > 65535 || n_chunks > 0x7fffffff) return hipErrorInvalidValue;
-  const dim3 grid((unsigned)n_chunks, (unsigned)n_groups);
+  if (lds > kDynLdsMax || n_chunks * n_groups > kMaxHardBlocks) return hipErrorInvalidValue;
+  a.n_chunks = (int32_t)n_chunks;
+  const dim3 grid((unsigned)(n_chunks * n_groups));
   switch (h.samples_per_lane) {
     case 4: return hard_dispatch<4>(a, grid, lds, st);
     case 2: return hard_dispatch<2>(a, grid, lds, st);

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <array>
 #include <cstdint>
 #include <cstdio>
@@ -179,6 +180,20 @@ struct HardLaunch {
   int tiles_per_group;           // layout tiles per block
 };
 hipError_t launch_hard_eval(const HardLaunch &h, hipStream_t s);
+// Workgroups of a hard-eval launch: one per (set chunk, tile group), in a
+// one-dimensional grid of 1024-thread blocks whose work-item count must fit
+// 32 bits.
+constexpr int64_t kMaxHardBlocks = (((int64_t)1 << 32) - 1) / 1024;
+inline int64_t hard_group_count(const DatasetRec &ds, int tiles_per_group) {
+  int64_t g = 0;
+  for (int c = 0; c < ds.nc; ++c) g += (ds.region_tiles[c] + tiles_per_group - 1) / tiles_per_group;
+  return g;
+}
+inline int64_t hard_block_count(const DatasetRec &ds, int sets_per_chunk, int32_t n_sets,
+                                int tiles_per_group) {
+  const int64_t chunks = ((int64_t)std::max<int32_t>(n_sets, 0) + sets_per_chunk - 1) / sets_per_chunk;
+  return chunks * hard_group_count(ds, tiles_per_group);
+}
 
 hipError_t launch_predict(const PopRec &pop, int32_t set, const float *rows, int64_t n,
                           int32_t *pred, hipStream_t s);

@@ -1,12 +1,12 @@
 """GPU parity of the soft (sigmoid-relaxed) path against the fp64 oracle:
 loss within 1e-5 relative per rule set (plus 1e-6 absolute: a loss that is
-exactly 0 in fp64 comes out as a few fp32 roundings); gradients within 1e-4
-relative, plus 1e-5 of the sum of the absolute per-sample terms (each fp32
-term carries ~1e-6 relative rounding, and a gradient whose terms cancel across
-samples cannot meet a purely relative bound), plus 1e-7 of the largest entry
-of the same gradient array (fp32 resolution at that array's scale; entries such
-as 1e-50 are not representable in fp32 at all); finite differences on a 64 x 8
-subproblem; determinism; the autograd wrapper."""
+exactly 0 in fp64 comes out as a few fp32 roundings); every gradient entry
+within 1e-4 relative of the fp64 value, with a floor of 1e-3 of the largest
+entry of the same array: |g - g64| <= 1e-4 * max(|g64|, 1e-3 * max|g64|)
+(entries that cancel to almost nothing across many samples cannot meet a
+purely relative bound in fp32).  Each check reports the largest fraction of
+the bound it used; finite differences on a 64 x 8 subproblem with steps of
+1e-6 tau; determinism; the autograd wrapper."""
 import numpy as np
 import pytest
 
@@ -19,8 +19,7 @@ pytestmark = pytest.mark.gpu
 LOSS_RTOL = 1e-5
 LOSS_ATOL = 1e-6
 GRAD_RTOL = 1e-4
-GRAD_ABS_SCALE = 1e-5
-GRAD_ARRAY_FLOOR = 1e-7
+GRAD_FLOOR = 1e-3   # of the largest |entry| of the same gradient array
 
 
 @pytest.fixture(scope="module")
@@ -57,12 +56,24 @@ def check_loss(got, ref):
     assert not bad.any(), (np.nonzero(bad)[0], got[bad], ref[bad])
 
 
-def check_grad(got, ref, ref_abs):
-    for k, (g, r, ra) in enumerate(zip(got, ref, ref_abs)):
-        floor = GRAD_ARRAY_FLOOR * np.abs(r).max() if r.size else 0.0
-        bound = GRAD_RTOL * np.abs(r) + GRAD_ABS_SCALE * ra + floor
-        bad = np.abs(g - r) > bound
-        assert not bad.any(), (k, np.nonzero(bad)[0][:10], g[bad][:5], r[bad][:5], ra[bad][:5])
+def check_grad(got, ref):
+    """Elementwise |g - g64| <= 1e-4 * max(|g64|, 1e-3 * max|g64|) for each of
+    (dcoef, dcoef2, dtheta); returns the largest fraction of the bound used."""
+    used = 0.0
+    for k, (g, r) in enumerate(zip(got, ref)):
+        if r.size == 0:
+            continue
+        scale = np.abs(r).max()
+        if scale == 0.0:
+            assert np.all(g == 0.0), (k, np.abs(g).max())
+            continue
+        bound = GRAD_RTOL * np.maximum(np.abs(r), GRAD_FLOOR * scale)
+        frac = np.abs(g - r) / bound
+        bad = frac > 1.0
+        assert not bad.any(), (k, np.nonzero(bad)[0][:10], g[bad][:5], r[bad][:5], frac.max())
+        used = max(used, float(frac.max()))
+    print(f"gradient bound used: {used:.3f}")
+    return used
 
 
 def run_case(ctx, data, pop, dloss=None):
@@ -72,8 +83,7 @@ def run_case(ctx, data, pop, dloss=None):
     check_loss(loss, ref)
     dl = np.ones(pop.n_sets) if dloss is None else dloss
     rg = oracle.soft_backward(data.x, data.y, tau, data.n_classes, pop, dloss=dl)
-    ra = oracle.soft_backward(data.x, data.y, tau, data.n_classes, pop, dloss=dl, absolute=True)
-    check_grad(grads, rg, ra)
+    check_grad(grads, rg)
 
 
 def test_soft_workload_shape_small(ctx):
@@ -130,7 +140,8 @@ def test_degenerate_rules_empty_sets_and_clamp(ctx):
 
 def test_finite_differences_64x8(ctx):
     """Gradient against fp64 central differences of the oracle's loss on a
-    64-sample x 8-feature subproblem (tau from the subproblem itself)."""
+    64-sample x 8-feature subproblem (tau from the subproblem itself), steps
+    h = 1e-6 tau_f for theta and 1e-6 tau_f / mean|x_f| for coefficients."""
     w = synth.tiny(31, n=64, nf=8, n_sets=6, rules=(1, 5), conds=(1, 3), ff_frac=0.3)
     x, y, pop = w.data.x, w.data.y, w.pop
     loss, grads = gpu_soft(ctx, w.data, pop)
@@ -145,14 +156,13 @@ def test_finite_differences_64x8(ctx):
     for j in range(pop.n_conds):
         f = pop.f[j]
         for k in ([0, 1] if pop.kind[j] else [0, 2]):
-            h = 1e-4 * float(tau[f]) / (meanabs[pop.g[j] if k == 1 else f] if k < 2 else 1.0)
+            h = 1e-6 * float(tau[f]) / (meanabs[pop.g[j] if k == 1 else f] if k < 2 else 1.0)
             plus = [b.copy() for b in base]
             minus = [b.copy() for b in base]
             plus[k][j] += h
             minus[k][j] -= h
             fd[k][j] = (total(plus) - total(minus)) / (2 * h)
-    ra = oracle.soft_backward(x, y, tau, 2, pop, absolute=True)
-    check_grad(grads, fd, ra)
+    check_grad(grads, fd)
 
 
 def test_deterministic_repeats(ctx):
@@ -183,24 +193,22 @@ def test_autograd_function(ctx):
     tau = oracle.tau(w.data.x)
     dl = wts.cpu().numpy().astype(np.float64)
     rg = oracle.soft_backward(w.data.x, w.data.y, tau, 2, w.pop, dloss=dl)
-    ra = oracle.soft_backward(w.data.x, w.data.y, tau, 2, w.pop, dloss=dl, absolute=True)
     check_grad([c1.grad.cpu().numpy().astype(np.float64), c2.grad.cpu().numpy().astype(np.float64),
-                th.grad.cpu().numpy().astype(np.float64)], rg, ra)
+                th.grad.cpu().numpy().astype(np.float64)], rg)
 
 
 def test_full_size_sampled_sets(ctx):
     """262,144 x 32, 1024 rule sets x 16 rules x 4 conditions, in the launch
-    configuration the benchmark times; 8 sampled rule sets are recomputed by
-    the oracle."""
+    configuration the benchmark times; 64 sampled rule sets are recomputed
+    by the oracle."""
     import torch
     w = synth.soft_workload(3)
     loss, grads = gpu_soft(ctx, w.data, w.pop)
-    sample = np.random.default_rng(1).choice(w.pop.n_sets, 8, replace=False)
+    sample = np.random.default_rng(1).choice(w.pop.n_sets, 64, replace=False)
     sub = w.pop.subset(sample)
     tau = oracle.tau(w.data.x)
     check_loss(loss[sample], oracle.soft_forward(w.data.x, w.data.y, tau, 2, sub))
     rg = oracle.soft_backward(w.data.x, w.data.y, tau, 2, sub)
-    ra = oracle.soft_backward(w.data.x, w.data.y, tau, 2, sub, absolute=True)
     idx = np.concatenate([np.arange(w.pop.rule_cond_off[w.pop.set_rule_off[s]],
                                     w.pop.rule_cond_off[w.pop.set_rule_off[s + 1]]) for s in sample])
-    check_grad([g[idx] for g in grads], rg, ra)
+    check_grad([g[idx] for g in grads], rg)

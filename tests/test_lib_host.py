@@ -22,7 +22,7 @@ def aerl():
 
 def header_symbols():
     text = open(os.path.join(ROOT, "include", "aerl.h")).read()
-    return sorted(set(re.findall(r"^\s*(?:aerl_status|void|const char \*)\s*(aerl_\w+)\(", text, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:aerl_status|void|int64_t|const char \*)\s*(aerl_\w+)\(", text, re.M)))
 
 
 def test_library_exports_every_declared_symbol(aerl):
@@ -44,6 +44,46 @@ def test_dataset_bytes_validation(aerl):
     assert aerl.aerl_dataset_bytes(10, 513, 2, C.byref(out)) == aerl.AERL_EINVAL
     assert aerl.aerl_dataset_bytes(10, 4, 65, C.byref(out)) == aerl.AERL_EINVAL
     assert aerl.aerl_dataset_bytes(0, 4, 2, C.byref(out)) == 0
+
+
+def test_sample_limit_keeps_the_padded_layout_in_int32(aerl):
+    """The label-grouped layout pads every class region to whole 256-sample
+    tiles and indexes the padded samples with int32: the largest accepted n
+    pads to at most 2^31 - 1 samples, one more sample is refused (host
+    arithmetic only; nothing of that size is allocated)."""
+    import ctypes as C
+    out = C.c_size_t()
+    for nc in (1, 2, 4, 64):
+        m = aerl.max_samples(nc)
+        assert ((m + 255) // 256 + nc) * 256 <= 2**31 - 1
+        assert ((m + 1 + 255) // 256 + nc) * 256 > 2**31 - 1
+        assert aerl.aerl_dataset_bytes(m, 1, nc, C.byref(out)) == 0
+        assert aerl.aerl_dataset_bytes(m + 1, 1, nc, C.byref(out)) == aerl.AERL_EINVAL
+    # the case where a 2^31-sample upload's last class base wrapped to INT32_MIN
+    assert aerl.aerl_dataset_bytes(2**31, 1, 2, C.byref(out)) == aerl.AERL_EINVAL
+    assert aerl.max_samples(0) == 0 and aerl.max_samples(65) == 0
+
+
+@pytest.mark.parametrize("counts", [[569 - 212, 212], [1 << 18] * 4, [(1 << 24) + 1000, 7],
+                                    [(1 << 30) - 300_000, (1 << 30) - 3], [(1 << 31) - 300_000, 1]])
+def test_hard_launch_plan_fits_the_grid(aerl, counts):
+    """The planner's one-dimensional grid (one 1024-thread workgroup per set
+    chunk and tile group) keeps its work-item count within 32 bits for every
+    dataset size up to the sample limit, and covers every tile."""
+    tiles = sum((c + 255) // 256 for c in counts)
+    for n_sets in (1, 100, 4096, 100_000):
+        p = aerl.eval_plan(counts, 8, n_sets, 256)
+        assert p["samples_per_lane"] in (1, 2, 4)
+        assert 1 <= p["tiles_per_group"] <= 255
+        groups = sum(-(-((c + 255) // 256) // p["tiles_per_group"]) for c in counts)
+        chunks = -(-n_sets // p["sets_per_chunk"])
+        assert p["workgroups"] == groups * chunks
+        assert p["workgroups"] * 1024 <= 2**32 - 1
+        assert groups * p["tiles_per_group"] >= tiles
+        if tiles * chunks * 1024 <= 2**32 - 1:
+            assert p["tiles_per_group"] == 1  # single tiles while they fit
+    with pytest.raises(aerl.AerlError):
+        aerl.eval_plan([aerl.max_samples(2), 300], 8, 10, 256)
 
 
 def _cond(**kw):

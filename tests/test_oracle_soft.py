@@ -176,16 +176,3 @@ def test_clamped_samples_have_zero_gradient():
     assert oracle.soft_forward(x, y, tau, 2, pop)[0] == 100.0
     g = oracle.soft_backward(x, y, tau, 2, pop)
     assert g[0][0] == 0 and g[2][0] == 0
-
-
-def test_absolute_gradient_bounds_the_gradient(sub):
-    """sum |terms| >= |sum terms|, with equality for a single sample."""
-    w, tau = sub
-    g = oracle.soft_backward(w.data.x, w.data.y, tau, 2, w.pop)
-    ga = oracle.soft_backward(w.data.x, w.data.y, tau, 2, w.pop, absolute=True)
-    for a, b in zip(g, ga):
-        assert np.all(b >= np.abs(a) - 1e-15) and np.all(b >= 0)
-    g1 = oracle.soft_backward(w.data.x[:1], w.data.y[:1], tau, 2, w.pop)
-    ga1 = oracle.soft_backward(w.data.x[:1], w.data.y[:1], tau, 2, w.pop, absolute=True)
-    for a, b in zip(g1, ga1):
-        np.testing.assert_allclose(np.abs(a), b, rtol=1e-14, atol=0)
