@@ -447,6 +447,25 @@ aerl_status aerl_soft_backward(aerl_ctx *ctx, int32_t dataset_id, int32_t pop_id
                                const float *dloss, float *dcoef, float *dcoef2, float *dtheta,
                                void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* aerl_soft_forward for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same kernels and the same results, bit for bit, with the
+ * per-block partial sums and condition records kept in a scratch array the
+ * library holds in device memory, one per GPU, AERL_NOALLOC_SCRATCH_BYTES
+ * long, from the GPU's first aerl_create until the process ends.  The
+ * caller passes inputs and outputs only.  The call allocates nothing
+ * (no hipMalloc, no library allocation).  Every call on a GPU shares that
+ * GPU's array: calls that overlap on one GPU (concurrent streams, threads
+ * or contexts) race and must be serialized by the caller; a call's
+ * partial sums are overwritten by the next call.  Errors: AERL_ENOMEM when
+ * the call would need more than AERL_NOALLOC_SCRATCH_BYTES of scratch
+ * (aerl_soft_workspace_bytes' forward_bytes), otherwise as
+ * aerl_soft_forward. */
+#define AERL_NOALLOC_SCRATCH_BYTES ((size_t)16 << 20)
+aerl_status aerl_soft_forward_noalloc(aerl_ctx *ctx, int32_t dataset_id, int32_t pop_id,
+                                      const float *coef, const float *coef2, const float *theta,
+                                      float *loss, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

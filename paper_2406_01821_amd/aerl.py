@@ -25,6 +25,7 @@ AERL_OK, AERL_EINVAL, AERL_ENOMEM, AERL_EDEVICE, AERL_ENOENT = 0, -1, -2, -3, -4
 AERL_EAGAIN, AERL_ETIMEDOUT, AERL_ESTATE = -5, -6, -7
 AERL_MAX_CLASSES = 64
 AERL_TILE = 256
+AERL_NOALLOC_SCRATCH_BYTES = 16 << 20
 STATUS_NAMES = {0: "AERL_OK", -1: "AERL_EINVAL", -2: "AERL_ENOMEM", -3: "AERL_EDEVICE",
                 -4: "AERL_ENOENT", -5: "AERL_EAGAIN", -6: "AERL_ETIMEDOUT", -7: "AERL_ESTATE"}
 
@@ -134,6 +135,7 @@ _SIGS = {
     "aerl_soft_workspace_bytes": ([_P, _I32, _I32, C.POINTER(_SZ), C.POINTER(_SZ)], _I32),
     "aerl_soft_forward": ([_P, _I32, _I32, _P, _P, _P, _P, _P, _SZ, _P], _I32),
     "aerl_soft_backward": ([_P, _I32, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _SZ, _P], _I32),
+    "aerl_soft_forward_noalloc": ([_P, _I32, _I32, _P, _P, _P, _P, _P], _I32),
 }
 for _name, (_args, _res) in _SIGS.items():
     _fn = getattr(lib, _name)
@@ -427,6 +429,13 @@ class Context:
         loss = torch.empty(pop.n_sets, dtype=torch.float32, device=self.device)
         self.check(aerl_soft_forward(self.h, ds.id, pop.id, _ptr(coef), _ptr(coef2), _ptr(theta),
                                      _ptr(loss), _ptr(ws), ws.numel(), _stream(stream)))
+        return loss
+
+    def soft_forward_noalloc(self, ds, pop, coef, coef2, theta, loss, stream=None):
+        """Soft forward into the caller's ``loss`` tensor using the library's
+        per-GPU scratch array (no device allocation in the call)."""
+        self.check(aerl_soft_forward_noalloc(self.h, ds.id, pop.id, _ptr(coef), _ptr(coef2),
+                                             _ptr(theta), _ptr(loss), _stream(stream)))
         return loss
 
     def soft_backward(self, ds, pop, coef, coef2, theta, dloss, ws=None, stream=None):

@@ -138,7 +138,8 @@ aerl_status aerl_create(aerl_ctx **out, int device_ordinal) {
   ctx->device = device_ordinal;
   if (hipSetDevice(device_ordinal) != hipSuccess ||
       hipDeviceGetAttribute(&ctx->n_cu, hipDeviceAttributeMultiprocessorCount, device_ordinal) !=
-          hipSuccess) {
+          hipSuccess ||
+      noalloc_scratch(device_ordinal, &ctx->noalloc_scratch) != hipSuccess) {
     delete ctx;
     return AERL_EDEVICE;
   }
@@ -511,6 +512,34 @@ aerl_status aerl_soft_forward(aerl_ctx *ctx, int32_t dataset_id, int32_t pop_id,
   ctx->err.clear();
   SoftLaunch l{};
   l.coef = coef; l.coef2 = coef2; l.theta = theta; l.loss = loss; l.ws = ws; l.ws_bytes = ws_bytes;
+  aerl_status st = soft_common(ctx, dataset_id, pop_id, &l, false);
+  if (st) return st;
+  if (!loss && l.pop->n_sets > 0) return fail(ctx, AERL_EINVAL, "loss is NULL");
+  AERL_HIP(ctx, hipSetDevice(ctx->device));
+  AERL_HIP(ctx, launch_soft_forward(l, stream));
+  return AERL_OK;
+}
+
+aerl_status aerl_soft_forward_noalloc(aerl_ctx *ctx, int32_t dataset_id, int32_t pop_id,
+                                      const float *coef, const float *coef2, const float *theta,
+                                      float *loss, hipStream_t stream) {
+  if (!ctx) return AERL_EINVAL;
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  ctx->err.clear();
+  if (!ctx->noalloc_scratch) return fail(ctx, AERL_EDEVICE, "no scratch array on device %d", ctx->device);
+  auto di = ctx->datasets.find(dataset_id);
+  auto pi = ctx->pops.find(pop_id);
+  if (di != ctx->datasets.end() && pi != ctx->pops.end()) {
+    const size_t need = soft_ws_bytes(di->second, pi->second, false);
+    if (need > AERL_NOALLOC_SCRATCH_BYTES)
+      return fail(ctx, AERL_ENOMEM,
+                  "the no-allocation soft forward needs %zu bytes of scratch; it holds %zu", need,
+                  (size_t)AERL_NOALLOC_SCRATCH_BYTES);
+  }
+  SoftLaunch l{};
+  l.coef = coef; l.coef2 = coef2; l.theta = theta; l.loss = loss;
+  l.ws = ctx->noalloc_scratch;
+  l.ws_bytes = AERL_NOALLOC_SCRATCH_BYTES;
   aerl_status st = soft_common(ctx, dataset_id, pop_id, &l, false);
   if (st) return st;
   if (!loss && l.pop->n_sets > 0) return fail(ctx, AERL_EINVAL, "loss is NULL");

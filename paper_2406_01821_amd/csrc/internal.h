@@ -161,6 +161,7 @@ struct aerl_ctx {
   std::map<std::string, std::array<int32_t, 3>> tuned;  // batch shape -> (sets, tiles, tile KiB)
   bool tune_file_loaded = false;
   aerl::Serve *serve = nullptr;
+  void *noalloc_scratch = nullptr;  // this device's copy of the no-allocation scratch array
 };
 
 namespace aerl {
@@ -240,5 +241,9 @@ size_t soft_ws_bytes(const DatasetRec &ds, const PopRec &pop, bool backward);
 bool soft_backward_supported(const DatasetRec &ds, const PopRec &pop);
 hipError_t launch_soft_forward(const SoftLaunch &l, hipStream_t s);
 hipError_t launch_soft_backward(const SoftLaunch &l, hipStream_t s);
+// Device address of the current device's no-allocation scratch array
+// (AERL_NOALLOC_SCRATCH_BYTES), resolved once per device; the device must be
+// current.
+hipError_t noalloc_scratch(int device, void **out);
 
 }  // namespace aerl

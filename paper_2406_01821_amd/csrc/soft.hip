@@ -968,6 +968,30 @@ hipError_t launch_soft_forward(const SoftLaunch &l, hipStream_t st) {
   return hipGetLastError();
 }
 
+namespace {
+// Scratch of the no-allocation soft forward: one copy per GPU, loaded with the
+// code object.  On the host this name is only a stand-in for the symbol;
+// kernels receive the device address hipGetSymbolAddress gives for it.
+static __device__ __align__(256) unsigned char scratch[AERL_NOALLOC_SCRATCH_BYTES];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t noalloc_scratch(int device, void **out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  if (!g_scratch_ptr[device]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch_ptr[device] = ptr;
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
+}
+
 hipError_t launch_soft_backward(const SoftLaunch &l, hipStream_t st) {
   const PopRec &pop = *l.pop;
   if (pop.n_sets == 0) return hipSuccess;
