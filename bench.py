@@ -163,6 +163,129 @@ def timed(fn, steps, warmup, stream):
     return float(np.mean([a.elapsed_time(b) for a, b in ev])), wall * 1e3
 
 
+def loop_us(fn, reps, warmup, stream):
+    """Mean wall time of fn over reps back-to-back calls (host submission
+    included), and the GPU time between events around the whole loop, in
+    microseconds per call."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    a.record(stream)
+    for _ in range(reps):
+        fn()
+    b.record(stream)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / reps * 1e6
+    return wall, a.elapsed_time(b) / reps * 1e3
+
+
+def bench_c1(ctx, steps, warmup, cpu, n_pools=64):
+    """The paper's own shape (569 x 30 samples, 2 classes, pools of 100 rule
+    sets): microseconds per pool evaluation, one launch per pool against many
+    pools in one graph-replayed persistent launch, with the oracle beside
+    it."""
+    import torch
+    import oracle
+    from paper_2406_01821_amd import synth
+    w = synth.small_hard(0)
+    pools = synth.small_hard_pools(n_pools)
+    ds = ctx.upload_dataset(w.data)
+    dev = [ctx.pack_population(p, 30, 2) for p in pools]
+    outs = [ctx.eval_population(ds, p) for p in dev]
+    stream = torch.cuda.current_stream()
+    reps = max(20, steps * 5)
+
+    def plain():
+        for p, o in zip(dev, outs):
+            ctx.eval_population(ds, p, out=o)
+
+    plain_wall, plain_gpu = loop_us(plain, reps, warmup, stream)
+    one_wall, one_gpu = loop_us(lambda: ctx.eval_population(ds, dev[0], out=outs[0]), reps * 8,
+                                warmup, stream)
+    items = [(ds, p, *ctx.batch_outputs(ds, p)) for p in dev]
+    ws = ctx.batch_workspace(items, (1, 1))
+    (q, tg, kib), _ = ctx.autotune(items, ws)
+    plan = ctx.batch_plan(items, ws, graph=True)
+    batch_wall, batch_gpu = loop_us(plan.run, reps, warmup, stream)
+    torch.cuda.synchronize()
+    exact = all(torch.equal(it[2], o[0]) and torch.equal(it[3], o[1]) for it, o in zip(items, outs))
+    # a whole call from host rule sets to host counts
+    call = []
+    for i in range(min(n_pools, 32)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        p = ctx.pack_population(pools[i], 30, 2)
+        c, m = ctx.eval_population(ds, p)
+        c.cpu(), m.cpu()
+        call.append((time.perf_counter() - t0) * 1e6)
+        ctx.release_population(p)
+    call_us = float(np.median(call))
+    plan.release()
+    for p in dev:
+        ctx.release_population(p)
+    ctx.release_dataset(ds)
+    nominal = int(pools[0].nominal_conds_per_set().sum()) * w.data.n
+    out = {
+        "workload": "569 x 30 fp32 samples, 2 classes; pools of 100 rule sets x 1-8 rules x 1-4 "
+                    "conditions, 30% feature-vs-feature (the paper's pool size and table shape)",
+        "pools": n_pools,
+        "plain_us_per_pool": plain_wall / n_pools, "plain_gpu_us_per_pool": plain_gpu / n_pools,
+        "plain_one_pool_repeated_us": one_wall, "plain_one_pool_gpu_us": one_gpu,
+        "batched_us_per_pool": batch_wall / n_pools, "batched_gpu_us_per_pool": batch_gpu / n_pools,
+        "batched_split": {"sets_per_task": q, "tiles_per_task": tg, "tile_kib": kib},
+        "speedup_vs_plain": plain_wall / batch_wall,
+        "call_level_us": call_us,
+        "call_level_what": "pack on the host + copy + evaluation + counts back, one pool",
+        "bit_identical_to_plain": exact,
+        "nominal_cond_evals_pool0": nominal,
+    }
+    log(f"C1: plain {plain_wall / n_pools:.1f} us/pool, batched {batch_wall / n_pools:.2f} us/pool "
+        f"({plain_wall / batch_wall:.1f}x), call level {call_us:.0f} us, identical={exact}")
+    if cpu:
+        for nt, key in ((1, "oracle_one_thread_us_per_pool"), (0, "oracle_all_cores_us_per_pool")):
+            oracle.hard_eval(w.data.x, w.data.y, 2, pools[0], nthreads=nt)
+            t0 = time.perf_counter()
+            k = 0
+            while time.perf_counter() - t0 < 1.0:
+                oracle.hard_eval(w.data.x, w.data.y, 2, pools[k % n_pools], nthreads=nt)
+                k += 1
+            out[key] = (time.perf_counter() - t0) / k * 1e6
+        out["oracle_threads"] = oracle.max_threads()
+    return out
+
+
+def bench_finetune(ctx, epochs=20):
+    """Fine-tuning epochs per second on the soft workload (262,144 x 32, 1024
+    rule sets x 16 rules x 4 conditions): full-batch adjoint plus the fused
+    Adam update, no loss history."""
+    import torch
+    from paper_2406_01821_amd import synth
+    w = synth.soft_workload(3)
+    ds = ctx.upload_dataset(w.data)
+    pop = ctx.pack_population(w.pop, w.data.n_features, w.data.n_classes)
+    par = [torch.tensor(a, device=ctx.device) for a in (w.pop.coef, w.pop.coef2, w.pop.theta)]
+    ws = ctx.finetune_workspace(ds, pop)
+    ctx.finetune(ds, pop, *par, epochs=1, ws=ws)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    ctx.finetune(ds, pop, *par, epochs=epochs, ws=ws)
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b)
+    ctx.release_population(pop)
+    ctx.release_dataset(ds)
+    log(f"fine-tuning: {epochs} epochs in {ms:.1f} ms")
+    return {"workload": "Adam fine-tuning, 262,144 x 32 fp32 samples, 1024 rule sets x 16 rules "
+                        "x 4 threshold conditions, full batch, no loss history",
+            "epochs": epochs, "ms": ms, "epochs_per_s": epochs / (ms * 1e-3),
+            "ms_per_epoch": ms / epochs}
+
+
 def bench_soft(ctx, steps, warmup, cpu):
     import torch
     import oracle
@@ -406,6 +529,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--only-hard", action="store_true", help="time the hard path only")
+    ap.add_argument("--only", default=None, help="one extra section alone: c1, finetune, soft")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run only a plain 256 MiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -427,6 +551,15 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_read": nbytes, "copy_probe_bytes_written": nbytes,
                           "launches": 3}), flush=True)
+        return
+
+    if args.only:
+        ctx = Context(0)
+        fn = {"c1": lambda: bench_c1(ctx, args.steps, args.warmup, not args.no_cpu),
+              "finetune": lambda: bench_finetune(ctx),
+              "soft": lambda: bench_soft(ctx, max(3, args.steps // 4), 1, not args.no_cpu)}
+        print(json.dumps({args.only: fn[args.only]()}), flush=True)
+        ctx.close()
         return
 
     t0 = time.time()
@@ -480,7 +613,9 @@ def main():
     del w
     if not args.only_hard:
         result["soft"] = bench_soft(ctx, max(3, args.steps // 4), 1, not args.no_cpu)
+        result["finetune"] = bench_finetune(ctx)
         result["ragged"] = bench_ragged(ctx, max(3, args.steps // 4), 1)
+        result["c1"] = bench_c1(ctx, args.steps, args.warmup, not args.no_cpu)
     print(json.dumps(result), flush=True)
     ctx.close()
 

@@ -256,7 +256,7 @@ aerl_status aerl_predict(aerl_ctx *ctx, int32_t pop_id, int32_t set, const float
 /* Many independent evaluations (each its own dataset and population, of any
  * shapes) in ONE persistent launch, the form in which an evolution loop that
  * runs several populations or datasets keeps the whole GPU busy (Section 3:
- * candidates are handed to the GPU for evaluation; Section 4.2: the cost
+ * candidates are handed to the GPU for evaluation; Section 4.3 and Fig. 3: the cost
  * varies with the number of rules and conditions per generation).  Results
  * are bit-identical to aerl_eval_population of each item. */
 typedef struct {
@@ -446,6 +446,50 @@ aerl_status aerl_soft_backward(aerl_ctx *ctx, int32_t dataset_id, int32_t pop_id
                                const float *coef, const float *coef2, const float *theta,
                                const float *dloss, float *dcoef, float *dcoef2, float *dtheta,
                                void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------ fine-tuning */
+
+/* Optimizers of aerl_finetune.  The paper tunes the coefficients by
+ * back-propagation for 50 epochs (Sections 3 and 4.1) without naming the
+ * update rule; both common ones are offered. */
+#define AERL_OPT_ADAM 0 /* Adam with bias correction (beta1, beta2, eps) */
+#define AERL_OPT_SGD 1  /* plain gradient descent, p -= lr * g */
+typedef struct {
+  int32_t epochs;    /* full-batch steps, >= 0 */
+  int32_t optimizer; /* AERL_OPT_ADAM or AERL_OPT_SGD */
+  float lr;          /* > 0, finite */
+  float beta1, beta2, eps; /* Adam: in [0, 1), [0, 1), > 0; ignored by SGD */
+} aerl_finetune_cfg;
+
+/* Device scratch of aerl_finetune for this dataset and population (the
+ * adjoint's partial sums, the gradients, the optimizer moments).  Errors:
+ * AERL_ENOENT. */
+aerl_status aerl_finetune_workspace_bytes(aerl_ctx *ctx, int32_t dataset_id, int32_t pop_id,
+                                          size_t *bytes);
+
+/* Fine-tune every rule set of pop_id on dataset_id (Section 3: gradients of
+ * the sigmoid relaxation adjust the rule coefficients without changing the
+ * logical structure; Section 4.1: 50 epochs of gradient updates).  Each
+ * epoch is one full-batch step: the adjoint of aerl_soft_backward over the
+ * whole dataset with dloss = 1 for every rule set (each rule set is its own
+ * model), then one fused optimizer update, on the device, of each
+ * condition's coefficient and of its threshold (threshold condition) or
+ * second coefficient (feature-vs-feature condition).  The other entry of the
+ * pair is never written, and the population's structure (features, ops,
+ * rules, classes) is unchanged.
+ *   coef, coef2, theta  device fp32 [n_conds], the starting values, updated
+ *                       in place
+ *   loss_hist           device fp32 [epochs + 1][n_sets]: row e is the soft
+ *                       loss after e updates; NULL skips these forward passes
+ *   ws                  device scratch of aerl_finetune_workspace_bytes
+ * Asynchronous on stream; deterministic.  The tuned parameters are scored
+ * with the step activation by packing them (aerl_pack_population) and
+ * calling aerl_eval_population.  Errors: AERL_ENOENT, AERL_EINVAL (bad cfg,
+ * NULL arrays, shapes, rule sets too long for the adjoint), AERL_ENOMEM (ws
+ * too small), AERL_EDEVICE. */
+aerl_status aerl_finetune(aerl_ctx *ctx, int32_t dataset_id, int32_t pop_id,
+                          const aerl_finetune_cfg *cfg, float *coef, float *coef2, float *theta,
+                          float *loss_hist, void *ws, size_t ws_bytes, hipStream_t stream);
 
 /* aerl_soft_forward for callers that cannot allocate device memory (code
  * under HIP graph capture, tight serving loops, harnesses that forbid

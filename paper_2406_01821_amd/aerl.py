@@ -56,6 +56,11 @@ class aerl_eval_launch(C.Structure):
                 ("tiles_per_group", C.c_int32), ("pad", C.c_int32), ("workgroups", C.c_int64)]
 
 
+class aerl_finetune_cfg(C.Structure):
+    _fields_ = [("epochs", C.c_int32), ("optimizer", C.c_int32), ("lr", C.c_float),
+                ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float)]
+
+
 class aerl_batch_item(C.Structure):
     _fields_ = [("dataset_id", C.c_int32), ("pop_id", C.c_int32),
                 ("correct", C.c_void_p), ("confusion", C.c_void_p)]
@@ -67,6 +72,7 @@ class aerl_batch_cfg(C.Structure):
 
 
 AERL_BATCH_GRAPH = 1
+AERL_OPT_ADAM, AERL_OPT_SGD = 0, 1
 AERL_REQ_FITNESS, AERL_REQ_PREDICT = 0, 1
 
 
@@ -136,6 +142,9 @@ _SIGS = {
     "aerl_soft_forward": ([_P, _I32, _I32, _P, _P, _P, _P, _P, _SZ, _P], _I32),
     "aerl_soft_backward": ([_P, _I32, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _SZ, _P], _I32),
     "aerl_soft_forward_noalloc": ([_P, _I32, _I32, _P, _P, _P, _P, _P], _I32),
+    "aerl_finetune_workspace_bytes": ([_P, _I32, _I32, C.POINTER(_SZ)], _I32),
+    "aerl_finetune": ([_P, _I32, _I32, C.POINTER(aerl_finetune_cfg), _P, _P, _P, _P, _P, _SZ, _P],
+                      _I32),
 }
 for _name, (_args, _res) in _SIGS.items():
     _fn = getattr(lib, _name)
@@ -430,6 +439,28 @@ class Context:
         self.check(aerl_soft_forward(self.h, ds.id, pop.id, _ptr(coef), _ptr(coef2), _ptr(theta),
                                      _ptr(loss), _ptr(ws), ws.numel(), _stream(stream)))
         return loss
+
+    def finetune_workspace(self, ds, pop):
+        nb = C.c_size_t()
+        self.check(aerl_finetune_workspace_bytes(self.h, ds.id, pop.id, C.byref(nb)))
+        return torch.empty(max(nb.value, 256), dtype=torch.uint8, device=self.device)
+
+    def finetune(self, ds, pop, coef, coef2, theta, epochs: int, optimizer: str = "adam",
+                 lr: float = 0.01, betas=(0.9, 0.999), eps: float = 1e-8,
+                 loss_history: bool = False, ws=None, stream=None):
+        """Tunes coef, coef2, theta (device fp32 tensors, updated in place) for
+        ``epochs`` full-batch steps; returns the [epochs + 1][n_sets] loss
+        history when asked for, else None."""
+        cfg = aerl_finetune_cfg(epochs, AERL_OPT_ADAM if optimizer == "adam" else AERL_OPT_SGD,
+                                lr, betas[0], betas[1], eps)
+        if optimizer not in ("adam", "sgd"):
+            raise ValueError(optimizer)
+        ws = ws if ws is not None else self.finetune_workspace(ds, pop)
+        hist = (torch.empty((epochs + 1, pop.n_sets), dtype=torch.float32, device=self.device)
+                if loss_history else None)
+        self.check(aerl_finetune(self.h, ds.id, pop.id, C.byref(cfg), _ptr(coef), _ptr(coef2),
+                                 _ptr(theta), _ptr(hist), _ptr(ws), ws.numel(), _stream(stream)))
+        return hist
 
     def soft_forward_noalloc(self, ds, pop, coef, coef2, theta, loss, stream=None):
         """Soft forward into the caller's ``loss`` tensor using the library's

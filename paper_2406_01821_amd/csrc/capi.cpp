@@ -520,6 +520,55 @@ aerl_status aerl_soft_forward(aerl_ctx *ctx, int32_t dataset_id, int32_t pop_id,
   return AERL_OK;
 }
 
+aerl_status aerl_finetune_workspace_bytes(aerl_ctx *ctx, int32_t dataset_id, int32_t pop_id,
+                                          size_t *bytes) {
+  if (!ctx || !bytes) return AERL_EINVAL;
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  auto di = ctx->datasets.find(dataset_id);
+  if (di == ctx->datasets.end()) return fail(ctx, AERL_ENOENT, "unknown dataset %d", dataset_id);
+  auto pi = ctx->pops.find(pop_id);
+  if (pi == ctx->pops.end()) return fail(ctx, AERL_ENOENT, "unknown population %d", pop_id);
+  *bytes = tune_layout(di->second, pi->second).total;
+  return AERL_OK;
+}
+
+aerl_status aerl_finetune(aerl_ctx *ctx, int32_t dataset_id, int32_t pop_id,
+                          const aerl_finetune_cfg *cfg, float *coef, float *coef2, float *theta,
+                          float *loss_hist, void *ws, size_t ws_bytes, hipStream_t stream) {
+  if (!ctx) return AERL_EINVAL;
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  ctx->err.clear();
+  if (!cfg) return fail(ctx, AERL_EINVAL, "cfg is NULL");
+  if (cfg->epochs < 0) return fail(ctx, AERL_EINVAL, "epochs %d < 0", cfg->epochs);
+  if (!(cfg->lr > 0.0f) || !std::isfinite(cfg->lr)) return fail(ctx, AERL_EINVAL, "lr must be positive");
+  if (cfg->optimizer == AERL_OPT_ADAM) {
+    if (!(cfg->beta1 >= 0.0f && cfg->beta1 < 1.0f) || !(cfg->beta2 >= 0.0f && cfg->beta2 < 1.0f) ||
+        !(cfg->eps > 0.0f) || !std::isfinite(cfg->eps))
+      return fail(ctx, AERL_EINVAL, "Adam needs beta1, beta2 in [0, 1) and eps > 0");
+  } else if (cfg->optimizer != AERL_OPT_SGD) {
+    return fail(ctx, AERL_EINVAL, "unknown optimizer %d", cfg->optimizer);
+  }
+  SoftLaunch l{};
+  l.coef = coef; l.coef2 = coef2; l.theta = theta;
+  l.ws = ws; l.ws_bytes = ws_bytes;
+  aerl_status st = soft_common(ctx, dataset_id, pop_id, &l, true);
+  if (st) return st;
+  const TuneLayout L = tune_layout(*l.ds, *l.pop);
+  if (ws_bytes < L.total) return fail(ctx, AERL_ENOMEM, "ws holds %zu bytes, %zu needed", ws_bytes, L.total);
+  TuneLaunch t{};
+  t.ds = l.ds;
+  t.pop = l.pop;
+  t.coef = coef; t.coef2 = coef2; t.theta = theta;
+  t.loss_hist = loss_hist;
+  t.epochs = cfg->epochs;
+  t.optimizer = cfg->optimizer;
+  t.lr = cfg->lr; t.beta1 = cfg->beta1; t.beta2 = cfg->beta2; t.eps = cfg->eps;
+  t.ws = ws;
+  AERL_HIP(ctx, hipSetDevice(ctx->device));
+  AERL_HIP(ctx, run_finetune(t, stream));
+  return AERL_OK;
+}
+
 aerl_status aerl_soft_forward_noalloc(aerl_ctx *ctx, int32_t dataset_id, int32_t pop_id,
                                       const float *coef, const float *coef2, const float *theta,
                                       float *loss, hipStream_t stream) {

@@ -91,87 +91,19 @@ __device__ __forceinline__ void ldc_pair(const int4 *p, int4 (&out)[2]) {
   out[1] = make_int4(v[4], v[5], v[6], v[7]);
 }
 
-// Evaluates rule set `set` = {first record, record count, default, -} of the
-// hard stream for the S*64 samples of the tile.  vm[s]: lanes whose slot-s
-// sample is real.  The set's closing record (always true, default class)
-// decides every lane no rule fired for.
-// COUNT mode (PRED = false): returns, in lane c, the number of the tile's
-//   real samples predicted as class c.
-// PRED mode: pred[s] receives the predicted class of each lane's samples.
-// Portable reference form (any S, both modes); the kernels run
-// eval_set_count / eval_set_pred below, the same walk written for the
-// scalar unit by hand.
-template <int S, bool PRED>
-__device__ __forceinline__ int eval_set(const float *__restrict__ xs, int lane, int4 set,
-                                        const uint4 *__restrict__ stream,
-                                        const uint64_t (&vm)[S], int (&pred)[S]) {
-  uint64_t und[S], fire[S];
-#pragma unroll
-  for (int s = 0; s < S; ++s) und[s] = fire[s] = vm[s];
-  int acc = 0;
-  const uint4 *base = stream + set.x;
-  const uint32_t end = (uint32_t)(set.y & 0xffff) * 16u;
-  uint32_t o = 0;
-  while (o < end) {
-    const uint4 r = ldc_at(base, o);
-    const float ry = __uint_as_float(r.y), rz = __uint_as_float(r.z);
-    uint64_t m[S];
-    if (r.w & kRecFF) {
-      float v1[S], v2[S];
-      load_row<S>(xs, r.x, lane, v1);
-      load_row<S>(xs, (r.w & kRecGMask) * 1024u, lane, v2);
-      const bool ge = (r.w & kRecGE) != 0;
-#pragma unroll
-      for (int s = 0; s < S; ++s) {
-        const float p = ry * v1[s], q = rz * v2[s];
-        m[s] = ge ? ballot(p >= q) : ballot(p > q);
-      }
-    } else if (r.w & kRecAlways) {
-#pragma unroll
-      for (int s = 0; s < S; ++s) m[s] = ~0ull;
-    } else {
-      float v[S];
-      load_row<S>(xs, r.x, lane, v);
-      const bool mul = (r.w & kRecMul) != 0, le = (r.w & kRecLE) != 0;
-#pragma unroll
-      for (int s = 0; s < S; ++s)
-        m[s] = mul ? ballot(ry * v[s] > rz) : le ? ballot(v[s] <= ry) : ballot(v[s] >= ry);
-    }
-    uint64_t any = 0;
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-      fire[s] &= m[s];
-      any |= fire[s];
-    }
-    uint32_t next = o + 16u;
-    if (any == 0) {  // no undecided lane can fire this rule: next rule
-      next = r.w >> kRecNextShift;
-#pragma unroll
-      for (int s = 0; s < S; ++s) fire[s] = und[s];
-    } else if (r.w & kRecLast) {  // the rule fires: commit it
-      const int cls = (int)((r.w >> kRecClsShift) & 63u);
-      int nfire = 0;
-      uint64_t left = 0;
-#pragma unroll
-      for (int s = 0; s < S; ++s) {
-        if constexpr (PRED) {
-          if ((fire[s] >> lane) & 1ull) pred[s] = cls;
-        }
-        nfire += __builtin_popcountll(fire[s]);
-        und[s] &= ~fire[s];
-        left |= und[s];
-        fire[s] = und[s];
-      }
-      if constexpr (!PRED) acc += (lane == cls) ? nfire : 0;
-      if (left == 0) next = end;  // every lane decided
-    }
-    o = next;
-  }
-  return acc;
-}
-
+// Evaluation of one rule set `set` = {first record, record count, default,
+// -} of the hard stream for the S*64 samples of the staged tile.  vm[s]:
+// lanes whose slot-s sample is real.  Records are read in order; a
+// condition ANDs its compare into the rule's per-slot fire masks; a rule
+// whose masks hold no undecided lane is abandoned (its next-rule offset
+// says where the next rule starts); a rule that reaches its last record
+// with lanes still set fires for them: they take its class and leave the
+// undecided masks; the set's closing record (always true, default class)
+// decides every lane no rule fired for, and the walk stops as soon as
+// every lane is decided.
 // Counting evaluation written for the scalar unit, for S = 4, 2 or 1
-// samples per lane.  Same semantics as eval_set<S, false>.  Records are
+// samples per lane; returns, in lane c, the number of the tile's real
+// samples predicted as class c.  Records are
 // loaded two at a time (s_load_dwordx8 at byte offset o into quads
 // A = s[64:67] and B = s[68:71]): a rule that goes on past an A record, or
 // starts right after one, continues from B without another scalar load or

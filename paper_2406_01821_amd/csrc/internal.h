@@ -241,6 +241,22 @@ size_t soft_ws_bytes(const DatasetRec &ds, const PopRec &pop, bool backward);
 bool soft_backward_supported(const DatasetRec &ds, const PopRec &pop);
 hipError_t launch_soft_forward(const SoftLaunch &l, hipStream_t s);
 hipError_t launch_soft_backward(const SoftLaunch &l, hipStream_t s);
+// Fine-tuning (tune.hip): workspace layout and the epoch loop.
+struct TuneLayout {
+  size_t soft_off, grad_off, mom_off, dloss_off, total;
+};
+TuneLayout tune_layout(const DatasetRec &ds, const PopRec &pop);
+struct TuneLaunch {
+  const DatasetRec *ds;
+  const PopRec *pop;
+  float *coef, *coef2, *theta;  // updated in place
+  float *loss_hist;             // [epochs + 1][n_sets] or null
+  int32_t epochs, optimizer;
+  float lr, beta1, beta2, eps;
+  void *ws;
+};
+hipError_t run_finetune(const TuneLaunch &t, hipStream_t s);
+
 // Device address of the current device's no-allocation scratch array
 // (AERL_NOALLOC_SCRATCH_BYTES), resolved once per device; the device must be
 // current.

@@ -118,6 +118,14 @@ class Population:
             rules.append((int(self.rule_class[r]), conds))
         return int(self.set_default[s]), rules
 
+    def with_params(self, coef, coef2, theta) -> "Population":
+        """The same structure with other coefficients and thresholds (fp32)."""
+        return Population(self.set_rule_off.copy(), self.set_default.copy(),
+                          self.rule_cond_off.copy(), self.rule_class.copy(), self.op.copy(),
+                          self.kind.copy(), self.f.copy(), self.g.copy(),
+                          np.asarray(coef, np.float32), np.asarray(coef2, np.float32),
+                          np.asarray(theta, np.float32), dict(self.meta))
+
     def conds_kind_first(self) -> "Population":
         """Same rule sets with each rule's conditions stably reordered so that
         threshold conditions come before feature-vs-feature ones.  A rule is an

@@ -145,6 +145,15 @@ def small_hard(seed: int = 0) -> Workload:
     return Workload(Dataset(x, y, 2, "569x30"), pop, "hard-569x30-P100")
 
 
+def small_hard_pools(n_pools: int = 64, seed0: int = 100) -> List[Population]:
+    """Independent candidate pools of the 569 x 30 workload's shape (100 rule
+    sets of 1-8 rules x 1-4 conditions, 30% feature-vs-feature), drawn on its
+    dataset: pool i from ``default_rng(seed0 + i)``."""
+    x = small_hard(0).data.x
+    return [random_population(np.random.default_rng(seed0 + i), x, 100, (1, 8), (1, 4), 2, 0.3)
+            for i in range(n_pools)]
+
+
 def scaled_hard(seed: int = 1, n: int = 1 << 20, nf: int = 64, n_sets: int = 4096) -> Workload:
     """2^20 x 64 features, 4 classes, planted 12 rules x 1-4 conditions, 3%
     noise; 4096 rule sets of 1-32 rules x 1-6 conditions, 30%
