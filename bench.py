@@ -286,6 +286,64 @@ def bench_finetune(ctx, epochs=20):
             "ms_per_epoch": ms / epochs}
 
 
+def bench_evolve(ctx, cpu, gens=20, tune_gens=5, epochs=50):
+    """Evolution runs on the 569 x 30 table with the paper's pool of 100,
+    with and without 50 epochs of fine-tuning per generation: generations per
+    second on the GPU, and the same loop (the library's host breeding) with
+    the oracle as the evaluator on the host cores, as the paper compares
+    whole runs on a CPU and a GPU."""
+    import torch
+    import oracle
+    from oracle import tune as otune
+    from paper_2406_01821_amd import synth
+    from paper_2406_01821_amd.aerl import evolve_cfg, breed
+    w = synth.small_hard(0)
+    x, y = w.data.x, w.data.y
+    lo, hi = x.min(axis=0), x.max(axis=0)
+    ds = ctx.upload_dataset(w.data)
+    out = {"workload": "evolution on 569 x 30 fp32 samples, 2 classes, pool of 100 rule sets of "
+                       "1-8 rules x 1-4 conditions, tournament 3, elite 2; fine-tuning: 50 Adam "
+                       "epochs per generation (lr 0.01), Baldwinian"}
+    for key, kw, n in (("plain", {}, gens), ("finetune", dict(tune_epochs=epochs), tune_gens)):
+        cfg = evolve_cfg(seed=1, **kw)
+        run = ctx.evolve(ds, cfg, lo, hi)
+        run.run(1)
+        torch.cuda.synchronize()
+        s0 = run.state()
+        t0 = time.perf_counter()
+        run.run(n)
+        dt = time.perf_counter() - t0
+        s1 = run.state()
+        run.release()
+        out[key] = {"generations": n, "s": dt, "gen_per_s": n / dt,
+                    "best_accuracy": float(s1["fitness"].max()) / w.data.n,
+                    "host_eval_s": s1["seconds_eval"] - s0["seconds_eval"],
+                    "host_tune_s": s1["seconds_tune"] - s0["seconds_tune"],
+                    "host_breed_s": s1["seconds_breed"] - s0["seconds_breed"]}
+        log(f"evolution {key}: {n / dt:.1f} generations/s")
+        if cpu:
+            pop, fit, state = s1["pool"], s1["fitness"], s1["rng_state"]
+            m = max(2, n // 4)
+            t0 = time.perf_counter()
+            for _ in range(m):
+                pop, state = breed(pop, fit, cfg, 30, 2, lo, hi, state)
+                scored = pop
+                if key == "finetune":
+                    tau = oracle.tau(x)
+                    ps, _ = otune.finetune(x, y, tau, 2, pop, epochs, optimizer="adam", lr=0.01)
+                    scored = pop.with_params(*ps[-1])
+                fit, _ = oracle.hard_eval(x, y, 2, scored, confusion=False)
+            dt_cpu = (time.perf_counter() - t0) / m
+            out[key]["cpu_oracle"] = {"s_per_generation": dt_cpu, "generations": m,
+                                      "cores": oracle.max_threads(), "kind": "oracle",
+                                      "what": "library host breeding + oracle evaluation"
+                                              + (" + fp64 oracle fine-tuning" if key == "finetune"
+                                                 else "")}
+            out[key]["cpu_over_gpu"] = dt_cpu / (dt / n)
+    ctx.release_dataset(ds)
+    return out
+
+
 def bench_soft(ctx, steps, warmup, cpu):
     import torch
     import oracle
@@ -557,6 +615,7 @@ def main():
         ctx = Context(0)
         fn = {"c1": lambda: bench_c1(ctx, args.steps, args.warmup, not args.no_cpu),
               "finetune": lambda: bench_finetune(ctx),
+              "evolve": lambda: bench_evolve(ctx, not args.no_cpu),
               "soft": lambda: bench_soft(ctx, max(3, args.steps // 4), 1, not args.no_cpu)}
         print(json.dumps({args.only: fn[args.only]()}), flush=True)
         ctx.close()
@@ -616,6 +675,7 @@ def main():
         result["finetune"] = bench_finetune(ctx)
         result["ragged"] = bench_ragged(ctx, max(3, args.steps // 4), 1)
         result["c1"] = bench_c1(ctx, args.steps, args.warmup, not args.no_cpu)
+        result["evolution"] = bench_evolve(ctx, not args.no_cpu)
     print(json.dumps(result), flush=True)
     ctx.close()
 

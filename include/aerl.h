@@ -491,6 +491,126 @@ aerl_status aerl_finetune(aerl_ctx *ctx, int32_t dataset_id, int32_t pop_id,
                           const aerl_finetune_cfg *cfg, float *coef, float *coef2, float *theta,
                           float *loss_hist, void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* ------------------------------------------------------------ evolution */
+
+/* The evolution loop that feeds the library (Section 3: evolution on the
+ * CPU by tournament selection and offspring with randomized coefficients,
+ * candidates evaluated on the GPU, optional back-propagation every
+ * generation whose tuned fitness steers selection, the Baldwin effect;
+ * Section 4.1: a pool of 100 candidate rule sets).  The paper names no
+ * operator details; the ones below are this library's reading.
+ *
+ * Random stream: SplitMix64 (Steele, Lea and Flood, OOPSLA 2014), state s:
+ *   next(): s += 0x9e3779b97f4a7c15; z = s; z = (z ^ z >> 30) * 0xbf58476d1ce4e5b9;
+ *           z = (z ^ z >> 27) * 0x94d049bb133111eb; return z ^ z >> 31
+ *   below(n) = ((next() >> 32) * n) >> 32;  unit() = (next() >> 40) * 2^-24
+ * Random condition: feature-vs-feature if unit() < ff_frac (and F >= 2);
+ *   f = below(F); g = (f + 1 + below(F - 1)) % F (feature-vs-feature);
+ *   op = below(4); coef = unit(); then coef2 = unit() (feature-vs-feature)
+ *   or theta = (float)(lo[f] + unit() * (hi[f] - lo[f])) in double.
+ * Random rule: class = below(C), one random condition.  Random pool: per
+ *   rule set R = 1 + below(max_rules), default = below(C); per rule
+ *   K = 1 + below(max_conds), class = below(C), K random conditions.
+ * Next generation from pool P with fitness F: the elite best (fitness
+ *   descending, ties by index) pass unchanged; each other slot: child = copy
+ *   of tournament() (tournament draws i = below(pool) that many times and
+ *   keeps the fittest, ties to the lower index); if unit() < p_crossover,
+ *   B = tournament(), ca = below(R_child + 1), cb = below(R_B + 1), rules =
+ *   child[0, ca) + B[cb, R_B) (child[0, 1) if empty), cut to max_rules; each
+ *   condition in order: if unit() < p_coef, coef = unit() then coef2 or
+ *   theta redrawn as for a random condition; if unit() < p_struct, t =
+ *   below(4): 0 add a random condition to rule below(R) if it has fewer
+ *   than max_conds; 1 drop condition below(K_r) of rule r = below(R) if
+ *   K_r >= 2; 2 insert a random rule at below(R + 1) if R < max_rules;
+ *   3 drop rule below(R) if R >= 2.  Draws guarded by a condition happen
+ *   only when it holds. */
+typedef struct {
+  int32_t pool;        /* rule sets per generation, >= 2 (the paper: 100) */
+  int32_t tournament;  /* tournament size, >= 1 */
+  int32_t elite;       /* best rule sets kept unchanged, 0 .. pool - 1 */
+  int32_t max_rules;   /* rules per rule set, 1 .. 64 */
+  int32_t max_conds;   /* conditions per rule, 1 .. AERL_MAX_RULE_CONDS,
+                          max_rules * max_conds <= 1022 */
+  float ff_frac;       /* probability that a new condition compares two features */
+  float p_crossover, p_coef, p_struct; /* probabilities, in [0, 1] */
+  int32_t tune_epochs; /* fine-tuning epochs per generation, 0 = none */
+  aerl_finetune_cfg tune; /* its optimizer (the epochs field is ignored) */
+  uint64_t seed;       /* initial SplitMix64 state */
+} aerl_evolve_cfg;
+
+/* A pool written by the library into caller arrays of capacity
+ * pool + 1, pool, pool * max_rules + 1, pool * max_rules and
+ * pool * max_rules * max_conds. */
+typedef struct {
+  int32_t n_sets, n_rules, n_conds; /* written */
+  int32_t *set_rule_off, *set_default, *rule_cond_off, *rule_class;
+  uint8_t *op, *kind;
+  int32_t *f, *g;
+  float *coef, *coef2, *theta;
+} aerl_population_out;
+
+/* Host-only steps of the loop (no GPU): a random initial pool, and the next
+ * generation from a pool and its fitness (correct counts), as specified
+ * above.  lo, hi: per-feature ranges [F] for drawn thresholds; *rng_state is
+ * the SplitMix64 state, advanced.  Errors: AERL_EINVAL (cfg, ranges, pool
+ * not of cfg->pool rule sets or outside max_rules / max_conds). */
+aerl_status aerl_random_pool(const aerl_evolve_cfg *cfg, int32_t n_features, int32_t n_classes,
+                             const float *lo, const float *hi, uint64_t *rng_state,
+                             aerl_population_out *out);
+aerl_status aerl_breed(const aerl_population *pool, const int32_t *fitness,
+                       const aerl_evolve_cfg *cfg, int32_t n_features, int32_t n_classes,
+                       const float *lo, const float *hi, uint64_t *rng_state,
+                       aerl_population_out *out);
+
+/* Device bytes of the arena a run on dataset_id needs (packed pools,
+ * fitness, and with fine-tuning the parameters and the tuning workspace).
+ * Errors: AERL_ENOENT. */
+aerl_status aerl_evolve_arena_bytes(aerl_ctx *ctx, int32_t dataset_id, const aerl_evolve_cfg *cfg,
+                                    size_t *bytes);
+
+/* Start a run on dataset_id: generation 0 is `initial` (cfg->pool rule sets
+ * within max_rules / max_conds) or, when NULL, a random pool drawn from the
+ * seed; it is evaluated before the call returns.  Each evaluation packs the
+ * pool, scores it with aerl_eval_population and copies the counts to the
+ * host; with tune_epochs > 0 the pool is first fine-tuned on the device
+ * (aerl_finetune), and the tuned rule sets are scored (Baldwinian: the pool
+ * itself keeps its untuned coefficients).  arena: device memory of
+ * aerl_evolve_arena_bytes, 256-byte aligned, the caller's, used until
+ * aerl_evolve_release.  Synchronous on stream.  Errors: AERL_ENOENT,
+ * AERL_EINVAL, AERL_ENOMEM (arena too small), AERL_EDEVICE. */
+aerl_status aerl_evolve_create(aerl_ctx *ctx, int32_t dataset_id, const aerl_evolve_cfg *cfg,
+                               const float *lo, const float *hi, const aerl_population *initial,
+                               void *arena, size_t arena_bytes, hipStream_t stream,
+                               int32_t *evo_id);
+
+/* Breed and evaluate `generations` more generations.  Synchronous.  Errors:
+ * AERL_ENOENT, AERL_EINVAL, AERL_EDEVICE. */
+aerl_status aerl_evolve_run(aerl_ctx *ctx, int32_t evo_id, int32_t generations, hipStream_t stream);
+
+/* The current generation: its pool, its fitness (of the tuned rule sets when
+ * fine-tuning), the tuned parameters (NULL without fine-tuning), the random
+ * state and host wall-clock seconds spent so far evaluating, tuning and
+ * breeding.  Library-owned arrays, valid until the next call on evo_id. */
+typedef struct {
+  int32_t generation, pad;
+  aerl_population pool;
+  const int32_t *fitness;
+  const float *tuned_coef, *tuned_coef2, *tuned_theta;
+  uint64_t rng_state;
+  double seconds_eval, seconds_tune, seconds_breed;
+} aerl_evolve_info;
+aerl_status aerl_evolve_state(aerl_ctx *ctx, int32_t evo_id, aerl_evolve_info *out);
+
+/* Checkpoint a run to a file (configuration, ranges, generation, random
+ * state, pool, fitness, tuned parameters) and resume one on a dataset of the
+ * same shape: the resumed run continues exactly as the saved one would.
+ * Errors: AERL_ENOENT, AERL_EINVAL (unreadable or inconsistent file),
+ * AERL_ENOMEM, AERL_EDEVICE. */
+aerl_status aerl_evolve_save(aerl_ctx *ctx, int32_t evo_id, const char *path);
+aerl_status aerl_evolve_load(aerl_ctx *ctx, int32_t dataset_id, const char *path, void *arena,
+                             size_t arena_bytes, int32_t *evo_id);
+aerl_status aerl_evolve_release(aerl_ctx *ctx, int32_t evo_id);
+
 /* aerl_soft_forward for callers that cannot allocate device memory (code
  * under HIP graph capture, tight serving loops, harnesses that forbid
  * allocation): the same kernels and the same results, bit for bit, with the

@@ -61,6 +61,29 @@ class aerl_finetune_cfg(C.Structure):
                 ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float)]
 
 
+class aerl_evolve_cfg(C.Structure):
+    _fields_ = [("pool", C.c_int32), ("tournament", C.c_int32), ("elite", C.c_int32),
+                ("max_rules", C.c_int32), ("max_conds", C.c_int32), ("ff_frac", C.c_float),
+                ("p_crossover", C.c_float), ("p_coef", C.c_float), ("p_struct", C.c_float),
+                ("tune_epochs", C.c_int32), ("tune", aerl_finetune_cfg), ("seed", C.c_uint64)]
+
+
+class aerl_population_out(C.Structure):
+    _fields_ = [("n_sets", C.c_int32), ("n_rules", C.c_int32), ("n_conds", C.c_int32),
+                ("set_rule_off", C.c_void_p), ("set_default", C.c_void_p),
+                ("rule_cond_off", C.c_void_p), ("rule_class", C.c_void_p),
+                ("op", C.c_void_p), ("kind", C.c_void_p), ("f", C.c_void_p), ("g", C.c_void_p),
+                ("coef", C.c_void_p), ("coef2", C.c_void_p), ("theta", C.c_void_p)]
+
+
+class aerl_evolve_info(C.Structure):
+    _fields_ = [("generation", C.c_int32), ("pad", C.c_int32), ("pool", aerl_population),
+                ("fitness", C.c_void_p), ("tuned_coef", C.c_void_p), ("tuned_coef2", C.c_void_p),
+                ("tuned_theta", C.c_void_p), ("rng_state", C.c_uint64),
+                ("seconds_eval", C.c_double), ("seconds_tune", C.c_double),
+                ("seconds_breed", C.c_double)]
+
+
 class aerl_batch_item(C.Structure):
     _fields_ = [("dataset_id", C.c_int32), ("pop_id", C.c_int32),
                 ("correct", C.c_void_p), ("confusion", C.c_void_p)]
@@ -142,6 +165,18 @@ _SIGS = {
     "aerl_soft_forward": ([_P, _I32, _I32, _P, _P, _P, _P, _P, _SZ, _P], _I32),
     "aerl_soft_backward": ([_P, _I32, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _SZ, _P], _I32),
     "aerl_soft_forward_noalloc": ([_P, _I32, _I32, _P, _P, _P, _P, _P], _I32),
+    "aerl_random_pool": ([C.POINTER(aerl_evolve_cfg), _I32, _I32, _P, _P, C.POINTER(C.c_uint64),
+                          C.POINTER(aerl_population_out)], _I32),
+    "aerl_breed": ([C.POINTER(aerl_population), _P, C.POINTER(aerl_evolve_cfg), _I32, _I32, _P, _P,
+                    C.POINTER(C.c_uint64), C.POINTER(aerl_population_out)], _I32),
+    "aerl_evolve_arena_bytes": ([_P, _I32, C.POINTER(aerl_evolve_cfg), C.POINTER(_SZ)], _I32),
+    "aerl_evolve_create": ([_P, _I32, C.POINTER(aerl_evolve_cfg), _P, _P, C.POINTER(aerl_population),
+                            _P, _SZ, _P, C.POINTER(_I32)], _I32),
+    "aerl_evolve_run": ([_P, _I32, _I32, _P], _I32),
+    "aerl_evolve_state": ([_P, _I32, C.POINTER(aerl_evolve_info)], _I32),
+    "aerl_evolve_save": ([_P, _I32, C.c_char_p], _I32),
+    "aerl_evolve_load": ([_P, _I32, C.c_char_p, _P, _SZ, C.POINTER(_I32)], _I32),
+    "aerl_evolve_release": ([_P, _I32], _I32),
     "aerl_finetune_workspace_bytes": ([_P, _I32, _I32, C.POINTER(_SZ)], _I32),
     "aerl_finetune": ([_P, _I32, _I32, C.POINTER(aerl_finetune_cfg), _P, _P, _P, _P, _P, _SZ, _P],
                       _I32),
@@ -217,6 +252,69 @@ class _HostPop:
             (pop.rule_class, i32), (pop.op, u8), (pop.kind, u8), (pop.f, i32), (pop.g, i32),
             (pop.coef, f32), (pop.coef2, f32), (pop.theta, f32))]
         self.s = aerl_population(pop.n_sets, *[a.ctypes.data for a in self.arrays])
+
+
+def evolve_cfg(pool=100, tournament=3, elite=2, max_rules=8, max_conds=4, ff_frac=0.3,
+               p_crossover=0.5, p_coef=0.2, p_struct=0.3, tune_epochs=0, optimizer="adam",
+               lr=0.01, betas=(0.9, 0.999), eps=1e-8, seed=0) -> aerl_evolve_cfg:
+    """An aerl_evolve_cfg (defaults: the paper's pool of 100)."""
+    tune = aerl_finetune_cfg(0, AERL_OPT_ADAM if optimizer == "adam" else AERL_OPT_SGD, lr,
+                             betas[0], betas[1], eps)
+    return aerl_evolve_cfg(pool, tournament, elite, max_rules, max_conds, ff_frac, p_crossover,
+                           p_coef, p_struct, tune_epochs, tune, seed)
+
+
+class _PoolOut:
+    """Caller-side arrays of a pool the library writes (at capacity)."""
+
+    def __init__(self, cfg: aerl_evolve_cfg):
+        R = cfg.pool * cfg.max_rules
+        K = R * cfg.max_conds
+        i32, u8, f32 = np.int32, np.uint8, np.float32
+        self.a = dict(set_rule_off=np.zeros(cfg.pool + 1, i32), set_default=np.zeros(cfg.pool, i32),
+                      rule_cond_off=np.zeros(R + 1, i32), rule_class=np.zeros(R, i32),
+                      op=np.zeros(K, u8), kind=np.zeros(K, u8), f=np.zeros(K, i32),
+                      g=np.zeros(K, i32), coef=np.zeros(K, f32), coef2=np.zeros(K, f32),
+                      theta=np.zeros(K, f32))
+        self.s = aerl_population_out(0, 0, 0, *[v.ctypes.data for v in self.a.values()])
+
+    def population(self) -> Population:
+        a, s = self.a, self.s
+        return Population(a["set_rule_off"][:s.n_sets + 1].copy(), a["set_default"][:s.n_sets].copy(),
+                          a["rule_cond_off"][:s.n_rules + 1].copy(), a["rule_class"][:s.n_rules].copy(),
+                          *[a[k][:s.n_conds].copy() for k in ("op", "kind", "f", "g", "coef", "coef2",
+                                                               "theta")])
+
+
+def _ranges(lo, hi):
+    return (np.ascontiguousarray(lo, dtype=np.float32), np.ascontiguousarray(hi, dtype=np.float32))
+
+
+def random_pool(cfg: aerl_evolve_cfg, n_features: int, n_classes: int, lo, hi, state: int):
+    """Host-only random pool; returns (Population, new random state)."""
+    lo, hi = _ranges(lo, hi)
+    out = _PoolOut(cfg)
+    st = C.c_uint64(state)
+    rc = aerl_random_pool(C.byref(cfg), n_features, n_classes, lo.ctypes.data, hi.ctypes.data,
+                          C.byref(st), C.byref(out.s))
+    if rc != AERL_OK:
+        raise AerlError(rc, "aerl_random_pool failed")
+    return out.population(), st.value
+
+
+def breed(pop: Population, fitness, cfg: aerl_evolve_cfg, n_features: int, n_classes: int, lo, hi,
+          state: int):
+    """Host-only next generation; returns (Population, new random state)."""
+    lo, hi = _ranges(lo, hi)
+    hp = _HostPop(pop)
+    fit = np.ascontiguousarray(fitness, dtype=np.int32)
+    out = _PoolOut(cfg)
+    st = C.c_uint64(state)
+    rc = aerl_breed(C.byref(hp.s), fit.ctypes.data, C.byref(cfg), n_features, n_classes,
+                    lo.ctypes.data, hi.ctypes.data, C.byref(st), C.byref(out.s))
+    if rc != AERL_OK:
+        raise AerlError(rc, "aerl_breed failed")
+    return out.population(), st.value
 
 
 @dataclass
@@ -462,6 +560,32 @@ class Context:
                                  _ptr(theta), _ptr(hist), _ptr(ws), ws.numel(), _stream(stream)))
         return hist
 
+    def evolve_arena(self, ds: "DeviceDataset", cfg: aerl_evolve_cfg):
+        nb = C.c_size_t()
+        self.check(aerl_evolve_arena_bytes(self.h, ds.id, C.byref(cfg), C.byref(nb)))
+        return torch.empty(max(nb.value, 256), dtype=torch.uint8, device=self.device)
+
+    def evolve(self, ds: "DeviceDataset", cfg: aerl_evolve_cfg, lo, hi, initial=None,
+               stream=None) -> Evolution:
+        """Starts an evolution loop (generation 0 evaluated on return)."""
+        lo, hi = _ranges(lo, hi)
+        arena = self.evolve_arena(ds, cfg)
+        hp = _HostPop(initial) if initial is not None else None
+        eid = C.c_int32()
+        self.check(aerl_evolve_create(self.h, ds.id, C.byref(cfg), lo.ctypes.data, hi.ctypes.data,
+                                      C.byref(hp.s) if hp else None, _ptr(arena), arena.numel(),
+                                      _stream(stream), C.byref(eid)))
+        return Evolution(self, eid.value, arena, ds.n_features)
+
+    def evolve_load(self, ds: "DeviceDataset", path: str, cfg: aerl_evolve_cfg) -> Evolution:
+        """Resumes a checkpointed loop (cfg sizes the arena; the file's own
+        configuration is used)."""
+        arena = self.evolve_arena(ds, cfg)
+        eid = C.c_int32()
+        self.check(aerl_evolve_load(self.h, ds.id, path.encode(), _ptr(arena), arena.numel(),
+                                    C.byref(eid)))
+        return Evolution(self, eid.value, arena, ds.n_features)
+
     def soft_forward_noalloc(self, ds, pop, coef, coef2, theta, loss, stream=None):
         """Soft forward into the caller's ``loss`` tensor using the library's
         per-GPU scratch array (no device allocation in the call)."""
@@ -476,6 +600,47 @@ class Context:
                                       _ptr(dloss), _ptr(g[0]), _ptr(g[1]), _ptr(g[2]), _ptr(ws),
                                       ws.numel(), _stream(stream)))
         return tuple(g)
+
+
+class Evolution:
+    """A running evolution loop on the device; holds its arena."""
+
+    def __init__(self, ctx: "Context", evo_id: int, arena, n_features: int):
+        self.ctx, self.id, self.arena, self.nf = ctx, evo_id, arena, n_features
+
+    def run(self, generations: int, stream=None):
+        self.ctx.check(aerl_evolve_run(self.ctx.h, self.id, generations, _stream(stream)))
+
+    def state(self) -> dict:
+        info = aerl_evolve_info()
+        self.ctx.check(aerl_evolve_state(self.ctx.h, self.id, C.byref(info)))
+        p = info.pool
+        n = p.n_sets
+        view = lambda ptr, cnt, t: np.ctypeslib.as_array(C.cast(ptr, C.POINTER(t)), (cnt,)).copy()
+        rso = view(p.set_rule_off, n + 1, C.c_int32)
+        nr = int(rso[-1])
+        rco = view(p.rule_cond_off, nr + 1, C.c_int32)
+        nk = int(rco[-1])
+        pop = Population(rso, view(p.set_default, n, C.c_int32), rco, view(p.rule_class, nr, C.c_int32),
+                         view(p.op, nk, C.c_uint8), view(p.kind, nk, C.c_uint8),
+                         view(p.f, nk, C.c_int32), view(p.g, nk, C.c_int32),
+                         view(p.coef, nk, C.c_float), view(p.coef2, nk, C.c_float),
+                         view(p.theta, nk, C.c_float))
+        tuned = None
+        if info.tuned_coef:
+            tuned = tuple(view(ptr, nk, C.c_float)
+                          for ptr in (info.tuned_coef, info.tuned_coef2, info.tuned_theta))
+        return dict(generation=info.generation, pool=pop, fitness=view(info.fitness, n, C.c_int32),
+                    tuned=tuned, rng_state=info.rng_state, seconds_eval=info.seconds_eval,
+                    seconds_tune=info.seconds_tune, seconds_breed=info.seconds_breed)
+
+    def save(self, path: str):
+        self.ctx.check(aerl_evolve_save(self.ctx.h, self.id, path.encode()))
+
+    def release(self):
+        if self.id is not None:
+            self.ctx.check(aerl_evolve_release(self.ctx.h, self.id))
+            self.id = None
 
 
 class ServeTicket:

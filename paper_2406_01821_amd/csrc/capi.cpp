@@ -123,6 +123,40 @@ void hard_config(const DatasetRec &ds, int32_t n_sets, int n_cu, int *S, int *Q,
 }  // namespace
 }  // namespace aerl
 
+namespace aerl {
+namespace {
+void set_device_views(PopRec &rec, const PackedLayout &L, void *ws) {
+  char *b = static_cast<char *>(ws);
+  rec.sets = reinterpret_cast<const int4 *>(b + L.sets_off);
+  rec.ssets = reinterpret_cast<const int4 *>(b + L.ssets_off);
+  rec.rules = reinterpret_cast<const int4 *>(b + L.rules_off);
+  rec.hconds = reinterpret_cast<const uint4 *>(b + L.hconds_off);
+  rec.sconds = reinterpret_cast<const uint32_t *>(b + L.sconds_off);
+  rec.heads = reinterpret_cast<const uint4 *>(b + L.heads_off);
+}
+}  // namespace
+
+aerl_status pack_staged(aerl_ctx *ctx, const aerl_population *pop, int32_t nf, int32_t nc, void *ws,
+                        size_t ws_bytes, void *staging, size_t staging_bytes, hipStream_t stream,
+                        int32_t *pop_id) {
+  int32_t n_rules = 0, n_conds = 0;
+  aerl_status st = validate_population(ctx, pop, nf, nc, &n_rules, &n_conds);
+  if (st) return st;
+  const PackedLayout L = packed_layout(pop->n_sets, n_rules, n_conds);
+  if (!ws || ((uintptr_t)ws & 255)) return fail(ctx, AERL_EINVAL, "ws is NULL or not 256-byte aligned");
+  if (ws_bytes < L.total || staging_bytes < L.total)
+    return fail(ctx, AERL_ENOMEM, "ws or staging holds less than the %zu bytes needed", L.total);
+  PopRec rec;
+  pack_population_image(pop, nf, nc, n_rules, n_conds, staging, &rec);
+  AERL_HIP(ctx, hipMemcpyAsync(ws, staging, L.total, hipMemcpyHostToDevice, stream));
+  set_device_views(rec, L, ws);
+  const int32_t id = ctx->next_id++;
+  ctx->pops[id] = rec;  // staging is the caller's: nothing to free on release
+  *pop_id = id;
+  return AERL_OK;
+}
+}  // namespace aerl
+
 using namespace aerl;
 
 extern "C" {
@@ -297,6 +331,7 @@ aerl_status aerl_population_bytes(const aerl_population *pop, int32_t n_features
   return AERL_OK;
 }
 
+
 aerl_status aerl_pack_population(aerl_ctx *ctx, const aerl_population *pop, int32_t nf, int32_t nc,
                                  void *ws, size_t ws_bytes, hipStream_t stream, int32_t *pop_id) {
   if (!ctx) return AERL_EINVAL;
@@ -322,13 +357,7 @@ aerl_status aerl_pack_population(aerl_ctx *ctx, const aerl_population *pop, int3
     (void)hipHostFree(rec.staging);
     return fail(ctx, AERL_EDEVICE, "staging copy failed: %s", hipGetErrorString(e));
   }
-  char *b = static_cast<char *>(ws);
-  rec.sets = reinterpret_cast<const int4 *>(b + L.sets_off);
-  rec.ssets = reinterpret_cast<const int4 *>(b + L.ssets_off);
-  rec.rules = reinterpret_cast<const int4 *>(b + L.rules_off);
-  rec.hconds = reinterpret_cast<const uint4 *>(b + L.hconds_off);
-  rec.sconds = reinterpret_cast<const uint32_t *>(b + L.sconds_off);
-  rec.heads = reinterpret_cast<const uint4 *>(b + L.heads_off);
+  set_device_views(rec, L, ws);
   const int32_t id = ctx->next_id++;
   ctx->pops[id] = rec;
   *pop_id = id;

@@ -147,6 +147,12 @@ struct PlanDeleter {
   void operator()(BatchPlanRec *p) const { destroy_plan(p); }
 };
 
+struct Evo;
+void destroy_evo(Evo *e);
+struct EvoDeleter {
+  void operator()(Evo *e) const { destroy_evo(e); }
+};
+
 }  // namespace aerl
 
 struct aerl_ctx {
@@ -159,6 +165,7 @@ struct aerl_ctx {
   std::unordered_map<int32_t, aerl::PopRec> pops;
   std::unordered_map<int32_t, std::unique_ptr<aerl::BatchPlanRec, aerl::PlanDeleter>> plans;
   std::map<std::string, std::array<int32_t, 3>> tuned;  // batch shape -> (sets, tiles, tile KiB)
+  std::unordered_map<int32_t, std::unique_ptr<aerl::Evo, aerl::EvoDeleter>> evos;
   bool tune_file_loaded = false;
   aerl::Serve *serve = nullptr;
   void *noalloc_scratch = nullptr;  // this device's copy of the no-allocation scratch array
@@ -256,6 +263,20 @@ struct TuneLaunch {
   void *ws;
 };
 hipError_t run_finetune(const TuneLaunch &t, hipStream_t s);
+
+// Evolution loop (evolve.cpp): device arena layout of a run.
+constexpr int32_t kMaxEvolveRules = 64;
+struct EvolveArena {
+  size_t pack_off, pack_bytes, correct_off, param_off, tune_off, tune_bytes, staging_bytes, total;
+  bool tune_ok;
+};
+EvolveArena evolve_arena(const DatasetRec &ds, const aerl_evolve_cfg &c);
+// aerl_pack_population through a caller-owned pinned staging buffer (no
+// per-call host allocation); the caller keeps the staging alive until the
+// copy has completed on stream.
+aerl_status pack_staged(aerl_ctx *ctx, const aerl_population *pop, int32_t nf, int32_t nc, void *ws,
+                        size_t ws_bytes, void *staging, size_t staging_bytes, hipStream_t stream,
+                        int32_t *pop_id);
 
 // Device address of the current device's no-allocation scratch array
 // (AERL_NOALLOC_SCRATCH_BYTES), resolved once per device; the device must be

@@ -548,3 +548,54 @@ def test_large_population_packs_like_each_set_alone(aerl):
         assert list(s1[0][2:]) == list(sets[s][2:])
         np.testing.assert_array_equal(hc[first:first + count], hc1[:count], err_msg=f"set {s}")
         np.testing.assert_array_equal(hd[first:first + count], hd1[:count], err_msg=f"set {s}")
+
+
+def _pool_arrays(pop):
+    return [pop.set_rule_off, pop.set_default, pop.rule_cond_off, pop.rule_class, pop.op, pop.kind,
+            pop.f, pop.g, pop.coef.view(np.uint32), pop.coef2.view(np.uint32),
+            pop.theta.view(np.uint32)]
+
+
+@pytest.mark.parametrize("nf,nc,kw", [(30, 2, {}), (1, 3, dict(ff_frac=1.0)),
+                                      (6, 4, dict(max_rules=1, max_conds=1, elite=0)),
+                                      (9, 2, dict(p_crossover=1.0, p_struct=1.0, tournament=1))])
+def test_breeding_matches_the_reference_bit_for_bit(aerl, nf, nc, kw):
+    """The library's host-side random pool and next generation (SplitMix64
+    draws, tournament selection, crossover, coefficient and structure
+    mutation) against oracle/evolve.py over eight generations of arbitrary
+    fitness: identical pools, float bits included, and random states."""
+    from oracle import evolve as ev
+    from paper_2406_01821_amd.population import from_rule_lists
+    c = dict(pool=24, tournament=3, elite=2, max_rules=6, max_conds=4, ff_frac=0.3,
+             p_crossover=0.5, p_coef=0.3, p_struct=0.6)
+    c.update(kw)
+    cfg = aerl.evolve_cfg(**c, seed=11)
+    rng = np.random.default_rng(nf)
+    lo = rng.normal(size=nf).astype(np.float32)
+    hi = (lo + rng.random(nf) * 5).astype(np.float32)
+    pop, state = aerl.random_pool(cfg, nf, nc, lo, hi, 11)
+    r = ev.SplitMix64(11)
+    ref = ev.random_pool(r, c, nf, nc, lo, hi)
+    for gen in range(8):
+        want = from_rule_lists(ev.to_rule_lists(ref))
+        for a, b in zip(_pool_arrays(pop), _pool_arrays(want)):
+            np.testing.assert_array_equal(a, b)
+        assert state == r.state
+        fit = np.random.default_rng(100 + gen).integers(0, 40, size=c["pool"]).astype(np.int32)
+        pop, state = aerl.breed(pop, fit, cfg, nf, nc, lo, hi, state)
+        ref = ev.next_generation(r, ref, fit, c, nf, nc, lo, hi)
+
+
+def test_breeding_rejects_bad_input(aerl):
+    cfg = aerl.evolve_cfg(pool=4, max_rules=2, max_conds=2)
+    lo, hi = np.zeros(3, np.float32), np.ones(3, np.float32)
+    pop, st = aerl.random_pool(cfg, 3, 2, lo, hi, 1)
+    with pytest.raises(aerl.AerlError):
+        aerl.breed(pop, np.zeros(3, np.int32), aerl.evolve_cfg(pool=3, max_rules=2, max_conds=2),
+                   3, 2, lo, hi, st)
+    with pytest.raises(aerl.AerlError):
+        aerl.random_pool(aerl.evolve_cfg(pool=4, elite=4), 3, 2, lo, hi, 1)
+    with pytest.raises(aerl.AerlError):
+        aerl.random_pool(cfg, 3, 2, hi, lo - 1, 1)
+    with pytest.raises(aerl.AerlError):
+        aerl.random_pool(aerl.evolve_cfg(pool=4, max_rules=100), 3, 2, lo, hi, 1)
