@@ -8,5 +8,6 @@ pin the C code on tiny inputs.
 """
 from .oracle import (  # noqa: F401
     build, lib_path, hard_eval, predict, workcount, tau, soft_forward, soft_forward_naive,
-    soft_backward, soft_logprobs, max_threads, label_grouped_tiles,
+    soft_backward, soft_logprobs, max_threads, label_grouped_tiles, smax_probs, smax_forward,
+    smax_backward,
 )

@@ -425,3 +425,144 @@ int orc_soft_backward(int64_t n, int32_t nf, const float *x, const int32_t *y, c
   }
   return bad ? -2 : 0;
 }
+
+/* ------------------------------------------------------------ softmax head
+ * Section 5 names probabilistic outputs through a softmax activation as a
+ * variant.  Reading: every rule votes for its class with its soft truth
+ * r_k = prod_j sigmoid(z_kj), the default class receives the probability
+ * that no rule fires, D = prod_k (1 - r_k):
+ *   v_c = sum_{k: class_k = c} r_k + [c = default] * D,
+ *   P_c = exp(beta * v_c) / sum_c' exp(beta * v_c'),
+ * L = min(-log P_y, 100), loss = mean over samples.  Unlike the first-firing
+ * relaxation, the order of the rules does not matter. */
+
+static void smax_votes(const orc_population *p, const double *coef, const double *coef2,
+                       const double *theta, int32_t s, const float *xr, const float *tau,
+                       int32_t nc, double *v, double *r) {
+  for (int c = 0; c < nc; ++c) v[c] = 0.0;
+  double none = 1.0;
+  int32_t k0 = p->set_rule_off[s];
+  for (int32_t k = k0; k < p->set_rule_off[s + 1]; ++k) {
+    double lr = 0.0;
+    for (int32_t j = p->rule_cond_off[k]; j < p->rule_cond_off[k + 1]; ++j)
+      lr += log_sigmoid(cond_z(p, coef, coef2, theta, j, xr, tau));
+    double rk = exp(lr);
+    v[p->rule_class[k]] += rk;
+    none *= 1.0 - rk;
+    if (r) r[k - k0] = rk;
+  }
+  v[p->set_default[s]] += none;
+}
+
+/* log P_c for every class from the votes. */
+static void smax_logp(const double *v, int32_t nc, double beta, double *logp) {
+  double m = -INFINITY;
+  for (int c = 0; c < nc; ++c)
+    if (beta * v[c] > m) m = beta * v[c];
+  double sum = 0.0;
+  for (int c = 0; c < nc; ++c) sum += exp(beta * v[c] - m);
+  for (int c = 0; c < nc; ++c) logp[c] = beta * v[c] - m - log(sum);
+}
+
+/* Class probabilities of rule set s for every sample: probs[n][nc]. */
+int orc_smax_probs(int64_t n, int32_t nf, const float *x, const float *tau, int32_t nc,
+                   const orc_population *p, const double *coef, const double *coef2,
+                   const double *theta, int32_t s, double beta, double *probs) {
+  if (nc > MAX_CLASSES) return -1;
+  double v[MAX_CLASSES], lp[MAX_CLASSES];
+  for (int64_t i = 0; i < n; ++i) {
+    smax_votes(p, coef, coef2, theta, s, x + i * nf, tau, nc, v, NULL);
+    smax_logp(v, nc, beta, lp);
+    for (int c = 0; c < nc; ++c) probs[i * nc + c] = exp(lp[c]);
+  }
+  return 0;
+}
+
+int orc_smax_forward(int64_t n, int32_t nf, const float *x, const int32_t *y, const float *tau,
+                     int32_t nc, const orc_population *p, const double *coef, const double *coef2,
+                     const double *theta, double beta, double *loss, int nthreads) {
+  if (nc > MAX_CLASSES) return -1;
+  const int nt = pick_threads(nthreads);
+  (void)nt;
+#pragma omp parallel for schedule(static) num_threads(nt)
+  for (int32_t s = 0; s < p->n_sets; ++s) {
+    double v[MAX_CLASSES], lp[MAX_CLASSES];
+    double acc = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+      smax_votes(p, coef, coef2, theta, s, x + i * nf, tau, nc, v, NULL);
+      smax_logp(v, nc, beta, lp);
+      double L = -lp[y[i]];
+      acc += L > LOSS_CAP ? LOSS_CAP : L;
+    }
+    loss[s] = n > 0 ? acc / (double)n : 0.0;
+  }
+  return 0;
+}
+
+/* Gradient of sum_s dloss[s] * loss[s] under the softmax head, by the chain
+ * rule written out: dL/dv_c = beta (P_c - [c = y]);
+ * dL/dr_k = dL/dv_{class_k} - dL/dv_default * prod_{i != k} (1 - r_i);
+ * dL/dz_kj = dL/dr_k * r_k * sigmoid(-z_kj); clamped samples contribute
+ * nothing. */
+int orc_smax_backward(int64_t n, int32_t nf, const float *x, const int32_t *y, const float *tau,
+                      int32_t nc, const orc_population *p, const double *coef,
+                      const double *coef2, const double *theta, double beta, const double *dloss,
+                      double *dcoef, double *dcoef2, double *dtheta, int nthreads) {
+  if (nc > MAX_CLASSES) return -1;
+  int32_t n_conds = p->rule_cond_off[p->set_rule_off[p->n_sets]];
+  memset(dcoef, 0, sizeof(double) * (size_t)n_conds);
+  memset(dcoef2, 0, sizeof(double) * (size_t)n_conds);
+  memset(dtheta, 0, sizeof(double) * (size_t)n_conds);
+  int32_t max_r = 0;
+  for (int32_t s = 0; s < p->n_sets; ++s) {
+    int32_t r = p->set_rule_off[s + 1] - p->set_rule_off[s];
+    if (r > max_r) max_r = r;
+  }
+  const int nt = pick_threads(nthreads);
+  (void)nt;
+  int bad = 0;
+#pragma omp parallel num_threads(nt)
+  {
+    double *r = (double *)malloc(sizeof(double) * (size_t)(max_r + 1));
+    double v[MAX_CLASSES], lp[MAX_CLASSES], g[MAX_CLASSES];
+    if (!r) {
+#pragma omp atomic write
+      bad = 1;
+    }
+#pragma omp for schedule(static)
+    for (int32_t s = 0; s < p->n_sets; ++s) {
+      if (!r) continue;
+      int32_t k0 = p->set_rule_off[s], R = p->set_rule_off[s + 1] - k0;
+      double scale = n > 0 ? dloss[s] / (double)n : 0.0;
+      for (int64_t i = 0; i < n; ++i) {
+        const float *xr = x + i * nf;
+        smax_votes(p, coef, coef2, theta, s, xr, tau, nc, v, r);
+        smax_logp(v, nc, beta, lp);
+        if (-lp[y[i]] > LOSS_CAP) continue;
+        for (int c = 0; c < nc; ++c) g[c] = beta * (exp(lp[c]) - (c == y[i] ? 1.0 : 0.0));
+        for (int32_t k = 0; k < R; ++k) {
+          double others = 1.0;
+          for (int32_t m = 0; m < R; ++m)
+            if (m != k) others *= 1.0 - r[m];
+          double dr = g[p->rule_class[k0 + k]] - g[p->set_default[s]] * others;
+          if (dr == 0.0 || r[k] == 0.0) continue;
+          int32_t kk = k0 + k;
+          for (int32_t j = p->rule_cond_off[kk]; j < p->rule_cond_off[kk + 1]; ++j) {
+            double z = cond_z(p, coef, coef2, theta, j, xr, tau);
+            double dz = dr * r[k] * exp(log_sigmoid(-z));
+            int f = p->f[j];
+            double st = cond_sign(p->op[j]) / (double)tau[f];
+            dcoef[j] += scale * dz * st * (double)xr[f];
+            double t2 = -scale * dz * st * (p->kind[j] ? (double)xr[p->g[j]] : 1.0);
+            if (p->kind[j])
+              dcoef2[j] += t2;
+            else
+              dtheta[j] += t2;
+          }
+        }
+      }
+    }
+    free(r);
+  }
+  return bad ? -2 : 0;
+}

@@ -60,6 +60,11 @@ def _load():
             "orc_soft_forward": ([I64, I32, P, P, P, I32, PP, P, P, P, P, C.c_int], C.c_int),
             "orc_soft_forward_naive": ([I64, I32, P, P, P, I32, PP, P, P, P, P], C.c_int),
             "orc_soft_backward": ([I64, I32, P, P, P, I32, PP, P, P, P, P, P, P, P, C.c_int], C.c_int),
+            "orc_smax_probs": ([I64, I32, P, P, I32, PP, P, P, P, I32, C.c_double, P], C.c_int),
+            "orc_smax_forward": ([I64, I32, P, P, P, I32, PP, P, P, P, C.c_double, P, C.c_int],
+                                 C.c_int),
+            "orc_smax_backward": ([I64, I32, P, P, P, I32, PP, P, P, P, C.c_double, P, P, P, P,
+                                   C.c_int], C.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(lib, name)
@@ -222,3 +227,45 @@ def soft_backward(x, y, tau_, n_classes, pop, dloss=None, coef=None, coef2=None,
                                    _ptr(g2), _ptr(g3), nthreads)
     assert rc == 0
     return g1, g2, g3
+
+
+# ---------------------------------------------------------------- softmax head
+def smax_probs(x, tau_, n_classes, pop, s, beta, coef=None, coef2=None, theta=None):
+    """fp64 class probabilities [n][C] of rule set s under the softmax head."""
+    x, _ = _xy(x)
+    v = _PopView(pop)
+    c1, c2, th = _params(pop, coef, coef2, theta)
+    t = np.ascontiguousarray(tau_, np.float32)
+    out = np.zeros((x.shape[0], n_classes), np.float64)
+    assert _load().orc_smax_probs(x.shape[0], x.shape[1], _ptr(x), _ptr(t), n_classes, v.ref(),
+                                  _ptr(c1), _ptr(c2), _ptr(th), s, float(beta), _ptr(out)) == 0
+    return out
+
+
+def smax_forward(x, y, tau_, n_classes, pop, beta, coef=None, coef2=None, theta=None, nthreads=0):
+    """fp64 loss per rule set under the softmax head."""
+    x, y = _xy(x, y)
+    v = _PopView(pop)
+    c1, c2, th = _params(pop, coef, coef2, theta)
+    t = np.ascontiguousarray(tau_, np.float32)
+    loss = np.zeros(v.n_sets, np.float64)
+    assert _load().orc_smax_forward(x.shape[0], x.shape[1], _ptr(x), _ptr(y), _ptr(t), n_classes,
+                                    v.ref(), _ptr(c1), _ptr(c2), _ptr(th), float(beta),
+                                    _ptr(loss), nthreads) == 0
+    return loss
+
+
+def smax_backward(x, y, tau_, n_classes, pop, beta, dloss=None, coef=None, coef2=None, theta=None,
+                  nthreads=0):
+    """fp64 gradients (dcoef, dcoef2, dtheta) of sum_s dloss[s] * loss[s] under
+    the softmax head."""
+    x, y = _xy(x, y)
+    v = _PopView(pop)
+    c1, c2, th = _params(pop, coef, coef2, theta)
+    t = np.ascontiguousarray(tau_, np.float32)
+    dl = np.ascontiguousarray(np.ones(v.n_sets) if dloss is None else dloss, np.float64)
+    g = [np.zeros(v.n_conds, np.float64) for _ in range(3)]
+    assert _load().orc_smax_backward(x.shape[0], x.shape[1], _ptr(x), _ptr(y), _ptr(t), n_classes,
+                                     v.ref(), _ptr(c1), _ptr(c2), _ptr(th), float(beta), _ptr(dl),
+                                     _ptr(g[0]), _ptr(g[1]), _ptr(g[2]), nthreads) == 0
+    return tuple(g)
