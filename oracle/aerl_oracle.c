@@ -56,10 +56,22 @@ typedef struct {
   const int32_t *rule_cond_off; /* [n_rules+1] */
   const int32_t *rule_class;    /* [n_rules] */
   const uint8_t *op;            /* [n_conds] 0 <, 1 <=, 2 >, 3 >= */
-  const uint8_t *kind;          /* [n_conds] 0 threshold, 1 feature-vs-feature */
+  const uint8_t *kind;          /* [n_conds] 0 threshold, 1 feature-vs-feature, 2 categorical */
   const int32_t *f, *g;         /* [n_conds] */
   const float *coef, *coef2, *theta; /* [n_conds] */
+  const uint64_t *cat_mask;     /* [n_conds], categorical conditions only (may be NULL) */
 } orc_population;
+
+/* Categorical condition (Section 5 names categorical features as an
+ * extension).  Reading: the feature holds category codes 0..63 as floats;
+ * the condition holds when x[f] is exactly one of the codes in the set
+ * (bit k of cat_mask for code k).  Any other value (a fraction, a negative,
+ * 64 and above, an infinity, NaN) is in no set.  Equality is a one-code set. */
+static int category_member(uint64_t mask, float v) {
+  if (!(v >= 0.0f && v <= 63.0f)) return 0;
+  if (v != floorf(v)) return 0;
+  return (int)((mask >> (int)v) & 1u);
+}
 
 int orc_max_threads(void) {
 #ifdef _OPENMP
@@ -96,6 +108,7 @@ static int compare(int op, float lhs, float rhs) {
 /* Truth of condition j on sample row xr (Section 3: one row of the rule
  * tensor against one sample).  Each product is rounded to float once. */
 static int condition_holds(const orc_population *p, int64_t j, const float *xr) {
+  if (p->kind[j] == 2) return category_member(p->cat_mask[j], xr[p->f[j]]);
   float lhs = p->coef[j] * xr[p->f[j]];
   float rhs = p->kind[j] ? p->coef2[j] * xr[p->g[j]] : p->theta[j];
   return compare(p->op[j], lhs, rhs);
@@ -179,7 +192,7 @@ int orc_workcount(int64_t n_tiles, const int64_t *tile_ptr, const int64_t *tile_
             int64_t n_alive = 0;
             for (int64_t i = 0; i < m; ++i) { alive[i] = undecided[i]; n_alive += alive[i]; }
             for (int32_t j = p->rule_cond_off[k]; j < p->rule_cond_off[k + 1] && n_alive > 0; ++j) {
-              if (p->kind[j]) ++wf; else ++wt;
+              if (p->kind[j] == 1) ++wf; else ++wt;
               n_alive = 0;
               for (int64_t i = 0; i < m; ++i) {
                 if (alive[i]) {
@@ -248,6 +261,9 @@ static double cond_sign(int op) { return op >= 2 ? 1.0 : -1.0; }
 static double cond_z(const orc_population *p, const double *coef, const double *coef2,
                      const double *theta, int64_t j, const float *xr, const float *tau) {
   int f = p->f[j];
+  /* a categorical condition has no parameter to relax: its soft truth is
+   * its truth, sigmoid(+inf) = 1 or sigmoid(-inf) = 0 */
+  if (p->kind[j] == 2) return category_member(p->cat_mask[j], xr[f]) ? INFINITY : -INFINITY;
   double lhs = coef[j] * (double)xr[f];
   double rhs = p->kind[j] ? coef2[j] * (double)xr[p->g[j]] : theta[j];
   return cond_sign(p->op[j]) * (lhs - rhs) / (double)tau[f];
@@ -404,14 +420,15 @@ int orc_soft_backward(int64_t n, int32_t nf, const float *x, const int32_t *y, c
           if (g == 0.0) continue;
           int32_t kk = k0 + k;
           for (int32_t j = p->rule_cond_off[kk]; j < p->rule_cond_off[kk + 1]; ++j) {
+            if (p->kind[j] == 2) continue; /* no parameters */
             double z = cond_z(p, coef, coef2, theta, j, xr, tau);
             double dz = g * exp(log_sigmoid(-z)); /* dL/dz = dL/da * sigmoid(-z) */
             int f = p->f[j];
             double st = cond_sign(p->op[j]) / (double)tau[f];
             double tc = scale * dz * st * (double)xr[f];
-            double t2 = -scale * dz * st * (p->kind[j] ? (double)xr[p->g[j]] : 1.0);
+            double t2 = -scale * dz * st * (p->kind[j] == 1 ? (double)xr[p->g[j]] : 1.0);
             dcoef[j] += tc;
-            if (p->kind[j])
+            if (p->kind[j] == 1)
               dcoef2[j] += t2;
             else
               dtheta[j] += t2;
@@ -548,13 +565,14 @@ int orc_smax_backward(int64_t n, int32_t nf, const float *x, const int32_t *y, c
           if (dr == 0.0 || r[k] == 0.0) continue;
           int32_t kk = k0 + k;
           for (int32_t j = p->rule_cond_off[kk]; j < p->rule_cond_off[kk + 1]; ++j) {
+            if (p->kind[j] == 2) continue; /* no parameters */
             double z = cond_z(p, coef, coef2, theta, j, xr, tau);
             double dz = dr * r[k] * exp(log_sigmoid(-z));
             int f = p->f[j];
             double st = cond_sign(p->op[j]) / (double)tau[f];
             dcoef[j] += scale * dz * st * (double)xr[f];
-            double t2 = -scale * dz * st * (p->kind[j] ? (double)xr[p->g[j]] : 1.0);
-            if (p->kind[j])
+            double t2 = -scale * dz * st * (p->kind[j] == 1 ? (double)xr[p->g[j]] : 1.0);
+            if (p->kind[j] == 1)
               dcoef2[j] += t2;
             else
               dtheta[j] += t2;

@@ -60,7 +60,18 @@ def theta_value(t) -> Fraction:
     return Fraction(t)
 
 
+def category_code(v):
+    """The category code an exact float value names (0..63), else None."""
+    q = Fraction(float(v)) if np.isfinite(v) else None
+    if q is None or q.denominator != 1 or not 0 <= q <= 63:
+        return None
+    return int(q)
+
+
 def condition(cond, row) -> bool:
+    if cond["kind"] == 2:
+        code = category_code(row[cond["f"]])
+        return code is not None and (int(cond.get("mask", 0)) >> code) & 1 == 1
     lhs = product_f32(cond["coef"], row[cond["f"]])
     if cond["kind"] == 1:
         rhs = product_f32(cond["coef2"], row[cond["g"]])

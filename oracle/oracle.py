@@ -37,7 +37,8 @@ class _Pop(C.Structure):
                 ("set_rule_off", C.c_void_p), ("set_default", C.c_void_p),
                 ("rule_cond_off", C.c_void_p), ("rule_class", C.c_void_p),
                 ("op", C.c_void_p), ("kind", C.c_void_p), ("f", C.c_void_p), ("g", C.c_void_p),
-                ("coef", C.c_void_p), ("coef2", C.c_void_p), ("theta", C.c_void_p)]
+                ("coef", C.c_void_p), ("coef2", C.c_void_p), ("theta", C.c_void_p),
+                ("cat_mask", C.c_void_p)]
 
 
 _lib = None
@@ -90,10 +91,13 @@ class _PopView:
             f=np.ascontiguousarray(pop.f, np.int32), g=np.ascontiguousarray(pop.g, np.int32),
             coef=np.ascontiguousarray(pop.coef, np.float32),
             coef2=np.ascontiguousarray(pop.coef2, np.float32),
-            theta=np.ascontiguousarray(pop.theta, np.float32))
+            theta=np.ascontiguousarray(pop.theta, np.float32),
+            cat_mask=np.ascontiguousarray(getattr(pop, "cat_mask", None)
+                                          if getattr(pop, "cat_mask", None) is not None
+                                          else np.zeros(len(pop.op), np.uint64), np.uint64))
         self.s = _Pop(int(pop.set_default.shape[0]), *[_ptr(self.arrays[k]) for k in (
             "set_rule_off", "set_default", "rule_cond_off", "rule_class", "op", "kind", "f", "g",
-            "coef", "coef2", "theta")])
+            "coef", "coef2", "theta", "cat_mask")])
         self.n_sets = int(pop.set_default.shape[0])
         self.n_conds = int(pop.op.shape[0])
 

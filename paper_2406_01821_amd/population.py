@@ -21,7 +21,7 @@ Nothing here evaluates a rule; the containers only hold and reshape arrays.
 from __future__ import annotations
 
 from dataclasses import dataclass, field
-from typing import List, Sequence
+from typing import Optional, List, Sequence
 
 import numpy as np
 
@@ -65,6 +65,7 @@ class Population:
     coef2: np.ndarray          # float32 [n_conds]
     theta: np.ndarray          # float32 [n_conds]
     meta: dict = field(default_factory=dict)
+    cat_mask: Optional[np.ndarray] = None  # uint64 [n_conds]: code set of kind-2 conditions
 
     def __post_init__(self):
         i32 = lambda a: np.ascontiguousarray(a, dtype=np.int32)
@@ -77,6 +78,8 @@ class Population:
         self.op, self.kind = u8(self.op), u8(self.kind)
         self.f, self.g = i32(self.f), i32(self.g)
         self.coef, self.coef2, self.theta = f32(self.coef), f32(self.coef2), f32(self.theta)
+        self.cat_mask = (np.zeros(self.op.shape[0], np.uint64) if self.cat_mask is None
+                         else np.ascontiguousarray(self.cat_mask, dtype=np.uint64))
 
     @property
     def n_sets(self) -> int:
@@ -112,9 +115,12 @@ class Population:
         for r in self.rules_of(s):
             conds = []
             for j in self.conds_of(r):
-                conds.append(dict(op=int(self.op[j]), kind=int(self.kind[j]), f=int(self.f[j]),
-                                  g=int(self.g[j]), coef=np.float32(self.coef[j]),
-                                  coef2=np.float32(self.coef2[j]), theta=np.float32(self.theta[j])))
+                d = dict(op=int(self.op[j]), kind=int(self.kind[j]), f=int(self.f[j]),
+                         g=int(self.g[j]), coef=np.float32(self.coef[j]),
+                         coef2=np.float32(self.coef2[j]), theta=np.float32(self.theta[j]))
+                if self.kind[j] == 2:
+                    d["mask"] = int(self.cat_mask[j])
+                conds.append(d)
             rules.append((int(self.rule_class[r]), conds))
         return int(self.set_default[s]), rules
 
@@ -124,7 +130,7 @@ class Population:
                           self.rule_cond_off.copy(), self.rule_class.copy(), self.op.copy(),
                           self.kind.copy(), self.f.copy(), self.g.copy(),
                           np.asarray(coef, np.float32), np.asarray(coef2, np.float32),
-                          np.asarray(theta, np.float32), dict(self.meta))
+                          np.asarray(theta, np.float32), dict(self.meta), self.cat_mask.copy())
 
     def conds_kind_first(self) -> "Population":
         """Same rule sets with each rule's conditions stably reordered so that
@@ -138,7 +144,8 @@ class Population:
         return Population(self.set_rule_off.copy(), self.set_default.copy(),
                           self.rule_cond_off.copy(), self.rule_class.copy(),
                           self.op[perm], self.kind[perm], self.f[perm], self.g[perm],
-                          self.coef[perm], self.coef2[perm], self.theta[perm], dict(self.meta))
+                          self.coef[perm], self.coef2[perm], self.theta[perm], dict(self.meta),
+                          self.cat_mask[perm])
 
 
 def from_rule_lists(sets: List) -> Population:
@@ -146,7 +153,7 @@ def from_rule_lists(sets: List) -> Population:
     where each cond is a dict with keys op, kind, f, g, coef, coef2, theta
     (missing keys default to 0)."""
     set_rule_off, set_default, rule_cond_off, rule_class = [0], [], [0], []
-    cols = {k: [] for k in ("op", "kind", "f", "g", "coef", "coef2", "theta")}
+    cols = {k: [] for k in ("op", "kind", "f", "g", "coef", "coef2", "theta", "mask")}
     for default, rules in sets:
         set_default.append(int(default))
         for cls, conds in rules:
@@ -161,7 +168,8 @@ def from_rule_lists(sets: List) -> Population:
                       np.array(cols["op"], dtype=np.uint8), np.array(cols["kind"], dtype=np.uint8),
                       np.array(cols["f"], dtype=np.int32), np.array(cols["g"], dtype=np.int32),
                       np.array(cols["coef"], dtype=np.float32), np.array(cols["coef2"], dtype=np.float32),
-                      np.array(cols["theta"], dtype=np.float32))
+                      np.array(cols["theta"], dtype=np.float32), {},
+                      np.array([int(m) for m in cols["mask"]], dtype=np.uint64))
 
 
 def concat(pops: Sequence[Population]) -> Population:

@@ -197,6 +197,59 @@ def soft_workload(seed: int = 3, n: int = 262_144, nf: int = 32, n_sets: int = 1
     return Workload(Dataset(x, y, 2, f"{n}x{nf}"), pop, f"soft-{n}x{nf}-P{n_sets}")
 
 
+def categorical_population(rng: np.random.Generator, x: np.ndarray, cat_cols: int, n_codes: int,
+                           n_sets: int, rules: tuple, conds: tuple, n_classes: int,
+                           cat_frac: float = 0.3, ff_frac: float = 0.2) -> Population:
+    """Random rule sets over a table whose last ``cat_cols`` columns hold
+    category codes 0..n_codes-1: a random population of the numeric columns
+    (``random_population``), then each condition, with probability
+    ``cat_frac``, becomes categorical on a uniform categorical column with a
+    random code set (each code in with probability 1/2; one code, an
+    equality test, with probability 1/4).  Draws after the population: per
+    condition u (categorical?), column, equality?, code, set bits."""
+    nf = x.shape[1]
+    num = nf - cat_cols
+    pop = random_population(rng, x[:, :num], n_sets, rules, conds, n_classes, ff_frac)
+    K = pop.n_conds
+    make = rng.random(K) < cat_frac
+    col = num + rng.integers(0, cat_cols, size=K)
+    eq = rng.random(K) < 0.25
+    code = rng.integers(0, n_codes, size=K)
+    bits = rng.integers(0, 2, size=(K, n_codes)).astype(np.uint64)
+    weights = np.uint64(1) << np.arange(n_codes, dtype=np.uint64)
+    sets_mask = (bits * weights).sum(axis=1).astype(np.uint64)
+    mask = np.where(eq, np.uint64(1) << code.astype(np.uint64), sets_mask).astype(np.uint64)
+    kind = np.where(make, 2, pop.kind).astype(np.uint8)
+    f = np.where(make, col, pop.f).astype(np.int32)
+    g = np.where(make, 0, pop.g).astype(np.int32)
+    coef = np.where(make, np.float32(0), pop.coef).astype(np.float32)
+    coef2 = np.where(make, np.float32(0), pop.coef2).astype(np.float32)
+    theta = np.where(make, np.float32(0), pop.theta).astype(np.float32)
+    return Population(pop.set_rule_off, pop.set_default, pop.rule_cond_off, pop.rule_class, pop.op,
+                      kind, f, g, coef, coef2, theta, {}, np.where(make, mask, 0).astype(np.uint64))
+
+
+def categorical_workload(seed: int = 5, n: int = 1 << 18, n_num: int = 24, cat_cols: int = 8,
+                         n_codes: int = 12, n_classes: int = 3, n_sets: int = 1024,
+                         rules=(1, 16), conds=(1, 4)) -> Workload:
+    """A table of log-normal numeric columns followed by ``cat_cols``
+    categorical columns of codes 0..n_codes-1 (Zipf-like code frequencies,
+    stored as float32); labels planted on the numeric columns with the code
+    of the first categorical column mixed in; rule sets with 30%
+    categorical conditions."""
+    rng = np.random.default_rng(seed)
+    xn = lognormal_features(rng, n, n_num)
+    w = 1.0 / np.arange(1, n_codes + 1)
+    codes = rng.choice(n_codes, size=(n, cat_cols), p=w / w.sum()).astype(np.float32)
+    x = np.concatenate([xn, codes], axis=1)
+    y = planted_labels(xn, n_classes, 6, (1, 3), 0.03, seed)
+    flip = codes[:, 0] == 0
+    y = np.where(flip, (y + 1) % n_classes, y).astype(np.int32)
+    pop = categorical_population(rng, x, cat_cols, n_codes, n_sets, rules, conds, n_classes)
+    return Workload(Dataset(x, y, n_classes, f"{n}x{n_num}+{cat_cols}cat"), pop,
+                    f"categorical-{n}x{n_num + cat_cols}-P{n_sets}")
+
+
 def tiny(seed: int, n: int = 100, nf: int = 8, n_classes: int = 2, n_sets: int = 20,
          rules=(1, 6), conds=(1, 4), ff_frac: float = 0.3) -> Workload:
     """Small random case for tests (labels uniform, no planting)."""
