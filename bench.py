@@ -344,6 +344,69 @@ def bench_evolve(ctx, cpu, gens=20, tune_gens=5, epochs=50):
     return out
 
 
+def bench_softmax(ctx, steps, warmup, beta=2.0):
+    """The softmax head on the soft workload: forward and adjoint rates."""
+    import torch
+    from paper_2406_01821_amd import synth
+    w = synth.soft_workload(3)
+    ds = ctx.upload_dataset(w.data)
+    pop = ctx.pack_population(w.pop, w.data.n_features, w.data.n_classes)
+    c1, c2, th = [torch.tensor(a, device=ctx.device) for a in (w.pop.coef, w.pop.coef2, w.pop.theta)]
+    wsf = ctx.soft_workspace(ds, pop, False)
+    wsb = ctx.soft_workspace(ds, pop, True)
+    dl = torch.ones(w.pop.n_sets, device=ctx.device)
+    stream = torch.cuda.current_stream()
+    fwd_ms, _ = timed(lambda: ctx.softmax_forward(ds, pop, c1, c2, th, beta, ws=wsf), steps, warmup,
+                      stream)
+    bwd_ms, _ = timed(lambda: ctx.softmax_backward(ds, pop, c1, c2, th, beta, dl, ws=wsb), steps,
+                      warmup, stream)
+    n = w.data.n
+    conds = int(w.pop.nominal_conds_per_set().sum()) * n
+    rules = w.pop.n_rules * n
+    nc = 2
+    # per rule: the first-firing rule cost minus its class log-sum-exp, plus
+    # one exponential and nc selects for the vote
+    rule_fwd = 10 + 3 * TRANS + nc
+    fwd_slots = float(SOFT_FWD_COND * conds + rule_fwd * rules)
+    bwd_slots = fwd_slots + float(SOFT_BWD_COND * conds + (1 * TRANS + 2 * nc + 4) * rules)
+    ctx.release_population(pop)
+    ctx.release_dataset(ds)
+    log(f"softmax head: forward {fwd_ms:.3f} ms, backward {bwd_ms:.3f} ms")
+    rl = lambda slots, ms: {"bound": "alu", "achieved": slots / (ms * 1e-3) / 1e12,
+                            "peak": VALU_PEAK / 1e12, "unit": "Tlane-op/s",
+                            "frac": slots / (ms * 1e-3) / VALU_PEAK}
+    return {"workload": "softmax head (beta 2), 262,144 x 32 fp32 samples, 2 classes, 1024 rule "
+                        "sets x 16 rules x 4 threshold conditions",
+            "forward": {"ms": fwd_ms, "cond_evals_per_s": conds / (fwd_ms * 1e-3),
+                        "roofline": rl(fwd_slots, fwd_ms)},
+            "backward": {"ms": bwd_ms, "cond_evals_per_s": conds / (bwd_ms * 1e-3),
+                         "roofline": rl(bwd_slots, bwd_ms)}}
+
+
+def bench_categorical(ctx, steps, warmup):
+    """Hard fitness on a table with categorical columns: 2^18 samples x (24
+    numeric + 8 categorical) columns, 3 classes, 1024 rule sets with 30%
+    categorical conditions (code-set tests)."""
+    import torch
+    from paper_2406_01821_amd import synth
+    w = synth.categorical_workload(5)
+    ds = ctx.upload_dataset(w.data)
+    pop = ctx.pack_population(w.pop, w.data.n_features, w.data.n_classes)
+    out = ctx.eval_population(ds, pop)
+    stream = torch.cuda.current_stream()
+    ms, wall = timed(lambda: ctx.eval_population(ds, pop, out=out), steps, warmup, stream)
+    nominal = int(w.pop.nominal_conds_per_set().sum()) * w.data.n
+    ctx.release_population(pop)
+    ctx.release_dataset(ds)
+    log(f"categorical: {ms:.3f} ms per pass")
+    return {"workload": "hard fitness, 2^18 x (24 numeric + 8 categorical) fp32 columns, 3 "
+                        "classes, 1024 rule sets x 1-16 rules x 1-4 conditions, 30% categorical "
+                        "(code sets over 12 codes), 20% feature-vs-feature",
+            "ms": ms, "wall_ms": wall, "nominal_cond_evals": nominal,
+            "cond_evals_per_s": nominal / (wall * 1e-3),
+            "categorical_conditions": int((w.pop.kind == 2).sum()), "conditions": w.pop.n_conds}
+
+
 def bench_soft(ctx, steps, warmup, cpu):
     import torch
     import oracle
@@ -616,6 +679,8 @@ def main():
         fn = {"c1": lambda: bench_c1(ctx, args.steps, args.warmup, not args.no_cpu),
               "finetune": lambda: bench_finetune(ctx),
               "evolve": lambda: bench_evolve(ctx, not args.no_cpu),
+              "softmax": lambda: bench_softmax(ctx, max(3, args.steps // 4), 1),
+              "categorical": lambda: bench_categorical(ctx, args.steps, args.warmup),
               "soft": lambda: bench_soft(ctx, max(3, args.steps // 4), 1, not args.no_cpu)}
         print(json.dumps({args.only: fn[args.only]()}), flush=True)
         ctx.close()
@@ -673,6 +738,8 @@ def main():
     if not args.only_hard:
         result["soft"] = bench_soft(ctx, max(3, args.steps // 4), 1, not args.no_cpu)
         result["finetune"] = bench_finetune(ctx)
+        result["softmax"] = bench_softmax(ctx, max(3, args.steps // 4), 1)
+        result["categorical"] = bench_categorical(ctx, args.steps, args.warmup)
         result["ragged"] = bench_ragged(ctx, max(3, args.steps // 4), 1)
         result["c1"] = bench_c1(ctx, args.steps, args.warmup, not args.no_cpu)
         result["evolution"] = bench_evolve(ctx, not args.no_cpu)

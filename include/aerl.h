@@ -62,8 +62,9 @@ enum {
 /* Condition operators and kinds (Section 3, Fig. 1a/b). */
 enum { AERL_OP_LT = 0, AERL_OP_LE = 1, AERL_OP_GT = 2, AERL_OP_GE = 3 };
 enum {
-  AERL_KIND_THRESHOLD = 0, /* coef*x[f] op theta            (one non-zero weight)            */
-  AERL_KIND_FEATURE = 1    /* coef*x[f] op coef2*x[g]      (two non-zero weights, zero bias) */
+  AERL_KIND_THRESHOLD = 0,  /* coef*x[f] op theta            (one non-zero weight)            */
+  AERL_KIND_FEATURE = 1,    /* coef*x[f] op coef2*x[g]      (two non-zero weights, zero bias) */
+  AERL_KIND_CATEGORICAL = 2 /* x[f] in a set of category codes (Section 5's categorical features) */
 };
 
 typedef struct aerl_ctx aerl_ctx;
@@ -150,6 +151,12 @@ aerl_status aerl_release_dataset(aerl_ctx *ctx, int32_t dataset_id);
  * and predicts rule_class[r].  Condition j is
  *   kind 0: coef[j]*x[f[j]] op[j] theta[j]
  *   kind 1: coef[j]*x[f[j]] op[j] coef2[j]*x[g[j]]
+ *   kind 2: x[f[j]] is a category code k in 0..63 (the value is exactly the
+ *           integer k) with bit k of cat_mask[j] set; any other value (a
+ *           fraction, a negative, 64 or more, an infinity, NaN) is in no
+ *           set.  An equality test is a one-code set.  op and coef are
+ *           not used.  The soft relaxation takes the condition's truth as
+ *           its soft truth (it has nothing to tune): its gradients are 0.
  * with each product rounded to fp32 once.  Empty rule sets and empty rules
  * (an empty AND always fires) are allowed. */
 typedef struct {
@@ -165,6 +172,7 @@ typedef struct {
   const float *coef;            /* [n_conds] */
   const float *coef2;           /* [n_conds], read for kind 1 only */
   const float *theta;           /* [n_conds], read for kind 0 only; +-inf allowed */
+  const uint64_t *cat_mask;     /* [n_conds], read for kind 2 only; may be NULL without kind 2 */
 } aerl_population;
 
 /* Bytes of the device workspace that holds the packed form of `pop`.
@@ -438,14 +446,56 @@ aerl_status aerl_soft_forward(aerl_ctx *ctx, int32_t dataset_id, int32_t pop_id,
  * theta entries of kind-1 conditions are written as 0).  The adjoint
  * recomputes every sigmoid instead of storing activations.  dloss is
  * device fp32 [n_sets]; ws holds at least backward_bytes.  Deterministic.
- * Rule sets of up to 32 rules run with the per-rule state in registers;
- * longer ones keep it in LDS, which bounds them (about 38 rules with few
- * features).  Errors: AERL_ENOENT, AERL_EINVAL (also: rule sets too long
- * for the adjoint kernel), AERL_EDEVICE. */
+ * Rule sets of up to 32 rules run with the per-rule state in per-lane
+ * memory; longer ones keep it in LDS with fewer waves per workgroup as they
+ * grow, which bounds them (about 300 rules with few features).  Errors:
+ * AERL_ENOENT, AERL_EINVAL (also: rule sets too long for the adjoint
+ * kernel), AERL_EDEVICE. */
 aerl_status aerl_soft_backward(aerl_ctx *ctx, int32_t dataset_id, int32_t pop_id,
                                const float *coef, const float *coef2, const float *theta,
                                const float *dloss, float *dcoef, float *dcoef2, float *dtheta,
                                void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------- softmax head */
+
+/* Soft loss of every rule set under the softmax head (Section 5: a softmax
+ * activation gives probabilistic, finer-grained class outputs).  Condition
+ * soft truths as in aerl_soft_forward; every rule votes for its class with
+ * its soft truth r_k, the default class receives the probability that no
+ * rule fires, D = prod_k (1 - r_k):
+ *   v_c = sum_{k: class_k = c} r_k + [c = default] * D,
+ *   P_c = exp(beta * v_c) / sum_c' exp(beta * v_c'),
+ * loss[s] = mean over samples of min(-log P(label), 100).  The order of the
+ * rules does not matter under this head.  beta: finite, >= 0 (the
+ * sharpness).  At most 16 classes.  ws: forward_bytes of
+ * aerl_soft_workspace_bytes.  Deterministic.  Errors: as aerl_soft_forward,
+ * plus AERL_EINVAL (more than 16 classes, bad beta). */
+aerl_status aerl_softmax_forward(aerl_ctx *ctx, int32_t dataset_id, int32_t pop_id,
+                                 const float *coef, const float *coef2, const float *theta,
+                                 float beta, float *loss, void *ws, size_t ws_bytes,
+                                 hipStream_t stream);
+
+/* Gradient of sum_s dloss[s] * loss[s] under the softmax head (outputs as
+ * aerl_soft_backward): dL/dv_c = beta (P_c - [c = y]),
+ * dL/dr_k = dL/dv_{class_k} - dL/dv_default * prod_{i != k} (1 - r_i),
+ * dL/dz = dL/dr_k * r_k * sigmoid(-z).  Every sigmoid is recomputed.
+ * ws: backward_bytes.  Deterministic.  Errors: as aerl_soft_backward, plus
+ * AERL_EINVAL (more than 16 classes, rule sets too long for the kernel's
+ * LDS, bad beta). */
+aerl_status aerl_softmax_backward(aerl_ctx *ctx, int32_t dataset_id, int32_t pop_id,
+                                  const float *coef, const float *coef2, const float *theta,
+                                  float beta, const float *dloss, float *dcoef, float *dcoef2,
+                                  float *dtheta, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Class probabilities P_c (the softmax head) of rule set `set` for n
+ * request rows: rows device fp32 [n][f] row-major, probs device fp32
+ * [n][C]; tau comes from dataset_id (the table the rule sets were tuned
+ * on).  Non-finite rows give non-finite probabilities.  ws: forward_bytes.
+ * Errors: AERL_ENOENT, AERL_EINVAL, AERL_EDEVICE. */
+aerl_status aerl_softmax_proba(aerl_ctx *ctx, int32_t dataset_id, int32_t pop_id, int32_t set,
+                               const float *coef, const float *coef2, const float *theta,
+                               float beta, const float *rows, int64_t n, float *probs, void *ws,
+                               size_t ws_bytes, hipStream_t stream);
 
 /* ------------------------------------------------------------ fine-tuning */
 

@@ -41,7 +41,8 @@ class aerl_population(C.Structure):
                 ("set_rule_off", C.c_void_p), ("set_default", C.c_void_p),
                 ("rule_cond_off", C.c_void_p), ("rule_class", C.c_void_p),
                 ("op", C.c_void_p), ("kind", C.c_void_p), ("f", C.c_void_p), ("g", C.c_void_p),
-                ("coef", C.c_void_p), ("coef2", C.c_void_p), ("theta", C.c_void_p)]
+                ("coef", C.c_void_p), ("coef2", C.c_void_p), ("theta", C.c_void_p),
+                ("cat_mask", C.c_void_p)]
 
 
 class aerl_dataset_info(C.Structure):
@@ -165,6 +166,11 @@ _SIGS = {
     "aerl_soft_forward": ([_P, _I32, _I32, _P, _P, _P, _P, _P, _SZ, _P], _I32),
     "aerl_soft_backward": ([_P, _I32, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _SZ, _P], _I32),
     "aerl_soft_forward_noalloc": ([_P, _I32, _I32, _P, _P, _P, _P, _P], _I32),
+    "aerl_softmax_forward": ([_P, _I32, _I32, _P, _P, _P, C.c_float, _P, _P, _SZ, _P], _I32),
+    "aerl_softmax_backward": ([_P, _I32, _I32, _P, _P, _P, C.c_float, _P, _P, _P, _P, _P, _SZ, _P],
+                              _I32),
+    "aerl_softmax_proba": ([_P, _I32, _I32, _I32, _P, _P, _P, C.c_float, _P, _I64, _P, _P, _SZ, _P],
+                           _I32),
     "aerl_random_pool": ([C.POINTER(aerl_evolve_cfg), _I32, _I32, _P, _P, C.POINTER(C.c_uint64),
                           C.POINTER(aerl_population_out)], _I32),
     "aerl_breed": ([C.POINTER(aerl_population), _P, C.POINTER(aerl_evolve_cfg), _I32, _I32, _P, _P,
@@ -250,7 +256,8 @@ class _HostPop:
         self.arrays = [np.ascontiguousarray(a, dtype=t) for a, t in (
             (pop.set_rule_off, i32), (pop.set_default, i32), (pop.rule_cond_off, i32),
             (pop.rule_class, i32), (pop.op, u8), (pop.kind, u8), (pop.f, i32), (pop.g, i32),
-            (pop.coef, f32), (pop.coef2, f32), (pop.theta, f32))]
+            (pop.coef, f32), (pop.coef2, f32), (pop.theta, f32),
+            (pop.cat_mask, np.uint64))]
         self.s = aerl_population(pop.n_sets, *[a.ctypes.data for a in self.arrays])
 
 
@@ -586,6 +593,33 @@ class Context:
                                     C.byref(eid)))
         return Evolution(self, eid.value, arena, ds.n_features)
 
+    def softmax_forward(self, ds, pop, coef, coef2, theta, beta: float, ws=None, stream=None):
+        ws = ws if ws is not None else self.soft_workspace(ds, pop, False)
+        loss = torch.empty(pop.n_sets, dtype=torch.float32, device=self.device)
+        self.check(aerl_softmax_forward(self.h, ds.id, pop.id, _ptr(coef), _ptr(coef2), _ptr(theta),
+                                        beta, _ptr(loss), _ptr(ws), ws.numel(), _stream(stream)))
+        return loss
+
+    def softmax_backward(self, ds, pop, coef, coef2, theta, beta: float, dloss, ws=None,
+                         stream=None):
+        ws = ws if ws is not None else self.soft_workspace(ds, pop, True)
+        g = [torch.empty(pop.n_conds, dtype=torch.float32, device=self.device) for _ in range(3)]
+        self.check(aerl_softmax_backward(self.h, ds.id, pop.id, _ptr(coef), _ptr(coef2), _ptr(theta),
+                                         beta, _ptr(dloss), _ptr(g[0]), _ptr(g[1]), _ptr(g[2]),
+                                         _ptr(ws), ws.numel(), _stream(stream)))
+        return tuple(g)
+
+    def softmax_proba(self, ds, pop, set_index: int, coef, coef2, theta, beta: float, rows,
+                      ws=None, stream=None):
+        """Class probabilities [n][C] of one rule set for request rows."""
+        rows = torch.as_tensor(rows, dtype=torch.float32).to(self.device).contiguous()
+        ws = ws if ws is not None else self.soft_workspace(ds, pop, False)
+        out = torch.empty((rows.shape[0], ds.n_classes), dtype=torch.float32, device=self.device)
+        self.check(aerl_softmax_proba(self.h, ds.id, pop.id, set_index, _ptr(coef), _ptr(coef2),
+                                      _ptr(theta), beta, _ptr(rows), rows.shape[0], _ptr(out),
+                                      _ptr(ws), ws.numel(), _stream(stream)))
+        return out
+
     def soft_forward_noalloc(self, ds, pop, coef, coef2, theta, loss, stream=None):
         """Soft forward into the caller's ``loss`` tensor using the library's
         per-GPU scratch array (no device allocation in the call)."""
@@ -697,3 +731,25 @@ class SoftLoss(torch.autograd.Function):
         g1, g2, g3 = aerl_ctx.soft_backward(ds, pop, coef, coef2, theta,
                                             dloss.contiguous().float())
         return g1, g2, g3, None, None, None
+
+
+class SoftmaxLoss(torch.autograd.Function):
+    """loss[P] under the softmax head (rule votes through a softmax of
+    sharpness beta); gradients through the library's adjoint kernel."""
+
+    @staticmethod
+    def forward(ctx, coef, coef2, theta, aerl_ctx: Context, ds: DeviceDataset,
+                pop: DevicePopulation, beta: float):
+        coef, coef2, theta = coef.contiguous(), coef2.contiguous(), theta.contiguous()
+        loss = aerl_ctx.softmax_forward(ds, pop, coef, coef2, theta, beta)
+        ctx.save_for_backward(coef, coef2, theta)
+        ctx.aerl = (aerl_ctx, ds, pop, beta)
+        return loss
+
+    @staticmethod
+    def backward(ctx, dloss):
+        coef, coef2, theta = ctx.saved_tensors
+        aerl_ctx, ds, pop, beta = ctx.aerl
+        g1, g2, g3 = aerl_ctx.softmax_backward(ds, pop, coef, coef2, theta, beta,
+                                               dloss.contiguous().float())
+        return g1, g2, g3, None, None, None, None

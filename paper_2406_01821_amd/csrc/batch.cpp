@@ -51,7 +51,9 @@ int32_t sets_per_item(const DatasetRec &ds, int32_t n_sets, const BatchSplit &sp
   const int32_t Q = sp.Q;
   const size_t tile_bytes = (size_t)ds.nf * 64 * batch_samples_per_lane(ds.nf, sp.tile_budget) * 4;
   const int32_t q_fit =
-      (int32_t)std::min<size_t>((kBatchLdsMax - tile_bytes - 4) / ((size_t)ds.nc * 2), 1 << 20);
+      (int32_t)std::min<size_t>((kBatchLdsMax - tile_bytes - (size_t)ds.nf * 8 - 4) /
+                                    ((size_t)std::max(hard_counters_per_set(ds.nc), 1) * 2),
+                                1 << 20);
   return std::max(1, std::min({Q, n_sets, q_fit}));
 }
 }  // namespace
@@ -71,6 +73,7 @@ void build_batch_tables(const std::vector<BatchSource> &src, const BatchSplit &s
   b->tasks.clear();
   b->zero.clear();
   b->lds = 0;
+  b->cat = false;
   std::vector<std::pair<double, BatchTask>> costed;
   for (size_t i = 0; i < src.size(); ++i) {
     const DatasetRec &ds = *src[i].ds;
@@ -90,6 +93,7 @@ void build_batch_tables(const std::vector<BatchSource> &src, const BatchSplit &s
     it.S = S;
     b->items.push_back(it);
     if (n_sets <= 0) continue;
+    b->cat = b->cat || src[i].cat;
     b->zero.push_back({it.correct, n_sets});
     if (it.confusion) b->zero.push_back({it.confusion, (int64_t)n_sets * ds.nc * ds.nc});
     const size_t tile_bytes = (size_t)ds.nf * 64 * S * 4;
@@ -138,6 +142,7 @@ void emit_batch_tables(const BatchTables &b, void *img, char *dev, int n_cu, Bat
   bl->n_tasks = (int32_t)b.tasks.size();
   bl->n_zero = (int32_t)b.zero.size();
   bl->lds = b.lds;
+  bl->cat = b.cat;
   const int per_cu = 2 * (b.lds + kStaticLds) <= kLdsPerCu ? 2 : 1;
   bl->grid = std::max<int64_t>(1, std::min<int64_t>((int64_t)n_cu * per_cu, (int64_t)b.tasks.size()));
 }
@@ -177,7 +182,7 @@ std::vector<BatchSource> sources(const std::vector<ItemView> &v) {
     // The set records lead the population's host staging copy of its image.
     src.push_back({it.ds, it.pop->n_sets, static_cast<const int4 *>(it.pop->staging),
                    it.pop->sets, it.pop->hconds, it.pop->heads, it.item->correct,
-                   it.item->confusion});
+                   it.item->confusion, it.pop->n_cat > 0});
   }
   return src;
 }

@@ -34,6 +34,7 @@ struct BatchLaunch {
   int32_t n_tasks, n_zero;
   int64_t grid;
   size_t lds;
+  bool cat;  // some item has categorical conditions
 };
 
 hipError_t launch_batch(const BatchLaunch &b, hipStream_t st);
@@ -61,6 +62,7 @@ struct BatchSource {
   const uint4 *heads;     // device head table
   int32_t *correct;       // device [n_sets]
   int32_t *confusion;     // device [n_sets][nc][nc] or null
+  bool cat;               // the population has categorical conditions
 };
 
 // Work tables of a batch and their layout in one device copy.
@@ -69,6 +71,7 @@ struct BatchTables {
   std::vector<BatchTask> tasks;
   std::vector<BatchZero> zero;
   size_t lds = 0;
+  bool cat = false;
   size_t items_off = 0, tasks_off = 0, zero_off = 0, counter_off = 0, bytes = 0;
 };
 

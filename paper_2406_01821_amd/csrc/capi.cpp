@@ -27,7 +27,7 @@ size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct DatasetMem {
   int64_t n_pad_max, n_tiles_max, n_blocks;
-  size_t x_off, y_off, perm_off, tile_off, tau_off, counts_off, base_off, flags_off, total;
+  size_t x_off, y_off, perm_off, tile_off, tau_off, counts_off, base_off, flags_off, tpart_off, total;
 };
 
 DatasetMem dataset_mem(int64_t n, int32_t nf, int32_t nc) {
@@ -44,6 +44,7 @@ DatasetMem dataset_mem(int64_t n, int32_t nf, int32_t nc) {
   m.counts_off = off; off = align256(off + sizeof(int32_t) * (size_t)(m.n_blocks * nc + 1));
   m.base_off = off;  off = align256(off + sizeof(int32_t) * (size_t)(m.n_blocks * nc + 1));
   m.flags_off = off; off = align256(off + sizeof(int32_t) * 2);
+  m.tpart_off = off; off = align256(off + sizeof(double) * 2 * (size_t)nf * kTauParts);
   m.total = off;
   return m;
 }
@@ -133,6 +134,7 @@ void set_device_views(PopRec &rec, const PackedLayout &L, void *ws) {
   rec.hconds = reinterpret_cast<const uint4 *>(b + L.hconds_off);
   rec.sconds = reinterpret_cast<const uint32_t *>(b + L.sconds_off);
   rec.heads = reinterpret_cast<const uint4 *>(b + L.heads_off);
+  rec.cmask = reinterpret_cast<const uint2 *>(b + L.cmask_off);
 }
 }  // namespace
 
@@ -283,7 +285,8 @@ aerl_status aerl_upload_dataset(aerl_ctx *ctx, const float *x, const int32_t *y,
   AERL_HIP(ctx, launch_fill_i32(d.perm, d.n_pad, -1, stream));
   AERL_HIP(ctx, launch_scatter_transpose(x, y, n, nf, nc, base_dev, d.x_fm, d.y_pad, d.perm, d.n_pad,
                                          M.n_blocks, stream));
-  AERL_HIP(ctx, launch_tau(d.x_fm, d.y_pad, d.n_pad, nf, n, d.tau, stream));
+  AERL_HIP(ctx, launch_tau(d.x_fm, d.tile_info, d.n_pad, nf, n,
+                           reinterpret_cast<double *>(base + M.tpart_off), d.tau, stream));
   AERL_HIP(ctx, hipStreamSynchronize(stream));
   const int32_t id = ctx->next_id++;
   ctx->datasets[id] = d;
@@ -508,7 +511,7 @@ aerl_status aerl_soft_workspace_bytes(aerl_ctx *ctx, int32_t dataset_id, int32_t
 }
 
 static aerl_status soft_common(aerl_ctx *ctx, int32_t dataset_id, int32_t pop_id, SoftLaunch *l,
-                               bool backward) {
+                               bool backward, bool first_firing = true) {
   auto di = ctx->datasets.find(dataset_id);
   if (di == ctx->datasets.end()) return fail(ctx, AERL_ENOENT, "unknown dataset %d", dataset_id);
   auto pi = ctx->pops.find(pop_id);
@@ -522,7 +525,7 @@ static aerl_status soft_common(aerl_ctx *ctx, int32_t dataset_id, int32_t pop_id
   if ((int64_t)pop.n_sets > kMaxHardBlocks)
     return fail(ctx, AERL_EINVAL, "%d rule sets exceed the soft kernels' launch limit %lld", pop.n_sets,
                 (long long)kMaxHardBlocks);
-  if (backward && !soft_backward_supported(ds, pop))
+  if (backward && first_firing && !soft_backward_supported(ds, pop))
     return fail(ctx, AERL_EINVAL, "rule sets of %d rules exceed the adjoint kernel's LDS", pop.max_rules);
   const size_t need = soft_ws_bytes(ds, pop, backward);
   if (need && (!l->ws || ((uintptr_t)l->ws & 255)))
@@ -546,6 +549,77 @@ aerl_status aerl_soft_forward(aerl_ctx *ctx, int32_t dataset_id, int32_t pop_id,
   if (!loss && l.pop->n_sets > 0) return fail(ctx, AERL_EINVAL, "loss is NULL");
   AERL_HIP(ctx, hipSetDevice(ctx->device));
   AERL_HIP(ctx, launch_soft_forward(l, stream));
+  return AERL_OK;
+}
+
+static aerl_status smax_common(aerl_ctx *ctx, int32_t dataset_id, int32_t pop_id, SoftLaunch *l,
+                               bool backward, float beta) {
+  if (!(beta >= 0.0f) || !std::isfinite(beta)) return fail(ctx, AERL_EINVAL, "beta must be finite and >= 0");
+  auto di = ctx->datasets.find(dataset_id);
+  auto pi = ctx->pops.find(pop_id);
+  if (di != ctx->datasets.end() && pi != ctx->pops.end()) {
+    if (di->second.nc > kSmaxMaxClasses)
+      return fail(ctx, AERL_EINVAL, "the softmax head takes at most %d classes", kSmaxMaxClasses);
+    if (!smax_supported(di->second, pi->second))
+      return fail(ctx, AERL_EINVAL, "rule sets of %d rules exceed the softmax kernel's LDS",
+                  pi->second.max_rules);
+  }
+  return soft_common(ctx, dataset_id, pop_id, l, backward, false);
+}
+
+aerl_status aerl_softmax_forward(aerl_ctx *ctx, int32_t dataset_id, int32_t pop_id,
+                                 const float *coef, const float *coef2, const float *theta,
+                                 float beta, float *loss, void *ws, size_t ws_bytes,
+                                 hipStream_t stream) {
+  if (!ctx) return AERL_EINVAL;
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  ctx->err.clear();
+  SoftLaunch l{};
+  l.coef = coef; l.coef2 = coef2; l.theta = theta; l.loss = loss; l.ws = ws; l.ws_bytes = ws_bytes;
+  aerl_status st = smax_common(ctx, dataset_id, pop_id, &l, false, beta);
+  if (st) return st;
+  if (!loss && l.pop->n_sets > 0) return fail(ctx, AERL_EINVAL, "loss is NULL");
+  AERL_HIP(ctx, hipSetDevice(ctx->device));
+  AERL_HIP(ctx, launch_smax_forward(l, beta, stream));
+  return AERL_OK;
+}
+
+aerl_status aerl_softmax_backward(aerl_ctx *ctx, int32_t dataset_id, int32_t pop_id,
+                                  const float *coef, const float *coef2, const float *theta,
+                                  float beta, const float *dloss, float *dcoef, float *dcoef2,
+                                  float *dtheta, void *ws, size_t ws_bytes, hipStream_t stream) {
+  if (!ctx) return AERL_EINVAL;
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  ctx->err.clear();
+  SoftLaunch l{};
+  l.coef = coef; l.coef2 = coef2; l.theta = theta; l.dloss = dloss;
+  l.dcoef = dcoef; l.dcoef2 = dcoef2; l.dtheta = dtheta; l.ws = ws; l.ws_bytes = ws_bytes;
+  aerl_status st = smax_common(ctx, dataset_id, pop_id, &l, true, beta);
+  if (st) return st;
+  if (l.pop->n_conds > 0 && (!dcoef || !dcoef2 || !dtheta))
+    return fail(ctx, AERL_EINVAL, "a gradient array is NULL");
+  if (l.pop->n_sets > 0 && !dloss) return fail(ctx, AERL_EINVAL, "dloss is NULL");
+  AERL_HIP(ctx, hipSetDevice(ctx->device));
+  AERL_HIP(ctx, launch_smax_backward(l, beta, stream));
+  return AERL_OK;
+}
+
+aerl_status aerl_softmax_proba(aerl_ctx *ctx, int32_t dataset_id, int32_t pop_id, int32_t set,
+                               const float *coef, const float *coef2, const float *theta,
+                               float beta, const float *rows, int64_t n, float *probs, void *ws,
+                               size_t ws_bytes, hipStream_t stream) {
+  if (!ctx) return AERL_EINVAL;
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  ctx->err.clear();
+  SoftLaunch l{};
+  l.coef = coef; l.coef2 = coef2; l.theta = theta; l.ws = ws; l.ws_bytes = ws_bytes;
+  aerl_status st = smax_common(ctx, dataset_id, pop_id, &l, false, beta);
+  if (st) return st;
+  if (set < 0 || set >= l.pop->n_sets) return fail(ctx, AERL_EINVAL, "set %d outside [0, %d)", set, l.pop->n_sets);
+  if (n < 0 || n > INT32_MAX) return fail(ctx, AERL_EINVAL, "n = %lld outside [0, 2^31)", (long long)n);
+  if (n > 0 && (!rows || !probs)) return fail(ctx, AERL_EINVAL, "rows or probs is NULL");
+  AERL_HIP(ctx, hipSetDevice(ctx->device));
+  AERL_HIP(ctx, launch_smax_proba(l, set, beta, rows, n, probs, stream));
   return AERL_OK;
 }
 

@@ -319,7 +319,7 @@ __device__ __forceinline__ void ldc_pair(const int4 *p, int4 (&out)[2]) {
 // Start of a record whose row is at byte offset XX: read the row; records
 // with a flag in MASK go to SPEC; falls through (row waited for) with a fast
 // record of the walk's current direction.  In the >= direction MASK is
-// kRecSpecial | kRecDirChg = 0xa07, in the <= direction kRecSpecial = 0xa03.
+// kRecSpecial | kRecDirChg = 0xa0f, in the <= direction kRecSpecial = 0xa0b.
 #define AERL_FETCH(S, XX, XW, MASK, SPEC)               \
   AERL_CAT(AERL_ADDR_, S)(XX)                           \
   AERL_CAT(AERL_RD_, S)                                 \
@@ -365,16 +365,67 @@ __device__ __forceinline__ void ldc_pair(const int4 *p, int4 (&out)[2]) {
   AERL_CAT(AERL_FFCMP_, AERL_SM(S, MODE))("ge")         \
   "s_branch " POST "\n"
 
+// Categorical record (code set in Y, Z), row already requested: per slot,
+// the value's code k = cvt_u32(x) names the sample's category when
+// cvt_f32(k) == x (an exact integer, not NaN) and k < 64; the sample is in
+// the set when, further, bit k of the 64-bit mask (v[38:39]) is set.  Slots
+// are taken last to first, so that f0 is written last: SCC = (f0 != 0).
+#define AERL_CATSLOT(V, DST, SRC)                       \
+  "v_cvt_u32_f32_e32 v36, " V "\n"                      \
+  "v_cvt_f32_u32_e32 v37, v36\n"                        \
+  "v_cmp_eq_f32_e32 vcc, v37, " V "\n"                  \
+  "v_cmp_gt_u32_e64 %[m], 64, v36\n"                    \
+  "s_and_b64 vcc, vcc, %[m]\n"                          \
+  "v_lshrrev_b64 v[36:37], v36, v[38:39]\n"             \
+  "v_and_b32_e32 v36, 1, v36\n"                         \
+  "v_cmp_ne_u32_e64 %[m], 0, v36\n"                     \
+  "s_and_b64 %[m], %[m], vcc\n"                         \
+  "s_and_b64 " DST ", " SRC ", %[m]\n"
+#define AERL_CATT_4(S0, S1, S2, S3)                     \
+  AERL_CATSLOT("v35", "s[62:63]", S3)                   \
+  AERL_CATSLOT("v34", "s[60:61]", S2)                   \
+  AERL_CATSLOT("v33", "s[58:59]", S1)                   \
+  AERL_CATSLOT("v32", "s[56:57]", S0)
+#define AERL_CATT_2(S0, S1)                             \
+  AERL_CATSLOT("v33", "s[58:59]", S1)                   \
+  AERL_CATSLOT("v32", "s[56:57]", S0)
+#define AERL_CATT_1(S0) AERL_CATSLOT("v32", "s[56:57]", S0)
+#define AERL_CAT_4U AERL_CATT_4("%[u0]", "%[u1]", "%[u2]", "%[u3]")
+#define AERL_CAT_4F AERL_CATT_4("s[56:57]", "s[58:59]", "s[60:61]", "s[62:63]")
+#define AERL_CAT_2U AERL_CATT_2("%[u0]", "%[u1]")
+#define AERL_CAT_2F AERL_CATT_2("s[56:57]", "s[58:59]")
+#define AERL_CAT_1U AERL_CATT_1("%[u0]")
+#define AERL_CAT_1F AERL_CATT_1("s[56:57]")
+#define AERL_CAT_BODY(S, MODE, Y, Z, POST)              \
+  "s_waitcnt lgkmcnt(0)\n"                              \
+  "v_mov_b32_e32 v38, " Y "\n"                          \
+  "v_mov_b32_e32 v39, " Z "\n"                          \
+  AERL_CAT(AERL_CAT_, AERL_SM(S, MODE))                 \
+  "s_branch " POST "\n"
+
 // Special record entry once a plain last record is ruled out:
-// feature-vs-feature, always-true (rule starts only, ALW), else a zero
-// coefficient; then POST.
-#define AERL_SPEC(S, MODE, Y, Z, W, TAG, POST, ALW)     \
+// feature-vs-feature, always-true (rule starts only, ALW), categorical
+// (AERL_SPEC_C only), else a zero coefficient; then POST.  Walks of
+// populations without categorical conditions use AERL_SPEC_N, which leaves
+// the code-set body out of the walk's code.
+#define AERL_SPEC_N(S, MODE, Y, Z, W, TAG, POST, ALW)   \
   "s_bitcmp1_b32 " W ", 9\n"                            \
   "s_cbranch_scc1 .Lff_" TAG "_%=\n"                    \
   ALW                                                   \
   AERL_MULREC(S, MODE, Y, Z, POST)                      \
   ".Lff_" TAG "_%=:\n"                                  \
   AERL_FF_BODY(S, MODE, W, Y, Z, TAG, POST)
+#define AERL_SPEC_C(S, MODE, Y, Z, W, TAG, POST, ALW)   \
+  "s_bitcmp1_b32 " W ", 9\n"                            \
+  "s_cbranch_scc1 .Lff_" TAG "_%=\n"                    \
+  ALW                                                   \
+  "s_bitcmp1_b32 " W ", 3\n"                            \
+  "s_cbranch_scc1 .Lcat_" TAG "_%=\n"                   \
+  AERL_MULREC(S, MODE, Y, Z, POST)                      \
+  ".Lff_" TAG "_%=:\n"                                  \
+  AERL_FF_BODY(S, MODE, W, Y, Z, TAG, POST)             \
+  ".Lcat_" TAG "_%=:\n"                                 \
+  AERL_CAT_BODY(S, MODE, Y, Z, POST)
 
 // How a walk moves between rules.  SEQ visits every rule in order (the
 // next rule starts where a record's next field points, or right after a
@@ -416,20 +467,20 @@ __device__ __forceinline__ void ldc_pair(const int4 *p, int4 (&out)[2]) {
 // The whole walk for S samples per lane; KIND is COUNT or PRED.  Labels:
 // s/n = a rule starts / continues at the record, a/b = quad A / B, _le = the
 // <= direction (taken from a rule's first <= record to its end).
-#define AERL_WALK(S, KIND, WAY)                                            \
+#define AERL_WALK(S, KIND, WAY, SP)                                            \
   AERL_CAT(AERL_START_, WAY)                                               \
   /* load the pair (o, o+16) into A, B; a rule starts at A */              \
   ".Lload_%=:\n"                                                           \
   "s_load_dwordx8 s[64:71], %[base], %[o]\n"                               \
   "s_waitcnt lgkmcnt(0)\n"                                                 \
-  AERL_FETCH(S, "s64", "s67", "0xa07", ".Lpsa_%=")                         \
+  AERL_FETCH(S, "s64", "s67", "0xa0f", ".Lpsa_%=")                         \
   AERL_CAT(AERL_CMP_, AERL_SM(S, U))("le", "s65")                          \
   /* after a fast record in A: on with B unless no f_i fires */            \
   ".Lqa_%=:\n"                                                             \
   "s_cbranch_scc0 .Lka_%=\n"                                               \
   /* B continues the rule */                                               \
   ".Lnb_%=:\n"                                                             \
-  AERL_FETCH(S, "s68", "s71", "0xa07", ".Lpnb_%=")                         \
+  AERL_FETCH(S, "s68", "s71", "0xa0f", ".Lpnb_%=")                         \
   AERL_CAT(AERL_CMP_, AERL_SM(S, F))("le", "s69")                          \
   ".Lqb_%=:\n"                                                             \
   "s_cbranch_scc0 .Lkb_%=\n"                                               \
@@ -438,7 +489,7 @@ __device__ __forceinline__ void ldc_pair(const int4 *p, int4 (&out)[2]) {
   "s_add_u32 %[o], %[o], 32\n"                                             \
   "s_load_dwordx8 s[64:71], %[base], %[o]\n"                               \
   "s_waitcnt lgkmcnt(0)\n"                                                 \
-  AERL_FETCH(S, "s64", "s67", "0xa07", ".Lpna_%=")                         \
+  AERL_FETCH(S, "s64", "s67", "0xa0f", ".Lpna_%=")                         \
   AERL_CAT(AERL_CMP_, AERL_SM(S, F))("le", "s65")                          \
   "s_cbranch_scc1 .Lnb_%=\n"                                               \
   /* f0 == 0 after a fast record in A: alive if another slot fires, else */ \
@@ -451,14 +502,14 @@ __device__ __forceinline__ void ldc_pair(const int4 *p, int4 (&out)[2]) {
   AERL_CAT(AERL_NXD_, WAY)("s71")                                          \
   /* a rule starts at B (the previous one ended at A) */                   \
   ".Lsb_%=:\n"                                                             \
-  AERL_FETCH(S, "s68", "s71", "0xa07", ".Lpsb_%=")                         \
+  AERL_FETCH(S, "s68", "s71", "0xa0f", ".Lpsb_%=")                         \
   AERL_CAT(AERL_CMP_, AERL_SM(S, U))("le", "s69")                          \
   "s_branch .Lqb_%=\n"                                                     \
   /* the same walk in the <= direction (rules continue, never start) */    \
   ".Lqa_le_%=:\n"                                                          \
   "s_cbranch_scc0 .Lka_le_%=\n"                                            \
   ".Lnb_le_%=:\n"                                                          \
-  AERL_FETCH(S, "s68", "s71", "0xa03", ".Lpnb_%=")                         \
+  AERL_FETCH(S, "s68", "s71", "0xa0b", ".Lpnb_%=")                         \
   AERL_CAT(AERL_CMP_, AERL_SM(S, F))("ge", "s69")                          \
   ".Lqb_le_%=:\n"                                                          \
   "s_cbranch_scc0 .Lkb_le_%=\n"                                            \
@@ -466,7 +517,7 @@ __device__ __forceinline__ void ldc_pair(const int4 *p, int4 (&out)[2]) {
   "s_add_u32 %[o], %[o], 32\n"                                             \
   "s_load_dwordx8 s[64:71], %[base], %[o]\n"                               \
   "s_waitcnt lgkmcnt(0)\n"                                                 \
-  AERL_FETCH(S, "s64", "s67", "0xa03", ".Lpna_%=")                         \
+  AERL_FETCH(S, "s64", "s67", "0xa0b", ".Lpna_%=")                         \
   AERL_CAT(AERL_CMP_, AERL_SM(S, F))("ge", "s65")                          \
   "s_cbranch_scc1 .Lnb_le_%=\n"                                            \
   ".Lka_le_%=:\n"                                                          \
@@ -495,37 +546,37 @@ __device__ __forceinline__ void ldc_pair(const int4 *p, int4 (&out)[2]) {
   /* special records (the direction change alone goes to .Ld*, a plain */  \
   /* last record, flags 0x203 clear, to .Lt*) */                           \
   ".Lpsa_%=:\n"                                                            \
-  "s_and_b32 %[t0], s67, 0xa03\n"                                          \
+  "s_and_b32 %[t0], s67, 0xa0b\n"                                          \
   "s_cbranch_scc0 .Ldsa_%=\n"                                              \
-  "s_and_b32 %[t0], s67, 0x203\n"                                          \
+  "s_and_b32 %[t0], s67, 0x20b\n"                                          \
   "s_cbranch_scc0 .Ltsa_%=\n"                                              \
-  AERL_SPEC(S, U, "s65", "s66", "s67", "sa", ".Lxa_%=",                    \
+  AERL_CAT(AERL_SPEC_, SP)(S, U, "s65", "s66", "s67", "sa", ".Lxa_%=",                    \
             "s_bitcmp1_b32 s67, 1\n s_cbranch_scc1 .Lalwa_%=\n")           \
   ".Ltsa_%=:\n"                                                            \
   AERL_LASTREC(S, U, "s65", "s67", "tsa", ".Lza_%=")                       \
   ".Lpna_%=:\n"                                                            \
-  "s_and_b32 %[t0], s67, 0xa03\n"                                          \
+  "s_and_b32 %[t0], s67, 0xa0b\n"                                          \
   "s_cbranch_scc0 .Ldna_%=\n"                                              \
-  "s_and_b32 %[t0], s67, 0x203\n"                                          \
+  "s_and_b32 %[t0], s67, 0x20b\n"                                          \
   "s_cbranch_scc0 .Ltna_%=\n"                                              \
-  AERL_SPEC(S, F, "s65", "s66", "s67", "na", ".Lxa_%=", "")                \
+  AERL_CAT(AERL_SPEC_, SP)(S, F, "s65", "s66", "s67", "na", ".Lxa_%=", "")                \
   ".Ltna_%=:\n"                                                            \
   AERL_LASTREC(S, F, "s65", "s67", "tna", ".Lza_%=")                       \
   ".Lpsb_%=:\n"                                                            \
-  "s_and_b32 %[t0], s71, 0xa03\n"                                          \
+  "s_and_b32 %[t0], s71, 0xa0b\n"                                          \
   "s_cbranch_scc0 .Ldsb_%=\n"                                              \
-  "s_and_b32 %[t0], s71, 0x203\n"                                          \
+  "s_and_b32 %[t0], s71, 0x20b\n"                                          \
   "s_cbranch_scc0 .Ltsb_%=\n"                                              \
-  AERL_SPEC(S, U, "s69", "s70", "s71", "sb", ".Lxb_%=",                    \
+  AERL_CAT(AERL_SPEC_, SP)(S, U, "s69", "s70", "s71", "sb", ".Lxb_%=",                    \
             "s_bitcmp1_b32 s71, 1\n s_cbranch_scc1 .Lalwb_%=\n")           \
   ".Ltsb_%=:\n"                                                            \
   AERL_LASTREC(S, U, "s69", "s71", "tsb", ".Lzb_%=")                       \
   ".Lpnb_%=:\n"                                                            \
-  "s_and_b32 %[t0], s71, 0xa03\n"                                          \
+  "s_and_b32 %[t0], s71, 0xa0b\n"                                          \
   "s_cbranch_scc0 .Ldnb_%=\n"                                              \
-  "s_and_b32 %[t0], s71, 0x203\n"                                          \
+  "s_and_b32 %[t0], s71, 0x20b\n"                                          \
   "s_cbranch_scc0 .Ltnb_%=\n"                                              \
-  AERL_SPEC(S, F, "s69", "s70", "s71", "nb", ".Lxb_%=", "")                \
+  AERL_CAT(AERL_SPEC_, SP)(S, F, "s69", "s70", "s71", "nb", ".Lxb_%=", "")                \
   ".Ltnb_%=:\n"                                                            \
   AERL_LASTREC(S, F, "s69", "s71", "tnb", ".Lzb_%=")                       \
   /* after a special record in A (what follows it in its rule is special */ \
@@ -572,8 +623,9 @@ __device__ __forceinline__ void ldc_pair(const int4 *p, int4 (&out)[2]) {
       "v35", "v36", "v37", "v38", "v39", "vcc", "scc", "memory"
 
 // Counting walk over every rule of the set (SEQ) or over the rules whose bit
-// is set in mk (FLT; vst holds the rules' byte offsets, one per lane).
-template <int S, bool FLT>
+// is set in mk (FLT; vst holds the rules' byte offsets, one per lane).  CAT:
+// the walk takes categorical records (populations that have them).
+template <int S, bool FLT, bool CAT>
 __device__ __forceinline__ int eval_set_count(uint32_t lds_lane, int lane, int4 set,
                                               const uint4 *__restrict__ stream,
                                               const uint64_t (&vm)[S], uint64_t mk = 0,
@@ -587,9 +639,9 @@ __device__ __forceinline__ int eval_set_count(uint32_t lds_lane, int lane, int4 
 #define AERL_U_2 uint64_t u0 = vm[0], u1 = vm[1];
 #define AERL_U_1 uint64_t u0 = vm[0];
 
-#define AERL_COUNT_SPECIALIZE(S)                                                              \
+#define AERL_COUNT_SPECIALIZE(S, CAT, SP)                                                     \
   template <>                                                                                 \
-  __device__ __forceinline__ int eval_set_count<S, false>(                                    \
+  __device__ __forceinline__ int eval_set_count<S, false, CAT>(                               \
       uint32_t lds_lane, int lane, int4 set, const uint4 *__restrict__ stream,                \
       const uint64_t(&vm)[S], uint64_t, uint32_t) {                                           \
     const uint4 *base = stream + set.x;                                                       \
@@ -597,14 +649,14 @@ __device__ __forceinline__ int eval_set_count(uint32_t lds_lane, int lane, int4 
     uint64_t m;                                                                               \
     uint32_t o, t0, vt, vt2;                                                                  \
     int acc = 0;                                                                              \
-    asm volatile(AERL_WALK(S, COUNT, SEQ)                                                     \
+    asm volatile(AERL_WALK(S, COUNT, SEQ, SP)                                                 \
                  : AERL_COUNT_OUTS_##S, AERL_TEMPS                                            \
                  : [base] "s"(base), [lds] "v"(lds_lane), [lane] "v"(lane)                    \
                  : AERL_WALK_CLOBBERS);                                                       \
     return acc;                                                                               \
   }                                                                                           \
   template <>                                                                                 \
-  __device__ __forceinline__ int eval_set_count<S, true>(                                     \
+  __device__ __forceinline__ int eval_set_count<S, true, CAT>(                                \
       uint32_t lds_lane, int lane, int4 set, const uint4 *__restrict__ stream,                \
       const uint64_t(&vm)[S], uint64_t mk, uint32_t vst) {                                    \
     const uint4 *base = stream + set.x;                                                       \
@@ -612,16 +664,19 @@ __device__ __forceinline__ int eval_set_count(uint32_t lds_lane, int lane, int4 
     uint64_t m;                                                                               \
     uint32_t o, t0, vt, vt2;                                                                  \
     int acc = 0;                                                                              \
-    asm volatile(AERL_WALK(S, COUNT, FLT)                                                     \
+    asm volatile(AERL_WALK(S, COUNT, FLT, SP)                                                 \
                  : AERL_COUNT_OUTS_##S, AERL_TEMPS, [mk] "+s"(mk)                             \
                  : [base] "s"(base), [lds] "v"(lds_lane), [lane] "v"(lane), [vst] "v"(vst)    \
                  : AERL_WALK_CLOBBERS);                                                       \
     return acc;                                                                               \
   }
 
-AERL_COUNT_SPECIALIZE(4)
-AERL_COUNT_SPECIALIZE(2)
-AERL_COUNT_SPECIALIZE(1)
+AERL_COUNT_SPECIALIZE(4, false, N)
+AERL_COUNT_SPECIALIZE(2, false, N)
+AERL_COUNT_SPECIALIZE(1, false, N)
+AERL_COUNT_SPECIALIZE(4, true, C)
+AERL_COUNT_SPECIALIZE(2, true, C)
+AERL_COUNT_SPECIALIZE(1, true, C)
 
 // Prediction form of the sequential walk: pred[s] receives the class of each
 // lane's samples in vm (others keep their value).
@@ -639,7 +694,7 @@ __device__ __forceinline__ void eval_set_pred<4>(uint32_t lds_lane, int lane, in
   uint64_t m;
   uint32_t o, t0, vt, vt2;
   int p0 = pred[0], p1 = pred[1], p2 = pred[2], p3 = pred[3];
-  asm volatile(AERL_WALK(4, PRED, SEQ)
+  asm volatile(AERL_WALK(4, PRED, SEQ, C)
                : [p0] "+v"(p0), [p1] "+v"(p1), [p2] "+v"(p2), [p3] "+v"(p3), [u0] "+s"(u0),
                  [u1] "+s"(u1), [u2] "+s"(u2), [u3] "+s"(u3), AERL_TEMPS
                : [base] "s"(base), [lds] "v"(lds_lane)
@@ -657,7 +712,7 @@ __device__ __forceinline__ void eval_set_pred<2>(uint32_t lds_lane, int lane, in
   uint64_t m;
   uint32_t o, t0, vt, vt2;
   int p0 = pred[0], p1 = pred[1];
-  asm volatile(AERL_WALK(2, PRED, SEQ)
+  asm volatile(AERL_WALK(2, PRED, SEQ, C)
                : [p0] "+v"(p0), [p1] "+v"(p1), [u0] "+s"(u0), [u1] "+s"(u1), AERL_TEMPS
                : [base] "s"(base), [lds] "v"(lds_lane)
                : AERL_WALK_CLOBBERS);
@@ -674,7 +729,7 @@ __device__ __forceinline__ void eval_set_pred<1>(uint32_t lds_lane, int lane, in
   uint64_t m;
   uint32_t o, t0, vt, vt2;
   int p0 = pred[0];
-  asm volatile(AERL_WALK(1, PRED, SEQ)
+  asm volatile(AERL_WALK(1, PRED, SEQ, C)
                : [p0] "+v"(p0), [u0] "+s"(u0), AERL_TEMPS
                : [base] "s"(base), [lds] "v"(lds_lane)
                : AERL_WALK_CLOBBERS);

@@ -261,6 +261,14 @@ aerl_status write_out(const std::vector<Set> &pool, const aerl_evolve_cfg &c, ae
   return AERL_OK;
 }
 
+// The loop breeds threshold and feature-vs-feature conditions only.
+aerl_status check_kinds(aerl_ctx *ctx, const aerl_population &p, int32_t n_conds) {
+  for (int32_t j = 0; j < n_conds; ++j)
+    if (p.kind[j] > AERL_KIND_FEATURE)
+      return fail(ctx, AERL_EINVAL, "condition %d: the evolution loop breeds kinds 0 and 1 only", j);
+  return AERL_OK;
+}
+
 aerl_status check_cfg(aerl_ctx *ctx, const aerl_evolve_cfg *c, int32_t nf, int32_t nc, const float *lo,
                       const float *hi) {
   if (!c) return fail(ctx, AERL_EINVAL, "cfg is NULL");
@@ -461,7 +469,7 @@ aerl_status aerl_breed(const aerl_population *pool, const int32_t *fitness, cons
   int32_t nr = 0, nk = 0;
   s = validate_population(nullptr, pool, nf, nc, &nr, &nk);
   if (s) return s;
-  if (pool->n_sets != cfg->pool) return AERL_EINVAL;
+  if (pool->n_sets != cfg->pool || check_kinds(nullptr, *pool, nk)) return AERL_EINVAL;
   const std::vector<Set> in = from_view(*pool);
   for (const Set &st : in) {
     if (st.rules.empty() || (int32_t)st.rules.size() > cfg->max_rules) return AERL_EINVAL;
@@ -507,6 +515,8 @@ aerl_status aerl_evolve_create(aerl_ctx *ctx, int32_t dataset_id, const aerl_evo
   if (initial) {
     int32_t nr = 0, nk = 0;
     s = validate_population(ctx, initial, nf, nc, &nr, &nk);
+    if (s) return s;
+    s = check_kinds(ctx, *initial, nk);
     if (s) return s;
     if (initial->n_sets != cfg->pool)
       return fail(ctx, AERL_EINVAL, "initial population has %d rule sets, the pool %d", initial->n_sets, cfg->pool);

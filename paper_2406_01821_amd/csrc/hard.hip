@@ -40,10 +40,12 @@ struct HardArgs {
   int32_t region_tiles[AERL_MAX_CLASSES];
 };
 
-template <int S>
+// CAT: the population has categorical conditions (their walk body is left
+// out of the other instantiation, which keeps the common walk's code tight).
+template <int S, bool CAT>
 __global__ __launch_bounds__(kHardBlock) AERL_HARD_SGPR_CAP void k_hard(const HardArgs a) {
   extern __shared__ __align__(16) float smem[];
-  __shared__ int32_t next_q;
+  __shared__ int32_t sh[2];
   // Which class region and which tiles this block covers (uniform loop).
   HardTask t;
   t.x_fm = a.x_fm;
@@ -77,7 +79,7 @@ __global__ __launch_bounds__(kHardBlock) AERL_HARD_SGPR_CAP void k_hard(const Ha
   }
   t.q0 = chunk * a.sets_per_chunk;
   t.Q = min(a.sets_per_chunk, a.set_count - t.q0);
-  hard_block<S>(t, smem, &next_q);
+  hard_block<S, CAT>(t, smem, sh);
 }
 
 // Prediction for one rule set over row-major rows: one wave per 64*S rows.
@@ -91,8 +93,11 @@ __global__ __launch_bounds__(64) void k_predict(const float *__restrict__ rows, 
 }
 
 template <int S>
-hipError_t hard_dispatch(const HardArgs &a, dim3 grid, size_t lds, hipStream_t st) {
-  hipLaunchKernelGGL(k_hard<S>, grid, dim3(kHardBlock), lds, st, a);
+hipError_t hard_dispatch(const HardArgs &a, dim3 grid, size_t lds, bool cat, hipStream_t st) {
+  if (cat)
+    hipLaunchKernelGGL((k_hard<S, true>), grid, dim3(kHardBlock), lds, st, a);
+  else
+    hipLaunchKernelGGL((k_hard<S, false>), grid, dim3(kHardBlock), lds, st, a);
   return hipGetLastError();
 }
 
@@ -131,9 +136,9 @@ hipError_t launch_hard_eval(const HardLaunch &h, hipStream_t st) {
   a.n_chunks = (int32_t)n_chunks;
   const dim3 grid((unsigned)(n_chunks * n_groups));
   switch (h.samples_per_lane) {
-    case 4: return hard_dispatch<4>(a, grid, lds, st);
-    case 2: return hard_dispatch<2>(a, grid, lds, st);
-    case 1: return hard_dispatch<1>(a, grid, lds, st);
+    case 4: return hard_dispatch<4>(a, grid, lds, pop.n_cat > 0, st);
+    case 2: return hard_dispatch<2>(a, grid, lds, pop.n_cat > 0, st);
+    case 1: return hard_dispatch<1>(a, grid, lds, pop.n_cat > 0, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -39,20 +39,26 @@ struct HardTask {
 // tile's largest x, or x <= t with t below its smallest) cannot fire for any
 // of them: the walk skips it without reading its records (exact).
 // Per-class prediction counts live in LDS (one writer per rule set and
-// tile) and reach the outputs once, through integer atomics.  smem holds
-// nf*64*S floats, then nf (max, -min) pairs, then Q*nc 16-bit counters (a
-// block covers at most 255 layout tiles, so a counter stays below 2^16).
-// Ends with a barrier, so the caller may reuse smem.
-template <int S>
-__device__ __forceinline__ void hard_block(const HardTask &t, float *smem, int32_t *next_q) {
+// tile) and reach the outputs once, through integer atomics; the last
+// class's count is what the other classes leave of the block's samples.
+// smem holds nf*64*S floats, then nf (max, -min) pairs, then Q*(nc-1)
+// 16-bit counters (a block covers at most 255 layout tiles, so a counter
+// stays below 2^16).  sh[0] is the rule-set counter, sh[1] the block's real
+// sample count (kept in LDS by one thread, so that it holds no register
+// through the walk).  Ends with a barrier, so the caller may reuse smem.
+template <int S, bool CAT>
+__device__ __forceinline__ void hard_block(const HardTask &t, float *smem, int32_t *sh) {
+  int32_t *next_q = sh;
   constexpr int TS = 64 * S;           // samples per wave tile
   constexpr int WPT = AERL_TILE / TS;  // wave tiles per layout tile
   float *xs = smem;                                                    // [nf][TS]
   float *ext = smem + (size_t)t.nf * TS;                               // [nf][max, -min]
-  uint16_t *cnt = reinterpret_cast<uint16_t *>(ext + 2 * t.nf);        // [Q][nc]
+  const int ncc = hard_counters_per_set(t.nc);                        // counted classes
+  uint16_t *cnt = reinterpret_cast<uint16_t *>(ext + 2 * t.nf);        // [Q][ncc]
   uint32_t *cnt32 = reinterpret_cast<uint32_t *>(cnt);
   const int lane = threadIdx.x & 63;
-  for (int i = threadIdx.x; i < t.Q * t.nc; i += blockDim.x) cnt[i] = 0;
+  for (int i = threadIdx.x; i < t.Q * ncc; i += blockDim.x) cnt[i] = 0;
+  if (threadIdx.x == 0) sh[1] = 0;
   const int n4 = t.nf * (TS / 4);
   const float4 *src = reinterpret_cast<const float4 *>(t.x_fm);
   float4 *dst = reinterpret_cast<float4 *>(xs);
@@ -77,6 +83,7 @@ __device__ __forceinline__ void hard_block(const HardTask &t, float *smem, int32
 #pragma unroll
     for (int s = 0; s < S; ++s) vm[s] = ballot(lane * S + s < valid);
     if (valid == 0) continue;  // an empty wave tile (S < 4 at a region's end)
+    if (threadIdx.x == 0) sh[1] += valid;
     // largest and negated smallest value of each feature over the valid
     // samples: 16 threads per feature
     for (int f0 = 0; f0 < t.nf; f0 += 64) {
@@ -137,27 +144,32 @@ __device__ __forceinline__ void hard_block(const HardTask &t, float *smem, int32
                                 (uint32_t)!(e2 < __uint_as_float(h.w));
           // the closing record (last entry) is always visited
           const uint64_t mk = ballot(keep != 0u) | (1ull << (nh - 1));
-          acc = eval_set_count<S, true>(lds_lane, lane, s4, t.conds, vm, mk, h.x & kHeadOffMask);
+          acc = eval_set_count<S, true, CAT>(lds_lane, lane, s4, t.conds, vm, mk, h.x & kHeadOffMask);
         } else {
-          acc = eval_set_count<S, false>(lds_lane, lane, s4, t.conds, vm);
+          acc = eval_set_count<S, false, CAT>(lds_lane, lane, s4, t.conds, vm);
         }
         // two 16-bit counters per word: a no-return atomic add, no carry
         // between the halves (each counter stays below 2^16)
-        if (lane < t.nc) {
-          const int i = q * t.nc + lane;
+        if (lane < ncc) {
+          const int i = q * ncc + lane;
           atomicAdd(cnt32 + (i >> 1), (uint32_t)acc << ((i & 1) * 16));
         }
       }
     }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < t.Q * t.nc; i += blockDim.x) {
-    const int v = cnt[i];
-    if (v == 0) continue;
-    const int q = i / t.nc, c = i - q * t.nc;
+  // the block's real samples (every set predicts one class for each)
+  const int n_block = sh[1];
+  for (int q = threadIdx.x; q < t.Q; q += blockDim.x) {
     const int64_t p = t.q0 + q;
-    if (t.confusion) atomicAdd(&t.confusion[(p * t.nc + t.label) * t.nc + c], v);
-    if (c == t.label) atomicAdd(&t.correct[p], v);
+    int rest = n_block;
+    for (int c = 0; c < t.nc; ++c) {
+      const int v = c < ncc ? (int)cnt[q * ncc + c] : rest;
+      rest -= v;
+      if (v == 0) continue;
+      if (t.confusion) atomicAdd(&t.confusion[(p * t.nc + t.label) * t.nc + c], v);
+      if (c == t.label) atomicAdd(&t.correct[p], v);
+    }
   }
   __syncthreads();
 }

@@ -59,20 +59,26 @@ aerl_status fail(aerl_ctx *ctx, aerl_status code, const char *fmt, ...);
 //                           y*x[f] >= z*x[g]     (kRecFF | kRecGE)
 // kRecLast marks a rule's last record.  The closing record is an always-true
 // last record of the set's default class, so every walk ends in a commit.
-// Soft condition (caller order): f | g << 12 | kind << 24 | (op >= 2) << 25.
+// Soft condition (caller order): f | g << 12 | feature << 24 | (op >= 2) << 25
+// | categorical << 26; a categorical condition's code set is in the packed
+// image's mask array (caller order, two words per condition).
+constexpr uint32_t kSoftFF = 1u << 24, kSoftCat = 1u << 26;
 constexpr uint32_t kRecGMask = 0x1ffu;
 constexpr uint32_t kRecMul = 1u << 0;     // threshold records only
 constexpr uint32_t kRecAlways = 1u << 1;  // threshold records only
 // Inside a rule the folded thresholds come >= first, then <=; the first <=
 // record carries kRecDirChg, which moves the walk to its <= fast path.
 constexpr uint32_t kRecDirChg = 1u << 2;  // threshold records only
+// Categorical record: x[f] is a code k in 0..63 with bit k of the mask
+// {y (codes 0..31), z (codes 32..63)} set.
+constexpr uint32_t kRecCat = 1u << 3;     // non-feature records only
 constexpr uint32_t kRecFF = 1u << 9;
 constexpr uint32_t kRecGE = 1u << 10;  // feature records
 constexpr uint32_t kRecLE = 1u << 10;  // threshold records
 constexpr uint32_t kRecLast = 1u << 11;
 // Records that leave the walk's fast path (the folded compare of a rule's
 // non-last record in the walk's current direction).
-constexpr uint32_t kRecSpecial = kRecFF | kRecLast | kRecMul | kRecAlways;
+constexpr uint32_t kRecSpecial = kRecFF | kRecLast | kRecMul | kRecAlways | kRecCat;
 constexpr uint32_t kRecClsShift = 12;
 constexpr uint32_t kRecNextShift = 18;
 // Records of one rule set, closing record included: next-rule byte offsets
@@ -94,7 +100,7 @@ constexpr uint32_t kHeadExtShift = 14;
 // Sets with at most this many head entries take the filtered walk.
 constexpr int32_t kMaxHeads = 64;
 struct PackedLayout {
-  size_t sets_off, ssets_off, rules_off, hconds_off, sconds_off, heads_off, total;
+  size_t sets_off, ssets_off, rules_off, hconds_off, sconds_off, heads_off, cmask_off, total;
 };
 
 struct DatasetRec {
@@ -117,12 +123,14 @@ struct PopRec {
   int64_t nominal_conds = 0;
   int32_t max_set_conds = 0;
   int32_t n_ff = 0;            // feature-vs-feature conditions
+  int32_t n_cat = 0;           // categorical conditions
   const int4 *sets = nullptr;
   const int4 *ssets = nullptr;
   const int4 *rules = nullptr;
   const uint4 *hconds = nullptr;
   const uint32_t *sconds = nullptr;
   const uint4 *heads = nullptr;
+  const uint2 *cmask = nullptr;
   void *staging = nullptr;     // pinned host copy of the packed image
   hipEvent_t staged = nullptr; // completion of the staging copy
 };
@@ -214,8 +222,10 @@ hipError_t launch_scatter_transpose(const float *x, const int32_t *y, int64_t n,
                                     int32_t nc, const int32_t *block_base, float *x_fm,
                                     int32_t *y_pad, int32_t *perm, int64_t n_pad,
                                     int64_t n_blocks, hipStream_t s);
-hipError_t launch_tau(const float *x_fm, const int32_t *y_pad, int64_t n_pad, int32_t nf,
-                      int64_t n, float *tau, hipStream_t s);
+// tau from the resident layout: part holds 2 * nf * kTauParts doubles.
+constexpr int kTauParts = 64;
+hipError_t launch_tau(const float *x_fm, const int32_t *tile_info, int64_t n_pad, int32_t nf,
+                      int64_t n, double *part, float *tau, hipStream_t s);
 constexpr int kUploadBlock = 256;  // samples per block in the upload kernels
 
 // LDS of one CU, and the most dynamic LDS a hard-eval block may ask for (the
@@ -224,13 +234,17 @@ constexpr size_t kLdsPerCu = 160 * 1024;
 constexpr size_t kStaticLds = 64;
 constexpr size_t kDynLdsMax = kLdsPerCu - kStaticLds;
 
-// Dynamic LDS of a hard-eval block: the feature tile (nf x 64*S floats) and
-// one 16-bit prediction counter per (rule set, class).  A block adds at most
-// 256 samples per layout tile to a counter, so it covers at most
+// Dynamic LDS of a hard-eval block: the feature tile (nf x 64*S floats),
+// the tile's per-feature extremes and one 16-bit prediction counter per
+// (rule set, class) for every class but the last (a set predicts the last
+// class for the block's samples the other counters leave).  A block adds at
+// most 256 samples per layout tile to a counter, so it covers at most
 // kMaxTilesPerBlock layout tiles.
 constexpr int kMaxTilesPerBlock = 255;
+__host__ __device__ inline int hard_counters_per_set(int nc) { return nc > 1 ? nc - 1 : 0; }
 inline size_t hard_block_lds(int nf, int S, int Q, int nc) {
-  return (size_t)nf * 64 * S * 4 + (size_t)nf * 8 + (((size_t)Q * nc * 2 + 3) & ~size_t(3));
+  return (size_t)nf * 64 * S * 4 + (size_t)nf * 8 +
+         (((size_t)Q * hard_counters_per_set(nc) * 2 + 3) & ~size_t(3));
 }
 
 // Soft path (soft.hip)
@@ -248,6 +262,15 @@ size_t soft_ws_bytes(const DatasetRec &ds, const PopRec &pop, bool backward);
 bool soft_backward_supported(const DatasetRec &ds, const PopRec &pop);
 hipError_t launch_soft_forward(const SoftLaunch &l, hipStream_t s);
 hipError_t launch_soft_backward(const SoftLaunch &l, hipStream_t s);
+// Softmax head (soft.hip): up to kSmaxMaxClasses classes; same workspace as
+// the first-firing soft path (soft_ws_bytes).
+constexpr int kSmaxMaxClasses = 16;
+bool smax_supported(const DatasetRec &ds, const PopRec &pop);
+hipError_t launch_smax_forward(const SoftLaunch &l, float beta, hipStream_t s);
+hipError_t launch_smax_backward(const SoftLaunch &l, float beta, hipStream_t s);
+hipError_t launch_smax_proba(const SoftLaunch &l, int32_t set, float beta, const float *rows,
+                             int64_t n, float *probs, hipStream_t s);
+
 // Fine-tuning (tune.hip): workspace layout and the epoch loop.
 struct TuneLayout {
   size_t soft_off, grad_off, mom_off, dloss_off, total;

@@ -94,45 +94,73 @@ __global__ __launch_bounds__(kUploadBlock) void k_scatter_transpose(
   }
 }
 
-// tau[f] = 0.05 * population std over the real samples, fp64 two-pass with a
-// fixed thread-strided order and a fixed tree, rounded to float; 1 if std 0.
+// tau[f] = 0.05 * population std over the real samples (1 if the std is 0),
+// fp64 two-pass, rounded to float.  Each pass splits every feature row into
+// kTauParts slices of whole layout tiles, one 256-thread block per (slice,
+// feature); a sample counts when its tile's valid count says it is real
+// (the tile table, not a per-sample label read).  Block sums use a fixed
+// tree and the slice partials are added in slice order, so tau is the same
+// from run to run.  Pass 1 writes the slices' sums, pass 2 the slices' sums
+// of squared deviations from the mean (which every block forms from the
+// pass-1 partials in the same order), and the last kernel finishes tau.
 constexpr int kTauBlock = 256;
-__global__ __launch_bounds__(kTauBlock) void k_tau(const float *__restrict__ x_fm,
-                                                   const int32_t *__restrict__ y_pad,
-                                                   int64_t n_pad, int64_t n,
-                                                   float *__restrict__ tau) {
-  __shared__ double red[kTauBlock];
+
+__device__ __forceinline__ double block_sum(double v, double *red) {
   const int t = threadIdx.x;
-  const float *row = x_fm + (int64_t)blockIdx.x * n_pad;
+  red[t] = v;
+  __syncthreads();
+  for (int h = kTauBlock / 2; h > 0; h >>= 1) {
+    if (t < h) red[t] += red[t + h];
+    __syncthreads();
+  }
+  const double s = red[0];
+  __syncthreads();
+  return s;
+}
+
+__device__ __forceinline__ double tau_mean(const double *__restrict__ part, int f, int64_t n) {
   double s = 0.0;
-  for (int64_t i = t; i < n_pad; i += kTauBlock)
-    if (y_pad[i] >= 0) s += (double)row[i];
-  red[t] = s;
-  __syncthreads();
-  for (int h = kTauBlock / 2; h > 0; h >>= 1) {
-    if (t < h) red[t] += red[t + h];
-    __syncthreads();
-  }
-  const double mean = n > 0 ? red[0] / (double)n : 0.0;
-  __syncthreads();
-  double q = 0.0;
-  for (int64_t i = t; i < n_pad; i += kTauBlock)
-    if (y_pad[i] >= 0) {
-      double d = (double)row[i] - mean;
-      q += d * d;
+  for (int b = 0; b < kTauParts; ++b) s += part[(int64_t)f * kTauParts + b];
+  return n > 0 ? s / (double)n : 0.0;
+}
+
+// PASS 1: part1[f][b] = sum of the slice's real x; PASS 2: part2[f][b] = sum
+// of (x - mean)^2.
+template <int PASS>
+__global__ __launch_bounds__(kTauBlock) void k_tau_part(const float *__restrict__ x_fm,
+                                                        const int32_t *__restrict__ tile_info,
+                                                        int64_t n_pad, int64_t n,
+                                                        double *__restrict__ part1,
+                                                        double *__restrict__ part2) {
+  __shared__ double red[kTauBlock];
+  const int f = blockIdx.y, b = blockIdx.x;
+  const int64_t tiles = n_pad / AERL_TILE;
+  const int64_t t0 = tiles * b / kTauParts, t1 = tiles * (b + 1) / kTauParts;
+  const float *row = x_fm + (int64_t)f * n_pad;
+  const double mean = PASS == 2 ? tau_mean(part1, f, n) : 0.0;
+  double s = 0.0;
+  for (int64_t t = t0; t < t1; ++t) {
+    const int valid = tile_info[t] >> 8;
+    const int i = threadIdx.x;  // one sample of the tile per thread
+    if (i < valid) {
+      const double v = (double)row[t * AERL_TILE + i];
+      s += PASS == 1 ? v : (v - mean) * (v - mean);
     }
-  red[t] = q;
-  __syncthreads();
-  for (int h = kTauBlock / 2; h > 0; h >>= 1) {
-    if (t < h) red[t] += red[t + h];
-    __syncthreads();
   }
-  if (t == 0) {
-    double sd = n > 0 ? sqrt(red[0] / (double)n) : 0.0;
-    const float tf = sd > 0.0 ? (float)(0.05 * sd) : 1.0f;
-    tau[blockIdx.x] = tf;
-    tau[gridDim.x + blockIdx.x] = (float)(1.0 / (double)tf);  // 1/tau follows tau
-  }
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) (PASS == 1 ? part1 : part2)[(int64_t)f * kTauParts + b] = s;
+}
+
+__global__ void k_tau_final(const double *__restrict__ part2, int32_t nf, int64_t n,
+                            float *__restrict__ tau) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nf) return;
+  double q = 0.0;
+  for (int b = 0; b < kTauParts; ++b) q += part2[(int64_t)f * kTauParts + b];
+  const double sd = n > 0 ? sqrt(q / (double)n) : 0.0;
+  const float tf = sd > 0.0 ? (float)(0.05 * sd) : 1.0f;
+  tau[f] = tf;
+  tau[nf + f] = (float)(1.0 / (double)tf);  // 1/tau follows tau
 }
 
 }  // namespace
@@ -164,9 +192,16 @@ hipError_t launch_scatter_transpose(const float *x, const int32_t *y, int64_t n,
   return hipGetLastError();
 }
 
-hipError_t launch_tau(const float *x_fm, const int32_t *y_pad, int64_t n_pad, int32_t nf,
-                      int64_t n, float *tau, hipStream_t s) {
-  hipLaunchKernelGGL(k_tau, dim3((unsigned)nf), dim3(kTauBlock), 0, s, x_fm, y_pad, n_pad, n,
+hipError_t launch_tau(const float *x_fm, const int32_t *tile_info, int64_t n_pad, int32_t nf,
+                      int64_t n, double *part, float *tau, hipStream_t s) {
+  if (nf <= 0) return hipSuccess;
+  double *part1 = part, *part2 = part + (int64_t)nf * kTauParts;
+  const dim3 grid(kTauParts, (unsigned)nf);
+  hipLaunchKernelGGL(k_tau_part<1>, grid, dim3(kTauBlock), 0, s, x_fm, tile_info, n_pad, n, part1,
+                     part2);
+  hipLaunchKernelGGL(k_tau_part<2>, grid, dim3(kTauBlock), 0, s, x_fm, tile_info, n_pad, n, part1,
+                     part2);
+  hipLaunchKernelGGL(k_tau_final, dim3((unsigned)((nf + 63) / 64)), dim3(64), 0, s, part2, nf, n,
                      tau);
   return hipGetLastError();
 }

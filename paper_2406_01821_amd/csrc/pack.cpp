@@ -146,6 +146,8 @@ PackedLayout packed_layout(int32_t n_sets, int32_t n_rules, int32_t n_conds) {
   off = align256(off + sizeof(uint32_t) * (size_t)(n_conds > 0 ? n_conds : 1));
   L.heads_off = off;
   off = align256(off + sizeof(uint4) * ((size_t)n_conds + (size_t)n_rules + (size_t)std::max(n_sets, 0) + 1));
+  L.cmask_off = off;
+  off = align256(off + sizeof(uint2) * (size_t)(n_conds > 0 ? n_conds : 1));
   L.total = off;
   return L;
 }
@@ -186,9 +188,13 @@ aerl_status validate_population(aerl_ctx *ctx, const aerl_population *p, int32_t
     return fail(ctx, AERL_EINVAL, "condition arrays are NULL");
   for (int32_t j = 0; j < n_conds; ++j) {
     if (p->op[j] > 3) return fail(ctx, AERL_EINVAL, "op[%d] = %d is not an operator", j, p->op[j]);
-    if (p->kind[j] > 1) return fail(ctx, AERL_EINVAL, "kind[%d] = %d is not a kind", j, p->kind[j]);
+    if (p->kind[j] > 2) return fail(ctx, AERL_EINVAL, "kind[%d] = %d is not a kind", j, p->kind[j]);
     if (p->f[j] < 0 || p->f[j] >= nf)
       return fail(ctx, AERL_EINVAL, "f[%d] = %d outside [0, %d)", j, p->f[j], nf);
+    if (p->kind[j] == AERL_KIND_CATEGORICAL) {
+      if (!p->cat_mask) return fail(ctx, AERL_EINVAL, "cat_mask is NULL with a categorical condition");
+      continue;
+    }
     if (!std::isfinite(p->coef[j])) return fail(ctx, AERL_EINVAL, "coef[%d] is not finite", j);
     if (p->kind[j] == AERL_KIND_FEATURE) {
       if (!p->g || !p->coef2) return fail(ctx, AERL_EINVAL, "g/coef2 arrays are NULL");
@@ -253,15 +259,18 @@ void pack_sets(const aerl_population *p, const int32_t *first_of, int32_t s0, in
         hc[out++] = make_uint4(0u, 0u, 0u, kRecAlways | kRecLast | cls | next);
         continue;
       }
-      // groups: folded >=, folded <=, zero coefficient, feature >, feature >=
-      // (the sign of the rewritten coefficient decides a threshold's group);
-      // a stable counting sort puts the rule's conditions in group order
+      // groups: folded >=, folded <=, zero coefficient, feature >, feature >=,
+      // categorical (the sign of the rewritten coefficient decides a
+      // threshold's group); a stable counting sort puts the rule's conditions
+      // in group order
       uint8_t grp_of[256], order[256];  // at most AERL_MAX_RULE_CONDS conditions
-      int32_t start[6] = {0, 0, 0, 0, 0, 0};
+      int32_t start[7] = {0, 0, 0, 0, 0, 0, 0};
       for (int32_t j = j0; j < j1; ++j) {
         const int op = p->op[j];
         int g;
-        if (p->kind[j] == AERL_KIND_FEATURE) {
+        if (p->kind[j] == AERL_KIND_CATEGORICAL) {
+          g = 5;
+        } else if (p->kind[j] == AERL_KIND_FEATURE) {
           g = (op == AERL_OP_GT || op == AERL_OP_LT) ? 3 : 4;
         } else {
           const float a0 = (op == AERL_OP_LT || op == AERL_OP_LE) ? -p->coef[j] : p->coef[j];
@@ -270,7 +279,7 @@ void pack_sets(const aerl_population *p, const int32_t *first_of, int32_t s0, in
         grp_of[j - j0] = (uint8_t)g;
         ++start[g + 1];
       }
-      for (int g = 0; g < 5; ++g) start[g + 1] += start[g];
+      for (int g = 0; g < 6; ++g) start[g + 1] += start[g];
       for (int32_t i = 0; i < k; ++i) order[start[grp_of[i]]++] = (uint8_t)i;
       int prev_grp = -1;
       for (int32_t pos = 0; pos < k; ++pos) {
@@ -279,7 +288,14 @@ void pack_sets(const aerl_population *p, const int32_t *first_of, int32_t s0, in
         const int op = p->op[j];
         float a, b;
         uint32_t w = cls | next;
-        if (grp < 3) {
+        uint32_t ya = 0, zb = 0;  // raw operand bits of a categorical record
+        if (grp == 5) {
+          const uint64_t mk = p->cat_mask[j];
+          ya = (uint32_t)mk;
+          zb = (uint32_t)(mk >> 32);
+          a = b = 0.0f;
+          w |= kRecCat;
+        } else if (grp < 3) {
           uint32_t flags;
           threshold_record(p->coef[j], p->theta[j], op, &a, &b, &flags);
           if (grp == 1 && prev_grp != 1) flags |= kRecDirChg;
@@ -303,7 +319,8 @@ void pack_sets(const aerl_population *p, const int32_t *first_of, int32_t s0, in
             head.w = tt;
           }
         }
-        hc[out++] = make_uint4((uint32_t)p->f[j] * 1024u, fbits(a), fbits(b), w);
+        hc[out++] = make_uint4((uint32_t)p->f[j] * 1024u, grp == 5 ? ya : fbits(a),
+                               grp == 5 ? zb : fbits(b), w);
       }
     }
     const uint32_t end = (uint32_t)(out - first + 1) * 16u << kRecNextShift;
@@ -326,19 +343,25 @@ void pack_sets(const aerl_population *p, const int32_t *first_of, int32_t s0, in
 // Soft-path rule records and condition words of rules [q0, q1); counts the
 // feature-vs-feature conditions among their conditions.
 void pack_rules(const aerl_population *p, int32_t q0, int32_t q1, int4 *rules, uint32_t *sc,
-                int32_t *n_ff) {
-  int32_t ff = 0;
+                uint2 *cm, int32_t *n_ff, int32_t *n_cat) {
+  int32_t ff = 0, cat = 0;
   for (int32_t r = q0; r < q1; ++r) {
     const int32_t j0 = p->rule_cond_off[r], j1 = p->rule_cond_off[r + 1];
     rules[r] = make_int4(j0, j1 - j0, p->rule_class[r], 0);
     for (int32_t j = j0; j < j1; ++j) {
-      const uint32_t g = p->kind[j] == AERL_KIND_FEATURE ? (uint32_t)p->g[j] : 0u;
-      sc[j] = (uint32_t)p->f[j] | (g << 12) | ((uint32_t)p->kind[j] << 24) |
-              ((uint32_t)(p->op[j] >= AERL_OP_GT) << 25);
-      ff += p->kind[j] == AERL_KIND_FEATURE;
+      const bool is_ff = p->kind[j] == AERL_KIND_FEATURE;
+      const bool is_cat = p->kind[j] == AERL_KIND_CATEGORICAL;
+      const uint32_t g = is_ff ? (uint32_t)p->g[j] : 0u;
+      sc[j] = (uint32_t)p->f[j] | (g << 12) | (is_ff ? kSoftFF : 0u) |
+              ((uint32_t)(p->op[j] >= AERL_OP_GT) << 25) | (is_cat ? kSoftCat : 0u);
+      const uint64_t mk = is_cat ? p->cat_mask[j] : 0u;
+      cm[j] = make_uint2((uint32_t)mk, (uint32_t)(mk >> 32));
+      ff += is_ff;
+      cat += is_cat;
     }
   }
   *n_ff = ff;
+  *n_cat = cat;
 }
 
 // Runs fn(i) for i in [0, n) on up to n host threads (i = 0 on the caller).
@@ -373,6 +396,7 @@ void pack_population_image(const aerl_population *p, int32_t nf, int32_t nc, int
   uint4 *hc = reinterpret_cast<uint4 *>(base + L.hconds_off);
   uint32_t *sc = reinterpret_cast<uint32_t *>(base + L.sconds_off);
   uint4 *heads = reinterpret_cast<uint4 *>(base + L.heads_off);
+  uint2 *cm = reinterpret_cast<uint2 *>(base + L.cmask_off);
   // first record of every rule set: one per condition, one per empty rule,
   // one closing record
   std::vector<int32_t> first(p->n_sets + 1);
@@ -394,14 +418,15 @@ void pack_population_image(const aerl_population *p, int32_t nf, int32_t nc, int
   zero_tail(L.rules_off + sizeof(int4) * (size_t)n_rules, L.hconds_off);
   zero_tail(L.hconds_off + sizeof(uint4) * (size_t)n_rec, L.sconds_off);
   zero_tail(L.sconds_off + sizeof(uint32_t) * (size_t)n_conds, L.heads_off);
-  zero_tail(L.heads_off + sizeof(uint4) * (size_t)n_rec, L.total);
+  zero_tail(L.heads_off + sizeof(uint4) * (size_t)n_rec, L.cmask_off);
+  zero_tail(L.cmask_off + sizeof(uint2) * (size_t)n_conds, L.total);
   // about 16k conditions per thread, at most 8 threads
   const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
   const int parts = (int)std::max<int64_t>(
       1, std::min<int64_t>({(int64_t)std::min(hw, 8u), (int64_t)n_conds / 16384 + 1,
                             (int64_t)std::max(p->n_sets, 1)}));
   std::vector<PackStats> stats(parts);
-  std::vector<int32_t> ffs(parts, 0);
+  std::vector<int32_t> ffs(parts, 0), cats(parts, 0);
   run_parts(parts, [&](int i) {
     // sets split by records, rules by index
     const int64_t lo_rec = (int64_t)n_rec * i / parts, hi_rec = (int64_t)n_rec * (i + 1) / parts;
@@ -411,11 +436,12 @@ void pack_population_image(const aerl_population *p, int32_t nf, int32_t nc, int
     pack_sets(p, first.data(), s0, s1, sets, ssets, hc, heads, &stats[i]);
     const int32_t q0 = (int32_t)((int64_t)n_rules * i / parts);
     const int32_t q1 = (int32_t)((int64_t)n_rules * (i + 1) / parts);
-    pack_rules(p, q0, q1, rules, sc, &ffs[i]);
+    pack_rules(p, q0, q1, rules, sc, cm, &ffs[i], &cats[i]);
   });
   PackStats all;
-  int32_t n_ff = 0;
+  int32_t n_ff = 0, n_cat = 0;
   for (int i = 0; i < parts; ++i) {
+    n_cat += cats[i];
     all.max_rules = std::max(all.max_rules, stats[i].max_rules);
     all.max_rule_conds = std::max(all.max_rule_conds, stats[i].max_rule_conds);
     all.max_set_conds = std::max(all.max_set_conds, stats[i].max_set_conds);
@@ -426,6 +452,7 @@ void pack_population_image(const aerl_population *p, int32_t nf, int32_t nc, int
   (void)nc;
   rec->max_set_conds = all.max_set_conds;
   rec->n_ff = n_ff;
+  rec->n_cat = n_cat;
   rec->n_sets = p->n_sets;
   rec->n_rules = n_rules;
   rec->n_conds = n_conds;

@@ -24,11 +24,13 @@ __global__ void k_batch_zero(const BatchZero *__restrict__ z, int32_t n_z, int32
   }
 }
 
+// CAT: some item has categorical conditions.
+template <bool CAT>
 __global__ __launch_bounds__(kBatchBlock) AERL_HARD_SGPR_CAP void k_hard_batch(
     const BatchItem *__restrict__ items, const BatchTask *__restrict__ tasks, int32_t n_tasks,
     int32_t *__restrict__ counter) {
   extern __shared__ __align__(16) float smem[];
-  __shared__ int32_t next_q;
+  __shared__ int32_t sh[2];
   __shared__ int32_t task_id;
   for (;;) {
     if (threadIdx.x == 0) task_id = atomicAdd(counter, 1);
@@ -54,9 +56,9 @@ __global__ __launch_bounds__(kBatchBlock) AERL_HARD_SGPR_CAP void k_hard_batch(
     t.tile_hi = tk.tile_hi;
     t.label = tk.label;
     switch (it.S) {
-      case 4: hard_block<4>(t, smem, &next_q); break;
-      case 2: hard_block<2>(t, smem, &next_q); break;
-      default: hard_block<1>(t, smem, &next_q); break;
+      case 4: hard_block<4, CAT>(t, smem, sh); break;
+      case 2: hard_block<2, CAT>(t, smem, sh); break;
+      default: hard_block<1, CAT>(t, smem, sh); break;
     }
   }
 }
@@ -91,8 +93,12 @@ hipError_t launch_batch(const BatchLaunch &b, hipStream_t st) {
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || b.n_tasks == 0) return e;
-  hipLaunchKernelGGL(k_hard_batch, dim3((unsigned)b.grid), dim3(kBatchBlock), b.lds, st, b.items,
-                     b.tasks, b.n_tasks, b.counter);
+  if (b.cat)
+    hipLaunchKernelGGL(k_hard_batch<true>, dim3((unsigned)b.grid), dim3(kBatchBlock), b.lds, st,
+                       b.items, b.tasks, b.n_tasks, b.counter);
+  else
+    hipLaunchKernelGGL(k_hard_batch<false>, dim3((unsigned)b.grid), dim3(kBatchBlock), b.lds, st,
+                       b.items, b.tasks, b.n_tasks, b.counter);
   return hipGetLastError();
 }
 

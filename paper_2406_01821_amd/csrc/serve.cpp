@@ -229,7 +229,7 @@ bool Serve::launch_one(std::unique_lock<std::mutex> &lk, Slot &slot) {
       int32_t *cf = r->h_conf ? reinterpret_cast<int32_t *>(dev + r->out_off + al(r->correct_bytes()))
                               : nullptr;
       src.push_back({r->ds, r->rec.n_sets, reinterpret_cast<const int4 *>(r->image.data()), dsets,
-                     dconds, dheads, c, cf});
+                     dconds, dheads, c, cf, r->rec.n_cat > 0});
     } else {
       const int S = predict_samples_per_lane(r->nf);
       plds = std::max(plds, (size_t)r->nf * 64 * S * 4);

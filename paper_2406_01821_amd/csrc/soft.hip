@@ -241,6 +241,17 @@ __device__ __forceinline__ void group_range(const SoftArgs &a, int g, int &label
   }
 }
 
+// A categorical condition has no parameter to relax: its soft truth is its
+// truth, z = +inf (x[f] is a code k in 0..63 with bit k of the mask {lo, hi}
+// set) or -inf.
+__device__ __forceinline__ float cat_z(float v, uint32_t lo, uint32_t hi) {
+  const bool ok = v >= 0.0f && v <= 63.0f && v == truncf(v);  // NaN fails
+  const int code = ok ? (int)v : 0;
+  const uint32_t word = code < 32 ? lo : hi;
+  const bool in = ok && ((word >> (code & 31)) & 1u) != 0u;
+  return in ? __builtin_huge_valf() : -__builtin_huge_valf();
+}
+
 // z2 = z*log2(e) of condition j for S values of x[f], with x[f] and the
 // right-hand factor xg: x[g] for feature conditions, 1 for threshold ones (so
 // dz*xg is their theta term).  Branch-free on the kind (the row of g is read
@@ -252,10 +263,18 @@ __device__ __forceinline__ void cond_z(const SoftArgs &a, const float *xs, int l
   const uint4 r = ldc(a.crec, j);
   const uint32_t sc = r.x;
   const uint32_t f = sc & 0xfffu, g = (sc >> 12) & 0xfffu;
-  ff = ((sc >> 24) & 1u) != 0;
+  ff = (sc & kSoftFF) != 0;
   const float c = __uint_as_float(r.y), rv = __uint_as_float(r.z), sinv = __uint_as_float(r.w);
   load_row<S>(xs, f * 1024u, lane, xf);
   load_row<S>(xs, g * 1024u, lane, xg);
+  if (sc & kSoftCat) {
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      z[s] = cat_z(xf[s], r.y, r.z);
+      xg[s] = 1.0f;
+    }
+    return;
+  }
 #pragma unroll
   for (int s = 0; s < S; ++s) {
     const float rhs = ff ? rv * xg[s] : rv;
@@ -289,11 +308,14 @@ __device__ __forceinline__ void cond_z_only(const SoftArgs &a, const float *xs, 
   const float c = __uint_as_float(r.y), rv = __uint_as_float(r.z), sinv = __uint_as_float(r.w);
   float xf[S];
   load_row<S>(xs, f * 1024u, lane, xf);
-  if ((sc >> 24) & 1u) {
+  if (sc & kSoftFF) {
     float xg[S];
     load_row<S>(xs, g * 1024u, lane, xg);
 #pragma unroll
     for (int s = 0; s < S; ++s) z[s] = fmaf(c, xf[s], -(rv * xg[s])) * sinv;
+  } else if (sc & kSoftCat) {
+#pragma unroll
+    for (int s = 0; s < S; ++s) z[s] = cat_z(xf[s], r.y, r.z);
   } else {
 #pragma unroll
     for (int s = 0; s < S; ++s) z[s] = fmaf(c, xf[s], -rv) * sinv;
@@ -318,11 +340,14 @@ __device__ __forceinline__ void cond_z4(const SoftArgs &a, const float *xs, int 
     const uint32_t sc = r[4 * k];
     const float c = __uint_as_float(r[4 * k + 1]), rv = __uint_as_float(r[4 * k + 2]);
     const float sinv = __uint_as_float(r[4 * k + 3]);
-    if (!TONLY && ((sc >> 24) & 1u)) {
+    if (!TONLY && (sc & kSoftFF)) {
       float xg[S];
       load_row<S>(xs, ((sc >> 12) & 0xfffu) * 1024u, lane, xg);
 #pragma unroll
       for (int s = 0; s < S; ++s) z[k][s] = fmaf(c, xf[k][s], -(rv * xg[s])) * sinv;
+    } else if (!TONLY && (sc & kSoftCat)) {
+#pragma unroll
+      for (int s = 0; s < S; ++s) z[k][s] = cat_z(xf[k][s], r[4 * k + 1], r[4 * k + 2]);
     } else {
 #pragma unroll
       for (int s = 0; s < S; ++s) z[k][s] = fmaf(c, xf[k][s], -rv) * sinv;
@@ -335,11 +360,16 @@ __device__ __forceinline__ void cond_z4(const SoftArgs &a, const float *xs, int 
 // feature-vs-feature condition; sinv = +-log2(e)/tau_f by direction.
 __global__ void k_soft_prep(const uint32_t *__restrict__ sconds, const float *__restrict__ inv_tau,
                             const float *__restrict__ coef, const float *__restrict__ coef2,
-                            const float *__restrict__ theta, int32_t n_conds,
-                            uint4 *__restrict__ crec) {
+                            const float *__restrict__ theta, const uint2 *__restrict__ cmask,
+                            int32_t n_conds, uint4 *__restrict__ crec) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n_conds) return;
   const uint32_t sc = sconds[j];
+  if (sc & kSoftCat) {  // the code set replaces the parameters
+    const uint2 m = cmask[j];
+    crec[j] = make_uint4(sc, m.x, m.y, 0u);
+    return;
+  }
   const float inv = inv_tau[sc & 0xfffu] * kLog2e;
   const float sinv = ((sc >> 25) & 1u) ? inv : -inv;
   const float rv = ((sc >> 24) & 1u) ? coef2[j] : theta[j];
@@ -446,6 +476,8 @@ __global__ void k_soft_fwd_final(const double *__restrict__ part, int32_t n_grou
 }
 
 // ----------------------------------------------------------------- backward
+// Waves per block of the LDS-state adjoint kernels: up to kBwdWaves, fewer
+// for rule sets whose per-wave state ([R][2][64] floats) would not fit.
 constexpr int kBwdWaves = 8;
 
 __global__ __launch_bounds__(kBwdWaves * 64) void k_soft_bwd(const SoftArgs a) {
@@ -548,10 +580,12 @@ __global__ __launch_bounds__(kBwdWaves * 64) void k_soft_bwd(const SoftArgs a) {
   }
 }
 
-// Register-resident adjoint for rule sets of at most RMAX rules: S samples
-// per lane, and the only per-rule state kept between the two sweeps is
-// l_k = a_k + (survival before k), RMAX x S floats in VGPRs (read and
-// written through a uniform branch chain on k).  The reverse sweep
+// Adjoint for rule sets of at most RMAX rules with S samples per lane: the
+// only per-rule state kept between the two sweeps is l_k = a_k + (survival
+// before k), an RMAX x S array of floats per lane, read and written through
+// a uniform branch chain on k; at the 64-VGPR budget of eight waves per SIMD
+// the compiler keeps it in per-lane private memory (scratch, served by the
+// vector caches) for RMAX = 16 with four samples per lane.  The reverse sweep
 // recomputes every condition once: the same exp/log gives the rule's a_k
 // and log(1 - r_k) for the U recurrence and log sigmoid(z) for the
 // gradient.  Per condition the S slots are summed in the lane, then over the
@@ -788,8 +822,22 @@ __global__ void k_soft_bwd_final(const float *__restrict__ part, int32_t n_group
 struct SoftPlan {
   int S, Q, TG, n_groups;
   int rmax;  // backward: rule bound of the register-resident kernel, 0 = general kernel
+  int waves; // LDS-state kernels: waves per block
   size_t lds;
 };
+
+// Waves and rule-set chunk of an LDS-state adjoint kernel (tile xs bytes,
+// per_set accumulator bytes, per_wave state bytes): the most waves (at most
+// max_waves) that fit with one rule set per chunk, then the largest chunk
+// (at most max_q sets) that fits.
+void lds_state_plan(SoftPlan &p, size_t xs, size_t per_set, size_t per_wave, int max_waves,
+                    int max_q, int n_sets) {
+  p.waves = max_waves;
+  while (p.waves > 1 && xs + per_set + p.waves * per_wave > kDynLdsMax) p.waves >>= 1;
+  p.Q = std::max(1, std::min(n_sets, max_q));
+  while (p.Q > 1 && xs + p.Q * per_set + p.waves * per_wave > kDynLdsMax) p.Q >>= 1;
+  p.lds = xs + (size_t)p.Q * per_set + p.waves * per_wave;
+}
 
 int64_t count_groups(const DatasetRec &ds, int tg) {
   int64_t g = 0;
@@ -833,11 +881,7 @@ SoftPlan plan_backward(const DatasetRec &ds, const PopRec &pop) {
   }
   p.rmax = 0;
   p.S = 1;
-  const size_t xs = (size_t)ds.nf * 64 * 4;
-  const size_t per_wave = (size_t)R * 128 * 4;
-  p.Q = std::max(1, std::min(pop.n_sets, 16));
-  while (p.Q > 1 && xs + p.Q * per_set + kBwdWaves * per_wave > kDynLdsMax) p.Q >>= 1;
-  p.lds = xs + (size_t)p.Q * per_set + kBwdWaves * per_wave;
+  lds_state_plan(p, (size_t)ds.nf * 64 * 4, per_set, (size_t)R * 128 * 4, kBwdWaves, 16, pop.n_sets);
   return p;
 }
 
@@ -927,7 +971,7 @@ hipError_t launch_prep(const SoftLaunch &l, const SoftArgs &a, uint4 *crec, hipS
   const int n = l.pop->n_conds;
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_soft_prep, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a.sconds,
-                     a.inv_tau, a.coef, a.coef2, a.theta, n, crec);
+                     a.inv_tau, a.coef, a.coef2, a.theta, l.pop->cmask, n, crec);
   return hipGetLastError();
 }
 
@@ -950,7 +994,7 @@ hipError_t launch_soft_forward(const SoftLaunch &l, hipStream_t st) {
   if (e0 != hipSuccess) return e0;
   if (p.n_groups > 0) {
     const dim3 grid((unsigned)((pop.n_sets + p.Q - 1) / p.Q), (unsigned)p.n_groups);
-    const bool prod = pop.max_rule_conds <= kProdMaxConds, tonly = pop.n_ff == 0;
+    const bool prod = pop.max_rule_conds <= kProdMaxConds, tonly = pop.n_ff == 0 && pop.n_cat == 0;
     if (prod && tonly) {
       launch_fwd<RuleProd, true>(p, grid, st, a);
     } else if (prod) {
@@ -965,6 +1009,471 @@ hipError_t launch_soft_forward(const SoftLaunch &l, hipStream_t st) {
   }
   hipLaunchKernelGGL(k_soft_fwd_final, dim3((unsigned)((pop.n_sets + 255) / 256)), dim3(256), 0, st,
                      a.part_loss, p.n_groups, pop.n_sets, l.ds->n, l.loss);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ softmax head
+// Section 5: probabilistic outputs through a softmax.  Each rule votes for
+// its class with its soft truth r_k, the default class takes the probability
+// that no rule fires, D = prod_k (1 - r_k):
+//   v_c = sum_{k: class_k = c} r_k + [c = default] D,  P = softmax(beta v),
+// L = min(-log P_y, 100).  Adjoint: dL/dv_c = beta (P_c - [c = y]),
+// dL/dr_k = dL/dv_{class_k} - dL/dv_default * prod_{i != k} (1 - r_i), the
+// product being 2^(S_k + T_k) with the prefix S_k and suffix T_k sums of
+// log2(1 - r_i); dL/dz = dL/dr_k * r_k * sigmoid(-z).  Classes are padded to
+// NC (a power of two up to kSmaxMaxClasses) in registers; rule classes are
+// wave-uniform, so a vote is NC selects.
+namespace {
+
+template <int NC>
+__device__ __forceinline__ void add_vote(float (&v)[NC], int cls, float r) {
+#pragma unroll
+  for (int c = 0; c < NC; ++c) v[c] += (c == cls) ? r : 0.0f;
+}
+
+template <int NC>
+__device__ __forceinline__ float pick(const float (&v)[NC], int cls) {
+  float out = 0.0f;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) out = (c == cls) ? v[c] : out;
+  return out;
+}
+
+// log2 P_y from the votes, and P (every class) into p.  beta2 = beta*log2(e).
+template <int NC>
+__device__ __forceinline__ float smax_log2py(const float (&v)[NC], int nc, float beta2, int y,
+                                             float (&p)[NC]) {
+  float m = kNegInf;
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+    if (c < nc) m = fmaxf(m, beta2 * v[c]);
+  float sum = 0.0f;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    p[c] = c < nc ? fexp2(beta2 * v[c] - m) : 0.0f;
+    sum += p[c];
+  }
+  const float inv = 1.0f / sum;
+  float ty = 0.0f;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    ty = (c == y) ? beta2 * v[c] : ty;
+    p[c] *= inv;
+  }
+  return ty - m - flog2(sum);
+}
+
+constexpr int kSmaxFwdS = 2;
+constexpr int kSmaxBwdWaves = 4;
+
+template <int NC, class Acc, bool TONLY>
+__global__ __launch_bounds__(kSoftBlock) void k_smax_fwd(const SoftArgs a, float beta2) {
+  constexpr int S = kSmaxFwdS, TS = 64 * S, WPT = AERL_TILE / TS;
+  extern __shared__ __align__(16) float smem[];
+  float *xs = smem;
+  double *acc = reinterpret_cast<double *>(smem + (size_t)a.nf * TS);  // [Q]
+  __shared__ int32_t next_q;
+  const int lane = threadIdx.x & 63;
+  int label, tile_lo, tile_hi;
+  group_range(a, blockIdx.y, label, tile_lo, tile_hi);
+  const int q0 = blockIdx.x * a.sets_per_chunk;
+  const int Q = min(a.sets_per_chunk, a.n_sets - q0);
+  for (int i = threadIdx.x; i < Q; i += blockDim.x) acc[i] = 0.0;
+  const int n4 = a.nf * (TS / 4);
+  const float4 *src = reinterpret_cast<const float4 *>(a.x_fm);
+  float4 *dst = reinterpret_cast<float4 *>(xs);
+  const int64_t row4 = a.n_pad / 4;
+  for (int64_t wt = (int64_t)tile_lo * WPT; wt < (int64_t)tile_hi * WPT; ++wt) {
+    __syncthreads();
+    const int64_t base4 = wt * (TS / 4);
+    for (int i = threadIdx.x; i < n4; i += blockDim.x) {
+      const int f = i / (TS / 4), k = i % (TS / 4);
+      dst[i] = src[(int64_t)f * row4 + base4 + k];
+    }
+    if (threadIdx.x == 0) next_q = 0;
+    __syncthreads();
+    const int info = ldc(a.tile_info, wt / WPT);
+    const int valid = min(max((info >> 8) - (int)(wt % WPT) * TS, 0), TS);
+    for (;;) {
+      const int q = next_item(&next_q);
+      if (q >= Q) break;
+      const int4 ss = ldc(a.ssets, q0 + q);
+      const int dflt = ldc(a.sets, q0 + q).z;
+      float v[S][NC], surv[S];
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        surv[s] = 0.0f;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) v[s][c] = 0.0f;
+      }
+      for (int k = 0; k < ss.y; ++k) {
+        const int4 r = ldc(a.rules, ss.x + k);
+        Acc ra[S];
+        int j = r.x;
+        const int je = r.x + r.y;
+        for (; j + 4 <= je; j += 4) {
+          float z[4][S];
+          cond_z4<S, TONLY>(a, xs, lane, j, z);
+#pragma unroll
+          for (int c4 = 0; c4 < 4; ++c4) {
+#pragma unroll
+            for (int s = 0; s < S; ++s) (void)ra[s].add(z[c4][s]);
+          }
+        }
+        for (; j < je; ++j) {
+          float z[S];
+          cond_z_only<S>(a, xs, lane, j, z);
+#pragma unroll
+          for (int s = 0; s < S; ++s) (void)ra[s].add(z[s]);
+        }
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          float a2, b2;
+          acc_finish(ra[s], a2, b2);
+          add_vote(v[s], r.z, fexp2(a2));
+          surv[s] += b2;
+        }
+      }
+      float part = 0.0f;
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        add_vote(v[s], dflt, fexp2(surv[s]));
+        float p[NC];
+        const float l2 = smax_log2py(v[s], a.nc, beta2, label, p);
+        part += lane * S + s < valid ? sample_loss(l2) : 0.0f;
+      }
+      part = wave_sum(part);
+      if (lane == 0) acc[q] += (double)part;
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < Q; i += blockDim.x)
+    a.part_loss[(int64_t)blockIdx.y * a.n_sets + q0 + i] = acc[i];
+}
+
+template <int NC, class Acc, bool TONLY>
+__global__ __launch_bounds__(kSmaxBwdWaves * 64) void k_smax_bwd(const SoftArgs a, float beta,
+                                                                 float beta2) {
+  constexpr int TS = 64, WPT = AERL_TILE / TS;
+  extern __shared__ __align__(16) float smem[];
+  float *xs = smem;                                                     // [nf][64]
+  float *acc = xs + (size_t)a.nf * TS;                                  // [Q][max_set_conds][2]
+  float *store = acc + (size_t)a.sets_per_chunk * a.max_set_conds * 2;  // [wave][R][2][64]
+  __shared__ int32_t next_q;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  float *my = store + (size_t)wave * a.max_rules * 128;
+  int label, tile_lo, tile_hi;
+  group_range(a, blockIdx.y, label, tile_lo, tile_hi);
+  const int q0 = blockIdx.x * a.sets_per_chunk;
+  const int Q = min(a.sets_per_chunk, a.n_sets - q0);
+  for (int i = threadIdx.x; i < Q * a.max_set_conds * 2; i += blockDim.x) acc[i] = 0.0f;
+  const int n4 = a.nf * (TS / 4);
+  const float4 *src = reinterpret_cast<const float4 *>(a.x_fm);
+  float4 *dst = reinterpret_cast<float4 *>(xs);
+  const int64_t row4 = a.n_pad / 4;
+  for (int64_t wt = (int64_t)tile_lo * WPT; wt < (int64_t)tile_hi * WPT; ++wt) {
+    __syncthreads();
+    const int64_t base4 = wt * (TS / 4);
+    for (int i = threadIdx.x; i < n4; i += blockDim.x) {
+      const int f = i / (TS / 4), k = i % (TS / 4);
+      dst[i] = src[(int64_t)f * row4 + base4 + k];
+    }
+    if (threadIdx.x == 0) next_q = 0;
+    __syncthreads();
+    const int info = ldc(a.tile_info, wt / WPT);
+    const int valid = min(max((info >> 8) - (int)(wt % WPT) * TS, 0), TS);
+    const bool live = lane < valid;
+    for (;;) {
+      const int q = next_item(&next_q);
+      if (q >= Q) break;
+      const int4 ss = ldc(a.ssets, q0 + q);
+      const int dflt = ldc(a.sets, q0 + q).z;
+      // forward sweep: log2 r_k and the prefix of log2(1 - r_i) before k
+      float v[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) v[c] = 0.0f;
+      float surv = 0.0f;
+      for (int k = 0; k < ss.y; ++k) {
+        const int4 r = ldc(a.rules, ss.x + k);
+        Acc ra;
+        for (int j = r.x; j < r.x + r.y; ++j) {
+          float z[1];
+          cond_z_only<1>(a, xs, lane, j, z);
+          (void)ra.add(z[0]);
+        }
+        float a2, b2;
+        acc_finish(ra, a2, b2);
+        my[k * 128 + lane] = a2;
+        my[k * 128 + 64 + lane] = surv;
+        add_vote(v, r.z, fexp2(a2));
+        surv += b2;
+      }
+      add_vote(v, dflt, fexp2(surv));
+      float p[NC];
+      const float l2 = smax_log2py(v, a.nc, beta2, label, p);
+      // clamped samples (and padding) get no gradient
+      const bool on = live && -l2 * kLn2 <= kLossCap;
+      // dL/dv_c = beta (P_c - [c = y]); for the label, -beta times the sum of
+      // the other classes' probabilities (P_y - 1 would cancel when P_y ~ 1)
+      float others = 0.0f;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) others += c == label ? 0.0f : p[c];
+      float gv[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) gv[c] = on ? beta * (c == label ? -others : p[c]) : 0.0f;
+      const float gd = pick(gv, dflt);
+      // reverse sweep with the suffix of log2(1 - r_i) after k
+      float tail = 0.0f;
+      const bool few = ss.w <= 64;
+      int tot0 = 0, tot1 = 0;
+      for (int k = ss.y - 1; k >= 0; --k) {
+        const int4 r = ldc(a.rules, ss.x + k);
+        const float a2k = my[k * 128 + lane];
+        const float others = my[k * 128 + 64 + lane] + tail;  // log2 prod_{i != k} (1 - r_i)
+        // a rule of the default class: g_d (1 - prod), with 1 - prod formed
+        // directly (the difference of the two terms would cancel)
+        const float drk = r.z == dflt ? gd * one_minus_exp2(others)
+                                      : pick(gv, r.z) - gd * fexp2(others);
+        Acc ra;
+        for (int j = r.x; j < r.x + r.y; ++j) {
+          float z[1], xf[1], xg[1];
+          if constexpr (TONLY) {
+            cond_z_t<1>(a, xs, lane, j, z, xf, xg);
+          } else {
+            bool ff;
+            cond_z<1>(a, xs, lane, j, z, xf, xg, ff);
+          }
+          const float t = ra.add(z[0]);
+          // dL/dz = dL/dr_k * r_k * sigmoid(-z)
+          const float dz = drk * acc_sig_neg(ra, a2k, z[0], t);
+          const float g0 = wave_total_last(dz * xg[0]);
+          const float g1 = wave_total_last(dz * xf[0]);
+          if (few) {
+            // lane i keeps the walk's totals of condition i of the set
+            const int v0 = __builtin_amdgcn_readlane(__float_as_int(g0), 63);
+            const int v1 = __builtin_amdgcn_readlane(__float_as_int(g1), 63);
+            const bool mine = lane == j - ss.z;
+            tot0 = mine ? v0 : tot0;
+            tot1 = mine ? v1 : tot1;
+          } else if (lane == 63) {
+            // one writer per (rule set, tile): the order of these adds is fixed
+            float *ap = acc + ((size_t)q * a.max_set_conds + (j - ss.z)) * 2;
+            ap[0] += g0;
+            ap[1] += g1;
+          }
+        }
+        float a2, b2;
+        acc_finish(ra, a2, b2);
+        tail += b2;
+      }
+      if (few && lane < ss.w) {
+        float *ap = acc + ((size_t)q * a.max_set_conds + lane) * 2;
+        ap[0] += __int_as_float(tot0);
+        ap[1] += __int_as_float(tot1);
+      }
+    }
+  }
+  __syncthreads();
+  for (int q = 0; q < Q; ++q) {
+    const int4 ss = ldc(a.ssets, q0 + q);
+    for (int i = threadIdx.x; i < ss.w * 2; i += blockDim.x)
+      a.part_grad[((int64_t)blockIdx.y * a.n_conds + ss.z) * 2 + i] =
+          acc[(size_t)q * a.max_set_conds * 2 + i];
+  }
+}
+
+// Class probabilities of one rule set for row-major rows, one row per
+// thread (the gathered condition records give z).
+template <int NC>
+__global__ __launch_bounds__(256) void k_smax_proba(const float *__restrict__ rows, int64_t n,
+                                                    int32_t nf, int32_t nc, int32_t set,
+                                                    const int4 *__restrict__ sets,
+                                                    const int4 *__restrict__ ssets,
+                                                    const int4 *__restrict__ rules,
+                                                    const uint4 *__restrict__ crec, float beta2,
+                                                    float *__restrict__ probs) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int4 ss = ssets[set];
+  const int32_t dflt = sets[set].z;
+  const float *x = rows + i * nf;
+  float v[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) v[c] = 0.0f;
+  float surv = 0.0f;
+  for (int k = 0; k < ss.y; ++k) {
+    const int4 r = rules[ss.x + k];
+    RuleAcc ra;
+    for (int j = r.x; j < r.x + r.y; ++j) {
+      const uint4 c4 = crec[j];
+      const uint32_t sc = c4.x;
+      const float xf = x[sc & 0xfffu];
+      if (sc & kSoftCat) {
+        (void)ra.add(cat_z(xf, c4.y, c4.z));
+        continue;
+      }
+      const float rv = __uint_as_float(c4.z);
+      const float rhs = (sc & kSoftFF) ? rv * x[(sc >> 12) & 0xfffu] : rv;
+      (void)ra.add(fmaf(__uint_as_float(c4.y), xf, -rhs) * __uint_as_float(c4.w));
+    }
+    float a2, b2;
+    acc_finish(ra, a2, b2);
+    add_vote(v, r.z, fexp2(a2));
+    surv += b2;
+  }
+  add_vote(v, dflt, fexp2(surv));
+  float p[NC];
+  (void)smax_log2py(v, nc, beta2, 0, p);
+  for (int c = 0; c < nc; ++c) probs[i * nc + c] = p[c];
+}
+
+int smax_nc(int nc) { return nc <= 2 ? 2 : nc <= 4 ? 4 : nc <= 8 ? 8 : 16; }
+
+SoftPlan plan_smax_backward(const DatasetRec &ds, const PopRec &pop) {
+  SoftPlan p{};
+  const int R = std::max(pop.max_rules, 1);
+  const size_t per_set = (size_t)std::max(pop.max_set_conds, 1) * 2 * 4;
+  p.TG = 1;
+  while (count_groups(ds, p.TG) > kMaxGroups) p.TG *= 2;
+  p.n_groups = (int)count_groups(ds, p.TG);
+  p.S = 1;
+  lds_state_plan(p, (size_t)ds.nf * 64 * 4, per_set, (size_t)R * 128 * 4, kSmaxBwdWaves, 16,
+                 pop.n_sets);
+  return p;
+}
+
+SoftPlan plan_smax_forward(const DatasetRec &ds, const PopRec &pop) {
+  SoftPlan p = plan_forward(ds, pop);  // same groups (and so the same workspace)
+  p.S = kSmaxFwdS;
+  p.lds = (size_t)ds.nf * 64 * p.S * 4 + (size_t)p.Q * 8;
+  return p;
+}
+
+template <int NC>
+void launch_smax_fwd_nc(const SoftPlan &p, dim3 grid, hipStream_t st, const SoftArgs &a, bool prod,
+                        bool tonly, float beta2) {
+  if (prod && tonly)
+    hipLaunchKernelGGL((k_smax_fwd<NC, RuleProd, true>), grid, dim3(kSoftBlock), p.lds, st, a, beta2);
+  else if (prod)
+    hipLaunchKernelGGL((k_smax_fwd<NC, RuleProd, false>), grid, dim3(kSoftBlock), p.lds, st, a, beta2);
+  else if (tonly)
+    hipLaunchKernelGGL((k_smax_fwd<NC, RuleAcc, true>), grid, dim3(kSoftBlock), p.lds, st, a, beta2);
+  else
+    hipLaunchKernelGGL((k_smax_fwd<NC, RuleAcc, false>), grid, dim3(kSoftBlock), p.lds, st, a, beta2);
+}
+
+template <int NC>
+void launch_smax_bwd_nc(const SoftPlan &p, dim3 grid, hipStream_t st, const SoftArgs &a, bool prod,
+                        bool tonly, float beta, float beta2) {
+  const dim3 b(p.waves * 64);
+  if (prod && tonly)
+    hipLaunchKernelGGL((k_smax_bwd<NC, RuleProd, true>), grid, b, p.lds, st, a, beta, beta2);
+  else if (prod)
+    hipLaunchKernelGGL((k_smax_bwd<NC, RuleProd, false>), grid, b, p.lds, st, a, beta, beta2);
+  else if (tonly)
+    hipLaunchKernelGGL((k_smax_bwd<NC, RuleAcc, true>), grid, b, p.lds, st, a, beta, beta2);
+  else
+    hipLaunchKernelGGL((k_smax_bwd<NC, RuleAcc, false>), grid, b, p.lds, st, a, beta, beta2);
+}
+
+}  // namespace
+
+bool smax_supported(const DatasetRec &ds, const PopRec &pop) {
+  return ds.nc <= kSmaxMaxClasses && plan_smax_backward(ds, pop).lds <= kDynLdsMax &&
+         plan_smax_forward(ds, pop).lds <= kDynLdsMax;
+}
+
+hipError_t launch_smax_forward(const SoftLaunch &l, float beta, hipStream_t st) {
+  const PopRec &pop = *l.pop;
+  if (pop.n_sets == 0) return hipSuccess;
+  const SoftPlan p = plan_smax_forward(*l.ds, pop);
+  SoftArgs a;
+  fill_args(a, l, p);
+  a.part_loss = static_cast<double *>(l.ws);
+  uint4 *crec = reinterpret_cast<uint4 *>(static_cast<char *>(l.ws) + soft_part_bytes(*l.ds, pop, false));
+  a.crec = crec;
+  hipError_t e = launch_prep(l, a, crec, st);
+  if (e != hipSuccess) return e;
+  const float beta2 = beta * kLog2e;
+  if (p.n_groups > 0) {
+    const dim3 grid((unsigned)((pop.n_sets + p.Q - 1) / p.Q), (unsigned)p.n_groups);
+    const bool prod = pop.max_rule_conds <= kProdMaxConds, tonly = pop.n_ff == 0 && pop.n_cat == 0;
+    switch (smax_nc(l.ds->nc)) {
+      case 2: launch_smax_fwd_nc<2>(p, grid, st, a, prod, tonly, beta2); break;
+      case 4: launch_smax_fwd_nc<4>(p, grid, st, a, prod, tonly, beta2); break;
+      case 8: launch_smax_fwd_nc<8>(p, grid, st, a, prod, tonly, beta2); break;
+      default: launch_smax_fwd_nc<16>(p, grid, st, a, prod, tonly, beta2); break;
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_soft_fwd_final, dim3((unsigned)((pop.n_sets + 255) / 256)), dim3(256), 0, st,
+                     a.part_loss, p.n_groups, pop.n_sets, l.ds->n, l.loss);
+  return hipGetLastError();
+}
+
+hipError_t launch_smax_backward(const SoftLaunch &l, float beta, hipStream_t st) {
+  const PopRec &pop = *l.pop;
+  if (pop.n_sets == 0) return hipSuccess;
+  const SoftPlan p = plan_smax_backward(*l.ds, pop);
+  if (p.lds > kDynLdsMax) return hipErrorInvalidValue;
+  SoftArgs a;
+  fill_args(a, l, p);
+  a.part_grad = static_cast<float *>(l.ws);
+  uint4 *crec = reinterpret_cast<uint4 *>(static_cast<char *>(l.ws) + soft_part_bytes(*l.ds, pop, true));
+  a.crec = crec;
+  hipError_t e = launch_prep(l, a, crec, st);
+  if (e != hipSuccess) return e;
+  const float beta2 = beta * kLog2e;
+  if (p.n_groups > 0) {
+    const dim3 grid((unsigned)((pop.n_sets + p.Q - 1) / p.Q), (unsigned)p.n_groups);
+    const bool prod = pop.max_rule_conds <= kProdMaxConds, tonly = pop.n_ff == 0 && pop.n_cat == 0;
+    switch (smax_nc(l.ds->nc)) {
+      case 2: launch_smax_bwd_nc<2>(p, grid, st, a, prod, tonly, beta, beta2); break;
+      case 4: launch_smax_bwd_nc<4>(p, grid, st, a, prod, tonly, beta, beta2); break;
+      case 8: launch_smax_bwd_nc<8>(p, grid, st, a, prod, tonly, beta, beta2); break;
+      default: launch_smax_bwd_nc<16>(p, grid, st, a, prod, tonly, beta, beta2); break;
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_soft_bwd_final, dim3((unsigned)pop.n_sets), dim3(64), 0, st, a.part_grad,
+                     p.n_groups, pop.n_conds, pop.ssets, pop.sconds, l.ds->inv_tau, l.dloss,
+                     l.ds->n, l.dcoef, l.dcoef2, l.dtheta);
+  return hipGetLastError();
+}
+
+hipError_t launch_smax_proba(const SoftLaunch &l, int32_t set, float beta, const float *rows,
+                             int64_t n, float *probs, hipStream_t st) {
+  const PopRec &pop = *l.pop;
+  if (n <= 0) return hipSuccess;
+  SoftArgs a;
+  fill_args(a, l, plan_forward(*l.ds, pop));
+  uint4 *crec = reinterpret_cast<uint4 *>(static_cast<char *>(l.ws) + soft_part_bytes(*l.ds, pop, false));
+  a.crec = crec;
+  hipError_t e = launch_prep(l, a, crec, st);
+  if (e != hipSuccess) return e;
+  const float beta2 = beta * kLog2e;
+  const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+  const int nc = l.ds->nc;
+  switch (smax_nc(nc)) {
+    case 2:
+      hipLaunchKernelGGL(k_smax_proba<2>, grid, block, 0, st, rows, n, pop.nf, nc, set, pop.sets,
+                         pop.ssets, pop.rules, crec, beta2, probs);
+      break;
+    case 4:
+      hipLaunchKernelGGL(k_smax_proba<4>, grid, block, 0, st, rows, n, pop.nf, nc, set, pop.sets,
+                         pop.ssets, pop.rules, crec, beta2, probs);
+      break;
+    case 8:
+      hipLaunchKernelGGL(k_smax_proba<8>, grid, block, 0, st, rows, n, pop.nf, nc, set, pop.sets,
+                         pop.ssets, pop.rules, crec, beta2, probs);
+      break;
+    default:
+      hipLaunchKernelGGL(k_smax_proba<16>, grid, block, 0, st, rows, n, pop.nf, nc, set, pop.sets,
+                         pop.ssets, pop.rules, crec, beta2, probs);
+      break;
+  }
   return hipGetLastError();
 }
 
@@ -1006,7 +1515,7 @@ hipError_t launch_soft_backward(const SoftLaunch &l, hipStream_t st) {
   if (e0 != hipSuccess) return e0;
   if (p.n_groups > 0) {
     const dim3 grid((unsigned)((pop.n_sets + p.Q - 1) / p.Q), (unsigned)p.n_groups);
-    const bool prod = pop.max_rule_conds <= kProdMaxConds, tonly = pop.n_ff == 0;
+    const bool prod = pop.max_rule_conds <= kProdMaxConds, tonly = pop.n_ff == 0 && pop.n_cat == 0;
     if (p.rmax > 0 && prod && tonly) {
       launch_bwd_reg<RuleProd, true>(p, grid, st, a);
     } else if (p.rmax > 0 && prod) {
@@ -1016,7 +1525,7 @@ hipError_t launch_soft_backward(const SoftLaunch &l, hipStream_t st) {
     } else if (p.rmax > 0) {
       launch_bwd_reg<RuleAcc, false>(p, grid, st, a);
     } else {
-      hipLaunchKernelGGL(k_soft_bwd, grid, dim3(kBwdWaves * 64), p.lds, st, a);
+      hipLaunchKernelGGL(k_soft_bwd, grid, dim3(p.waves * 64), p.lds, st, a);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -30,7 +30,8 @@ __global__ __launch_bounds__(kTuneBlock) void k_adam_step(
     float *__restrict__ v, float lr, float b1, float b2, float eps, float c1, float c2) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n_conds) return;
-  const bool ff = ((sconds[j] >> 24) & 1u) != 0;
+  if (sconds[j] & kSoftCat) return;  // a code set: nothing to tune
+  const bool ff = (sconds[j] & kSoftFF) != 0;
   float *rhs = ff ? coef2 : theta;
   const float g[2] = {dcoef[j], ff ? dcoef2[j] : dtheta[j]};
   float *p[2] = {coef + j, rhs + j};
@@ -52,7 +53,8 @@ __global__ __launch_bounds__(kTuneBlock) void k_sgd_step(
     const float *__restrict__ dcoef2, const float *__restrict__ dtheta, float lr) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n_conds) return;
-  const bool ff = ((sconds[j] >> 24) & 1u) != 0;
+  if (sconds[j] & kSoftCat) return;  // a code set: nothing to tune
+  const bool ff = (sconds[j] & kSoftFF) != 0;
   coef[j] -= lr * dcoef[j];
   if (ff)
     coef2[j] -= lr * dcoef2[j];

@@ -65,6 +65,30 @@ def test_upload_layout_groups_labels_and_computes_tau(ctx):
     assert ulps.max() <= 1
 
 
+@pytest.mark.parametrize("n", [5, 300_001])
+def test_tau_over_many_slices_is_exact_and_repeatable(ctx, n):
+    """tau over a row split into many slices (and over fewer tiles than
+    slices): within 1 ulp of the fp64 oracle, 1 for a constant column, and
+    the same bits on a second upload."""
+    import torch
+    rng = np.random.default_rng(n)
+    x = synth.lognormal_features(rng, n, 6)
+    x[:, 2] = 3.5
+    x[:, 4] *= 1e4
+    data = Dataset(x, rng.integers(0, 4, size=n).astype(np.int32), 4, "tau")
+    taus = []
+    for _ in range(2):
+        ds = ctx.upload_dataset(data)
+        info = ctx.dataset_info(ds)
+        torch.cuda.synchronize()
+        taus.append(info["tau"].cpu().numpy().copy())
+        ctx.release_dataset(ds)
+    ref = oracle.tau(x)
+    assert np.array_equal(taus[0], taus[1])
+    assert np.abs(taus[0].view(np.int32) - ref.view(np.int32)).max() <= 1
+    assert taus[0][2] == 1.0
+
+
 def test_small_workload_bit_exact(ctx):
     w = synth.small_hard(0)
     check_against_oracle(ctx, w.data, w.pop)

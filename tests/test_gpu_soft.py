@@ -100,20 +100,25 @@ def test_mixed_kinds_ops_and_classes(ctx, seed, nc):
 
 @pytest.mark.parametrize("rules,conds,nf", [((17, 32), (1, 3), 12), ((33, 36), (1, 3), 8),
                                             ((1, 8), (1, 3), 300), ((9, 16), (1, 3), 100),
-                                            ((1, 3), (58, 66), 40), ((9, 12), (55, 64), 16)])
+                                            ((1, 3), (58, 66), 40), ((9, 12), (55, 64), 16),
+                                            ((56, 64), (1, 8), 16), ((100, 120), (1, 2), 8)])
 def test_every_adjoint_variant(ctx, rules, conds, nf):
     """Rule bounds 8/16/32 of the register-resident adjoint (4, 2 or 1
     samples per lane by feature count), the LDS-resident kernel beyond 32
-    rules, and rules of more than 60 conditions (log-sum accumulator instead
-    of the product form)."""
+    rules (up to 64 rules x 8 conditions, the ragged workload's largest
+    shapes, and past 100 rules with fewer waves per block), and rules of
+    more than 60 conditions (log-sum accumulator instead of the product
+    form)."""
     w = synth.tiny(70 + rules[0] + conds[0], n=1500, nf=nf, n_classes=3, n_sets=12, rules=rules,
                    conds=conds, ff_frac=0.3)
     run_case(ctx, w.data, w.pop)
 
 
 def test_too_long_rule_sets_are_refused(ctx):
+    """Rule sets whose per-rule adjoint state does not fit one wave's LDS
+    (here 400 rules) are refused before any launch."""
     from paper_2406_01821_amd.aerl import AerlError, AERL_EINVAL
-    w = synth.tiny(90, n=300, nf=8, n_sets=2, rules=(64, 64), conds=(1, 2))
+    w = synth.tiny(90, n=300, nf=8, n_sets=2, rules=(400, 400), conds=(1, 1))
     ds = ctx.upload_dataset(w.data)
     p = ctx.pack_population(w.pop, 8, 2)
     c1, c2, th = params(w.pop, ctx.device)

@@ -1,0 +1,201 @@
+"""GPU parity of the softmax head (rule votes through a softmax, the
+probabilistic outputs of the paper's Section 5) against the fp64 oracle:
+loss within 1e-5 relative per rule set (plus 1e-6 absolute), gradients
+within 1e-4 * max(|g64|, 1e-3 * max|g64|) elementwise, class probabilities
+within 1e-5 relative (plus 1e-7 absolute) for request rows; finite
+differences, indifference to rule order, beta = 0, the full-size workload
+on sampled rule sets, determinism and the autograd wrapper."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2406_01821_amd import synth
+from paper_2406_01821_amd.population import from_rule_lists
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2406_01821_amd.aerl import Context
+    c = Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def _params(pop, dev):
+    import torch
+    return [torch.tensor(a, device=dev) for a in (pop.coef, pop.coef2, pop.theta)]
+
+
+def check_loss(got, ref):
+    bad = np.abs(got - ref) > 1e-5 * np.abs(ref) + 1e-6
+    assert not bad.any(), (np.nonzero(bad)[0], got[bad], ref[bad])
+
+
+def check_grad(got, ref):
+    used = 0.0
+    for k, (g, r) in enumerate(zip(got, ref)):
+        if r.size == 0:
+            continue
+        scale = np.abs(r).max()
+        if scale == 0.0:
+            assert np.all(g == 0.0), (k, np.abs(g).max())
+            continue
+        frac = np.abs(g - r) / (1e-4 * np.maximum(np.abs(r), 1e-3 * scale))
+        assert frac.max() <= 1.0, (k, np.argmax(frac), frac.max())
+        used = max(used, float(frac.max()))
+    print(f"gradient bound used: {used:.3f}")
+
+
+def gpu_case(ctx, data, pop, beta, dloss=None):
+    import torch
+    ds = ctx.upload_dataset(data)
+    p = ctx.pack_population(pop, data.n_features, data.n_classes)
+    c1, c2, th = _params(pop, ctx.device)
+    loss = ctx.softmax_forward(ds, p, c1, c2, th, beta)
+    dl = torch.tensor(np.ones(pop.n_sets) if dloss is None else dloss, dtype=torch.float32,
+                      device=ctx.device)
+    g = ctx.softmax_backward(ds, p, c1, c2, th, beta, dl)
+    torch.cuda.synchronize()
+    return ds, p, loss.cpu().numpy().astype(np.float64), [t.cpu().numpy().astype(np.float64) for t in g]
+
+
+def run_case(ctx, data, pop, beta, dloss=None):
+    _, _, loss, g = gpu_case(ctx, data, pop, beta, dloss)
+    tau = oracle.tau(data.x)
+    check_loss(loss, oracle.smax_forward(data.x, data.y, tau, data.n_classes, pop, beta))
+    dl = np.ones(pop.n_sets) if dloss is None else dloss
+    check_grad(g, oracle.smax_backward(data.x, data.y, tau, data.n_classes, pop, beta, dloss=dl))
+
+
+@pytest.mark.parametrize("nc,beta", [(2, 1.0), (3, 4.0), (4, 0.5), (9, 2.0)])
+def test_mixed_kinds_and_classes(ctx, nc, beta):
+    w = synth.tiny(60 + nc, n=3000, nf=9, n_classes=nc, n_sets=40, rules=(1, 8), conds=(1, 4),
+                   ff_frac=0.4)
+    run_case(ctx, w.data, w.pop, beta, dloss=np.linspace(0.5, 1.5, 40))
+
+
+@pytest.mark.parametrize("rules,conds,nf", [((17, 32), (1, 3), 12), ((40, 64), (1, 2), 8),
+                                            ((1, 3), (58, 66), 40), ((1, 8), (1, 3), 300)])
+def test_long_rule_sets_long_rules_wide_tables(ctx, rules, conds, nf):
+    w = synth.tiny(80 + rules[0] + conds[0], n=1200, nf=nf, n_classes=3, n_sets=10, rules=rules,
+                   conds=conds, ff_frac=0.3)
+    run_case(ctx, w.data, w.pop, 2.0)
+
+
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 257])
+def test_ragged_sample_counts(ctx, n):
+    w = synth.tiny(300 + n, n=n, nf=6, n_sets=10, rules=(1, 5), conds=(1, 3))
+    run_case(ctx, w.data, w.pop, 1.5)
+
+
+def test_probabilities_for_request_rows(ctx):
+    import torch
+    w = synth.tiny(71, n=2000, nf=10, n_classes=4, n_sets=6, rules=(1, 6), conds=(1, 3),
+                   ff_frac=0.3)
+    ds = ctx.upload_dataset(w.data)
+    p = ctx.pack_population(w.pop, 10, 4)
+    c1, c2, th = _params(w.pop, ctx.device)
+    rows = synth.lognormal_features(np.random.default_rng(5), 700, 10)
+    tau = oracle.tau(w.data.x)
+    for s in range(w.pop.n_sets):
+        got = ctx.softmax_proba(ds, p, s, c1, c2, th, 3.0, rows)
+        torch.cuda.synchronize()
+        got = got.cpu().numpy().astype(np.float64)
+        ref = oracle.smax_probs(rows, tau, 4, w.pop, s, 3.0)
+        assert np.all(np.abs(got - ref) <= 1e-5 * ref + 1e-7), np.abs(got - ref).max()
+        np.testing.assert_allclose(got.sum(axis=1), 1.0, rtol=3e-6)
+
+
+def test_finite_differences_64x8(ctx):
+    w = synth.tiny(72, n=64, nf=8, n_classes=3, n_sets=6, rules=(1, 5), conds=(1, 3), ff_frac=0.3)
+    x, y, pop = w.data.x, w.data.y, w.pop
+    _, _, _, g = gpu_case(ctx, w.data, pop, 2.0)
+    tau = oracle.tau(x)
+    base = [pop.coef.astype(np.float64), pop.coef2.astype(np.float64), pop.theta.astype(np.float64)]
+    meanabs = np.abs(x.astype(np.float64)).mean(axis=0)
+    fd = [np.zeros(pop.n_conds) for _ in range(3)]
+    for j in range(pop.n_conds):
+        f = pop.f[j]
+        for k in ([0, 1] if pop.kind[j] else [0, 2]):
+            h = 1e-6 * float(tau[f]) / (meanabs[pop.g[j] if k == 1 else f] if k < 2 else 1.0)
+            plus = [b.copy() for b in base]
+            minus = [b.copy() for b in base]
+            plus[k][j] += h
+            minus[k][j] -= h
+            fd[k][j] = (oracle.smax_forward(x, y, tau, 3, pop, 2.0, *plus).sum()
+                        - oracle.smax_forward(x, y, tau, 3, pop, 2.0, *minus).sum()) / (2 * h)
+    check_grad(g, fd)
+
+
+def test_rule_order_and_beta_zero(ctx):
+    w = synth.tiny(73, n=1500, nf=7, n_classes=3, n_sets=12, rules=(2, 6), conds=(1, 3))
+    rng = np.random.default_rng(1)
+    sets = []
+    for s in range(w.pop.n_sets):
+        d, rules = w.pop.to_rule_list(s)
+        sets.append((d, [rules[i] for i in rng.permutation(len(rules))]))
+    _, _, a, _ = gpu_case(ctx, w.data, w.pop, 2.0)
+    _, _, b, _ = gpu_case(ctx, w.data, from_rule_lists(sets), 2.0)
+    np.testing.assert_allclose(a, b, rtol=1e-5)
+    _, _, l0, g0 = gpu_case(ctx, w.data, w.pop, 0.0)
+    np.testing.assert_allclose(l0, np.log(3.0), rtol=1e-6)
+    assert all(np.all(x == 0.0) for x in g0)
+
+
+def test_full_size_sampled_sets(ctx):
+    """262,144 x 32, 1024 rule sets x 16 rules x 4 conditions; 64 sampled
+    rule sets recomputed by the oracle."""
+    w = synth.soft_workload(3)
+    _, _, loss, g = gpu_case(ctx, w.data, w.pop, 2.0)
+    sample = np.random.default_rng(2).choice(w.pop.n_sets, 64, replace=False)
+    sub = w.pop.subset(sample)
+    tau = oracle.tau(w.data.x)
+    check_loss(loss[sample], oracle.smax_forward(w.data.x, w.data.y, tau, 2, sub, 2.0))
+    idx = np.concatenate([np.arange(w.pop.rule_cond_off[w.pop.set_rule_off[s]],
+                                    w.pop.rule_cond_off[w.pop.set_rule_off[s + 1]]) for s in sample])
+    check_grad([x[idx] for x in g], oracle.smax_backward(w.data.x, w.data.y, tau, 2, sub, 2.0))
+
+
+def test_deterministic_and_autograd(ctx):
+    import torch
+    from paper_2406_01821_amd.aerl import SoftmaxLoss
+    w = synth.soft_workload(8, n=4096, nf=8, n_sets=16, n_rules=6, n_conds=3)
+    ds = ctx.upload_dataset(w.data)
+    p = ctx.pack_population(w.pop, 8, 2)
+    c1, c2, th = [t.requires_grad_() for t in _params(w.pop, ctx.device)]
+    loss = SoftmaxLoss.apply(c1, c2, th, ctx, ds, p, 1.5)
+    wts = torch.linspace(0.1, 1.0, 16, device=ctx.device)
+    (loss * wts).sum().backward()
+    tau = oracle.tau(w.data.x)
+    dl = wts.cpu().numpy().astype(np.float64)
+    check_grad([t.grad.cpu().numpy().astype(np.float64) for t in (c1, c2, th)],
+               oracle.smax_backward(w.data.x, w.data.y, tau, 2, w.pop, 1.5, dloss=dl))
+    l0 = ctx.softmax_forward(ds, p, c1.detach(), c2.detach(), th.detach(), 1.5)
+    g0 = ctx.softmax_backward(ds, p, c1.detach(), c2.detach(), th.detach(), 1.5, wts)
+    for _ in range(2):
+        assert torch.equal(ctx.softmax_forward(ds, p, c1.detach(), c2.detach(), th.detach(), 1.5), l0)
+        g = ctx.softmax_backward(ds, p, c1.detach(), c2.detach(), th.detach(), 1.5, wts)
+        assert all(torch.equal(a, b) for a, b in zip(g, g0))
+
+
+def test_refusals(ctx):
+    from paper_2406_01821_amd.aerl import AerlError, AERL_EINVAL
+    w = synth.tiny(74, n=300, nf=5, n_classes=17, n_sets=3)
+    ds = ctx.upload_dataset(w.data)
+    p = ctx.pack_population(w.pop, 5, 17)
+    c1, c2, th = _params(w.pop, ctx.device)
+    with pytest.raises(AerlError) as e:
+        ctx.softmax_forward(ds, p, c1, c2, th, 1.0)
+    assert e.value.status == AERL_EINVAL
+    w = synth.tiny(75, n=300, nf=5, n_sets=3)
+    ds = ctx.upload_dataset(w.data)
+    p = ctx.pack_population(w.pop, 5, 2)
+    c1, c2, th = _params(w.pop, ctx.device)
+    for beta in (-1.0, float("inf")):
+        with pytest.raises(AerlError) as e:
+            ctx.softmax_forward(ds, p, c1, c2, th, beta)
+        assert e.value.status == AERL_EINVAL

@@ -93,7 +93,7 @@ def _cond(**kw):
 
 
 @pytest.mark.parametrize("bad", [
-    dict(op=4), dict(kind=2), dict(f=5), dict(f=-1), dict(kind=1, g=0), dict(kind=1, g=7),
+    dict(op=4), dict(kind=3), dict(f=5), dict(f=-1), dict(kind=1, g=0), dict(kind=1, g=7),
     dict(coef=np.float32(np.nan)), dict(coef=np.float32(np.inf)), dict(theta=np.float32(np.nan)),
     dict(kind=1, g=1, coef2=np.float32(np.inf))])
 def test_population_validation_rejects(aerl, bad):
@@ -145,7 +145,7 @@ def decode_packed(img, n_sets, n_rules, n_conds, heads=False):
     return sets, hc, hd, raw[:, 1] >> 16
 
 
-FF, GE_LE, LAST, MUL, ALWAYS = 1 << 9, 1 << 10, 1 << 11, 1 << 0, 1 << 1
+FF, GE_LE, LAST, MUL, ALWAYS, CAT = 1 << 9, 1 << 10, 1 << 11, 1 << 0, 1 << 1, 1 << 3
 
 
 def record_mask(x, r):
@@ -153,6 +153,13 @@ def record_mask(x, r):
     arithmetic: x[f] >= y, x[f] <= y, y*x[f] > z, always, y*x[f] > z*x[g] or
     y*x[f] >= z*x[g]."""
     f1024, a, b, w = r
+    if not w & FF and w & CAT:  # x[f] a code k in 0..63 with bit k of {a, b} set
+        v = x[:, f1024 // 1024].astype(np.float64)
+        with np.errstate(invalid="ignore"):
+            ok = (v >= 0) & (v <= 63) & (v == np.floor(v))
+        code = np.where(ok, v, 0).astype(np.uint64)
+        mask = np.uint64(a) | (np.uint64(b) << np.uint64(32))
+        return ok & (((mask >> code) & np.uint64(1)) == 1)
     a = np.uint32(a).view(np.float32)
     b = np.uint32(b).view(np.float32)
     xf = x[:, f1024 // 1024]
@@ -227,6 +234,27 @@ def test_packed_rewrite_is_exact_against_oracle(aerl):
     xx = np.concatenate([x, w.data.x[:, :4]])
     for s in range(pop.n_sets):
         np.testing.assert_array_equal(eval_packed(xx, S, H, s), oracle.predict(xx, pop, s),
+                                      err_msg=str(s))
+
+
+def test_categorical_records_are_exact_against_oracle(aerl):
+    """Categorical conditions pack into records whose code-set test, walked
+    on the host, matches the oracle on every special value of a code
+    column (and the soft condition words flag them with their masks)."""
+    rng = np.random.default_rng(9)
+    special = np.array([0.0, -0.0, 1.0, 2.5, -1.0, 31.0, 32.0, 63.0, 64.0, 1e9, np.inf, -np.inf,
+                        np.nan, 5.0], np.float32)
+    x = np.concatenate([rng.uniform(-3, 3, size=(300, 3)).astype(np.float32),
+                        rng.choice(special, size=(300, 2)).astype(np.float32)], axis=1)
+    pop = synth.categorical_population(rng, x, 2, 64, 60, (1, 6), (1, 4), 3, cat_frac=0.5)
+    extra = [(0, [(1, [dict(kind=2, f=3, mask=m)])]) for m in
+             (0, 1, 1 << 31, 1 << 32, 1 << 63, (1 << 64) - 1, 0x5555_5555_5555_5555)]
+    pop = from_rule_lists([pop.to_rule_list(s) for s in range(pop.n_sets)] + extra)
+    assert (pop.kind == 2).sum() > 50
+    img = aerl.pack_host(pop, 5, 3)
+    S, H = decode_packed(img, pop.n_sets, pop.n_rules, pop.n_conds)
+    for s in range(pop.n_sets):
+        np.testing.assert_array_equal(eval_packed(x, S, H, s), oracle.predict(x, pop, s),
                                       err_msg=str(s))
 
 
@@ -427,7 +455,9 @@ def test_hard_kernels_fit_two_blocks_per_cu(tmp_path):
             if m and name:
                 counts[name] = int(m.group(1))
     hard = {k: v for k, v in counts.items() if "k_hardILi" in k or "k_hard_batch" in k}
-    assert len(hard) == 4, counts  # k_hard<4>, <2>, <1>, k_hard_batch
+    # k_hard<4>, <2>, <1> and k_hard_batch, each with and without the
+    # categorical walk
+    assert len(hard) == 8, counts
     assert all(v <= 80 for v in hard.values()), hard
 
 
