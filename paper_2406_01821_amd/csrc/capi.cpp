@@ -90,7 +90,7 @@ struct Pinned {
 void hard_config(const DatasetRec &ds, int32_t n_sets, int n_cu, int *S, int *Q, int *TG) {
   const int64_t tiles = std::max<int64_t>(ds.n_tiles, 1);
   const int64_t target = 4LL * n_cu;
-  int q = (int)std::min<int64_t>(std::max<int32_t>(n_sets, 1), 2048);
+  int q = (int)std::min<int64_t>(std::max<int32_t>(n_sets, 1), kHardChunkMax);
   // Two blocks per CU (eight waves per SIMD) hide the latency of the scalar
   // record loads and LDS reads far better than one: take the most samples per
   // lane whose tile leaves room for two blocks with a chunk of at least 64
@@ -108,17 +108,25 @@ void hard_config(const DatasetRec &ds, int32_t n_sets, int n_cu, int *S, int *Q,
     budget = kDynLdsMax;
   }
   *S = s;
-  while (q > 1 && hard_block_lds(ds.nf, s, q, ds.nc) > budget) q = (q + 1) / 2;
-  while (q > 64 && ((n_sets + q - 1) / q) * tiles < target) q = (q + 1) / 2;
-  // equal chunks (a short last chunk leaves its blocks underused)
-  const int chunks = (std::max<int32_t>(n_sets, 1) + q - 1) / q;
-  *Q = (std::max<int32_t>(n_sets, 1) + chunks - 1) / chunks;
-  // Single-tile groups (measured fastest: larger groups leave a partly
-  // filled last round of blocks), unless the grid would exceed the launch
-  // limit; then the fewest tiles per group that fit it.
-  int tg = 1;
-  while (tg < kMaxTilesPerBlock && hard_block_count(ds, *Q, n_sets, tg) > kMaxHardBlocks) ++tg;
-  *TG = tg;
+  // Chunk size and tiles per group, planned first for single-tile groups
+  // (10-bit counters) and again with 16-bit counters when the launch limit
+  // forces larger groups.
+  const int q_top = q;
+  for (bool c10 = true;; c10 = false) {
+    q = q_top;
+    while (q > 1 && hard_block_lds(ds.nf, s, q, ds.nc, c10) > budget) q = (q + 1) / 2;
+    while (q > 64 && ((n_sets + q - 1) / q) * tiles < target) q = (q + 1) / 2;
+    // equal chunks (a short last chunk leaves its blocks underused)
+    const int chunks = (std::max<int32_t>(n_sets, 1) + q - 1) / q;
+    *Q = (std::max<int32_t>(n_sets, 1) + chunks - 1) / chunks;
+    // Single-tile groups (measured fastest: larger groups leave a partly
+    // filled last round of blocks), unless the grid would exceed the launch
+    // limit; then the fewest tiles per group that fit it.
+    int tg = 1;
+    while (tg < kMaxTilesPerBlock && hard_block_count(ds, *Q, n_sets, tg) > kMaxHardBlocks) ++tg;
+    *TG = tg;
+    if (!c10 || hard_c10(tg)) break;
+  }
 }
 
 }  // namespace
@@ -420,7 +428,7 @@ static aerl_status eval_common(aerl_ctx *ctx, int32_t dataset_id, int32_t pop_id
   } else {
     if (S != 1 && S != 2 && S != 4) return fail(ctx, AERL_EINVAL, "samples_per_lane %d not in {1,2,4}", S);
     if (Q < 1 || TG < 1) return fail(ctx, AERL_EINVAL, "sets_per_chunk and tiles_per_group must be >= 1");
-    if (hard_block_lds(ds.nf, S, Q, ds.nc) > kDynLdsMax)
+    if (hard_block_lds(ds.nf, S, Q, ds.nc, hard_c10(TG)) > kDynLdsMax)
       return fail(ctx, AERL_EINVAL, "configuration needs more LDS than a workgroup can have");
     if (TG > kMaxTilesPerBlock)
       return fail(ctx, AERL_EINVAL, "tiles_per_group %d above %d", TG, kMaxTilesPerBlock);

@@ -42,7 +42,8 @@ struct HardArgs {
 
 // CAT: the population has categorical conditions (their walk body is left
 // out of the other instantiation, which keeps the common walk's code tight).
-template <int S, bool CAT>
+// C10: single-tile groups (10-bit LDS counters).
+template <int S, bool CAT, bool C10>
 __global__ __launch_bounds__(kHardBlock) AERL_HARD_SGPR_CAP void k_hard(const HardArgs a) {
   extern __shared__ __align__(16) float smem[];
   __shared__ int32_t sh[2];
@@ -79,7 +80,7 @@ __global__ __launch_bounds__(kHardBlock) AERL_HARD_SGPR_CAP void k_hard(const Ha
   }
   t.q0 = chunk * a.sets_per_chunk;
   t.Q = min(a.sets_per_chunk, a.set_count - t.q0);
-  hard_block<S, CAT>(t, smem, sh);
+  hard_block<S, CAT, C10>(t, smem, sh);
 }
 
 // Prediction for one rule set over row-major rows: one wave per 64*S rows.
@@ -93,11 +94,16 @@ __global__ __launch_bounds__(64) void k_predict(const float *__restrict__ rows, 
 }
 
 template <int S>
-hipError_t hard_dispatch(const HardArgs &a, dim3 grid, size_t lds, bool cat, hipStream_t st) {
-  if (cat)
-    hipLaunchKernelGGL((k_hard<S, true>), grid, dim3(kHardBlock), lds, st, a);
+hipError_t hard_dispatch(const HardArgs &a, dim3 grid, size_t lds, bool cat, bool c10,
+                         hipStream_t st) {
+  if (cat && c10)
+    hipLaunchKernelGGL((k_hard<S, true, true>), grid, dim3(kHardBlock), lds, st, a);
+  else if (cat)
+    hipLaunchKernelGGL((k_hard<S, true, false>), grid, dim3(kHardBlock), lds, st, a);
+  else if (c10)
+    hipLaunchKernelGGL((k_hard<S, false, true>), grid, dim3(kHardBlock), lds, st, a);
   else
-    hipLaunchKernelGGL((k_hard<S, false>), grid, dim3(kHardBlock), lds, st, a);
+    hipLaunchKernelGGL((k_hard<S, false, false>), grid, dim3(kHardBlock), lds, st, a);
   return hipGetLastError();
 }
 
@@ -131,14 +137,15 @@ hipError_t launch_hard_eval(const HardLaunch &h, hipStream_t st) {
   const int64_t n_groups = hard_group_count(ds, h.tiles_per_group);
   if (n_groups == 0) return hipSuccess;
   const int64_t n_chunks = (h.set_count + h.sets_per_chunk - 1) / h.sets_per_chunk;
-  const size_t lds = hard_block_lds(ds.nf, h.samples_per_lane, h.sets_per_chunk, ds.nc);
+  const bool c10 = hard_c10(h.tiles_per_group);
+  const size_t lds = hard_block_lds(ds.nf, h.samples_per_lane, h.sets_per_chunk, ds.nc, c10);
   if (lds > kDynLdsMax || n_chunks * n_groups > kMaxHardBlocks) return hipErrorInvalidValue;
   a.n_chunks = (int32_t)n_chunks;
   const dim3 grid((unsigned)(n_chunks * n_groups));
   switch (h.samples_per_lane) {
-    case 4: return hard_dispatch<4>(a, grid, lds, pop.n_cat > 0, st);
-    case 2: return hard_dispatch<2>(a, grid, lds, pop.n_cat > 0, st);
-    case 1: return hard_dispatch<1>(a, grid, lds, pop.n_cat > 0, st);
+    case 4: return hard_dispatch<4>(a, grid, lds, pop.n_cat > 0, c10, st);
+    case 2: return hard_dispatch<2>(a, grid, lds, pop.n_cat > 0, c10, st);
+    case 1: return hard_dispatch<1>(a, grid, lds, pop.n_cat > 0, c10, st);
     default: return hipErrorInvalidValue;
   }
 }

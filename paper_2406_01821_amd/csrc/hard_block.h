@@ -25,7 +25,7 @@ struct HardTask {
   const int32_t *tile_info;
   const int4 *sets;   // the population's set records
   const uint4 *conds; // the population's record stream
-  const uint4 *heads; // the population's head table (null: walk every rule)
+  const uint4 *heads; // the population's head table
   int32_t *correct;   // [n_sets]
   int32_t *confusion; // [n_sets][nc][nc] or null
   int32_t q0, Q, tile_lo, tile_hi, label;
@@ -39,14 +39,17 @@ struct HardTask {
 // tile's largest x, or x <= t with t below its smallest) cannot fire for any
 // of them: the walk skips it without reading its records (exact).
 // Per-class prediction counts live in LDS (one writer per rule set and
-// tile) and reach the outputs once, through integer atomics; the last
+// wave tile) and reach the outputs once, through integer atomics; the last
 // class's count is what the other classes leave of the block's samples.
-// smem holds nf*64*S floats, then nf (max, -min) pairs, then Q*(nc-1)
-// 16-bit counters (a block covers at most 255 layout tiles, so a counter
-// stays below 2^16).  sh[0] is the rule-set counter, sh[1] the block's real
-// sample count (kept in LDS by one thread, so that it holds no register
-// through the walk).  Ends with a barrier, so the caller may reuse smem.
-template <int S, bool CAT>
+// smem holds nf*64*S floats, then nf (max, -min) pairs, then the counters
+// of the classes but the last, hard_counter_bytes(Q, nc, C10) bytes: with
+// C10 (a block of one layout tile, so a count is at most 256) three 10-bit
+// counters per 32-bit word, else two 16-bit ones (a block covers at most 255
+// layout tiles, so a counter stays below 2^16).  sh[0] is the rule-set
+// counter, sh[1] the block's real sample count (kept in LDS by one thread,
+// so that it holds no register through the walk).  Ends with a barrier, so
+// the caller may reuse smem.
+template <int S, bool CAT, bool C10 = false>
 __device__ __forceinline__ void hard_block(const HardTask &t, float *smem, int32_t *sh) {
   int32_t *next_q = sh;
   constexpr int TS = 64 * S;           // samples per wave tile
@@ -54,10 +57,15 @@ __device__ __forceinline__ void hard_block(const HardTask &t, float *smem, int32
   float *xs = smem;                                                    // [nf][TS]
   float *ext = smem + (size_t)t.nf * TS;                               // [nf][max, -min]
   const int ncc = hard_counters_per_set(t.nc);                        // counted classes
-  uint16_t *cnt = reinterpret_cast<uint16_t *>(ext + 2 * t.nf);        // [Q][ncc]
-  uint32_t *cnt32 = reinterpret_cast<uint32_t *>(cnt);
+  uint32_t *cnt32 = reinterpret_cast<uint32_t *>(ext + 2 * t.nf);
   const int lane = threadIdx.x & 63;
-  for (int i = threadIdx.x; i < t.Q * ncc; i += blockDim.x) cnt[i] = 0;
+  // counter words per rule set, and lane c's word and bit offset in a set's
+  // counters
+  const int wps = C10 ? (ncc + 2) / 3 : (ncc + 1) / 2;
+  const uint32_t lane_word = C10 ? (uint32_t)lane / 3u : 0u;
+  const uint32_t lane_bit = C10 ? (uint32_t)lane % 3u * 10u : 0u;
+  for (int i = threadIdx.x; i < (int)(hard_counter_bytes(t.Q, t.nc, C10) / 4); i += blockDim.x)
+    cnt32[i] = 0u;
   if (threadIdx.x == 0) sh[1] = 0;
   const int n4 = t.nf * (TS / 4);
   const float4 *src = reinterpret_cast<const float4 *>(t.x_fm);
@@ -115,16 +123,16 @@ __device__ __forceinline__ void hard_block(const HardTask &t, float *smem, int32
       // both set records in one scalar load (at the chunk's odd end the
       // second is the record after it, inside the population image and
       // never used), and both sets' head entries requested before the
-      // first walk
+      // first walk; a lane past a set's last entry reads that entry again
+      // (its value is never used), so the loads need no lane mask
       int4 set[2];
       ldc_pair(t.sets + t.q0 + q0, set);
       uint4 head[2];
 #pragma unroll
       for (int k = 0; k < 2; ++k) {
         const int nh = set[k].y >> 16;
-        head[k] = make_uint4(0u, 0u, 0u, 0u);
-        if (q0 + k < q1 && t.heads && nh >= 1 && nh <= kMaxHeads && lane < nh)
-          head[k] = t.heads[set[k].x + lane];
+        if (q0 + k < q1 && nh >= 1 && nh <= kMaxHeads)
+          head[k] = t.heads[set[k].x + min(lane, nh - 1)];
       }
 #pragma unroll
       for (int k = 0; k < 2; ++k) {
@@ -133,26 +141,31 @@ __device__ __forceinline__ void hard_block(const HardTask &t, float *smem, int32
         const int4 s4 = set[k];
         const int nh = s4.y >> 16;
         int acc;
-        if (t.heads && nh >= 1 && nh <= kMaxHeads) {
+        if (nh >= 1 && nh <= kMaxHeads) {
           // lane j: rule j; table[e] < t' when no sample of the tile passes
           const uint4 h = head[k];
           const char *tb = reinterpret_cast<const char *>(ext);
           const float e1 = *reinterpret_cast<const float *>(tb + (h.x >> kHeadExtShift));
           const float e2 = *reinterpret_cast<const float *>(tb + h.z);
-          // (bitwise, so that both table reads are unconditional)
-          const uint32_t keep = (uint32_t)(lane < nh) & (uint32_t)!(e1 < __uint_as_float(h.y)) &
-                                (uint32_t)!(e2 < __uint_as_float(h.w));
-          // the closing record (last entry) is always visited
-          const uint64_t mk = ballot(keep != 0u) | (1ull << (nh - 1));
+          // rules 0..nh-1, less those a test rules out; the closing record
+          // (last entry) is always visited
+          const uint64_t rules = ~0ull >> (64 - nh);
+          const uint64_t mk = (ballot(!(e1 < __uint_as_float(h.y))) &
+                               ballot(!(e2 < __uint_as_float(h.w))) & rules) |
+                              (1ull << (nh - 1));
           acc = eval_set_count<S, true, CAT>(lds_lane, lane, s4, t.conds, vm, mk, h.x & kHeadOffMask);
         } else {
           acc = eval_set_count<S, false, CAT>(lds_lane, lane, s4, t.conds, vm);
         }
-        // two 16-bit counters per word: a no-return atomic add, no carry
-        // between the halves (each counter stays below 2^16)
+        // lane c < ncc adds class c's count: a no-return atomic add with no
+        // carry between the fields of a word (each count fits its field)
         if (lane < ncc) {
-          const int i = q * ncc + lane;
-          atomicAdd(cnt32 + (i >> 1), (uint32_t)acc << ((i & 1) * 16));
+          if (C10) {
+            atomicAdd(cnt32 + (uint32_t)(q * wps) + lane_word, (uint32_t)acc << lane_bit);
+          } else {
+            const int i = q * ncc + lane;
+            atomicAdd(cnt32 + (i >> 1), (uint32_t)acc << ((i & 1) * 16));
+          }
         }
       }
     }
@@ -164,7 +177,15 @@ __device__ __forceinline__ void hard_block(const HardTask &t, float *smem, int32
     const int64_t p = t.q0 + q;
     int rest = n_block;
     for (int c = 0; c < t.nc; ++c) {
-      const int v = c < ncc ? (int)cnt[q * ncc + c] : rest;
+      int v = rest;
+      if (c < ncc) {
+        if (C10) {
+          v = (int)(cnt32[q * wps + c / 3] >> (c % 3 * 10)) & 1023;
+        } else {
+          const int i = q * ncc + c;
+          v = (int)(cnt32[i >> 1] >> ((i & 1) * 16)) & 0xffff;
+        }
+      }
       rest -= v;
       if (v == 0) continue;
       if (t.confusion) atomicAdd(&t.confusion[(p * t.nc + t.label) * t.nc + c], v);

@@ -94,7 +94,9 @@ constexpr int32_t kMaxSetRecords = 1023;
 // any other record gives e = 0, t' = -inf.  With a tile's per-feature table
 // {max x[f], -min x[f]} at byte offsets 8f and 8f + 4, table[e] < t' holds
 // exactly when no sample of the tile passes the record, and then no sample
-// of the tile can fire the rule.
+// of the tile can fire the rule.  (Tests of the third and fourth records
+// skip about a third more record visits on the 2^20 x 64 workload, but the
+// second 16-byte load per rule costs more than they save there.)
 constexpr uint32_t kHeadOffMask = 0x3fffu;
 constexpr uint32_t kHeadExtShift = 14;
 // Sets with at most this many head entries take the filtered walk.
@@ -235,16 +237,26 @@ constexpr size_t kStaticLds = 64;
 constexpr size_t kDynLdsMax = kLdsPerCu - kStaticLds;
 
 // Dynamic LDS of a hard-eval block: the feature tile (nf x 64*S floats),
-// the tile's per-feature extremes and one 16-bit prediction counter per
-// (rule set, class) for every class but the last (a set predicts the last
-// class for the block's samples the other counters leave).  A block adds at
-// most 256 samples per layout tile to a counter, so it covers at most
-// kMaxTilesPerBlock layout tiles.
+// the tile's per-feature extremes and one prediction counter per (rule set,
+// class) for every class but the last (a set predicts the last class for the
+// block's samples the other counters leave): 16-bit counters, two per word,
+// or, when the block covers one layout tile (a count is then at most 256),
+// 10-bit counters, three per word.  A block adds at most 256 samples per
+// layout tile to a counter, so it covers at most kMaxTilesPerBlock layout
+// tiles.
 constexpr int kMaxTilesPerBlock = 255;
+// Most rule sets per block of the plain hard-eval path.
+constexpr int kHardChunkMax = 2048;
 __host__ __device__ inline int hard_counters_per_set(int nc) { return nc > 1 ? nc - 1 : 0; }
-inline size_t hard_block_lds(int nf, int S, int Q, int nc) {
-  return (size_t)nf * 64 * S * 4 + (size_t)nf * 8 +
-         (((size_t)Q * hard_counters_per_set(nc) * 2 + 3) & ~size_t(3));
+__host__ __device__ inline size_t hard_counter_bytes(int Q, int nc, bool c10) {
+  const int ncc = hard_counters_per_set(nc);
+  return (size_t)Q * 4 * (c10 ? (ncc + 2) / 3 : 0) +
+         (c10 ? 0 : (((size_t)Q * ncc * 2 + 3) & ~size_t(3)));
+}
+// Blocks of one layout tile count in 10-bit fields.
+inline bool hard_c10(int tiles_per_group) { return tiles_per_group == 1; }
+inline size_t hard_block_lds(int nf, int S, int Q, int nc, bool c10 = false) {
+  return (size_t)nf * 64 * S * 4 + (size_t)nf * 8 + hard_counter_bytes(Q, nc, c10);
 }
 
 // Soft path (soft.hip)

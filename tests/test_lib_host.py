@@ -455,9 +455,9 @@ def test_hard_kernels_fit_two_blocks_per_cu(tmp_path):
             if m and name:
                 counts[name] = int(m.group(1))
     hard = {k: v for k, v in counts.items() if "k_hardILi" in k or "k_hard_batch" in k}
-    # k_hard<4>, <2>, <1> and k_hard_batch, each with and without the
-    # categorical walk
-    assert len(hard) == 8, counts
+    # k_hard<4>, <2>, <1> (each with 10- and 16-bit counters) and
+    # k_hard_batch, each with and without the categorical walk
+    assert len(hard) == 14, counts
     assert all(v <= 80 for v in hard.values()), hard
 
 
@@ -529,8 +529,8 @@ def test_head_table_describes_every_rule(aerl):
             assert int(hd[first + k][0]) & 0x3fff == o
             for i, (e, t) in enumerate(head_tests(hd[first + k])):
                 r = [int(v) for v in hc[first + o // 16 + i]]
-                same_rule = i == 0 or not int(hc[first + o // 16][3]) & LAST
-                threshold = same_rule and not r[3] & (FF | MUL | ALWAYS)
+                same_rule = all(not int(hc[first + o // 16 + j][3]) & LAST for j in range(i))
+                threshold = same_rule and not r[3] & (FF | MUL | ALWAYS | CAT)
                 if not threshold:
                     assert (e, t) == (0, NO_TEST), (s, k, i)
                     continue
@@ -538,6 +538,8 @@ def test_head_table_describes_every_rule(aerl):
                 assert e == 8 * (r[0] // 1024) + (4 if le else 0), (s, k, i)
                 y = np.uint32(r[1]).view(np.float32)
                 assert t == int((-y if le else y).view(np.uint32)), (s, k, i)
+
+
 @pytest.mark.parametrize("seed", range(3))
 def test_head_filter_skips_only_rules_that_cannot_fire(aerl, seed):
     """The filtered walk on tiles of 1-256 rows gives the oracle's
