@@ -137,13 +137,29 @@ def cpu_oracle_detail(w, budget_s=2.0):
             "usable_cpus": usable}
 
 
-# Algorithmic VALU work of the soft path, in lane issue slots (transcendentals
-# count twice: v_exp_f32 / v_log_f32 issue at half rate on gfx950).
-TRANS = 2
-SOFT_FWD_COND = 6 + 2 * TRANS      # z, log sigmoid(z), accumulate
-SOFT_FWD_RULE = 10 + 3 * TRANS     # log(1-r), survival, class log-sum-exp
-SOFT_BWD_COND = 10 + 3 * TRANS     # sigmoid(-z), dL/dz, parameter terms
-SOFT_BWD_RULE = 3 * TRANS          # suffix recurrence
+# Algorithmic VALU work of the soft path, in lane issue slots of a plain fp32
+# operation; a transcendental (v_exp_f32 / v_log_f32) counts as many slots as
+# the issue-rate probe measures on the device (multiply rate / transcendental
+# rate), once per bench run.
+_TRANS = {}
+
+
+def trans_weight(ctx):
+    if "w" not in _TRANS:
+        mul, trans = ctx.probe_valu_rates()
+        _TRANS.update(w=mul / trans, mul_lane_ops_per_s=mul, trans_lane_ops_per_s=trans)
+        log(f"VALU probe: multiply {mul / 1e12:.2f} T, transcendental {trans / 1e12:.2f} T "
+            f"lane-op/s (weight {mul / trans:.2f})")
+    return _TRANS["w"]
+
+
+def soft_slots(t):
+    """Per-condition and per-rule lane slots of the first-firing soft head,
+    for a transcendental weight t: forward condition (z, log sigmoid(z),
+    accumulate), forward rule (log(1-r), survival, class log-sum-exp),
+    backward condition (sigmoid(-z), dL/dz, parameter terms) and backward
+    rule (suffix recurrence)."""
+    return 6 + 2 * t, 10 + 3 * t, 10 + 3 * t, 3 * t
 
 
 def timed(fn, steps, warmup, stream):
@@ -364,11 +380,13 @@ def bench_softmax(ctx, steps, warmup, beta=2.0):
     conds = int(w.pop.nominal_conds_per_set().sum()) * n
     rules = w.pop.n_rules * n
     nc = 2
+    t = trans_weight(ctx)
+    fc, _, bc, _ = soft_slots(t)
     # per rule: the first-firing rule cost minus its class log-sum-exp, plus
     # one exponential and nc selects for the vote
-    rule_fwd = 10 + 3 * TRANS + nc
-    fwd_slots = float(SOFT_FWD_COND * conds + rule_fwd * rules)
-    bwd_slots = fwd_slots + float(SOFT_BWD_COND * conds + (1 * TRANS + 2 * nc + 4) * rules)
+    rule_fwd = 10 + 3 * t + nc
+    fwd_slots = float(fc * conds + rule_fwd * rules)
+    bwd_slots = fwd_slots + float(bc * conds + (1 * t + 2 * nc + 4) * rules)
     ctx.release_population(pop)
     ctx.release_dataset(ds)
     log(f"softmax head: forward {fwd_ms:.3f} ms, backward {bwd_ms:.3f} ms")
@@ -426,11 +444,13 @@ def bench_soft(ctx, steps, warmup, cpu):
     n = w.data.n
     conds = int(w.pop.nominal_conds_per_set().sum()) * n
     rules = w.pop.n_rules * n
-    fwd_slots = float(SOFT_FWD_COND * conds + SOFT_FWD_RULE * rules)
-    bwd_slots = fwd_slots + float(SOFT_BWD_COND * conds + SOFT_BWD_RULE * rules)
+    fc, fr, bc, br = soft_slots(trans_weight(ctx))
+    fwd_slots = float(fc * conds + fr * rules)
+    bwd_slots = fwd_slots + float(bc * conds + br * rules)
     out = {
         "workload": "soft, 262,144 x 32 fp32 samples, 2 classes, 1024 rule sets x 16 rules x 4 "
                     "threshold conditions, tau = 0.05 std",
+        "transcendental_weight": dict(_TRANS),
         "forward": {"ms": fwd_ms, "cond_evals_per_s": conds / (fwd_ms * 1e-3),
                     "roofline": {"bound": "alu", "achieved": fwd_slots / (fwd_ms * 1e-3) / 1e12,
                                  "peak": VALU_PEAK / 1e12, "unit": "Tlane-op/s",
@@ -643,6 +663,77 @@ def bench_serve(ctx, small, ds_small, big, ds_big, n_requests=2000, rate_hz=2000
     }
 
 
+def trace_summary(path, first=None, last=None):
+    """Per-kernel statistics and cross-stream overlap of a rocprofv3 kernel
+    trace (its *_kernel_trace.csv), over the dispatches from the first one
+    whose name starts with `first` through the last one whose name starts
+    with `last` (the whole trace by default).  Overlap: the time during which
+    kernels of two or more streams (hardware queues) run at once, and the
+    dispatches that share some of their run time with a dispatch of another
+    stream."""
+    import csv
+    with open(path) as fh:
+        rows = list(csv.DictReader(fh))
+    key = "Stream_Id" if rows and "Stream_Id" in rows[0] else "Queue_Id"
+    ev = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"], r[key])
+                for r in rows)
+    if first:
+        i0 = next(i for i, e in enumerate(ev) if e[2].startswith(first))
+        ev = ev[i0:]
+    if last:
+        i1 = max(i for i, e in enumerate(ev) if e[2].startswith(last))
+        ev = ev[:i1 + 1]
+    stats = {}
+    for t0, t1, name, _ in ev:
+        st = stats.setdefault(name.split("(")[0][:60], [0, 0.0, float("inf"), 0.0])
+        d = (t1 - t0) * 1e-3
+        st[0] += 1
+        st[1] += d
+        st[2] = min(st[2], d)
+        st[3] = max(st[3], d)
+    # sweep line over (time, +1/-1, stream)
+    pts = sorted([(t0, 1, q) for t0, _, _, q in ev] + [(t1, -1, q) for _, t1, _, q in ev])
+    live, busy, multi, prev = {}, 0, 0, None
+    for t, d, q in pts:
+        if prev is not None and live:
+            busy += t - prev
+            if sum(1 for v in live.values() if v > 0) >= 2:
+                multi += t - prev
+        live[q] = live.get(q, 0) + d
+        if live[q] == 0:
+            del live[q]
+        prev = t
+    # dispatches overlapping one of another stream (sorted by start)
+    overl = [False] * len(ev)
+    active = []
+    for i, (t0, t1, _, q) in enumerate(ev):
+        active = [j for j in active if ev[j][1] > t0]
+        for j in active:
+            if ev[j][3] != q:
+                overl[i] = overl[j] = True
+        active.append(i)
+    span = (max(e[1] for e in ev) - ev[0][0]) * 1e-6 if ev else 0.0
+    out = {"dispatches": len(ev), "streams": len({e[3] for e in ev}), "span_ms": span,
+           "busy_ms": busy * 1e-6, "multi_stream_ms": multi * 1e-6,
+           "dispatches_overlapping_another_stream": int(sum(overl)),
+           "kernels": {k: {"calls": v[0], "avg_us": v[1] / v[0], "min_us": v[2], "max_us": v[3],
+                           "total_ms": v[1] * 1e-3} for k, v in
+                       sorted(stats.items(), key=lambda kv: -kv[1][1])}}
+    return out
+
+
+def bench_serve_alone(ctx):
+    """The serving section on its own (both datasets uploaded here)."""
+    from paper_2406_01821_amd import synth
+    small = synth.small_hard(0).data
+    big = synth.scaled_hard(1).data
+    ds_small, ds_big = ctx.upload_dataset(small), ctx.upload_dataset(big)
+    out = bench_serve(ctx, small, ds_small, big, ds_big)
+    ctx.release_dataset(ds_small)
+    ctx.release_dataset(ds_big)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -650,10 +741,18 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--only-hard", action="store_true", help="time the hard path only")
-    ap.add_argument("--only", default=None, help="one extra section alone: c1, finetune, soft")
+    ap.add_argument("--only", default=None, help="one extra section alone: c1, finetune, evolve, softmax, categorical, soft, serve")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run only a plain 256 MiB device copy (calibrates HBM byte counters)")
+    ap.add_argument("--trace-summary", default=None, metavar="CSV",
+                    help="summarize a rocprofv3 kernel trace (per kernel, cross-stream overlap)")
+    ap.add_argument("--trace-from", default=None, help="with --trace-summary: first kernel name")
+    ap.add_argument("--trace-to", default=None, help="with --trace-summary: last kernel name")
     args = ap.parse_args()
+    if args.trace_summary:
+        print(json.dumps(trace_summary(args.trace_summary, args.trace_from, args.trace_to),
+                         indent=1))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(rule sets or samples would be split across GPUs)", file=sys.stderr)
@@ -681,7 +780,8 @@ def main():
               "evolve": lambda: bench_evolve(ctx, not args.no_cpu),
               "softmax": lambda: bench_softmax(ctx, max(3, args.steps // 4), 1),
               "categorical": lambda: bench_categorical(ctx, args.steps, args.warmup),
-              "soft": lambda: bench_soft(ctx, max(3, args.steps // 4), 1, not args.no_cpu)}
+              "soft": lambda: bench_soft(ctx, max(3, args.steps // 4), 1, not args.no_cpu),
+              "serve": lambda: bench_serve_alone(ctx)}
         print(json.dumps({args.only: fn[args.only]()}), flush=True)
         ctx.close()
         return

@@ -661,6 +661,19 @@ aerl_status aerl_evolve_load(aerl_ctx *ctx, int32_t dataset_id, const char *path
                              size_t arena_bytes, int32_t *evo_id);
 aerl_status aerl_evolve_release(aerl_ctx *ctx, int32_t evo_id);
 
+/* ---------------------------------------------------------- measurement */
+
+/* Issue rates of the VALU instruction classes a roofline of the soft path
+ * weights (Section 4.3 measures cost against the amount of rule and
+ * condition work; this prices that work on the device).  Runs, on `stream`,
+ * a kernel of fp32 multiply chains and one of chains alternating v_exp_f32
+ * and v_log_f32, each filling every SIMD, and writes out[0] = multiply
+ * lane-ops per second, out[1] = transcendental lane-ops per second (their
+ * ratio is the issue cost of a transcendental in multiply slots).  Blocks
+ * until both kernels finish; allocates about 4 MiB of device memory for the
+ * call.  Errors: AERL_EINVAL (null argument), AERL_EDEVICE. */
+aerl_status aerl_probe_valu_rates(aerl_ctx *ctx, double *out, hipStream_t stream);
+
 /* aerl_soft_forward for callers that cannot allocate device memory (code
  * under HIP graph capture, tight serving loops, harnesses that forbid
  * allocation): the same kernels and the same results, bit for bit, with the

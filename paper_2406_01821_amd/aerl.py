@@ -166,6 +166,7 @@ _SIGS = {
     "aerl_soft_forward": ([_P, _I32, _I32, _P, _P, _P, _P, _P, _SZ, _P], _I32),
     "aerl_soft_backward": ([_P, _I32, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _SZ, _P], _I32),
     "aerl_soft_forward_noalloc": ([_P, _I32, _I32, _P, _P, _P, _P, _P], _I32),
+    "aerl_probe_valu_rates": ([_P, _P, _P], _I32),
     "aerl_softmax_forward": ([_P, _I32, _I32, _P, _P, _P, C.c_float, _P, _P, _SZ, _P], _I32),
     "aerl_softmax_backward": ([_P, _I32, _I32, _P, _P, _P, C.c_float, _P, _P, _P, _P, _P, _SZ, _P],
                               _I32),
@@ -626,6 +627,12 @@ class Context:
         self.check(aerl_soft_forward_noalloc(self.h, ds.id, pop.id, _ptr(coef), _ptr(coef2),
                                              _ptr(theta), _ptr(loss), _stream(stream)))
         return loss
+
+    def probe_valu_rates(self, stream=None):
+        """(multiply, transcendental) VALU lane-ops per second, measured."""
+        out = (C.c_double * 2)()
+        self.check(aerl_probe_valu_rates(self.h, out, _stream(stream)))
+        return float(out[0]), float(out[1])
 
     def soft_backward(self, ds, pop, coef, coef2, theta, dloss, ws=None, stream=None):
         ws = ws if ws is not None else self.soft_workspace(ds, pop, True)

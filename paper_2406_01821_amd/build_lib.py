@@ -21,7 +21,7 @@ BUILD = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 SOURCES = ["capi.cpp", "pack.cpp", "layout.hip", "hard.hip", "soft.hip", "ragged.hip", "batch.cpp",
-           "serve.cpp", "tune.hip", "evolve.cpp"]
+           "serve.cpp", "tune.hip", "evolve.cpp", "probe.hip"]
 FLAGS = [f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17", "-ffp-contract=off",
          "-fno-fast-math", "-fno-gpu-flush-denormals-to-zero",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -217,3 +217,13 @@ def test_full_size_sampled_sets(ctx):
     idx = np.concatenate([np.arange(w.pop.rule_cond_off[w.pop.set_rule_off[s]],
                                     w.pop.rule_cond_off[w.pop.set_rule_off[s + 1]]) for s in sample])
     check_grad([g[idx] for g in grads], rg)
+
+
+def test_valu_issue_rate_probe(ctx):
+    """The probe that prices a transcendental in the soft roofline: the fp32
+    multiply rate lies near 256 CUs x 64 lanes x 2.4 GHz, and a
+    transcendental costs at least one multiply slot."""
+    mul, trans = ctx.probe_valu_rates()
+    peak = 256 * 64 * 2.4e9
+    assert 0.5 * peak < mul < 1.1 * peak
+    assert 0.0 < trans <= 1.02 * mul
