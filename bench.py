@@ -675,8 +675,13 @@ def trace_summary(path, first=None, last=None):
     with open(path) as fh:
         rows = list(csv.DictReader(fh))
     key = "Stream_Id" if rows and "Stream_Id" in rows[0] else "Queue_Id"
-    ev = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"], r[key])
-                for r in rows)
+
+    def short(name):  # the kernel's name without namespaces or arguments
+        name = name.replace("void ", "").replace("(anonymous namespace)::", "")
+        return name.split("(")[0].replace("aerl::", "")[:60]
+
+    ev = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), short(r["Kernel_Name"]),
+                 r[key]) for r in rows)
     if first:
         i0 = next(i for i, e in enumerate(ev) if e[2].startswith(first))
         ev = ev[i0:]
@@ -685,7 +690,7 @@ def trace_summary(path, first=None, last=None):
         ev = ev[:i1 + 1]
     stats = {}
     for t0, t1, name, _ in ev:
-        st = stats.setdefault(name.split("(")[0][:60], [0, 0.0, float("inf"), 0.0])
+        st = stats.setdefault(name, [0, 0.0, float("inf"), 0.0])
         d = (t1 - t0) * 1e-3
         st[0] += 1
         st[1] += d

@@ -194,6 +194,11 @@ aerl_status aerl_create(aerl_ctx **out, int device_ordinal) {
 void aerl_destroy(aerl_ctx *ctx) {
   if (!ctx) return;
   serve_shutdown(ctx);
+  if (ctx->hard_part_done) {
+    (void)hipEventSynchronize(ctx->hard_part_done);
+    (void)hipEventDestroy(ctx->hard_part_done);
+  }
+  if (ctx->hard_part) (void)hipFree(ctx->hard_part);
   for (auto &kv : ctx->pops) {
     if (kv.second.staged) {
       (void)hipEventSynchronize(kv.second.staged);
@@ -401,6 +406,34 @@ aerl_status aerl_release_population(aerl_ctx *ctx, int32_t pop_id) {
   return AERL_OK;
 }
 
+// The context's per-tile counter buffer, at least `bytes` long, for a call
+// on `stream`: the stream first waits for the last call that used it (calls
+// that use it run one after another, across streams).  Grows it (after that
+// call ends) when too small; *out stays null when the allocation fails, and
+// the caller then counts with atomics instead.
+static aerl_status hard_part_buffer(aerl_ctx *ctx, size_t bytes, hipStream_t stream,
+                                    uint32_t **out) {
+  *out = nullptr;
+  if (!ctx->hard_part_done)
+    AERL_HIP(ctx, hipEventCreateWithFlags(&ctx->hard_part_done, hipEventDisableTiming));
+  if (ctx->hard_part_bytes < bytes) {
+    AERL_HIP(ctx, hipEventSynchronize(ctx->hard_part_done));
+    if (ctx->hard_part) AERL_HIP(ctx, hipFree(ctx->hard_part));
+    ctx->hard_part = nullptr;
+    ctx->hard_part_bytes = 0;
+    if (hipMalloc(&ctx->hard_part, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      ctx->hard_part = nullptr;
+      return AERL_OK;
+    }
+    ctx->hard_part_bytes = bytes;
+  } else {
+    AERL_HIP(ctx, hipStreamWaitEvent(stream, ctx->hard_part_done, 0));
+  }
+  *out = static_cast<uint32_t *>(ctx->hard_part);
+  return AERL_OK;
+}
+
 static aerl_status eval_common(aerl_ctx *ctx, int32_t dataset_id, int32_t pop_id, int32_t *correct,
                                int32_t *confusion, int S, int Q, int TG, hipStream_t stream) {
   if (!ctx) return AERL_EINVAL;
@@ -441,9 +474,23 @@ static aerl_status eval_common(aerl_ctx *ctx, int32_t dataset_id, int32_t pop_id
                 (long long)hard_block_count(ds, h.sets_per_chunk, pop.n_sets, h.tiles_per_group),
                 (long long)kMaxHardBlocks);
   AERL_HIP(ctx, hipSetDevice(ctx->device));
+  // Single-tile groups with two to four classes store per-tile counter words
+  // that a second kernel sums (far fewer output atomics than a flush per
+  // block), in the context's buffer when it can hold them.
+  if (hard_c10(h.tiles_per_group) && ds.nc >= 2 && ds.nc <= 4) {
+    const size_t need = (size_t)ds.n_tiles * (size_t)pop.n_sets * 4;
+    if (need > 0 && need <= kHardPartMaxBytes) {
+      aerl_status st = hard_part_buffer(ctx, need, stream, &h.part);
+      if (st) return st;
+    }
+  }
   AERL_HIP(ctx, launch_fill_i32(correct, pop.n_sets, 0, stream));
   if (confusion) AERL_HIP(ctx, launch_fill_i32(confusion, (int64_t)pop.n_sets * ds.nc * ds.nc, 0, stream));
   AERL_HIP(ctx, launch_hard_eval(h, stream));
+  if (h.part) {
+    AERL_HIP(ctx, launch_hard_reduce(h, ctx->n_cu, stream));
+    AERL_HIP(ctx, hipEventRecord(ctx->hard_part_done, stream));
+  }
   return AERL_OK;
 }
 

@@ -35,6 +35,7 @@ struct HardArgs {
   int32_t set_begin, set_count;
   int32_t *correct;
   int32_t *confusion;
+  uint32_t *part;
   int32_t sets_per_chunk, tiles_per_group, n_chunks;
   int32_t region_tile0[AERL_MAX_CLASSES];
   int32_t region_tiles[AERL_MAX_CLASSES];
@@ -59,6 +60,8 @@ __global__ __launch_bounds__(kHardBlock) AERL_HARD_SGPR_CAP void k_hard(const Ha
   t.heads = a.heads;
   t.correct = a.correct;
   t.confusion = a.confusion;
+  t.part = a.part;
+  t.part_stride = a.set_count;
   t.label = 0;
   t.tile_lo = t.tile_hi = 0;
   // one-dimensional grid, set chunk fastest: consecutive blocks share a tile
@@ -81,6 +84,46 @@ __global__ __launch_bounds__(kHardBlock) AERL_HARD_SGPR_CAP void k_hard(const Ha
   t.q0 = chunk * a.sets_per_chunk;
   t.Q = min(a.sets_per_chunk, a.set_count - t.q0);
   hard_block<S, CAT, C10>(t, smem, sh);
+}
+
+// Sums the per-tile counter words of a hard-eval launch over the tiles of
+// each class region.  part[tile][p] holds, in 10-bit fields, rule set p's
+// counts of classes 0..nc-2 among the tile's real samples; class nc-1 gets
+// the rest of them.  Thread p of block (x, y) takes rule set 256x + p over
+// the tiles of slice y (consecutive threads read consecutive words of a
+// tile's row) and adds each class region's totals to the outputs.
+constexpr int kReduceBlock = 256;
+__global__ __launch_bounds__(kReduceBlock) void k_hard_reduce(
+    const uint32_t *__restrict__ part, const int32_t *__restrict__ tile_info, int64_t n_tiles,
+    int32_t n_sets, int32_t nc, int32_t *__restrict__ correct, int32_t *__restrict__ confusion) {
+  const int p = blockIdx.x * kReduceBlock + threadIdx.x;
+  if (p >= n_sets) return;
+  const int64_t t0 = n_tiles * blockIdx.y / gridDim.y, t1 = n_tiles * (blockIdx.y + 1) / gridDim.y;
+  int label = -1;
+  int32_t c0 = 0, c1 = 0, c2 = 0, n = 0;
+  auto emit = [&]() {
+    if (label < 0) return;
+    for (int c = 0; c < nc; ++c) {
+      const int32_t v = c == nc - 1 ? n - c0 - c1 - c2 : c == 0 ? c0 : c == 1 ? c1 : c2;
+      if (v == 0) continue;
+      if (confusion) atomicAdd(&confusion[((int64_t)p * nc + label) * nc + c], v);
+      if (c == label) atomicAdd(&correct[p], v);
+    }
+  };
+  for (int64_t t = t0; t < t1; ++t) {
+    const int info = ldc(tile_info, t);
+    if ((info & 0xff) != label) {
+      emit();
+      label = info & 0xff;
+      c0 = c1 = c2 = n = 0;
+    }
+    const uint32_t w = part[t * n_sets + p];
+    c0 += (int32_t)(w & 1023u);
+    c1 += (int32_t)(w >> 10 & 1023u);
+    c2 += (int32_t)(w >> 20 & 1023u);
+    n += info >> 8;
+  }
+  emit();
 }
 
 // Prediction for one rule set over row-major rows: one wave per 64*S rows.
@@ -126,6 +169,9 @@ hipError_t launch_hard_eval(const HardLaunch &h, hipStream_t st) {
   a.set_count = h.set_count;
   a.correct = h.correct;
   a.confusion = h.confusion;
+  a.part = h.part;
+  if (h.part && !(hard_c10(h.tiles_per_group) && ds.nc >= 2 && ds.nc <= 4))
+    return hipErrorInvalidValue;
   a.sets_per_chunk = h.sets_per_chunk;
   a.tiles_per_group = h.tiles_per_group;
   for (int c = 0; c < ds.nc; ++c) {
@@ -148,6 +194,17 @@ hipError_t launch_hard_eval(const HardLaunch &h, hipStream_t st) {
     case 1: return hard_dispatch<1>(a, grid, lds, pop.n_cat > 0, c10, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_hard_reduce(const HardLaunch &h, int n_cu, hipStream_t st) {
+  const DatasetRec &ds = *h.ds;
+  if (h.set_count <= 0 || ds.n_tiles == 0) return hipSuccess;
+  if (!h.part || ds.nc < 2 || ds.nc > 4) return hipErrorInvalidValue;
+  const int64_t bx = (h.set_count + kReduceBlock - 1) / kReduceBlock;
+  const int64_t by = std::max<int64_t>(1, std::min<int64_t>(ds.n_tiles, (2LL * n_cu + bx - 1) / bx));
+  hipLaunchKernelGGL(k_hard_reduce, dim3((unsigned)bx, (unsigned)by), dim3(kReduceBlock), 0, st,
+                     h.part, ds.tile_info, ds.n_tiles, h.set_count, ds.nc, h.correct, h.confusion);
+  return hipGetLastError();
 }
 
 hipError_t launch_predict(const PopRec &pop, int32_t set, const float *rows, int64_t n,

@@ -28,6 +28,8 @@ struct HardTask {
   const uint4 *heads; // the population's head table
   int32_t *correct;   // [n_sets]
   int32_t *confusion; // [n_sets][nc][nc] or null
+  uint32_t *part;     // per-tile counter words [tiles][part_stride], or null
+  int32_t part_stride;
   int32_t q0, Q, tile_lo, tile_hi, label;
 };
 
@@ -45,10 +47,12 @@ struct HardTask {
 // of the classes but the last, hard_counter_bytes(Q, nc, C10) bytes: with
 // C10 (a block of one layout tile, so a count is at most 256) three 10-bit
 // counters per 32-bit word, else two 16-bit ones (a block covers at most 255
-// layout tiles, so a counter stays below 2^16).  sh[0] is the rule-set
-// counter, sh[1] the block's real sample count (kept in LDS by one thread,
-// so that it holds no register through the walk).  Ends with a barrier, so
-// the caller may reuse smem.
+// layout tiles, so a counter stays below 2^16).  With C10, at most four
+// classes (one word per rule set) and t.part set, the block stores its
+// counter words to t.part's row of its tile instead, for a second kernel to
+// sum.  sh[0] is the rule-set counter, sh[1] the block's real sample count
+// (kept in LDS by one thread, so that it holds no register through the
+// walk).  Ends with a barrier, so the caller may reuse smem.
 template <int S, bool CAT, bool C10 = false>
 __device__ __forceinline__ void hard_block(const HardTask &t, float *smem, int32_t *sh) {
   int32_t *next_q = sh;
@@ -171,6 +175,12 @@ __device__ __forceinline__ void hard_block(const HardTask &t, float *smem, int32
     }
   }
   __syncthreads();
+  if (C10 && t.part != nullptr) {
+    uint32_t *dst = t.part + (int64_t)t.tile_lo * t.part_stride + t.q0;
+    for (int q = threadIdx.x; q < t.Q; q += blockDim.x) dst[q] = cnt32[q];
+    __syncthreads();
+    return;
+  }
   // the block's real samples (every set predicts one class for each)
   const int n_block = sh[1];
   for (int q = threadIdx.x; q < t.Q; q += blockDim.x) {

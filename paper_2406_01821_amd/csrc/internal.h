@@ -179,6 +179,11 @@ struct aerl_ctx {
   bool tune_file_loaded = false;
   aerl::Serve *serve = nullptr;
   void *noalloc_scratch = nullptr;  // this device's copy of the no-allocation scratch array
+  // per-tile counter words of the plain hard path (grown on demand), and the
+  // end of the last call that used them
+  void *hard_part = nullptr;
+  size_t hard_part_bytes = 0;
+  hipEvent_t hard_part_done = nullptr;
 };
 
 namespace aerl {
@@ -196,8 +201,19 @@ struct HardLaunch {
   int samples_per_lane;          // 1, 2 or 4
   int sets_per_chunk;
   int tiles_per_group;           // layout tiles per block
+  // Per-tile counter words [n_tiles][set_count], or null.  With single-tile
+  // groups and two to four classes the blocks store their counter words
+  // here (one 32-bit word per rule set: classes 0..nc-2 in 10-bit fields)
+  // and launch_hard_reduce sums them into the outputs; otherwise every
+  // block adds its counts to the outputs with atomics.
+  uint32_t *part = nullptr;
 };
 hipError_t launch_hard_eval(const HardLaunch &h, hipStream_t s);
+// Sums h.part over the tiles of each class region into h.correct and
+// h.confusion (which must be zeroed), about two workgroups per CU.
+hipError_t launch_hard_reduce(const HardLaunch &h, int n_cu, hipStream_t s);
+// Largest per-tile counter buffer a context keeps.
+constexpr size_t kHardPartMaxBytes = (size_t)512 << 20;
 // Workgroups of a hard-eval launch: one per (set chunk, tile group), in a
 // one-dimensional grid of 1024-thread blocks whose work-item count must fit
 // 32 bits.

@@ -50,6 +50,8 @@ __global__ __launch_bounds__(kBatchBlock) AERL_HARD_SGPR_CAP void k_hard_batch(
     t.heads = it.heads;
     t.correct = it.correct;
     t.confusion = it.confusion;
+    t.part = nullptr;
+    t.part_stride = 0;
     t.q0 = tk.q0;
     t.Q = tk.Q;
     t.tile_lo = tk.tile_lo;
