@@ -28,21 +28,23 @@ HBM_PEAK = 8.0e12                     # bytes/s
 
 
 # HBM bytes per launch of the hard-eval kernel on the 2^20 x 64, 4096-set
-# workload, from two rocprofv3 --pmc runs (FETCH_SIZE 529,767 KiB and
-# WRITE_SIZE 589,513 KiB per dispatch, scaled by what the counters read for a
-# plain 256 MiB copy: x2.000 and x1.000).  Valid only for the kernel,
-# launch-configuration and record-layout sources it was measured on.
-HARD_TRAFFIC = {"bytes": 1.6885e9, "sources_sha256": "351d6213bee10713"}
+# workload, from two rocprofv3 --pmc runs (FETCH_SIZE 271,703.5 KiB and
+# WRITE_SIZE 65,568.0 KiB per dispatch, scaled by what the counters read for a
+# plain 256 MiB copy: x1.99978 and x1.000), and the same for the kernel that
+# sums its per-tile counts (FETCH_SIZE 32,957.1 KiB, WRITE_SIZE 10,039.3 KiB).
+# Valid only for the kernel, launch-configuration and record-layout sources
+# it was measured on.
+HARD_TRAFFIC = {"bytes": 6.2353e8, "reduce_bytes": 7.7769e7, "sources_sha256": "e6c8684645f1f9d7"}
 HARD_SOURCES = ("hard.hip", "hard_block.h", "eval_core.h", "capi.cpp", "pack.cpp", "internal.h")
 
 
-def hard_traffic():
+def hard_traffic(key="bytes"):
     import hashlib
     h = hashlib.sha256()
     for f in HARD_SOURCES:
         with open(os.path.join(ROOT, "paper_2406_01821_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
-    return HARD_TRAFFIC["bytes"] if h.hexdigest()[:16] == HARD_TRAFFIC["sources_sha256"] else None
+    return HARD_TRAFFIC[key] if h.hexdigest()[:16] == HARD_TRAFFIC["sources_sha256"] else None
 
 
 def log(msg):
@@ -814,6 +816,7 @@ def main():
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
                 "unit": "Tlane-op/s", "frac": achieved / VALU_PEAK, "traffic": hard_traffic(),
                 "kernel": "k_hard", "algorithmic_lane_ops": lane_ops,
+                "traffic_reduce_kernel": hard_traffic("reduce_bytes"),
                 "hbm_bytes_min": float(w.data.n * (w.data.n_features + 1) * 4)}
     result = {
         "metric": "rule-condition evals/s (hard fitness, nominal)",
