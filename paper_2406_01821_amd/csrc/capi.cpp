@@ -474,12 +474,13 @@ static aerl_status eval_common(aerl_ctx *ctx, int32_t dataset_id, int32_t pop_id
                 (long long)hard_block_count(ds, h.sets_per_chunk, pop.n_sets, h.tiles_per_group),
                 (long long)kMaxHardBlocks);
   AERL_HIP(ctx, hipSetDevice(ctx->device));
-  // Single-tile groups with two to four classes store per-tile counter words
-  // that a second kernel sums (far fewer output atomics than a flush per
-  // block), in the context's buffer when it can hold them.
+  // Large launches of single-tile groups with two to four classes store
+  // per-tile counter words that a second kernel sums (far fewer output
+  // atomics than a flush per block), in the context's buffer when it can
+  // hold them; small ones keep the flush (no second launch).
   if (hard_c10(h.tiles_per_group) && ds.nc >= 2 && ds.nc <= 4) {
     const size_t need = (size_t)ds.n_tiles * (size_t)pop.n_sets * 4;
-    if (need > 0 && need <= kHardPartMaxBytes) {
+    if (need >= kHardPartMinBytes && need <= kHardPartMaxBytes) {
       aerl_status st = hard_part_buffer(ctx, need, stream, &h.part);
       if (st) return st;
     }

@@ -212,7 +212,10 @@ hipError_t launch_hard_eval(const HardLaunch &h, hipStream_t s);
 // Sums h.part over the tiles of each class region into h.correct and
 // h.confusion (which must be zeroed), about two workgroups per CU.
 hipError_t launch_hard_reduce(const HardLaunch &h, int n_cu, hipStream_t s);
-// Largest per-tile counter buffer a context keeps.
+// Per-tile counter buffers the plain hard path uses: at least 16 MiB of
+// counter words (smaller launches flush per block, without a second
+// kernel), at most 512 MiB (larger ones flush per block too).
+constexpr size_t kHardPartMinBytes = (size_t)16 << 20;
 constexpr size_t kHardPartMaxBytes = (size_t)512 << 20;
 // Workgroups of a hard-eval launch: one per (set chunk, tile group), in a
 // one-dimensional grid of 1024-thread blocks whose work-item count must fit
