@@ -1282,6 +1282,169 @@ __global__ __launch_bounds__(kSmaxBwdWaves * 64) void k_smax_bwd(const SoftArgs 
   }
 }
 
+// Adjoint of the softmax head for rule sets of at most 16 rules and at most
+// four classes, four samples per lane, 16 waves per block: the per-rule
+// state between the two sweeps (log2 r_k and the prefix sum of
+// log2(1 - r_i) before k, for each of the lane's samples) is a 16 x 4 x 2
+// array per lane, read and written through a uniform branch chain on k (the
+// compiler keeps it in per-lane private memory at the 64-VGPR budget of
+// two blocks per CU).  Per condition the four slots are summed in the lane,
+// then over the wave; the walk's totals go to LDS as in the first-firing
+// adjoint.  Same formulas as k_smax_bwd.
+constexpr int kSmaxRegRules = 16;
+
+template <int NC, class Acc, bool TONLY>
+__global__ __launch_bounds__(kBwdRegBlock, 8) AERL_BWD_SGPR_CAP void k_smax_bwd_reg(
+    const SoftArgs a, float beta, float beta2) {
+  constexpr int S = 4, RMAX = kSmaxRegRules, TS = 64 * S, WPT = AERL_TILE / TS;
+  extern __shared__ __align__(16) float smem[];
+  float *xs = smem;                       // [nf][TS]
+  float *acc = xs + (size_t)a.nf * TS;    // [Q][max_set_conds][2]
+  __shared__ int32_t next_q;
+  const int lane = threadIdx.x & 63;
+  int label, tile_lo, tile_hi;
+  group_range(a, blockIdx.y, label, tile_lo, tile_hi);
+  const int q0 = blockIdx.x * a.sets_per_chunk;
+  const int Q = min(a.sets_per_chunk, a.n_sets - q0);
+  for (int i = threadIdx.x; i < Q * a.max_set_conds * 2; i += blockDim.x) acc[i] = 0.0f;
+  const int n4 = a.nf * (TS / 4);
+  const float4 *src = reinterpret_cast<const float4 *>(a.x_fm);
+  float4 *dst = reinterpret_cast<float4 *>(xs);
+  const int64_t row4 = a.n_pad / 4;
+  for (int64_t wt = (int64_t)tile_lo * WPT; wt < (int64_t)tile_hi * WPT; ++wt) {
+    __syncthreads();
+    const int64_t base4 = wt * (TS / 4);
+    for (int i = threadIdx.x; i < n4; i += blockDim.x) {
+      const int f = i / (TS / 4), k = i % (TS / 4);
+      dst[i] = src[(int64_t)f * row4 + base4 + k];
+    }
+    if (threadIdx.x == 0) next_q = 0;
+    __syncthreads();
+    const int info = ldc(a.tile_info, wt / WPT);
+    const int valid = min(max((info >> 8) - (int)(wt % WPT) * TS, 0), TS);
+    for (;;) {
+      const int q = next_item(&next_q);
+      if (q >= Q) break;
+      const int4 ss = ldc(a.ssets, q0 + q);
+      const int dflt = ldc(a.sets, q0 + q).z;
+      float LA[RMAX][S], LP[RMAX][S];
+      float v[S][NC], surv[S];
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        surv[s] = 0.0f;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) v[s][c] = 0.0f;
+      }
+      // forward sweep: log2 r_k and the prefix of log2(1 - r_i) before k
+      for (int k = 0; k < ss.y; ++k) {
+        const int4 r = ldc(a.rules, ss.x + k);
+        Acc ra[S];
+        for (int j = r.x; j < r.x + r.y; ++j) {
+          float z[S];
+          cond_z_only<S>(a, xs, lane, j, z);
+#pragma unroll
+          for (int s = 0; s < S; ++s) (void)ra[s].add(z[s]);
+        }
+        float a2s[S], pre[S];
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          float a2, b2;
+          acc_finish(ra[s], a2, b2);
+          a2s[s] = a2;
+          pre[s] = surv[s];
+          add_vote(v[s], r.z, fexp2(a2));
+          surv[s] += b2;
+        }
+        l_set<0, RMAX, S>(LA, k, a2s);
+        l_set<0, RMAX, S>(LP, k, pre);
+      }
+      // dL/dv per slot (clamped samples and padding get none); for the
+      // label, -beta times the other classes' probabilities
+      float gv[S][NC], gd[S], tail[S];
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        add_vote(v[s], dflt, fexp2(surv[s]));
+        float p[NC];
+        const float l2 = smax_log2py(v[s], a.nc, beta2, label, p);
+        const bool on = lane * S + s < valid && -l2 * kLn2 <= kLossCap;
+        float others = 0.0f;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) others += c == label ? 0.0f : p[c];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) gv[s][c] = on ? beta * (c == label ? -others : p[c]) : 0.0f;
+        gd[s] = pick(gv[s], dflt);
+        tail[s] = 0.0f;
+      }
+      // reverse sweep with the suffix of log2(1 - r_i) after k
+      const bool few = ss.w <= 64;
+      int tot0 = 0, tot1 = 0;
+      for (int k = ss.y - 1; k >= 0; --k) {
+        const int4 r = ldc(a.rules, ss.x + k);
+        float la[S], lp[S], drk[S];
+        l_get<0, RMAX, S>(LA, k, la);
+        l_get<0, RMAX, S>(LP, k, lp);
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          const float oth = lp[s] + tail[s];  // log2 prod_{i != k} (1 - r_i)
+          drk[s] = r.z == dflt ? gd[s] * one_minus_exp2(oth)
+                               : pick(gv[s], r.z) - gd[s] * fexp2(oth);
+        }
+        Acc ra[S];
+        for (int j = r.x; j < r.x + r.y; ++j) {
+          float z[S], xf[S], xg[S];
+          if constexpr (TONLY) {
+            cond_z_t<S>(a, xs, lane, j, z, xf, xg);
+          } else {
+            bool ff;
+            cond_z<S>(a, xs, lane, j, z, xf, xg, ff);
+          }
+          float g0 = 0.0f, g1 = 0.0f;
+#pragma unroll
+          for (int s = 0; s < S; ++s) {
+            const float t = ra[s].add(z[s]);
+            // dL/dz = dL/dr_k * r_k * sigmoid(-z)
+            const float dz = drk[s] * acc_sig_neg(ra[s], la[s], z[s], t);
+            g0 = fmaf(dz, xg[s], g0);
+            g1 = fmaf(dz, xf[s], g1);
+          }
+          g0 = wave_total_last(g0);
+          g1 = wave_total_last(g1);
+          if (few) {
+            const int v0 = __builtin_amdgcn_readlane(__float_as_int(g0), 63);
+            const int v1 = __builtin_amdgcn_readlane(__float_as_int(g1), 63);
+            const bool mine = lane == j - ss.z;
+            tot0 = mine ? v0 : tot0;
+            tot1 = mine ? v1 : tot1;
+          } else if (lane == 63) {
+            // one writer per (rule set, tile): the order of these adds is fixed
+            float *ap = acc + ((size_t)q * a.max_set_conds + (j - ss.z)) * 2;
+            ap[0] += g0;
+            ap[1] += g1;
+          }
+        }
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          float a2, b2;
+          acc_finish(ra[s], a2, b2);
+          tail[s] += b2;
+        }
+      }
+      if (few && lane < ss.w) {
+        float *ap = acc + ((size_t)q * a.max_set_conds + lane) * 2;
+        ap[0] += __int_as_float(tot0);
+        ap[1] += __int_as_float(tot1);
+      }
+    }
+  }
+  __syncthreads();
+  for (int q = 0; q < Q; ++q) {
+    const int4 ss = ldc(a.ssets, q0 + q);
+    for (int i = threadIdx.x; i < ss.w * 2; i += blockDim.x)
+      a.part_grad[((int64_t)blockIdx.y * a.n_conds + ss.z) * 2 + i] =
+          acc[(size_t)q * a.max_set_conds * 2 + i];
+  }
+}
+
 // Class probabilities of one rule set for row-major rows, one row per
 // thread (the gathered condition records give z).
 template <int NC>
@@ -1336,6 +1499,18 @@ SoftPlan plan_smax_backward(const DatasetRec &ds, const PopRec &pop) {
   p.TG = 1;
   while (count_groups(ds, p.TG) > kMaxGroups) p.TG *= 2;
   p.n_groups = (int)count_groups(ds, p.TG);
+  // up to 16 rules and four classes on at most 64 features: four samples per
+  // lane with the per-rule state in per-lane memory, two blocks per CU
+  if (R <= kSmaxRegRules && smax_nc(ds.nc) <= 4 && (size_t)ds.nf * 256 * 4 <= 64 * 1024) {
+    p.rmax = kSmaxRegRules;
+    p.S = 4;
+    const size_t xs = (size_t)ds.nf * 64 * p.S * 4;
+    p.Q = std::max(1, std::min(pop.n_sets, 64));
+    while (p.Q > 1 && xs + p.Q * per_set > kLdsPerCu / 2 - kStaticLds) p.Q >>= 1;
+    p.lds = xs + (size_t)p.Q * per_set;
+    if (p.lds <= kDynLdsMax) return p;
+  }
+  p.rmax = 0;
   p.S = 1;
   lds_state_plan(p, (size_t)ds.nf * 64 * 4, per_set, (size_t)R * 128 * 4, kSmaxBwdWaves, 16,
                  pop.n_sets);
@@ -1365,6 +1540,20 @@ void launch_smax_fwd_nc(const SoftPlan &p, dim3 grid, hipStream_t st, const Soft
 template <int NC>
 void launch_smax_bwd_nc(const SoftPlan &p, dim3 grid, hipStream_t st, const SoftArgs &a, bool prod,
                         bool tonly, float beta, float beta2) {
+  if constexpr (NC <= 4) {
+    if (p.rmax == kSmaxRegRules) {
+      const dim3 rb(kBwdRegBlock);
+      if (prod && tonly)
+        hipLaunchKernelGGL((k_smax_bwd_reg<NC, RuleProd, true>), grid, rb, p.lds, st, a, beta, beta2);
+      else if (prod)
+        hipLaunchKernelGGL((k_smax_bwd_reg<NC, RuleProd, false>), grid, rb, p.lds, st, a, beta, beta2);
+      else if (tonly)
+        hipLaunchKernelGGL((k_smax_bwd_reg<NC, RuleAcc, true>), grid, rb, p.lds, st, a, beta, beta2);
+      else
+        hipLaunchKernelGGL((k_smax_bwd_reg<NC, RuleAcc, false>), grid, rb, p.lds, st, a, beta, beta2);
+      return;
+    }
+  }
   const dim3 b(p.waves * 64);
   if (prod && tonly)
     hipLaunchKernelGGL((k_smax_bwd<NC, RuleProd, true>), grid, b, p.lds, st, a, beta, beta2);

@@ -78,6 +78,16 @@ def test_mixed_kinds_and_classes(ctx, nc, beta):
     run_case(ctx, w.data, w.pop, beta, dloss=np.linspace(0.5, 1.5, 40))
 
 
+@pytest.mark.parametrize("rules,conds", [((9, 16), (1, 4)), ((12, 16), (5, 8))])
+def test_up_to_sixteen_rules_four_classes(ctx, rules, conds):
+    """The adjoint that keeps per-rule state per lane (at most 16 rules, four
+    classes): sets up to its rule bound, and sets of more than 64 conditions
+    (their totals added per condition instead of once per walk)."""
+    w = synth.tiny(90 + rules[0], n=2500, nf=10, n_classes=4, n_sets=24, rules=rules,
+                   conds=conds, ff_frac=0.4)
+    run_case(ctx, w.data, w.pop, 1.5, dloss=np.linspace(0.25, 2.0, 24))
+
+
 @pytest.mark.parametrize("rules,conds,nf", [((17, 32), (1, 3), 12), ((40, 64), (1, 2), 8),
                                             ((1, 3), (58, 66), 40), ((1, 8), (1, 3), 300)])
 def test_long_rule_sets_long_rules_wide_tables(ctx, rules, conds, nf):
