@@ -389,8 +389,15 @@ struct aerl_serve_stats {
 
 /* Start the loop on ctx's device.  arena: caller-allocated device memory
  * (256-byte aligned) whose size is the admission budget; it must outlive
- * aerl_serve_stop.  cfg may be NULL.  Errors: AERL_ESTATE (already
- * running), AERL_EINVAL, AERL_EDEVICE. */
+ * aerl_serve_stop.  cfg may be NULL.  When the environment variable
+ * AERL_TRACE names a file at start, the loop appends one JSON line per
+ * completed request: ticket, kind, dataset, sets, rows, batch, slot,
+ * status, submit_us (from start), the host spans pack_us (validation and
+ * packing), queue_us, launch_us (launch to completion seen), copy_out_us
+ * (outputs to the caller's buffers), total_us, and its launch's device spans
+ * h2d_us, kernels_us, d2h_us (-1 when the launch failed).  Errors:
+ * AERL_ESTATE (already running), AERL_EINVAL (bad arena or configuration,
+ * a trace file that cannot be opened), AERL_EDEVICE. */
 aerl_status aerl_serve_start(aerl_ctx *ctx, void *arena, size_t arena_bytes,
                              const aerl_serve_cfg *cfg);
 

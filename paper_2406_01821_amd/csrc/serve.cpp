@@ -15,12 +15,15 @@
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
 #include <thread>
 
 #include "batch.h"
+#include "serve_sched.h"
 
 namespace aerl {
 
@@ -37,54 +40,6 @@ size_t al(size_t v) { return (v + 255) & ~size_t(255); }
 double us_between(Clock::time_point a, Clock::time_point b) {
   return std::chrono::duration<double, std::micro>(b - a).count();
 }
-
-// First-fit allocator of 256-byte-aligned ranges of the arena.
-class ArenaAlloc {
- public:
-  void reset(size_t bytes) {
-    free_.clear();
-    if (bytes) free_[0] = bytes;
-    used_ = 0;
-  }
-  size_t largest() const {
-    size_t m = 0;
-    for (const auto &kv : free_) m = std::max(m, kv.second);
-    return m;
-  }
-  bool alloc(size_t n, size_t *off) {
-    for (auto it = free_.begin(); it != free_.end(); ++it) {
-      if (it->second < n) continue;
-      *off = it->first;
-      const size_t rest = it->second - n, start = it->first + n;
-      free_.erase(it);
-      if (rest) free_[start] = rest;
-      used_ += n;
-      return true;
-    }
-    return false;
-  }
-  void release(size_t off, size_t n) {
-    used_ -= n;
-    auto it = free_.emplace(off, n).first;
-    auto nx = std::next(it);
-    if (nx != free_.end() && it->first + it->second == nx->first) {
-      it->second += nx->second;
-      free_.erase(nx);
-    }
-    if (it != free_.begin()) {
-      auto pv = std::prev(it);
-      if (pv->first + pv->second == it->first) {
-        pv->second += it->second;
-        free_.erase(it);
-      }
-    }
-  }
-  size_t used() const { return used_; }
-
- private:
-  std::map<size_t, size_t> free_;
-  size_t used_ = 0;
-};
 
 struct Req {
   uint64_t ticket = 0;
@@ -103,7 +58,7 @@ struct Req {
   size_t in_bytes = 0, out_bytes = 0, table_bytes = 0;
   size_t in_off = 0, rows_off = 0, out_off = 0;  // inside the launch's range
   double nominal = 0;
-  Clock::time_point t_submit, t_launch, t_done;
+  Clock::time_point t_submit, t_queued, t_launch, t_seen_done, t_done;
   aerl_status status = AERL_OK;
   int32_t batch_size = 0;
   bool done = false;
@@ -116,6 +71,10 @@ struct Req {
 struct Slot {
   hipStream_t stream = nullptr;
   hipEvent_t done = nullptr;
+  // with a trace: timing events before the upload, after it, after the
+  // kernels and after the download
+  hipEvent_t span[4] = {nullptr, nullptr, nullptr, nullptr};
+  int index = 0;
   void *h_in = nullptr, *h_out = nullptr;
   size_t in_cap = 0, out_cap = 0;
   bool busy = false;
@@ -154,6 +113,10 @@ struct Serve {
   ArenaAlloc alloc;
   std::vector<Slot> slots;
 
+  // AERL_TRACE span log (JSON lines, one per completed request), or null
+  FILE *trace = nullptr;
+  Clock::time_point t_start;
+
   // statistics since start or the last reset
   std::vector<double> lat_us;
   int64_t submitted = 0, completed = 0, launches = 0, launched_reqs = 0;
@@ -165,29 +128,20 @@ struct Serve {
   void run();
   bool launch_one(std::unique_lock<std::mutex> &lk, Slot &slot);
   void reap(std::unique_lock<std::mutex> &lk, Slot &slot, hipError_t status);
+  void write_trace(const Slot &slot, const std::vector<Req *> &rs, hipError_t status);
 };
 
 // Takes a FIFO prefix of the pending requests that fits in the largest free
 // arena range, lays it out and enqueues its copies and kernels on the slot.
 bool Serve::launch_one(std::unique_lock<std::mutex> &lk, Slot &slot) {
-  const size_t room = alloc.largest();
-  size_t need = kTableSlack, in = kTableSlack, out = 0;
-  std::vector<Req *> take;
-  // A launch also stays within the slot's pinned staging buffers (growing
-  // them costs a host allocation), unless its first request alone needs more.
-  while (!pending.empty() && (int32_t)take.size() < max_batch &&
-         need + pending.front()->dev_bytes() <= room) {
-    const Req *r = pending.front();
-    if (!take.empty() && (in + r->in_bytes + r->table_bytes > slot.in_cap ||
-                          out + r->out_bytes > slot.out_cap))
-      break;
-    need += r->dev_bytes();
-    in += r->in_bytes + r->table_bytes;
-    out += r->out_bytes;
-    take.push_back(pending.front());
-    pending.pop_front();
-  }
-  if (take.empty()) return false;
+  size_t need = 0;
+  const int32_t n_take = admit_prefix(
+      pending,
+      [](const Req *r) { return QueuedSize{r->dev_bytes(), r->in_bytes + r->table_bytes, r->out_bytes}; },
+      alloc.largest(), max_batch, kTableSlack, slot.in_cap, slot.out_cap, &need);
+  if (n_take == 0) return false;
+  std::vector<Req *> take(pending.begin(), pending.begin() + n_take);
+  pending.erase(pending.begin(), pending.begin() + n_take);
   size_t off = 0;
   alloc.alloc(need, &off);  // cannot fail: need <= the largest free range
   arena_peak = std::max(arena_peak, alloc.used());
@@ -271,13 +225,18 @@ bool Serve::launch_one(std::unique_lock<std::mutex> &lk, Slot &slot) {
     pl.tasks = reinterpret_cast<const PredictTask *>(dev + ptasks_off);
     pl.n_tasks = (int32_t)ptasks.size();
     pl.lds = plds;
-    e = hipMemcpyAsync(dev + out_end, slot.h_in, in_end - out_end, hipMemcpyHostToDevice,
-                       slot.stream);
+    if (trace) e = hipEventRecord(slot.span[0], slot.stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(dev + out_end, slot.h_in, in_end - out_end, hipMemcpyHostToDevice,
+                         slot.stream);
   }
+  if (e == hipSuccess && trace) e = hipEventRecord(slot.span[1], slot.stream);
   if (e == hipSuccess && !src.empty()) e = launch_batch(bl, slot.stream);
   if (e == hipSuccess && pl.n_tasks > 0) e = launch_predict_batch(pl, slot.stream);
+  if (e == hipSuccess && trace) e = hipEventRecord(slot.span[2], slot.stream);
   if (e == hipSuccess && out_end > 0)
     e = hipMemcpyAsync(slot.h_out, dev, out_end, hipMemcpyDeviceToHost, slot.stream);
+  if (e == hipSuccess && trace) e = hipEventRecord(slot.span[3], slot.stream);
   slot.out_bytes = out_end;
   if (e == hipSuccess) e = hipEventRecord(slot.done, slot.stream);
   if (e != hipSuccess) {
@@ -296,6 +255,7 @@ bool Serve::launch_one(std::unique_lock<std::mutex> &lk, Slot &slot) {
 void Serve::reap(std::unique_lock<std::mutex> &lk, Slot &slot, hipError_t status) {
   std::vector<Req *> rs = slot.reqs;
   lk.unlock();
+  const Clock::time_point t_seen = Clock::now();
   if (status == hipSuccess) {
     const char *h = static_cast<const char *>(slot.h_out);
     for (Req *r : rs) {
@@ -312,6 +272,7 @@ void Serve::reap(std::unique_lock<std::mutex> &lk, Slot &slot, hipError_t status
   const Clock::time_point now = Clock::now();
   for (Req *r : rs) {
     r->status = status == hipSuccess ? AERL_OK : AERL_EDEVICE;
+    r->t_seen_done = t_seen;
     r->t_done = now;
     r->done = true;
     if (r->kind == AERL_REQ_FITNESS && --ds_refs[r->dataset_id] == 0) ds_refs.erase(r->dataset_id);
@@ -322,10 +283,43 @@ void Serve::reap(std::unique_lock<std::mutex> &lk, Slot &slot, hipError_t status
     r->rows = std::vector<float>();
   }
   t_last = now;
+  if (trace) write_trace(slot, rs, status);
   alloc.release(slot.off, slot.bytes);
   slot.busy = false;
   slot.reqs.clear();
   cv_done.notify_all();
+}
+
+// One JSON line per request of a finished launch: the host spans (packing on
+// the submitting thread, waiting in the queue, launch to completion seen by
+// the scheduler, completion to outputs in the caller's buffers) and the
+// launch's device spans from its timing events (upload, kernels, download),
+// shared by every request of the launch.  Times in microseconds, the submit
+// time from the loop's start.
+void Serve::write_trace(const Slot &slot, const std::vector<Req *> &rs, hipError_t status) {
+  float dev_ms[3] = {-1.0f, -1.0f, -1.0f};
+  if (status == hipSuccess)
+    for (int i = 0; i < 3; ++i)
+      if (hipEventElapsedTime(&dev_ms[i], slot.span[i], slot.span[i + 1]) != hipSuccess) {
+        (void)hipGetLastError();
+        dev_ms[i] = -1.0f;
+      }
+  for (const Req *r : rs) {
+    std::fprintf(trace,
+                 "{\"ticket\": %llu, \"kind\": \"%s\", \"dataset\": %d, \"sets\": %d, "
+                 "\"rows\": %lld, \"batch\": %d, \"slot\": %d, \"status\": %d, "
+                 "\"submit_us\": %.1f, \"pack_us\": %.1f, \"queue_us\": %.1f, "
+                 "\"launch_us\": %.1f, \"copy_out_us\": %.1f, \"total_us\": %.1f, "
+                 "\"h2d_us\": %.1f, \"kernels_us\": %.1f, \"d2h_us\": %.1f}\n",
+                 (unsigned long long)r->ticket, r->kind == AERL_REQ_FITNESS ? "fitness" : "predict",
+                 r->kind == AERL_REQ_FITNESS ? r->dataset_id : -1, r->rec.n_sets,
+                 (long long)r->n_rows, r->batch_size, slot.index, (int)r->status,
+                 us_between(t_start, r->t_submit), us_between(r->t_submit, r->t_queued),
+                 us_between(r->t_queued, r->t_launch), us_between(r->t_launch, r->t_seen_done),
+                 us_between(r->t_seen_done, r->t_done), us_between(r->t_submit, r->t_done),
+                 dev_ms[0] * 1e3, dev_ms[1] * 1e3, dev_ms[2] * 1e3);
+  }
+  std::fflush(trace);
 }
 
 void Serve::run() {
@@ -383,6 +377,8 @@ void free_slots(Serve *sv) {
   for (Slot &s : sv->slots) {
     if (s.stream) (void)hipStreamDestroy(s.stream);
     if (s.done) (void)hipEventDestroy(s.done);
+    for (hipEvent_t ev : s.span)
+      if (ev) (void)hipEventDestroy(ev);
     if (s.h_in) (void)hipHostFree(s.h_in);
     if (s.h_out) (void)hipHostFree(s.h_out);
   }
@@ -432,14 +428,28 @@ aerl_status aerl_serve_start(aerl_ctx *ctx, void *arena, size_t arena_bytes,
   sv->ds_refs.clear();
   reset_stats(sv);
   AERL_HIP(ctx, hipSetDevice(ctx->device));
+  // AERL_TRACE=<file>: append one JSON line per completed request
+  const char *trace_path = std::getenv("AERL_TRACE");
+  if (sv->trace) std::fclose(sv->trace);
+  sv->trace = nullptr;
+  if (trace_path && *trace_path) {
+    sv->trace = std::fopen(trace_path, "a");
+    if (!sv->trace) return fail(ctx, AERL_EINVAL, "cannot open the trace file %s", trace_path);
+  }
+  sv->t_start = Clock::now();
   sv->slots.assign(max_inflight, Slot{});
+  int index = 0;
   for (Slot &s : sv->slots) {
+    s.index = index++;
     hipError_t e = hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
+    for (int i = 0; i < 4 && e == hipSuccess && sv->trace; ++i) e = hipEventCreate(&s.span[i]);
     if (e == hipSuccess) e = ensure_pinned(&s.h_in, &s.in_cap, kInitialPinned);
     if (e == hipSuccess) e = ensure_pinned(&s.h_out, &s.out_cap, kInitialPinned);
     if (e != hipSuccess) {
       free_slots(sv);
+      if (sv->trace) std::fclose(sv->trace);
+      sv->trace = nullptr;
       return fail(ctx, AERL_EDEVICE, "serving slot setup failed: %s", hipGetErrorString(e));
     }
   }
@@ -529,6 +539,7 @@ aerl_status aerl_serve_submit(aerl_ctx *ctx, const aerl_request *req, uint64_t *
   std::lock_guard<std::mutex> sl(sv->m);
   if (sv->stopping) return fail(ctx, AERL_ESTATE, "serving loop is stopping");
   r->t_submit = t0;
+  r->t_queued = Clock::now();
   r->ticket = sv->next_ticket++;
   if (!sv->have_first) {
     sv->have_first = true;
@@ -621,6 +632,8 @@ aerl_status aerl_serve_stop(aerl_ctx *ctx) {
     std::lock_guard<std::mutex> sl(sv->m);
     sv->running = false;
     free_slots(sv);
+    if (sv->trace) std::fclose(sv->trace);
+    sv->trace = nullptr;
     sv->ds_refs.clear();
     sv->cv_done.notify_all();
   }

@@ -225,3 +225,43 @@ def test_dataset_in_use_cannot_be_released(ctx, resident):
         ctx.release_dataset(ds)  # nothing in flight any more
     else:
         pytest.skip("requests finished before the release attempt")
+
+
+def test_trace_span_log(ctx, resident, tmp_path, monkeypatch):
+    """AERL_TRACE names a file at start: one JSON line per completed request
+    with its host spans (pack, queue, launch, copy-out) and its launch's
+    device spans (upload, kernels, download), consistent with one another
+    and with the request's own result; without it nothing is written."""
+    import json
+    (small, ds_small), (big, ds_big) = resident
+    datas, dss = (small, big), (ds_small, ds_big)
+    reqs = make_requests(small, big, 30, 9)
+    path = tmp_path / "spans.jsonl"
+    monkeypatch.setenv("AERL_TRACE", str(path))
+    ctx.serve_start(64 << 20, max_inflight=2)
+    tickets = [submit(ctx, dss, r) for r in reqs]
+    outs = [t.wait() for t in tickets]
+    ctx.serve_stop()
+    lines = [json.loads(s) for s in path.read_text().splitlines()]
+    assert len(lines) == len(reqs)
+    by_ticket = {d["ticket"]: d for d in lines}
+    assert sorted(by_ticket) == sorted(t.ticket for t in tickets)
+    for r, t, o in zip(reqs, tickets, outs):
+        d = by_ticket[t.ticket]
+        assert d["kind"] == r[0] and d["status"] == 0 and d["slot"] in (0, 1)
+        assert d["batch"] == t.result["batch_size"] >= 1
+        for k in ("pack_us", "queue_us", "launch_us", "copy_out_us", "h2d_us", "kernels_us",
+                  "d2h_us"):
+            assert d[k] >= 0.0, (k, d)
+        parts = d["pack_us"] + d["queue_us"] + d["launch_us"] + d["copy_out_us"]
+        assert abs(parts - d["total_us"]) <= 1.0 + 1e-3 * d["total_us"], d
+        assert abs(d["total_us"] - t.result["latency_us"]) <= 1.0 + 1e-3 * d["total_us"], d
+        # the launch's device work ends before the scheduler sees it done
+        assert d["h2d_us"] + d["kernels_us"] + d["d2h_us"] <= d["launch_us"] + 50.0, d
+        check_result(ctx, datas, dss, r, o, alone=False)
+    monkeypatch.delenv("AERL_TRACE")
+    size = path.stat().st_size
+    ctx.serve_start(16 << 20)
+    submit(ctx, dss, reqs[0]).wait()
+    ctx.serve_stop()
+    assert path.stat().st_size == size

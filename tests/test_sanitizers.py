@@ -11,12 +11,12 @@ import subprocess
 
 import pytest
 
+from paper_2406_01821_amd.build_lib import SOURCES
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2406_01821_amd", "csrc")
 HIPCC = "/opt/rocm/bin/hipcc"
 CLANG = "/opt/rocm/llvm/bin/clang++"
-SOURCES = ["capi.cpp", "pack.cpp", "layout.hip", "hard.hip", "soft.hip", "ragged.hip", "batch.cpp",
-           "serve.cpp", "tune.hip", "evolve.cpp"]
 
 
 def _run(cmd, env=None, timeout=600):
