@@ -52,8 +52,11 @@ def gpu_soft(ctx, data, pop, dloss=None):
 
 def check_loss(got, ref):
     err = np.abs(got - ref)
-    bad = err > LOSS_RTOL * np.abs(ref) + LOSS_ATOL
+    bound = LOSS_RTOL * np.abs(ref) + LOSS_ATOL
+    bad = err > bound
     assert not bad.any(), (np.nonzero(bad)[0], got[bad], ref[bad])
+    if err.size:
+        print(f"loss bound used: {float((err / bound).max()):.3f}")
 
 
 def check_grad(got, ref):

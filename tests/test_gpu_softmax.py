@@ -31,8 +31,12 @@ def _params(pop, dev):
 
 
 def check_loss(got, ref):
-    bad = np.abs(got - ref) > 1e-5 * np.abs(ref) + 1e-6
+    err = np.abs(got - ref)
+    bound = 1e-5 * np.abs(ref) + 1e-6
+    bad = err > bound
     assert not bad.any(), (np.nonzero(bad)[0], got[bad], ref[bad])
+    if err.size:
+        print(f"loss bound used: {float((err / bound).max()):.3f}")
 
 
 def check_grad(got, ref):
