@@ -152,6 +152,46 @@ PackedLayout packed_layout(int32_t n_sets, int32_t n_rules, int32_t n_conds) {
   return L;
 }
 
+// Runs fn(i) for i in [0, n) on up to n host threads (i = 0 on the caller).
+template <class F>
+void run_parts(int n, const F &fn) {
+  std::vector<std::thread> th;
+  th.reserve(n > 1 ? n - 1 : 0);
+  for (int i = 1; i < n; ++i) {
+    try {
+      th.emplace_back(fn, i);
+    } catch (...) {  // no thread to be had: this part runs here
+      fn(i);
+    }
+  }
+  fn(0);
+  for (auto &t : th) t.join();
+}
+
+// Whether every condition in [j0, j1) is valid, without a message: the
+// checks of the detailed pass below, branch-light, for the common case of
+// a valid population.  Needs the op, kind, f, coef, g, coef2 and theta
+// arrays (the caller checks them); cat_mask only where a condition is
+// categorical.
+bool conds_valid(const aerl_population *p, int32_t j0, int32_t j1, int32_t nf) {
+  bool ok = true;
+  for (int32_t j = j0; j < j1; ++j) {
+    const uint32_t op = p->op[j], kind = p->kind[j], f = (uint32_t)p->f[j];
+    bool c = op <= 3u && kind <= 2u && f < (uint32_t)nf;
+    if (kind == AERL_KIND_FEATURE) {
+      const uint32_t g = (uint32_t)p->g[j];
+      c = c && g < (uint32_t)nf && g != f && std::isfinite(p->coef[j]) &&
+          std::isfinite(p->coef2[j]);
+    } else if (kind == AERL_KIND_CATEGORICAL) {
+      c = c && p->cat_mask != nullptr;
+    } else {
+      c = c && std::isfinite(p->coef[j]) && !std::isnan(p->theta[j]);
+    }
+    ok = ok && c;
+  }
+  return ok;
+}
+
 // Validates pop; on success fills the counts.  Returns AERL_OK or AERL_EINVAL
 // with the message in ctx (ctx may be null: then only the code is returned).
 aerl_status validate_population(aerl_ctx *ctx, const aerl_population *p, int32_t nf, int32_t nc,
@@ -186,7 +226,20 @@ aerl_status validate_population(aerl_ctx *ctx, const aerl_population *p, int32_t
   const int32_t n_conds = n_rules > 0 ? p->rule_cond_off[n_rules] : 0;
   if (n_conds > 0 && (!p->op || !p->kind || !p->f || !p->coef))
     return fail(ctx, AERL_EINVAL, "condition arrays are NULL");
-  for (int32_t j = 0; j < n_conds; ++j) {
+  // the conditions in parallel parts first; the detailed pass (the first
+  // offending index and its message) only when some part finds a fault
+  bool fast_ok = false;
+  if (n_conds > 0 && p->g && p->coef2 && p->theta) {
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const int parts = (int)std::min<int64_t>(std::min(hw, 8u), (int64_t)n_conds / 32768 + 1);
+    std::vector<char> part_ok(parts, 0);
+    run_parts(parts, [&](int i) {
+      part_ok[i] = conds_valid(p, (int32_t)((int64_t)n_conds * i / parts),
+                               (int32_t)((int64_t)n_conds * (i + 1) / parts), nf);
+    });
+    fast_ok = std::all_of(part_ok.begin(), part_ok.end(), [](char v) { return v != 0; });
+  }
+  for (int32_t j = 0; j < (fast_ok ? 0 : n_conds); ++j) {
     if (p->op[j] > 3) return fail(ctx, AERL_EINVAL, "op[%d] = %d is not an operator", j, p->op[j]);
     if (p->kind[j] > 2) return fail(ctx, AERL_EINVAL, "kind[%d] = %d is not a kind", j, p->kind[j]);
     if (p->f[j] < 0 || p->f[j] >= nf)
@@ -364,21 +417,6 @@ void pack_rules(const aerl_population *p, int32_t q0, int32_t q1, int4 *rules, u
   *n_cat = cat;
 }
 
-// Runs fn(i) for i in [0, n) on up to n host threads (i = 0 on the caller).
-template <class F>
-void run_parts(int n, const F &fn) {
-  std::vector<std::thread> th;
-  th.reserve(n > 1 ? n - 1 : 0);
-  for (int i = 1; i < n; ++i) {
-    try {
-      th.emplace_back(fn, i);
-    } catch (...) {  // no thread to be had: this part runs here
-      fn(i);
-    }
-  }
-  fn(0);
-  for (auto &t : th) t.join();
-}
 
 }  // namespace
 

@@ -101,6 +101,37 @@ def test_population_validation_rejects(aerl, bad):
     assert aerl.population_status(pop, 5, 2) == aerl.AERL_EINVAL
 
 
+@pytest.mark.parametrize("field,value", [
+    ("op", 4), ("kind", 3), ("f", 9), ("f", -1), ("coef", np.float32(np.nan)),
+    ("theta", np.float32(np.nan)), ("g", -5)])
+def test_large_population_validation_finds_one_fault(aerl, field, value):
+    """A population of about 150k conditions is checked in several parallel
+    parts: one fault anywhere in it (first, last or in between, in a
+    threshold or a feature-vs-feature condition) is still found, and the
+    population without it passes."""
+    rng = np.random.default_rng(31)
+    x = synth.lognormal_features(rng, 200, 9)
+    pop = synth.random_population(rng, x, 12000, (1, 8), (1, 4), 3, 0.3)
+    assert pop.n_conds > 4 * 32768
+    assert aerl.population_status(pop, 9, 3) == 0
+    ff = np.nonzero(pop.kind == 1)[0]
+    t = np.nonzero(pop.kind == 0)[0]
+    for j in (0, pop.n_conds - 1, int(rng.integers(pop.n_conds)), int(t[len(t) // 2]),
+              int(ff[len(ff) // 3])):
+        if field == "theta" and pop.kind[j] != 0:
+            continue  # a feature-vs-feature condition has no theta
+        if field == "g" and pop.kind[j] != 1:
+            continue
+        arr = getattr(pop, field)
+        old = arr[j]
+        arr[j] = value
+        try:
+            assert aerl.population_status(pop, 9, 3) == aerl.AERL_EINVAL, (field, j)
+        finally:
+            arr[j] = old
+    assert aerl.population_status(pop, 9, 3) == 0
+
+
 def test_population_validation_rejects_structure(aerl):
     ok = from_rule_lists([(0, [(1, [_cond()])]), (1, [])])
     assert aerl.population_status(ok, 5, 2) == 0
