@@ -202,8 +202,10 @@ aerl_status aerl_pack_population(aerl_ctx *ctx, const aerl_population *pop, int3
 aerl_status aerl_pack_population_host(const aerl_population *pop, int32_t n_features,
                                       int32_t n_classes, void *dst, size_t dst_bytes);
 
-/* Forget a packed population (waits for its staging copy).  Errors:
- * AERL_ENOENT. */
+/* Forget a packed population (waits for its staging copy).  Its pinned
+ * host staging buffer stays with the context for later packs of a similar
+ * size (at most 8 buffers and 512 MiB kept; aerl_destroy frees them).
+ * Errors: AERL_ENOENT. */
 aerl_status aerl_release_population(aerl_ctx *ctx, int32_t pop_id);
 
 /* ------------------------------------------------------------------ hard */

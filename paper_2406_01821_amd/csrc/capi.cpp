@@ -146,6 +146,48 @@ void set_device_views(PopRec &rec, const PackedLayout &L, void *ws) {
 }
 }  // namespace
 
+// Pinned staging for a packed image of `bytes`: the smallest pooled buffer
+// that holds it without wasting more than its size again, else a new one.
+static hipError_t take_staging(aerl_ctx *ctx, size_t bytes, void **p, size_t *cap) {
+  size_t best = SIZE_MAX;
+  size_t k = ctx->staging_pool.size();
+  for (size_t i = 0; i < ctx->staging_pool.size(); ++i) {
+    const size_t c = ctx->staging_pool[i].second;
+    if (c >= bytes && c / 2 <= bytes && c < best) {
+      best = c;
+      k = i;
+    }
+  }
+  if (k < ctx->staging_pool.size()) {
+    *p = ctx->staging_pool[k].first;
+    *cap = ctx->staging_pool[k].second;
+    ctx->staging_pool.erase(ctx->staging_pool.begin() + (std::ptrdiff_t)k);
+    return hipSuccess;
+  }
+  *cap = 0;
+  hipError_t e = hipHostMalloc(p, bytes, hipHostMallocDefault);
+  if (e == hipSuccess) *cap = bytes;
+  return e;
+}
+
+// Returns a staging buffer whose copy has completed to the pool, which keeps
+// at most kStagingPoolBuffers buffers and kStagingPoolBytes bytes (the
+// oldest go first).
+constexpr size_t kStagingPoolBuffers = 8;
+constexpr size_t kStagingPoolBytes = (size_t)512 << 20;
+static void give_staging(aerl_ctx *ctx, void *p, size_t cap) {
+  if (!p) return;
+  ctx->staging_pool.emplace_back(p, cap);
+  size_t total = 0;
+  for (const auto &b : ctx->staging_pool) total += b.second;
+  while (!ctx->staging_pool.empty() &&
+         (ctx->staging_pool.size() > kStagingPoolBuffers || total > kStagingPoolBytes)) {
+    total -= ctx->staging_pool.front().second;
+    (void)hipHostFree(ctx->staging_pool.front().first);
+    ctx->staging_pool.erase(ctx->staging_pool.begin());
+  }
+}
+
 aerl_status pack_staged(aerl_ctx *ctx, const aerl_population *pop, int32_t nf, int32_t nc, void *ws,
                         size_t ws_bytes, void *staging, size_t staging_bytes, hipStream_t stream,
                         int32_t *pop_id) {
@@ -206,6 +248,7 @@ void aerl_destroy(aerl_ctx *ctx) {
     }
     if (kv.second.staging) (void)hipHostFree(kv.second.staging);
   }
+  for (const auto &b : ctx->staging_pool) (void)hipHostFree(b.first);
   delete ctx;
 }
 
@@ -362,7 +405,7 @@ aerl_status aerl_pack_population(aerl_ctx *ctx, const aerl_population *pop, int3
   if (ws_bytes < L.total) return fail(ctx, AERL_ENOMEM, "ws holds %zu bytes, %zu needed", ws_bytes, L.total);
   AERL_HIP(ctx, hipSetDevice(ctx->device));
   PopRec rec;
-  AERL_HIP(ctx, hipHostMalloc(&rec.staging, L.total, hipHostMallocDefault));
+  AERL_HIP(ctx, take_staging(ctx, L.total, &rec.staging, &rec.staging_cap));
   pack_population_image(pop, nf, nc, n_rules, n_conds, rec.staging, &rec);
   hipError_t e = hipMemcpyAsync(ws, rec.staging, L.total, hipMemcpyHostToDevice, stream);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&rec.staged, hipEventDisableTiming);
@@ -370,7 +413,7 @@ aerl_status aerl_pack_population(aerl_ctx *ctx, const aerl_population *pop, int3
   if (e != hipSuccess) {
     (void)hipStreamSynchronize(stream);
     if (rec.staged) (void)hipEventDestroy(rec.staged);
-    (void)hipHostFree(rec.staging);
+    give_staging(ctx, rec.staging, rec.staging_cap);
     return fail(ctx, AERL_EDEVICE, "staging copy failed: %s", hipGetErrorString(e));
   }
   set_device_views(rec, L, ws);
@@ -401,7 +444,7 @@ aerl_status aerl_release_population(aerl_ctx *ctx, int32_t pop_id) {
     (void)hipEventSynchronize(it->second.staged);
     (void)hipEventDestroy(it->second.staged);
   }
-  if (it->second.staging) (void)hipHostFree(it->second.staging);
+  give_staging(ctx, it->second.staging, it->second.staging_cap);
   ctx->pops.erase(it);
   return AERL_OK;
 }

@@ -133,7 +133,8 @@ struct PopRec {
   const uint32_t *sconds = nullptr;
   const uint4 *heads = nullptr;
   const uint2 *cmask = nullptr;
-  void *staging = nullptr;     // pinned host copy of the packed image
+  void *staging = nullptr;     // pinned host copy of the packed image (library-owned)
+  size_t staging_cap = 0;      // its capacity in bytes
   hipEvent_t staged = nullptr; // completion of the staging copy
 };
 
@@ -184,6 +185,9 @@ struct aerl_ctx {
   void *hard_part = nullptr;
   size_t hard_part_bytes = 0;
   hipEvent_t hard_part_done = nullptr;
+  // pinned staging buffers of released populations, reused by later packs
+  // (pinning host memory costs far more than packing into it)
+  std::vector<std::pair<void *, size_t>> staging_pool;
 };
 
 namespace aerl {
