@@ -216,10 +216,11 @@ aerl_status aerl_release_population(aerl_ctx *ctx, int32_t pop_id);
  *   correct    device int32 [n_sets]: samples whose prediction equals the label
  *   confusion  device int32 [n_sets][C][C] ([true][predicted]) or NULL
  * Outputs are overwritten (no accumulation).  Bit-exact.  With two to four
- * classes and 16-512 MiB of per-tile counts (4 bytes per rule set and
- * 256-sample tile) the call keeps those counts in a device buffer the
- * context owns (allocated or grown on the first call that needs more, freed
- * by aerl_destroy); calls that use it run one after another, also across
+ * classes, at least 4 Mi (256-sample tile, rule set) pairs and at most
+ * 512 MiB of per-tile counts ((C-1) 10-bit fields per rule set and tile)
+ * the call keeps those counts in a device buffer the context owns
+ * (allocated or grown on the first call that needs more, freed by
+ * aerl_destroy); calls that use it run one after another, also across
  * streams.  Errors:
  * AERL_ENOENT, AERL_EINVAL (feature count or class count of the population
  * and dataset differ, NULL correct), AERL_EDEVICE. */

@@ -522,8 +522,9 @@ static aerl_status eval_common(aerl_ctx *ctx, int32_t dataset_id, int32_t pop_id
   // atomics than a flush per block), in the context's buffer when it can
   // hold them; small ones keep the flush (no second launch).
   if (hard_c10(h.tiles_per_group) && ds.nc >= 2 && ds.nc <= 4) {
-    const size_t need = (size_t)ds.n_tiles * (size_t)pop.n_sets * 4;
-    if (need >= kHardPartMinBytes && need <= kHardPartMaxBytes) {
+    const size_t need =
+        (size_t)ds.n_tiles * (size_t)hard_part_row_words(pop.n_sets, h.sets_per_chunk, ds.nc) * 4;
+    if (ds.n_tiles * pop.n_sets >= kHardPartMinPairs && need <= kHardPartMaxBytes) {
       aerl_status st = hard_part_buffer(ctx, need, stream, &h.part);
       if (st) return st;
     }

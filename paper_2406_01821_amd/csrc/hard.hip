@@ -60,8 +60,8 @@ __global__ __launch_bounds__(kHardBlock) AERL_HARD_SGPR_CAP void k_hard(const Ha
   t.heads = a.heads;
   t.correct = a.correct;
   t.confusion = a.confusion;
-  t.part = a.part;
-  t.part_stride = a.set_count;
+  t.part = nullptr;
+  t.part_stride = 0;
   t.label = 0;
   t.tile_lo = t.tile_hi = 0;
   // one-dimensional grid, set chunk fastest: consecutive blocks share a tile
@@ -83,21 +83,36 @@ __global__ __launch_bounds__(kHardBlock) AERL_HARD_SGPR_CAP void k_hard(const Ha
   }
   t.q0 = chunk * a.sets_per_chunk;
   t.Q = min(a.sets_per_chunk, a.set_count - t.q0);
+  if (C10 && a.part) {
+    const int wpc = hard_c10_words(a.sets_per_chunk, a.nc);
+    t.part = a.part + (int64_t)chunk * wpc;
+    t.part_stride = a.n_chunks * wpc;
+  }
   hard_block<S, CAT, C10>(t, smem, sh);
 }
 
 // Sums the per-tile counter words of a hard-eval launch over the tiles of
-// each class region.  part[tile][p] holds, in 10-bit fields, rule set p's
-// counts of classes 0..nc-2 among the tile's real samples; class nc-1 gets
-// the rest of them.  Thread p of block (x, y) takes rule set 256x + p over
-// the tiles of slice y (consecutive threads read consecutive words of a
-// tile's row) and adds each class region's totals to the outputs.
+// each class region.  A tile's row holds, chunk by chunk of Q rule sets,
+// the 10-bit counters of classes 0..nc-2 among the tile's real samples,
+// counter i = q*(nc-1) + c of the chunk's set q in bits 10*(i%3) of word
+// i/3 (at most two words per set); class nc-1 gets the rest of them.
+// Thread p of block (x, y) takes rule set 256x + p over the tiles of slice
+// y (neighbouring threads read neighbouring words of a tile's row) and adds
+// each class region's totals to the outputs.
 constexpr int kReduceBlock = 256;
 __global__ __launch_bounds__(kReduceBlock) void k_hard_reduce(
     const uint32_t *__restrict__ part, const int32_t *__restrict__ tile_info, int64_t n_tiles,
-    int32_t n_sets, int32_t nc, int32_t *__restrict__ correct, int32_t *__restrict__ confusion) {
+    int32_t n_sets, int32_t Q, int32_t nc, int32_t *__restrict__ correct,
+    int32_t *__restrict__ confusion) {
   const int p = blockIdx.x * kReduceBlock + threadIdx.x;
   if (p >= n_sets) return;
+  const int ncc = nc - 1;
+  const int wpc = hard_c10_words(Q, nc);
+  const int64_t stride = (int64_t)((n_sets + Q - 1) / Q) * wpc;
+  const int i = (p % Q) * ncc;
+  const int64_t w = (int64_t)(p / Q) * wpc + i / 3;
+  const int b = i % 3 * 10;
+  const bool two = i % 3 + ncc > 3;  // the set's counters run into the next word
   const int64_t t0 = n_tiles * blockIdx.y / gridDim.y, t1 = n_tiles * (blockIdx.y + 1) / gridDim.y;
   int label = -1;
   int32_t c0 = 0, c1 = 0, c2 = 0, n = 0;
@@ -117,10 +132,15 @@ __global__ __launch_bounds__(kReduceBlock) void k_hard_reduce(
       label = info & 0xff;
       c0 = c1 = c2 = n = 0;
     }
-    const uint32_t w = part[t * n_sets + p];
-    c0 += (int32_t)(w & 1023u);
-    c1 += (int32_t)(w >> 10 & 1023u);
-    c2 += (int32_t)(w >> 20 & 1023u);
+    // the set's fields from bit 0 on, ten bits each (fields past ncc are
+    // the next sets' and are not used)
+    const uint32_t *row = part + t * stride + w;
+    uint64_t v = row[0];
+    if (two) v |= (uint64_t)row[1] << 30;
+    v >>= b;
+    c0 += (int32_t)(v & 1023u);
+    if (ncc > 1) c1 += (int32_t)(v >> 10 & 1023u);
+    if (ncc > 2) c2 += (int32_t)(v >> 20 & 1023u);
     n += info >> 8;
   }
   emit();
@@ -199,11 +219,12 @@ hipError_t launch_hard_eval(const HardLaunch &h, hipStream_t st) {
 hipError_t launch_hard_reduce(const HardLaunch &h, int n_cu, hipStream_t st) {
   const DatasetRec &ds = *h.ds;
   if (h.set_count <= 0 || ds.n_tiles == 0) return hipSuccess;
-  if (!h.part || ds.nc < 2 || ds.nc > 4) return hipErrorInvalidValue;
+  if (!h.part || ds.nc < 2 || ds.nc > 4 || h.sets_per_chunk < 1) return hipErrorInvalidValue;
   const int64_t bx = (h.set_count + kReduceBlock - 1) / kReduceBlock;
   const int64_t by = std::max<int64_t>(1, std::min<int64_t>(ds.n_tiles, (2LL * n_cu + bx - 1) / bx));
   hipLaunchKernelGGL(k_hard_reduce, dim3((unsigned)bx, (unsigned)by), dim3(kReduceBlock), 0, st,
-                     h.part, ds.tile_info, ds.n_tiles, h.set_count, ds.nc, h.correct, h.confusion);
+                     h.part, ds.tile_info, ds.n_tiles, h.set_count, h.sets_per_chunk, ds.nc,
+                     h.correct, h.confusion);
   return hipGetLastError();
 }
 

@@ -28,7 +28,7 @@ struct HardTask {
   const uint4 *heads; // the population's head table
   int32_t *correct;   // [n_sets]
   int32_t *confusion; // [n_sets][nc][nc] or null
-  uint32_t *part;     // per-tile counter words [tiles][part_stride], or null
+  uint32_t *part;     // this chunk's per-tile counter words (row stride part_stride), or null
   int32_t part_stride;
   int32_t q0, Q, tile_lo, tile_hi, label;
 };
@@ -44,15 +44,16 @@ struct HardTask {
 // wave tile) and reach the outputs once, through integer atomics; the last
 // class's count is what the other classes leave of the block's samples.
 // smem holds nf*64*S floats, then nf (max, -min) pairs, then the counters
-// of the classes but the last, hard_counter_bytes(Q, nc, C10) bytes: with
-// C10 (a block of one layout tile, so a count is at most 256) three 10-bit
-// counters per 32-bit word, else two 16-bit ones (a block covers at most 255
-// layout tiles, so a counter stays below 2^16).  With C10, at most four
-// classes (one word per rule set) and t.part set, the block stores its
-// counter words to t.part's row of its tile instead, for a second kernel to
-// sum.  sh[0] is the rule-set counter, sh[1] the block's real sample count
-// (kept in LDS by one thread, so that it holds no register through the
-// walk).  Ends with a barrier, so the caller may reuse smem.
+// of the classes but the last, hard_counter_bytes(Q, nc, C10) bytes,
+// counter q*(nc-1) + c for set q and class c: with C10 (a block of one
+// layout tile, so a count is at most 256) three 10-bit counters per 32-bit
+// word, else two 16-bit ones (a block covers at most 255 layout tiles, so a
+// counter stays below 2^16).  With C10 and t.part set, the block stores its
+// counter words to t.part's row of its tile instead (row stride
+// t.part_stride words), for a second kernel to sum.  sh[0] is the rule-set
+// counter, sh[1] the block's real sample count (kept in LDS by one thread,
+// so that it holds no register through the walk).  Ends with a barrier, so
+// the caller may reuse smem.
 template <int S, bool CAT, bool C10 = false>
 __device__ __forceinline__ void hard_block(const HardTask &t, float *smem, int32_t *sh) {
   int32_t *next_q = sh;
@@ -63,11 +64,6 @@ __device__ __forceinline__ void hard_block(const HardTask &t, float *smem, int32
   const int ncc = hard_counters_per_set(t.nc);                        // counted classes
   uint32_t *cnt32 = reinterpret_cast<uint32_t *>(ext + 2 * t.nf);
   const int lane = threadIdx.x & 63;
-  // counter words per rule set, and lane c's word and bit offset in a set's
-  // counters
-  const int wps = C10 ? (ncc + 2) / 3 : (ncc + 1) / 2;
-  const uint32_t lane_word = C10 ? (uint32_t)lane / 3u : 0u;
-  const uint32_t lane_bit = C10 ? (uint32_t)lane % 3u * 10u : 0u;
   for (int i = threadIdx.x; i < (int)(hard_counter_bytes(t.Q, t.nc, C10) / 4); i += blockDim.x)
     cnt32[i] = 0u;
   if (threadIdx.x == 0) sh[1] = 0;
@@ -164,20 +160,20 @@ __device__ __forceinline__ void hard_block(const HardTask &t, float *smem, int32
         // lane c < ncc adds class c's count: a no-return atomic add with no
         // carry between the fields of a word (each count fits its field)
         if (lane < ncc) {
-          if (C10) {
-            atomicAdd(cnt32 + (uint32_t)(q * wps) + lane_word, (uint32_t)acc << lane_bit);
-          } else {
-            const int i = q * ncc + lane;
+          const uint32_t i = (uint32_t)(q * ncc + lane);
+          if (C10)
+            atomicAdd(cnt32 + i / 3u, (uint32_t)acc << (i % 3u * 10u));
+          else
             atomicAdd(cnt32 + (i >> 1), (uint32_t)acc << ((i & 1) * 16));
-          }
         }
       }
     }
   }
   __syncthreads();
   if (C10 && t.part != nullptr) {
-    uint32_t *dst = t.part + (int64_t)t.tile_lo * t.part_stride + t.q0;
-    for (int q = threadIdx.x; q < t.Q; q += blockDim.x) dst[q] = cnt32[q];
+    uint32_t *dst = t.part + (int64_t)t.tile_lo * t.part_stride;
+    const int nw = hard_c10_words(t.Q, t.nc);
+    for (int w = threadIdx.x; w < nw; w += blockDim.x) dst[w] = cnt32[w];
     __syncthreads();
     return;
   }
@@ -189,12 +185,11 @@ __device__ __forceinline__ void hard_block(const HardTask &t, float *smem, int32
     for (int c = 0; c < t.nc; ++c) {
       int v = rest;
       if (c < ncc) {
-        if (C10) {
-          v = (int)(cnt32[q * wps + c / 3] >> (c % 3 * 10)) & 1023;
-        } else {
-          const int i = q * ncc + c;
+        const int i = q * ncc + c;
+        if (C10)
+          v = (int)(cnt32[i / 3] >> (i % 3 * 10)) & 1023;
+        else
           v = (int)(cnt32[i >> 1] >> ((i & 1) * 16)) & 0xffff;
-        }
       }
       rest -= v;
       if (v == 0) continue;

@@ -216,10 +216,11 @@ hipError_t launch_hard_eval(const HardLaunch &h, hipStream_t s);
 // Sums h.part over the tiles of each class region into h.correct and
 // h.confusion (which must be zeroed), about two workgroups per CU.
 hipError_t launch_hard_reduce(const HardLaunch &h, int n_cu, hipStream_t s);
-// Per-tile counter buffers the plain hard path uses: at least 16 MiB of
-// counter words (smaller launches flush per block, without a second
-// kernel), at most 512 MiB (larger ones flush per block too).
-constexpr size_t kHardPartMinBytes = (size_t)16 << 20;
+// Per-tile counter buffers the plain hard path uses: for launches of at
+// least 4 Mi (tile, rule set) pairs (smaller ones flush per block, without
+// a second kernel) and at most 512 MiB of counter words (larger ones flush
+// per block too).
+constexpr int64_t kHardPartMinPairs = (int64_t)4 << 20;
 constexpr size_t kHardPartMaxBytes = (size_t)512 << 20;
 // Workgroups of a hard-eval launch: one per (set chunk, tile group), in a
 // one-dimensional grid of 1024-thread blocks whose work-item count must fit
@@ -262,19 +263,27 @@ constexpr size_t kDynLdsMax = kLdsPerCu - kStaticLds;
 // Dynamic LDS of a hard-eval block: the feature tile (nf x 64*S floats),
 // the tile's per-feature extremes and one prediction counter per (rule set,
 // class) for every class but the last (a set predicts the last class for the
-// block's samples the other counters leave): 16-bit counters, two per word,
-// or, when the block covers one layout tile (a count is then at most 256),
-// 10-bit counters, three per word.  A block adds at most 256 samples per
-// layout tile to a counter, so it covers at most kMaxTilesPerBlock layout
-// tiles.
+// block's samples the other counters leave), counter i = q*(nc-1) + c of
+// the chunk's set q and class c: 16-bit counters, two per word, or, when the
+// block covers one layout tile (a count is then at most 256), 10-bit
+// counters, three per word.  A block adds at most 256 samples per layout
+// tile to a counter, so it covers at most kMaxTilesPerBlock layout tiles.
 constexpr int kMaxTilesPerBlock = 255;
 // Most rule sets per block of the plain hard-eval path.
 constexpr int kHardChunkMax = 2048;
 __host__ __device__ inline int hard_counters_per_set(int nc) { return nc > 1 ? nc - 1 : 0; }
+// 32-bit words holding the 10-bit counters of Q rule sets.
+__host__ __device__ inline int hard_c10_words(int Q, int nc) {
+  return (int)(((int64_t)Q * hard_counters_per_set(nc) + 2) / 3);
+}
 __host__ __device__ inline size_t hard_counter_bytes(int Q, int nc, bool c10) {
-  const int ncc = hard_counters_per_set(nc);
-  return (size_t)Q * 4 * (c10 ? (ncc + 2) / 3 : 0) +
-         (c10 ? 0 : (((size_t)Q * ncc * 2 + 3) & ~size_t(3)));
+  return c10 ? (size_t)hard_c10_words(Q, nc) * 4
+             : (((size_t)Q * hard_counters_per_set(nc) * 2 + 3) & ~size_t(3));
+}
+// Words per tile of the per-tile counter buffer: each chunk of Q rule sets
+// keeps its block's 10-bit counter words, chunk k at k * hard_c10_words(Q).
+inline int64_t hard_part_row_words(int32_t n_sets, int Q, int nc) {
+  return (int64_t)((n_sets + Q - 1) / Q) * hard_c10_words(Q, nc);
 }
 // Blocks of one layout tile count in 10-bit fields.
 inline bool hard_c10(int tiles_per_group) { return tiles_per_group == 1; }

@@ -227,22 +227,24 @@ def test_scaled_workload_full_size_every_set(ctx):
 
 @pytest.mark.parametrize("nc", [2, 3, 4])
 def test_per_tile_counts_every_class_count(ctx, nc):
-    """Launches whose per-tile counts fill at least 16 MiB (here about 1,200
-    tiles x 4,096 rule sets) store one counter word per (tile, rule set) and
-    a second kernel sums them: two to four classes (one to three counted
-    fields per word), a ragged last tile per class, every rule set against
-    the oracle, and the same counts from a launch that flushes per block
-    (two-tile groups)."""
+    """Launches of at least 4 Mi (tile, rule set) pairs (here about 1,200
+    tiles x 4,096 rule sets) store the blocks' 10-bit counter words per tile
+    and a second kernel sums them: two to four classes (one to three counted
+    fields per set, so sets share words or straddle two), a ragged last tile
+    per class, every rule set against the oracle; the same counts from
+    1001-set chunks (a short last chunk, chunks ending inside a word) and
+    from a launch that flushes per block (two-tile groups)."""
     w = synth.tiny(300 + nc, n=300_001, nf=9, n_classes=nc, n_sets=4096, rules=(0, 10),
                    conds=(0, 4))
-    assert (w.data.n + 255) // 256 * 4096 * 4 >= 16 << 20
+    assert (w.data.n + 255) // 256 * 4096 >= 4 << 20
     c, m = run_hard(ctx, w.data, w.pop)
     rc, rm = oracle.hard_eval(w.data.x, w.data.y, nc, w.pop)
     np.testing.assert_array_equal(c, rc)
     np.testing.assert_array_equal(m, rm)
-    c2, m2 = run_hard(ctx, w.data, w.pop, cfg=(4, 2048, 2))
-    np.testing.assert_array_equal(c2, rc)
-    np.testing.assert_array_equal(m2, rm)
+    for cfg in ((4, 1001, 1), (4, 2048, 2)):
+        c2, m2 = run_hard(ctx, w.data, w.pop, cfg=cfg)
+        np.testing.assert_array_equal(c2, rc)
+        np.testing.assert_array_equal(m2, rm)
 
 
 def test_dataset_past_65535_tiles(ctx):
