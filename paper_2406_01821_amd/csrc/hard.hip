@@ -84,7 +84,7 @@ __global__ __launch_bounds__(kHardBlock) AERL_HARD_SGPR_CAP void k_hard(const Ha
   t.q0 = chunk * a.sets_per_chunk;
   t.Q = min(a.sets_per_chunk, a.set_count - t.q0);
   if (C10 && a.part) {
-    const int wpc = hard_c10_words(a.sets_per_chunk, a.nc);
+    const int wpc = hard_part_chunk_words(a.sets_per_chunk, a.nc);
     t.part = a.part + (int64_t)chunk * wpc;
     t.part_stride = a.n_chunks * wpc;
   }
@@ -107,12 +107,14 @@ __global__ __launch_bounds__(kReduceBlock) void k_hard_reduce(
   const int p = blockIdx.x * kReduceBlock + threadIdx.x;
   if (p >= n_sets) return;
   const int ncc = nc - 1;
-  const int wpc = hard_c10_words(Q, nc);
+  const int wpc = hard_part_chunk_words(Q, nc);
   const int64_t stride = (int64_t)((n_sets + Q - 1) / Q) * wpc;
   const int i = (p % Q) * ncc;
   const int64_t w = (int64_t)(p / Q) * wpc + i / 3;
   const int b = i % 3 * 10;
-  const bool two = i % 3 + ncc > 3;  // the set's counters run into the next word
+  // the word after w when the set's counters run into it, else w again (a
+  // second read of the same word keeps the loop free of branches)
+  const int w2 = i % 3 + ncc > 3 ? 1 : 0;
   const int64_t t0 = n_tiles * blockIdx.y / gridDim.y, t1 = n_tiles * (blockIdx.y + 1) / gridDim.y;
   int label = -1;
   int32_t c0 = 0, c1 = 0, c2 = 0, n = 0;
@@ -132,12 +134,10 @@ __global__ __launch_bounds__(kReduceBlock) void k_hard_reduce(
       label = info & 0xff;
       c0 = c1 = c2 = n = 0;
     }
-    // the set's fields from bit 0 on, ten bits each (fields past ncc are
-    // the next sets' and are not used)
+    // the set's fields from bit 0 on, ten bits each (those past its ncc
+    // are not used)
     const uint32_t *row = part + t * stride + w;
-    uint64_t v = row[0];
-    if (two) v |= (uint64_t)row[1] << 30;
-    v >>= b;
+    const uint64_t v = ((uint64_t)row[w2] << 30 | row[0]) >> b;
     c0 += (int32_t)(v & 1023u);
     if (ncc > 1) c1 += (int32_t)(v >> 10 & 1023u);
     if (ncc > 2) c2 += (int32_t)(v >> 20 & 1023u);

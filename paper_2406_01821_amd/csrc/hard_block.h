@@ -44,16 +44,17 @@ struct HardTask {
 // wave tile) and reach the outputs once, through integer atomics; the last
 // class's count is what the other classes leave of the block's samples.
 // smem holds nf*64*S floats, then nf (max, -min) pairs, then the counters
-// of the classes but the last, hard_counter_bytes(Q, nc, C10) bytes,
-// counter q*(nc-1) + c for set q and class c: with C10 (a block of one
-// layout tile, so a count is at most 256) three 10-bit counters per 32-bit
-// word, else two 16-bit ones (a block covers at most 255 layout tiles, so a
-// counter stays below 2^16).  With C10 and t.part set, the block stores its
-// counter words to t.part's row of its tile instead (row stride
-// t.part_stride words), for a second kernel to sum.  sh[0] is the rule-set
-// counter, sh[1] the block's real sample count (kept in LDS by one thread,
-// so that it holds no register through the walk).  Ends with a barrier, so
-// the caller may reuse smem.
+// of the classes but the last, hard_counter_bytes(Q, nc, C10) bytes: with
+// C10 (a block of one layout tile, so a count is at most 256) a set's
+// counters in 10-bit fields, three per 32-bit word, else two 16-bit ones
+// per word, counter q*(nc-1) + c for set q and class c (a block covers at
+// most 255 layout tiles, so a counter stays below 2^16).  With C10, at most
+// four classes and t.part set, the block stores its counters to t.part's
+// row of its tile instead (row stride t.part_stride words), packed across
+// sets three fields to a word, for a second kernel to sum.  sh[0] is the
+// rule-set counter, sh[1] the block's real sample count (kept in LDS by one
+// thread, so that it holds no register through the walk).  Ends with a
+// barrier, so the caller may reuse smem.
 template <int S, bool CAT, bool C10 = false>
 __device__ __forceinline__ void hard_block(const HardTask &t, float *smem, int32_t *sh) {
   int32_t *next_q = sh;
@@ -64,6 +65,11 @@ __device__ __forceinline__ void hard_block(const HardTask &t, float *smem, int32
   const int ncc = hard_counters_per_set(t.nc);                        // counted classes
   uint32_t *cnt32 = reinterpret_cast<uint32_t *>(ext + 2 * t.nf);
   const int lane = threadIdx.x & 63;
+  // with C10: counter words per rule set, and lane c's word and bit offset
+  // in a set's counters
+  const int wps = (ncc + 2) / 3;
+  const uint32_t lane_word = (uint32_t)lane / 3u;
+  const uint32_t lane_bit = (uint32_t)lane % 3u * 10u;
   for (int i = threadIdx.x; i < (int)(hard_counter_bytes(t.Q, t.nc, C10) / 4); i += blockDim.x)
     cnt32[i] = 0u;
   if (threadIdx.x == 0) sh[1] = 0;
@@ -160,20 +166,41 @@ __device__ __forceinline__ void hard_block(const HardTask &t, float *smem, int32
         // lane c < ncc adds class c's count: a no-return atomic add with no
         // carry between the fields of a word (each count fits its field)
         if (lane < ncc) {
-          const uint32_t i = (uint32_t)(q * ncc + lane);
-          if (C10)
-            atomicAdd(cnt32 + i / 3u, (uint32_t)acc << (i % 3u * 10u));
-          else
+          if (C10) {
+            atomicAdd(cnt32 + (uint32_t)(q * wps) + lane_word, (uint32_t)acc << lane_bit);
+          } else {
+            const int i = q * ncc + lane;
             atomicAdd(cnt32 + (i >> 1), (uint32_t)acc << ((i & 1) * 16));
+          }
         }
       }
     }
   }
   __syncthreads();
   if (C10 && t.part != nullptr) {
+    // word w of the row holds counters 3w..3w+2 of the chunk (counter
+    // i = q*ncc + c), ten bits each; with four classes that is set w's word
     uint32_t *dst = t.part + (int64_t)t.tile_lo * t.part_stride;
-    const int nw = hard_c10_words(t.Q, t.nc);
-    for (int w = threadIdx.x; w < nw; w += blockDim.x) dst[w] = cnt32[w];
+    const int nw = hard_part_chunk_words(t.Q, t.nc), ni = t.Q * ncc;
+    if (ncc == 3) {
+      for (int w = threadIdx.x; w < nw; w += blockDim.x) dst[w] = cnt32[w];
+    } else if (ncc == 2) {
+      // one word per set in LDS, counters c = 0, 1 in bits 0 and 10
+      for (int w = threadIdx.x; w < nw; w += blockDim.x) {
+        uint32_t v = 0u;
+        for (int k = 0; k < 3 && 3 * w + k < ni; ++k) {
+          const int i = 3 * w + k;
+          v |= (cnt32[i >> 1] >> ((i & 1) * 10) & 1023u) << (10 * k);
+        }
+        dst[w] = v;
+      }
+    } else if (ncc == 1) {
+      for (int w = threadIdx.x; w < nw; w += blockDim.x) {
+        uint32_t v = 0u;
+        for (int k = 0; k < 3 && 3 * w + k < ni; ++k) v |= cnt32[3 * w + k] << (10 * k);
+        dst[w] = v;
+      }
+    }
     __syncthreads();
     return;
   }
@@ -185,11 +212,12 @@ __device__ __forceinline__ void hard_block(const HardTask &t, float *smem, int32
     for (int c = 0; c < t.nc; ++c) {
       int v = rest;
       if (c < ncc) {
-        const int i = q * ncc + c;
-        if (C10)
-          v = (int)(cnt32[i / 3] >> (i % 3 * 10)) & 1023;
-        else
+        if (C10) {
+          v = (int)(cnt32[q * wps + c / 3] >> (c % 3 * 10)) & 1023;
+        } else {
+          const int i = q * ncc + c;
           v = (int)(cnt32[i >> 1] >> ((i & 1) * 16)) & 0xffff;
+        }
       }
       rest -= v;
       if (v == 0) continue;

@@ -263,27 +263,28 @@ constexpr size_t kDynLdsMax = kLdsPerCu - kStaticLds;
 // Dynamic LDS of a hard-eval block: the feature tile (nf x 64*S floats),
 // the tile's per-feature extremes and one prediction counter per (rule set,
 // class) for every class but the last (a set predicts the last class for the
-// block's samples the other counters leave), counter i = q*(nc-1) + c of
-// the chunk's set q and class c: 16-bit counters, two per word, or, when the
-// block covers one layout tile (a count is then at most 256), 10-bit
-// counters, three per word.  A block adds at most 256 samples per layout
-// tile to a counter, so it covers at most kMaxTilesPerBlock layout tiles.
+// block's samples the other counters leave): 16-bit counters, two per word,
+// or, when the block covers one layout tile (a count is then at most 256),
+// a set's 10-bit counters, three per word.  A block adds at most 256
+// samples per layout tile to a counter, so it covers at most
+// kMaxTilesPerBlock layout tiles.
 constexpr int kMaxTilesPerBlock = 255;
 // Most rule sets per block of the plain hard-eval path.
 constexpr int kHardChunkMax = 2048;
 __host__ __device__ inline int hard_counters_per_set(int nc) { return nc > 1 ? nc - 1 : 0; }
-// 32-bit words holding the 10-bit counters of Q rule sets.
-__host__ __device__ inline int hard_c10_words(int Q, int nc) {
+__host__ __device__ inline size_t hard_counter_bytes(int Q, int nc, bool c10) {
+  const int ncc = hard_counters_per_set(nc);
+  return c10 ? (size_t)Q * 4 * ((ncc + 2) / 3) : (((size_t)Q * ncc * 2 + 3) & ~size_t(3));
+}
+// Words of one chunk of Q rule sets in a row of the per-tile counter
+// buffer: the chunk's 10-bit counters packed across sets, three per word.
+__host__ __device__ inline int hard_part_chunk_words(int Q, int nc) {
   return (int)(((int64_t)Q * hard_counters_per_set(nc) + 2) / 3);
 }
-__host__ __device__ inline size_t hard_counter_bytes(int Q, int nc, bool c10) {
-  return c10 ? (size_t)hard_c10_words(Q, nc) * 4
-             : (((size_t)Q * hard_counters_per_set(nc) * 2 + 3) & ~size_t(3));
-}
-// Words per tile of the per-tile counter buffer: each chunk of Q rule sets
-// keeps its block's 10-bit counter words, chunk k at k * hard_c10_words(Q).
+// Words per tile of the per-tile counter buffer: chunk k of Q rule sets at
+// word k * hard_part_chunk_words(Q).
 inline int64_t hard_part_row_words(int32_t n_sets, int Q, int nc) {
-  return (int64_t)((n_sets + Q - 1) / Q) * hard_c10_words(Q, nc);
+  return (int64_t)((n_sets + Q - 1) / Q) * hard_part_chunk_words(Q, nc);
 }
 // Blocks of one layout tile count in 10-bit fields.
 inline bool hard_c10(int tiles_per_group) { return tiles_per_group == 1; }
