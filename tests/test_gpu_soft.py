@@ -117,6 +117,44 @@ def test_every_adjoint_variant(ctx, rules, conds, nf):
     run_case(ctx, w.data, w.pop)
 
 
+def test_widest_table_and_longest_rules(ctx):
+    """512 features (one sample per lane in both directions, a 128 KiB tile)
+    with rules of 255 conditions (the log-sum accumulator) in rule sets of
+    up to 1022 conditions; the conditions pass most samples (thresholds in
+    the tails, a tenth near the median), so the rules' soft truths stay away
+    from 0 and every condition's gradient matters."""
+    rng = np.random.default_rng(5120)
+    n, nf, nc = 1500, 512, 3
+    x = synth.lognormal_features(rng, n, nf)
+    y = rng.integers(0, nc, n).astype(np.int32)
+
+    def cond():
+        f = int(rng.integers(nf))
+        u = rng.uniform(0.3, 0.7) if rng.random() < 0.1 else rng.uniform(0.0, 0.05)
+        k = int(rng.integers(4))
+        if k == 0:
+            return dict(op=3, f=f, coef=1.0, theta=np.float32(np.quantile(x[:, f], u)))
+        if k == 1:
+            return dict(op=1, f=f, coef=1.0, theta=np.float32(np.quantile(x[:, f], 1.0 - u)))
+        if k == 2:
+            return dict(op=2, f=f, coef=np.float32(rng.uniform(0.5, 2.0)),
+                        theta=np.float32(np.quantile(x[:, f], u)))
+        g = (f + 1 + int(rng.integers(nf - 1))) % nf
+        return dict(op=2, kind=1, f=f, g=g, coef=1.0, coef2=np.float32(1e-3))
+
+    def rule(k):
+        return (int(rng.integers(nc)), [cond() for _ in range(k)])
+
+    sets = [(0, [rule(255) for _ in range(4)] + [rule(2)]),
+            (1, [rule(255), rule(200), rule(64), rule(3)]),
+            (2, [rule(61), rule(255)])]
+    small = synth.tiny(5121, n=n, nf=nf, n_classes=nc, n_sets=6, rules=(1, 12), conds=(1, 6),
+                       ff_frac=0.3).pop
+    pop = from_rule_lists(sets + [small.to_rule_list(s) for s in range(small.n_sets)])
+    assert int(np.diff(pop.rule_cond_off).max()) == 255
+    run_case(ctx, Dataset(x, y, nc), pop, dloss=np.linspace(0.5, 1.5, pop.n_sets))
+
+
 def test_too_long_rule_sets_are_refused(ctx):
     """Rule sets whose per-rule adjoint state does not fit one wave's LDS
     (here 400 rules) are refused before any launch."""
