@@ -6,6 +6,7 @@ equivalent)."""
 import numpy as np
 import pytest
 
+import limits
 import oracle
 from paper_2406_01821_amd import synth
 from paper_2406_01821_amd.population import from_rule_lists
@@ -176,6 +177,36 @@ def test_empty_population_and_single_sample(ctx):
         ctx.release_population(p)
     for d in (ds1, ds2):
         ctx.release_dataset(d)
+
+
+@pytest.mark.parametrize("cfg", [None, (7, 3)])
+def test_mixed_widths_at_the_limits(ctx, cfg):
+    """One batch holding a 512-feature table with rule sets of 1023 records
+    (rules of 255 conditions), the paper's 569 x 30 shape and a 129-feature
+    table: the launch sizes its LDS for the widest item; every item against
+    the oracle, replayed from a graph."""
+    import torch
+    rng = np.random.default_rng(5125)
+    wide = limits.widest_table(rng, n=1500)
+    wide_pop = limits.longest_sets_population(rng, wide, n_extra=6, seed=5126)
+    c1 = synth.small_hard(0)
+    mid = synth.tiny(5127, n=900, nf=129, n_classes=4, n_sets=20, rules=(0, 16), conds=(0, 6))
+    cases = [(wide, wide_pop), (c1.data, c1.pop), (mid.data, mid.pop)]
+    devs = []
+    for d, pop in cases:
+        devs.append((ctx.upload_dataset(d), ctx.pack_population(pop, d.n_features, d.n_classes)))
+    items = make_items(ctx, devs)
+    ws = ctx.batch_workspace(items, cfg)
+    plan = ctx.batch_plan(items, ws, cfg, graph=True)
+    refs = [oracle.hard_eval(d.x, d.y, d.n_classes, pop) for d, pop in cases]
+    for _ in range(2):
+        plan.run()
+        torch.cuda.synchronize()
+        check_items(items, refs)
+    plan.release()
+    for ds, p in devs:
+        ctx.release_population(p)
+        ctx.release_dataset(ds)
 
 
 def test_empty_batch(ctx):

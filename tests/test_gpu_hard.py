@@ -4,6 +4,7 @@ semantics; Section 5: CPU and GPU results are equivalent)."""
 import numpy as np
 import pytest
 
+import limits
 import oracle
 from paper_2406_01821_amd import synth
 from paper_2406_01821_amd.population import Dataset, from_rule_lists
@@ -188,41 +189,12 @@ def test_limits_widest_table_and_longest_rule_set(ctx):
     default launch and a forced one, and predictions of the longest sets."""
     import torch
     rng = np.random.default_rng(512)
-    n, nf, nc = 2000, 512, 3
-    x = synth.lognormal_features(rng, n, nf)
-    y = rng.integers(0, nc, n).astype(np.int32)
-    lo, hi = np.quantile(x, 0.01, axis=0), np.quantile(x, 0.99, axis=0)
-
-    def cond():
-        f = int(rng.integers(nf))
-        k = int(rng.integers(4))
-        if k == 0:
-            return dict(op=3, f=f, coef=1.0, theta=np.float32(lo[f]))
-        if k == 1:
-            return dict(op=1, f=f, coef=1.0, theta=np.float32(hi[f]))
-        if k == 2:  # zero coefficient: 0*x > -1 for every finite x
-            return dict(op=2, f=f, coef=0.0, theta=-1.0)
-        g = (f + 1 + int(rng.integers(nf - 1))) % nf
-        return dict(op=2, kind=1, f=f, g=g, coef=1.0, coef2=np.float32(1e-3))
-
-    def rule(k):
-        return (int(rng.integers(nc)), [cond() for _ in range(k)])
-
-    long_sets = [
-        (0, [rule(255) for _ in range(4)] + [rule(2)]),              # 1022 conditions
-        (1, [rule(255) for _ in range(4)] + [rule(1), (2, [])]),      # 1021 + an empty rule
-        (2, [rule(255), (1, []), rule(64), rule(255), rule(255), rule(191)]),
-    ]
-    recs = [sum(max(len(c), 1) for _, c in rules) + 1 for _, rules in long_sets]
-    assert recs == [1023, 1023, 1022]
-    rest = synth.tiny(513, n=n, nf=nf, n_classes=nc, n_sets=12, rules=(0, 12), conds=(0, 6),
-                      ff_frac=0.3).pop
-    pop = from_rule_lists(long_sets + [rest.to_rule_list(s) for s in range(rest.n_sets)])
-    data = Dataset(x, y, nc)
+    data = limits.widest_table(rng)
+    pop = limits.longest_sets_population(rng, data)
     for cfg in (None, (1, 5, 3)):
         check_against_oracle(ctx, data, pop, cfg)
-    p = ctx.pack_population(pop, nf, nc)
-    rows = x[:700]
+    p = ctx.pack_population(pop, data.n_features, data.n_classes)
+    rows = data.x[:700]
     for s in range(3):
         got = ctx.predict(p, rows, s)
         torch.cuda.synchronize()
