@@ -75,7 +75,7 @@ def run_case(ctx, data, pop, beta, dloss=None):
     check_grad(g, oracle.smax_backward(data.x, data.y, tau, data.n_classes, pop, beta, dloss=dl))
 
 
-@pytest.mark.parametrize("nc,beta", [(2, 1.0), (3, 4.0), (4, 0.5), (9, 2.0)])
+@pytest.mark.parametrize("nc,beta", [(2, 1.0), (3, 4.0), (4, 0.5), (9, 2.0), (16, 1.5)])
 def test_mixed_kinds_and_classes(ctx, nc, beta):
     w = synth.tiny(60 + nc, n=3000, nf=9, n_classes=nc, n_sets=40, rules=(1, 8), conds=(1, 4),
                    ff_frac=0.4)
