@@ -42,14 +42,6 @@ struct Cond {
   int32_t f, g;
   float coef, coef2, theta;
 };
-struct Rule {
-  int32_t cls;
-  std::vector<Cond> conds;
-};
-struct Set {
-  int32_t dflt;
-  std::vector<Rule> rules;
-};
 
 struct Ranges {
   int32_t nf, nc;
@@ -79,13 +71,6 @@ Cond random_cond(Rng &r, const aerl_evolve_cfg &c, const Ranges &d) {
   return k;
 }
 
-Rule random_rule(Rng &r, const aerl_evolve_cfg &c, const Ranges &d) {
-  Rule u;
-  u.cls = r.below(d.nc);
-  u.conds.push_back(random_cond(r, c, d));
-  return u;
-}
-
 int32_t tournament(Rng &r, const int32_t *fit, int32_t n, int32_t k) {
   int32_t best = -1;
   for (int32_t t = 0; t < k; ++t) {
@@ -95,86 +80,54 @@ int32_t tournament(Rng &r, const int32_t *fit, int32_t n, int32_t k) {
   return best;
 }
 
-std::vector<Set> breed(Rng &r, const std::vector<Set> &pool, const int32_t *fit,
-                       const aerl_evolve_cfg &c, const Ranges &d) {
-  const int32_t n = (int32_t)pool.size();
-  std::vector<int32_t> order(n);
-  for (int32_t i = 0; i < n; ++i) order[i] = i;
-  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return fit[a] > fit[b]; });
-  std::vector<Set> out;
-  out.reserve(n);
-  for (int32_t i = 0; i < c.elite; ++i) out.push_back(pool[order[i]]);
-  for (int32_t i = c.elite; i < n; ++i) {
-    Set child = pool[tournament(r, fit, n, c.tournament)];
-    if (r.unit() < c.p_crossover) {
-      const Set &b = pool[tournament(r, fit, n, c.tournament)];
-      const int32_t ca = r.below((int32_t)child.rules.size() + 1);
-      const int32_t cb = r.below((int32_t)b.rules.size() + 1);
-      std::vector<Rule> merged(child.rules.begin(), child.rules.begin() + ca);
-      merged.insert(merged.end(), b.rules.begin() + cb, b.rules.end());
-      if (merged.empty()) merged.push_back(child.rules.front());
-      if ((int32_t)merged.size() > c.max_rules) merged.resize(c.max_rules);
-      child.rules = std::move(merged);
-    }
-    for (Rule &u : child.rules) {
-      for (Cond &k : u.conds) {
-        if (r.unit() < c.p_coef) {
-          k.coef = r.unit();
-          if (k.kind == 1)
-            k.coef2 = r.unit();
-          else
-            k.theta = range_theta(r, d, k.f);
-        }
-      }
-    }
-    if (r.unit() < c.p_struct) {
-      const int32_t t = r.below(4);
-      const int32_t R = (int32_t)child.rules.size();
-      if (t == 0) {
-        Rule &u = child.rules[r.below(R)];
-        if ((int32_t)u.conds.size() < c.max_conds) u.conds.push_back(random_cond(r, c, d));
-      } else if (t == 1) {
-        Rule &u = child.rules[r.below(R)];
-        if (u.conds.size() >= 2) u.conds.erase(u.conds.begin() + r.below((int32_t)u.conds.size()));
-      } else if (t == 2) {
-        if (R < c.max_rules) {
-          const int32_t pos = r.below(R + 1);
-          Rule u = random_rule(r, c, d);
-          child.rules.insert(child.rules.begin() + pos, std::move(u));
-        }
-      } else if (R >= 2) {
-        child.rules.erase(child.rules.begin() + r.below(R));
-      }
-    }
-    out.push_back(std::move(child));
-  }
-  return out;
-}
-
-std::vector<Set> random_pool(Rng &r, const aerl_evolve_cfg &c, const Ranges &d) {
-  std::vector<Set> pool(c.pool);
-  for (Set &s : pool) {
-    const int32_t R = 1 + r.below(c.max_rules);
-    s.dflt = r.below(d.nc);
-    for (int32_t k = 0; k < R; ++k) {
-      Rule u;
-      const int32_t K = 1 + r.below(c.max_conds);
-      u.cls = r.below(d.nc);
-      for (int32_t j = 0; j < K; ++j) u.conds.push_back(random_cond(r, c, d));
-      s.rules.push_back(std::move(u));
-    }
-  }
-  return pool;
-}
-
-// ------------------------------------------------------------ SoA forms
+// ------------------------------------------------------------ pools
+// A pool in the flat form of aerl_population, owning its arrays; the fields
+// a condition's kind does not use are 0 (g, coef2 of a threshold, theta of a
+// feature-vs-feature condition).
 struct Soa {
   std::vector<int32_t> set_rule_off, set_default, rule_cond_off, rule_class, f, g;
   std::vector<uint8_t> op, kind;
   std::vector<float> coef, coef2, theta;
+  int32_t n_sets() const { return (int32_t)set_default.size(); }
+  void clear() {
+    set_rule_off.assign(1, 0);
+    rule_cond_off.assign(1, 0);
+    for (auto *v : {&set_default, &rule_class, &f, &g}) v->clear();
+    op.clear();
+    kind.clear();
+    coef.clear();
+    coef2.clear();
+    theta.clear();
+  }
+  Cond cond(int32_t j) const { return Cond{op[j], kind[j], f[j], g[j], coef[j], coef2[j], theta[j]}; }
+  void push_cond(const Cond &k) {
+    op.push_back(k.op);
+    kind.push_back(k.kind);
+    f.push_back(k.f);
+    g.push_back(k.g);
+    coef.push_back(k.coef);
+    coef2.push_back(k.coef2);
+    theta.push_back(k.theta);
+  }
+  void end_rule(int32_t cls) {
+    rule_class.push_back(cls);
+    rule_cond_off.push_back((int32_t)op.size());
+  }
+  void end_set(int32_t dflt) {
+    set_default.push_back(dflt);
+    set_rule_off.push_back((int32_t)rule_class.size());
+  }
+  // rule set s of `from` appended unchanged
+  void copy_set(const Soa &from, int32_t s) {
+    for (int32_t r = from.set_rule_off[s]; r < from.set_rule_off[s + 1]; ++r) {
+      for (int32_t j = from.rule_cond_off[r]; j < from.rule_cond_off[r + 1]; ++j) push_cond(from.cond(j));
+      end_rule(from.rule_class[r]);
+    }
+    end_set(from.set_default[s]);
+  }
   aerl_population view() const {
     aerl_population p{};
-    p.n_sets = (int32_t)set_default.size();
+    p.n_sets = n_sets();
     p.set_rule_off = set_rule_off.data();
     p.set_default = set_default.data();
     p.rule_cond_off = rule_cond_off.data();
@@ -190,60 +143,164 @@ struct Soa {
   }
 };
 
-Soa to_soa(const std::vector<Set> &pool) {
+// A validated caller pool of kinds 0 and 1 in flat form.
+Soa from_view(const aerl_population &p) {
   Soa a;
-  a.set_rule_off.push_back(0);
-  a.rule_cond_off.push_back(0);
-  for (const Set &s : pool) {
-    a.set_default.push_back(s.dflt);
-    for (const Rule &u : s.rules) {
-      a.rule_class.push_back(u.cls);
-      for (const Cond &k : u.conds) {
-        a.op.push_back(k.op);
-        a.kind.push_back(k.kind);
-        a.f.push_back(k.f);
-        a.g.push_back(k.g);
-        a.coef.push_back(k.coef);
-        a.coef2.push_back(k.coef2);
-        a.theta.push_back(k.theta);
+  a.clear();
+  for (int32_t s = 0; s < p.n_sets; ++s) {
+    for (int32_t r = p.set_rule_off[s]; r < p.set_rule_off[s + 1]; ++r) {
+      for (int32_t j = p.rule_cond_off[r]; j < p.rule_cond_off[r + 1]; ++j) {
+        const bool ff = p.kind[j] != 0;
+        a.push_cond(Cond{p.op[j], p.kind[j], p.f[j], ff ? p.g[j] : 0, p.coef[j],
+                         ff ? p.coef2[j] : 0.0f, ff ? 0.0f : p.theta[j]});
       }
-      a.rule_cond_off.push_back((int32_t)a.op.size());
+      a.end_rule(p.rule_class[r]);
     }
-    a.set_rule_off.push_back((int32_t)a.rule_class.size());
+    a.end_set(p.set_default[s]);
   }
   return a;
 }
 
-std::vector<Set> from_view(const aerl_population &p) {
-  std::vector<Set> pool(p.n_sets);
+// Whether every rule set has 1..max_rules rules of 1..max_conds conditions.
+bool within_limits(const aerl_population &p, const aerl_evolve_cfg &c) {
   for (int32_t s = 0; s < p.n_sets; ++s) {
-    pool[s].dflt = p.set_default[s];
+    const int32_t R = p.set_rule_off[s + 1] - p.set_rule_off[s];
+    if (R < 1 || R > c.max_rules) return false;
     for (int32_t r = p.set_rule_off[s]; r < p.set_rule_off[s + 1]; ++r) {
-      Rule u;
-      u.cls = p.rule_class[r];
-      for (int32_t j = p.rule_cond_off[r]; j < p.rule_cond_off[r + 1]; ++j) {
-        Cond k{};
-        k.op = p.op[j];
-        k.kind = p.kind[j];
-        k.f = p.f[j];
-        k.g = k.kind ? p.g[j] : 0;
-        k.coef = p.coef[j];
-        k.coef2 = k.kind ? p.coef2[j] : 0.0f;
-        k.theta = k.kind ? 0.0f : p.theta[j];
-        u.conds.push_back(k);
-      }
-      pool[s].rules.push_back(std::move(u));
+      const int32_t K = p.rule_cond_off[r + 1] - p.rule_cond_off[r];
+      if (K < 1 || K > c.max_conds) return false;
     }
   }
-  return pool;
+  return true;
 }
 
-aerl_status write_out(const std::vector<Set> &pool, const aerl_evolve_cfg &c, aerl_population_out *o) {
+// The child being bred: its rules in order, each a range of a condition
+// buffer (rules added by a structural change put their condition at the
+// end of the buffer, so the ranges need not follow the rule order).
+struct Child {
+  struct RuleRef {
+    int32_t cls, start, count;
+  };
+  std::vector<RuleRef> rules;
+  std::vector<Cond> conds;
+  void add_rule(const Soa &p, int32_t r) {
+    const int32_t start = (int32_t)conds.size();
+    for (int32_t j = p.rule_cond_off[r]; j < p.rule_cond_off[r + 1]; ++j) conds.push_back(p.cond(j));
+    rules.push_back({p.rule_class[r], start, p.rule_cond_off[r + 1] - p.rule_cond_off[r]});
+  }
+  // shift the ranges that start at or after `at` by d
+  void shift_from(int32_t at, int32_t d) {
+    for (RuleRef &u : rules)
+      if (u.start >= at) u.start += d;
+  }
+};
+
+// The next generation (the operators specified with aerl_evolve_cfg), into
+// `out`; `ch` is scratch.  The random draws come in the same order as in
+// the specification: the elite need none; each child draws its tournament,
+// the crossover decision (and its second tournament and two cut points),
+// one redraw decision per condition in rule order (and the redrawn values),
+// the structural decision and its draws.
+void breed(Rng &r, const Soa &pool, const int32_t *fit, const aerl_evolve_cfg &c, const Ranges &d,
+           Soa &out, Child &ch) {
+  const int32_t n = pool.n_sets();
+  std::vector<int32_t> order(n);
+  for (int32_t i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return fit[a] > fit[b]; });
+  out.clear();
+  for (int32_t i = 0; i < c.elite; ++i) out.copy_set(pool, order[i]);
+  std::vector<std::pair<int32_t, int32_t>> refs;  // (rule set, rule) of the child's rules
+  refs.reserve(2 * (size_t)c.max_rules + 1);
+  for (int32_t i = c.elite; i < n; ++i) {
+    const int32_t pa = tournament(r, fit, n, c.tournament);
+    const int32_t a0 = pool.set_rule_off[pa], a1 = pool.set_rule_off[pa + 1];
+    refs.clear();
+    if (r.unit() < c.p_crossover) {
+      const int32_t pb = tournament(r, fit, n, c.tournament);
+      const int32_t b0 = pool.set_rule_off[pb], b1 = pool.set_rule_off[pb + 1];
+      const int32_t ca = r.below(a1 - a0 + 1);
+      const int32_t cb = r.below(b1 - b0 + 1);
+      for (int32_t k = a0; k < a0 + ca; ++k) refs.push_back({pa, k});
+      for (int32_t k = b0 + cb; k < b1; ++k) refs.push_back({pb, k});
+      if (refs.empty()) refs.push_back({pa, a0});
+      if ((int32_t)refs.size() > c.max_rules) refs.resize(c.max_rules);
+    } else {
+      for (int32_t k = a0; k < a1; ++k) refs.push_back({pa, k});
+    }
+    ch.rules.clear();
+    ch.conds.clear();
+    for (const auto &rf : refs) ch.add_rule(pool, rf.second);
+    // the conditions of the rules in order: the buffer holds them so
+    for (Cond &k : ch.conds) {
+      if (r.unit() < c.p_coef) {
+        k.coef = r.unit();
+        if (k.kind == 1)
+          k.coef2 = r.unit();
+        else
+          k.theta = range_theta(r, d, k.f);
+      }
+    }
+    if (r.unit() < c.p_struct) {
+      const int32_t t = r.below(4);
+      const int32_t R = (int32_t)ch.rules.size();
+      if (t == 0) {  // add a condition at the end of a rule
+        const int32_t u = r.below(R);
+        if (ch.rules[u].count < c.max_conds) {
+          const int32_t at = ch.rules[u].start + ch.rules[u].count;
+          const Cond k = random_cond(r, c, d);
+          ch.shift_from(at, 1);
+          ch.rules[u].count += 1;
+          ch.conds.insert(ch.conds.begin() + at, k);
+        }
+      } else if (t == 1) {  // drop a condition of a rule that keeps one
+        const int32_t u = r.below(R);
+        if (ch.rules[u].count >= 2) {
+          const int32_t at = ch.rules[u].start + r.below(ch.rules[u].count);
+          ch.conds.erase(ch.conds.begin() + at);
+          ch.rules[u].count -= 1;
+          ch.shift_from(at + 1, -1);
+        }
+      } else if (t == 2) {  // a new one-condition rule at a random position
+        if (R < c.max_rules) {
+          const int32_t pos = r.below(R + 1);
+          const int32_t cls = r.below(d.nc);
+          ch.conds.push_back(random_cond(r, c, d));
+          ch.rules.insert(ch.rules.begin() + pos, {cls, (int32_t)ch.conds.size() - 1, 1});
+        }
+      } else if (R >= 2) {  // drop a rule
+        ch.rules.erase(ch.rules.begin() + r.below(R));
+      }
+    }
+    for (const Child::RuleRef &u : ch.rules) {
+      for (int32_t k = 0; k < u.count; ++k) out.push_cond(ch.conds[u.start + k]);
+      out.end_rule(u.cls);
+    }
+    out.end_set(pool.set_default[pa]);
+  }
+}
+
+Soa random_pool(Rng &r, const aerl_evolve_cfg &c, const Ranges &d) {
+  Soa a;
+  a.clear();
+  for (int32_t s = 0; s < c.pool; ++s) {
+    const int32_t R = 1 + r.below(c.max_rules);
+    const int32_t dflt = r.below(d.nc);
+    for (int32_t k = 0; k < R; ++k) {
+      const int32_t K = 1 + r.below(c.max_conds);
+      const int32_t cls = r.below(d.nc);
+      for (int32_t j = 0; j < K; ++j) a.push_cond(random_cond(r, c, d));
+      a.end_rule(cls);
+    }
+    a.end_set(dflt);
+  }
+  return a;
+}
+
+aerl_status write_out(const Soa &a, aerl_population_out *o) {
   if (!o || !o->set_rule_off || !o->set_default || !o->rule_cond_off || !o->rule_class || !o->op ||
       !o->kind || !o->f || !o->g || !o->coef || !o->coef2 || !o->theta)
     return AERL_EINVAL;
-  const Soa a = to_soa(pool);
-  (void)c;  // capacities: pool + 1, pool, pool * max_rules + 1, pool * max_rules * max_conds
+  // capacities: pool + 1, pool, pool * max_rules + 1, pool * max_rules * max_conds
   std::memcpy(o->set_rule_off, a.set_rule_off.data(), a.set_rule_off.size() * 4);
   std::memcpy(o->set_default, a.set_default.data(), a.set_default.size() * 4);
   std::memcpy(o->rule_cond_off, a.rule_cond_off.data(), a.rule_cond_off.size() * 4);
@@ -255,7 +312,7 @@ aerl_status write_out(const std::vector<Set> &pool, const aerl_evolve_cfg &c, ae
   std::memcpy(o->coef, a.coef.data(), a.coef.size() * 4);
   std::memcpy(o->coef2, a.coef2.data(), a.coef2.size() * 4);
   std::memcpy(o->theta, a.theta.data(), a.theta.size() * 4);
-  o->n_sets = (int32_t)pool.size();
+  o->n_sets = a.n_sets();
   o->n_rules = (int32_t)a.rule_class.size();
   o->n_conds = (int32_t)a.op.size();
   return AERL_OK;
@@ -302,9 +359,10 @@ struct Evo {
   std::vector<float> lo, hi;
   Rng rng{0};
   int32_t generation = 0;
-  std::vector<Set> pool;
+  Soa pool;                      // the pool as last evaluated (state views point here)
+  Soa next;                      // breeding output, swapped in
+  Child scratch;
   std::vector<int32_t> fitness;
-  Soa soa;                       // the pool as last evaluated (state views point here)
   std::vector<float> tuned[3];   // tuned coef, coef2, theta of that pool
   char *arena = nullptr;
   size_t arena_bytes = 0;
@@ -354,9 +412,8 @@ namespace {
 // e.fitness, tuned parameters into e.tuned.  Synchronous.
 aerl_status evaluate(aerl_ctx *ctx, Evo &e, hipStream_t st) {
   using clk = std::chrono::steady_clock;
-  e.soa = to_soa(e.pool);
-  aerl_population view = e.soa.view();
-  const size_t nconds = e.soa.op.size();
+  aerl_population view = e.pool.view();
+  const size_t nconds = e.pool.op.size();
   char *pack = e.arena + e.layout.pack_off;
   int32_t *correct = reinterpret_cast<int32_t *>(e.arena + e.layout.correct_off);
   float *par = reinterpret_cast<float *>(e.arena + e.layout.param_off);
@@ -367,7 +424,7 @@ aerl_status evaluate(aerl_ctx *ctx, Evo &e, hipStream_t st) {
   for (auto &t : e.tuned) t.clear();
   if (e.cfg.tune_epochs > 0) {
     const auto t0 = clk::now();
-    const float *src[3] = {e.soa.coef.data(), e.soa.coef2.data(), e.soa.theta.data()};
+    const float *src[3] = {e.pool.coef.data(), e.pool.coef2.data(), e.pool.theta.data()};
     for (int k = 0; k < 3; ++k)
       AERL_HIP(ctx, hipMemcpyAsync(par + k * nconds, src[k], nconds * 4, hipMemcpyHostToDevice, st));
     aerl_finetune_cfg tc = e.cfg.tune;
@@ -396,8 +453,8 @@ aerl_status evaluate(aerl_ctx *ctx, Evo &e, hipStream_t st) {
   const auto t1 = clk::now();
   s = aerl_eval_population(ctx, e.dataset_id, pid, correct, nullptr, st);
   if (s == AERL_OK) {
-    e.fitness.resize(e.pool.size());
-    hipError_t h = hipMemcpyAsync(e.fitness.data(), correct, e.pool.size() * 4, hipMemcpyDeviceToHost, st);
+    e.fitness.resize(e.pool.n_sets());
+    hipError_t h = hipMemcpyAsync(e.fitness.data(), correct, e.pool.n_sets() * 4, hipMemcpyDeviceToHost, st);
     if (h == hipSuccess) h = hipStreamSynchronize(st);
     if (h != hipSuccess) s = fail(ctx, AERL_EDEVICE, "fitness copy failed: %s", hipGetErrorString(h));
   }
@@ -454,8 +511,7 @@ aerl_status aerl_random_pool(const aerl_evolve_cfg *cfg, int32_t nf, int32_t nc,
   if (s) return s;
   if (!rng_state) return AERL_EINVAL;
   Rng r{*rng_state};
-  const std::vector<Set> pool = random_pool(r, *cfg, Ranges{nf, nc, lo, hi});
-  s = write_out(pool, *cfg, out);
+  s = write_out(random_pool(r, *cfg, Ranges{nf, nc, lo, hi}), out);
   if (s == AERL_OK) *rng_state = r.s;
   return s;
 }
@@ -469,16 +525,14 @@ aerl_status aerl_breed(const aerl_population *pool, const int32_t *fitness, cons
   int32_t nr = 0, nk = 0;
   s = validate_population(nullptr, pool, nf, nc, &nr, &nk);
   if (s) return s;
-  if (pool->n_sets != cfg->pool || check_kinds(nullptr, *pool, nk)) return AERL_EINVAL;
-  const std::vector<Set> in = from_view(*pool);
-  for (const Set &st : in) {
-    if (st.rules.empty() || (int32_t)st.rules.size() > cfg->max_rules) return AERL_EINVAL;
-    for (const Rule &u : st.rules)
-      if (u.conds.empty() || (int32_t)u.conds.size() > cfg->max_conds) return AERL_EINVAL;
-  }
+  if (pool->n_sets != cfg->pool || check_kinds(nullptr, *pool, nk) || !within_limits(*pool, *cfg))
+    return AERL_EINVAL;
+  const Soa in = from_view(*pool);
   Rng r{*rng_state};
-  const std::vector<Set> next = breed(r, in, fitness, *cfg, Ranges{nf, nc, lo, hi});
-  s = write_out(next, *cfg, out);
+  Soa next;
+  Child scratch;
+  breed(r, in, fitness, *cfg, Ranges{nf, nc, lo, hi}, next, scratch);
+  s = write_out(next, out);
   if (s == AERL_OK) *rng_state = r.s;
   return s;
 }
@@ -520,14 +574,10 @@ aerl_status aerl_evolve_create(aerl_ctx *ctx, int32_t dataset_id, const aerl_evo
     if (s) return s;
     if (initial->n_sets != cfg->pool)
       return fail(ctx, AERL_EINVAL, "initial population has %d rule sets, the pool %d", initial->n_sets, cfg->pool);
+    if (!within_limits(*initial, *cfg))
+      return fail(ctx, AERL_EINVAL,
+                  "initial rule sets need 1..max_rules rules of 1..max_conds conditions");
     e->pool = from_view(*initial);
-    for (const Set &st : e->pool) {
-      if (st.rules.empty() || (int32_t)st.rules.size() > cfg->max_rules)
-        return fail(ctx, AERL_EINVAL, "initial rule sets need 1..max_rules rules");
-      for (const Rule &u : st.rules)
-        if (u.conds.empty() || (int32_t)u.conds.size() > cfg->max_conds)
-          return fail(ctx, AERL_EINVAL, "initial rules need 1..max_conds conditions");
-    }
   } else {
     e->pool = random_pool(e->rng, *cfg, Ranges{nf, nc, e->lo.data(), e->hi.data()});
   }
@@ -554,7 +604,9 @@ aerl_status aerl_evolve_run(aerl_ctx *ctx, int32_t evo_id, int32_t generations, 
   AERL_HIP(ctx, hipSetDevice(ctx->device));
   for (int32_t g = 0; g < generations; ++g) {
     const auto t0 = std::chrono::steady_clock::now();
-    e.pool = breed(e.rng, e.pool, e.fitness.data(), e.cfg, Ranges{e.nf, e.nc, e.lo.data(), e.hi.data()});
+    breed(e.rng, e.pool, e.fitness.data(), e.cfg, Ranges{e.nf, e.nc, e.lo.data(), e.hi.data()}, e.next,
+          e.scratch);
+    std::swap(e.pool, e.next);
     e.sec_breed += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     aerl_status s = evaluate(ctx, e, stream);
     if (s) return s;
@@ -572,7 +624,7 @@ aerl_status aerl_evolve_state(aerl_ctx *ctx, int32_t evo_id, aerl_evolve_info *o
   const Evo &e = *it->second;
   std::memset(out, 0, sizeof *out);
   out->generation = e.generation;
-  out->pool = e.soa.view();
+  out->pool = e.pool.view();
   out->fitness = e.fitness.data();
   const bool tuned = e.cfg.tune_epochs > 0;
   out->tuned_coef = tuned ? e.tuned[0].data() : nullptr;
@@ -601,7 +653,7 @@ aerl_status aerl_evolve_save(aerl_ctx *ctx, int32_t evo_id, const char *path) {
   o.write(reinterpret_cast<const char *>(&e.rng.s), 8);
   put(o, e.lo);
   put(o, e.hi);
-  const Soa &a = e.soa;
+  const Soa &a = e.pool;
   put(o, a.set_rule_off); put(o, a.set_default); put(o, a.rule_cond_off); put(o, a.rule_class);
   put(o, a.op); put(o, a.kind); put(o, a.f); put(o, a.g);
   put(o, a.coef); put(o, a.coef2); put(o, a.theta);
@@ -650,10 +702,10 @@ aerl_status aerl_evolve_load(aerl_ctx *ctx, int32_t dataset_id, const char *path
       a.f.size() != a.op.size() || a.g.size() != a.op.size() || a.kind.size() != a.op.size() ||
       a.coef.size() != a.op.size() || a.coef2.size() != a.op.size() || a.theta.size() != a.op.size() ||
       validate_population(ctx, &v, e->nf, e->nc, &nr, &nk) != AERL_OK ||
-      (size_t)nr != a.rule_class.size() || (size_t)nk != a.op.size())
+      (size_t)nr != a.rule_class.size() || (size_t)nk != a.op.size() ||
+      check_kinds(ctx, v, nk) != AERL_OK || !within_limits(v, e->cfg))
     return fail(ctx, AERL_EINVAL, "%s holds an invalid pool", path);
   e->pool = from_view(v);
-  e->soa = std::move(a);
   s = attach(ctx, *e, dataset_id, arena, arena_bytes);
   if (s) return s;
   const int32_t id = ctx->next_id++;

@@ -152,6 +152,12 @@ PackedLayout packed_layout(int32_t n_sets, int32_t n_rules, int32_t n_conds) {
   return L;
 }
 
+// Host threads available (read once: the query reads a system file).
+unsigned host_threads() {
+  static const unsigned n = std::max(1u, std::thread::hardware_concurrency());
+  return n;
+}
+
 // Runs fn(i) for i in [0, n) on up to n host threads (i = 0 on the caller).
 template <class F>
 void run_parts(int n, const F &fn) {
@@ -230,7 +236,7 @@ aerl_status validate_population(aerl_ctx *ctx, const aerl_population *p, int32_t
   // offending index and its message) only when some part finds a fault
   bool fast_ok = false;
   if (n_conds > 0 && p->g && p->coef2 && p->theta) {
-    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const unsigned hw = host_threads();
     const int parts = (int)std::min<int64_t>(std::min(hw, 8u), (int64_t)n_conds / 32768 + 1);
     std::vector<char> part_ok(parts, 0);
     run_parts(parts, [&](int i) {
@@ -459,7 +465,7 @@ void pack_population_image(const aerl_population *p, int32_t nf, int32_t nc, int
   zero_tail(L.heads_off + sizeof(uint4) * (size_t)n_rec, L.cmask_off);
   zero_tail(L.cmask_off + sizeof(uint2) * (size_t)n_conds, L.total);
   // about 16k conditions per thread, at most 8 threads
-  const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+  const unsigned hw = host_threads();
   const int parts = (int)std::max<int64_t>(
       1, std::min<int64_t>({(int64_t)std::min(hw, 8u), (int64_t)n_conds / 16384 + 1,
                             (int64_t)std::max(p->n_sets, 1)}));

@@ -621,12 +621,16 @@ def _pool_arrays(pop):
 
 @pytest.mark.parametrize("nf,nc,kw", [(30, 2, {}), (1, 3, dict(ff_frac=1.0)),
                                       (6, 4, dict(max_rules=1, max_conds=1, elite=0)),
-                                      (9, 2, dict(p_crossover=1.0, p_struct=1.0, tournament=1))])
+                                      (9, 2, dict(p_crossover=1.0, p_struct=1.0, tournament=1)),
+                                      (5, 3, dict(max_rules=3, max_conds=2, p_struct=1.0,
+                                                  p_crossover=0.8, p_coef=0.5))])
 def test_breeding_matches_the_reference_bit_for_bit(aerl, nf, nc, kw):
     """The library's host-side random pool and next generation (SplitMix64
     draws, tournament selection, crossover, coefficient and structure
-    mutation) against oracle/evolve.py over eight generations of arbitrary
-    fitness: identical pools, float bits included, and random states."""
+    mutation) against oracle/evolve.py over twenty generations of arbitrary
+    fitness: identical pools, float bits included, and random states (one
+    case keeps rule sets at their rule and condition caps, so that every
+    structural change meets its limit)."""
     from oracle import evolve as ev
     from paper_2406_01821_amd.population import from_rule_lists
     c = dict(pool=24, tournament=3, elite=2, max_rules=6, max_conds=4, ff_frac=0.3,
@@ -639,7 +643,7 @@ def test_breeding_matches_the_reference_bit_for_bit(aerl, nf, nc, kw):
     pop, state = aerl.random_pool(cfg, nf, nc, lo, hi, 11)
     r = ev.SplitMix64(11)
     ref = ev.random_pool(r, c, nf, nc, lo, hi)
-    for gen in range(8):
+    for gen in range(20):
         want = from_rule_lists(ev.to_rule_lists(ref))
         for a, b in zip(_pool_arrays(pop), _pool_arrays(want)):
             np.testing.assert_array_equal(a, b)
