@@ -102,6 +102,29 @@ def test_checkpoint_resumes_exactly(ctx, table, tmp_path):
     np.testing.assert_array_equal(a["fitness"], b["fitness"])
 
 
+def test_checkpoint_beyond_its_limits_is_refused(ctx, table, tmp_path):
+    """A checkpoint whose pool breaks its own configuration's limits (here
+    max_rules lowered to 1 in the file) is refused when loaded: the run's
+    device arena is sized from those limits."""
+    from paper_2406_01821_amd.aerl import AerlError, AERL_EINVAL, aerl_evolve_cfg, evolve_cfg
+    w, ds, lo, hi = table
+    cfg = evolve_cfg(**dict(CFG, pool=20), seed=12)
+    run = ctx.evolve(ds, cfg, lo, hi)
+    path = os.path.join(str(tmp_path), "run.ckpt")
+    run.save(path)
+    assert int(np.diff(run.state()["pool"].set_rule_off).max()) > 1
+    run.release()
+    raw = bytearray(open(path, "rb").read())
+    off = 8 + aerl_evolve_cfg.max_rules.offset  # after the 8-byte magic
+    assert int.from_bytes(raw[off:off + 4], "little") == CFG["max_rules"]
+    raw[off:off + 4] = (1).to_bytes(4, "little")
+    with open(path, "wb") as fh:
+        fh.write(raw)
+    with pytest.raises(AerlError) as e:
+        ctx.evolve_load(ds, path, cfg)
+    assert e.value.status == AERL_EINVAL
+
+
 def test_given_initial_pool_and_refusals(ctx, table):
     from paper_2406_01821_amd.aerl import AerlError, AERL_EINVAL, evolve_cfg
     w, ds, lo, hi = table
