@@ -760,7 +760,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--only-hard", action="store_true", help="time the hard path only")
-    ap.add_argument("--only", default=None, help="one extra section alone: c1, finetune, evolve, softmax, categorical, soft, serve")
+    ap.add_argument("--only", default=None, help="one extra section alone: c1, finetune, evolve, softmax, categorical, soft, serve, ragged")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run only a plain 256 MiB device copy (calibrates HBM byte counters)")
     ap.add_argument("--trace-summary", default=None, metavar="CSV",
@@ -800,7 +800,8 @@ def main():
               "softmax": lambda: bench_softmax(ctx, max(3, args.steps // 4), 1),
               "categorical": lambda: bench_categorical(ctx, args.steps, args.warmup),
               "soft": lambda: bench_soft(ctx, max(3, args.steps // 4), 1, not args.no_cpu),
-              "serve": lambda: bench_serve_alone(ctx)}
+              "serve": lambda: bench_serve_alone(ctx),
+              "ragged": lambda: bench_ragged(ctx, max(3, args.steps // 4), 1)}
         print(json.dumps({args.only: fn[args.only]()}), flush=True)
         ctx.close()
         return
