@@ -386,6 +386,8 @@ def bench_softmax(ctx, steps, warmup, beta=2.0):
     wsb = ctx.soft_workspace(ds, pop, True)
     dl = torch.ones(w.pop.n_sets, device=ctx.device)
     stream = torch.cuda.current_stream()
+    trans_weight(ctx)  # the rate probe, run first: it also brings a cold GPU to speed
+    warmup = max(warmup, 3)
     fwd_ms, _ = timed(lambda: ctx.softmax_forward(ds, pop, c1, c2, th, beta, ws=wsf), steps, warmup,
                       stream)
     bwd_ms, _ = timed(lambda: ctx.softmax_backward(ds, pop, c1, c2, th, beta, dl, ws=wsb), steps,
@@ -452,6 +454,8 @@ def bench_soft(ctx, steps, warmup, cpu):
     wsb = ctx.soft_workspace(ds, pop, True)
     dl = torch.ones(w.pop.n_sets, device=dev)
     stream = torch.cuda.current_stream()
+    trans_weight(ctx)  # the rate probe, run first: it also brings a cold GPU to speed
+    warmup = max(warmup, 3)
     fwd_ms, _ = timed(lambda: ctx.soft_forward(ds, pop, c1, c2, th, ws=wsf), steps, warmup, stream)
     bwd_ms, _ = timed(lambda: ctx.soft_backward(ds, pop, c1, c2, th, dl, ws=wsb), steps, warmup,
                       stream)

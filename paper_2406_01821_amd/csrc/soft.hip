@@ -845,15 +845,39 @@ int64_t count_groups(const DatasetRec &ds, int tg) {
   return g;
 }
 
-constexpr int64_t kMaxGroups = 64;
+// Tiles per block group.  A launch has (set chunks) x (tile groups) blocks;
+// the fewest groups that still give about `target` blocks (measured on the
+// 262,144 x 32, 1024-set workload: a forward grid of one wave of blocks,
+// 64 groups, runs 10.9 ms, 1024 groups 6.9 ms, as its blocks no longer stage
+// their tiles in step; the adjoint runs 22.8 ms at 64 groups and 20.8 ms at
+// 256), then fewer while the per-group partial sums (bytes_per_group each)
+// exceed max_bytes.
+int tiles_per_group(const DatasetRec &ds, int64_t chunks, int64_t target, size_t bytes_per_group,
+                    size_t max_bytes) {
+  int32_t widest = 1;
+  for (int c = 0; c < ds.nc; ++c) widest = std::max(widest, ds.region_tiles[c]);
+  const int64_t need = (target + std::max<int64_t>(chunks, 1) - 1) / std::max<int64_t>(chunks, 1);
+  int tg = 1;
+  while (tg < widest && count_groups(ds, 2 * tg) >= need) tg *= 2;
+  while (tg < widest && (size_t)count_groups(ds, tg) * bytes_per_group > max_bytes) tg *= 2;
+  return tg;
+}
+// Forward: 16 blocks per block slot (four 512-thread blocks per CU on 256
+// CUs), fp64 partials of at most 8 MiB (half the no-allocation scratch).
+constexpr int64_t kFwdTargetBlocks = 16384;
+constexpr size_t kFwdPartMax = (size_t)8 << 20;
+// Backward: 8 blocks per slot (two 1024-thread blocks per CU), partial
+// gradients of at most 1 GiB.
+constexpr int64_t kBwdTargetBlocks = 4096;
+constexpr size_t kBwdPartMax = (size_t)1 << 30;
 
 SoftPlan plan_forward(const DatasetRec &ds, const PopRec &pop) {
   SoftPlan p{};
   p.S = 4;
   while (p.S > 1 && (size_t)ds.nf * 256 * p.S > 64 * 1024) p.S >>= 1;
   p.Q = std::max(1, std::min(pop.n_sets, 64));
-  p.TG = 1;
-  while (count_groups(ds, p.TG) > kMaxGroups) p.TG *= 2;
+  p.TG = tiles_per_group(ds, (pop.n_sets + p.Q - 1) / p.Q, kFwdTargetBlocks,
+                         (size_t)std::max(pop.n_sets, 1) * sizeof(double), kFwdPartMax);
   p.n_groups = (int)count_groups(ds, p.TG);
   p.lds = (size_t)ds.nf * 64 * p.S * 4 + (size_t)p.Q * 8;
   return p;
@@ -866,8 +890,8 @@ SoftPlan plan_backward(const DatasetRec &ds, const PopRec &pop) {
   SoftPlan p{};
   const int R = std::max(pop.max_rules, 1);
   const size_t per_set = (size_t)std::max(pop.max_set_conds, 1) * 2 * 4;
-  p.TG = 1;
-  while (count_groups(ds, p.TG) > kMaxGroups) p.TG *= 2;
+  p.TG = tiles_per_group(ds, (pop.n_sets + 63) / 64, kBwdTargetBlocks,
+                         (size_t)std::max(pop.n_conds, 1) * 2 * sizeof(float), kBwdPartMax);
   p.n_groups = (int)count_groups(ds, p.TG);
   p.rmax = R <= 8 ? 8 : R <= 16 ? 16 : R <= 32 ? 32 : 0;
   if (p.rmax > 0) {
@@ -1496,8 +1520,8 @@ SoftPlan plan_smax_backward(const DatasetRec &ds, const PopRec &pop) {
   SoftPlan p{};
   const int R = std::max(pop.max_rules, 1);
   const size_t per_set = (size_t)std::max(pop.max_set_conds, 1) * 2 * 4;
-  p.TG = 1;
-  while (count_groups(ds, p.TG) > kMaxGroups) p.TG *= 2;
+  p.TG = tiles_per_group(ds, (pop.n_sets + 63) / 64, kBwdTargetBlocks,
+                         (size_t)std::max(pop.n_conds, 1) * 2 * sizeof(float), kBwdPartMax);
   p.n_groups = (int)count_groups(ds, p.TG);
   // up to 16 rules and four classes on at most 64 features: four samples per
   // lane with the per-rule state in per-lane memory, two blocks per CU

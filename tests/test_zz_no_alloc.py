@@ -56,9 +56,10 @@ def test_noalloc_matches_the_workspace_entry_twice(ctx):
 def test_noalloc_refuses_what_does_not_fit(ctx):
     import torch
     from paper_2406_01821_amd.aerl import AerlError, AERL_ENOMEM, AERL_NOALLOC_SCRATCH_BYTES
-    # 70,000 conditions: 1.1 MB of records plus 64 groups x 70,000 sets of
-    # fp64 partials, far past the scratch array
-    w = synth.soft_workload(13, n=1 << 15, nf=8, n_sets=70_000, n_rules=1, n_conds=1)
+    # 600,000 one-condition rule sets: 9.6 MB of condition records plus at
+    # least one group of fp64 partials per class region (2 x 600,000 x 8 B),
+    # past the 16 MiB scratch array
+    w = synth.soft_workload(13, n=1 << 15, nf=8, n_sets=600_000, n_rules=1, n_conds=1)
     ds = ctx.upload_dataset(w.data)
     p = ctx.pack_population(w.pop, 8, 2)
     assert ctx.soft_workspace(ds, p, False).numel() > AERL_NOALLOC_SCRATCH_BYTES
