@@ -466,13 +466,27 @@ __global__ __launch_bounds__(kSoftBlock) void k_soft_fwd(const SoftArgs a) {
     a.part_loss[(int64_t)blockIdx.y * a.n_sets + q0 + i] = acc[i];
 }
 
-__global__ void k_soft_fwd_final(const double *__restrict__ part, int32_t n_groups, int32_t n_sets,
-                                 int64_t n, float *__restrict__ loss) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n_sets) return;
+// Mean loss per rule set from the per-group partial sums: block b takes
+// sets 64b .. 64b+63 (lane: set, so a wave reads 512 contiguous bytes per
+// group), wave w the groups w, w+16, ...; the 16 wave sums are then added
+// in wave order (a fixed order: the result does not depend on timing).
+constexpr int kFwdFinalWaves = 16;
+__global__ __launch_bounds__(kFwdFinalWaves * 64) void k_soft_fwd_final(
+    const double *__restrict__ part, int32_t n_groups, int32_t n_sets, int64_t n,
+    float *__restrict__ loss) {
+  __shared__ double acc[kFwdFinalWaves][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int p = blockIdx.x * 64 + lane;
   double s = 0.0;
-  for (int g = 0; g < n_groups; ++g) s += part[(int64_t)g * n_sets + p];
-  loss[p] = n > 0 ? (float)(s / (double)n) : 0.0f;
+  if (p < n_sets)
+    for (int g = w; g < n_groups; g += kFwdFinalWaves) s += part[(int64_t)g * n_sets + p];
+  acc[w][lane] = s;
+  __syncthreads();
+  if (w == 0 && p < n_sets) {
+    double t = 0.0;
+    for (int k = 0; k < kFwdFinalWaves; ++k) t += acc[k][lane];
+    loss[p] = n > 0 ? (float)(t / (double)n) : 0.0f;
+  }
 }
 
 // ----------------------------------------------------------------- backward
@@ -804,8 +818,21 @@ __global__ void k_soft_bwd_final(const float *__restrict__ part, int32_t n_group
   const double scale = n > 0 ? (double)dloss[p] / (double)n : 0.0;
   for (int i = threadIdx.x; i < ss.w; i += blockDim.x) {
     const int j = ss.z + i;
+    // groups in order, eight loads in flight at a time
     double g0 = 0.0, g1 = 0.0;
-    for (int g = 0; g < n_groups; ++g) {
+    int g = 0;
+    for (; g + 8 <= n_groups; g += 8) {
+      float2 v[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        v[k] = *reinterpret_cast<const float2 *>(part + ((int64_t)(g + k) * n_conds + j) * 2);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        g0 += (double)v[k].x;
+        g1 += (double)v[k].y;
+      }
+    }
+    for (; g < n_groups; ++g) {
       const float *pp = part + ((int64_t)g * n_conds + j) * 2;
       g0 += (double)pp[0];
       g1 += (double)pp[1];
@@ -1031,7 +1058,8 @@ hipError_t launch_soft_forward(const SoftLaunch &l, hipStream_t st) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_soft_fwd_final, dim3((unsigned)((pop.n_sets + 255) / 256)), dim3(256), 0, st,
+  hipLaunchKernelGGL(k_soft_fwd_final, dim3((unsigned)((pop.n_sets + 63) / 64)),
+                     dim3(kFwdFinalWaves * 64), 0, st,
                      a.part_loss, p.n_groups, pop.n_sets, l.ds->n, l.loss);
   return hipGetLastError();
 }
@@ -1620,7 +1648,8 @@ hipError_t launch_smax_forward(const SoftLaunch &l, float beta, hipStream_t st) 
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_soft_fwd_final, dim3((unsigned)((pop.n_sets + 255) / 256)), dim3(256), 0, st,
+  hipLaunchKernelGGL(k_soft_fwd_final, dim3((unsigned)((pop.n_sets + 63) / 64)),
+                     dim3(kFwdFinalWaves * 64), 0, st,
                      a.part_loss, p.n_groups, pop.n_sets, l.ds->n, l.loss);
   return hipGetLastError();
 }
