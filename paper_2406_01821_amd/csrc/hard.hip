@@ -127,21 +127,34 @@ __global__ __launch_bounds__(kReduceBlock) void k_hard_reduce(
       if (c == label) atomicAdd(&correct[p], v);
     }
   };
-  for (int64_t t = t0; t < t1; ++t) {
-    const int info = ldc(tile_info, t);
-    if ((info & 0xff) != label) {
-      emit();
-      label = info & 0xff;
-      c0 = c1 = c2 = n = 0;
+  // tiles in order, the words of eight requested before they are used
+  constexpr int kBatch = 8;
+  for (int64_t tb = t0; tb < t1; tb += kBatch) {
+    uint32_t lo[kBatch], hi[kBatch];
+#pragma unroll
+    for (int k = 0; k < kBatch; ++k) {
+      const int64_t t = min(tb + k, t1 - 1);  // past the slice: its last tile again, unused
+      const uint32_t *row = part + t * stride + w;
+      lo[k] = row[0];
+      hi[k] = row[w2];
     }
-    // the set's fields from bit 0 on, ten bits each (those past its ncc
-    // are not used)
-    const uint32_t *row = part + t * stride + w;
-    const uint64_t v = ((uint64_t)row[w2] << 30 | row[0]) >> b;
-    c0 += (int32_t)(v & 1023u);
-    if (ncc > 1) c1 += (int32_t)(v >> 10 & 1023u);
-    if (ncc > 2) c2 += (int32_t)(v >> 20 & 1023u);
-    n += info >> 8;
+#pragma unroll
+    for (int k = 0; k < kBatch; ++k) {
+      if (tb + k >= t1) break;
+      const int info = ldc(tile_info, tb + k);
+      if ((info & 0xff) != label) {
+        emit();
+        label = info & 0xff;
+        c0 = c1 = c2 = n = 0;
+      }
+      // the set's fields from bit 0 on, ten bits each (those past its ncc
+      // are not used)
+      const uint64_t v = ((uint64_t)hi[k] << 30 | lo[k]) >> b;
+      c0 += (int32_t)(v & 1023u);
+      if (ncc > 1) c1 += (int32_t)(v >> 10 & 1023u);
+      if (ncc > 2) c2 += (int32_t)(v >> 20 & 1023u);
+      n += info >> 8;
+    }
   }
   emit();
 }
