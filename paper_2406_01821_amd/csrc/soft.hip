@@ -196,6 +196,27 @@ __device__ __forceinline__ float wave_total_last(float v) {
   return v;
 }
 
+// Wave totals of four values at once, each ending in lane 15 of one row:
+// row 0 the total of a0, row 1 of b0, row 2 of a1, row 3 of b1.  The
+// half-wave swaps pair lane l with l + 32 (a0 with a1, b0 with b1 in the two
+// halves), then rows with the row 16 lanes on; an inclusive scan in each
+// row finishes.  A fixed order, so bit-identical from run to run.
+__device__ __forceinline__ float wave_totals4(float a0, float a1, float b0, float b1) {
+  const auto sa = __builtin_amdgcn_permlane32_swap(__float_as_uint(a0), __float_as_uint(a1), false, false);
+  const auto sb = __builtin_amdgcn_permlane32_swap(__float_as_uint(b0), __float_as_uint(b1), false, false);
+  // lanes 0-31: a0 (b0) over lanes l and l + 32; lanes 32-63: a1 (b1)
+  const float pa = __uint_as_float(sa[0]) + __uint_as_float(sa[1]);
+  const float pb = __uint_as_float(sb[0]) + __uint_as_float(sb[1]);
+  const auto sr = __builtin_amdgcn_permlane16_swap(__float_as_uint(pa), __float_as_uint(pb), false, false);
+  // rows 0 and 2: pa over a row and the next; rows 1 and 3: pb
+  float v = __uint_as_float(sr[0]) + __uint_as_float(sr[1]);
+  v = dpp_add<0x111, 0xf>(v);
+  v = dpp_add<0x112, 0xf>(v);
+  v = dpp_add<0x114, 0xf>(v);
+  v = dpp_add<0x118, 0xf>(v);
+  return v;
+}
+
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
@@ -640,10 +661,6 @@ constexpr int kBwdRegBlock = 1024;
 #define AERL_BWD_SGPR_CAP __attribute__((amdgpu_num_sgpr(80)))
 
 // TONLY: the population has threshold conditions only (no x[g] rows).
-// Rule sets of at most 64 conditions keep the wave totals of the current
-// walk in two VGPRs (lane i: condition i of the set) and add them to the
-// block accumulators once per walk; longer
-// rule sets add each condition's totals as they come.
 template <int S, int RMAX, class Acc, bool TONLY>
 __device__ __forceinline__ void soft_bwd_reg(const SoftArgs &a) {
   constexpr int TS = 64 * S, WPT = AERL_TILE / TS;
@@ -718,8 +735,6 @@ __device__ __forceinline__ void soft_bwd_reg(const SoftArgs &a) {
         U[s] = dflt == label ? 0.0f : kNegInf;
       }
       // reverse sweep
-      const bool few = ss.w <= 64;
-      int tot0 = 0, tot1 = 0;
       for (int k = ss.y - 1; k >= 0; --k) {
         const int4 r = ldc(a.rules, ss.x + k);
         const bool hit = r.z == label;
@@ -736,36 +751,37 @@ __device__ __forceinline__ void soft_bwd_reg(const SoftArgs &a) {
           }
         }
         Acc ra[S];
-        for (int j = r.x; j < r.x + r.y; ++j) {
-          float z[S], xf[S], xg[S];
-          if constexpr (TONLY) {
-            cond_z_t<S>(a, xs, lane, j, z, xf, xg);
-          } else {
-            bool ff;
-            cond_z<S>(a, xs, lane, j, z, xf, xg, ff);
-          }
-          float g0 = 0.0f, g1 = 0.0f;
+        // conditions two at a time: their four sums over the wave in one
+        // reduction (wave_totals4), added to the block accumulators by the
+        // lane that holds each (one writer per rule set and tile: the order
+        // of these adds is fixed)
+        for (int j0 = r.x; j0 < r.x + r.y; j0 += 2) {
+          float g0[2] = {0.0f, 0.0f}, g1[2] = {0.0f, 0.0f};
 #pragma unroll
-          for (int s = 0; s < S; ++s) {
-            const float t = ra[s].add(z[s]);
-            // dL/dz = dL/da_k * sigmoid(-z)
-            const float dz = mul[s] * acc_sig_neg(ra[s], pre[s], z[s], t);
-            g0 = fmaf(dz, xg[s], g0);
-            g1 = fmaf(dz, xf[s], g1);
+          for (int c = 0; c < 2; ++c) {
+            const int j = j0 + c;
+            if (j >= r.x + r.y) break;
+            float z[S], xf[S], xg[S];
+            if constexpr (TONLY) {
+              cond_z_t<S>(a, xs, lane, j, z, xf, xg);
+            } else {
+              bool ff;
+              cond_z<S>(a, xs, lane, j, z, xf, xg, ff);
+            }
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+              const float t = ra[s].add(z[s]);
+              // dL/dz = dL/da_k * sigmoid(-z)
+              const float dz = mul[s] * acc_sig_neg(ra[s], pre[s], z[s], t);
+              g0[c] = fmaf(dz, xg[s], g0[c]);
+              g1[c] = fmaf(dz, xf[s], g1[c]);
+            }
           }
-          g0 = wave_total_last(g0);
-          g1 = wave_total_last(g1);
-          if (few) {
-            const int v0 = __builtin_amdgcn_readlane(__float_as_int(g0), 63);
-            const int v1 = __builtin_amdgcn_readlane(__float_as_int(g1), 63);
-            const bool mine = lane == j - ss.z;
-            tot0 = mine ? v0 : tot0;
-            tot1 = mine ? v1 : tot1;
-          } else if (lane == 63) {
-            // one writer per (rule set, tile): the order of these adds is fixed
-            float *ap = acc + ((size_t)q * a.max_set_conds + (j - ss.z)) * 2;
-            ap[0] += g0;
-            ap[1] += g1;
+          const float tot = wave_totals4(g0[0], g0[1], g1[0], g1[1]);
+          const int row = lane >> 4, c = row >> 1;
+          if ((lane & 15) == 15 && j0 + c < r.x + r.y) {
+            float *ap = acc + ((size_t)q * a.max_set_conds + (j0 + c - ss.z)) * 2 + (row & 1);
+            *ap += tot;
           }
         }
 #pragma unroll
@@ -774,13 +790,6 @@ __device__ __forceinline__ void soft_bwd_reg(const SoftArgs &a) {
           acc_finish(ra[s], a2, b2);
           U[s] = lse(hit ? a2 : kNegInf, b2 + U[s]);
         }
-      }
-      if (few && lane < ss.w) {
-        // every condition of the set was visited once: lane i holds the
-        // totals of condition i; one writer per (rule set, tile)
-        float *ap = acc + ((size_t)q * a.max_set_conds + lane) * 2;
-        ap[0] += __int_as_float(tot0);
-        ap[1] += __int_as_float(tot1);
       }
     }
   }
@@ -1428,8 +1437,6 @@ __global__ __launch_bounds__(kBwdRegBlock, 8) AERL_BWD_SGPR_CAP void k_smax_bwd_
         tail[s] = 0.0f;
       }
       // reverse sweep with the suffix of log2(1 - r_i) after k
-      const bool few = ss.w <= 64;
-      int tot0 = 0, tot1 = 0;
       for (int k = ss.y - 1; k >= 0; --k) {
         const int4 r = ldc(a.rules, ss.x + k);
         float la[S], lp[S], drk[S];
@@ -1442,36 +1449,37 @@ __global__ __launch_bounds__(kBwdRegBlock, 8) AERL_BWD_SGPR_CAP void k_smax_bwd_
                                : pick(gv[s], r.z) - gd[s] * fexp2(oth);
         }
         Acc ra[S];
-        for (int j = r.x; j < r.x + r.y; ++j) {
-          float z[S], xf[S], xg[S];
-          if constexpr (TONLY) {
-            cond_z_t<S>(a, xs, lane, j, z, xf, xg);
-          } else {
-            bool ff;
-            cond_z<S>(a, xs, lane, j, z, xf, xg, ff);
-          }
-          float g0 = 0.0f, g1 = 0.0f;
+        // conditions two at a time: their four sums over the wave in one
+        // reduction (wave_totals4), added to the block accumulators by the
+        // lane that holds each (one writer per rule set and tile: the order
+        // of these adds is fixed)
+        for (int j0 = r.x; j0 < r.x + r.y; j0 += 2) {
+          float g0[2] = {0.0f, 0.0f}, g1[2] = {0.0f, 0.0f};
 #pragma unroll
-          for (int s = 0; s < S; ++s) {
-            const float t = ra[s].add(z[s]);
-            // dL/dz = dL/dr_k * r_k * sigmoid(-z)
-            const float dz = drk[s] * acc_sig_neg(ra[s], la[s], z[s], t);
-            g0 = fmaf(dz, xg[s], g0);
-            g1 = fmaf(dz, xf[s], g1);
+          for (int c = 0; c < 2; ++c) {
+            const int j = j0 + c;
+            if (j >= r.x + r.y) break;
+            float z[S], xf[S], xg[S];
+            if constexpr (TONLY) {
+              cond_z_t<S>(a, xs, lane, j, z, xf, xg);
+            } else {
+              bool ff;
+              cond_z<S>(a, xs, lane, j, z, xf, xg, ff);
+            }
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+              const float t = ra[s].add(z[s]);
+              // dL/dz = dL/dr_k * r_k * sigmoid(-z)
+              const float dz = drk[s] * acc_sig_neg(ra[s], la[s], z[s], t);
+              g0[c] = fmaf(dz, xg[s], g0[c]);
+              g1[c] = fmaf(dz, xf[s], g1[c]);
+            }
           }
-          g0 = wave_total_last(g0);
-          g1 = wave_total_last(g1);
-          if (few) {
-            const int v0 = __builtin_amdgcn_readlane(__float_as_int(g0), 63);
-            const int v1 = __builtin_amdgcn_readlane(__float_as_int(g1), 63);
-            const bool mine = lane == j - ss.z;
-            tot0 = mine ? v0 : tot0;
-            tot1 = mine ? v1 : tot1;
-          } else if (lane == 63) {
-            // one writer per (rule set, tile): the order of these adds is fixed
-            float *ap = acc + ((size_t)q * a.max_set_conds + (j - ss.z)) * 2;
-            ap[0] += g0;
-            ap[1] += g1;
+          const float tot = wave_totals4(g0[0], g0[1], g1[0], g1[1]);
+          const int row = lane >> 4, c = row >> 1;
+          if ((lane & 15) == 15 && j0 + c < r.x + r.y) {
+            float *ap = acc + ((size_t)q * a.max_set_conds + (j0 + c - ss.z)) * 2 + (row & 1);
+            *ap += tot;
           }
         }
 #pragma unroll
@@ -1480,11 +1488,6 @@ __global__ __launch_bounds__(kBwdRegBlock, 8) AERL_BWD_SGPR_CAP void k_smax_bwd_
           acc_finish(ra[s], a2, b2);
           tail[s] += b2;
         }
-      }
-      if (few && lane < ss.w) {
-        float *ap = acc + ((size_t)q * a.max_set_conds + lane) * 2;
-        ap[0] += __int_as_float(tot0);
-        ap[1] += __int_as_float(tot1);
       }
     }
   }
