@@ -146,12 +146,16 @@ __device__ __forceinline__ float min0(float v) {
 
 struct RuleProd {
   float m = 0.0f, pt = 0.0f;  // m = M in bits, pt = p * 2^64
+  // returns 1 + u, rounded once
   __device__ __forceinline__ float add(float z2) {
     const float ut = fexp2(64.0f - fabsf(z2));  // u * 2^64
-    const float u = ut * 0x1p-64f;
-    pt = fmaf(pt, u, pt + ut);
+    const float w = fmaf(ut, 0x1p-64f, 1.0f);
+    // p' = p (1 + u) + u: rounding 1 + u first moves the product by at most
+    // one rounding of it (a term of p' that is at least p), so p' keeps the
+    // accuracy of two roundings while sharing 1 + u with the sigmoid
+    pt = fmaf(pt, w, ut);
     m -= min0(z2);  // m += max(-z2, 0), the same value bit for bit
-    return u;
+    return w;
   }
 };
 // log2(x * 2^-64) for x >= 0, from the exact exponent and the mantissa, so
@@ -172,8 +176,8 @@ __device__ __forceinline__ void acc_finish(const RuleProd &r, float &a2, float &
   b2 = a2 > -0x1p-60f ? log2_scaled64(fmaf(one_minus_exp2(-r.m), 0x1p64f, r.pt)) - l1p
                        : log1mexp2(a2);
 }
-__device__ __forceinline__ float acc_sig_neg(const RuleProd &, float pre, float z2, float u) {
-  return fexp2(pre - fmaxf(z2, 0.0f)) * frcp(1.0f + u);
+__device__ __forceinline__ float acc_sig_neg(const RuleProd &, float pre, float z2, float w) {
+  return fexp2(pre - fmaxf(z2, 0.0f)) * frcp(w);
 }
 
 // Loss of one sample in nats from log2 P_y.
@@ -705,7 +709,19 @@ __device__ __forceinline__ void soft_bwd_reg(const SoftArgs &a) {
       for (int k = 0; k < ss.y; ++k) {
         const int4 r = ldc(a.rules, ss.x + k);
         Acc ra[S];
-        for (int j = r.x; j < r.x + r.y; ++j) {
+        // conditions four at a time, then one at a time (same order)
+        int j = r.x;
+        const int je = r.x + r.y;
+        for (; j + 4 <= je; j += 4) {
+          float z[4][S];
+          cond_z4<S, TONLY>(a, xs, lane, j, z);
+#pragma unroll
+          for (int c4 = 0; c4 < 4; ++c4) {
+#pragma unroll
+            for (int s = 0; s < S; ++s) (void)ra[s].add(z[c4][s]);
+          }
+        }
+        for (; j < je; ++j) {
           float z[S];
           cond_z_only<S>(a, xs, lane, j, z);
 #pragma unroll
@@ -738,17 +754,17 @@ __device__ __forceinline__ void soft_bwd_reg(const SoftArgs &a) {
       for (int k = ss.y - 1; k >= 0; --k) {
         const int4 r = ldc(a.rules, ss.x + k);
         const bool hit = r.z == label;
-        float lk[S], pre[S], mul[S];
+        // dL/da_k = -(1 - 2^U) 2^pre for a rule of the label, +2^pre for
+        // another: log2 of its size goes into pre (-inf for a sample with no
+        // gradient) and its sign, the same for the whole wave, onto the sums.
+        // U, the log2 of a probability, can round to just above 0: 1 - 2^U
+        // is then taken as 0.
+        float lk[S], pre[S];
         l_get<0, RMAX, S>(L, k, lk);
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-          if (hit) {
-            pre[s] = lk[s] - logpy[s];
-            mul[s] = -one_minus_exp2(U[s]) * gate[s];
-          } else {
-            pre[s] = lk[s] + U[s] - logpy[s];
-            mul[s] = gate[s];
-          }
+          const float lm = hit ? log1mexp2(fminf(U[s], 0.0f)) : U[s];
+          pre[s] = gate[s] != 0.0f ? lk[s] + lm - logpy[s] : kNegInf;
         }
         Acc ra[S];
         // conditions two at a time: their four sums over the wave in one
@@ -756,7 +772,8 @@ __device__ __forceinline__ void soft_bwd_reg(const SoftArgs &a) {
         // lane that holds each (one writer per rule set and tile: the order
         // of these adds is fixed)
         for (int j0 = r.x; j0 < r.x + r.y; j0 += 2) {
-          float g0[2] = {0.0f, 0.0f}, g1[2] = {0.0f, 0.0f};
+          // sums start at -0, so that the first term is added exactly as is
+          float g0[2] = {-0.0f, -0.0f}, g1[2] = {-0.0f, -0.0f};
 #pragma unroll
           for (int c = 0; c < 2; ++c) {
             const int j = j0 + c;
@@ -771,8 +788,8 @@ __device__ __forceinline__ void soft_bwd_reg(const SoftArgs &a) {
 #pragma unroll
             for (int s = 0; s < S; ++s) {
               const float t = ra[s].add(z[s]);
-              // dL/dz = dL/da_k * sigmoid(-z)
-              const float dz = mul[s] * acc_sig_neg(ra[s], pre[s], z[s], t);
+              // |dL/dz| = |dL/da_k| * sigmoid(-z)
+              const float dz = acc_sig_neg(ra[s], pre[s], z[s], t);
               g0[c] = fmaf(dz, xg[s], g0[c]);
               g1[c] = fmaf(dz, xf[s], g1[c]);
             }
@@ -781,7 +798,7 @@ __device__ __forceinline__ void soft_bwd_reg(const SoftArgs &a) {
           const int row = lane >> 4, c = row >> 1;
           if ((lane & 15) == 15 && j0 + c < r.x + r.y) {
             float *ap = acc + ((size_t)q * a.max_set_conds + (j0 + c - ss.z)) * 2 + (row & 1);
-            *ap += tot;
+            *ap += hit ? -tot : tot;
           }
         }
 #pragma unroll
@@ -1400,7 +1417,19 @@ __global__ __launch_bounds__(kBwdRegBlock, 8) AERL_BWD_SGPR_CAP void k_smax_bwd_
       for (int k = 0; k < ss.y; ++k) {
         const int4 r = ldc(a.rules, ss.x + k);
         Acc ra[S];
-        for (int j = r.x; j < r.x + r.y; ++j) {
+        // conditions four at a time, then one at a time (same order)
+        int j = r.x;
+        const int je = r.x + r.y;
+        for (; j + 4 <= je; j += 4) {
+          float z[4][S];
+          cond_z4<S, TONLY>(a, xs, lane, j, z);
+#pragma unroll
+          for (int c4 = 0; c4 < 4; ++c4) {
+#pragma unroll
+            for (int s = 0; s < S; ++s) (void)ra[s].add(z[c4][s]);
+          }
+        }
+        for (; j < je; ++j) {
           float z[S];
           cond_z_only<S>(a, xs, lane, j, z);
 #pragma unroll
@@ -1454,7 +1483,8 @@ __global__ __launch_bounds__(kBwdRegBlock, 8) AERL_BWD_SGPR_CAP void k_smax_bwd_
         // lane that holds each (one writer per rule set and tile: the order
         // of these adds is fixed)
         for (int j0 = r.x; j0 < r.x + r.y; j0 += 2) {
-          float g0[2] = {0.0f, 0.0f}, g1[2] = {0.0f, 0.0f};
+          // sums start at -0, so that the first term is added exactly as is
+          float g0[2] = {-0.0f, -0.0f}, g1[2] = {-0.0f, -0.0f};
 #pragma unroll
           for (int c = 0; c < 2; ++c) {
             const int j = j0 + c;

@@ -53,7 +53,7 @@ def gpu_soft(ctx, data, pop, dloss=None):
 def check_loss(got, ref):
     err = np.abs(got - ref)
     bound = LOSS_RTOL * np.abs(ref) + LOSS_ATOL
-    bad = err > bound
+    bad = ~(err <= bound)  # a NaN counts as out of bounds
     assert not bad.any(), (np.nonzero(bad)[0], got[bad], ref[bad])
     if err.size:
         print(f"loss bound used: {float((err / bound).max()):.3f}")
@@ -72,7 +72,7 @@ def check_grad(got, ref):
             continue
         bound = GRAD_RTOL * np.maximum(np.abs(r), GRAD_FLOOR * scale)
         frac = np.abs(g - r) / bound
-        bad = frac > 1.0
+        bad = ~(frac <= 1.0)  # a NaN counts as out of bounds
         assert not bad.any(), (k, np.nonzero(bad)[0][:10], g[bad][:5], r[bad][:5], frac.max())
         used = max(used, float(frac.max()))
     print(f"gradient bound used: {used:.3f}")
@@ -220,6 +220,8 @@ def test_deterministic_repeats(ctx):
     dl = torch.ones(16, device=ctx.device)
     l0 = ctx.soft_forward(ds, p, c1, c2, th)
     g0 = ctx.soft_backward(ds, p, c1, c2, th, dl)
+    # every entry finite (a NaN would also fail the equalities below)
+    assert all(bool(torch.isfinite(a).all()) for a in g0)
     for _ in range(3):
         assert torch.equal(ctx.soft_forward(ds, p, c1, c2, th), l0)
         g = ctx.soft_backward(ds, p, c1, c2, th, dl)

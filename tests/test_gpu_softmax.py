@@ -33,7 +33,7 @@ def _params(pop, dev):
 def check_loss(got, ref):
     err = np.abs(got - ref)
     bound = 1e-5 * np.abs(ref) + 1e-6
-    bad = err > bound
+    bad = ~(err <= bound)  # a NaN counts as out of bounds
     assert not bad.any(), (np.nonzero(bad)[0], got[bad], ref[bad])
     if err.size:
         print(f"loss bound used: {float((err / bound).max()):.3f}")
