@@ -627,8 +627,9 @@ __global__ __launch_bounds__(kBwdWaves * 64) void k_soft_bwd(const SoftArgs a) {
 // vector caches) for RMAX = 16 with four samples per lane.  The reverse sweep
 // recomputes every condition once: the same exp/log gives the rule's a_k
 // and log(1 - r_k) for the U recurrence and log sigmoid(z) for the
-// gradient.  Per condition the S slots are summed in the lane, then over the
-// wave with DPP; lane 63 adds to the block's LDS accumulators (one writer per
+// gradient.  Per condition the S slots are summed in the lane; two
+// conditions' sums go over the wave in one reduction (wave_totals4), and the
+// lane that ends each adds it to the block's LDS accumulators (one writer per
 // rule set and tile).
 template <int K, int RMAX, int S>
 __device__ __forceinline__ void l_get(const float (&L)[RMAX][S], int k, float (&out)[S]) {
