@@ -73,6 +73,10 @@ struct RuleAcc {
     us += e_s;
     return lp;
   }
+  // add's return value for z2, without adding the condition
+  __device__ static __forceinline__ float term(float z2) {
+    return log2_1p_unit(fexp2(kShift2 - fabsf(z2)) * kExp2NegShift);
+  }
 };
 
 // 1 - 2^a for a <= 0 (bits).  Near 0 uses Kahan's form of expm1,
@@ -113,6 +117,7 @@ __device__ __forceinline__ void acc_finish(const RuleAcc &r, float &a2, float &b
   a2 = r.a;
   b2 = rule_log_miss(r);
 }
+__device__ __forceinline__ float acc_log_r(const RuleAcc &r) { return r.a; }
 __device__ __forceinline__ float acc_sig_neg(const RuleAcc &, float pre, float z2, float lp) {
   return fexp2(pre - (fmaxf(z2, 0.0f) + lp));
 }
@@ -157,6 +162,10 @@ struct RuleProd {
     m -= min0(z2);  // m += max(-z2, 0), the same value bit for bit
     return w;
   }
+  // add's return value for z2, without adding the condition
+  __device__ static __forceinline__ float term(float z2) {
+    return fmaf(fexp2(64.0f - fabsf(z2)), 0x1p-64f, 1.0f);
+  }
 };
 // log2(x * 2^-64) for x >= 0, from the exact exponent and the mantissa, so
 // that a result near -64 carries no rounding of 64.
@@ -175,6 +184,10 @@ __device__ __forceinline__ void acc_finish(const RuleProd &r, float &a2, float &
   a2 = -r.m - l1p;
   b2 = a2 > -0x1p-60f ? log2_scaled64(fmaf(one_minus_exp2(-r.m), 0x1p64f, r.pt)) - l1p
                        : log1mexp2(a2);
+}
+// a2 alone, the same value as acc_finish's
+__device__ __forceinline__ float acc_log_r(const RuleProd &r) {
+  return -r.m - log2_1p(r.pt * 0x1p-64f);
 }
 __device__ __forceinline__ float acc_sig_neg(const RuleProd &, float pre, float z2, float w) {
   return fexp2(pre - fmaxf(z2, 0.0f)) * frcp(w);
@@ -620,17 +633,62 @@ __global__ __launch_bounds__(kBwdWaves * 64) void k_soft_bwd(const SoftArgs a) {
 }
 
 // Adjoint for rule sets of at most RMAX rules with S samples per lane: the
-// only per-rule state kept between the two sweeps is l_k = a_k + (survival
-// before k), an RMAX x S array of floats per lane, read and written through
-// a uniform branch chain on k; at the 64-VGPR budget of eight waves per SIMD
-// the compiler keeps it in per-lane private memory (scratch, served by the
-// vector caches) for RMAX = 16 with four samples per lane.  The reverse sweep
-// recomputes every condition once: the same exp/log gives the rule's a_k
-// and log(1 - r_k) for the U recurrence and log sigmoid(z) for the
-// gradient.  Per condition the S slots are summed in the lane; two
+// per-rule state kept between the two sweeps is l_k = a_k + (survival
+// before k) and log2(1 - r_k), two RMAX x S arrays of floats per lane, read
+// and written through a uniform branch chain on k; at the 64-VGPR budget of
+// eight waves per SIMD the compiler keeps them in per-lane private memory
+// (scratch, served by the vector caches) for RMAX = 16 with four samples per
+// lane.  The reverse sweep recomputes every condition once for its
+// sigmoid(-z); only a rule of the label adds its conditions up again, for
+// the a_k of the U recurrence (the other rules' step of it needs
+// log2(1 - r_k) alone).  Per condition the S slots are summed in the lane; two
 // conditions' sums go over the wave in one reduction (wave_totals4), and the
 // lane that ends each adds it to the block's LDS accumulators (one writer per
 // rule set and tile).
+// The reverse sweep over one rule's conditions, two at a time: their four
+// sums over the wave in one reduction (wave_totals4), added (negated when
+// neg) to the rule set's block accumulators accq by the lane that holds each
+// (one writer per rule set and tile: the order of these adds is fixed).
+// pre: log2 |dL/da_k| per slot (with MUL, log2 r_k, and mul holds
+// dL/dr_k).  UPD: also adds every condition to ra, for the rule's log2 r
+// afterwards.
+template <int S, class Acc, bool TONLY, bool UPD, bool MUL = false>
+__device__ __forceinline__ void bwd_rule_conds(const SoftArgs &a, const float *xs, int lane,
+                                               int4 r, int cz, float *accq, const float (&pre)[S],
+                                               const float (&mul)[S], bool neg, Acc (&ra)[S]) {
+  for (int j0 = r.x; j0 < r.x + r.y; j0 += 2) {
+    // sums start at -0, so that the first term is added exactly as is
+    float g0[2] = {-0.0f, -0.0f}, g1[2] = {-0.0f, -0.0f};
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const int j = j0 + c;
+      if (j >= r.x + r.y) break;
+      float z[S], xf[S], xg[S];
+      if constexpr (TONLY) {
+        cond_z_t<S>(a, xs, lane, j, z, xf, xg);
+      } else {
+        bool ff;
+        cond_z<S>(a, xs, lane, j, z, xf, xg, ff);
+      }
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const float t = UPD ? ra[s].add(z[s]) : Acc::term(z[s]);
+        // |dL/dz| = |dL/da_k| * sigmoid(-z), or dL/dz = dL/dr_k * r_k * sigmoid(-z)
+        const float sg = acc_sig_neg(ra[s], pre[s], z[s], t);
+        const float dz = MUL ? mul[s] * sg : sg;
+        g0[c] = fmaf(dz, xg[s], g0[c]);
+        g1[c] = fmaf(dz, xf[s], g1[c]);
+      }
+    }
+    const float tot = wave_totals4(g0[0], g0[1], g1[0], g1[1]);
+    const int row = lane >> 4, c = row >> 1;
+    if ((lane & 15) == 15 && j0 + c < r.x + r.y) {
+      float *ap = accq + (j0 + c - cz) * 2 + (row & 1);
+      *ap += neg ? -tot : tot;
+    }
+  }
+}
+
 template <int K, int RMAX, int S>
 __device__ __forceinline__ void l_get(const float (&L)[RMAX][S], int k, float (&out)[S]) {
   if constexpr (K < RMAX) {
@@ -702,7 +760,7 @@ __device__ __forceinline__ void soft_bwd_reg(const SoftArgs &a) {
       if (q >= Q) break;
       const int4 ss = ldc(a.ssets, q0 + q);
       const int dflt = ldc(a.sets, q0 + q).z;
-      float L[RMAX][S];
+      float L[RMAX][S], B[RMAX][S];
       float logpy[S], surv[S];
 #pragma unroll
       for (int s = 0; s < S; ++s) { logpy[s] = kNegInf; surv[s] = 0.0f; }
@@ -729,16 +787,18 @@ __device__ __forceinline__ void soft_bwd_reg(const SoftArgs &a) {
           for (int s = 0; s < S; ++s) (void)ra[s].add(z[s]);
         }
         const bool hit = r.z == label;
-        float lk[S];
+        float lk[S], bk[S];
 #pragma unroll
         for (int s = 0; s < S; ++s) {
           float a2, b2;
           acc_finish(ra[s], a2, b2);
           lk[s] = a2 + surv[s];
+          bk[s] = b2;
           if (hit) logpy[s] = lse(logpy[s], lk[s]);
           surv[s] += b2;
         }
         l_set<0, RMAX, S>(L, k, lk);
+        l_set<0, RMAX, S>(B, k, bk);
       }
       float gate[S], U[S];
 #pragma unroll
@@ -760,53 +820,26 @@ __device__ __forceinline__ void soft_bwd_reg(const SoftArgs &a) {
         // gradient) and its sign, the same for the whole wave, onto the sums.
         // U, the log2 of a probability, can round to just above 0: 1 - 2^U
         // is then taken as 0.
-        float lk[S], pre[S];
+        float lk[S], bk[S], pre[S];
         l_get<0, RMAX, S>(L, k, lk);
+        l_get<0, RMAX, S>(B, k, bk);
 #pragma unroll
         for (int s = 0; s < S; ++s) {
           const float lm = hit ? log1mexp2(fminf(U[s], 0.0f)) : U[s];
           pre[s] = gate[s] != 0.0f ? lk[s] + lm - logpy[s] : kNegInf;
         }
+        float *accq = acc + (size_t)q * a.max_set_conds * 2;
         Acc ra[S];
-        // conditions two at a time: their four sums over the wave in one
-        // reduction (wave_totals4), added to the block accumulators by the
-        // lane that holds each (one writer per rule set and tile: the order
-        // of these adds is fixed)
-        for (int j0 = r.x; j0 < r.x + r.y; j0 += 2) {
-          // sums start at -0, so that the first term is added exactly as is
-          float g0[2] = {-0.0f, -0.0f}, g1[2] = {-0.0f, -0.0f};
+        if (hit) {
+          // U takes the rule's own log2 r: the conditions are added again
+          bwd_rule_conds<S, Acc, TONLY, true>(a, xs, lane, r, ss.z, accq, pre, pre, true, ra);
 #pragma unroll
-          for (int c = 0; c < 2; ++c) {
-            const int j = j0 + c;
-            if (j >= r.x + r.y) break;
-            float z[S], xf[S], xg[S];
-            if constexpr (TONLY) {
-              cond_z_t<S>(a, xs, lane, j, z, xf, xg);
-            } else {
-              bool ff;
-              cond_z<S>(a, xs, lane, j, z, xf, xg, ff);
-            }
+          for (int s = 0; s < S; ++s) U[s] = lse(acc_log_r(ra[s]), bk[s] + U[s]);
+        } else {
+          // U_k = log2(1 - r_k) + U_k+1, from the forward sweep's log2(1 - r_k)
+          bwd_rule_conds<S, Acc, TONLY, false>(a, xs, lane, r, ss.z, accq, pre, pre, false, ra);
 #pragma unroll
-            for (int s = 0; s < S; ++s) {
-              const float t = ra[s].add(z[s]);
-              // |dL/dz| = |dL/da_k| * sigmoid(-z)
-              const float dz = acc_sig_neg(ra[s], pre[s], z[s], t);
-              g0[c] = fmaf(dz, xg[s], g0[c]);
-              g1[c] = fmaf(dz, xf[s], g1[c]);
-            }
-          }
-          const float tot = wave_totals4(g0[0], g0[1], g1[0], g1[1]);
-          const int row = lane >> 4, c = row >> 1;
-          if ((lane & 15) == 15 && j0 + c < r.x + r.y) {
-            float *ap = acc + ((size_t)q * a.max_set_conds + (j0 + c - ss.z)) * 2 + (row & 1);
-            *ap += hit ? -tot : tot;
-          }
-        }
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-          float a2, b2;
-          acc_finish(ra[s], a2, b2);
-          U[s] = lse(hit ? a2 : kNegInf, b2 + U[s]);
+          for (int s = 0; s < S; ++s) U[s] = bk[s] + U[s];
         }
       }
     }
@@ -1363,13 +1396,14 @@ __global__ __launch_bounds__(kSmaxBwdWaves * 64) void k_smax_bwd(const SoftArgs 
 
 // Adjoint of the softmax head for rule sets of at most 16 rules and at most
 // four classes, four samples per lane, 16 waves per block: the per-rule
-// state between the two sweeps (log2 r_k and the prefix sum of
-// log2(1 - r_i) before k, for each of the lane's samples) is a 16 x 4 x 2
-// array per lane, read and written through a uniform branch chain on k (the
-// compiler keeps it in per-lane private memory at the 64-VGPR budget of
-// two blocks per CU).  Per condition the four slots are summed in the lane,
-// then over the wave; the walk's totals go to LDS as in the first-firing
-// adjoint.  Same formulas as k_smax_bwd.
+// state between the two sweeps (log2 r_k, the prefix sum of log2(1 - r_i)
+// before k and log2(1 - r_k), for each of the lane's samples) is a
+// 16 x 4 x 3 array per lane, read and written through a uniform branch chain
+// on k (the compiler keeps it in per-lane private memory at the 64-VGPR
+// budget of two blocks per CU).  The reverse sweep needs each condition's
+// sigmoid(-z) alone, so it adds no condition up again; the conditions' sums
+// go over the wave and to LDS as in the first-firing adjoint.  Same
+// formulas as k_smax_bwd.
 constexpr int kSmaxRegRules = 16;
 
 template <int NC, class Acc, bool TONLY>
@@ -1406,7 +1440,7 @@ __global__ __launch_bounds__(kBwdRegBlock, 8) AERL_BWD_SGPR_CAP void k_smax_bwd_
       if (q >= Q) break;
       const int4 ss = ldc(a.ssets, q0 + q);
       const int dflt = ldc(a.sets, q0 + q).z;
-      float LA[RMAX][S], LP[RMAX][S];
+      float LA[RMAX][S], LP[RMAX][S], LB[RMAX][S];
       float v[S][NC], surv[S];
 #pragma unroll
       for (int s = 0; s < S; ++s) {
@@ -1436,18 +1470,20 @@ __global__ __launch_bounds__(kBwdRegBlock, 8) AERL_BWD_SGPR_CAP void k_smax_bwd_
 #pragma unroll
           for (int s = 0; s < S; ++s) (void)ra[s].add(z[s]);
         }
-        float a2s[S], pre[S];
+        float a2s[S], pre[S], b2s[S];
 #pragma unroll
         for (int s = 0; s < S; ++s) {
           float a2, b2;
           acc_finish(ra[s], a2, b2);
           a2s[s] = a2;
           pre[s] = surv[s];
+          b2s[s] = b2;
           add_vote(v[s], r.z, fexp2(a2));
           surv[s] += b2;
         }
         l_set<0, RMAX, S>(LA, k, a2s);
         l_set<0, RMAX, S>(LP, k, pre);
+        l_set<0, RMAX, S>(LB, k, b2s);
       }
       // dL/dv per slot (clamped samples and padding get none); for the
       // label, -beta times the other classes' probabilities
@@ -1478,47 +1514,16 @@ __global__ __launch_bounds__(kBwdRegBlock, 8) AERL_BWD_SGPR_CAP void k_smax_bwd_
           drk[s] = r.z == dflt ? gd[s] * one_minus_exp2(oth)
                                : pick(gv[s], r.z) - gd[s] * fexp2(oth);
         }
+        // the conditions' terms need no accumulator: log2(1 - r_k) comes
+        // from the forward sweep
         Acc ra[S];
-        // conditions two at a time: their four sums over the wave in one
-        // reduction (wave_totals4), added to the block accumulators by the
-        // lane that holds each (one writer per rule set and tile: the order
-        // of these adds is fixed)
-        for (int j0 = r.x; j0 < r.x + r.y; j0 += 2) {
-          // sums start at -0, so that the first term is added exactly as is
-          float g0[2] = {-0.0f, -0.0f}, g1[2] = {-0.0f, -0.0f};
+        bwd_rule_conds<S, Acc, TONLY, false, true>(a, xs, lane, r, ss.z,
+                                                   acc + (size_t)q * a.max_set_conds * 2, la, drk,
+                                                   false, ra);
+        float lb[S];
+        l_get<0, RMAX, S>(LB, k, lb);
 #pragma unroll
-          for (int c = 0; c < 2; ++c) {
-            const int j = j0 + c;
-            if (j >= r.x + r.y) break;
-            float z[S], xf[S], xg[S];
-            if constexpr (TONLY) {
-              cond_z_t<S>(a, xs, lane, j, z, xf, xg);
-            } else {
-              bool ff;
-              cond_z<S>(a, xs, lane, j, z, xf, xg, ff);
-            }
-#pragma unroll
-            for (int s = 0; s < S; ++s) {
-              const float t = ra[s].add(z[s]);
-              // dL/dz = dL/dr_k * r_k * sigmoid(-z)
-              const float dz = drk[s] * acc_sig_neg(ra[s], la[s], z[s], t);
-              g0[c] = fmaf(dz, xg[s], g0[c]);
-              g1[c] = fmaf(dz, xf[s], g1[c]);
-            }
-          }
-          const float tot = wave_totals4(g0[0], g0[1], g1[0], g1[1]);
-          const int row = lane >> 4, c = row >> 1;
-          if ((lane & 15) == 15 && j0 + c < r.x + r.y) {
-            float *ap = acc + ((size_t)q * a.max_set_conds + (j0 + c - ss.z)) * 2 + (row & 1);
-            *ap += tot;
-          }
-        }
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-          float a2, b2;
-          acc_finish(ra[s], a2, b2);
-          tail[s] += b2;
-        }
+        for (int s = 0; s < S; ++s) tail[s] += lb[s];
       }
     }
   }
