@@ -133,9 +133,10 @@ __device__ __forceinline__ float log2_1p(float p) {
 // conditions.  With u_j = e^-|z_j| and M = sum_j max(-z_j, 0),
 //   r = e^-M / prod_j (1 + u_j),  p = prod_j (1 + u_j) - 1 >= 0,
 //   log r = -M - log1p(p),  1 - r = (p + (1 - e^-M)) / (1 + p),
-// and p is built by p <- p + u + p*u, a sum of non-negative terms, so it
-// keeps full relative accuracy (also when r is within e^-100 of 1) with one
-// exponential per condition; the logarithms are taken once per rule.  p is
+// and p is built by p <- p (1 + u) + u from non-negative terms (1 + u
+// rounded once), so it keeps full relative accuracy (also when r is within
+// e^-100 of 1) with one exponential per condition; the logarithms are taken
+// once per rule.  p is
 // kept scaled by 2^64 (pt), so that u down to 2^-190 stays a normal float;
 // with at most 60 conditions pt < 2^124.
 constexpr int kProdMaxConds = 60;
