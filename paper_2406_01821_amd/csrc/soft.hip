@@ -959,11 +959,21 @@ constexpr size_t kFwdPartMax = (size_t)8 << 20;
 constexpr int64_t kBwdTargetBlocks = 4096;
 constexpr size_t kBwdPartMax = (size_t)1 << 30;
 
+// Rule sets per block: 64, or fewer, down to one per wave (min_q), while
+// the grid (set chunks x `groups` tile groups) stays under `target` blocks,
+// so that a small workload spreads over more CUs instead of walking several
+// rule sets per wave on a few of them.
+int sets_per_block(int n_sets, int64_t groups, int64_t target, int min_q) {
+  int q = std::max(1, std::min(n_sets, 64));
+  while (q / 2 >= min_q && (int64_t)((n_sets + q - 1) / q) * groups < target) q /= 2;
+  return q;
+}
+
 SoftPlan plan_forward(const DatasetRec &ds, const PopRec &pop) {
   SoftPlan p{};
   p.S = 4;
   while (p.S > 1 && (size_t)ds.nf * 256 * p.S > 64 * 1024) p.S >>= 1;
-  p.Q = std::max(1, std::min(pop.n_sets, 64));
+  p.Q = sets_per_block(pop.n_sets, count_groups(ds, 1), kFwdTargetBlocks, kSoftBlock / 64);
   p.TG = tiles_per_group(ds, (pop.n_sets + p.Q - 1) / p.Q, kFwdTargetBlocks,
                          (size_t)std::max(pop.n_sets, 1) * sizeof(double), kFwdPartMax);
   p.n_groups = (int)count_groups(ds, p.TG);
@@ -986,7 +996,7 @@ SoftPlan plan_backward(const DatasetRec &ds, const PopRec &pop) {
     p.S = p.rmax <= 16 ? 4 : 2;
     while (p.S > 1 && (size_t)ds.nf * 256 * p.S > 64 * 1024) p.S >>= 1;
     const size_t xs = (size_t)ds.nf * 64 * p.S * 4;
-    p.Q = std::max(1, std::min(pop.n_sets, 64));
+    p.Q = sets_per_block(pop.n_sets, p.n_groups, kBwdTargetBlocks, kBwdRegBlock / 64);
     while (p.Q > 1 && xs + p.Q * per_set > kLdsPerCu / 2 - kStaticLds) p.Q >>= 1;  // two blocks per CU
     p.lds = xs + (size_t)p.Q * per_set;
     if (p.lds <= kDynLdsMax) return p;
@@ -1597,7 +1607,7 @@ SoftPlan plan_smax_backward(const DatasetRec &ds, const PopRec &pop) {
     p.rmax = kSmaxRegRules;
     p.S = 4;
     const size_t xs = (size_t)ds.nf * 64 * p.S * 4;
-    p.Q = std::max(1, std::min(pop.n_sets, 64));
+    p.Q = sets_per_block(pop.n_sets, p.n_groups, kBwdTargetBlocks, kBwdRegBlock / 64);
     while (p.Q > 1 && xs + p.Q * per_set > kLdsPerCu / 2 - kStaticLds) p.Q >>= 1;
     p.lds = xs + (size_t)p.Q * per_set;
     if (p.lds <= kDynLdsMax) return p;
