@@ -368,9 +368,11 @@ struct Evo {
   size_t arena_bytes = 0;
   EvolveArena layout{};
   void *staging = nullptr;       // pinned host image of a packed pool
+  int32_t *fit_pinned = nullptr; // pinned landing place of the fitness counts
   double sec_eval = 0, sec_tune = 0, sec_breed = 0;
   ~Evo() {
     if (staging) (void)hipHostFree(staging);
+    if (fit_pinned) (void)hipHostFree(fit_pinned);
   }
 };
 
@@ -453,10 +455,11 @@ aerl_status evaluate(aerl_ctx *ctx, Evo &e, hipStream_t st) {
   const auto t1 = clk::now();
   s = aerl_eval_population(ctx, e.dataset_id, pid, correct, nullptr, st);
   if (s == AERL_OK) {
-    e.fitness.resize(e.pool.n_sets());
-    hipError_t h = hipMemcpyAsync(e.fitness.data(), correct, e.pool.n_sets() * 4, hipMemcpyDeviceToHost, st);
+    const int32_t n = e.pool.n_sets();
+    hipError_t h = hipMemcpyAsync(e.fit_pinned, correct, (size_t)n * 4, hipMemcpyDeviceToHost, st);
     if (h == hipSuccess) h = hipStreamSynchronize(st);
     if (h != hipSuccess) s = fail(ctx, AERL_EDEVICE, "fitness copy failed: %s", hipGetErrorString(h));
+    else e.fitness.assign(e.fit_pinned, e.fit_pinned + n);
   }
   (void)aerl_release_population(ctx, pid);
   e.sec_eval += std::chrono::duration<double>(clk::now() - t1).count();
@@ -479,6 +482,8 @@ aerl_status attach(aerl_ctx *ctx, Evo &e, int32_t dataset_id, void *arena, size_
   e.arena = static_cast<char *>(arena);
   e.arena_bytes = arena_bytes;
   AERL_HIP(ctx, hipHostMalloc(&e.staging, e.layout.staging_bytes, hipHostMallocDefault));
+  AERL_HIP(ctx, hipHostMalloc(reinterpret_cast<void **>(&e.fit_pinned),
+                              (size_t)std::max(e.cfg.pool, 1) * 4, hipHostMallocDefault));
   return AERL_OK;
 }
 
